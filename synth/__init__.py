@@ -1,0 +1,188 @@
+"""Seeded synthetic snapshot sets shaped like the HAPOD paper's workloads.
+
+This module is shared by the CPU oracle (``oracle/``) and by the GPU path's
+tests and benchmark.  It holds only data recipes: grids, coefficient draws,
+the sinusoid and Gaussian-bump families, and the tree shapes of the benchmark
+workloads.  It contains none of the method's arithmetic (no Gram matrix, no
+eigensolve, no truncation, no lift).
+
+Recipes (the paper's own datasets are not reproducible here, so these stand in
+for them):
+
+* grid: ``x_i = i / (n + 1)``, ``i = 1..n`` -- interior points of (0, 1).
+* sinusoid family: column ``j`` is
+  ``sum_{k=1..K} exp(-k / tau) * c_jk * sqrt(2) * sin(k * pi * x_i)``
+  plus i.i.d. Gaussian noise of standard deviation ``noise_std``;
+  ``c_jk ~ N(0, 1)`` drawn as ``C = rng.standard_normal((m, K))`` (row j is
+  snapshot j), then the noise as ``rng.standard_normal((m, n)).T * noise_std``,
+  with ``rng = numpy.random.default_rng(seed)`` (PCG64).
+* Gaussian bumps: ``s_j(x_i) = exp(-(x_i - c_j)^2 / (2 w_j^2))`` with
+  ``(u, v) = rng.random((m, 2))`` per column, ``c_j = u``,
+  ``w_j = wmin + (wmax - wmin) * v``.
+
+Large device-resident inputs are produced by :mod:`synth.device` with the
+same coefficients (drawn here, on the host) and the same formulas.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+__all__ = [
+    "grid",
+    "sinusoid_coeffs",
+    "sinusoid_dense_factors",
+    "sinusoid",
+    "bump_params",
+    "bumps",
+    "star_tree",
+    "chain_tree",
+    "balanced_tree",
+    "Workload",
+    "WORKLOADS",
+]
+
+
+# --------------------------------------------------------------------------
+# grids and coefficient draws
+# --------------------------------------------------------------------------
+def grid(n: int) -> np.ndarray:
+    """Interior uniform grid ``x_i = i/(n+1)``, i = 1..n (float64)."""
+    return np.arange(1, n + 1, dtype=np.float64) / float(n + 1)
+
+
+def sinusoid_coeffs(m: int, K: int, seed: int) -> np.ndarray:
+    """``C`` of shape (m, K): row j holds the coefficients of snapshot j."""
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal((m, K))
+
+
+def sinusoid_dense_factors(n: int, K: int, tau: float):
+    """Return ``(Phi, decay)`` with ``Phi[i, k-1] = sqrt(2) sin(k pi x_i)`` and
+    ``decay[k-1] = exp(-k/tau)``: the noise-free data is
+    ``Phi @ (C * decay).T``."""
+    x = grid(n)
+    k = np.arange(1, K + 1, dtype=np.float64)
+    phi = math.sqrt(2.0) * np.sin(np.pi * np.outer(x, k))
+    decay = np.exp(-k / float(tau))
+    return phi, decay
+
+
+def sinusoid(n: int, m: int, K: int, tau: float, noise_std: float, seed: int,
+             dtype=np.float64) -> np.ndarray:
+    """Dense ``n x m`` snapshot matrix (Fortran order) of the sinusoid family."""
+    rng = np.random.default_rng(seed)
+    C = rng.standard_normal((m, K))
+    phi, decay = sinusoid_dense_factors(n, K, tau)
+    S = phi @ (C * decay).T
+    if noise_std > 0.0:
+        S = S + rng.standard_normal((m, n)).T * noise_std
+    return np.asfortranarray(S.astype(dtype, copy=False))
+
+
+def bump_params(m: int, seed: int, wmin: float = 0.01, wmax: float = 0.05):
+    """Centres and widths of ``m`` Gaussian bumps."""
+    rng = np.random.default_rng(seed)
+    u = rng.random((m, 2))
+    return u[:, 0].copy(), wmin + (wmax - wmin) * u[:, 1]
+
+
+def bumps(n: int, m: int, seed: int, wmin: float = 0.01, wmax: float = 0.05,
+          dtype=np.float64) -> np.ndarray:
+    """Dense ``n x m`` Gaussian-bump snapshot matrix (Fortran order)."""
+    c, w = bump_params(m, seed, wmin, wmax)
+    x = grid(n)
+    S = np.exp(-np.subtract.outer(x, c) ** 2 / (2.0 * w * w))
+    return np.asfortranarray(S.astype(dtype, copy=False))
+
+
+# --------------------------------------------------------------------------
+# tree shapes (parent arrays; the root has parent -1)
+# --------------------------------------------------------------------------
+def star_tree(num_leaves: int):
+    """Distributed HAPOD: leaves 0..L-1, root L."""
+    return [num_leaves] * num_leaves + [-1]
+
+
+def chain_tree(num_chunks: int):
+    """Incremental HAPOD with ``num_chunks`` data chunks.
+
+    Node ids: alpha_1..alpha_L are 0..L-1 (alpha_L = root), beta_1..beta_{L-1}
+    are L..2L-2.  alpha_1 is a leaf holding chunk 0; beta_l holds chunk l and
+    is a child of alpha_{l+1}, together with alpha_l.
+    Returns ``(parent, chunk_of_leaf)`` where ``chunk_of_leaf`` maps leaf node
+    id to chunk index.
+    """
+    L = num_chunks
+    parent = [0] * (2 * L - 1)
+    for l in range(L):          # alpha_{l+1}
+        parent[l] = l + 1 if l + 1 < L else -1
+    for l in range(1, L):       # beta_l -> alpha_{l+1}
+        parent[L + l - 1] = l
+    chunk = {0: 0}
+    for l in range(1, L):
+        chunk[L + l - 1] = l
+    return parent, chunk
+
+
+def balanced_tree(num_leaves: int, depth: int):
+    """Balanced tree over ``num_leaves`` leaves with ``depth`` levels and
+    arity ``ceil(num_leaves ** (1/(depth-1)))`` (leaves are level 1).
+    Leaves are 0..num_leaves-1; inner nodes follow level by level; the root
+    is last."""
+    if depth < 2:
+        raise ValueError("depth must be >= 2")
+    arity = int(math.ceil(num_leaves ** (1.0 / (depth - 1)) - 1e-12))
+    parent = []
+    level_nodes = list(range(num_leaves))
+    parent.extend([None] * num_leaves)
+    next_id = num_leaves
+    while len(level_nodes) > 1:
+        groups = [level_nodes[i:i + arity] for i in range(0, len(level_nodes), arity)]
+        new_nodes = []
+        for g in groups:
+            nid = next_id
+            next_id += 1
+            parent.append(None)
+            for c in g:
+                parent[c] = nid
+            new_nodes.append(nid)
+        level_nodes = new_nodes
+    parent[level_nodes[0]] = -1
+    return parent
+
+
+# --------------------------------------------------------------------------
+# the benchmark workloads
+# --------------------------------------------------------------------------
+@dataclass(frozen=True)
+class Workload:
+    name: str
+    n: int
+    leaf_cols: tuple
+    family: str            # "sinusoid", "bumps", "mixed"
+    eps_star: float
+    omega: float
+    K: int = 0
+    tau: float = 0.0
+    noise_std: float = 0.0
+    seed: int = 0
+    precision: str = "fp64"
+    tree: str = "star"
+    extra: dict = field(default_factory=dict)
+
+    @property
+    def num_snapshots(self) -> int:
+        return int(sum(self.leaf_cols))
+
+
+WORKLOADS = {
+    # n=4096, 4 leaves x 64 columns, star tree, sinusoid K=200, tau=10
+    "star4096x256": Workload("star4096x256", 4096, (64,) * 4, "sinusoid",
+                             1e-6, 0.75, K=200, tau=10.0, noise_std=1e-10),
+    # n=2^20, 64 leaves x 128 columns, star tree, sinusoid K=400, tau=20
+    "star1Mx8192": Workload("star1Mx8192", 1 << 20, (128,) * 64, "sinusoid",
+                            1e-5, 0.75, K=400, tau=20.0, noise_std=1e-10),
+}
