@@ -1,0 +1,229 @@
+/*
+ * hapod.h -- C ABI of the MI355X (gfx950) hierarchical approximate POD.
+ *
+ * The library computes, for every node of a rooted tree, the local POD of the
+ * node's input columns by the method of snapshots (Rem. 2.3 of Himpe, Leibner
+ * & Rave, "Hierarchical Approximate POD"):
+ *
+ *   Gram      G = S^T S                                   (Rem. 2.3)
+ *   eigh      G = V diag(lambda) V^T, lambda descending   (Rem. 2.3)
+ *   truncate  N = min{N' : sum_{n>N'} lambda_n <= eps^2}   (Def. 2.5, Thm. 2.4)
+ *   lift      inner node: W = S V_N          (= U Sigma, the scaled modes)
+ *             root:       U = S V_N Lambda_N^(-1/2)       (Rem. 2.3, Def. 3.2)
+ *
+ * and drives those node PODs level by level over the tree (Def. 3.1, Def. 3.2)
+ * with the local tolerances of Thm. 3.5.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Matrices are column-major with a leading dimension ("ld") >= rows.
+ * - Snapshot / mode storage type follows the precision: HAPOD_FP64 stores
+ *   double, HAPOD_FP32 and HAPOD_BF16X3 store float.  Gram matrices,
+ *   eigenvalues, eigenvectors, singular values and tolerances are always
+ *   double.
+ * - "device" pointers are HIP device allocations on the current device;
+ *   "host" pointers are ordinary host memory.  Each argument says which.
+ * - stream: a hipStream_t passed as void* (NULL = the null stream).  All
+ *   device work is ordered on it.  Entry points that return host results
+ *   synchronise the stream before returning; the others are asynchronous.
+ * - The caller owns every buffer it passes in.  The library never frees
+ *   caller memory and never keeps a caller pointer beyond the call, except
+ *   leaf pointers returned by a leaf provider, which must stay valid until
+ *   hapod_run returns.
+ * - Every function returns a status and never aborts; a human-readable
+ *   message for the last failure on the calling thread is returned by
+ *   hapod_last_error().
+ * - Results are deterministic: reductions run in a fixed order and no
+ *   floating-point atomics are used, so reruns are bitwise identical.
+ */
+#ifndef HAPOD_H
+#define HAPOD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  HAPOD_OK = 0,
+  HAPOD_E_INVALID = 1,   /* bad argument (negative size, eps < 0, omega outside [0,1], NULL) */
+  HAPOD_E_TREE = 2,      /* parent array violates Def. 3.1 (roots, range, cycles)           */
+  HAPOD_E_NOMEM = 3,     /* device allocation failed or the memory cap would be exceeded    */
+  HAPOD_E_DEVICE = 4,    /* a HIP runtime call failed                                       */
+  HAPOD_E_NUMERIC = 5,   /* non-finite Gram diagonal (NaN/Inf in the input)                 */
+  HAPOD_E_STATE = 6,     /* plan not run yet / node has no result                           */
+  HAPOD_E_CALLBACK = 7,  /* the leaf provider returned a non-zero code                      */
+  HAPOD_E_UNSUPPORTED = 8 /* size beyond a kernel's documented limit                        */
+} hapod_status;
+
+typedef enum {
+  HAPOD_FP64 = 0,    /* Gram and lift on FP64 MFMA, double storage                         */
+  HAPOD_FP32 = 1,    /* Gram and lift on FP32 MFMA, FP32 accumulation, float storage       */
+  HAPOD_BF16X3 = 2   /* split-BF16, three products hi*hi + hi*lo + lo*hi on BF16 MFMA      */
+} hapod_precision;
+
+/* ------------------------------------------------------------------------ */
+/* Step-level entry points: one method-of-snapshots step each.              */
+/* ------------------------------------------------------------------------ */
+
+/* Gram matrix G = S^T S (Rem. 2.3).
+ *   S      device, n x m column-major, ld lds >= n, storage type of prec.
+ *   G      device, m x m double, ld ldg >= m; the full symmetric matrix is
+ *          written (both triangles, bitwise symmetric).
+ * Row blocks are accumulated in the precision's MFMA accumulator and the
+ * block partial sums are added in double, in a fixed order.
+ * n == 0 gives G = 0; m == 0 is a no-op.                                    */
+hapod_status hapod_gram(hapod_precision prec, int64_t n, int64_t m,
+                        const void* S, int64_t lds, double* G, int64_t ldg,
+                        void* stream);
+
+/* Symmetric eigendecomposition of a Gram matrix (Rem. 2.3), in double.
+ *   G       device, m x m, ld ldg; overwritten (destroyed).
+ *   lambda  device, m doubles: eigenvalues, descending; equal values keep
+ *           their original index order.
+ *   V       device, m x m double, ld ldv: orthonormal eigenvectors, column k
+ *           for lambda[k], each with its largest-magnitude entry positive.
+ *   sweeps  host, may be NULL: Jacobi sweeps used.
+ * Synchronises the stream when sweeps != NULL.  m <= HAPOD_EIG_MAX.         */
+#define HAPOD_EIG_MAX 8192
+hapod_status hapod_eigh(int64_t m, double* G, int64_t ldg, double* lambda,
+                        double* V, int64_t ldv, int32_t* sweeps, void* stream);
+
+/* Truncation rank of Def. 2.5 from eigenvalues of a Gram matrix.
+ *   lambda  device, m doubles, descending.  Negative values are rounding
+ *           artefacts of the Gram product; they count as zero energy.
+ *   eps     the local tolerance; the rank is the smallest N with
+ *           sum_{n>N} max(lambda_n, 0) <= eps^2 (tail summed in double).
+ *   info    host, 4 doubles, may be NULL: {tail(N), lambda_1, lambda_min,
+ *           number of negative eigenvalues}.
+ *   rank    host.
+ * Synchronises the stream.                                                  */
+hapod_status hapod_truncate(int64_t m, const double* lambda, double eps,
+                            int64_t* rank, double* info, void* stream);
+
+/* Mode lift (Rem. 2.3, Def. 3.2).
+ *   S       device, n x m, ld lds, storage type of prec.
+ *   V       device, m x N double, ld ldv (eigenvectors for the kept modes).
+ *   lambda  device, N doubles, or NULL.  NULL: out = S V (scaled modes
+ *           sigma_k phi_k, what a parent node consumes).  Non-NULL:
+ *           out = S V diag(lambda)^(-1/2) (orthonormal modes, the root's
+ *           output).
+ *   out     device, n x N, ld ldo, storage type of prec.                    */
+hapod_status hapod_lift(hapod_precision prec, int64_t n, int64_t m, int64_t N,
+                        const void* S, int64_t lds, const double* V, int64_t ldv,
+                        const double* lambda, void* out, int64_t ldo,
+                        void* stream);
+
+/* Re-orthonormalisation of computed modes in double: two passes of
+ * Cholesky-QR (W = U^T U accumulated in double, W = R^T R, U <- U R^-1).
+ *   U  device, n x N, ld ldu, storage type of prec; overwritten.
+ * Columns whose Cholesky pivot is not positive are left as they are and
+ * reported through *bad (host, may be NULL).  N <= 1024.                    */
+hapod_status hapod_reorth(hapod_precision prec, int64_t n, int64_t N, void* U,
+                          int64_t ldu, int64_t* bad, void* stream);
+
+/* One local POD(S, eps) (Def. 2.5) by the method of snapshots.
+ *   S       device, n x m, ld lds, storage type of prec.
+ *   eps     >= 0.  eps == 0 is the pass-through POD(S, 0) = {(1, s)}: out
+ *           receives a copy of S and every sigma is 1 (Def. 2.5).
+ *   scaled  0: out holds orthonormal modes phi_k; 1: out holds sigma_k phi_k.
+ *   out     device, n x m capacity, ld ldo, storage type of prec; the first
+ *           *rank columns are written.
+ *   sigma   host, m doubles capacity; the first *rank are written.
+ *   rank    host.
+ * Synchronises the stream.                                                  */
+hapod_status hapod_node_pod(hapod_precision prec, int64_t n, int64_t m,
+                            const void* S, int64_t lds, double eps, int32_t scaled,
+                            void* out, int64_t ldo, double* sigma, int64_t* rank,
+                            void* stream);
+
+/* ------------------------------------------------------------------------ */
+/* Tree-level entry points.                                                 */
+/* ------------------------------------------------------------------------ */
+
+typedef struct hapod_plan_s* hapod_plan_t;
+
+/* A rooted tree (Def. 3.1) with the snapshot-to-leaf map D (Def. 3.2):
+ *   parent[i]    parent of node i, -1 for the (single) root.
+ *   leaf_cols[i] |D^-1(i)|, the number of snapshots at leaf i (ignored for
+ *                inner nodes).
+ *   n            dimension of the snapshot space V (rows).
+ * Arrays are host memory, read during hapod_plan only.                     */
+typedef struct {
+  int32_t num_nodes;
+  const int32_t* parent;
+  const int64_t* leaf_cols;
+  int64_t n;
+} hapod_tree;
+
+typedef struct {
+  hapod_precision prec;
+  int32_t reorth;                  /* 1: hapod_reorth on the root modes                    */
+  int64_t mem_cap_bytes;           /* 0: no cap; else device bytes the plan may hold       */
+  const double* node_eps_override; /* host, num_nodes values or NULL; an entry >= 0
+                                      replaces the Thm. 3.5 tolerance of that node         */
+  int32_t jacobi_max;              /* 0: default; nodes with m above it take the
+                                      subspace-iteration eigensolver                       */
+} hapod_options;
+
+/* Validate the tree (Def. 3.1), compute levels (height: leaves are level 1),
+ * |S~_alpha| and the Thm. 3.5 tolerances
+ *   eps(root)  = sqrt(|S|) omega eps_star,
+ *   eps(alpha) = sqrt(|S~_alpha|) (L_T - 1)^(-1/2) sqrt(1 - omega^2) eps_star,
+ * then apply node_eps_override.  opts may be NULL (FP64, no re-orth).
+ * No device memory is allocated.                                            */
+hapod_status hapod_plan(const hapod_tree* tree, double eps_star, double omega,
+                        const hapod_options* opts, hapod_plan_t* out);
+
+/* Host copies of the plan: eps (double), level (int32), acc (|S~_alpha|,
+ * int64), each num_nodes long; any may be NULL.                             */
+hapod_status hapod_plan_query(hapod_plan_t plan, double* eps, int32_t* level,
+                              int64_t* acc);
+
+/* Leaf provider: returns in *ptr a device pointer to the leaf's n x
+ * leaf_cols[leaf] snapshot matrix (storage type of the plan's precision)
+ * and its leading dimension in *ld.  Called once per leaf, in level order,
+ * before that leaf's level is launched on `stream`.  Non-zero return aborts
+ * the run with HAPOD_E_CALLBACK.                                            */
+typedef int32_t (*hapod_leaf_fn)(void* user, int32_t leaf, const void** ptr,
+                                 int64_t* ld, void* stream);
+
+/* Run the HAPOD (Def. 3.2) level by level.  All nodes of one level go
+ * through one batched sequence of launches (Gram, reduction, eigensolve,
+ * truncation, lift); ranks are read back between levels to size the next
+ * one.  Intermediate node outputs are released once their parent is done;
+ * the root's modes and the per-node ranks and singular values are kept in
+ * the plan until the next run or hapod_destroy.  Synchronises the stream. */
+hapod_status hapod_run(hapod_plan_t plan, hapod_leaf_fn get_leaf, void* user,
+                       void* stream);
+
+/* Results of the last run.  node = -1 means the root.
+ *   rank   host: |HAPOD(node)|.
+ *   sigma  host, rank doubles, may be NULL.
+ *   U      device, n x rank, ld ldu, storage type of the plan, may be NULL;
+ *          only the root's modes are kept (orthonormal unless the root's
+ *          tolerance is 0, in which case they are its input vectors and
+ *          sigma is 1).
+ * Synchronises the stream.                                                  */
+hapod_status hapod_modes(hapod_plan_t plan, int32_t node, void* U, int64_t ldu,
+                         double* sigma, int64_t* rank, void* stream);
+
+/* Per-node diagnostics of the last run, host, num_nodes entries each, any may
+ * be NULL: input columns m, negative Gram eigenvalues, lambda_1, lambda_min. */
+hapod_status hapod_node_stats(hapod_plan_t plan, int64_t* m_in, int64_t* n_negative,
+                              double* lambda1, double* lambda_min);
+
+/* Device time in milliseconds of the phases of the last run, measured with
+ * HIP events on the run's stream: {total, gram, eig, truncate, lift, reorth}. */
+hapod_status hapod_run_timing(hapod_plan_t plan, double* ms6);
+
+void hapod_destroy(hapod_plan_t plan);
+
+const char* hapod_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HAPOD_H */

@@ -1,0 +1,306 @@
+"""Python binding of the HIP HAPOD library (``libhapod.so``, gfx950).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels behind the C ABI declared in ``include/hapod.h``.  Functions carry the
+C names.  Matrices are column-major: a torch tensor ``S`` of shape (n, m) with
+``S.stride(0) == 1`` and leading dimension ``S.stride(1) >= n`` (for example
+``torch.empty(m, n).t()``); :func:`colmajor` allocates one.  Device tensors
+supply device pointers, torch's current stream is the HIP stream.
+
+Importing this module loads the library and raises if it is missing: there is
+no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhapod.so")
+
+FP64, FP32, BF16X3 = 0, 1, 2
+PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3}
+STATUS = {0: "OK", 1: "E_INVALID", 2: "E_TREE", 3: "E_NOMEM", 4: "E_DEVICE", 5: "E_NUMERIC",
+          6: "E_STATE", 7: "E_CALLBACK", 8: "E_UNSUPPORTED"}
+HAPOD_EIG_MAX = 8192
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_1607_05210_amd.build`")
+_lib = C.CDLL(LIB_PATH)
+
+_i32, _i64, _dbl, _vp = C.c_int32, C.c_int64, C.c_double, C.c_void_p
+_pi64, _pdbl, _pi32 = C.POINTER(C.c_int64), C.POINTER(C.c_double), C.POINTER(C.c_int32)
+
+
+class HapodTree(C.Structure):
+    _fields_ = [("num_nodes", _i32), ("parent", _pi32), ("leaf_cols", _pi64), ("n", _i64)]
+
+
+class HapodOptions(C.Structure):
+    _fields_ = [("prec", _i32), ("reorth", _i32), ("mem_cap_bytes", _i64),
+                ("node_eps_override", _pdbl), ("jacobi_max", _i32)]
+
+
+LEAF_FN = C.CFUNCTYPE(_i32, _vp, _i32, C.POINTER(_vp), _pi64, _vp)
+
+_SIGS = {
+    "hapod_gram": [_i32, _i64, _i64, _vp, _i64, _vp, _i64, _vp],
+    "hapod_eigh": [_i64, _vp, _i64, _vp, _vp, _i64, _pi32, _vp],
+    "hapod_truncate": [_i64, _vp, _dbl, _pi64, _pdbl, _vp],
+    "hapod_lift": [_i32, _i64, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _vp, _i64, _vp],
+    "hapod_reorth": [_i32, _i64, _i64, _vp, _i64, _pi64, _vp],
+    "hapod_node_pod": [_i32, _i64, _i64, _vp, _i64, _dbl, _i32, _vp, _i64, _pdbl, _pi64, _vp],
+    "hapod_plan": [C.POINTER(HapodTree), _dbl, _dbl, C.POINTER(HapodOptions), C.POINTER(_vp)],
+    "hapod_plan_query": [_vp, _pdbl, _pi32, _pi64],
+    "hapod_run": [_vp, LEAF_FN, _vp, _vp],
+    "hapod_modes": [_vp, _i32, _vp, _i64, _pdbl, _pi64, _vp],
+    "hapod_node_stats": [_vp, _pi64, _pi64, _pdbl, _pdbl],
+    "hapod_run_timing": [_vp, _pdbl],
+}
+for _name, _args in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.argtypes = _args
+    _f.restype = _i32
+_lib.hapod_destroy.argtypes = [_vp]
+_lib.hapod_destroy.restype = None
+_lib.hapod_last_error.argtypes = []
+_lib.hapod_last_error.restype = C.c_char_p
+
+EXPORTED = sorted(list(_SIGS) + ["hapod_destroy", "hapod_last_error"])
+
+
+class HapodError(RuntimeError):
+    def __init__(self, status, where):
+        self.status = status
+        msg = _lib.hapod_last_error().decode(errors="replace")
+        super().__init__(f"{where}: {STATUS.get(status, status)}: {msg}")
+
+
+def _check(st, where):
+    if st != 0:
+        raise HapodError(st, where)
+
+
+def hapod_last_error() -> str:
+    return _lib.hapod_last_error().decode(errors="replace")
+
+
+# ---------------------------------------------------------------------------
+# marshalling helpers
+# ---------------------------------------------------------------------------
+def _stream(stream=None):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def colmajor(n, m, dtype=torch.float64, device="cuda", ld=None, fill=None):
+    """Column-major n x m tensor (shape (n, m), stride (1, ld))."""
+    ld = n if ld is None else ld
+    base = torch.empty((max(m, 0), max(ld, 1)), dtype=dtype, device=device)
+    if fill is not None:
+        base.fill_(fill)
+    return base[:, :n].t() if n > 0 else base[:, :0].t()
+
+
+def _mat(t, name, dtype=None):
+    """(pointer, rows, cols, ld) of a column-major tensor."""
+    if t.dim() != 2:
+        raise ValueError(f"{name}: expected a 2-D tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name}: expected {dtype}, got {t.dtype}")
+    n, m = t.shape
+    if m > 1 and n > 0 and t.stride(0) != 1:
+        raise ValueError(f"{name}: must be column-major (stride(0) == 1)")
+    ld = t.stride(1) if m > 1 else max(n, 1)
+    return C.c_void_p(t.data_ptr()), n, m, max(ld, 1)
+
+
+def _elem(prec):
+    return torch.float64 if prec == FP64 else torch.float32
+
+
+def _prec(p):
+    return PRECISIONS[p] if isinstance(p, str) else int(p)
+
+
+# ---------------------------------------------------------------------------
+# step-level entry points
+# ---------------------------------------------------------------------------
+def hapod_gram(prec, S, G=None, stream=None):
+    prec = _prec(prec)
+    p, n, m, lds = _mat(S, "S", _elem(prec))
+    if G is None:
+        G = colmajor(m, m, torch.float64, S.device)
+    pg, _, _, ldg = _mat(G, "G", torch.float64)
+    _check(_lib.hapod_gram(prec, n, m, p, lds, pg, ldg, _stream(stream)), "hapod_gram")
+    return G
+
+
+def hapod_eigh(G, stream=None):
+    """Destroys G.  Returns (lambda, V, sweeps)."""
+    pg, m, _, ldg = _mat(G, "G", torch.float64)
+    lam = torch.empty(m, dtype=torch.float64, device=G.device)
+    V = colmajor(m, m, torch.float64, G.device)
+    pv, _, _, ldv = _mat(V, "V")
+    sw = C.c_int32(0)
+    _check(_lib.hapod_eigh(m, pg, ldg, C.c_void_p(lam.data_ptr()), pv, ldv, C.byref(sw), _stream(stream)),
+           "hapod_eigh")
+    return lam, V, sw.value
+
+
+def hapod_truncate(lam, eps, stream=None):
+    """Returns (rank, info[4])."""
+    r = C.c_int64(0)
+    info = (C.c_double * 4)()
+    _check(_lib.hapod_truncate(lam.numel(), C.c_void_p(lam.data_ptr()), float(eps), C.byref(r), info,
+                               _stream(stream)), "hapod_truncate")
+    return r.value, list(info)
+
+
+def hapod_lift(prec, S, V, N, lam=None, out=None, stream=None):
+    prec = _prec(prec)
+    ps, n, m, lds = _mat(S, "S", _elem(prec))
+    pv, mv, _, ldv = _mat(V, "V", torch.float64)
+    if out is None:
+        out = colmajor(n, N, _elem(prec), S.device)
+    po, _, _, ldo = _mat(out, "out", _elem(prec))
+    pl = C.c_void_p(lam.data_ptr()) if lam is not None else None
+    _check(_lib.hapod_lift(prec, n, m, N, ps, lds, pv, ldv, pl, po, ldo, _stream(stream)), "hapod_lift")
+    return out
+
+
+def hapod_reorth(prec, U, stream=None):
+    prec = _prec(prec)
+    pu, n, N, ldu = _mat(U, "U", _elem(prec))
+    bad = C.c_int64(0)
+    _check(_lib.hapod_reorth(prec, n, N, pu, ldu, C.byref(bad), _stream(stream)), "hapod_reorth")
+    return bad.value
+
+
+def hapod_node_pod(prec, S, eps, scaled=False, out=None, stream=None):
+    """Returns (sigma[rank] numpy, out[:, :rank])."""
+    import numpy as np
+    prec = _prec(prec)
+    ps, n, m, lds = _mat(S, "S", _elem(prec))
+    if out is None:
+        out = colmajor(n, m, _elem(prec), S.device)
+    po, _, _, ldo = _mat(out, "out", _elem(prec))
+    sig = np.zeros(max(m, 1))
+    r = C.c_int64(0)
+    _check(_lib.hapod_node_pod(prec, n, m, ps, lds, float(eps), int(bool(scaled)), po, ldo,
+                               sig.ctypes.data_as(_pdbl), C.byref(r), _stream(stream)), "hapod_node_pod")
+    return sig[:r.value].copy(), out[:, :r.value]
+
+
+# ---------------------------------------------------------------------------
+# plans
+# ---------------------------------------------------------------------------
+class Plan:
+    """Owns a ``hapod_plan_t``; ``run`` feeds device tensors as the leaves."""
+
+    _destroy = _lib.hapod_destroy
+
+    def __init__(self, parent, leaf_cols, n, eps_star, omega, prec="fp64", reorth=False,
+                 mem_cap_bytes=0, eps_override=None, jacobi_max=0):
+        import numpy as np
+        self.num_nodes = len(parent)
+        self.n = int(n)
+        self.prec = _prec(prec)
+        self._parent = (C.c_int32 * self.num_nodes)(*[int(p) for p in parent])
+        self._cols = (C.c_int64 * self.num_nodes)(*[int(c) for c in leaf_cols])
+        tree = HapodTree(self.num_nodes, self._parent, self._cols, self.n)
+        ov = None
+        if eps_override is not None:
+            arr = np.asarray(eps_override, dtype=np.float64)
+            ov = arr.ctypes.data_as(_pdbl)
+        opts = HapodOptions(self.prec, int(bool(reorth)), int(mem_cap_bytes), ov, int(jacobi_max))
+        h = C.c_void_p()
+        _check(_lib.hapod_plan(C.byref(tree), float(eps_star), float(omega), C.byref(opts), C.byref(h)),
+               "hapod_plan")
+        self._h = h
+        self._keep = []
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            Plan._destroy(h)
+            self._h = None
+
+    def query(self):
+        import numpy as np
+        eps = np.zeros(self.num_nodes)
+        lev = np.zeros(self.num_nodes, dtype=np.int32)
+        acc = np.zeros(self.num_nodes, dtype=np.int64)
+        _check(_lib.hapod_plan_query(self._h, eps.ctypes.data_as(_pdbl), lev.ctypes.data_as(_pi32),
+                                     acc.ctypes.data_as(_pi64)), "hapod_plan_query")
+        return eps, lev, acc
+
+    def run(self, leaves, stream=None):
+        """``leaves``: dict leaf id -> column-major device tensor, or a
+        callable leaf id -> tensor (called once per leaf, in level order)."""
+        elem = _elem(self.prec)
+        held = {}
+        err = []
+
+        def cb(user, leaf, ptr, ld, s):
+            try:
+                t = leaves(leaf) if callable(leaves) else leaves[leaf]
+                p, n, m, ldt = _mat(t, f"leaf {leaf}", elem)
+                held[leaf] = t
+                ptr[0] = p.value
+                ld[0] = ldt
+                return 0
+            except Exception as e:  # reported through HAPOD_E_CALLBACK
+                err.append(e)
+                return 1
+
+        fn = LEAF_FN(cb)
+        st = _lib.hapod_run(self._h, fn, None, _stream(stream))
+        if st != 0 and err:
+            raise HapodError(st, f"hapod_run ({err[0]!r})")
+        _check(st, "hapod_run")
+        return self
+
+    def modes(self, node=-1, with_U=True, stream=None):
+        import numpy as np
+        r = C.c_int64(0)
+        _check(_lib.hapod_modes(self._h, node, None, self.n, None, C.byref(r), _stream(stream)), "hapod_modes")
+        N = r.value
+        sig = np.zeros(max(N, 1))
+        U = colmajor(self.n, N, _elem(self.prec)) if with_U else None
+        pu = C.c_void_p(U.data_ptr()) if U is not None and N > 0 else None
+        _check(_lib.hapod_modes(self._h, node, pu, self.n, sig.ctypes.data_as(_pdbl), C.byref(r),
+                                _stream(stream)), "hapod_modes")
+        return sig[:N].copy(), U
+
+    def node_stats(self):
+        import numpy as np
+        k = self.num_nodes
+        m_in = np.zeros(k, dtype=np.int64)
+        nneg = np.zeros(k, dtype=np.int64)
+        l1 = np.zeros(k)
+        lmin = np.zeros(k)
+        _check(_lib.hapod_node_stats(self._h, m_in.ctypes.data_as(_pi64), nneg.ctypes.data_as(_pi64),
+                                     l1.ctypes.data_as(_pdbl), lmin.ctypes.data_as(_pdbl)), "hapod_node_stats")
+        return dict(m_in=m_in, n_negative=nneg, lambda1=l1, lambda_min=lmin)
+
+    def ranks(self):
+        import numpy as np
+        out = np.zeros(self.num_nodes, dtype=np.int64)
+        for a in range(self.num_nodes):
+            r = C.c_int64(0)
+            _check(_lib.hapod_modes(self._h, a, None, self.n, None, C.byref(r), None), "hapod_modes")
+            out[a] = r.value
+        return out
+
+    def timing(self):
+        t = (C.c_double * 6)()
+        _check(_lib.hapod_run_timing(self._h, t), "hapod_run_timing")
+        return dict(zip(["total", "gram", "eig", "truncate", "lift", "reorth"], list(t)))
+
+
+def hapod_plan(parent, leaf_cols, n, eps_star, omega, **kw) -> Plan:
+    return Plan(parent, leaf_cols, n, eps_star, omega, **kw)

@@ -1,0 +1,1189 @@
+// C ABI of the HAPOD library: step-level entry points, the plan (tree
+// validation, levels, Thm. 3.5 tolerances) and the level scheduler.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "internal.hpp"
+#include "wide.hpp"
+
+namespace hapod {
+
+namespace {
+thread_local std::string g_last_error;
+}
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+void* pool_alloc_cb(void* pool, size_t bytes);
+void pool_free_cb(void* pool, void* p);
+hapod_status gram_impl(int compute, int eb, int64_t n, int64_t m, const void* S, int64_t lds, double* G, int64_t ldg,
+                       hipStream_t stream);
+
+namespace {
+
+int elem_bytes(hapod_precision p) { return p == HAPOD_FP64 ? 8 : 4; }
+int compute_mode(hapod_precision p) { return p == HAPOD_FP64 ? 0 : (p == HAPOD_FP32 ? 1 : 2); }
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+// ---------------------------------------------------------------------------
+// Device memory pool: exact-size reuse of freed blocks, so repeated runs of
+// the same plan allocate nothing after the first; an optional cap on the
+// bytes held.
+// ---------------------------------------------------------------------------
+class Pool {
+ public:
+  ~Pool() { release_all(); }
+  hapod_status alloc(size_t bytes, void** out) {
+    bytes = align_up(std::max<size_t>(bytes, kAlign));
+    auto it = free_.find(bytes);
+    if (it != free_.end() && !it->second.empty()) {
+      *out = it->second.back();
+      it->second.pop_back();
+      return HAPOD_OK;
+    }
+    if (cap_ && held_ + bytes > cap_) {
+      // give cached blocks back before failing
+      trim();
+      if (held_ + bytes > cap_) {
+        set_error("device memory cap exceeded: need " + std::to_string(held_ + bytes) + " bytes, cap " +
+                  std::to_string(cap_));
+        return HAPOD_E_NOMEM;
+      }
+    }
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+      trim();
+      e = hipMalloc(&p, bytes);
+      if (e != hipSuccess) {
+        (void)hipGetLastError();
+        set_error("hipMalloc of " + std::to_string(bytes) + " bytes failed");
+        return HAPOD_E_NOMEM;
+      }
+    }
+    size_of_[p] = bytes;
+    held_ += bytes;
+    *out = p;
+    return HAPOD_OK;
+  }
+  void free(void* p) {
+    if (!p) return;
+    auto it = size_of_.find(p);
+    if (it == size_of_.end()) return;
+    free_[it->second].push_back(p);
+  }
+  void trim() {
+    for (auto& kv : free_)
+      for (void* p : kv.second) {
+        held_ -= size_of_[p];
+        size_of_.erase(p);
+        (void)hipFree(p);
+      }
+    free_.clear();
+  }
+  void release_all() {
+    for (auto& kv : size_of_) (void)hipFree(kv.first);
+    size_of_.clear();
+    free_.clear();
+    held_ = 0;
+  }
+  void set_cap(size_t c) { cap_ = c; }
+  size_t held() const { return held_; }
+
+ private:
+  std::map<size_t, std::vector<void*>> free_;
+  std::map<void*, size_t> size_of_;
+  size_t held_ = 0, cap_ = 0;
+};
+
+// Host staging blob that becomes one device blob (descriptor tables).
+struct Blob {
+  std::vector<char> host;
+  size_t add(const void* p, size_t bytes) {
+    size_t off = align_up(host.size());
+    host.resize(off + bytes);
+    if (bytes) std::memcpy(host.data() + off, p, bytes);
+    return off;
+  }
+  template <class T> size_t add_vec(const std::vector<T>& v) { return add(v.data(), v.size() * sizeof(T)); }
+};
+
+// ---------------------------------------------------------------------------
+// One batch of local PODs (all nodes of a level, or a single node).
+// ---------------------------------------------------------------------------
+struct PodJob {
+  // inputs
+  std::vector<const void*> cols;  // host copy of the column pointers
+  int64_t n = 0;
+  int64_t m = 0;
+  double eps = 0.0;
+  bool root = false;    // lift with Lambda^{-1/2}
+  void* out = nullptr;  // n x m capacity
+  int64_t ldo = 0;
+  // outputs (host, after sync)
+  int64_t rank = 0;
+  std::vector<double> sigma;
+  double info[6] = {0, 0, 0, 0, 0, 0};
+  int32_t sweeps = 0;
+  bool wide = false;
+};
+
+struct PhaseTimes {
+  float gram = 0, eig = 0, trunc = 0, lift = 0;
+};
+
+struct Events {
+  hipEvent_t e[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  bool ok = false;
+  Events() {
+    ok = true;
+    for (auto& x : e)
+      if (hipEventCreate(&x) != hipSuccess) ok = false;
+  }
+  ~Events() {
+    for (auto& x : e)
+      if (x) (void)hipEventDestroy(x);
+  }
+};
+
+int pick_chunks(int64_t n, int pairs, int target_items, int64_t min_rows) {
+  int64_t want = std::max<int64_t>(1, (target_items + pairs - 1) / pairs);
+  int64_t maxc = std::max<int64_t>(1, n / std::max<int64_t>(min_rows, 1));
+  return (int)std::max<int64_t>(1, std::min(want, maxc));
+}
+
+hapod_status run_pod_batch(hapod_precision prec, std::vector<PodJob>& jobs, int policy_small, int policy_wide,
+                           int jacobi_max, Pool& pool, hipStream_t stream, PhaseTimes* times) {
+  const int compute = compute_mode(prec);
+  const int eb = elem_bytes(prec);
+  const int nj = (int)jobs.size();
+  if (nj == 0) return HAPOD_OK;
+  const double u_p = (prec == HAPOD_FP64) ? std::ldexp(1.0, -53) : std::ldexp(1.0, -24);
+
+  // ---- sizes & scratch layout ---------------------------------------------
+  struct Lay {
+    size_t cols, G, partial, lam, V, B, sigma, rank, info, jwork, vwork, sweeps;
+    int ntiles, pairs, nchunks;
+    int64_t chunk_rows;
+  };
+  std::vector<Lay> lay(nj);
+  size_t total = 0;
+  int total_pairs = 0;
+  const int KB = (compute == 2) ? 32 : 16;
+  // enough row chunks to give every CU several workgroups
+  int sum_pairs = 0;
+  for (auto& j : jobs) {
+    int nt = (int)((j.m + kGramTile - 1) / kGramTile);
+    sum_pairs += nt * (nt + 1) / 2;
+  }
+  const int target_items = std::max(2048, sum_pairs);
+  for (int i = 0; i < nj; ++i) {
+    PodJob& j = jobs[i];
+    Lay& L = lay[i];
+    const int64_t m = j.m;
+    j.wide = (m > jacobi_max);
+    L.ntiles = (int)((m + kGramTile - 1) / kGramTile);
+    L.pairs = L.ntiles * (L.ntiles + 1) / 2;
+    const int per_node_target = std::max(1, (int)((int64_t)target_items * L.pairs / std::max(sum_pairs, 1)));
+    L.nchunks = pick_chunks(j.n, L.pairs, per_node_target, 2048);
+    int64_t cr = (j.n + L.nchunks - 1) / L.nchunks;
+    cr = (cr + 63) / 64 * 64;
+    if (cr < KB) cr = KB;
+    L.chunk_rows = cr;
+    L.nchunks = (int)std::max<int64_t>(1, (j.n + cr - 1) / cr);
+    auto take = [&](size_t bytes) {
+      size_t off = total;
+      total = align_up(total + bytes);
+      return off;
+    };
+    L.cols = take(sizeof(void*) * std::max<int64_t>(m, 1));
+    L.G = take(sizeof(double) * m * m);
+    L.partial = (L.nchunks > 1) ? take(sizeof(double) * (size_t)L.pairs * L.nchunks * kGramTile * kGramTile) : 0;
+    L.lam = take(sizeof(double) * std::max<int64_t>(m, 1));
+    L.V = take(sizeof(double) * m * m);
+    L.B = take(sizeof(double) * m * m);
+    L.sigma = take(sizeof(double) * std::max<int64_t>(m, 1));
+    L.rank = take(sizeof(int64_t));
+    L.info = take(sizeof(double) * 8);
+    L.jwork = (!j.wide && m > kJacobiLdsMax) ? take(sizeof(double) * jacobi_work_doubles((int)m)) : 0;
+    L.vwork = (!j.wide) ? take(sizeof(double) * jacobi_vwork_doubles((int)std::max<int64_t>(m, 1))) : 0;
+    L.sweeps = take(sizeof(int32_t) * 2);
+    total_pairs += L.pairs;
+  }
+  const size_t flag_off = total;
+  total = align_up(total + 64);
+  char* scratch = nullptr;
+  HAPOD_TRY(pool.alloc(total, (void**)&scratch));
+  struct Guard {
+    Pool& p;
+    void* s;
+    ~Guard() { p.free(s); }
+  } guard{pool, scratch};
+
+  // ---- descriptor tables ----------------------------------------------------
+  std::vector<GramNode> gnodes(nj);
+  std::vector<GramItem> gitems;
+  std::vector<int32_t> rpairs, rnode;
+  std::vector<EigNode> enodes_small, enodes_big;
+  std::vector<TruncNode> tnodes(nj);
+  std::vector<LiftNode> lnodes;
+  bool vec_ok = true;
+  int pair_base = 0, lift_items = 0, max_small = 0, max_big = 0;
+  for (int i = 0; i < nj; ++i) {
+    PodJob& j = jobs[i];
+    Lay& L = lay[i];
+    const int64_t m = j.m;
+    for (const void* c : j.cols)
+      if (((uintptr_t)c & 15u) != 0) vec_ok = false;
+    if (L.chunk_rows % KB) vec_ok = false;
+    GramNode& g = gnodes[i];
+    g.cols = (const void* const*)(scratch + L.cols);
+    g.n = j.n;
+    g.chunk_rows = L.chunk_rows;
+    g.G = (double*)(scratch + L.G);
+    g.partial = L.nchunks > 1 ? (double*)(scratch + L.partial) : nullptr;
+    g.ldg = m;
+    g.m = (int32_t)m;
+    g.nchunks = L.nchunks;
+    g.ntiles = L.ntiles;
+    g.pair_base = pair_base;
+    int p = pair_base;
+    for (int ti = 0; ti < L.ntiles; ++ti)
+      for (int tj = ti; tj < L.ntiles; ++tj, ++p) {
+        for (int c = 0; c < L.nchunks; ++c) gitems.push_back(GramItem{i, (int16_t)ti, (int16_t)tj, c, p});
+        if (L.nchunks > 1) {
+          rpairs.push_back(p);
+          rnode.push_back(i);
+        }
+      }
+    pair_base = p;
+    if (!j.wide && m > 0) {
+      EigNode e{};
+      e.G = g.G;
+      e.work = L.jwork ? (double*)(scratch + L.jwork) : nullptr;
+      e.Vwork = (double*)(scratch + L.vwork);
+      e.lambda = (double*)(scratch + L.lam);
+      e.V = (double*)(scratch + L.V);
+      e.ldg = m;
+      e.ldv = m;
+      e.m = (int32_t)m;
+      e.sweeps = (int32_t*)(scratch + L.sweeps);
+      if (m <= kJacobiLdsMax) {
+        enodes_small.push_back(e);
+        max_small = std::max<int>(max_small, (int)m);
+      } else {
+        enodes_big.push_back(e);
+        max_big = std::max<int>(max_big, (int)m);
+      }
+    }
+    TruncNode& t = tnodes[i];
+    t.lambda = (double*)(scratch + L.lam);
+    t.V = (double*)(scratch + L.V);
+    t.B = (double*)(scratch + L.B);
+    t.sigma = (double*)(scratch + L.sigma);
+    t.rank = (int64_t*)(scratch + L.rank);
+    t.info = (double*)(scratch + L.info);
+    t.eps2 = j.eps * j.eps;
+    t.floor_abs = 0.0;
+    t.ldv = m;
+    t.ldb = std::max<int64_t>(m, 1);
+    t.m = (int32_t)m;
+    t.policy = j.wide ? policy_wide : policy_small;
+    t.root = j.root ? 1 : 0;
+    if (m > 0 && j.n > 0) {
+      LiftNode l{};
+      l.cols = g.cols;
+      l.B = t.B;
+      l.rank = t.rank;
+      l.out = j.out;
+      l.n = j.n;
+      l.ldb = t.ldb;
+      l.ldo = j.ldo;
+      l.m = (int32_t)m;
+      l.row_tiles = (int32_t)((j.n + kLiftTileM - 1) / kLiftTileM);
+      l.col_tiles = (int32_t)((m + kLiftTileN - 1) / kLiftTileN);
+      l.item_base = lift_items;
+      lift_items += l.row_tiles * l.col_tiles;
+      lnodes.push_back(l);
+    }
+  }
+
+  Blob blob;
+  std::vector<size_t> col_off(nj);
+  for (int i = 0; i < nj; ++i) col_off[i] = blob.add_vec(jobs[i].cols);
+  const size_t o_g = blob.add_vec(gnodes), o_gi = blob.add_vec(gitems), o_rp = blob.add_vec(rpairs),
+               o_rn = blob.add_vec(rnode), o_es = blob.add_vec(enodes_small), o_eb = blob.add_vec(enodes_big),
+               o_t = blob.add_vec(tnodes), o_l = blob.add_vec(lnodes);
+  char* dblob = nullptr;
+  HAPOD_TRY(pool.alloc(blob.host.size(), (void**)&dblob));
+  struct Guard2 {
+    Pool& p;
+    void* s;
+    ~Guard2() { p.free(s); }
+  } guard2{pool, dblob};
+  HAPOD_HIP(hipMemcpyAsync(dblob, blob.host.data(), blob.host.size(), hipMemcpyHostToDevice, stream));
+  for (int i = 0; i < nj; ++i)
+    if (jobs[i].m > 0)
+      HAPOD_HIP(hipMemcpyAsync(scratch + lay[i].cols, dblob + col_off[i], sizeof(void*) * jobs[i].m,
+                               hipMemcpyDeviceToDevice, stream));
+  int32_t* d_flag = (int32_t*)(scratch + flag_off);
+  HAPOD_HIP(hipMemsetAsync(d_flag, 0, 64, stream));
+
+  Events ev;
+  if (times && ev.ok) HAPOD_HIP(hipEventRecord(ev.e[0], stream));
+  // ---- Gram -----------------------------------------------------------------
+  HAPOD_TRY(launch_gram(compute, (const GramNode*)(dblob + o_g), (const GramItem*)(dblob + o_gi), (int)gitems.size(),
+                        (const int32_t*)(dblob + o_rp), (const int32_t*)(dblob + o_rn), (int)rpairs.size(), vec_ok,
+                        stream));
+  for (int i = 0; i < nj; ++i) HAPOD_TRY(launch_check_diag(gnodes[i].G, gnodes[i].ldg, jobs[i].m, d_flag, stream));
+  if (times && ev.ok) HAPOD_HIP(hipEventRecord(ev.e[1], stream));
+  // ---- eigensolve -----------------------------------------------------------
+  if (!enodes_small.empty())
+    HAPOD_TRY(launch_jacobi((const EigNode*)(dblob + o_es), (int)enodes_small.size(), max_small, stream));
+  if (!enodes_big.empty())
+    HAPOD_TRY(launch_jacobi((const EigNode*)(dblob + o_eb), (int)enodes_big.size(), max_big, stream));
+  for (int i = 0; i < nj; ++i) {
+    if (!jobs[i].wide) continue;
+    WideResult wr;
+    HAPOD_TRY(wide_eigh(gnodes[i].G, jobs[i].m, jobs[i].m, (double*)(scratch + lay[i].lam),
+                        (double*)(scratch + lay[i].V), jobs[i].m, u_p, &pool_alloc_cb, &pool_free_cb,
+                        &pool, stream, &wr));
+    // eigenvalues beyond the computed block are set to zero by wide_eigh;
+    // the floor of the truncation is the Gram's rounding level
+    tnodes[i].floor_abs = wr.floor_abs;
+    jobs[i].sweeps = wr.iterations;
+  }
+  if (times && ev.ok) HAPOD_HIP(hipEventRecord(ev.e[2], stream));
+  // wide nodes changed floor_abs on the host: refresh their descriptors
+  for (int i = 0; i < nj; ++i)
+    if (jobs[i].wide)
+      HAPOD_HIP(hipMemcpyAsync(dblob + o_t + i * sizeof(TruncNode), &tnodes[i], sizeof(TruncNode),
+                               hipMemcpyHostToDevice, stream));
+  // ---- truncation -----------------------------------------------------------
+  HAPOD_TRY(launch_truncate((const TruncNode*)(dblob + o_t), nj, stream));
+  if (times && ev.ok) HAPOD_HIP(hipEventRecord(ev.e[3], stream));
+  // ---- lift -----------------------------------------------------------------
+  HAPOD_TRY(launch_lift(compute, (const LiftNode*)(dblob + o_l), (int)lnodes.size(), lift_items, stream));
+  if (times && ev.ok) HAPOD_HIP(hipEventRecord(ev.e[4], stream));
+
+  // ---- results ----------------------------------------------------------------
+  HAPOD_HIP(hipStreamSynchronize(stream));
+  int32_t flag = 0;
+  HAPOD_HIP(hipMemcpy(&flag, d_flag, sizeof(flag), hipMemcpyDeviceToHost));
+  if (flag) {
+    set_error("non-finite Gram diagonal: the input holds NaN or Inf");
+    return HAPOD_E_NUMERIC;
+  }
+  for (int i = 0; i < nj; ++i) {
+    PodJob& j = jobs[i];
+    HAPOD_HIP(hipMemcpy(&j.rank, scratch + lay[i].rank, sizeof(int64_t), hipMemcpyDeviceToHost));
+    HAPOD_HIP(hipMemcpy(j.info, scratch + lay[i].info, sizeof(double) * 6, hipMemcpyDeviceToHost));
+    j.sigma.assign((size_t)j.rank, 0.0);
+    if (j.rank > 0)
+      HAPOD_HIP(hipMemcpy(j.sigma.data(), scratch + lay[i].sigma, sizeof(double) * j.rank, hipMemcpyDeviceToHost));
+    if (!j.wide && j.m > 0)
+      HAPOD_HIP(hipMemcpy(&j.sweeps, scratch + lay[i].sweeps, sizeof(int32_t), hipMemcpyDeviceToHost));
+  }
+  if (times && ev.ok) {
+    float a = 0;
+    if (hipEventElapsedTime(&a, ev.e[0], ev.e[1]) == hipSuccess) times->gram += a;
+    if (hipEventElapsedTime(&a, ev.e[1], ev.e[2]) == hipSuccess) times->eig += a;
+    if (hipEventElapsedTime(&a, ev.e[2], ev.e[3]) == hipSuccess) times->trunc += a;
+    if (hipEventElapsedTime(&a, ev.e[3], ev.e[4]) == hipSuccess) times->lift += a;
+  }
+  return HAPOD_OK;
+}
+
+std::vector<const void*> column_table(const void* base, int64_t ld, int64_t m, int eb) {
+  std::vector<const void*> v((size_t)m);
+  for (int64_t j = 0; j < m; ++j) v[j] = (const char*)base + j * ld * eb;
+  return v;
+}
+
+hapod_status check_prec(hapod_precision p) {
+  if (p != HAPOD_FP64 && p != HAPOD_FP32 && p != HAPOD_BF16X3) {
+    set_error("unknown precision");
+    return HAPOD_E_INVALID;
+  }
+  return HAPOD_OK;
+}
+
+// Pool used by the step-level entry points (no plan).
+Pool& step_pool() {
+  static Pool p;
+  return p;
+}
+
+}  // namespace
+
+// pool callbacks for wide_eigh
+void* pool_alloc_cb(void* pool, size_t bytes) {
+  void* p = nullptr;
+  if (static_cast<Pool*>(pool)->alloc(bytes, &p) != HAPOD_OK) return nullptr;
+  return p;
+}
+void pool_free_cb(void* pool, void* p) { static_cast<Pool*>(pool)->free(p); }
+
+}  // namespace hapod
+
+using namespace hapod;
+
+// ===========================================================================
+// Plan
+// ===========================================================================
+struct hapod_plan_s {
+  int32_t num_nodes = 0;
+  std::vector<int32_t> parent;
+  std::vector<int64_t> leaf_cols;
+  int64_t n = 0;
+  hapod_options opts{};
+  std::vector<double> eps;
+  std::vector<int32_t> level;
+  std::vector<int64_t> acc;
+  std::vector<std::vector<int32_t>> children;
+  std::vector<std::vector<int32_t>> by_level;  // index 0 = level 1
+  int32_t root = -1;
+  // last run
+  bool has_result = false;
+  std::vector<int64_t> rank, m_in, n_neg;
+  std::vector<double> lam1, lam_min;
+  std::vector<std::vector<double>> sigma;
+  void* root_U = nullptr;  // owned by the pool
+  bool root_passthrough = false;
+  std::vector<const void*> root_cols;  // pass-through root: its input columns
+  double timing[6] = {0, 0, 0, 0, 0, 0};
+  Pool pool;
+};
+
+extern "C" {
+
+const char* hapod_last_error(void) { return g_last_error.c_str(); }
+
+hapod_status hapod_plan(const hapod_tree* tree, double eps_star, double omega, const hapod_options* opts,
+                        hapod_plan_t* out) {
+  if (!tree || !out || !tree->parent || !tree->leaf_cols) {
+    set_error("hapod_plan: NULL argument");
+    return HAPOD_E_INVALID;
+  }
+  if (!(eps_star >= 0.0) || !(omega >= 0.0 && omega <= 1.0) || tree->n <= 0 || tree->num_nodes <= 0) {
+    set_error("hapod_plan: need eps_star >= 0, 0 <= omega <= 1, n > 0, num_nodes > 0");
+    return HAPOD_E_INVALID;
+  }
+  if (opts) HAPOD_TRY(check_prec(opts->prec));
+  auto P = std::make_unique<hapod_plan_s>();
+  const int32_t nn = tree->num_nodes;
+  P->num_nodes = nn;
+  P->parent.assign(tree->parent, tree->parent + nn);
+  P->leaf_cols.assign(tree->leaf_cols, tree->leaf_cols + nn);
+  P->n = tree->n;
+  if (opts) P->opts = *opts;
+  else {
+    P->opts.prec = HAPOD_FP64;
+  }
+  // ---- Def. 3.1: one root, parents in range, everything reaches the root ----
+  int roots = 0;
+  for (int32_t i = 0; i < nn; ++i) {
+    const int32_t p = P->parent[i];
+    if (p == -1) {
+      ++roots;
+      P->root = i;
+    } else if (p < 0 || p >= nn || p == i) {
+      set_error("hapod_plan: parent[" + std::to_string(i) + "] out of range");
+      return HAPOD_E_TREE;
+    }
+  }
+  if (roots != 1) {
+    set_error("hapod_plan: expected exactly one root, found " + std::to_string(roots));
+    return HAPOD_E_TREE;
+  }
+  for (int32_t i = 0; i < nn; ++i) {
+    int32_t j = i, steps = 0;
+    while (j != P->root) {
+      j = P->parent[j];
+      if (++steps > nn) {
+        set_error("hapod_plan: node " + std::to_string(i) + " is on a cycle");
+        return HAPOD_E_TREE;
+      }
+    }
+  }
+  P->children.assign(nn, {});
+  for (int32_t i = 0; i < nn; ++i)
+    if (P->parent[i] >= 0) P->children[P->parent[i]].push_back(i);
+  for (int32_t i = 0; i < nn; ++i)
+    if (P->children[i].empty() && P->leaf_cols[i] < 0) {
+      set_error("hapod_plan: negative leaf column count");
+      return HAPOD_E_INVALID;
+    }
+  // ---- levels (height) and |S~_alpha| by a children-first order --------------
+  std::vector<int32_t> order;
+  order.reserve(nn);
+  {
+    std::vector<std::pair<int32_t, bool>> st{{P->root, false}};
+    while (!st.empty()) {
+      auto [a, done] = st.back();
+      st.pop_back();
+      if (done) {
+        order.push_back(a);
+        continue;
+      }
+      st.push_back({a, true});
+      for (auto it = P->children[a].rbegin(); it != P->children[a].rend(); ++it) st.push_back({*it, false});
+    }
+  }
+  P->level.assign(nn, 0);
+  P->acc.assign(nn, 0);
+  for (int32_t a : order) {
+    int32_t lv = 0;
+    int64_t cnt = 0;
+    for (int32_t b : P->children[a]) {
+      lv = std::max(lv, P->level[b]);
+      cnt += P->acc[b];
+    }
+    P->level[a] = lv + 1;
+    P->acc[a] = P->children[a].empty() ? P->leaf_cols[a] : cnt;
+  }
+  const int32_t LT = P->level[P->root];
+  P->by_level.assign(LT, {});
+  for (int32_t i = 0; i < nn; ++i) P->by_level[P->level[i] - 1].push_back(i);
+  // ---- Thm. 3.5 ----------------------------------------------------------------
+  P->eps.assign(nn, 0.0);
+  const double total = (double)P->acc[P->root];
+  for (int32_t a = 0; a < nn; ++a) {
+    if (a == P->root)
+      P->eps[a] = std::sqrt(total) * omega * eps_star;
+    else
+      P->eps[a] = std::sqrt((double)P->acc[a]) / std::sqrt((double)(LT - 1)) * std::sqrt(1.0 - omega * omega) *
+                  eps_star;
+  }
+  if (P->opts.node_eps_override)
+    for (int32_t a = 0; a < nn; ++a)
+      if (P->opts.node_eps_override[a] >= 0.0) P->eps[a] = P->opts.node_eps_override[a];
+  P->opts.node_eps_override = nullptr;  // not kept beyond the call
+  if (P->opts.mem_cap_bytes > 0) P->pool.set_cap((size_t)P->opts.mem_cap_bytes);
+  *out = P.release();
+  return HAPOD_OK;
+}
+
+hapod_status hapod_plan_query(hapod_plan_t plan, double* eps, int32_t* level, int64_t* acc) {
+  if (!plan) {
+    set_error("hapod_plan_query: NULL plan");
+    return HAPOD_E_INVALID;
+  }
+  const size_t nn = plan->num_nodes;
+  if (eps) std::memcpy(eps, plan->eps.data(), nn * sizeof(double));
+  if (level) std::memcpy(level, plan->level.data(), nn * sizeof(int32_t));
+  if (acc) std::memcpy(acc, plan->acc.data(), nn * sizeof(int64_t));
+  return HAPOD_OK;
+}
+
+void hapod_destroy(hapod_plan_t plan) { delete plan; }
+
+// ===========================================================================
+// Run
+// ===========================================================================
+hapod_status hapod_run(hapod_plan_t P, hapod_leaf_fn get_leaf, void* user, void* stream_) {
+  if (!P || !get_leaf) {
+    set_error("hapod_run: NULL argument");
+    return HAPOD_E_INVALID;
+  }
+  hipStream_t stream = (hipStream_t)stream_;
+  const hapod_precision prec = P->opts.prec;
+  const int eb = elem_bytes(prec);
+  const int32_t nn = P->num_nodes;
+  const int jmax = P->opts.jacobi_max > 0 ? std::min<int>(P->opts.jacobi_max, kJacobiMax) : 256;
+  P->has_result = false;
+  if (P->root_U) {
+    P->pool.free(P->root_U);
+    P->root_U = nullptr;
+  }
+  P->root_passthrough = false;
+  P->rank.assign(nn, 0);
+  P->m_in.assign(nn, 0);
+  P->n_neg.assign(nn, 0);
+  P->lam1.assign(nn, 0.0);
+  P->lam_min.assign(nn, 0.0);
+  P->sigma.assign(nn, {});
+  for (double& t : P->timing) t = 0.0;
+
+  // per node: the column pointers it hands to its parent, and its own buffer
+  std::vector<std::vector<const void*>> out_cols(nn);
+  std::vector<void*> out_buf(nn, nullptr);
+  hipEvent_t t0 = nullptr, t1 = nullptr;
+  HAPOD_HIP(hipEventCreate(&t0));
+  HAPOD_HIP(hipEventCreate(&t1));
+  struct EvGuard {
+    hipEvent_t a, b;
+    ~EvGuard() {
+      (void)hipEventDestroy(a);
+      (void)hipEventDestroy(b);
+    }
+  } evg{t0, t1};
+  auto release_all = [&]() {
+    for (int32_t i = 0; i < nn; ++i)
+      if (out_buf[i] && i != P->root) {
+        P->pool.free(out_buf[i]);
+        out_buf[i] = nullptr;
+      }
+  };
+  HAPOD_HIP(hipEventRecord(t0, stream));
+  PhaseTimes pt;
+  const int32_t LT = (int32_t)P->by_level.size();
+  for (int32_t l = 0; l < LT; ++l) {
+    std::vector<PodJob> jobs;
+    std::vector<int32_t> job_node;
+    for (int32_t a : P->by_level[l]) {
+      std::vector<const void*> in;
+      if (P->children[a].empty()) {
+        const void* ptr = nullptr;
+        int64_t ld = 0;
+        const int32_t rc = get_leaf(user, a, &ptr, &ld, stream_);
+        if (rc != 0) {
+          release_all();
+          set_error("leaf provider returned " + std::to_string(rc) + " for leaf " + std::to_string(a));
+          return HAPOD_E_CALLBACK;
+        }
+        if ((P->leaf_cols[a] > 0 && !ptr) || ld < P->n) {
+          release_all();
+          set_error("leaf provider gave a NULL pointer or ld < n for leaf " + std::to_string(a));
+          return HAPOD_E_CALLBACK;
+        }
+        in = column_table(ptr, ld, P->leaf_cols[a], eb);
+      } else {
+        for (int32_t b : P->children[a]) in.insert(in.end(), out_cols[b].begin(), out_cols[b].end());
+      }
+      P->m_in[a] = (int64_t)in.size();
+      if (P->eps[a] == 0.0) {
+        // POD(S, 0) = {(1, s)}: no decomposition; the vectors pass through
+        P->rank[a] = (int64_t)in.size();
+        P->sigma[a].assign(in.size(), 1.0);
+        out_cols[a] = in;
+        if (a == P->root) {
+          P->root_passthrough = true;
+          P->root_cols = in;
+        }
+        continue;
+      }
+      PodJob j;
+      j.cols = std::move(in);
+      j.n = P->n;
+      j.m = (int64_t)j.cols.size();
+      j.eps = P->eps[a];
+      j.root = (a == P->root);
+      j.ldo = P->n;
+      if (j.m > 0) {
+        hapod_status s = P->pool.alloc((size_t)P->n * j.m * eb, &j.out);
+        if (s != HAPOD_OK) {
+          release_all();
+          return s;
+        }
+        out_buf[a] = j.out;
+      }
+      jobs.push_back(std::move(j));
+      job_node.push_back(a);
+    }
+    hapod_status s = run_pod_batch(prec, jobs, 0, 1, jmax, P->pool, stream, &pt);
+    if (s != HAPOD_OK) {
+      release_all();
+      return s;
+    }
+    for (size_t k = 0; k < jobs.size(); ++k) {
+      const int32_t a = job_node[k];
+      const PodJob& j = jobs[k];
+      P->rank[a] = j.rank;
+      P->sigma[a] = j.sigma;
+      P->lam1[a] = j.info[1];
+      P->lam_min[a] = j.info[2];
+      P->n_neg[a] = (int64_t)j.info[3];
+      out_cols[a] = column_table(j.out, P->n, j.rank, eb);
+      if (j.rank == 0 && out_buf[a]) {
+        P->pool.free(out_buf[a]);
+        out_buf[a] = nullptr;
+      }
+    }
+    // the children of this level are consumed
+    for (int32_t a : P->by_level[l])
+      for (int32_t b : P->children[a])
+        if (out_buf[b]) {
+          P->pool.free(out_buf[b]);
+          out_buf[b] = nullptr;
+        }
+  }
+  HAPOD_HIP(hipEventRecord(t1, stream));
+  // re-orthonormalise the root's modes
+  float reorth_ms = 0.f;
+  if (P->opts.reorth && !P->root_passthrough && out_buf[P->root] && P->rank[P->root] > 0) {
+    hipEvent_t r0 = nullptr;
+    HAPOD_HIP(hipEventCreate(&r0));
+    HAPOD_HIP(hipEventRecord(r0, stream));
+    int64_t bad = 0;
+    hapod_status s = hapod_reorth(prec, P->n, P->rank[P->root], out_buf[P->root], P->n, &bad, stream_);
+    float ms = 0;
+    (void)hipEventRecord(t1, stream);
+    (void)hipEventSynchronize(t1);
+    (void)hipEventElapsedTime(&ms, r0, t1);
+    reorth_ms = ms;
+    (void)hipEventDestroy(r0);
+    if (s != HAPOD_OK) {
+      release_all();
+      return s;
+    }
+  }
+  HAPOD_HIP(hipStreamSynchronize(stream));
+  float total_ms = 0.f;
+  (void)hipEventElapsedTime(&total_ms, t0, t1);
+  P->timing[0] = total_ms;
+  P->timing[1] = pt.gram;
+  P->timing[2] = pt.eig;
+  P->timing[3] = pt.trunc;
+  P->timing[4] = pt.lift;
+  P->timing[5] = reorth_ms;
+  P->root_U = out_buf[P->root];
+  out_buf[P->root] = nullptr;
+  release_all();
+  P->has_result = true;
+  return HAPOD_OK;
+}
+
+hapod_status hapod_modes(hapod_plan_t P, int32_t node, void* U, int64_t ldu, double* sigma, int64_t* rank,
+                         void* stream_) {
+  if (!P) {
+    set_error("hapod_modes: NULL plan");
+    return HAPOD_E_INVALID;
+  }
+  if (!P->has_result) {
+    set_error("hapod_modes: no completed run");
+    return HAPOD_E_STATE;
+  }
+  if (node == -1) node = P->root;
+  if (node < 0 || node >= P->num_nodes) {
+    set_error("hapod_modes: node out of range");
+    return HAPOD_E_INVALID;
+  }
+  const int64_t N = P->rank[node];
+  if (rank) *rank = N;
+  if (sigma && N > 0) std::memcpy(sigma, P->sigma[node].data(), sizeof(double) * N);
+  if (U) {
+    if (node != P->root) {
+      set_error("hapod_modes: only the root's modes are kept");
+      return HAPOD_E_STATE;
+    }
+    if (ldu < P->n) {
+      set_error("hapod_modes: ldu < n");
+      return HAPOD_E_INVALID;
+    }
+    hipStream_t stream = (hipStream_t)stream_;
+    const int eb = elem_bytes(P->opts.prec);
+    if (N > 0) {
+      if (P->root_passthrough) {
+        void* dcols = nullptr;
+        HAPOD_TRY(P->pool.alloc(sizeof(void*) * N, &dcols));
+        HAPOD_HIP(hipMemcpyAsync(dcols, P->root_cols.data(), sizeof(void*) * N, hipMemcpyHostToDevice, stream));
+        hapod_status s = launch_copy_cols(eb, P->n, N, (const void* const*)dcols, U, ldu, stream);
+        HAPOD_HIP(hipStreamSynchronize(stream));
+        P->pool.free(dcols);
+        HAPOD_TRY(s);
+      } else {
+        HAPOD_HIP(hipMemcpy2DAsync(U, (size_t)ldu * eb, P->root_U, (size_t)P->n * eb, (size_t)P->n * eb, (size_t)N,
+                                   hipMemcpyDeviceToDevice, stream));
+      }
+    }
+    HAPOD_HIP(hipStreamSynchronize(stream));
+  }
+  return HAPOD_OK;
+}
+
+hapod_status hapod_node_stats(hapod_plan_t P, int64_t* m_in, int64_t* n_negative, double* lambda1,
+                              double* lambda_min) {
+  if (!P) {
+    set_error("hapod_node_stats: NULL plan");
+    return HAPOD_E_INVALID;
+  }
+  if (!P->has_result) {
+    set_error("hapod_node_stats: no completed run");
+    return HAPOD_E_STATE;
+  }
+  const size_t nn = P->num_nodes;
+  if (m_in) std::memcpy(m_in, P->m_in.data(), nn * sizeof(int64_t));
+  if (n_negative) std::memcpy(n_negative, P->n_neg.data(), nn * sizeof(int64_t));
+  if (lambda1) std::memcpy(lambda1, P->lam1.data(), nn * sizeof(double));
+  if (lambda_min) std::memcpy(lambda_min, P->lam_min.data(), nn * sizeof(double));
+  return HAPOD_OK;
+}
+
+hapod_status hapod_run_timing(hapod_plan_t P, double* ms6) {
+  if (!P || !ms6) {
+    set_error("hapod_run_timing: NULL argument");
+    return HAPOD_E_INVALID;
+  }
+  std::memcpy(ms6, P->timing, sizeof(P->timing));
+  return HAPOD_OK;
+}
+
+// ===========================================================================
+// Step-level entry points
+// ===========================================================================
+hapod_status hapod_gram(hapod_precision prec, int64_t n, int64_t m, const void* S, int64_t lds, double* G,
+                        int64_t ldg, void* stream_) {
+  HAPOD_TRY(check_prec(prec));
+  return gram_impl(compute_mode(prec), elem_bytes(prec), n, m, S, lds, G, ldg, (hipStream_t)stream_);
+}
+
+}  // extern "C"
+
+namespace hapod {
+hapod_status gram_impl(int compute, int eb, int64_t n, int64_t m, const void* S, int64_t lds, double* G, int64_t ldg,
+                       hipStream_t stream) {
+  if (n < 0 || m < 0 || (m > 0 && (!G || (n > 0 && !S))) || lds < std::max<int64_t>(n, 1) ||
+      ldg < std::max<int64_t>(m, 1)) {
+    set_error("hapod_gram: bad sizes or NULL pointer");
+    return HAPOD_E_INVALID;
+  }
+  if (m == 0) return HAPOD_OK;
+  if (m > 65535) {
+    set_error("hapod_gram: m too large");
+    return HAPOD_E_UNSUPPORTED;
+  }
+  Pool& pool = step_pool();
+  auto cols = column_table(S, lds, m, eb);
+  const int nt = (int)((m + kGramTile - 1) / kGramTile);
+  const int pairs = nt * (nt + 1) / 2;
+  const int KB = (compute == 2) ? 32 : 16;
+  int nch = (n > 0) ? pick_chunks(n, pairs, 2048, 2048) : 1;
+  int64_t cr = (n > 0) ? ((n + nch - 1) / nch + 63) / 64 * 64 : 64;
+  nch = (n > 0) ? (int)((n + cr - 1) / cr) : 1;
+  bool vec_ok = (cr % KB == 0);
+  for (auto c : cols)
+    if ((uintptr_t)c & 15u) vec_ok = false;
+  void *dcols = nullptr, *dpart = nullptr, *dblob = nullptr;
+  HAPOD_TRY(pool.alloc(sizeof(void*) * m, &dcols));
+  if (nch > 1) HAPOD_TRY(pool.alloc(sizeof(double) * pairs * nch * kGramTile * kGramTile, &dpart));
+  GramNode g{};
+  g.cols = (const void* const*)dcols;
+  g.n = n;
+  g.chunk_rows = cr;
+  g.G = G;
+  g.partial = (double*)dpart;
+  g.ldg = ldg;
+  g.m = (int32_t)m;
+  g.nchunks = nch;
+  g.ntiles = nt;
+  g.pair_base = 0;
+  std::vector<GramItem> items;
+  std::vector<int32_t> rp, rn;
+  int p = 0;
+  for (int ti = 0; ti < nt; ++ti)
+    for (int tj = ti; tj < nt; ++tj, ++p) {
+      for (int c = 0; c < nch; ++c) items.push_back(GramItem{0, (int16_t)ti, (int16_t)tj, c, p});
+      if (nch > 1) {
+        rp.push_back(p);
+        rn.push_back(0);
+      }
+    }
+  Blob blob;
+  const size_t o_c = blob.add_vec(cols), o_g = blob.add(&g, sizeof(g)), o_i = blob.add_vec(items),
+               o_rp = blob.add_vec(rp), o_rn = blob.add_vec(rn);
+  HAPOD_TRY(pool.alloc(blob.host.size(), &dblob));
+  char* db = (char*)dblob;
+  hapod_status st = HAPOD_OK;
+  do {
+    if (hipMemcpy(db, blob.host.data(), blob.host.size(), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(dcols, db + o_c, sizeof(void*) * m, hipMemcpyDeviceToDevice) != hipSuccess) {
+      set_error("hapod_gram: descriptor upload failed");
+      st = HAPOD_E_DEVICE;
+      break;
+    }
+    if (n == 0) {
+      if (hipMemset2DAsync(G, ldg * sizeof(double), 0, m * sizeof(double), m, stream) != hipSuccess) {
+        set_error("hapod_gram: memset failed");
+        st = HAPOD_E_DEVICE;
+      }
+      break;
+    }
+    st = launch_gram(compute, (const GramNode*)(db + o_g), (const GramItem*)(db + o_i),
+                     (int)items.size(), (const int32_t*)(db + o_rp), (const int32_t*)(db + o_rn), (int)rp.size(),
+                     vec_ok, stream);
+  } while (0);
+  (void)hipStreamSynchronize(stream);
+  pool.free(dcols);
+  pool.free(dpart);
+  pool.free(dblob);
+  return st;
+}
+}  // namespace hapod
+
+extern "C" {
+
+hapod_status hapod_eigh(int64_t m, double* G, int64_t ldg, double* lambda, double* V, int64_t ldv, int32_t* sweeps,
+                        void* stream_) {
+  if (m < 0 || (m > 0 && (!G || !lambda || !V)) || ldg < std::max<int64_t>(m, 1) || ldv < std::max<int64_t>(m, 1)) {
+    set_error("hapod_eigh: bad sizes or NULL pointer");
+    return HAPOD_E_INVALID;
+  }
+  if (m == 0) return HAPOD_OK;
+  if (m > HAPOD_EIG_MAX) {
+    set_error("hapod_eigh: m above HAPOD_EIG_MAX");
+    return HAPOD_E_UNSUPPORTED;
+  }
+  hipStream_t stream = (hipStream_t)stream_;
+  Pool& pool = step_pool();
+  if (m > kJacobiMax) {
+    WideResult wr;
+    HAPOD_TRY(wide_eigh(G, ldg, m, lambda, V, ldv, std::ldexp(1.0, -53), &pool_alloc_cb, &pool_free_cb,
+                        &pool, stream, &wr));
+    HAPOD_HIP(hipStreamSynchronize(stream));
+    if (sweeps) *sweeps = wr.iterations;
+    return HAPOD_OK;
+  }
+  void *work = nullptr, *vwork = nullptr, *dn = nullptr, *dsw = nullptr;
+  if (m > kJacobiLdsMax) HAPOD_TRY(pool.alloc(sizeof(double) * jacobi_work_doubles((int)m), &work));
+  HAPOD_TRY(pool.alloc(sizeof(double) * jacobi_vwork_doubles((int)m), &vwork));
+  HAPOD_TRY(pool.alloc(sizeof(EigNode), &dn));
+  HAPOD_TRY(pool.alloc(sizeof(int32_t), &dsw));
+  EigNode e{};
+  e.G = G;
+  e.work = (double*)work;
+  e.Vwork = (double*)vwork;
+  e.lambda = lambda;
+  e.V = V;
+  e.ldg = ldg;
+  e.ldv = ldv;
+  e.m = (int32_t)m;
+  e.sweeps = (int32_t*)dsw;
+  hapod_status st = HAPOD_OK;
+  if (hipMemcpy(dn, &e, sizeof(e), hipMemcpyHostToDevice) != hipSuccess) {
+    set_error("hapod_eigh: descriptor upload failed");
+    st = HAPOD_E_DEVICE;
+  } else {
+    st = launch_jacobi((const EigNode*)dn, 1, (int)m, stream);
+  }
+  (void)hipStreamSynchronize(stream);
+  if (st == HAPOD_OK && sweeps) (void)hipMemcpy(sweeps, dsw, sizeof(int32_t), hipMemcpyDeviceToHost);
+  pool.free(work);
+  pool.free(vwork);
+  pool.free(dn);
+  pool.free(dsw);
+  return st;
+}
+
+hapod_status hapod_truncate(int64_t m, const double* lambda, double eps, int64_t* rank, double* info, void* stream_) {
+  if (m < 0 || (m > 0 && !lambda) || !rank || !(eps >= 0.0)) {
+    set_error("hapod_truncate: bad argument");
+    return HAPOD_E_INVALID;
+  }
+  hipStream_t stream = (hipStream_t)stream_;
+  Pool& pool = step_pool();
+  void *dn = nullptr, *dsig = nullptr, *drank = nullptr, *dinfo = nullptr;
+  HAPOD_TRY(pool.alloc(sizeof(TruncNode), &dn));
+  HAPOD_TRY(pool.alloc(sizeof(double) * std::max<int64_t>(m, 1), &dsig));
+  HAPOD_TRY(pool.alloc(sizeof(int64_t), &drank));
+  HAPOD_TRY(pool.alloc(sizeof(double) * 8, &dinfo));
+  TruncNode t{};
+  t.lambda = lambda;
+  t.V = nullptr;
+  t.B = nullptr;
+  t.sigma = (double*)dsig;
+  t.rank = (int64_t*)drank;
+  t.info = (double*)dinfo;
+  t.eps2 = eps * eps;
+  t.m = (int32_t)m;
+  t.policy = 0;
+  hapod_status st = HAPOD_OK;
+  if (hipMemcpy(dn, &t, sizeof(t), hipMemcpyHostToDevice) != hipSuccess) {
+    set_error("hapod_truncate: descriptor upload failed");
+    st = HAPOD_E_DEVICE;
+  } else {
+    st = launch_truncate((const TruncNode*)dn, 1, stream);
+  }
+  (void)hipStreamSynchronize(stream);
+  if (st == HAPOD_OK) {
+    double inf[6];
+    (void)hipMemcpy(rank, drank, sizeof(int64_t), hipMemcpyDeviceToHost);
+    (void)hipMemcpy(inf, dinfo, sizeof(inf), hipMemcpyDeviceToHost);
+    if (info) {
+      info[0] = inf[0];
+      info[1] = inf[1];
+      info[2] = inf[2];
+      info[3] = inf[3];
+    }
+  }
+  pool.free(dn);
+  pool.free(dsig);
+  pool.free(drank);
+  pool.free(dinfo);
+  return st;
+}
+
+hapod_status hapod_lift(hapod_precision prec, int64_t n, int64_t m, int64_t N, const void* S, int64_t lds,
+                        const double* V, int64_t ldv, const double* lambda, void* out, int64_t ldo, void* stream_) {
+  HAPOD_TRY(check_prec(prec));
+  if (n < 0 || m < 0 || N < 0 || N > std::max<int64_t>(m, 0) || lds < std::max<int64_t>(n, 1) ||
+      ldv < std::max<int64_t>(m, 1) || ldo < std::max<int64_t>(n, 1) ||
+      (n > 0 && m > 0 && N > 0 && (!S || !V || !out))) {
+    set_error("hapod_lift: bad sizes or NULL pointer");
+    return HAPOD_E_INVALID;
+  }
+  if (n == 0 || N == 0) return HAPOD_OK;
+  hipStream_t stream = (hipStream_t)stream_;
+  const int eb = elem_bytes(prec);
+  Pool& pool = step_pool();
+  auto cols = column_table(S, lds, m, eb);
+  void *dcols = nullptr, *dB = nullptr, *drank = nullptr, *dn = nullptr;
+  HAPOD_TRY(pool.alloc(sizeof(void*) * std::max<int64_t>(m, 1), &dcols));
+  HAPOD_TRY(pool.alloc(sizeof(double) * std::max<int64_t>(m * N, 1), &dB));
+  HAPOD_TRY(pool.alloc(sizeof(int64_t), &drank));
+  HAPOD_TRY(pool.alloc(sizeof(LiftNode), &dn));
+  LiftNode l{};
+  l.cols = (const void* const*)dcols;
+  l.B = (const double*)dB;
+  l.rank = (const int64_t*)drank;
+  l.out = out;
+  l.n = n;
+  l.ldb = N;
+  l.ldo = ldo;
+  l.m = (int32_t)m;
+  l.row_tiles = (int32_t)((n + kLiftTileM - 1) / kLiftTileM);
+  l.col_tiles = (int32_t)((N + kLiftTileN - 1) / kLiftTileN);
+  l.item_base = 0;
+  hapod_status st = HAPOD_OK;
+  do {
+    if (m == 0) {  // S V with no columns: zero output
+      if (hipMemset2DAsync(out, ldo * eb, 0, n * eb, N, stream) != hipSuccess) st = HAPOD_E_DEVICE;
+      break;
+    }
+    if (hipMemcpy(dcols, cols.data(), sizeof(void*) * m, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(dn, &l, sizeof(l), hipMemcpyHostToDevice) != hipSuccess) {
+      set_error("hapod_lift: descriptor upload failed");
+      st = HAPOD_E_DEVICE;
+      break;
+    }
+    st = launch_lift_operand(V, ldv, lambda, m, N, (double*)dB, N, stream);
+    if (st != HAPOD_OK) break;
+    st = launch_set_scalar_i64((int64_t*)drank, N, stream);
+    if (st != HAPOD_OK) break;
+    st = launch_lift(compute_mode(prec), (const LiftNode*)dn, 1, l.row_tiles * l.col_tiles, stream);
+  } while (0);
+  (void)hipStreamSynchronize(stream);
+  pool.free(dcols);
+  pool.free(dB);
+  pool.free(drank);
+  pool.free(dn);
+  return st;
+}
+
+hapod_status hapod_reorth(hapod_precision prec, int64_t n, int64_t N, void* U, int64_t ldu, int64_t* bad,
+                          void* stream_) {
+  HAPOD_TRY(check_prec(prec));
+  if (n < 0 || N < 0 || ldu < std::max<int64_t>(n, 1) || (n > 0 && N > 0 && !U)) {
+    set_error("hapod_reorth: bad sizes or NULL pointer");
+    return HAPOD_E_INVALID;
+  }
+  if (N > 1024) {
+    set_error("hapod_reorth: N above 1024");
+    return HAPOD_E_UNSUPPORTED;
+  }
+  if (bad) *bad = 0;
+  if (n == 0 || N == 0) return HAPOD_OK;
+  hipStream_t stream = (hipStream_t)stream_;
+  const int eb = elem_bytes(prec);
+  Pool& pool = step_pool();
+  void *W = nullptr, *Rinv = nullptr, *tmp = nullptr, *dcols = nullptr, *dn = nullptr, *drank = nullptr,
+       *dbad = nullptr;
+  HAPOD_TRY(pool.alloc(sizeof(double) * N * N, &W));
+  HAPOD_TRY(pool.alloc(sizeof(double) * N * N, &Rinv));
+  HAPOD_TRY(pool.alloc((size_t)n * N * eb, &tmp));
+  HAPOD_TRY(pool.alloc(sizeof(void*) * N, &dcols));
+  HAPOD_TRY(pool.alloc(sizeof(LiftNode), &dn));
+  HAPOD_TRY(pool.alloc(sizeof(int64_t), &drank));
+  HAPOD_TRY(pool.alloc(sizeof(int32_t), &dbad));
+  hapod_status st = HAPOD_OK;
+  int64_t total_bad = 0;
+  auto cols = column_table(U, ldu, N, eb);
+  for (int pass = 0; pass < 2 && st == HAPOD_OK; ++pass) {
+    // W = U^T U accumulated in FP64
+    st = gram_impl(prec == HAPOD_FP64 ? 0 : 3, eb, n, N, U, ldu, (double*)W, N, stream);
+    if (st != HAPOD_OK) break;
+    st = launch_chol_inv((double*)W, N, N, (double*)Rinv, N, (int32_t*)dbad, stream);
+    if (st != HAPOD_OK) break;
+    LiftNode l{};
+    l.cols = (const void* const*)dcols;
+    l.B = (const double*)Rinv;
+    l.rank = (const int64_t*)drank;
+    l.out = tmp;
+    l.n = n;
+    l.ldb = N;
+    l.ldo = n;
+    l.m = (int32_t)N;
+    l.row_tiles = (int32_t)((n + kLiftTileM - 1) / kLiftTileM);
+    l.col_tiles = (int32_t)((N + kLiftTileN - 1) / kLiftTileN);
+    if (hipMemcpyAsync(dcols, cols.data(), sizeof(void*) * N, hipMemcpyHostToDevice, stream) != hipSuccess ||
+        hipMemcpyAsync(dn, &l, sizeof(l), hipMemcpyHostToDevice, stream) != hipSuccess) {
+      set_error("hapod_reorth: upload failed");
+      st = HAPOD_E_DEVICE;
+      break;
+    }
+    st = launch_set_scalar_i64((int64_t*)drank, N, stream);
+    if (st != HAPOD_OK) break;
+    st = launch_lift(prec == HAPOD_FP64 ? 0 : 1, (const LiftNode*)dn, 1, l.row_tiles * l.col_tiles, stream);
+    if (st != HAPOD_OK) break;
+    if (hipMemcpy2DAsync(U, ldu * eb, tmp, n * eb, n * eb, N, hipMemcpyDeviceToDevice, stream) != hipSuccess) {
+      set_error("hapod_reorth: copy back failed");
+      st = HAPOD_E_DEVICE;
+      break;
+    }
+    int32_t nb = 0;
+    (void)hipStreamSynchronize(stream);
+    (void)hipMemcpy(&nb, dbad, sizeof(int32_t), hipMemcpyDeviceToHost);
+    total_bad = std::max<int64_t>(total_bad, nb);
+  }
+  (void)hipStreamSynchronize(stream);
+  if (bad) *bad = total_bad;
+  for (void* p : {W, Rinv, tmp, dcols, dn, drank, dbad}) pool.free(p);
+  return st;
+}
+
+hapod_status hapod_node_pod(hapod_precision prec, int64_t n, int64_t m, const void* S, int64_t lds, double eps,
+                            int32_t scaled, void* out, int64_t ldo, double* sigma, int64_t* rank, void* stream_) {
+  HAPOD_TRY(check_prec(prec));
+  if (n < 0 || m < 0 || !(eps >= 0.0) || !rank || lds < std::max<int64_t>(n, 1) || ldo < std::max<int64_t>(n, 1) ||
+      (n > 0 && m > 0 && (!S || !out))) {
+    set_error("hapod_node_pod: bad argument");
+    return HAPOD_E_INVALID;
+  }
+  hipStream_t stream = (hipStream_t)stream_;
+  const int eb = elem_bytes(prec);
+  if (eps == 0.0) {  // POD(S, 0) = {(1, s)}
+    if (n > 0 && m > 0)
+      HAPOD_HIP(hipMemcpy2DAsync(out, ldo * eb, S, lds * eb, n * eb, m, hipMemcpyDeviceToDevice, stream));
+    HAPOD_HIP(hipStreamSynchronize(stream));
+    *rank = m;
+    if (sigma)
+      for (int64_t i = 0; i < m; ++i) sigma[i] = 1.0;
+    return HAPOD_OK;
+  }
+  if (m == 0 || n == 0) {
+    *rank = 0;
+    return HAPOD_OK;
+  }
+  std::vector<PodJob> jobs(1);
+  jobs[0].cols = column_table(S, lds, m, eb);
+  jobs[0].n = n;
+  jobs[0].m = m;
+  jobs[0].eps = eps;
+  jobs[0].root = (scaled == 0);
+  jobs[0].out = out;
+  jobs[0].ldo = ldo;
+  HAPOD_TRY(run_pod_batch(prec, jobs, 0, 1, 256, step_pool(), stream, nullptr));
+  *rank = jobs[0].rank;
+  if (sigma && jobs[0].rank > 0) std::memcpy(sigma, jobs[0].sigma.data(), sizeof(double) * jobs[0].rank);
+  return HAPOD_OK;
+}
+
+}  // extern "C"

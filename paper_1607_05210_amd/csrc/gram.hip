@@ -1,0 +1,259 @@
+// Batched Gram matrices G = S^T S of the method of snapshots (Rem. 2.3).
+//
+// Work item = (node, upper tile pair (ti <= tj) of 128 x 128, row chunk).
+// A 256-thread workgroup computes one tile; each of its four wavefronts owns
+// a 64 x 64 sub-tile as 4 x 4 blocks of 16 x 16 MFMA accumulators.  The
+// reduction index of the MFMA is the snapshot row, so every lane streams a
+// contiguous run of rows of one column (column-major input): rows
+// [k0 + R*g, k0 + R*g + R) of column c0 + l%16 for lane l = 16 g + l%16.
+// Run element t feeds MFMA number t; the same row permutation is used for
+// both operands, so the contraction is unchanged.
+//
+// Row chunks are accumulated in the MFMA's accumulator (FP64, or FP32 for
+// the FP32 and split-BF16 forms); chunk partial tiles are summed in FP64 by
+// gram_reduce in chunk order, so results do not depend on scheduling.
+#include "internal.hpp"
+#include "mfma.hpp"
+
+namespace hapod {
+namespace {
+
+constexpr int T = kGramTile;
+constexpr int WT = 64;
+constexpr int NB = WT / 16;
+
+template <int C> struct GramTraits;
+// FP64 storage, FP64 MFMA 16x16x4: 4-row runs, 16 rows per batch
+template <> struct GramTraits<0> { using Elem = double; using Acc = d4; static constexpr int R = 4; };
+// FP32 storage, FP32 MFMA 16x16x4
+template <> struct GramTraits<1> { using Elem = float; using Acc = f4; static constexpr int R = 4; };
+// FP32 storage, split-BF16 MFMA 16x16x32 (8 rows per lane per MFMA)
+template <> struct GramTraits<2> { using Elem = float; using Acc = f4; static constexpr int R = 8; };
+// FP32 storage promoted to FP64, FP64 MFMA (used for double-accumulated
+// Gram matrices of float data, e.g. re-orthonormalisation)
+template <> struct GramTraits<3> { using Elem = float; using Acc = d4; static constexpr int R = 4; };
+
+template <typename Elem, int R, bool VEC>
+__device__ __forceinline__ void load_run(const Elem* p, int64_t row, int64_t r1, float* out) {
+  if (p == nullptr) {
+#pragma unroll
+    for (int t = 0; t < R; ++t) out[t] = 0.f;
+    return;
+  }
+  if (VEC && row + R <= r1) {
+    if constexpr (R == 4) {
+      float4 v = *reinterpret_cast<const float4*>(p + row);
+      out[0] = v.x; out[1] = v.y; out[2] = v.z; out[3] = v.w;
+    } else {
+      float4 v0 = *reinterpret_cast<const float4*>(p + row);
+      float4 v1 = *reinterpret_cast<const float4*>(p + row + 4);
+      out[0] = v0.x; out[1] = v0.y; out[2] = v0.z; out[3] = v0.w;
+      out[4] = v1.x; out[5] = v1.y; out[6] = v1.z; out[7] = v1.w;
+    }
+  } else {
+#pragma unroll
+    for (int t = 0; t < R; ++t) out[t] = (row + t < r1) ? (float)p[row + t] : 0.f;
+  }
+}
+
+template <int R, bool VEC>
+__device__ __forceinline__ void load_run(const double* p, int64_t row, int64_t r1, double* out) {
+  if (p == nullptr) {
+#pragma unroll
+    for (int t = 0; t < R; ++t) out[t] = 0.0;
+    return;
+  }
+  if (VEC && row + R <= r1) {
+    double2 v0 = *reinterpret_cast<const double2*>(p + row);
+    double2 v1 = *reinterpret_cast<const double2*>(p + row + 2);
+    out[0] = v0.x; out[1] = v0.y; out[2] = v1.x; out[3] = v1.y;
+  } else {
+#pragma unroll
+    for (int t = 0; t < R; ++t) out[t] = (row + t < r1) ? p[row + t] : 0.0;
+  }
+}
+
+template <int C, bool VEC>
+__global__ __launch_bounds__(256) void gram_tile_kernel(const GramNode* __restrict__ nodes,
+                                                        const GramItem* __restrict__ items) {
+  using Tr = GramTraits<C>;
+  using Elem = typename Tr::Elem;
+  using Acc = typename Tr::Acc;
+  constexpr int R = Tr::R;
+  constexpr int KB = 4 * R;  // rows per batch
+
+  const GramItem item = items[xcd_item(blockIdx.x, gridDim.x)];
+  const GramNode nd = nodes[item.node];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wi = wave >> 1, wj = wave & 1;
+  const bool diag = (item.ti == item.tj);
+  // the lower sub-tile of a diagonal tile mirrors the upper one
+  if (diag && wi > wj) return;
+  const int li = lane & 15, g = lane >> 4;
+  const int cA0 = item.ti * T + wi * WT, cB0 = item.tj * T + wj * WT;
+  if (cA0 >= nd.m || cB0 >= nd.m) return;
+
+  const int64_t r0 = (int64_t)item.chunk * nd.chunk_rows;
+  const int64_t r1 = min(nd.n, r0 + nd.chunk_rows);
+
+  const Elem* pa[NB];
+  const Elem* pb[NB];
+#pragma unroll
+  for (int a = 0; a < NB; ++a) {
+    int ca = cA0 + a * 16 + li, cb = cB0 + a * 16 + li;
+    pa[a] = ca < nd.m ? reinterpret_cast<const Elem*>(nd.cols[ca]) : nullptr;
+    pb[a] = cb < nd.m ? reinterpret_cast<const Elem*>(nd.cols[cb]) : nullptr;
+  }
+
+  Acc acc[NB][NB];
+#pragma unroll
+  for (int a = 0; a < NB; ++a)
+#pragma unroll
+    for (int b = 0; b < NB; ++b) acc[a][b] = Acc{0, 0, 0, 0};
+
+  for (int64_t k0 = r0; k0 < r1; k0 += KB) {
+    const int64_t row = k0 + (int64_t)R * g;
+    if constexpr (C == 0) {
+      double va[NB][R], vb[NB][R];
+#pragma unroll
+      for (int a = 0; a < NB; ++a) {
+        load_run<R, VEC>(pa[a], row, r1, va[a]);
+        load_run<R, VEC>(pb[a], row, r1, vb[a]);
+      }
+#pragma unroll
+      for (int t = 0; t < R; ++t)
+#pragma unroll
+        for (int a = 0; a < NB; ++a)
+#pragma unroll
+          for (int b = 0; b < NB; ++b) acc[a][b] = mfma_f64(va[a][t], vb[b][t], acc[a][b]);
+    } else {
+      float va[NB][R], vb[NB][R];
+#pragma unroll
+      for (int a = 0; a < NB; ++a) {
+        load_run<Elem, R, VEC>(pa[a], row, r1, va[a]);
+        load_run<Elem, R, VEC>(pb[a], row, r1, vb[a]);
+      }
+      if constexpr (C == 1) {
+#pragma unroll
+        for (int t = 0; t < R; ++t)
+#pragma unroll
+          for (int a = 0; a < NB; ++a)
+#pragma unroll
+            for (int b = 0; b < NB; ++b) acc[a][b] = mfma_f32(va[a][t], vb[b][t], acc[a][b]);
+      } else if constexpr (C == 3) {
+#pragma unroll
+        for (int t = 0; t < R; ++t)
+#pragma unroll
+          for (int a = 0; a < NB; ++a)
+#pragma unroll
+            for (int b = 0; b < NB; ++b)
+              acc[a][b] = mfma_f64((double)va[a][t], (double)vb[b][t], acc[a][b]);
+      } else {
+        bf8 ha[NB], la[NB], hb[NB], lb[NB];
+#pragma unroll
+        for (int a = 0; a < NB; ++a) {
+          split_bf16x8(va[a], ha[a], la[a]);
+          split_bf16x8(vb[a], hb[a], lb[a]);
+        }
+#pragma unroll
+        for (int a = 0; a < NB; ++a)
+#pragma unroll
+          for (int b = 0; b < NB; ++b) {
+            acc[a][b] = mfma_bf16(la[a], hb[b], acc[a][b]);
+            acc[a][b] = mfma_bf16(ha[a], lb[b], acc[a][b]);
+            acc[a][b] = mfma_bf16(ha[a], hb[b], acc[a][b]);
+          }
+      }
+    }
+  }
+
+  // store: direct into G (single chunk) or into the chunk's partial tile
+  if (nd.nchunks == 1) {
+#pragma unroll
+    for (int a = 0; a < NB; ++a)
+#pragma unroll
+      for (int b = 0; b < NB; ++b)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          int row = cA0 + a * 16 + acc_row<Acc>(lane, v);
+          int col = cB0 + b * 16 + acc_col(lane);
+          if (row < nd.m && col < nd.m && row <= col) {
+            double x = (double)acc[a][b][v];
+            nd.G[(int64_t)col * nd.ldg + row] = x;
+            nd.G[(int64_t)row * nd.ldg + col] = x;
+          }
+        }
+  } else {
+    double* P = nd.partial + ((int64_t)(item.pair - nd.pair_base) * nd.nchunks + item.chunk) * (T * T);
+#pragma unroll
+    for (int a = 0; a < NB; ++a)
+#pragma unroll
+      for (int b = 0; b < NB; ++b)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          int i = wi * WT + a * 16 + acc_row<Acc>(lane, v);
+          int j = wj * WT + b * 16 + acc_col(lane);
+          P[j * T + i] = (double)acc[a][b][v];
+        }
+  }
+}
+
+// One workgroup per (node, tile pair): sum the chunk partials in chunk order
+// and write the upper-triangle entries of the tile to both triangles of G.
+__global__ __launch_bounds__(256) void gram_reduce_kernel(const GramNode* __restrict__ nodes,
+                                                          const int32_t* __restrict__ pairs,
+                                                          const int32_t* __restrict__ pair_node) {
+  const int node = pair_node[blockIdx.x];
+  const int pair = pairs[blockIdx.x];
+  const GramNode nd = nodes[node];
+  const int lp = pair - nd.pair_base;
+  // recover (ti, tj) from the local pair index in row-major upper order
+  int ti = 0, rem = lp, rowlen = nd.ntiles;
+  while (rem >= rowlen) { rem -= rowlen; ++ti; --rowlen; }
+  const int tj = ti + rem;
+  const double* P = nd.partial + (int64_t)lp * nd.nchunks * (T * T);
+  for (int e = threadIdx.x; e < T * T; e += blockDim.x) {
+    const int i = e & (T - 1), j = e / T;
+    const int row = ti * T + i, col = tj * T + j;
+    if (row >= nd.m || col >= nd.m || row > col) continue;
+    double s = 0.0;
+    for (int c = 0; c < nd.nchunks; ++c) s += P[(int64_t)c * (T * T) + j * T + i];
+    nd.G[(int64_t)col * nd.ldg + row] = s;
+    nd.G[(int64_t)row * nd.ldg + col] = s;
+  }
+}
+
+template <int C>
+hapod_status launch_gram_c(const GramNode* d_nodes, const GramItem* d_items, int num_items,
+                           bool vec_ok, hipStream_t stream) {
+  if (num_items <= 0) return HAPOD_OK;
+  if (vec_ok)
+    hipLaunchKernelGGL((gram_tile_kernel<C, true>), dim3(num_items), dim3(256), 0, stream, d_nodes, d_items);
+  else
+    hipLaunchKernelGGL((gram_tile_kernel<C, false>), dim3(num_items), dim3(256), 0, stream, d_nodes, d_items);
+  HAPOD_HIP(hipGetLastError());
+  return HAPOD_OK;
+}
+
+}  // namespace
+
+hapod_status launch_gram(int compute, const GramNode* d_nodes, const GramItem* d_items,
+                         int num_items, const int32_t* d_reduce_pairs,
+                         const int32_t* d_reduce_node, int num_reduce, bool vec_ok,
+                         hipStream_t stream) {
+  switch (compute) {
+    case 0: HAPOD_TRY(launch_gram_c<0>(d_nodes, d_items, num_items, vec_ok, stream)); break;
+    case 1: HAPOD_TRY(launch_gram_c<1>(d_nodes, d_items, num_items, vec_ok, stream)); break;
+    case 2: HAPOD_TRY(launch_gram_c<2>(d_nodes, d_items, num_items, vec_ok, stream)); break;
+    case 3: HAPOD_TRY(launch_gram_c<3>(d_nodes, d_items, num_items, vec_ok, stream)); break;
+    default: set_error("launch_gram: unknown compute mode"); return HAPOD_E_INVALID;
+  }
+  if (num_reduce > 0) {
+    hipLaunchKernelGGL(gram_reduce_kernel, dim3(num_reduce), dim3(256), 0, stream, d_nodes,
+                       d_reduce_pairs, d_reduce_node);
+    HAPOD_HIP(hipGetLastError());
+  }
+  return HAPOD_OK;
+}
+
+}  // namespace hapod

@@ -1,0 +1,148 @@
+// Internal declarations shared by the HIP kernels and the C-ABI layer.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/hapod.h"
+
+namespace hapod {
+
+// ---- error plumbing --------------------------------------------------------
+void set_error(const std::string& msg);
+
+#define HAPOD_HIP(call)                                                       \
+  do {                                                                        \
+    hipError_t e_ = (call);                                                   \
+    if (e_ != hipSuccess) {                                                   \
+      ::hapod::set_error(std::string(#call) + ": " + hipGetErrorString(e_));  \
+      return (e_ == hipErrorOutOfMemory) ? HAPOD_E_NOMEM : HAPOD_E_DEVICE;    \
+    }                                                                         \
+  } while (0)
+
+#define HAPOD_TRY(expr)                 \
+  do {                                  \
+    hapod_status s_ = (expr);           \
+    if (s_ != HAPOD_OK) return s_;      \
+  } while (0)
+
+// ---- batched Gram ----------------------------------------------------------
+// One node's input: m columns, column j starting at cols[j] (device pointer
+// array), rows [0, n).  Tiles of kGramTile x kGramTile on the upper triangle;
+// rows split into nchunks chunks of chunk_rows.  With nchunks == 1 the tile is
+// written straight into G (both triangles); otherwise into
+// partial[(pair * nchunks + chunk) * T*T] and reduced by gram_reduce.
+constexpr int kGramTile = 128;
+
+struct GramNode {
+  const void* const* cols;
+  int64_t n;
+  int64_t chunk_rows;
+  double* G;
+  double* partial;
+  int64_t ldg;
+  int32_t m;
+  int32_t nchunks;
+  int32_t ntiles;      // ceil(m / T)
+  int32_t pair_base;   // first tile-pair index of this node in the level
+};
+
+struct GramItem {
+  int32_t node;
+  int16_t ti, tj;
+  int32_t chunk;
+  int32_t pair;        // tile-pair index within the level
+};
+
+// compute: 0 = FP64 MFMA (double storage), 1 = FP32 MFMA (float storage),
+//          2 = split-BF16 x3 (float storage), 3 = FP64 MFMA (float storage)
+hapod_status launch_gram(int compute, const GramNode* d_nodes, const GramItem* d_items,
+                         int num_items, const int32_t* d_reduce_pairs,
+                         const int32_t* d_reduce_node, int num_reduce, bool vec_ok,
+                         hipStream_t stream);
+
+// ---- batched Jacobi eigensolver -------------------------------------------
+struct EigNode {
+  double* G;        // m x m, ld = ldg, input (upper triangle read)
+  double* work;     // 2 * m2 * m2 doubles (global variant) scratch
+  double* Vwork;    // 2 * m * m2 doubles scratch
+  double* lambda;   // m outputs (descending)
+  double* V;        // m x m outputs, ld = ldv
+  int64_t ldg;
+  int64_t ldv;
+  int32_t m;
+  int32_t pad;
+  int32_t* sweeps;  // 1 int output (may be null)
+};
+constexpr int kJacobiLdsMax = 128;   // packed double-buffered upper triangle fits in LDS
+constexpr int kJacobiMax = 1024;     // global-memory variant limit
+hapod_status launch_jacobi(const EigNode* d_nodes, int num_nodes, int max_m,
+                           hipStream_t stream);
+size_t jacobi_work_doubles(int m);
+size_t jacobi_vwork_doubles(int m);
+
+// ---- batched truncation ----------------------------------------------------
+// policy: 0 = clamp negatives (Def. 2.5 on the computed spectrum),
+//         1 = clip the rounding band |lambda| <= theta,
+//             theta = max(-lambda_min, floor_abs)
+struct TruncNode {
+  const double* lambda;   // m, descending
+  const double* V;        // m x m, ld ldv (eigenvectors)
+  double* B;              // lift operand, row-major m x ldb
+  double* sigma;          // m outputs (first N valid)
+  int64_t* rank;          // 1 output
+  double* info;           // 6 outputs: tail(N), lambda1, lambda_min, n_neg, theta, rank_clamp
+  double eps2;
+  double floor_abs;
+  int64_t ldv;
+  int64_t ldb;
+  int32_t m;
+  int32_t policy;
+  int32_t root;           // 1: B = V Lambda^{-1/2}, else B = V
+  int32_t pad;
+};
+hapod_status launch_truncate(const TruncNode* d_nodes, int num_nodes, hipStream_t stream);
+// B[k * ldb + n] = V[k][n] (lambda == nullptr) or V[k][n] / sqrt(lambda[n])
+hapod_status launch_lift_operand(const double* V, int64_t ldv, const double* lambda, int64_t m, int64_t N,
+                                 double* B, int64_t ldb, hipStream_t stream);
+
+// ---- batched lift -----------------------------------------------------------
+// out = S * B[:, :N] where S is given by column pointers (m columns, n rows)
+// and B is row-major (ldb), N read from *rank on the device.
+constexpr int kLiftTileM = 128;
+constexpr int kLiftTileN = 128;
+struct LiftNode {
+  const void* const* cols;
+  const double* B;
+  const int64_t* rank;   // device pointer to N
+  void* out;
+  int64_t n;
+  int64_t ldb;
+  int64_t ldo;
+  int32_t m;
+  int32_t row_tiles;
+  int32_t col_tiles;     // worst case ceil(maxN / TN)
+  int32_t item_base;
+};
+// compute as for launch_gram (0, 1, 2); output storage = input storage
+hapod_status launch_lift(int compute, const LiftNode* d_nodes, int num_nodes,
+                         int num_items, hipStream_t stream);
+
+// ---- helpers ----------------------------------------------------------------
+hapod_status launch_fill_colptrs(const void* base, int64_t ld, int64_t m, int elem_bytes,
+                                 const void** d_out, hipStream_t stream);
+hapod_status launch_copy_cols(int elem_bytes, int64_t n, int64_t m, const void* const* cols,
+                              void* out, int64_t ldo, hipStream_t stream);
+hapod_status launch_check_diag(const double* G, int64_t ldg, int64_t m, int32_t* d_flag,
+                               hipStream_t stream);
+hapod_status launch_set_scalar_i64(int64_t* p, int64_t v, hipStream_t stream);
+
+// ---- Cholesky-QR re-orthonormalisation -------------------------------------
+hapod_status launch_chol_inv(double* W, int64_t ldw, int64_t N, double* Rinv, int64_t ldr,
+                             int32_t* d_bad, hipStream_t stream);
+
+}  // namespace hapod

@@ -1,0 +1,140 @@
+// Small helper kernels: column-pointer tables, column copies, the Gram
+// diagonal check, and the Cholesky factor / triangular inverse used by the
+// Cholesky-QR re-orthonormalisation.
+#include "internal.hpp"
+
+namespace hapod {
+namespace {
+
+__global__ void fill_colptrs_kernel(const char* base, int64_t ld_bytes, int64_t m, const void** out) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < m) out[j] = base + j * ld_bytes;
+}
+
+template <typename E>
+__global__ void copy_cols_kernel(int64_t n, int64_t m, const void* const* cols, E* out, int64_t ldo) {
+  const int64_t j = blockIdx.y;
+  const E* src = reinterpret_cast<const E*>(cols[j]);
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x)
+    out[j * ldo + r] = src[r];
+}
+
+__global__ void check_diag_kernel(const double* G, int64_t ldg, int64_t m, int32_t* flag) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
+    const double d = G[i * ldg + i];
+    if (!isfinite(d)) *flag = 1;
+  }
+}
+
+__global__ void set_i64_kernel(int64_t* p, int64_t v) { *p = v; }
+
+// W (N x N, symmetric, upper used) = R^T R in place (upper R), then Rinv =
+// R^{-1} (upper, row-major).  A pivot <= 1e-12 of its original diagonal marks the column
+// as dependent: its row of R becomes e_k (the column is left unchanged).
+__global__ __launch_bounds__(256) void chol_inv_kernel(double* W, int64_t ldw, int64_t N, double* Rinv,
+                                                       int64_t ldr, int32_t* bad) {
+  __shared__ double piv;
+  __shared__ int nbad;
+  const int tid = threadIdx.x;
+  if (tid == 0) nbad = 0;
+  __syncthreads();
+  for (int64_t k = 0; k < N; ++k) {
+    if (tid == 0) {
+      const double d = W[k * ldw + k];
+      // the original diagonal of column k is kept in Rinv's diagonal slot
+      const double d0 = Rinv[k * ldr + k];
+      if (!(d > 1e-12 * d0) || !isfinite(d)) {
+        piv = 0.0;
+        ++nbad;
+      } else {
+        piv = sqrt(d);
+      }
+    }
+    __syncthreads();
+    const double p = piv;
+    for (int64_t j = k + 1 + tid; j < N; j += blockDim.x)
+      W[j * ldw + k] = (p > 0.0) ? W[j * ldw + k] / p : 0.0;
+    __syncthreads();
+    if (tid == 0) W[k * ldw + k] = (p > 0.0) ? p : 1.0;
+    // trailing update of the upper triangle: W[i][j] -= R[k][i] R[k][j], k < i <= j
+    const int64_t rem = N - k - 1;
+    for (int64_t e = tid; e < rem * rem; e += blockDim.x) {
+      const int64_t i = k + 1 + e % rem, j = k + 1 + e / rem;
+      if (i > j) continue;
+      W[j * ldw + i] -= W[i * ldw + k] * W[j * ldw + k];
+    }
+    __syncthreads();
+  }
+  // Rinv (row-major, element (i, j) at i * ldr + j): column j solves
+  // R x = e_j by back substitution
+  for (int64_t j = tid; j < N; j += blockDim.x) {
+    for (int64_t i = j + 1; i < N; ++i) Rinv[i * ldr + j] = 0.0;
+    Rinv[j * ldr + j] = 1.0 / W[j * ldw + j];
+    for (int64_t i = j - 1; i >= 0; --i) {
+      double s = 0.0;
+      for (int64_t l = i + 1; l <= j; ++l) s += W[l * ldw + i] * Rinv[l * ldr + j];
+      Rinv[i * ldr + j] = -s / W[i * ldw + i];
+    }
+  }
+  if (tid == 0 && bad) *bad = nbad;
+}
+
+__global__ void copy_diag_kernel(const double* W, int64_t ldw, int64_t N, double* R, int64_t ldr) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < N) R[k * ldr + k] = W[k * ldw + k];
+}
+
+}  // namespace
+
+hapod_status launch_fill_colptrs(const void* base, int64_t ld, int64_t m, int elem_bytes,
+                                 const void** d_out, hipStream_t stream) {
+  if (m <= 0) return HAPOD_OK;
+  hipLaunchKernelGGL(fill_colptrs_kernel, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, stream,
+                     (const char*)base, ld * elem_bytes, m, d_out);
+  HAPOD_HIP(hipGetLastError());
+  return HAPOD_OK;
+}
+
+hapod_status launch_copy_cols(int elem_bytes, int64_t n, int64_t m, const void* const* cols, void* out,
+                              int64_t ldo, hipStream_t stream) {
+  if (m <= 0 || n <= 0) return HAPOD_OK;
+  if (m > 65535) {
+    set_error("launch_copy_cols: too many columns");
+    return HAPOD_E_UNSUPPORTED;
+  }
+  const unsigned gx = (unsigned)std::min<int64_t>((n + 255) / 256, 1024);
+  if (elem_bytes == 8)
+    hipLaunchKernelGGL(copy_cols_kernel<double>, dim3(gx, (unsigned)m), dim3(256), 0, stream, n, m, cols,
+                       (double*)out, ldo);
+  else
+    hipLaunchKernelGGL(copy_cols_kernel<float>, dim3(gx, (unsigned)m), dim3(256), 0, stream, n, m, cols,
+                       (float*)out, ldo);
+  HAPOD_HIP(hipGetLastError());
+  return HAPOD_OK;
+}
+
+hapod_status launch_check_diag(const double* G, int64_t ldg, int64_t m, int32_t* d_flag, hipStream_t stream) {
+  if (m <= 0) return HAPOD_OK;
+  hipLaunchKernelGGL(check_diag_kernel, dim3((unsigned)std::min<int64_t>((m + 255) / 256, 64)), dim3(256), 0,
+                     stream, G, ldg, m, d_flag);
+  HAPOD_HIP(hipGetLastError());
+  return HAPOD_OK;
+}
+
+hapod_status launch_set_scalar_i64(int64_t* p, int64_t v, hipStream_t stream) {
+  hipLaunchKernelGGL(set_i64_kernel, dim3(1), dim3(1), 0, stream, p, v);
+  HAPOD_HIP(hipGetLastError());
+  return HAPOD_OK;
+}
+
+hapod_status launch_chol_inv(double* W, int64_t ldw, int64_t N, double* Rinv, int64_t ldr, int32_t* d_bad,
+                             hipStream_t stream) {
+  if (N <= 0) return HAPOD_OK;
+  hipLaunchKernelGGL(copy_diag_kernel, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, stream, W, ldw, N, Rinv,
+                     ldr);
+  hipLaunchKernelGGL(chol_inv_kernel, dim3(1), dim3(256), 0, stream, W, ldw, N, Rinv, ldr, d_bad);
+  HAPOD_HIP(hipGetLastError());
+  return HAPOD_OK;
+}
+
+}  // namespace hapod

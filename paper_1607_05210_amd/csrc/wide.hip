@@ -1,0 +1,384 @@
+// Eigensolver for Gram matrices too large for one workgroup's Jacobi
+// (the wide root of a star tree): the leading eigenpairs of G by Lanczos with
+// full reorthogonalisation, in FP64.
+//
+//   q_0: deterministic pseudo-random unit vector.
+//   step j: w = G q_j; two passes of classical Gram-Schmidt against
+//           q_0..q_j (h = Q^T w, w -= Q h); alpha_j = sum of the two
+//           coefficients of q_j; beta_j = ||w||; q_{j+1} = w / beta_j.
+//   T = tridiag(beta, alpha, beta) (k x k).  Its eigenvalues theta_i come from
+//   Sturm-sequence bisection (one thread per eigenvalue), its eigenvectors
+//   z_i from inverse iteration with a pivoted tridiagonal LU (one thread per
+//   eigenvector).  Ritz pairs: (theta_i, Q z_i), residual beta_{k-1} |z_i[k-1]|.
+//
+// The pairs returned are the leading Ritz pairs whose residual is below the
+// Gram's rounding level or 1e-8 of their value; eigenvalues past them are reported
+// as 0, and the rounding level floor_abs = max(-theta_min, u_p trace(G) / 10)
+// is handed to the truncation, which counts eigenvalues at or below it as
+// zero energy.
+#include <cmath>
+#include <vector>
+
+#include "mfma.hpp"
+#include "wide.hpp"
+
+namespace hapod {
+namespace {
+
+constexpr int kMaxSteps = 768;
+
+__device__ __forceinline__ double hash_unit(uint64_t x) {
+  // splitmix64 finaliser -> uniform in [-0.5, 0.5)
+  x += 0x9e3779b97f4a7c15ull;
+  x = (x ^ (x >> 30)) * 0xbf58476d1ce4e5b9ull;
+  x = (x ^ (x >> 27)) * 0x94d049bb133111ebull;
+  x ^= x >> 31;
+  return (double)(x >> 11) * (1.0 / 9007199254740992.0) - 0.5;
+}
+
+__device__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// q = random, unnormalised (normalised by the finish kernel)
+__global__ void lanczos_init_kernel(double* w, int64_t m) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x)
+    w[i] = hash_unit((uint64_t)i * 7919u + 17u);
+}
+
+// w[c] = G[:, c] . q  (G symmetric), one wavefront per column
+__global__ __launch_bounds__(256) void matvec_kernel(const double* __restrict__ G, int64_t ldg, int64_t m,
+                                                     const double* __restrict__ q, double* __restrict__ w) {
+  const int64_t c = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (c >= m) return;
+  const double* col = G + c * ldg;
+  double s = 0.0;
+  for (int64_t r = lane; r < m; r += 64) s += col[r] * q[r];
+  s = wave_sum(s);
+  if (lane == 0) w[c] = s;
+}
+
+// h[c] = Q[:, c] . w for c <= j, one wavefront per column
+__global__ __launch_bounds__(256) void proj_kernel(const double* __restrict__ Q, int64_t m, int j,
+                                                   const double* __restrict__ w, double* __restrict__ h) {
+  const int c = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (c > j) return;
+  const double* col = Q + (int64_t)c * m;
+  double s = 0.0;
+  for (int64_t r = lane; r < m; r += 64) s += col[r] * w[r];
+  s = wave_sum(s);
+  if (lane == 0) h[c] = s;
+}
+
+// w -= Q[:, 0..j] h ; accumulate alpha_j += h[j]
+__global__ __launch_bounds__(256) void update_kernel(const double* __restrict__ Q, int64_t m, int j,
+                                                     double* __restrict__ w, const double* __restrict__ h,
+                                                     double* __restrict__ alpha) {
+  __shared__ double hs[kMaxSteps + 1];
+  for (int c = threadIdx.x; c <= j; c += blockDim.x) hs[c] = h[c];
+  __syncthreads();
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (blockIdx.x == 0 && threadIdx.x == 0) alpha[j] += hs[j];
+  if (i >= m) return;
+  double s = 0.0;
+  for (int c = 0; c <= j; ++c) s += Q[(int64_t)c * m + i] * hs[c];
+  w[i] -= s;
+}
+
+// beta = ||w||, q_next = w / beta (single workgroup)
+__global__ __launch_bounds__(1024) void finish_kernel(const double* __restrict__ w, int64_t m,
+                                                      double* __restrict__ q_next, double* __restrict__ beta_out) {
+  __shared__ double part[16];
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < m; i += blockDim.x) s += w[i] * w[i];
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
+  __syncthreads();
+  double tot = 0.0;
+  for (int i = 0; i < (int)(blockDim.x >> 6); ++i) tot += part[i];
+  const double beta = sqrt(tot);
+  const double inv = beta > 0.0 ? 1.0 / beta : 0.0;
+  for (int64_t i = threadIdx.x; i < m; i += blockDim.x) q_next[i] = w[i] * inv;
+  if (threadIdx.x == 0 && beta_out) *beta_out = beta;
+}
+
+__global__ void trace_kernel(const double* G, int64_t ldg, int64_t m, double* out) {
+  __shared__ double part[16];
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < m; i += blockDim.x) s += G[i * ldg + i];
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) t += part[i];
+    *out = t;
+  }
+}
+
+// number of eigenvalues of tridiag(e, d, e) below mu (Sturm sequence)
+__device__ int sturm_count(const double* d, const double* e2, int k, double mu, double pivmin) {
+  int cnt = 0;
+  double q = d[0] - mu;
+  if (fabs(q) < pivmin) q = -pivmin;
+  cnt += (q < 0.0);
+  for (int j = 1; j < k; ++j) {
+    q = (d[j] - mu) - e2[j - 1] / q;
+    if (fabs(q) < pivmin) q = -pivmin;
+    cnt += (q < 0.0);
+  }
+  return cnt;
+}
+
+// theta[i] = i-th largest eigenvalue of T, by bisection
+__global__ void bisect_kernel(const double* __restrict__ d, const double* __restrict__ e, int k,
+                              double* __restrict__ e2all, double* __restrict__ theta) {
+  // e^2 in this block's own region, and the Gershgorin interval (cheap)
+  double* e2buf = e2all + (int64_t)blockIdx.x * k;
+  for (int j = threadIdx.x; j < k - 1; j += blockDim.x) e2buf[j] = e[j] * e[j];
+  __syncthreads();
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= k) return;
+  double lo = 1e300, hi = -1e300, emax2 = 0.0;
+  for (int j = 0; j < k; ++j) {
+    const double r = (j > 0 ? fabs(e[j - 1]) : 0.0) + (j < k - 1 ? fabs(e[j]) : 0.0);
+    lo = fmin(lo, d[j] - r);
+    hi = fmax(hi, d[j] + r);
+    if (j < k - 1) emax2 = fmax(emax2, e2buf[j]);
+  }
+  const double tnorm = fmax(fabs(lo), fabs(hi));
+  const double pivmin = fmax(2.2250738585072014e-308, 2.2250738585072014e-308 * emax2);
+  const double slack = 4.0 * 2.220446049250313e-16 * tnorm + 2.0 * pivmin;
+  lo -= slack;
+  hi += slack;
+  const int target = k - 1 - i;  // ascending index
+  for (int it = 0; it < 200; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (mid <= lo || mid >= hi) break;
+    if (hi - lo <= 2.0 * 2.220446049250313e-16 * fmax(fabs(lo), fabs(hi)) + pivmin) break;
+    if (sturm_count(d, e2buf, k, mid, pivmin) > target) hi = mid;
+    else lo = mid;
+  }
+  theta[i] = 0.5 * (lo + hi);
+}
+
+// inverse iteration: z_i solves (T - theta_i) z = z_prev (pivoted LU), three
+// times from a pseudo-random start; written as column i of Z (row-major,
+// Z[r * ldz + i]).  Scratch: 5 k doubles + k ints per thread.
+__global__ void inviter_kernel(const double* __restrict__ d, const double* __restrict__ e, int k,
+                               const double* __restrict__ theta, int nvec, double* __restrict__ scratch,
+                               int* __restrict__ iscratch, double* __restrict__ Z, int64_t ldz,
+                               double* __restrict__ last) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nvec) return;
+  double* dl = scratch + (int64_t)i * 5 * k;
+  double* dd = dl + k;
+  double* du = dd + k;
+  double* du2 = du + k;
+  double* b = du2 + k;
+  int* piv = iscratch + (int64_t)i * k;
+  double tnorm = 0.0;
+  for (int j = 0; j < k; ++j) tnorm = fmax(tnorm, fabs(d[j]) + (j < k - 1 ? fabs(e[j]) : 0.0) + (j > 0 ? fabs(e[j - 1]) : 0.0));
+  const double tiny = fmax(2.220446049250313e-16 * tnorm, 1e-300);
+  const double mu = theta[i];
+  // LU with partial pivoting of T - mu I (LAPACK gttrf layout)
+  for (int j = 0; j < k; ++j) {
+    dd[j] = d[j] - mu;
+    if (j < k - 1) { dl[j] = e[j]; du[j] = e[j]; }
+    du2[j] = 0.0;
+  }
+  for (int j = 0; j < k - 1; ++j) {
+    if (fabs(dd[j]) >= fabs(dl[j])) {
+      piv[j] = j;
+      if (dd[j] == 0.0) dd[j] = tiny;
+      const double f = dl[j] / dd[j];
+      dl[j] = f;
+      dd[j + 1] -= f * du[j];
+    } else {
+      piv[j] = j + 1;
+      const double f = dd[j] / dl[j];
+      dd[j] = dl[j];
+      dl[j] = f;
+      const double tmp = du[j];
+      du[j] = dd[j + 1];
+      dd[j + 1] = tmp - f * dd[j + 1];
+      if (j < k - 2) {
+        du2[j] = du[j + 1];
+        du[j + 1] = -f * du[j + 1];
+      }
+    }
+  }
+  if (dd[k - 1] == 0.0) dd[k - 1] = tiny;
+  for (int j = 0; j < k; ++j)
+    if (fabs(dd[j]) < tiny) dd[j] = (dd[j] < 0.0 ? -tiny : tiny);
+  for (int j = 0; j < k; ++j) b[j] = hash_unit((uint64_t)i * 1000003u + j) + 1.0;
+  for (int it = 0; it < 3; ++it) {
+    // forward with L
+    for (int j = 0; j < k - 1; ++j) {
+      if (piv[j] == j) {
+        b[j + 1] -= dl[j] * b[j];
+      } else {
+        const double t = b[j];
+        b[j] = b[j + 1];
+        b[j + 1] = t - dl[j] * b[j];
+      }
+    }
+    // back substitution with U (diag dd, super du, super-super du2)
+    b[k - 1] /= dd[k - 1];
+    if (k > 1) b[k - 2] = (b[k - 2] - du[k - 2] * b[k - 1]) / dd[k - 2];
+    for (int j = k - 3; j >= 0; --j) b[j] = (b[j] - du[j] * b[j + 1] - du2[j] * b[j + 2]) / dd[j];
+    double nrm = 0.0;
+    for (int j = 0; j < k; ++j) nrm += b[j] * b[j];
+    nrm = sqrt(nrm);
+    const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
+    for (int j = 0; j < k; ++j) b[j] *= inv;
+  }
+  for (int j = 0; j < k; ++j) Z[(int64_t)j * ldz + i] = b[j];
+  last[i] = b[k - 1];
+}
+
+// make the largest-magnitude entry of every column positive (one wave per column)
+__global__ __launch_bounds__(256) void sign_fix_kernel(double* V, int64_t ldv, int64_t m, int64_t ncols) {
+  const int64_t c = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (c >= ncols) return;
+  double* col = V + c * ldv;
+  double best = -1.0;
+  int64_t arg = m;
+  for (int64_t r = lane; r < m; r += 64) {
+    const double a = fabs(col[r]);
+    if (a > best) { best = a; arg = r; }
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const double ob = __shfl_xor(best, off, 64);
+    const int64_t oa = __shfl_xor(arg, off, 64);
+    if (ob > best || (ob == best && oa < arg)) { best = ob; arg = oa; }
+  }
+  const double sgn = (arg < m && col[arg] < 0.0) ? -1.0 : 1.0;
+  if (sgn < 0.0)
+    for (int64_t r = lane; r < m; r += 64) col[r] = -col[r];
+}
+
+__global__ void write_lambda_kernel(const double* theta, int b, double* lambda, int64_t m) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x)
+    lambda[i] = (i < b) ? theta[i] : 0.0;
+}
+
+}  // namespace
+
+hapod_status wide_eigh(const double* G, int64_t ldg, int64_t m, double* lambda, double* V, int64_t ldv, double u_p,
+                       wide_alloc_fn alloc, wide_free_fn release, void* ctx, hipStream_t stream, WideResult* res) {
+  if (m <= 0) return HAPOD_OK;
+  const int k = (int)std::min<int64_t>(m, kMaxSteps);
+  // ---- scratch ------------------------------------------------------------------
+  std::vector<void*> owned;
+  auto get = [&](size_t bytes) -> void* {
+    void* p = alloc(ctx, bytes);
+    if (p) owned.push_back(p);
+    return p;
+  };
+  struct Rel {
+    std::vector<void*>& o;
+    wide_free_fn f;
+    void* c;
+    ~Rel() {
+      for (void* p : o) f(c, p);
+    }
+  } rel{owned, release, ctx};
+  double* Q = (double*)get(sizeof(double) * m * (k + 1));
+  double* w = (double*)get(sizeof(double) * m);
+  double* h = (double*)get(sizeof(double) * (k + 1));
+  double* alpha = (double*)get(sizeof(double) * k);
+  double* beta = (double*)get(sizeof(double) * (k + 1));
+  double* theta = (double*)get(sizeof(double) * k);
+  double* e2 = (double*)get(sizeof(double) * (size_t)k * ((k + 255) / 256));
+  double* Z = (double*)get(sizeof(double) * (size_t)k * k);
+  double* last = (double*)get(sizeof(double) * k);
+  double* isc = (double*)get(sizeof(double) * (size_t)5 * k * k);
+  int* ipiv = (int*)get(sizeof(int) * (size_t)k * k);
+  double* tr = (double*)get(sizeof(double));
+  const void** qcols = (const void**)get(sizeof(void*) * k);
+  int64_t* drank = (int64_t*)get(sizeof(int64_t));
+  void* dnode = get(sizeof(LiftNode));
+  if (!Q || !w || !h || !alpha || !beta || !theta || !e2 || !Z || !last || !isc || !ipiv || !tr || !qcols || !drank ||
+      !dnode) {
+    set_error("wide_eigh: scratch allocation failed");
+    return HAPOD_E_NOMEM;
+  }
+  HAPOD_HIP(hipMemsetAsync(alpha, 0, sizeof(double) * k, stream));
+  hipLaunchKernelGGL(trace_kernel, dim3(1), dim3(1024), 0, stream, G, ldg, m, tr);
+  // q_0
+  hipLaunchKernelGGL(lanczos_init_kernel, dim3(64), dim3(256), 0, stream, w, m);
+  hipLaunchKernelGGL(finish_kernel, dim3(1), dim3(1024), 0, stream, w, m, Q, (double*)nullptr);
+  const unsigned mv_blocks = (unsigned)((m + 3) / 4);
+  const unsigned up_blocks = (unsigned)((m + 255) / 256);
+  for (int j = 0; j < k; ++j) {
+    const double* qj = Q + (int64_t)j * m;
+    hipLaunchKernelGGL(matvec_kernel, dim3(mv_blocks), dim3(256), 0, stream, G, ldg, m, qj, w);
+    for (int pass = 0; pass < 2; ++pass) {
+      hipLaunchKernelGGL(proj_kernel, dim3((unsigned)((j + 4) / 4)), dim3(256), 0, stream, Q, m, j, w, h);
+      hipLaunchKernelGGL(update_kernel, dim3(up_blocks), dim3(256), 0, stream, Q, m, j, w, h, alpha);
+    }
+    hipLaunchKernelGGL(finish_kernel, dim3(1), dim3(1024), 0, stream, w, m, Q + (int64_t)(j + 1) * m, beta + j);
+  }
+  HAPOD_HIP(hipGetLastError());
+  // ---- tridiagonal eigenproblem -------------------------------------------------
+  const unsigned bblocks = (unsigned)((k + 255) / 256);
+  hipLaunchKernelGGL(bisect_kernel, dim3(bblocks), dim3(256), 0, stream, alpha, beta, k, e2, theta);
+  HAPOD_HIP(hipGetLastError());
+  hipLaunchKernelGGL(inviter_kernel, dim3(bblocks), dim3(256), 0, stream, alpha, beta, k, theta, k, isc, ipiv, Z,
+                     (int64_t)k, last);
+  HAPOD_HIP(hipGetLastError());
+  // ---- choose the converged leading block (host) ----------------------------------
+  std::vector<double> th(k), lz(k), bet(k);
+  double trace = 0.0;
+  HAPOD_HIP(hipMemcpyAsync(th.data(), theta, sizeof(double) * k, hipMemcpyDeviceToHost, stream));
+  HAPOD_HIP(hipMemcpyAsync(lz.data(), last, sizeof(double) * k, hipMemcpyDeviceToHost, stream));
+  HAPOD_HIP(hipMemcpyAsync(bet.data(), beta, sizeof(double) * k, hipMemcpyDeviceToHost, stream));
+  HAPOD_HIP(hipMemcpyAsync(&trace, tr, sizeof(double), hipMemcpyDeviceToHost, stream));
+  HAPOD_HIP(hipStreamSynchronize(stream));
+  const double bk = bet[k - 1];
+  const double theta_min = *std::min_element(th.begin(), th.end());
+  const double floor_abs = std::max(std::max(-theta_min, 0.0), 0.1 * u_p * std::fabs(trace));
+  // a Ritz pair counts as converged when its residual is below 1e-8 of its
+  // own value or below the Gram's rounding level
+  int b = 0;
+  while (b < k && std::fabs(bk * lz[b]) <= std::max(1e-8 * std::fabs(th[b]), floor_abs)) ++b;
+  if (k == m) b = k;  // complete tridiagonalisation: every pair is exact
+  // ---- Ritz vectors V[:, :b] = Q_k Z[:, :b] (FP64 lift GEMM) ------------------------
+  if (b > 0) {
+    HAPOD_TRY(launch_fill_colptrs(Q, m, k, 8, qcols, stream));
+    HAPOD_TRY(launch_set_scalar_i64(drank, b, stream));
+    LiftNode l{};
+    l.cols = (const void* const*)qcols;
+    l.B = Z;
+    l.rank = drank;
+    l.out = V;
+    l.n = m;
+    l.ldb = k;
+    l.ldo = ldv;
+    l.m = k;
+    l.row_tiles = (int32_t)((m + kLiftTileM - 1) / kLiftTileM);
+    l.col_tiles = (int32_t)((b + kLiftTileN - 1) / kLiftTileN);
+    l.item_base = 0;
+    HAPOD_HIP(hipMemcpyAsync(dnode, &l, sizeof(l), hipMemcpyHostToDevice, stream));
+    HAPOD_TRY(launch_lift(0, (const LiftNode*)dnode, 1, l.row_tiles * l.col_tiles, stream));
+    hipLaunchKernelGGL(sign_fix_kernel, dim3((unsigned)((b + 3) / 4)), dim3(256), 0, stream, V, ldv, m, (int64_t)b);
+  }
+  hipLaunchKernelGGL(write_lambda_kernel, dim3(64), dim3(256), 0, stream, theta, b, lambda, m);
+  HAPOD_HIP(hipGetLastError());
+  HAPOD_HIP(hipStreamSynchronize(stream));
+  if (res) {
+    res->iterations = k;
+    res->block = b;
+    res->floor_abs = floor_abs;
+  }
+  return HAPOD_OK;
+}
+
+}  // namespace hapod

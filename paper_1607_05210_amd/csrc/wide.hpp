@@ -1,0 +1,26 @@
+// Eigensolver for Gram matrices too large for the one-workgroup Jacobi
+// kernel: the leading part of the spectrum by a Krylov method on the GPU.
+#pragma once
+
+#include "internal.hpp"
+
+namespace hapod {
+
+struct WideResult {
+  int32_t iterations = 0;   // Krylov steps taken
+  int32_t block = 0;        // number of eigenpairs computed
+  double floor_abs = 0.0;   // rounding level of the Gram's spectrum
+};
+
+typedef void* (*wide_alloc_fn)(void* ctx, size_t bytes);
+typedef void (*wide_free_fn)(void* ctx, void* p);
+
+// G: m x m (ld ldg), symmetric, read only.  Writes lambda[0..m) (descending;
+// entries beyond the computed block are 0) and the first `block` columns of
+// V (m x ?, ld ldv).  u_p: unit roundoff of the precision the Gram was
+// formed in.
+hapod_status wide_eigh(const double* G, int64_t ldg, int64_t m, double* lambda, double* V, int64_t ldv,
+                       double u_p, wide_alloc_fn alloc, wide_free_fn release, void* ctx, hipStream_t stream,
+                       WideResult* res);
+
+}  // namespace hapod

@@ -1,0 +1,96 @@
+"""CPU checks of the C-ABI library: it loads, exports every function the
+header declares, and its host-side plan logic (Def. 3.1 validation, levels,
+|S~_alpha|, Thm. 3.5 tolerances) matches the oracle.  No device calls."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import tolerances, tree
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hapod.h")
+
+
+def header_functions():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    names = set(re.findall(r"\b(hapod_[a-z_]+)\s*\(", txt))
+    return sorted(n for n in names if n not in ("hapod_leaf_fn",))
+
+
+def test_header_declares_the_boundary():
+    names = header_functions()
+    for must in ["hapod_plan", "hapod_node_pod", "hapod_run", "hapod_modes", "hapod_gram",
+                 "hapod_eigh", "hapod_truncate", "hapod_lift", "hapod_reorth"]:
+        assert must in names
+
+
+def test_library_exports_every_declared_function():
+    hp = pytest.importorskip("paper_1607_05210_amd")
+    import ctypes
+    lib = ctypes.CDLL(hp.LIB_PATH)
+    for name in header_functions():
+        assert hasattr(lib, name), name
+    assert sorted(header_functions()) == sorted(hp.EXPORTED)
+
+
+TREES = [
+    (synth.star_tree(4), [64] * 4 + [0], 1e-6, 0.75, ()),
+    (synth.star_tree(64), [128] * 64 + [0], 1e-5, 0.75, ()),
+    ([4, 4, 5, 6, 6, 6, -1], [3, 5, 7, 11, 0, 0, 0], 0.1, 0.5, ()),
+    (synth.balanced_tree(1024, 3), [16 + (i % 240) for i in range(1024)] + [0] * 33, 1e-3, 0.75, ()),
+    ([-1], [9], 0.5, 0.3, ()),
+]
+
+
+@pytest.mark.parametrize("case", range(len(TREES)))
+def test_plan_matches_oracle(case):
+    hp = pytest.importorskip("paper_1607_05210_amd")
+    parent, cols, eps_star, omega, _ = TREES[case]
+    plan = hp.Plan(parent, cols, 100, eps_star, omega)
+    eps, lev, acc = plan.query()
+    assert list(lev) == tree.levels(parent)
+    assert list(acc) == tree.acc_counts(parent, cols)
+    ref = tolerances.hapod_tolerances(parent, cols, eps_star, omega)
+    np.testing.assert_allclose(eps, ref, rtol=1e-15, atol=0)
+
+
+def test_plan_chain_with_zero_overrides():
+    hp = pytest.importorskip("paper_1607_05210_amd")
+    parent, chunk = synth.chain_tree(6)
+    cols = [10] * len(parent)
+    betas = [b for b in chunk if b != 0]
+    ov = [-1.0] * len(parent)
+    for b in betas:
+        ov[b] = 0.0
+    plan = hp.Plan(parent, cols, 50, 1e-3, 0.75, eps_override=ov)
+    eps, lev, acc = plan.query()
+    ref = tolerances.hapod_tolerances(parent, cols, 1e-3, 0.75, zero_nodes=betas)
+    np.testing.assert_allclose(eps, ref, rtol=1e-15, atol=0)
+
+
+@pytest.mark.parametrize("parent", [[1, 0], [-1, -1], [3, -1, 1, 0], [5, -1], [0, -1]])
+def test_plan_rejects_invalid_trees(parent):
+    hp = pytest.importorskip("paper_1607_05210_amd")
+    with pytest.raises(hp.HapodError) as e:
+        hp.Plan(parent, [1] * len(parent), 10, 1e-3, 0.5)
+    assert e.value.status == 2
+
+
+@pytest.mark.parametrize("eps_star,omega,n", [(-1.0, 0.5, 10), (1.0, 1.5, 10), (1.0, -0.1, 10), (1.0, 0.5, 0)])
+def test_plan_rejects_invalid_arguments(eps_star, omega, n):
+    hp = pytest.importorskip("paper_1607_05210_amd")
+    with pytest.raises(hp.HapodError) as e:
+        hp.Plan(synth.star_tree(2), [3, 3, 0], n, eps_star, omega)
+    assert e.value.status == 1
+
+
+def test_modes_before_run_is_a_state_error():
+    hp = pytest.importorskip("paper_1607_05210_amd")
+    plan = hp.Plan(synth.star_tree(2), [3, 3, 0], 10, 1e-3, 0.5)
+    with pytest.raises(hp.HapodError) as e:
+        plan.node_stats()
+    assert e.value.status == 6
