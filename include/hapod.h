@@ -219,6 +219,11 @@ hapod_status hapod_node_stats(hapod_plan_t plan, int64_t* m_in, int64_t* n_negat
  * HIP events on the run's stream: {total, gram, eig, truncate, lift, reorth}. */
 hapod_status hapod_run_timing(hapod_plan_t plan, double* ms6);
 
+/* Device time in milliseconds of the phases of one level (1 = leaves) of the
+ * last run, measured with HIP events on the run's stream around that level's
+ * launches: {gram, eigensolve, truncate, lift}.  ms4: host, 4 doubles.      */
+hapod_status hapod_level_timing(hapod_plan_t plan, int32_t level, double* ms4);
+
 void hapod_destroy(hapod_plan_t plan);
 
 const char* hapod_last_error(void);

@@ -27,7 +27,7 @@ STATUS = {0: "OK", 1: "E_INVALID", 2: "E_TREE", 3: "E_NOMEM", 4: "E_DEVICE", 5: 
 HAPOD_EIG_MAX = 8192
 
 if not os.path.exists(LIB_PATH):
-    raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_1607_05210_amd.build`")
+    raise ImportError(f"{LIB_PATH} is not built; run `python paper_1607_05210_amd/build.py`")
 _lib = C.CDLL(LIB_PATH)
 
 _i32, _i64, _dbl, _vp = C.c_int32, C.c_int64, C.c_double, C.c_void_p
@@ -58,6 +58,7 @@ _SIGS = {
     "hapod_modes": [_vp, _i32, _vp, _i64, _pdbl, _pi64, _vp],
     "hapod_node_stats": [_vp, _pi64, _pi64, _pdbl, _pdbl],
     "hapod_run_timing": [_vp, _pdbl],
+    "hapod_level_timing": [_vp, _i32, _pdbl],
 }
 for _name, _args in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -295,6 +296,11 @@ class Plan:
             _check(_lib.hapod_modes(self._h, a, None, self.n, None, C.byref(r), None), "hapod_modes")
             out[a] = r.value
         return out
+
+    def level_timing(self, level):
+        t = (C.c_double * 4)()
+        _check(_lib.hapod_level_timing(self._h, int(level), t), "hapod_level_timing")
+        return dict(zip(["gram", "eig", "truncate", "lift"], list(t)))
 
     def timing(self):
         t = (C.c_double * 6)()

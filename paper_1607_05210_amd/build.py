@@ -1,6 +1,7 @@
 """Build the HIP library ``libhapod.so`` for gfx950 in-tree.
 
-Usage: ``python -m paper_1607_05210_amd.build`` (or ``build()`` from Python).
+Usage: ``python paper_1607_05210_amd/build.py`` (run by path: importing the
+package loads the library this script builds).
 Every source is compiled by hipcc (C++17, -O3) for gfx950 and linked into
 ``paper_1607_05210_amd/libhapod.so`` next to this file.
 """

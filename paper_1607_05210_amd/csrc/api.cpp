@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -460,6 +461,7 @@ struct hapod_plan_s {
   bool root_passthrough = false;
   std::vector<const void*> root_cols;  // pass-through root: its input columns
   double timing[6] = {0, 0, 0, 0, 0, 0};
+  std::vector<std::array<double, 4>> level_ms;  // {gram, eig, trunc, lift} per level
   Pool pool;
 };
 
@@ -586,6 +588,23 @@ hapod_status hapod_plan_query(hapod_plan_t plan, double* eps, int32_t* level, in
 
 void hapod_destroy(hapod_plan_t plan) { delete plan; }
 
+hapod_status hapod_level_timing(hapod_plan_t P, int32_t level, double* ms4) {
+  if (!P || !ms4) {
+    set_error("hapod_level_timing: NULL argument");
+    return HAPOD_E_INVALID;
+  }
+  if (!P->has_result) {
+    set_error("hapod_level_timing: no completed run");
+    return HAPOD_E_STATE;
+  }
+  if (level < 1 || level > (int32_t)P->level_ms.size()) {
+    set_error("hapod_level_timing: level out of range");
+    return HAPOD_E_INVALID;
+  }
+  for (int i = 0; i < 4; ++i) ms4[i] = P->level_ms[level - 1][i];
+  return HAPOD_OK;
+}
+
 // ===========================================================================
 // Run
 // ===========================================================================
@@ -636,6 +655,7 @@ hapod_status hapod_run(hapod_plan_t P, hapod_leaf_fn get_leaf, void* user, void*
   HAPOD_HIP(hipEventRecord(t0, stream));
   PhaseTimes pt;
   const int32_t LT = (int32_t)P->by_level.size();
+  P->level_ms.assign(LT, {0.0, 0.0, 0.0, 0.0});
   for (int32_t l = 0; l < LT; ++l) {
     std::vector<PodJob> jobs;
     std::vector<int32_t> job_node;
@@ -689,11 +709,17 @@ hapod_status hapod_run(hapod_plan_t P, hapod_leaf_fn get_leaf, void* user, void*
       jobs.push_back(std::move(j));
       job_node.push_back(a);
     }
-    hapod_status s = run_pod_batch(prec, jobs, 0, 1, jmax, P->pool, stream, &pt);
+    PhaseTimes lt;
+    hapod_status s = run_pod_batch(prec, jobs, 0, 1, jmax, P->pool, stream, &lt);
     if (s != HAPOD_OK) {
       release_all();
       return s;
     }
+    P->level_ms[l] = {lt.gram, lt.eig, lt.trunc, lt.lift};
+    pt.gram += lt.gram;
+    pt.eig += lt.eig;
+    pt.trunc += lt.trunc;
+    pt.lift += lt.lift;
     for (size_t k = 0; k < jobs.size(); ++k) {
       const int32_t a = job_node[k];
       const PodJob& j = jobs[k];
