@@ -123,12 +123,14 @@ struct Blob {
 struct PodJob {
   // inputs
   std::vector<const void*> cols;  // host copy of the column pointers
+  std::vector<int64_t> rbs;       // row-block stride of every column
   int64_t n = 0;
   int64_t m = 0;
   double eps = 0.0;
   bool root = false;    // lift with Lambda^{-1/2}
-  void* out = nullptr;  // n x m capacity
-  int64_t ldo = 0;
+  void* out = nullptr;  // n x m capacity; element (r, c) at out[c * ocs + blk_off(r, obs)]
+  int64_t ocs = 0;
+  int64_t obs = kRowBlock;
   // outputs (host, after sync)
   int64_t rank = 0;
   std::vector<double> sigma;
@@ -171,7 +173,7 @@ hapod_status run_pod_batch(hapod_precision prec, std::vector<PodJob>& jobs, int 
 
   // ---- sizes & scratch layout ---------------------------------------------
   struct Lay {
-    size_t cols, G, partial, lam, V, B, sigma, rank, info, jwork, vwork, sweeps;
+    size_t cols, rbs, G, partial, lam, V, B, sigma, rank, info, jwork, vwork, sweeps;
     int ntiles, pairs, nchunks;
     int64_t chunk_rows;
   };
@@ -196,7 +198,7 @@ hapod_status run_pod_batch(hapod_precision prec, std::vector<PodJob>& jobs, int 
     const int per_node_target = std::max(1, (int)((int64_t)target_items * L.pairs / std::max(sum_pairs, 1)));
     L.nchunks = pick_chunks(j.n, L.pairs, per_node_target, 2048);
     int64_t cr = (j.n + L.nchunks - 1) / L.nchunks;
-    cr = (cr + 63) / 64 * 64;
+    cr = (cr + kRowBlock - 1) / kRowBlock * kRowBlock;
     if (cr < KB) cr = KB;
     L.chunk_rows = cr;
     L.nchunks = (int)std::max<int64_t>(1, (j.n + cr - 1) / cr);
@@ -206,6 +208,7 @@ hapod_status run_pod_batch(hapod_precision prec, std::vector<PodJob>& jobs, int 
       return off;
     };
     L.cols = take(sizeof(void*) * std::max<int64_t>(m, 1));
+    L.rbs = take(sizeof(int64_t) * std::max<int64_t>(m, 1));
     L.G = take(sizeof(double) * m * m);
     L.partial = (L.nchunks > 1) ? take(sizeof(double) * (size_t)L.pairs * L.nchunks * kGramTile * kGramTile) : 0;
     L.lam = take(sizeof(double) * std::max<int64_t>(m, 1));
@@ -235,9 +238,8 @@ hapod_status run_pod_batch(hapod_precision prec, std::vector<PodJob>& jobs, int 
   std::vector<int32_t> rpairs, rnode;
   std::vector<EigNode> enodes_small, enodes_big;
   std::vector<TruncNode> tnodes(nj);
-  std::vector<LiftNode> lnodes;
   bool vec_ok = true;
-  int pair_base = 0, lift_items = 0, max_small = 0, max_big = 0;
+  int pair_base = 0, max_small = 0, max_big = 0;
   for (int i = 0; i < nj; ++i) {
     PodJob& j = jobs[i];
     Lay& L = lay[i];
@@ -247,6 +249,7 @@ hapod_status run_pod_batch(hapod_precision prec, std::vector<PodJob>& jobs, int 
     if (L.chunk_rows % KB) vec_ok = false;
     GramNode& g = gnodes[i];
     g.cols = (const void* const*)(scratch + L.cols);
+    g.rbs = (const int64_t*)(scratch + L.rbs);
     g.n = j.n;
     g.chunk_rows = L.chunk_rows;
     g.G = (double*)(scratch + L.G);
@@ -299,30 +302,17 @@ hapod_status run_pod_batch(hapod_precision prec, std::vector<PodJob>& jobs, int 
     t.m = (int32_t)m;
     t.policy = j.wide ? policy_wide : policy_small;
     t.root = j.root ? 1 : 0;
-    if (m > 0 && j.n > 0) {
-      LiftNode l{};
-      l.cols = g.cols;
-      l.B = t.B;
-      l.rank = t.rank;
-      l.out = j.out;
-      l.n = j.n;
-      l.ldb = t.ldb;
-      l.ldo = j.ldo;
-      l.m = (int32_t)m;
-      l.row_tiles = (int32_t)((j.n + kLiftTileM - 1) / kLiftTileM);
-      l.col_tiles = (int32_t)((m + kLiftTileN - 1) / kLiftTileN);
-      l.item_base = lift_items;
-      lift_items += l.row_tiles * l.col_tiles;
-      lnodes.push_back(l);
-    }
   }
 
   Blob blob;
-  std::vector<size_t> col_off(nj);
-  for (int i = 0; i < nj; ++i) col_off[i] = blob.add_vec(jobs[i].cols);
+  std::vector<size_t> col_off(nj), rbs_off(nj);
+  for (int i = 0; i < nj; ++i) {
+    col_off[i] = blob.add_vec(jobs[i].cols);
+    rbs_off[i] = blob.add_vec(jobs[i].rbs);
+  }
   const size_t o_g = blob.add_vec(gnodes), o_gi = blob.add_vec(gitems), o_rp = blob.add_vec(rpairs),
                o_rn = blob.add_vec(rnode), o_es = blob.add_vec(enodes_small), o_eb = blob.add_vec(enodes_big),
-               o_t = blob.add_vec(tnodes), o_l = blob.add_vec(lnodes);
+               o_t = blob.add_vec(tnodes);
   char* dblob = nullptr;
   HAPOD_TRY(pool.alloc(blob.host.size(), (void**)&dblob));
   struct Guard2 {
@@ -332,9 +322,12 @@ hapod_status run_pod_batch(hapod_precision prec, std::vector<PodJob>& jobs, int 
   } guard2{pool, dblob};
   HAPOD_HIP(hipMemcpyAsync(dblob, blob.host.data(), blob.host.size(), hipMemcpyHostToDevice, stream));
   for (int i = 0; i < nj; ++i)
-    if (jobs[i].m > 0)
+    if (jobs[i].m > 0) {
       HAPOD_HIP(hipMemcpyAsync(scratch + lay[i].cols, dblob + col_off[i], sizeof(void*) * jobs[i].m,
                                hipMemcpyDeviceToDevice, stream));
+      HAPOD_HIP(hipMemcpyAsync(scratch + lay[i].rbs, dblob + rbs_off[i], sizeof(int64_t) * jobs[i].m,
+                               hipMemcpyDeviceToDevice, stream));
+    }
   int32_t* d_flag = (int32_t*)(scratch + flag_off);
   HAPOD_HIP(hipMemsetAsync(d_flag, 0, 64, stream));
 
@@ -371,8 +364,45 @@ hapod_status run_pod_batch(hapod_precision prec, std::vector<PodJob>& jobs, int 
   // ---- truncation -----------------------------------------------------------
   HAPOD_TRY(launch_truncate((const TruncNode*)(dblob + o_t), nj, stream));
   if (times && ev.ok) HAPOD_HIP(hipEventRecord(ev.e[3], stream));
-  // ---- lift -----------------------------------------------------------------
-  HAPOD_TRY(launch_lift(compute, (const LiftNode*)(dblob + o_l), (int)lnodes.size(), lift_items, stream));
+  // ---- lift, sized by the ranks just computed ---------------------------------
+  std::vector<int64_t> ranks(nj, 0);
+  HAPOD_HIP(hipStreamSynchronize(stream));
+  for (int i = 0; i < nj; ++i)
+    HAPOD_HIP(hipMemcpy(&ranks[i], scratch + lay[i].rank, sizeof(int64_t), hipMemcpyDeviceToHost));
+  std::vector<LiftNode> lnodes;
+  int lift_items = 0;
+  for (int i = 0; i < nj; ++i) {
+    const PodJob& j = jobs[i];
+    if (j.m <= 0 || j.n <= 0 || ranks[i] <= 0) continue;
+    LiftNode l{};
+    l.cols = gnodes[i].cols;
+    l.rbs = gnodes[i].rbs;
+    l.B = tnodes[i].B;
+    l.rank = tnodes[i].rank;
+    l.out = j.out;
+    l.n = j.n;
+    l.ldb = tnodes[i].ldb;
+    l.ocs = j.ocs;
+    l.obs = j.obs;
+    l.m = (int32_t)j.m;
+    l.row_tiles = (int32_t)((j.n + kLiftTileM - 1) / kLiftTileM);
+    l.col_tiles = (int32_t)((ranks[i] + kLiftTileN - 1) / kLiftTileN);
+    l.item_base = lift_items;
+    lift_items += l.row_tiles * l.col_tiles;
+    lnodes.push_back(l);
+  }
+  char* dlift = nullptr;
+  if (!lnodes.empty()) {
+    HAPOD_TRY(pool.alloc(sizeof(LiftNode) * lnodes.size(), (void**)&dlift));
+    HAPOD_HIP(hipMemcpy(dlift, lnodes.data(), sizeof(LiftNode) * lnodes.size(), hipMemcpyHostToDevice));
+  }
+  struct Guard3 {
+    Pool& p;
+    void* s;
+    ~Guard3() { p.free(s); }
+  } guard3{pool, dlift};
+  if (times && ev.ok) HAPOD_HIP(hipEventRecord(ev.e[3], stream));
+  HAPOD_TRY(launch_lift(compute, (const LiftNode*)dlift, (int)lnodes.size(), lift_items, stream));
   if (times && ev.ok) HAPOD_HIP(hipEventRecord(ev.e[4], stream));
 
   // ---- results ----------------------------------------------------------------
@@ -403,10 +433,21 @@ hapod_status run_pod_batch(hapod_precision prec, std::vector<PodJob>& jobs, int 
   return HAPOD_OK;
 }
 
+// plain column-major n x m (leading dimension ld)
 std::vector<const void*> column_table(const void* base, int64_t ld, int64_t m, int eb) {
   std::vector<const void*> v((size_t)m);
   for (int64_t j = 0; j < m; ++j) v[j] = (const char*)base + j * ld * eb;
   return v;
+}
+// row-block-tiled n x m_cap buffer: column j starts kRowBlock * j elements in
+int64_t tiled_rbs(int64_t m_cap) { return m_cap * kRowBlock; }
+std::vector<const void*> tiled_table(const void* base, int64_t m, int eb) {
+  std::vector<const void*> v((size_t)m);
+  for (int64_t j = 0; j < m; ++j) v[j] = (const char*)base + j * kRowBlock * eb;
+  return v;
+}
+size_t tiled_bytes(int64_t n, int64_t m_cap, int eb) {
+  return (size_t)((n + kRowBlock - 1) / kRowBlock) * kRowBlock * m_cap * eb;
 }
 
 hapod_status check_prec(hapod_precision p) {
@@ -460,6 +501,7 @@ struct hapod_plan_s {
   void* root_U = nullptr;  // owned by the pool
   bool root_passthrough = false;
   std::vector<const void*> root_cols;  // pass-through root: its input columns
+  std::vector<int64_t> root_rbs;
   double timing[6] = {0, 0, 0, 0, 0, 0};
   std::vector<std::array<double, 4>> level_ms;  // {gram, eig, trunc, lift} per level
   Pool pool;
@@ -632,8 +674,10 @@ hapod_status hapod_run(hapod_plan_t P, hapod_leaf_fn get_leaf, void* user, void*
   P->sigma.assign(nn, {});
   for (double& t : P->timing) t = 0.0;
 
-  // per node: the column pointers it hands to its parent, and its own buffer
+  // per node: the columns it hands to its parent (pointer and row-block
+  // stride), and its own buffer
   std::vector<std::vector<const void*>> out_cols(nn);
+  std::vector<std::vector<int64_t>> out_rbs(nn);
   std::vector<void*> out_buf(nn, nullptr);
   hipEvent_t t0 = nullptr, t1 = nullptr;
   HAPOD_HIP(hipEventCreate(&t0));
@@ -661,6 +705,7 @@ hapod_status hapod_run(hapod_plan_t P, hapod_leaf_fn get_leaf, void* user, void*
     std::vector<int32_t> job_node;
     for (int32_t a : P->by_level[l]) {
       std::vector<const void*> in;
+      std::vector<int64_t> in_rbs;
       if (P->children[a].empty()) {
         const void* ptr = nullptr;
         int64_t ld = 0;
@@ -676,8 +721,12 @@ hapod_status hapod_run(hapod_plan_t P, hapod_leaf_fn get_leaf, void* user, void*
           return HAPOD_E_CALLBACK;
         }
         in = column_table(ptr, ld, P->leaf_cols[a], eb);
+        in_rbs.assign(in.size(), kRowBlock);
       } else {
-        for (int32_t b : P->children[a]) in.insert(in.end(), out_cols[b].begin(), out_cols[b].end());
+        for (int32_t b : P->children[a]) {
+          in.insert(in.end(), out_cols[b].begin(), out_cols[b].end());
+          in_rbs.insert(in_rbs.end(), out_rbs[b].begin(), out_rbs[b].end());
+        }
       }
       P->m_in[a] = (int64_t)in.size();
       if (P->eps[a] == 0.0) {
@@ -685,21 +734,28 @@ hapod_status hapod_run(hapod_plan_t P, hapod_leaf_fn get_leaf, void* user, void*
         P->rank[a] = (int64_t)in.size();
         P->sigma[a].assign(in.size(), 1.0);
         out_cols[a] = in;
+        out_rbs[a] = in_rbs;
         if (a == P->root) {
           P->root_passthrough = true;
           P->root_cols = in;
+          P->root_rbs = in_rbs;
         }
         continue;
       }
       PodJob j;
       j.cols = std::move(in);
+      j.rbs = std::move(in_rbs);
       j.n = P->n;
       j.m = (int64_t)j.cols.size();
       j.eps = P->eps[a];
       j.root = (a == P->root);
-      j.ldo = P->n;
+      // the root's modes go out plain column-major; every other node's
+      // scaled modes stay in a row-block-tiled buffer for its parent
+      j.ocs = j.root ? P->n : kRowBlock;
+      j.obs = j.root ? kRowBlock : tiled_rbs(j.m);
       if (j.m > 0) {
-        hapod_status s = P->pool.alloc((size_t)P->n * j.m * eb, &j.out);
+        const size_t bytes = j.root ? (size_t)P->n * j.m * eb : tiled_bytes(P->n, j.m, eb);
+        hapod_status s = P->pool.alloc(bytes, &j.out);
         if (s != HAPOD_OK) {
           release_all();
           return s;
@@ -728,7 +784,13 @@ hapod_status hapod_run(hapod_plan_t P, hapod_leaf_fn get_leaf, void* user, void*
       P->lam1[a] = j.info[1];
       P->lam_min[a] = j.info[2];
       P->n_neg[a] = (int64_t)j.info[3];
-      out_cols[a] = column_table(j.out, P->n, j.rank, eb);
+      if (a == P->root) {
+        out_cols[a] = column_table(j.out, P->n, j.rank, eb);
+        out_rbs[a].assign((size_t)j.rank, kRowBlock);
+      } else {
+        out_cols[a] = tiled_table(j.out, j.rank, eb);
+        out_rbs[a].assign((size_t)j.rank, tiled_rbs(j.m));
+      }
       if (j.rank == 0 && out_buf[a]) {
         P->pool.free(out_buf[a]);
         out_buf[a] = nullptr;
@@ -809,12 +871,15 @@ hapod_status hapod_modes(hapod_plan_t P, int32_t node, void* U, int64_t ldu, dou
     const int eb = elem_bytes(P->opts.prec);
     if (N > 0) {
       if (P->root_passthrough) {
-        void* dcols = nullptr;
+        void *dcols = nullptr, *drbs = nullptr;
         HAPOD_TRY(P->pool.alloc(sizeof(void*) * N, &dcols));
+        HAPOD_TRY(P->pool.alloc(sizeof(int64_t) * N, &drbs));
         HAPOD_HIP(hipMemcpyAsync(dcols, P->root_cols.data(), sizeof(void*) * N, hipMemcpyHostToDevice, stream));
-        hapod_status s = launch_copy_cols(eb, P->n, N, (const void* const*)dcols, U, ldu, stream);
+        HAPOD_HIP(hipMemcpyAsync(drbs, P->root_rbs.data(), sizeof(int64_t) * N, hipMemcpyHostToDevice, stream));
+        hapod_status s = launch_copy_cols(eb, P->n, N, (const void* const*)dcols, (const int64_t*)drbs, U, ldu, stream);
         HAPOD_HIP(hipStreamSynchronize(stream));
         P->pool.free(dcols);
+        P->pool.free(drbs);
         HAPOD_TRY(s);
       } else {
         HAPOD_HIP(hipMemcpy2DAsync(U, (size_t)ldu * eb, P->root_U, (size_t)P->n * eb, (size_t)P->n * eb, (size_t)N,
@@ -883,16 +948,19 @@ hapod_status gram_impl(int compute, int eb, int64_t n, int64_t m, const void* S,
   const int pairs = nt * (nt + 1) / 2;
   const int KB = (compute == 2) ? 32 : 16;
   int nch = (n > 0) ? pick_chunks(n, pairs, 2048, 2048) : 1;
-  int64_t cr = (n > 0) ? ((n + nch - 1) / nch + 63) / 64 * 64 : 64;
+  int64_t cr = (n > 0) ? ((n + nch - 1) / nch + kRowBlock - 1) / kRowBlock * kRowBlock : kRowBlock;
   nch = (n > 0) ? (int)((n + cr - 1) / cr) : 1;
   bool vec_ok = (cr % KB == 0);
   for (auto c : cols)
     if ((uintptr_t)c & 15u) vec_ok = false;
-  void *dcols = nullptr, *dpart = nullptr, *dblob = nullptr;
+  void *dcols = nullptr, *dpart = nullptr, *dblob = nullptr, *drbs = nullptr;
   HAPOD_TRY(pool.alloc(sizeof(void*) * m, &dcols));
+  HAPOD_TRY(pool.alloc(sizeof(int64_t) * m, &drbs));
+  HAPOD_TRY(launch_fill_i64((int64_t*)drbs, kRowBlock, m, stream));
   if (nch > 1) HAPOD_TRY(pool.alloc(sizeof(double) * pairs * nch * kGramTile * kGramTile, &dpart));
   GramNode g{};
   g.cols = (const void* const*)dcols;
+  g.rbs = (const int64_t*)drbs;
   g.n = n;
   g.chunk_rows = cr;
   g.G = G;
@@ -939,6 +1007,7 @@ hapod_status gram_impl(int compute, int eb, int64_t n, int64_t m, const void* S,
   } while (0);
   (void)hipStreamSynchronize(stream);
   pool.free(dcols);
+  pool.free(drbs);
   pool.free(dpart);
   pool.free(dblob);
   return st;
@@ -1061,19 +1130,23 @@ hapod_status hapod_lift(hapod_precision prec, int64_t n, int64_t m, int64_t N, c
   const int eb = elem_bytes(prec);
   Pool& pool = step_pool();
   auto cols = column_table(S, lds, m, eb);
-  void *dcols = nullptr, *dB = nullptr, *drank = nullptr, *dn = nullptr;
+  void *dcols = nullptr, *dB = nullptr, *drank = nullptr, *dn = nullptr, *drbs = nullptr;
   HAPOD_TRY(pool.alloc(sizeof(void*) * std::max<int64_t>(m, 1), &dcols));
+  HAPOD_TRY(pool.alloc(sizeof(int64_t) * std::max<int64_t>(m, 1), &drbs));
+  HAPOD_TRY(launch_fill_i64((int64_t*)drbs, kRowBlock, m, stream));
   HAPOD_TRY(pool.alloc(sizeof(double) * std::max<int64_t>(m * N, 1), &dB));
   HAPOD_TRY(pool.alloc(sizeof(int64_t), &drank));
   HAPOD_TRY(pool.alloc(sizeof(LiftNode), &dn));
   LiftNode l{};
   l.cols = (const void* const*)dcols;
+  l.rbs = (const int64_t*)drbs;
   l.B = (const double*)dB;
   l.rank = (const int64_t*)drank;
   l.out = out;
   l.n = n;
   l.ldb = N;
-  l.ldo = ldo;
+  l.ocs = ldo;
+  l.obs = kRowBlock;
   l.m = (int32_t)m;
   l.row_tiles = (int32_t)((n + kLiftTileM - 1) / kLiftTileM);
   l.col_tiles = (int32_t)((N + kLiftTileN - 1) / kLiftTileN);
@@ -1098,6 +1171,7 @@ hapod_status hapod_lift(hapod_precision prec, int64_t n, int64_t m, int64_t N, c
   } while (0);
   (void)hipStreamSynchronize(stream);
   pool.free(dcols);
+  pool.free(drbs);
   pool.free(dB);
   pool.free(drank);
   pool.free(dn);
@@ -1121,7 +1195,7 @@ hapod_status hapod_reorth(hapod_precision prec, int64_t n, int64_t N, void* U, i
   const int eb = elem_bytes(prec);
   Pool& pool = step_pool();
   void *W = nullptr, *Rinv = nullptr, *tmp = nullptr, *dcols = nullptr, *dn = nullptr, *drank = nullptr,
-       *dbad = nullptr;
+       *dbad = nullptr, *drbs = nullptr;
   HAPOD_TRY(pool.alloc(sizeof(double) * N * N, &W));
   HAPOD_TRY(pool.alloc(sizeof(double) * N * N, &Rinv));
   HAPOD_TRY(pool.alloc((size_t)n * N * eb, &tmp));
@@ -1129,6 +1203,8 @@ hapod_status hapod_reorth(hapod_precision prec, int64_t n, int64_t N, void* U, i
   HAPOD_TRY(pool.alloc(sizeof(LiftNode), &dn));
   HAPOD_TRY(pool.alloc(sizeof(int64_t), &drank));
   HAPOD_TRY(pool.alloc(sizeof(int32_t), &dbad));
+  HAPOD_TRY(pool.alloc(sizeof(int64_t) * N, &drbs));
+  HAPOD_TRY(launch_fill_i64((int64_t*)drbs, kRowBlock, N, stream));
   hapod_status st = HAPOD_OK;
   int64_t total_bad = 0;
   auto cols = column_table(U, ldu, N, eb);
@@ -1140,12 +1216,14 @@ hapod_status hapod_reorth(hapod_precision prec, int64_t n, int64_t N, void* U, i
     if (st != HAPOD_OK) break;
     LiftNode l{};
     l.cols = (const void* const*)dcols;
+    l.rbs = (const int64_t*)drbs;
     l.B = (const double*)Rinv;
     l.rank = (const int64_t*)drank;
     l.out = tmp;
     l.n = n;
     l.ldb = N;
-    l.ldo = n;
+    l.ocs = n;
+    l.obs = kRowBlock;
     l.m = (int32_t)N;
     l.row_tiles = (int32_t)((n + kLiftTileM - 1) / kLiftTileM);
     l.col_tiles = (int32_t)((N + kLiftTileN - 1) / kLiftTileN);
@@ -1171,7 +1249,7 @@ hapod_status hapod_reorth(hapod_precision prec, int64_t n, int64_t N, void* U, i
   }
   (void)hipStreamSynchronize(stream);
   if (bad) *bad = total_bad;
-  for (void* p : {W, Rinv, tmp, dcols, dn, drank, dbad}) pool.free(p);
+  for (void* p : {W, Rinv, tmp, dcols, dn, drank, dbad, drbs}) pool.free(p);
   return st;
 }
 
@@ -1200,12 +1278,14 @@ hapod_status hapod_node_pod(hapod_precision prec, int64_t n, int64_t m, const vo
   }
   std::vector<PodJob> jobs(1);
   jobs[0].cols = column_table(S, lds, m, eb);
+  jobs[0].rbs.assign((size_t)m, kRowBlock);
   jobs[0].n = n;
   jobs[0].m = m;
   jobs[0].eps = eps;
   jobs[0].root = (scaled == 0);
   jobs[0].out = out;
-  jobs[0].ldo = ldo;
+  jobs[0].ocs = ldo;
+  jobs[0].obs = kRowBlock;
   HAPOD_TRY(run_pod_batch(prec, jobs, 0, 1, 256, step_pool(), stream, nullptr));
   *rank = jobs[0].rank;
   if (sigma && jobs[0].rank > 0) std::memcpy(sigma, jobs[0].sigma.data(), sizeof(double) * jobs[0].rank);

@@ -33,8 +33,11 @@ template <> struct GramTraits<2> { using Elem = float; using Acc = f4; static co
 // Gram matrices of float data, e.g. re-orthonormalisation)
 template <> struct GramTraits<3> { using Elem = float; using Acc = d4; static constexpr int R = 4; };
 
+// A run of R rows starting at `row` (a multiple of R, so it never crosses a
+// 128-row block) of a column with row-block stride rbs.
 template <typename Elem, int R, bool VEC>
-__device__ __forceinline__ void load_run(const Elem* p, int64_t row, int64_t r1, float* out) {
+__device__ __forceinline__ void load_run(const Elem* p0, int64_t rbs, int64_t row, int64_t r1, float* out) {
+  const Elem* p = p0 ? p0 + blk_off(row, rbs) - row : nullptr;
   if (p == nullptr) {
 #pragma unroll
     for (int t = 0; t < R; ++t) out[t] = 0.f;
@@ -57,7 +60,8 @@ __device__ __forceinline__ void load_run(const Elem* p, int64_t row, int64_t r1,
 }
 
 template <int R, bool VEC>
-__device__ __forceinline__ void load_run(const double* p, int64_t row, int64_t r1, double* out) {
+__device__ __forceinline__ void load_run(const double* p0, int64_t rbs, int64_t row, int64_t r1, double* out) {
+  const double* p = p0 ? p0 + blk_off(row, rbs) - row : nullptr;
   if (p == nullptr) {
 #pragma unroll
     for (int t = 0; t < R; ++t) out[t] = 0.0;
@@ -98,11 +102,14 @@ __global__ __launch_bounds__(256) void gram_tile_kernel(const GramNode* __restri
 
   const Elem* pa[NB];
   const Elem* pb[NB];
+  int64_t sa[NB], sb[NB];
 #pragma unroll
   for (int a = 0; a < NB; ++a) {
     int ca = cA0 + a * 16 + li, cb = cB0 + a * 16 + li;
     pa[a] = ca < nd.m ? reinterpret_cast<const Elem*>(nd.cols[ca]) : nullptr;
     pb[a] = cb < nd.m ? reinterpret_cast<const Elem*>(nd.cols[cb]) : nullptr;
+    sa[a] = ca < nd.m ? nd.rbs[ca] : kRowBlock;
+    sb[a] = cb < nd.m ? nd.rbs[cb] : kRowBlock;
   }
 
   Acc acc[NB][NB];
@@ -117,8 +124,8 @@ __global__ __launch_bounds__(256) void gram_tile_kernel(const GramNode* __restri
       double va[NB][R], vb[NB][R];
 #pragma unroll
       for (int a = 0; a < NB; ++a) {
-        load_run<R, VEC>(pa[a], row, r1, va[a]);
-        load_run<R, VEC>(pb[a], row, r1, vb[a]);
+        load_run<R, VEC>(pa[a], sa[a], row, r1, va[a]);
+        load_run<R, VEC>(pb[a], sb[a], row, r1, vb[a]);
       }
 #pragma unroll
       for (int t = 0; t < R; ++t)
@@ -130,8 +137,8 @@ __global__ __launch_bounds__(256) void gram_tile_kernel(const GramNode* __restri
       float va[NB][R], vb[NB][R];
 #pragma unroll
       for (int a = 0; a < NB; ++a) {
-        load_run<Elem, R, VEC>(pa[a], row, r1, va[a]);
-        load_run<Elem, R, VEC>(pb[a], row, r1, vb[a]);
+        load_run<Elem, R, VEC>(pa[a], sa[a], row, r1, va[a]);
+        load_run<Elem, R, VEC>(pb[a], sb[a], row, r1, vb[a]);
       }
       if constexpr (C == 1) {
 #pragma unroll

@@ -30,9 +30,20 @@ void set_error(const std::string& msg);
     if (s_ != HAPOD_OK) return s_;      \
   } while (0)
 
+// ---- storage of a column ---------------------------------------------------
+// Rows are grouped in blocks of kRowBlock.  Element r of a column starting at
+// p lives at p[(r / kRowBlock) * rbs + r % kRowBlock]: rbs == kRowBlock is a
+// plain column-major column; rbs == m_cap * kRowBlock is a column of a
+// row-block-tiled n x m_cap buffer (all columns of one 128-row block stored
+// contiguously), the layout of every buffer the library owns.
+constexpr int kRowBlock = 128;
+__host__ __device__ inline int64_t blk_off(int64_t r, int64_t rbs) {
+  return (r >> 7) * rbs + (r & (kRowBlock - 1));
+}
+
 // ---- batched Gram ----------------------------------------------------------
-// One node's input: m columns, column j starting at cols[j] (device pointer
-// array), rows [0, n).  Tiles of kGramTile x kGramTile on the upper triangle;
+// One node's input: m columns, column j starting at cols[j] with row-block
+// stride rbs[j] (device arrays), rows [0, n).  Tiles of kGramTile x kGramTile on the upper triangle;
 // rows split into nchunks chunks of chunk_rows.  With nchunks == 1 the tile is
 // written straight into G (both triangles); otherwise into
 // partial[(pair * nchunks + chunk) * T*T] and reduced by gram_reduce.
@@ -40,6 +51,7 @@ constexpr int kGramTile = 128;
 
 struct GramNode {
   const void* const* cols;
+  const int64_t* rbs;
   int64_t n;
   int64_t chunk_rows;
   double* G;
@@ -117,12 +129,14 @@ constexpr int kLiftTileM = 128;
 constexpr int kLiftTileN = 128;
 struct LiftNode {
   const void* const* cols;
+  const int64_t* rbs;
   const double* B;
   const int64_t* rank;   // device pointer to N
-  void* out;
+  void* out;             // element (r, c) at out[c * ocs + blk_off(r, obs)]
   int64_t n;
   int64_t ldb;
-  int64_t ldo;
+  int64_t ocs;           // column stride: ld (plain) or kRowBlock (tiled)
+  int64_t obs;           // row-block stride: kRowBlock (plain) or m_cap * kRowBlock
   int32_t m;
   int32_t row_tiles;
   int32_t col_tiles;     // worst case ceil(maxN / TN)
@@ -136,10 +150,11 @@ hapod_status launch_lift(int compute, const LiftNode* d_nodes, int num_nodes,
 hapod_status launch_fill_colptrs(const void* base, int64_t ld, int64_t m, int elem_bytes,
                                  const void** d_out, hipStream_t stream);
 hapod_status launch_copy_cols(int elem_bytes, int64_t n, int64_t m, const void* const* cols,
-                              void* out, int64_t ldo, hipStream_t stream);
+                              const int64_t* rbs, void* out, int64_t ldo, hipStream_t stream);
 hapod_status launch_check_diag(const double* G, int64_t ldg, int64_t m, int32_t* d_flag,
                                hipStream_t stream);
 hapod_status launch_set_scalar_i64(int64_t* p, int64_t v, hipStream_t stream);
+hapod_status launch_fill_i64(int64_t* p, int64_t v, int64_t count, hipStream_t stream);
 
 // ---- Cholesky-QR re-orthonormalisation -------------------------------------
 hapod_status launch_chol_inv(double* W, int64_t ldw, int64_t N, double* Rinv, int64_t ldr,

@@ -1,7 +1,6 @@
 // Batched mode lift out = S B (Rem. 2.3, Def. 3.2): S is n x m (column
 // pointers), B the row-major lift operand written by the truncation kernel,
-// N (the node's rank) read from device memory, so a launch sized for the
-// worst case retires the tiles beyond N at once.
+// N (the node's rank) read from device memory; tiles beyond N retire at once.
 //
 // Work item = (node, 128-row tile, 128-column tile); four wavefronts per
 // workgroup, each a 64 x 64 sub-tile of 16 x 16 MFMA blocks.  The MFMA rows
@@ -32,8 +31,10 @@ __global__ __launch_bounds__(256) void lift_kernel(const LiftNode* __restrict__ 
   int ni = 0;
   while (ni + 1 < num_nodes && nodes[ni + 1].item_base <= item) ++ni;
   const LiftNode nd = nodes[ni];
+  // column tiles of one row stripe are adjacent: they land on the same XCD
+  // and share that stripe of S through its L2
   const int local = item - nd.item_base;
-  const int rt = local % nd.row_tiles, ct = local / nd.row_tiles;
+  const int rt = local / nd.col_tiles, ct = local % nd.col_tiles;
   const int64_t N = *nd.rank;
   if ((int64_t)ct * TN >= N) return;
 
@@ -55,12 +56,13 @@ __global__ __launch_bounds__(256) void lift_kernel(const LiftNode* __restrict__ 
     if constexpr (C == 0 || C == 1) {
       const int k = k0 + g;
       const Elem* col = (k < m) ? reinterpret_cast<const Elem*>(nd.cols[k]) : nullptr;
+      const int64_t rbs = (k < m) ? nd.rbs[k] : kRowBlock;
       Elem va[NB];
       double vb[NB];
 #pragma unroll
       for (int a = 0; a < NB; ++a) {
         const int64_t row = r0 + a * 16 + li;
-        va[a] = (col && row < nd.n) ? col[row] : Elem(0);
+        va[a] = (col && row < nd.n) ? col[blk_off(row, rbs)] : Elem(0);
       }
 #pragma unroll
       for (int b = 0; b < NB; ++b) {
@@ -81,10 +83,11 @@ __global__ __launch_bounds__(256) void lift_kernel(const LiftNode* __restrict__ 
       for (int e = 0; e < 8; ++e) {
         const int k = k0 + 8 * g + e;
         const float* col = (k < m) ? reinterpret_cast<const float*>(nd.cols[k]) : nullptr;
+        const int64_t rbs = (k < m) ? nd.rbs[k] : kRowBlock;
 #pragma unroll
         for (int a = 0; a < NB; ++a) {
           const int64_t row = r0 + a * 16 + li;
-          xa[a][e] = (col && row < nd.n) ? col[row] : 0.f;
+          xa[a][e] = (col && row < nd.n) ? col[blk_off(row, rbs)] : 0.f;
         }
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
@@ -117,7 +120,7 @@ __global__ __launch_bounds__(256) void lift_kernel(const LiftNode* __restrict__ 
       for (int v = 0; v < 4; ++v) {
         const int64_t row = r0 + a * 16 + acc_row<Acc>(lane, v);
         const int64_t col = n0 + b * 16 + acc_col(lane);
-        if (row < nd.n && col < N) out[col * nd.ldo + row] = (Elem)acc[a][b][v];
+        if (row < nd.n && col < N) out[col * nd.ocs + blk_off(row, nd.obs)] = (Elem)acc[a][b][v];
       }
 }
 

@@ -12,11 +12,13 @@ __global__ void fill_colptrs_kernel(const char* base, int64_t ld_bytes, int64_t 
 }
 
 template <typename E>
-__global__ void copy_cols_kernel(int64_t n, int64_t m, const void* const* cols, E* out, int64_t ldo) {
+__global__ void copy_cols_kernel(int64_t n, int64_t m, const void* const* cols, const int64_t* rbs, E* out,
+                                 int64_t ldo) {
   const int64_t j = blockIdx.y;
   const E* src = reinterpret_cast<const E*>(cols[j]);
+  const int64_t s = rbs[j];
   for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x)
-    out[j * ldo + r] = src[r];
+    out[j * ldo + r] = src[blk_off(r, s)];
 }
 
 __global__ void check_diag_kernel(const double* G, int64_t ldg, int64_t m, int32_t* flag) {
@@ -27,6 +29,11 @@ __global__ void check_diag_kernel(const double* G, int64_t ldg, int64_t m, int32
 }
 
 __global__ void set_i64_kernel(int64_t* p, int64_t v) { *p = v; }
+
+__global__ void fill_i64_kernel(int64_t* p, int64_t v, int64_t count) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
 
 // W (N x N, symmetric, upper used) = R^T R in place (upper R), then Rinv =
 // R^{-1} (upper, row-major).  A pivot <= 1e-12 of its original diagonal marks the column
@@ -95,8 +102,8 @@ hapod_status launch_fill_colptrs(const void* base, int64_t ld, int64_t m, int el
   return HAPOD_OK;
 }
 
-hapod_status launch_copy_cols(int elem_bytes, int64_t n, int64_t m, const void* const* cols, void* out,
-                              int64_t ldo, hipStream_t stream) {
+hapod_status launch_copy_cols(int elem_bytes, int64_t n, int64_t m, const void* const* cols, const int64_t* rbs,
+                              void* out, int64_t ldo, hipStream_t stream) {
   if (m <= 0 || n <= 0) return HAPOD_OK;
   if (m > 65535) {
     set_error("launch_copy_cols: too many columns");
@@ -104,10 +111,10 @@ hapod_status launch_copy_cols(int elem_bytes, int64_t n, int64_t m, const void* 
   }
   const unsigned gx = (unsigned)std::min<int64_t>((n + 255) / 256, 1024);
   if (elem_bytes == 8)
-    hipLaunchKernelGGL(copy_cols_kernel<double>, dim3(gx, (unsigned)m), dim3(256), 0, stream, n, m, cols,
+    hipLaunchKernelGGL(copy_cols_kernel<double>, dim3(gx, (unsigned)m), dim3(256), 0, stream, n, m, cols, rbs,
                        (double*)out, ldo);
   else
-    hipLaunchKernelGGL(copy_cols_kernel<float>, dim3(gx, (unsigned)m), dim3(256), 0, stream, n, m, cols,
+    hipLaunchKernelGGL(copy_cols_kernel<float>, dim3(gx, (unsigned)m), dim3(256), 0, stream, n, m, cols, rbs,
                        (float*)out, ldo);
   HAPOD_HIP(hipGetLastError());
   return HAPOD_OK;
@@ -123,6 +130,14 @@ hapod_status launch_check_diag(const double* G, int64_t ldg, int64_t m, int32_t*
 
 hapod_status launch_set_scalar_i64(int64_t* p, int64_t v, hipStream_t stream) {
   hipLaunchKernelGGL(set_i64_kernel, dim3(1), dim3(1), 0, stream, p, v);
+  HAPOD_HIP(hipGetLastError());
+  return HAPOD_OK;
+}
+
+hapod_status launch_fill_i64(int64_t* p, int64_t v, int64_t count, hipStream_t stream) {
+  if (count <= 0) return HAPOD_OK;
+  hipLaunchKernelGGL(fill_i64_kernel, dim3((unsigned)std::min<int64_t>((count + 255) / 256, 1024)), dim3(256), 0,
+                     stream, p, v, count);
   HAPOD_HIP(hipGetLastError());
   return HAPOD_OK;
 }

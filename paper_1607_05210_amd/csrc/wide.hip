@@ -303,9 +303,10 @@ hapod_status wide_eigh(const double* G, int64_t ldg, int64_t m, double* lambda, 
   int* ipiv = (int*)get(sizeof(int) * (size_t)k * k);
   double* tr = (double*)get(sizeof(double));
   const void** qcols = (const void**)get(sizeof(void*) * k);
+  int64_t* qrbs = (int64_t*)get(sizeof(int64_t) * k);
   int64_t* drank = (int64_t*)get(sizeof(int64_t));
   void* dnode = get(sizeof(LiftNode));
-  if (!Q || !w || !h || !alpha || !beta || !theta || !e2 || !Z || !last || !isc || !ipiv || !tr || !qcols || !drank ||
+  if (!Q || !w || !h || !alpha || !beta || !theta || !e2 || !Z || !last || !isc || !ipiv || !tr || !qcols || !qrbs || !drank ||
       !dnode) {
     set_error("wide_eigh: scratch allocation failed");
     return HAPOD_E_NOMEM;
@@ -353,15 +354,18 @@ hapod_status wide_eigh(const double* G, int64_t ldg, int64_t m, double* lambda, 
   // ---- Ritz vectors V[:, :b] = Q_k Z[:, :b] (FP64 lift GEMM) ------------------------
   if (b > 0) {
     HAPOD_TRY(launch_fill_colptrs(Q, m, k, 8, qcols, stream));
+    HAPOD_TRY(launch_fill_i64(qrbs, kRowBlock, k, stream));
     HAPOD_TRY(launch_set_scalar_i64(drank, b, stream));
     LiftNode l{};
     l.cols = (const void* const*)qcols;
+    l.rbs = qrbs;
     l.B = Z;
     l.rank = drank;
     l.out = V;
     l.n = m;
     l.ldb = k;
-    l.ldo = ldv;
+    l.ocs = ldv;
+    l.obs = kRowBlock;
     l.m = k;
     l.row_tiles = (int32_t)((m + kLiftTileM - 1) / kLiftTileM);
     l.col_tiles = (int32_t)((b + kLiftTileN - 1) / kLiftTileN);
