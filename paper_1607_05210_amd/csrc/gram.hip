@@ -33,47 +33,64 @@ template <> struct GramTraits<2> { using Elem = float; using Acc = f4; static co
 // Gram matrices of float data, e.g. re-orthonormalisation)
 template <> struct GramTraits<3> { using Elem = float; using Acc = d4; static constexpr int R = 4; };
 
-// A run of R rows starting at `row` (a multiple of R, so it never crosses a
-// 128-row block) of a column with row-block stride rbs.
-template <typename Elem, int R, bool VEC>
-__device__ __forceinline__ void load_run(const Elem* p0, int64_t rbs, int64_t row, int64_t r1, float* out) {
-  const Elem* p = p0 ? p0 + blk_off(row, rbs) - row : nullptr;
-  if (p == nullptr) {
+// Loads of one R-row run from a row-block-aligned global pointer (no guards).
+template <int R, bool VEC>
+__device__ __forceinline__ void run_full(gptr<double> p, double* out) {
+  if constexpr (VEC) {
+    const dv2 v0 = *(gptr<dv2>)(p);
+    const dv2 v1 = *(gptr<dv2>)(p + 2);
+    out[0] = v0[0]; out[1] = v0[1]; out[2] = v1[0]; out[3] = v1[1];
+  } else {
 #pragma unroll
-    for (int t = 0; t < R; ++t) out[t] = 0.f;
-    return;
+    for (int t = 0; t < R; ++t) out[t] = p[t];
   }
-  if (VEC && row + R <= r1) {
-    if constexpr (R == 4) {
-      float4 v = *reinterpret_cast<const float4*>(p + row);
-      out[0] = v.x; out[1] = v.y; out[2] = v.z; out[3] = v.w;
-    } else {
-      float4 v0 = *reinterpret_cast<const float4*>(p + row);
-      float4 v1 = *reinterpret_cast<const float4*>(p + row + 4);
-      out[0] = v0.x; out[1] = v0.y; out[2] = v0.z; out[3] = v0.w;
-      out[4] = v1.x; out[5] = v1.y; out[6] = v1.z; out[7] = v1.w;
+}
+template <int R, bool VEC>
+__device__ __forceinline__ void run_full(gptr<float> p, float* out) {
+  if constexpr (VEC) {
+#pragma unroll
+    for (int q = 0; q < R / 4; ++q) {
+      const fv4 v = *(gptr<fv4>)(p + 4 * q);
+      out[4 * q] = v[0]; out[4 * q + 1] = v[1]; out[4 * q + 2] = v[2]; out[4 * q + 3] = v[3];
     }
   } else {
 #pragma unroll
-    for (int t = 0; t < R; ++t) out[t] = (row + t < r1) ? (float)p[row + t] : 0.f;
+    for (int t = 0; t < R; ++t) out[t] = p[t];
   }
 }
 
-template <int R, bool VEC>
-__device__ __forceinline__ void load_run(const double* p0, int64_t rbs, int64_t row, int64_t r1, double* out) {
-  const double* p = p0 ? p0 + blk_off(row, rbs) - row : nullptr;
-  if (p == nullptr) {
+template <int C, typename Acc, int R>
+__device__ __forceinline__ void mfma_batch(Acc (&acc)[NB][NB], typename GramTraits<C>::Elem (&va)[NB][R],
+                                           typename GramTraits<C>::Elem (&vb)[NB][R]) {
+  if constexpr (C == 0 || C == 3) {
 #pragma unroll
-    for (int t = 0; t < R; ++t) out[t] = 0.0;
-    return;
-  }
-  if (VEC && row + R <= r1) {
-    double2 v0 = *reinterpret_cast<const double2*>(p + row);
-    double2 v1 = *reinterpret_cast<const double2*>(p + row + 2);
-    out[0] = v0.x; out[1] = v0.y; out[2] = v1.x; out[3] = v1.y;
+    for (int t = 0; t < R; ++t)
+#pragma unroll
+      for (int a = 0; a < NB; ++a)
+#pragma unroll
+        for (int b = 0; b < NB; ++b) acc[a][b] = mfma_f64((double)va[a][t], (double)vb[b][t], acc[a][b]);
+  } else if constexpr (C == 1) {
+#pragma unroll
+    for (int t = 0; t < R; ++t)
+#pragma unroll
+      for (int a = 0; a < NB; ++a)
+#pragma unroll
+        for (int b = 0; b < NB; ++b) acc[a][b] = mfma_f32(va[a][t], vb[b][t], acc[a][b]);
   } else {
+    bf8 ha[NB], la[NB], hb[NB], lb[NB];
 #pragma unroll
-    for (int t = 0; t < R; ++t) out[t] = (row + t < r1) ? p[row + t] : 0.0;
+    for (int a = 0; a < NB; ++a) {
+      split_bf16x8(va[a], ha[a], la[a]);
+      split_bf16x8(vb[a], hb[a], lb[a]);
+    }
+#pragma unroll
+    for (int a = 0; a < NB; ++a)
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        acc[a][b] = mfma_bf16(la[a], hb[b], acc[a][b]);
+        acc[a][b] = mfma_bf16(ha[a], lb[b], acc[a][b]);
+        acc[a][b] = mfma_bf16(ha[a], hb[b], acc[a][b]);
+      }
   }
 }
 
@@ -84,7 +101,8 @@ __global__ __launch_bounds__(256) void gram_tile_kernel(const GramNode* __restri
   using Elem = typename Tr::Elem;
   using Acc = typename Tr::Acc;
   constexpr int R = Tr::R;
-  constexpr int KB = 4 * R;  // rows per batch
+  constexpr int KB = 4 * R;             // rows per MFMA batch
+  constexpr int NBT = kRowBlock / KB;   // batches per 128-row block
 
   const GramItem item = items[xcd_item(blockIdx.x, gridDim.x)];
   const GramNode nd = nodes[item.node];
@@ -97,19 +115,22 @@ __global__ __launch_bounds__(256) void gram_tile_kernel(const GramNode* __restri
   const int cA0 = item.ti * T + wi * WT, cB0 = item.tj * T + wj * WT;
   if (cA0 >= nd.m || cB0 >= nd.m) return;
 
+  // row range of this chunk; chunks start on 128-row block boundaries
   const int64_t r0 = (int64_t)item.chunk * nd.chunk_rows;
   const int64_t r1 = min(nd.n, r0 + nd.chunk_rows);
 
+  // column bases; columns past m alias the block's first column (their
+  // products land in accumulator entries that are never stored)
   const Elem* pa[NB];
   const Elem* pb[NB];
   int64_t sa[NB], sb[NB];
 #pragma unroll
   for (int a = 0; a < NB; ++a) {
-    int ca = cA0 + a * 16 + li, cb = cB0 + a * 16 + li;
-    pa[a] = ca < nd.m ? reinterpret_cast<const Elem*>(nd.cols[ca]) : nullptr;
-    pb[a] = cb < nd.m ? reinterpret_cast<const Elem*>(nd.cols[cb]) : nullptr;
-    sa[a] = ca < nd.m ? nd.rbs[ca] : kRowBlock;
-    sb[a] = cb < nd.m ? nd.rbs[cb] : kRowBlock;
+    const int ca = min(cA0 + a * 16 + li, nd.m - 1), cb = min(cB0 + a * 16 + li, nd.m - 1);
+    pa[a] = reinterpret_cast<const Elem*>(nd.cols[ca]);
+    pb[a] = reinterpret_cast<const Elem*>(nd.cols[cb]);
+    sa[a] = nd.rbs[ca];
+    sb[a] = nd.rbs[cb];
   }
 
   Acc acc[NB][NB];
@@ -118,60 +139,41 @@ __global__ __launch_bounds__(256) void gram_tile_kernel(const GramNode* __restri
 #pragma unroll
     for (int b = 0; b < NB; ++b) acc[a][b] = Acc{0, 0, 0, 0};
 
-  for (int64_t k0 = r0; k0 < r1; k0 += KB) {
+  // full 128-row blocks: constant offsets, no guards
+  const int64_t blk0 = r0 >> 7, nfull = (r1 - r0) >> 7;
+  for (int64_t bi = 0; bi < nfull; ++bi) {
+    gptr<Elem> qa[NB], qb[NB];
+#pragma unroll
+    for (int a = 0; a < NB; ++a) {
+      qa[a] = as_global(pa[a] + (blk0 + bi) * sa[a] + R * g);
+      qb[a] = as_global(pb[a] + (blk0 + bi) * sb[a] + R * g);
+    }
+#pragma unroll
+    for (int bt = 0; bt < NBT; ++bt) {
+      Elem va[NB][R], vb[NB][R];
+#pragma unroll
+      for (int a = 0; a < NB; ++a) {
+        run_full<R, VEC>(qa[a] + bt * KB, va[a]);
+        run_full<R, VEC>(qb[a] + bt * KB, vb[a]);
+      }
+      mfma_batch<C, Acc, R>(acc, va, vb);
+    }
+  }
+  // partial last block: guarded runs
+  for (int64_t k0 = r0 + (nfull << 7); k0 < r1; k0 += KB) {
     const int64_t row = k0 + (int64_t)R * g;
-    if constexpr (C == 0) {
-      double va[NB][R], vb[NB][R];
+    Elem va[NB][R], vb[NB][R];
 #pragma unroll
-      for (int a = 0; a < NB; ++a) {
-        load_run<R, VEC>(pa[a], sa[a], row, r1, va[a]);
-        load_run<R, VEC>(pb[a], sb[a], row, r1, vb[a]);
-      }
+    for (int a = 0; a < NB; ++a) {
+      const Elem* xa = pa[a] + blk_off(row, sa[a]);
+      const Elem* xb = pb[a] + blk_off(row, sb[a]);
 #pragma unroll
-      for (int t = 0; t < R; ++t)
-#pragma unroll
-        for (int a = 0; a < NB; ++a)
-#pragma unroll
-          for (int b = 0; b < NB; ++b) acc[a][b] = mfma_f64(va[a][t], vb[b][t], acc[a][b]);
-    } else {
-      float va[NB][R], vb[NB][R];
-#pragma unroll
-      for (int a = 0; a < NB; ++a) {
-        load_run<Elem, R, VEC>(pa[a], sa[a], row, r1, va[a]);
-        load_run<Elem, R, VEC>(pb[a], sb[a], row, r1, vb[a]);
-      }
-      if constexpr (C == 1) {
-#pragma unroll
-        for (int t = 0; t < R; ++t)
-#pragma unroll
-          for (int a = 0; a < NB; ++a)
-#pragma unroll
-            for (int b = 0; b < NB; ++b) acc[a][b] = mfma_f32(va[a][t], vb[b][t], acc[a][b]);
-      } else if constexpr (C == 3) {
-#pragma unroll
-        for (int t = 0; t < R; ++t)
-#pragma unroll
-          for (int a = 0; a < NB; ++a)
-#pragma unroll
-            for (int b = 0; b < NB; ++b)
-              acc[a][b] = mfma_f64((double)va[a][t], (double)vb[b][t], acc[a][b]);
-      } else {
-        bf8 ha[NB], la[NB], hb[NB], lb[NB];
-#pragma unroll
-        for (int a = 0; a < NB; ++a) {
-          split_bf16x8(va[a], ha[a], la[a]);
-          split_bf16x8(vb[a], hb[a], lb[a]);
-        }
-#pragma unroll
-        for (int a = 0; a < NB; ++a)
-#pragma unroll
-          for (int b = 0; b < NB; ++b) {
-            acc[a][b] = mfma_bf16(la[a], hb[b], acc[a][b]);
-            acc[a][b] = mfma_bf16(ha[a], lb[b], acc[a][b]);
-            acc[a][b] = mfma_bf16(ha[a], hb[b], acc[a][b]);
-          }
+      for (int t = 0; t < R; ++t) {
+        va[a][t] = (row + t < r1) ? xa[t] : Elem(0);
+        vb[a][t] = (row + t < r1) ? xb[t] : Elem(0);
       }
     }
+    mfma_batch<C, Acc, R>(acc, va, vb);
   }
 
   // store: direct into G (single chunk) or into the chunk's partial tile

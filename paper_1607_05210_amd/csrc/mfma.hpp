@@ -11,6 +11,8 @@ namespace hapod {
 typedef double d4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef double dv2 __attribute__((ext_vector_type(2)));
+typedef float fv4 __attribute__((ext_vector_type(4)));
 
 // 16x16 MFMA accumulators.  Operand lanes: lane l supplies row (A) / column
 // (B) index l % 16 and reduction slot l / 16.  Result lanes: lane l holds
@@ -59,6 +61,11 @@ __device__ __forceinline__ void split_bf16x8(const float* x, bf8& hi, bf8& lo) {
     lo[e] = __builtin_bit_cast(__bf16, l);
   }
 }
+
+// Pointers into global memory (address space 1): loads through them become
+// global_load instructions instead of generic flat loads.
+template <class T> using gptr = const __attribute__((address_space(1))) T*;
+template <class T> __device__ __forceinline__ gptr<T> as_global(const T* p) { return (gptr<T>)p; }
 
 // Map a linear workgroup id to a work-item index so that each of the 8 XCDs
 // (which receive workgroups round-robin) gets one contiguous range of items.
