@@ -32,6 +32,24 @@ int elem_bytes(hapod_precision p) { return p == HAPOD_FP64 ? 8 : 4; }
 int compute_mode(hapod_precision p) { return p == HAPOD_FP64 ? 0 : (p == HAPOD_FP32 ? 1 : 2); }
 
 constexpr size_t kAlign = 256;
+constexpr int64_t kPresplitMinCols = 256;
+
+// plain column-major n x m (leading dimension ld)
+std::vector<const void*> column_table(const void* base, int64_t ld, int64_t m, int eb) {
+  std::vector<const void*> v((size_t)m);
+  for (int64_t j = 0; j < m; ++j) v[j] = (const char*)base + j * ld * eb;
+  return v;
+}
+// row-block-tiled n x m_cap buffer: column j starts kRowBlock * j elements in
+int64_t tiled_rbs(int64_t m_cap) { return m_cap * kRowBlock; }
+std::vector<const void*> tiled_table(const void* base, int64_t m, int eb) {
+  std::vector<const void*> v((size_t)m);
+  for (int64_t j = 0; j < m; ++j) v[j] = (const char*)base + j * kRowBlock * eb;
+  return v;
+}
+size_t tiled_bytes(int64_t n, int64_t m_cap, int eb) {
+  return (size_t)((n + kRowBlock - 1) / kRowBlock) * kRowBlock * m_cap * eb;
+}
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 // ---------------------------------------------------------------------------
@@ -173,7 +191,8 @@ hapod_status run_pod_batch(hapod_precision prec, std::vector<PodJob>& jobs, int 
 
   // ---- sizes & scratch layout ---------------------------------------------
   struct Lay {
-    size_t cols, rbs, G, partial, lam, V, B, sigma, rank, info, jwork, vwork, sweeps;
+    size_t cols, rbs, cols2, rbs2, G, partial, lam, V, B, sigma, rank, info, jwork, vwork, sweeps;
+    bool presplit;
     int ntiles, pairs, nchunks;
     int64_t chunk_rows;
   };
@@ -209,6 +228,11 @@ hapod_status run_pod_batch(hapod_precision prec, std::vector<PodJob>& jobs, int 
     };
     L.cols = take(sizeof(void*) * std::max<int64_t>(m, 1));
     L.rbs = take(sizeof(int64_t) * std::max<int64_t>(m, 1));
+    // split-BF16: nodes with several column tiles get a split twin of their
+    // input once, instead of splitting every element in each tile that reads it
+    L.presplit = (compute == 2 && m >= kPresplitMinCols && j.n > 0);
+    L.cols2 = L.presplit ? take(sizeof(void*) * m) : 0;
+    L.rbs2 = L.presplit ? take(sizeof(int64_t) * m) : 0;
     L.G = take(sizeof(double) * m * m);
     L.partial = (L.nchunks > 1) ? take(sizeof(double) * (size_t)L.pairs * L.nchunks * kGramTile * kGramTile) : 0;
     L.lam = take(sizeof(double) * std::max<int64_t>(m, 1));
@@ -231,6 +255,24 @@ hapod_status run_pod_batch(hapod_precision prec, std::vector<PodJob>& jobs, int 
     void* s;
     ~Guard() { p.free(s); }
   } guard{pool, scratch};
+  // split twins (released with the batch)
+  std::vector<void*> split_buf(nj, nullptr);
+  struct GuardV {
+    Pool& p;
+    std::vector<void*>& v;
+    ~GuardV() {
+      for (void* q : v) p.free(q);
+    }
+  } guardv{pool, split_buf};
+  std::vector<std::vector<const void*>> cols2(nj);
+  std::vector<std::vector<int64_t>> rbs2(nj);
+  for (int i = 0; i < nj; ++i) {
+    if (!lay[i].presplit) continue;
+    const int64_t m = jobs[i].m;
+    HAPOD_TRY(pool.alloc(tiled_bytes(jobs[i].n, m, 4), &split_buf[i]));
+    cols2[i] = tiled_table(split_buf[i], m, 4);
+    rbs2[i].assign((size_t)m, tiled_rbs(m));
+  }
 
   // ---- descriptor tables ----------------------------------------------------
   std::vector<GramNode> gnodes(nj);
@@ -248,8 +290,9 @@ hapod_status run_pod_batch(hapod_precision prec, std::vector<PodJob>& jobs, int 
       if (((uintptr_t)c & 15u) != 0) vec_ok = false;
     if (L.chunk_rows % KB) vec_ok = false;
     GramNode& g = gnodes[i];
-    g.cols = (const void* const*)(scratch + L.cols);
-    g.rbs = (const int64_t*)(scratch + L.rbs);
+    g.cols = (const void* const*)(scratch + (L.presplit ? L.cols2 : L.cols));
+    g.rbs = (const int64_t*)(scratch + (L.presplit ? L.rbs2 : L.rbs));
+    g.split = L.presplit ? 1 : 0;
     g.n = j.n;
     g.chunk_rows = L.chunk_rows;
     g.G = (double*)(scratch + L.G);
@@ -305,10 +348,12 @@ hapod_status run_pod_batch(hapod_precision prec, std::vector<PodJob>& jobs, int 
   }
 
   Blob blob;
-  std::vector<size_t> col_off(nj), rbs_off(nj);
+  std::vector<size_t> col_off(nj), rbs_off(nj), col2_off(nj), rbs2_off(nj);
   for (int i = 0; i < nj; ++i) {
     col_off[i] = blob.add_vec(jobs[i].cols);
     rbs_off[i] = blob.add_vec(jobs[i].rbs);
+    col2_off[i] = blob.add_vec(cols2[i]);
+    rbs2_off[i] = blob.add_vec(rbs2[i]);
   }
   const size_t o_g = blob.add_vec(gnodes), o_gi = blob.add_vec(gitems), o_rp = blob.add_vec(rpairs),
                o_rn = blob.add_vec(rnode), o_es = blob.add_vec(enodes_small), o_eb = blob.add_vec(enodes_big),
@@ -327,13 +372,23 @@ hapod_status run_pod_batch(hapod_precision prec, std::vector<PodJob>& jobs, int 
                                hipMemcpyDeviceToDevice, stream));
       HAPOD_HIP(hipMemcpyAsync(scratch + lay[i].rbs, dblob + rbs_off[i], sizeof(int64_t) * jobs[i].m,
                                hipMemcpyDeviceToDevice, stream));
+      if (lay[i].presplit) {
+        HAPOD_HIP(hipMemcpyAsync(scratch + lay[i].cols2, dblob + col2_off[i], sizeof(void*) * jobs[i].m,
+                                 hipMemcpyDeviceToDevice, stream));
+        HAPOD_HIP(hipMemcpyAsync(scratch + lay[i].rbs2, dblob + rbs2_off[i], sizeof(int64_t) * jobs[i].m,
+                                 hipMemcpyDeviceToDevice, stream));
+      }
     }
   int32_t* d_flag = (int32_t*)(scratch + flag_off);
   HAPOD_HIP(hipMemsetAsync(d_flag, 0, 64, stream));
 
   Events ev;
   if (times && ev.ok) HAPOD_HIP(hipEventRecord(ev.e[0], stream));
-  // ---- Gram -----------------------------------------------------------------
+  // ---- split twins, then Gram ---------------------------------------------------
+  for (int i = 0; i < nj; ++i)
+    if (lay[i].presplit)
+      HAPOD_TRY(launch_split_cols(jobs[i].n, jobs[i].m, (const void* const*)(scratch + lay[i].cols),
+                                  (const int64_t*)(scratch + lay[i].rbs), (float*)split_buf[i], stream));
   HAPOD_TRY(launch_gram(compute, (const GramNode*)(dblob + o_g), (const GramItem*)(dblob + o_gi), (int)gitems.size(),
                         (const int32_t*)(dblob + o_rp), (const int32_t*)(dblob + o_rn), (int)rpairs.size(), vec_ok,
                         stream));
@@ -375,8 +430,8 @@ hapod_status run_pod_batch(hapod_precision prec, std::vector<PodJob>& jobs, int 
     const PodJob& j = jobs[i];
     if (j.m <= 0 || j.n <= 0 || ranks[i] <= 0) continue;
     LiftNode l{};
-    l.cols = gnodes[i].cols;
-    l.rbs = gnodes[i].rbs;
+    l.cols = (const void* const*)(scratch + lay[i].cols);
+    l.rbs = (const int64_t*)(scratch + lay[i].rbs);
     l.B = tnodes[i].B;
     l.rank = tnodes[i].rank;
     l.out = j.out;
@@ -433,22 +488,6 @@ hapod_status run_pod_batch(hapod_precision prec, std::vector<PodJob>& jobs, int 
   return HAPOD_OK;
 }
 
-// plain column-major n x m (leading dimension ld)
-std::vector<const void*> column_table(const void* base, int64_t ld, int64_t m, int eb) {
-  std::vector<const void*> v((size_t)m);
-  for (int64_t j = 0; j < m; ++j) v[j] = (const char*)base + j * ld * eb;
-  return v;
-}
-// row-block-tiled n x m_cap buffer: column j starts kRowBlock * j elements in
-int64_t tiled_rbs(int64_t m_cap) { return m_cap * kRowBlock; }
-std::vector<const void*> tiled_table(const void* base, int64_t m, int eb) {
-  std::vector<const void*> v((size_t)m);
-  for (int64_t j = 0; j < m; ++j) v[j] = (const char*)base + j * kRowBlock * eb;
-  return v;
-}
-size_t tiled_bytes(int64_t n, int64_t m_cap, int eb) {
-  return (size_t)((n + kRowBlock - 1) / kRowBlock) * kRowBlock * m_cap * eb;
-}
 
 hapod_status check_prec(hapod_precision p) {
   if (p != HAPOD_FP64 && p != HAPOD_FP32 && p != HAPOD_BF16X3) {
@@ -958,9 +997,25 @@ hapod_status gram_impl(int compute, int eb, int64_t n, int64_t m, const void* S,
   HAPOD_TRY(pool.alloc(sizeof(int64_t) * m, &drbs));
   HAPOD_TRY(launch_fill_i64((int64_t*)drbs, kRowBlock, m, stream));
   if (nch > 1) HAPOD_TRY(pool.alloc(sizeof(double) * pairs * nch * kGramTile * kGramTile, &dpart));
+  // split-BF16 with several column tiles: read a split twin (as the level batch does)
+  void* dsplit = nullptr;
+  const bool presplit = (compute == 2 && m >= kPresplitMinCols && n > 0);
+  std::vector<const void*> cols_g = cols;
+  std::vector<int64_t> rbs_g;
+  if (presplit) {
+    HAPOD_TRY(pool.alloc(tiled_bytes(n, m, 4), &dsplit));
+    cols_g = tiled_table(dsplit, m, 4);
+    rbs_g.assign((size_t)m, tiled_rbs(m));
+  }
+  void *dcols_g = nullptr, *drbs_g = nullptr;
+  if (presplit) {
+    HAPOD_TRY(pool.alloc(sizeof(void*) * m, &dcols_g));
+    HAPOD_TRY(pool.alloc(sizeof(int64_t) * m, &drbs_g));
+  }
   GramNode g{};
-  g.cols = (const void* const*)dcols;
-  g.rbs = (const int64_t*)drbs;
+  g.cols = (const void* const*)(presplit ? dcols_g : dcols);
+  g.rbs = (const int64_t*)(presplit ? drbs_g : drbs);
+  g.split = presplit ? 1 : 0;
   g.n = n;
   g.chunk_rows = cr;
   g.G = G;
@@ -994,6 +1049,16 @@ hapod_status gram_impl(int compute, int eb, int64_t n, int64_t m, const void* S,
       st = HAPOD_E_DEVICE;
       break;
     }
+    if (presplit) {
+      if (hipMemcpy(dcols_g, cols_g.data(), sizeof(void*) * m, hipMemcpyHostToDevice) != hipSuccess ||
+          hipMemcpy(drbs_g, rbs_g.data(), sizeof(int64_t) * m, hipMemcpyHostToDevice) != hipSuccess) {
+        set_error("hapod_gram: descriptor upload failed");
+        st = HAPOD_E_DEVICE;
+        break;
+      }
+      st = launch_split_cols(n, m, (const void* const*)dcols, (const int64_t*)drbs, (float*)dsplit, stream);
+      if (st != HAPOD_OK) break;
+    }
     if (n == 0) {
       if (hipMemset2DAsync(G, ldg * sizeof(double), 0, m * sizeof(double), m, stream) != hipSuccess) {
         set_error("hapod_gram: memset failed");
@@ -1010,6 +1075,9 @@ hapod_status gram_impl(int compute, int eb, int64_t n, int64_t m, const void* S,
   pool.free(drbs);
   pool.free(dpart);
   pool.free(dblob);
+  pool.free(dsplit);
+  pool.free(dcols_g);
+  pool.free(drbs_g);
   return st;
 }
 }  // namespace hapod

@@ -139,6 +139,42 @@ __global__ __launch_bounds__(256) void gram_tile_kernel(const GramNode* __restri
 #pragma unroll
     for (int b = 0; b < NB; ++b) acc[a][b] = Acc{0, 0, 0, 0};
 
+  if constexpr (C == 2) {
+    if (nd.split) {
+      // pre-split columns: hi and lo bf16 runs straight from memory; blocks
+      // are zero-padded past n, so every block is read whole
+      const int64_t blk0 = r0 >> 7, nblk = (r1 - r0 + kRowBlock - 1) >> 7;
+      for (int64_t bi = 0; bi < nblk; ++bi) {
+        gptr<bf8> ha[NB], hb[NB];
+#pragma unroll
+        for (int a = 0; a < NB; ++a) {
+          ha[a] = (gptr<bf8>)as_global(pa[a] + (blk0 + bi) * sa[a]) + g;
+          hb[a] = (gptr<bf8>)as_global(pb[a] + (blk0 + bi) * sb[a]) + g;
+        }
+#pragma unroll
+        for (int bt = 0; bt < NBT; ++bt) {
+          bf8 xh[NB], xl[NB], yh[NB], yl[NB];
+#pragma unroll
+          for (int a = 0; a < NB; ++a) {
+            xh[a] = ha[a][4 * bt];
+            xl[a] = ha[a][4 * bt + 16];
+            yh[a] = hb[a][4 * bt];
+            yl[a] = hb[a][4 * bt + 16];
+          }
+#pragma unroll
+          for (int a = 0; a < NB; ++a)
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+              acc[a][b] = mfma_bf16(xl[a], yh[b], acc[a][b]);
+              acc[a][b] = mfma_bf16(xh[a], yl[b], acc[a][b]);
+              acc[a][b] = mfma_bf16(xh[a], yh[b], acc[a][b]);
+            }
+        }
+      }
+      goto store;
+    }
+  }
+  {
   // full 128-row blocks: constant offsets, no guards
   const int64_t blk0 = r0 >> 7, nfull = (r1 - r0) >> 7;
   for (int64_t bi = 0; bi < nfull; ++bi) {
@@ -175,7 +211,9 @@ __global__ __launch_bounds__(256) void gram_tile_kernel(const GramNode* __restri
     }
     mfma_batch<C, Acc, R>(acc, va, vb);
   }
+  }
 
+store:
   // store: direct into G (single chunk) or into the chunk's partial tile
   if (nd.nchunks == 1) {
 #pragma unroll

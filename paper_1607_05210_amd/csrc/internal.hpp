@@ -61,6 +61,8 @@ struct GramNode {
   int32_t nchunks;
   int32_t ntiles;      // ceil(m / T)
   int32_t pair_base;   // first tile-pair index of this node in the level
+  int32_t split;       // 1: columns hold split-BF16 blocks (see launch_split_cols)
+  int32_t pad;
 };
 
 struct GramItem {
@@ -155,6 +157,12 @@ hapod_status launch_check_diag(const double* G, int64_t ldg, int64_t m, int32_t*
                                hipStream_t stream);
 hapod_status launch_set_scalar_i64(int64_t* p, int64_t v, hipStream_t stream);
 hapod_status launch_fill_i64(int64_t* p, int64_t v, int64_t count, hipStream_t stream);
+// Split-BF16 twin of m float columns (pointer + row-block stride each) into a
+// row-block-tiled buffer of capacity m: block b of column c occupies the 128
+// float slots at dst + (b * m + c) * 128 and holds 128 bf16 hi values followed
+// by 128 bf16 lo values (x = hi + lo + O(2^-17 |x|)); rows past n are zero.
+hapod_status launch_split_cols(int64_t n, int64_t m, const void* const* cols, const int64_t* rbs, float* dst,
+                               hipStream_t stream);
 
 // ---- Cholesky-QR re-orthonormalisation -------------------------------------
 hapod_status launch_chol_inv(double* W, int64_t ldw, int64_t N, double* Rinv, int64_t ldr,

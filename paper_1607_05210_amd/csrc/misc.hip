@@ -2,9 +2,23 @@
 // diagonal check, and the Cholesky factor / triangular inverse used by the
 // Cholesky-QR re-orthonormalisation.
 #include "internal.hpp"
+#include "mfma.hpp"
 
 namespace hapod {
 namespace {
+
+__global__ __launch_bounds__(128) void split_cols_kernel(int64_t n, int64_t m, const void* const* cols,
+                                                         const int64_t* rbs, float* dst) {
+  const int64_t b = blockIdx.x, c = blockIdx.y;
+  const int64_t r = b * kRowBlock + threadIdx.x;
+  const float* src = reinterpret_cast<const float*>(cols[c]);
+  const float x = (r < n) ? src[blk_off(r, rbs[c])] : 0.f;
+  const uint16_t h = bf16_bits_rne(x);
+  const uint16_t l = bf16_bits_rne(x - bf16_bits_to_float(h));
+  uint16_t* blk = reinterpret_cast<uint16_t*>(dst + (b * m + c) * kRowBlock);
+  blk[threadIdx.x] = h;
+  blk[kRowBlock + threadIdx.x] = l;
+}
 
 __global__ void fill_colptrs_kernel(const char* base, int64_t ld_bytes, int64_t m, const void** out) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -138,6 +152,19 @@ hapod_status launch_fill_i64(int64_t* p, int64_t v, int64_t count, hipStream_t s
   if (count <= 0) return HAPOD_OK;
   hipLaunchKernelGGL(fill_i64_kernel, dim3((unsigned)std::min<int64_t>((count + 255) / 256, 1024)), dim3(256), 0,
                      stream, p, v, count);
+  HAPOD_HIP(hipGetLastError());
+  return HAPOD_OK;
+}
+
+hapod_status launch_split_cols(int64_t n, int64_t m, const void* const* cols, const int64_t* rbs, float* dst,
+                               hipStream_t stream) {
+  if (n <= 0 || m <= 0) return HAPOD_OK;
+  if (m > 65535) {
+    set_error("launch_split_cols: too many columns");
+    return HAPOD_E_UNSUPPORTED;
+  }
+  const unsigned nb = (unsigned)((n + kRowBlock - 1) / kRowBlock);
+  hipLaunchKernelGGL(split_cols_kernel, dim3(nb, (unsigned)m), dim3(kRowBlock), 0, stream, n, m, cols, rbs, dst);
   HAPOD_HIP(hipGetLastError());
   return HAPOD_OK;
 }
