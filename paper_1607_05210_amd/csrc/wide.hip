@@ -17,6 +17,8 @@
 // is handed to the truncation, which counts eigenvalues at or below it as
 // zero energy.
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <vector>
 
 #include "mfma.hpp"
@@ -26,6 +28,9 @@ namespace hapod {
 namespace {
 
 constexpr int kMaxSteps = 768;
+constexpr int kMinSteps = 128;      // no stop before this many steps
+constexpr int kCheckEvery = 32;     // stopping test period
+constexpr double kPlateau = 0.7;    // beta_j >= 0.7 beta_{j-32}: plateau
 
 __device__ __forceinline__ double hash_unit(uint64_t x) {
   // splitmix64 finaliser -> uniform in [-0.5, 0.5)
@@ -61,32 +66,60 @@ __global__ __launch_bounds__(256) void matvec_kernel(const double* __restrict__ 
   if (lane == 0) w[c] = s;
 }
 
-// h[c] = Q[:, c] . w for c <= j, one wavefront per column
-__global__ __launch_bounds__(256) void proj_kernel(const double* __restrict__ Q, int64_t m, int j,
-                                                   const double* __restrict__ w, double* __restrict__ h) {
-  const int c = blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  if (c > j) return;
-  const double* col = Q + (int64_t)c * m;
-  double s = 0.0;
-  for (int64_t r = lane; r < m; r += 64) s += col[r] * w[r];
-  s = wave_sum(s);
-  if (lane == 0) h[c] = s;
+constexpr int kProjCols = 16;    // Lanczos vectors per projection workgroup
+constexpr int kProjRows = 1024;  // rows per projection workgroup
+
+// partial[c * nrc + rc] = Q[rows of chunk rc, c] . w[rows of chunk rc], c <= j
+__global__ __launch_bounds__(256) void proj_partial_kernel(const double* __restrict__ Q, int64_t m, int j,
+                                                           const double* __restrict__ w,
+                                                           double* __restrict__ partial, int nrc) {
+  __shared__ double red[kProjCols][4];
+  const int c0 = blockIdx.x * kProjCols, rc = blockIdx.y;
+  const int ncols = min(kProjCols, j + 1 - c0);
+  const int64_t r0 = (int64_t)rc * kProjRows, r1 = min(m, r0 + kProjRows);
+  double acc[kProjCols];
+#pragma unroll
+  for (int c = 0; c < kProjCols; ++c) acc[c] = 0.0;
+  for (int64_t r = r0 + threadIdx.x; r < r1; r += blockDim.x) {
+    const double wr = w[r];
+#pragma unroll
+    for (int c = 0; c < kProjCols; ++c)
+      if (c < ncols) acc[c] += Q[(int64_t)(c0 + c) * m + r] * wr;
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int c = 0; c < kProjCols; ++c) {
+    const double v = wave_sum(acc[c]);
+    if (lane == 0) red[c][wave] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < ncols)
+    partial[(int64_t)(c0 + threadIdx.x) * nrc + rc] =
+        red[threadIdx.x][0] + red[threadIdx.x][1] + red[threadIdx.x][2] + red[threadIdx.x][3];
 }
 
-// w -= Q[:, 0..j] h ; accumulate alpha_j += h[j]
+// h[c] = sum over row chunks of partial[c] (fixed order); w -= Q[:, 0..j] h;
+// alpha_j += h[j].  64 rows per workgroup, columns split over 4 wavefronts.
 __global__ __launch_bounds__(256) void update_kernel(const double* __restrict__ Q, int64_t m, int j,
-                                                     double* __restrict__ w, const double* __restrict__ h,
-                                                     double* __restrict__ alpha) {
+                                                     double* __restrict__ w, const double* __restrict__ partial,
+                                                     int nrc, double* __restrict__ alpha) {
   __shared__ double hs[kMaxSteps + 1];
-  for (int c = threadIdx.x; c <= j; c += blockDim.x) hs[c] = h[c];
+  __shared__ double part[4][64];
+  for (int c = threadIdx.x; c <= j; c += blockDim.x) {
+    double t = 0.0;
+    for (int rc = 0; rc < nrc; ++rc) t += partial[(int64_t)c * nrc + rc];
+    hs[c] = t;
+  }
   __syncthreads();
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (blockIdx.x == 0 && threadIdx.x == 0) alpha[j] += hs[j];
-  if (i >= m) return;
-  double s = 0.0;
-  for (int c = 0; c <= j; ++c) s += Q[(int64_t)c * m + i] * hs[c];
-  w[i] -= s;
+  const int rl = threadIdx.x & 63, cg = threadIdx.x >> 6;
+  const int64_t i = (int64_t)blockIdx.x * 64 + rl;
+  double t = 0.0;
+  if (i < m)
+    for (int c = cg; c <= j; c += 4) t += Q[(int64_t)c * m + i] * hs[c];
+  part[cg][rl] = t;
+  __syncthreads();
+  if (cg == 0 && i < m) w[i] -= part[0][rl] + part[1][rl] + part[2][rl] + part[3][rl];
 }
 
 // beta = ||w||, q_next = w / beta (single workgroup)
@@ -104,6 +137,11 @@ __global__ __launch_bounds__(1024) void finish_kernel(const double* __restrict__
   const double inv = beta > 0.0 ? 1.0 / beta : 0.0;
   for (int64_t i = threadIdx.x; i < m; i += blockDim.x) q_next[i] = w[i] * inv;
   if (threadIdx.x == 0 && beta_out) *beta_out = beta;
+}
+
+__global__ void zero_kernel(double* p, int64_t count) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0.0;
 }
 
 __global__ void trace_kernel(const double* G, int64_t ldg, int64_t m, double* out) {
@@ -134,14 +172,16 @@ __device__ int sturm_count(const double* d, const double* e2, int k, double mu, 
   return cnt;
 }
 
-// theta[i] = i-th largest eigenvalue of T, by bisection
-__global__ void bisect_kernel(const double* __restrict__ d, const double* __restrict__ e, int k,
-                              double* __restrict__ e2all, double* __restrict__ theta) {
-  // e^2 in this block's own region, and the Gershgorin interval (cheap)
+// theta[i] = i-th largest eigenvalue of T, by multisection: one wavefront
+// per eigenvalue, 64 Sturm counts per step shrink the bracket 65-fold.
+__global__ __launch_bounds__(256) void bisect_kernel(const double* __restrict__ d, const double* __restrict__ e,
+                                                     int k, double* __restrict__ e2all,
+                                                     double* __restrict__ theta) {
   double* e2buf = e2all + (int64_t)blockIdx.x * k;
   for (int j = threadIdx.x; j < k - 1; j += blockDim.x) e2buf[j] = e[j] * e[j];
   __syncthreads();
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
   if (i >= k) return;
   double lo = 1e300, hi = -1e300, emax2 = 0.0;
   for (int j = 0; j < k; ++j) {
@@ -156,14 +196,21 @@ __global__ void bisect_kernel(const double* __restrict__ d, const double* __rest
   lo -= slack;
   hi += slack;
   const int target = k - 1 - i;  // ascending index
-  for (int it = 0; it < 200; ++it) {
-    const double mid = 0.5 * (lo + hi);
-    if (mid <= lo || mid >= hi) break;
+  for (int it = 0; it < 20; ++it) {
     if (hi - lo <= 2.0 * 2.220446049250313e-16 * fmax(fabs(lo), fabs(hi)) + pivmin) break;
-    if (sturm_count(d, e2buf, k, mid, pivmin) > target) hi = mid;
-    else lo = mid;
+    // lane l tests x_l = lo + (l + 1) (hi - lo) / 65
+    const double x = lo + (hi - lo) * (double)(lane + 1) / 65.0;
+    const bool above = sturm_count(d, e2buf, k, x, pivmin) > target;
+    const uint64_t mask = __ballot(above);
+    // first lane whose point lies above the eigenvalue bounds it from above
+    const int first = mask ? __ffsll((unsigned long long)mask) - 1 : 64;
+    const double nlo = (first == 0) ? lo : lo + (hi - lo) * (double)first / 65.0;
+    const double nhi = (first == 64) ? hi : lo + (hi - lo) * (double)(first + 1) / 65.0;
+    if (!(nlo >= lo && nhi <= hi) || (nlo == lo && nhi == hi)) break;
+    lo = nlo;
+    hi = nhi;
   }
-  theta[i] = 0.5 * (lo + hi);
+  if (lane == 0) theta[i] = 0.5 * (lo + hi);
 }
 
 // inverse iteration: z_i solves (T - theta_i) z = z_prev (pivoted LU), three
@@ -175,70 +222,84 @@ __global__ void inviter_kernel(const double* __restrict__ d, const double* __res
                                double* __restrict__ last) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nvec) return;
-  double* dl = scratch + (int64_t)i * 5 * k;
-  double* dd = dl + k;
-  double* du = dd + k;
-  double* du2 = du + k;
-  double* b = du2 + k;
-  int* piv = iscratch + (int64_t)i * k;
+  // interleaved scratch: entry j of this thread's array X at X[j * nvec]
+  const int64_t st = nvec;
+  double* dl = scratch + i;
+  double* dd = dl + st * k;
+  double* du = dd + st * k;
+  double* du2 = du + st * k;
+  double* b = du2 + st * k;
+  int* piv = iscratch + i;
+#define DL(x) dl[(int64_t)(x) * st]
+#define DD(x) dd[(int64_t)(x) * st]
+#define DU(x) du[(int64_t)(x) * st]
+#define DU2(x) du2[(int64_t)(x) * st]
+#define BB(x) b[(int64_t)(x) * st]
+#define PIV(x) piv[(int64_t)(x) * st]
   double tnorm = 0.0;
   for (int j = 0; j < k; ++j) tnorm = fmax(tnorm, fabs(d[j]) + (j < k - 1 ? fabs(e[j]) : 0.0) + (j > 0 ? fabs(e[j - 1]) : 0.0));
   const double tiny = fmax(2.220446049250313e-16 * tnorm, 1e-300);
   const double mu = theta[i];
   // LU with partial pivoting of T - mu I (LAPACK gttrf layout)
   for (int j = 0; j < k; ++j) {
-    dd[j] = d[j] - mu;
-    if (j < k - 1) { dl[j] = e[j]; du[j] = e[j]; }
-    du2[j] = 0.0;
+    DD(j) = d[j] - mu;
+    if (j < k - 1) { DL(j) = e[j]; DU(j) = e[j]; }
+    DU2(j) = 0.0;
   }
   for (int j = 0; j < k - 1; ++j) {
-    if (fabs(dd[j]) >= fabs(dl[j])) {
-      piv[j] = j;
-      if (dd[j] == 0.0) dd[j] = tiny;
-      const double f = dl[j] / dd[j];
-      dl[j] = f;
-      dd[j + 1] -= f * du[j];
+    if (fabs(DD(j)) >= fabs(DL(j))) {
+      PIV(j) = j;
+      if (DD(j) == 0.0) DD(j) = tiny;
+      const double f = DL(j) / DD(j);
+      DL(j) = f;
+      DD(j + 1) -= f * DU(j);
     } else {
-      piv[j] = j + 1;
-      const double f = dd[j] / dl[j];
-      dd[j] = dl[j];
-      dl[j] = f;
-      const double tmp = du[j];
-      du[j] = dd[j + 1];
-      dd[j + 1] = tmp - f * dd[j + 1];
+      PIV(j) = j + 1;
+      const double f = DD(j) / DL(j);
+      DD(j) = DL(j);
+      DL(j) = f;
+      const double tmp = DU(j);
+      DU(j) = DD(j + 1);
+      DD(j + 1) = tmp - f * DD(j + 1);
       if (j < k - 2) {
-        du2[j] = du[j + 1];
-        du[j + 1] = -f * du[j + 1];
+        DU2(j) = DU(j + 1);
+        DU(j + 1) = -f * DU(j + 1);
       }
     }
   }
-  if (dd[k - 1] == 0.0) dd[k - 1] = tiny;
+  if (DD(k - 1) == 0.0) DD(k - 1) = tiny;
   for (int j = 0; j < k; ++j)
-    if (fabs(dd[j]) < tiny) dd[j] = (dd[j] < 0.0 ? -tiny : tiny);
-  for (int j = 0; j < k; ++j) b[j] = hash_unit((uint64_t)i * 1000003u + j) + 1.0;
+    if (fabs(DD(j)) < tiny) DD(j) = (DD(j) < 0.0 ? -tiny : tiny);
+  for (int j = 0; j < k; ++j) BB(j) = hash_unit((uint64_t)i * 1000003u + j) + 1.0;
   for (int it = 0; it < 3; ++it) {
     // forward with L
     for (int j = 0; j < k - 1; ++j) {
-      if (piv[j] == j) {
-        b[j + 1] -= dl[j] * b[j];
+      if (PIV(j) == j) {
+        BB(j + 1) -= DL(j) * BB(j);
       } else {
-        const double t = b[j];
-        b[j] = b[j + 1];
-        b[j + 1] = t - dl[j] * b[j];
+        const double t = BB(j);
+        BB(j) = BB(j + 1);
+        BB(j + 1) = t - DL(j) * BB(j);
       }
     }
-    // back substitution with U (diag dd, super du, super-super du2)
-    b[k - 1] /= dd[k - 1];
-    if (k > 1) b[k - 2] = (b[k - 2] - du[k - 2] * b[k - 1]) / dd[k - 2];
-    for (int j = k - 3; j >= 0; --j) b[j] = (b[j] - du[j] * b[j + 1] - du2[j] * b[j + 2]) / dd[j];
+    // back substitution with U (diag DD, super DU, super-super DU2)
+    BB(k - 1) /= DD(k - 1);
+    if (k > 1) BB(k - 2) = (BB(k - 2) - DU(k - 2) * BB(k - 1)) / DD(k - 2);
+    for (int j = k - 3; j >= 0; --j) BB(j) = (BB(j) - DU(j) * BB(j + 1) - DU2(j) * BB(j + 2)) / DD(j);
     double nrm = 0.0;
-    for (int j = 0; j < k; ++j) nrm += b[j] * b[j];
+    for (int j = 0; j < k; ++j) nrm += BB(j) * BB(j);
     nrm = sqrt(nrm);
     const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
-    for (int j = 0; j < k; ++j) b[j] *= inv;
+    for (int j = 0; j < k; ++j) BB(j) *= inv;
   }
-  for (int j = 0; j < k; ++j) Z[(int64_t)j * ldz + i] = b[j];
-  last[i] = b[k - 1];
+  for (int j = 0; j < k; ++j) Z[(int64_t)j * ldz + i] = BB(j);
+  last[i] = BB(k - 1);
+#undef DL
+#undef DD
+#undef DU
+#undef DU2
+#undef BB
+#undef PIV
 }
 
 // make the largest-magnitude entry of every column positive (one wave per column)
@@ -292,11 +353,12 @@ hapod_status wide_eigh(const double* G, int64_t ldg, int64_t m, double* lambda, 
   } rel{owned, release, ctx};
   double* Q = (double*)get(sizeof(double) * m * (k + 1));
   double* w = (double*)get(sizeof(double) * m);
-  double* h = (double*)get(sizeof(double) * (k + 1));
+  const int nrc = (int)((m + kProjRows - 1) / kProjRows);
+  double* h = (double*)get(sizeof(double) * (size_t)(k + 1) * nrc);
   double* alpha = (double*)get(sizeof(double) * k);
   double* beta = (double*)get(sizeof(double) * (k + 1));
   double* theta = (double*)get(sizeof(double) * k);
-  double* e2 = (double*)get(sizeof(double) * (size_t)k * ((k + 255) / 256));
+  double* e2 = (double*)get(sizeof(double) * (size_t)k * ((k + 3) / 4));
   double* Z = (double*)get(sizeof(double) * (size_t)k * k);
   double* last = (double*)get(sizeof(double) * k);
   double* isc = (double*)get(sizeof(double) * (size_t)5 * k * k);
@@ -311,50 +373,82 @@ hapod_status wide_eigh(const double* G, int64_t ldg, int64_t m, double* lambda, 
     set_error("wide_eigh: scratch allocation failed");
     return HAPOD_E_NOMEM;
   }
-  HAPOD_HIP(hipMemsetAsync(alpha, 0, sizeof(double) * k, stream));
+  hipLaunchKernelGGL(zero_kernel, dim3(4), dim3(256), 0, stream, alpha, (int64_t)k);
   hipLaunchKernelGGL(trace_kernel, dim3(1), dim3(1024), 0, stream, G, ldg, m, tr);
   // q_0
   hipLaunchKernelGGL(lanczos_init_kernel, dim3(64), dim3(256), 0, stream, w, m);
   hipLaunchKernelGGL(finish_kernel, dim3(1), dim3(1024), 0, stream, w, m, Q, (double*)nullptr);
   const unsigned mv_blocks = (unsigned)((m + 3) / 4);
-  const unsigned up_blocks = (unsigned)((m + 255) / 256);
+  const unsigned up_blocks = (unsigned)((m + 63) / 64);
+  // the rounding level of G's spectrum, for the stopping test
+  double trace = 0.0;
+  HAPOD_HIP(hipMemcpyAsync(&trace, tr, sizeof(double), hipMemcpyDeviceToHost, stream));
+  HAPOD_HIP(hipStreamSynchronize(stream));
+  const double floor_trace = 0.1 * u_p * std::fabs(trace);
+  int steps = k;
+  double prev_check = 0.0;
+  const char* venv = std::getenv("HAPOD_VERBOSE");
+  const bool verbose = venv && venv[0] == '1';
   for (int j = 0; j < k; ++j) {
     const double* qj = Q + (int64_t)j * m;
     hipLaunchKernelGGL(matvec_kernel, dim3(mv_blocks), dim3(256), 0, stream, G, ldg, m, qj, w);
     for (int pass = 0; pass < 2; ++pass) {
-      hipLaunchKernelGGL(proj_kernel, dim3((unsigned)((j + 4) / 4)), dim3(256), 0, stream, Q, m, j, w, h);
-      hipLaunchKernelGGL(update_kernel, dim3(up_blocks), dim3(256), 0, stream, Q, m, j, w, h, alpha);
+      hipLaunchKernelGGL(proj_partial_kernel, dim3((unsigned)((j + kProjCols) / kProjCols), (unsigned)nrc),
+                         dim3(256), 0, stream, Q, m, j, w, h, nrc);
+      hipLaunchKernelGGL(update_kernel, dim3(up_blocks), dim3(256), 0, stream, Q, m, j, w, h, nrc, alpha);
     }
     hipLaunchKernelGGL(finish_kernel, dim3(1), dim3(1024), 0, stream, w, m, Q + (int64_t)(j + 1) * m, beta + j);
+    // Stop once the Krylov space has taken in everything above the rounding
+    // level of G: the residual norms beta_j then stop falling (they sit at
+    // that level).  Test every kCheckEvery steps: beta_j at or below
+    // u_p trace(G) / 10, or beta_j fell less than kPlateau-fold over the last
+    // period after having fallen 1000-fold from beta_0.
+    if ((j + 1) % kCheckEvery == 0 && j + 1 < k) {
+      double bj = 0.0, b0 = 0.0;
+      HAPOD_HIP(hipMemcpyAsync(&bj, beta + j, sizeof(double), hipMemcpyDeviceToHost, stream));
+      HAPOD_HIP(hipMemcpyAsync(&b0, beta, sizeof(double), hipMemcpyDeviceToHost, stream));
+      HAPOD_HIP(hipStreamSynchronize(stream));
+      if (verbose)
+        std::fprintf(stderr, "[hapod wide] m=%lld step %d beta %.3e floor_trace %.3e\n", (long long)m, j + 1, bj,
+                     floor_trace);
+      const bool plateau = prev_check > 0.0 && bj >= kPlateau * prev_check && bj <= 1e-3 * b0;
+      prev_check = bj;
+      if (j + 1 >= kMinSteps && (bj <= floor_trace || plateau)) {
+        steps = j + 1;
+        break;
+      }
+    }
   }
   HAPOD_HIP(hipGetLastError());
-  // ---- tridiagonal eigenproblem -------------------------------------------------
-  const unsigned bblocks = (unsigned)((k + 255) / 256);
-  hipLaunchKernelGGL(bisect_kernel, dim3(bblocks), dim3(256), 0, stream, alpha, beta, k, e2, theta);
+  // ---- tridiagonal eigenproblem of the steps taken ---------------------------------
+  const int kk = steps;
+  hipLaunchKernelGGL(bisect_kernel, dim3((unsigned)((kk + 3) / 4)), dim3(256), 0, stream, alpha, beta, kk, e2, theta);
   HAPOD_HIP(hipGetLastError());
-  hipLaunchKernelGGL(inviter_kernel, dim3(bblocks), dim3(256), 0, stream, alpha, beta, k, theta, k, isc, ipiv, Z,
-                     (int64_t)k, last);
+  const unsigned bblocks = (unsigned)((kk + 255) / 256);
+  hipLaunchKernelGGL(inviter_kernel, dim3(bblocks), dim3(256), 0, stream, alpha, beta, kk, theta, kk, isc, ipiv, Z,
+                     (int64_t)kk, last);
   HAPOD_HIP(hipGetLastError());
   // ---- choose the converged leading block (host) ----------------------------------
-  std::vector<double> th(k), lz(k), bet(k);
-  double trace = 0.0;
-  HAPOD_HIP(hipMemcpyAsync(th.data(), theta, sizeof(double) * k, hipMemcpyDeviceToHost, stream));
-  HAPOD_HIP(hipMemcpyAsync(lz.data(), last, sizeof(double) * k, hipMemcpyDeviceToHost, stream));
-  HAPOD_HIP(hipMemcpyAsync(bet.data(), beta, sizeof(double) * k, hipMemcpyDeviceToHost, stream));
-  HAPOD_HIP(hipMemcpyAsync(&trace, tr, sizeof(double), hipMemcpyDeviceToHost, stream));
+  std::vector<double> th(kk), lz(kk), bet(kk);
+  HAPOD_HIP(hipMemcpyAsync(th.data(), theta, sizeof(double) * kk, hipMemcpyDeviceToHost, stream));
+  HAPOD_HIP(hipMemcpyAsync(lz.data(), last, sizeof(double) * kk, hipMemcpyDeviceToHost, stream));
+  HAPOD_HIP(hipMemcpyAsync(bet.data(), beta, sizeof(double) * kk, hipMemcpyDeviceToHost, stream));
   HAPOD_HIP(hipStreamSynchronize(stream));
-  const double bk = bet[k - 1];
+  const double bk = bet[kk - 1];
   const double theta_min = *std::min_element(th.begin(), th.end());
-  const double floor_abs = std::max(std::max(-theta_min, 0.0), 0.1 * u_p * std::fabs(trace));
+  const double floor_abs = std::max(std::max(-theta_min, 0.0), floor_trace);
   // a Ritz pair counts as converged when its residual is below 1e-8 of its
   // own value or below the Gram's rounding level
   int b = 0;
-  while (b < k && std::fabs(bk * lz[b]) <= std::max(1e-8 * std::fabs(th[b]), floor_abs)) ++b;
-  if (k == m) b = k;  // complete tridiagonalisation: every pair is exact
+  while (b < kk && std::fabs(bk * lz[b]) <= std::max(1e-8 * std::fabs(th[b]), floor_abs)) ++b;
+  if (kk == m) b = kk;  // complete tridiagonalisation: every pair is exact
+  if (verbose)
+    std::fprintf(stderr, "[hapod wide] m=%lld steps %d block %d theta_1 %.6e theta_min %.3e floor %.3e\n",
+                 (long long)m, kk, b, th[0], theta_min, floor_abs);
   // ---- Ritz vectors V[:, :b] = Q_k Z[:, :b] (FP64 lift GEMM) ------------------------
   if (b > 0) {
-    HAPOD_TRY(launch_fill_colptrs(Q, m, k, 8, qcols, stream));
-    HAPOD_TRY(launch_fill_i64(qrbs, kRowBlock, k, stream));
+    HAPOD_TRY(launch_fill_colptrs(Q, m, kk, 8, qcols, stream));
+    HAPOD_TRY(launch_fill_i64(qrbs, kRowBlock, kk, stream));
     HAPOD_TRY(launch_set_scalar_i64(drank, b, stream));
     LiftNode l{};
     l.cols = (const void* const*)qcols;
@@ -363,10 +457,10 @@ hapod_status wide_eigh(const double* G, int64_t ldg, int64_t m, double* lambda, 
     l.rank = drank;
     l.out = V;
     l.n = m;
-    l.ldb = k;
+    l.ldb = kk;
     l.ocs = ldv;
     l.obs = kRowBlock;
-    l.m = k;
+    l.m = kk;
     l.row_tiles = (int32_t)((m + kLiftTileM - 1) / kLiftTileM);
     l.col_tiles = (int32_t)((b + kLiftTileN - 1) / kLiftTileN);
     l.item_base = 0;
@@ -378,7 +472,7 @@ hapod_status wide_eigh(const double* G, int64_t ldg, int64_t m, double* lambda, 
   HAPOD_HIP(hipGetLastError());
   HAPOD_HIP(hipStreamSynchronize(stream));
   if (res) {
-    res->iterations = k;
+    res->iterations = kk;
     res->block = b;
     res->floor_abs = floor_abs;
   }
