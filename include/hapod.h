@@ -150,12 +150,17 @@ typedef struct hapod_plan_s* hapod_plan_t;
  *   leaf_cols[i] |D^-1(i)|, the number of snapshots at leaf i (ignored for
  *                inner nodes).
  *   n            dimension of the snapshot space V (rows).
+ *   leaf_rows    NULL (every leaf holds n rows) or, per node, the number of
+ *                leading rows a leaf's snapshots hold (1..n); the remaining
+ *                rows are zero and never read.  An inner node's vectors hold
+ *                the maximum over its children.
  * Arrays are host memory, read during hapod_plan only.                     */
 typedef struct {
   int32_t num_nodes;
   const int32_t* parent;
   const int64_t* leaf_cols;
   int64_t n;
+  const int64_t* leaf_rows;
 } hapod_tree;
 
 typedef struct {
@@ -164,8 +169,11 @@ typedef struct {
   int64_t mem_cap_bytes;           /* 0: no cap; else device bytes the plan may hold       */
   const double* node_eps_override; /* host, num_nodes values or NULL; an entry >= 0
                                       replaces the Thm. 3.5 tolerance of that node         */
-  int32_t jacobi_max;              /* 0: default; nodes with m above it take the
-                                      subspace-iteration eigensolver                       */
+  int32_t jacobi_max;              /* 0: default (256); nodes with more input columns take
+                                      the Lanczos eigensolver                              */
+  int32_t leaf_wave;               /* 0: all leaves of a level in one launch group; k > 0:
+                                      at most k leaves per group, so the provider needs at
+                                      most k leaves resident at a time                     */
 } hapod_options;
 
 /* Validate the tree (Def. 3.1), compute levels (height: leaves are level 1),
@@ -182,11 +190,16 @@ hapod_status hapod_plan(const hapod_tree* tree, double eps_star, double omega,
 hapod_status hapod_plan_query(hapod_plan_t plan, double* eps, int32_t* level,
                               int64_t* acc);
 
-/* Leaf provider: returns in *ptr a device pointer to the leaf's n x
- * leaf_cols[leaf] snapshot matrix (storage type of the plan's precision)
- * and its leading dimension in *ld.  Called once per leaf, in level order,
- * before that leaf's level is launched on `stream`.  Non-zero return aborts
- * the run with HAPOD_E_CALLBACK.                                            */
+/* Leaf provider: returns in *ptr a device pointer to the leaf's
+ * leaf_rows[leaf] x leaf_cols[leaf] snapshot matrix (column-major, storage
+ * type of the plan's precision) and its leading dimension in *ld.  Called
+ * once per leaf per run, just before the launch group that first reads it:
+ * the leaf's own group, or for a pass-through leaf (eps = 0) its parent's.
+ * The data must stay valid until that group has completed; hapod_run
+ * synchronises the stream at the end of every group, before the provider
+ * is called again, so a provider may stream leaves through a few reused
+ * buffers (with leaf_wave bounding how many one group needs).  Non-zero
+ * return aborts the run with HAPOD_E_CALLBACK.                              */
 typedef int32_t (*hapod_leaf_fn)(void* user, int32_t leaf, const void** ptr,
                                  int64_t* ld, void* stream);
 

@@ -35,12 +35,13 @@ _pi64, _pdbl, _pi32 = C.POINTER(C.c_int64), C.POINTER(C.c_double), C.POINTER(C.c
 
 
 class HapodTree(C.Structure):
-    _fields_ = [("num_nodes", _i32), ("parent", _pi32), ("leaf_cols", _pi64), ("n", _i64)]
+    _fields_ = [("num_nodes", _i32), ("parent", _pi32), ("leaf_cols", _pi64), ("n", _i64),
+                ("leaf_rows", _pi64)]
 
 
 class HapodOptions(C.Structure):
     _fields_ = [("prec", _i32), ("reorth", _i32), ("mem_cap_bytes", _i64),
-                ("node_eps_override", _pdbl), ("jacobi_max", _i32)]
+                ("node_eps_override", _pdbl), ("jacobi_max", _i32), ("leaf_wave", _i32)]
 
 
 LEAF_FN = C.CFUNCTYPE(_i32, _vp, _i32, C.POINTER(_vp), _pi64, _vp)
@@ -205,19 +206,23 @@ class Plan:
     _destroy = _lib.hapod_destroy
 
     def __init__(self, parent, leaf_cols, n, eps_star, omega, prec="fp64", reorth=False,
-                 mem_cap_bytes=0, eps_override=None, jacobi_max=0):
+                 mem_cap_bytes=0, eps_override=None, jacobi_max=0, leaf_rows=None, leaf_wave=0):
         import numpy as np
         self.num_nodes = len(parent)
         self.n = int(n)
         self.prec = _prec(prec)
         self._parent = (C.c_int32 * self.num_nodes)(*[int(p) for p in parent])
         self._cols = (C.c_int64 * self.num_nodes)(*[int(c) for c in leaf_cols])
-        tree = HapodTree(self.num_nodes, self._parent, self._cols, self.n)
+        self._rows = None
+        if leaf_rows is not None:
+            self._rows = (C.c_int64 * self.num_nodes)(*[int(r) for r in leaf_rows])
+        tree = HapodTree(self.num_nodes, self._parent, self._cols, self.n, self._rows)
         ov = None
         if eps_override is not None:
             arr = np.asarray(eps_override, dtype=np.float64)
             ov = arr.ctypes.data_as(_pdbl)
-        opts = HapodOptions(self.prec, int(bool(reorth)), int(mem_cap_bytes), ov, int(jacobi_max))
+        opts = HapodOptions(self.prec, int(bool(reorth)), int(mem_cap_bytes), ov, int(jacobi_max),
+                            int(leaf_wave))
         h = C.c_void_p()
         _check(_lib.hapod_plan(C.byref(tree), float(eps_star), float(omega), C.byref(opts), C.byref(h)),
                "hapod_plan")

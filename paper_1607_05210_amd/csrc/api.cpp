@@ -142,6 +142,7 @@ struct PodJob {
   // inputs
   std::vector<const void*> cols;  // host copy of the column pointers
   std::vector<int64_t> rbs;       // row-block stride of every column
+  std::vector<int64_t> crows;     // rows every column holds (<= n)
   int64_t n = 0;
   int64_t m = 0;
   double eps = 0.0;
@@ -191,7 +192,7 @@ hapod_status run_pod_batch(hapod_precision prec, std::vector<PodJob>& jobs, int 
 
   // ---- sizes & scratch layout ---------------------------------------------
   struct Lay {
-    size_t cols, rbs, cols2, rbs2, G, partial, lam, V, B, sigma, rank, info, jwork, vwork, sweeps;
+    size_t cols, rbs, crows, cols2, rbs2, crows2, G, partial, lam, V, B, sigma, rank, info, jwork, vwork, sweeps;
     bool presplit;
     int ntiles, pairs, nchunks;
     int64_t chunk_rows;
@@ -228,11 +229,13 @@ hapod_status run_pod_batch(hapod_precision prec, std::vector<PodJob>& jobs, int 
     };
     L.cols = take(sizeof(void*) * std::max<int64_t>(m, 1));
     L.rbs = take(sizeof(int64_t) * std::max<int64_t>(m, 1));
+    L.crows = take(sizeof(int64_t) * std::max<int64_t>(m, 1));
     // split-BF16: nodes with several column tiles get a split twin of their
     // input once, instead of splitting every element in each tile that reads it
     L.presplit = (compute == 2 && m >= kPresplitMinCols && j.n > 0);
     L.cols2 = L.presplit ? take(sizeof(void*) * m) : 0;
     L.rbs2 = L.presplit ? take(sizeof(int64_t) * m) : 0;
+    L.crows2 = L.presplit ? take(sizeof(int64_t) * m) : 0;
     L.G = take(sizeof(double) * m * m);
     L.partial = (L.nchunks > 1) ? take(sizeof(double) * (size_t)L.pairs * L.nchunks * kGramTile * kGramTile) : 0;
     L.lam = take(sizeof(double) * std::max<int64_t>(m, 1));
@@ -265,13 +268,14 @@ hapod_status run_pod_batch(hapod_precision prec, std::vector<PodJob>& jobs, int 
     }
   } guardv{pool, split_buf};
   std::vector<std::vector<const void*>> cols2(nj);
-  std::vector<std::vector<int64_t>> rbs2(nj);
+  std::vector<std::vector<int64_t>> rbs2(nj), crows2(nj);
   for (int i = 0; i < nj; ++i) {
     if (!lay[i].presplit) continue;
     const int64_t m = jobs[i].m;
     HAPOD_TRY(pool.alloc(tiled_bytes(jobs[i].n, m, 4), &split_buf[i]));
     cols2[i] = tiled_table(split_buf[i], m, 4);
     rbs2[i].assign((size_t)m, tiled_rbs(m));
+    crows2[i].assign((size_t)m, jobs[i].n);
   }
 
   // ---- descriptor tables ----------------------------------------------------
@@ -292,6 +296,7 @@ hapod_status run_pod_batch(hapod_precision prec, std::vector<PodJob>& jobs, int 
     GramNode& g = gnodes[i];
     g.cols = (const void* const*)(scratch + (L.presplit ? L.cols2 : L.cols));
     g.rbs = (const int64_t*)(scratch + (L.presplit ? L.rbs2 : L.rbs));
+    g.crows = (const int64_t*)(scratch + (L.presplit ? L.crows2 : L.crows));
     g.split = L.presplit ? 1 : 0;
     g.n = j.n;
     g.chunk_rows = L.chunk_rows;
@@ -348,12 +353,14 @@ hapod_status run_pod_batch(hapod_precision prec, std::vector<PodJob>& jobs, int 
   }
 
   Blob blob;
-  std::vector<size_t> col_off(nj), rbs_off(nj), col2_off(nj), rbs2_off(nj);
+  std::vector<size_t> col_off(nj), rbs_off(nj), rows_off(nj), col2_off(nj), rbs2_off(nj), rows2_off(nj);
   for (int i = 0; i < nj; ++i) {
     col_off[i] = blob.add_vec(jobs[i].cols);
     rbs_off[i] = blob.add_vec(jobs[i].rbs);
+    rows_off[i] = blob.add_vec(jobs[i].crows);
     col2_off[i] = blob.add_vec(cols2[i]);
     rbs2_off[i] = blob.add_vec(rbs2[i]);
+    rows2_off[i] = blob.add_vec(crows2[i]);
   }
   const size_t o_g = blob.add_vec(gnodes), o_gi = blob.add_vec(gitems), o_rp = blob.add_vec(rpairs),
                o_rn = blob.add_vec(rnode), o_es = blob.add_vec(enodes_small), o_eb = blob.add_vec(enodes_big),
@@ -372,7 +379,11 @@ hapod_status run_pod_batch(hapod_precision prec, std::vector<PodJob>& jobs, int 
                                hipMemcpyDeviceToDevice, stream));
       HAPOD_HIP(hipMemcpyAsync(scratch + lay[i].rbs, dblob + rbs_off[i], sizeof(int64_t) * jobs[i].m,
                                hipMemcpyDeviceToDevice, stream));
+      HAPOD_HIP(hipMemcpyAsync(scratch + lay[i].crows, dblob + rows_off[i], sizeof(int64_t) * jobs[i].m,
+                               hipMemcpyDeviceToDevice, stream));
       if (lay[i].presplit) {
+        HAPOD_HIP(hipMemcpyAsync(scratch + lay[i].crows2, dblob + rows2_off[i], sizeof(int64_t) * jobs[i].m,
+                                 hipMemcpyDeviceToDevice, stream));
         HAPOD_HIP(hipMemcpyAsync(scratch + lay[i].cols2, dblob + col2_off[i], sizeof(void*) * jobs[i].m,
                                  hipMemcpyDeviceToDevice, stream));
         HAPOD_HIP(hipMemcpyAsync(scratch + lay[i].rbs2, dblob + rbs2_off[i], sizeof(int64_t) * jobs[i].m,
@@ -388,7 +399,8 @@ hapod_status run_pod_batch(hapod_precision prec, std::vector<PodJob>& jobs, int 
   for (int i = 0; i < nj; ++i)
     if (lay[i].presplit)
       HAPOD_TRY(launch_split_cols(jobs[i].n, jobs[i].m, (const void* const*)(scratch + lay[i].cols),
-                                  (const int64_t*)(scratch + lay[i].rbs), (float*)split_buf[i], stream));
+                                  (const int64_t*)(scratch + lay[i].rbs), (const int64_t*)(scratch + lay[i].crows),
+                                  (float*)split_buf[i], stream));
   HAPOD_TRY(launch_gram(compute, (const GramNode*)(dblob + o_g), (const GramItem*)(dblob + o_gi), (int)gitems.size(),
                         (const int32_t*)(dblob + o_rp), (const int32_t*)(dblob + o_rn), (int)rpairs.size(), vec_ok,
                         stream));
@@ -432,6 +444,7 @@ hapod_status run_pod_batch(hapod_precision prec, std::vector<PodJob>& jobs, int 
     LiftNode l{};
     l.cols = (const void* const*)(scratch + lay[i].cols);
     l.rbs = (const int64_t*)(scratch + lay[i].rbs);
+    l.crows = (const int64_t*)(scratch + lay[i].crows);
     l.B = tnodes[i].B;
     l.rank = tnodes[i].rank;
     l.out = j.out;
@@ -540,7 +553,8 @@ struct hapod_plan_s {
   void* root_U = nullptr;  // owned by the pool
   bool root_passthrough = false;
   std::vector<const void*> root_cols;  // pass-through root: its input columns
-  std::vector<int64_t> root_rbs;
+  std::vector<int64_t> root_rbs, root_rows;
+  std::vector<int64_t> rows;           // rows each node's vectors hold
   double timing[6] = {0, 0, 0, 0, 0, 0};
   std::vector<std::array<double, 4>> level_ms;  // {gram, eig, trunc, lift} per level
   Pool pool;
@@ -621,17 +635,26 @@ hapod_status hapod_plan(const hapod_tree* tree, double eps_star, double omega, c
       for (auto it = P->children[a].rbegin(); it != P->children[a].rend(); ++it) st.push_back({*it, false});
     }
   }
+  if (tree->leaf_rows)
+    for (int32_t i = 0; i < nn; ++i)
+      if (P->children[i].empty() && (tree->leaf_rows[i] < 1 || tree->leaf_rows[i] > tree->n)) {
+        set_error("hapod_plan: leaf_rows outside 1..n");
+        return HAPOD_E_INVALID;
+      }
   P->level.assign(nn, 0);
   P->acc.assign(nn, 0);
+  P->rows.assign(nn, 0);
   for (int32_t a : order) {
     int32_t lv = 0;
-    int64_t cnt = 0;
+    int64_t cnt = 0, rw = 0;
     for (int32_t b : P->children[a]) {
       lv = std::max(lv, P->level[b]);
       cnt += P->acc[b];
+      rw = std::max(rw, P->rows[b]);
     }
     P->level[a] = lv + 1;
     P->acc[a] = P->children[a].empty() ? P->leaf_cols[a] : cnt;
+    P->rows[a] = P->children[a].empty() ? (tree->leaf_rows ? tree->leaf_rows[a] : tree->n) : rw;
   }
   const int32_t LT = P->level[P->root];
   P->by_level.assign(LT, {});
@@ -699,6 +722,7 @@ hapod_status hapod_run(hapod_plan_t P, hapod_leaf_fn get_leaf, void* user, void*
   const int eb = elem_bytes(prec);
   const int32_t nn = P->num_nodes;
   const int jmax = P->opts.jacobi_max > 0 ? std::min<int>(P->opts.jacobi_max, kJacobiMax) : 256;
+  const int wave = P->opts.leaf_wave > 0 ? P->opts.leaf_wave : INT32_MAX;
   P->has_result = false;
   if (P->root_U) {
     P->pool.free(P->root_U);
@@ -713,11 +737,13 @@ hapod_status hapod_run(hapod_plan_t P, hapod_leaf_fn get_leaf, void* user, void*
   P->sigma.assign(nn, {});
   for (double& t : P->timing) t = 0.0;
 
-  // per node: the columns it hands to its parent (pointer and row-block
-  // stride), and its own buffer
+  // Per node: the columns it hands to its parent (pointer, row-block stride,
+  // rows held) and its own buffer.  A pass-through leaf's columns are fetched
+  // from the provider only when its parent's group is built.
   std::vector<std::vector<const void*>> out_cols(nn);
-  std::vector<std::vector<int64_t>> out_rbs(nn);
+  std::vector<std::vector<int64_t>> out_rbs(nn), out_rows(nn);
   std::vector<void*> out_buf(nn, nullptr);
+  std::vector<char> deferred(nn, 0);
   hipEvent_t t0 = nullptr, t1 = nullptr;
   HAPOD_HIP(hipEventCreate(&t0));
   HAPOD_HIP(hipEventCreate(&t1));
@@ -735,113 +761,155 @@ hapod_status hapod_run(hapod_plan_t P, hapod_leaf_fn get_leaf, void* user, void*
         out_buf[i] = nullptr;
       }
   };
+  auto fetch_leaf = [&](int32_t a, std::vector<const void*>& cols, std::vector<int64_t>& rbs,
+                        std::vector<int64_t>& rows) -> hapod_status {
+    const void* ptr = nullptr;
+    int64_t ld = 0;
+    const int32_t rc = get_leaf(user, a, &ptr, &ld, stream_);
+    if (rc != 0) {
+      set_error("leaf provider returned " + std::to_string(rc) + " for leaf " + std::to_string(a));
+      return HAPOD_E_CALLBACK;
+    }
+    if (P->leaf_cols[a] > 0 && (!ptr || ld < P->rows[a])) {
+      set_error("leaf provider gave a NULL pointer or ld < rows for leaf " + std::to_string(a));
+      return HAPOD_E_CALLBACK;
+    }
+    cols = column_table(ptr, ld, P->leaf_cols[a], eb);
+    rbs.assign(cols.size(), kRowBlock);
+    rows.assign(cols.size(), P->rows[a]);
+    return HAPOD_OK;
+  };
   HAPOD_HIP(hipEventRecord(t0, stream));
   PhaseTimes pt;
   const int32_t LT = (int32_t)P->by_level.size();
   P->level_ms.assign(LT, {0.0, 0.0, 0.0, 0.0});
   for (int32_t l = 0; l < LT; ++l) {
-    std::vector<PodJob> jobs;
-    std::vector<int32_t> job_node;
+    // launch groups of this level: leaves in waves of at most `wave` nodes
+    std::vector<std::vector<int32_t>> groups(1);
+    int in_group = 0;
     for (int32_t a : P->by_level[l]) {
-      std::vector<const void*> in;
-      std::vector<int64_t> in_rbs;
-      if (P->children[a].empty()) {
-        const void* ptr = nullptr;
-        int64_t ld = 0;
-        const int32_t rc = get_leaf(user, a, &ptr, &ld, stream_);
-        if (rc != 0) {
-          release_all();
-          set_error("leaf provider returned " + std::to_string(rc) + " for leaf " + std::to_string(a));
-          return HAPOD_E_CALLBACK;
-        }
-        if ((P->leaf_cols[a] > 0 && !ptr) || ld < P->n) {
-          release_all();
-          set_error("leaf provider gave a NULL pointer or ld < n for leaf " + std::to_string(a));
-          return HAPOD_E_CALLBACK;
-        }
-        in = column_table(ptr, ld, P->leaf_cols[a], eb);
-        in_rbs.assign(in.size(), kRowBlock);
-      } else {
-        for (int32_t b : P->children[a]) {
-          in.insert(in.end(), out_cols[b].begin(), out_cols[b].end());
-          in_rbs.insert(in_rbs.end(), out_rbs[b].begin(), out_rbs[b].end());
-        }
-      }
-      P->m_in[a] = (int64_t)in.size();
-      if (P->eps[a] == 0.0) {
-        // POD(S, 0) = {(1, s)}: no decomposition; the vectors pass through
-        P->rank[a] = (int64_t)in.size();
-        P->sigma[a].assign(in.size(), 1.0);
-        out_cols[a] = in;
-        out_rbs[a] = in_rbs;
-        if (a == P->root) {
-          P->root_passthrough = true;
-          P->root_cols = in;
-          P->root_rbs = in_rbs;
-        }
+      const bool leaf = P->children[a].empty();
+      if (leaf && P->eps[a] == 0.0) {  // pass-through leaf: read by its parent
+        deferred[a] = 1;
+        P->m_in[a] = P->leaf_cols[a];
+        P->rank[a] = P->leaf_cols[a];
+        P->sigma[a].assign((size_t)P->leaf_cols[a], 1.0);
         continue;
       }
-      PodJob j;
-      j.cols = std::move(in);
-      j.rbs = std::move(in_rbs);
-      j.n = P->n;
-      j.m = (int64_t)j.cols.size();
-      j.eps = P->eps[a];
-      j.root = (a == P->root);
-      // the root's modes go out plain column-major; every other node's
-      // scaled modes stay in a row-block-tiled buffer for its parent
-      j.ocs = j.root ? P->n : kRowBlock;
-      j.obs = j.root ? kRowBlock : tiled_rbs(j.m);
-      if (j.m > 0) {
-        const size_t bytes = j.root ? (size_t)P->n * j.m * eb : tiled_bytes(P->n, j.m, eb);
-        hapod_status s = P->pool.alloc(bytes, &j.out);
+      if (leaf && in_group == wave) {
+        groups.emplace_back();
+        in_group = 0;
+      }
+      groups.back().push_back(a);
+      in_group += leaf ? 1 : 0;
+    }
+    PhaseTimes lt;
+    for (auto& grp : groups) {
+      std::vector<PodJob> jobs;
+      std::vector<int32_t> job_node;
+      for (int32_t a : grp) {
+        std::vector<const void*> in;
+        std::vector<int64_t> in_rbs, in_rows;
+        hapod_status s = HAPOD_OK;
+        if (P->children[a].empty()) {
+          s = fetch_leaf(a, in, in_rbs, in_rows);
+        } else {
+          for (int32_t b : P->children[a]) {
+            if (deferred[b]) {
+              s = fetch_leaf(b, out_cols[b], out_rbs[b], out_rows[b]);
+              if (s != HAPOD_OK) break;
+              deferred[b] = 0;
+            }
+            in.insert(in.end(), out_cols[b].begin(), out_cols[b].end());
+            in_rbs.insert(in_rbs.end(), out_rbs[b].begin(), out_rbs[b].end());
+            in_rows.insert(in_rows.end(), out_rows[b].begin(), out_rows[b].end());
+          }
+        }
         if (s != HAPOD_OK) {
           release_all();
           return s;
         }
-        out_buf[a] = j.out;
+        P->m_in[a] = (int64_t)in.size();
+        if (P->eps[a] == 0.0) {
+          // POD(S, 0) = {(1, s)}: no decomposition; the vectors pass through
+          P->rank[a] = (int64_t)in.size();
+          P->sigma[a].assign(in.size(), 1.0);
+          out_cols[a] = in;
+          out_rbs[a] = in_rbs;
+          out_rows[a] = in_rows;
+          if (a == P->root) {
+            P->root_passthrough = true;
+            P->root_cols = in;
+            P->root_rbs = in_rbs;
+            P->root_rows = in_rows;
+          }
+          continue;
+        }
+        PodJob j;
+        j.cols = std::move(in);
+        j.rbs = std::move(in_rbs);
+        j.crows = std::move(in_rows);
+        j.n = P->rows[a];
+        j.m = (int64_t)j.cols.size();
+        j.eps = P->eps[a];
+        j.root = (a == P->root);
+        // the root's modes go out plain column-major with n rows; every other
+        // node's scaled modes stay in a row-block-tiled buffer of its own rows
+        j.ocs = j.root ? P->n : kRowBlock;
+        j.obs = j.root ? kRowBlock : tiled_rbs(j.m);
+        if (j.m > 0) {
+          const size_t bytes = j.root ? (size_t)P->n * j.m * eb : tiled_bytes(j.n, j.m, eb);
+          s = P->pool.alloc(bytes, &j.out);
+          if (s == HAPOD_OK && j.root && j.n < P->n) s = launch_zero_bytes(j.out, bytes, stream);
+          if (s != HAPOD_OK) {
+            release_all();
+            return s;
+          }
+          out_buf[a] = j.out;
+        }
+        jobs.push_back(std::move(j));
+        job_node.push_back(a);
       }
-      jobs.push_back(std::move(j));
-      job_node.push_back(a);
-    }
-    PhaseTimes lt;
-    hapod_status s = run_pod_batch(prec, jobs, 0, 1, jmax, P->pool, stream, &lt);
-    if (s != HAPOD_OK) {
-      release_all();
-      return s;
+      hapod_status s = run_pod_batch(prec, jobs, 0, 1, jmax, P->pool, stream, &lt);
+      if (s != HAPOD_OK) {
+        release_all();
+        return s;
+      }
+      for (size_t k = 0; k < jobs.size(); ++k) {
+        const int32_t a = job_node[k];
+        const PodJob& j = jobs[k];
+        P->rank[a] = j.rank;
+        P->sigma[a] = j.sigma;
+        P->lam1[a] = j.info[1];
+        P->lam_min[a] = j.info[2];
+        P->n_neg[a] = (int64_t)j.info[3];
+        if (a == P->root) {
+          out_cols[a] = column_table(j.out, P->n, j.rank, eb);
+          out_rbs[a].assign((size_t)j.rank, kRowBlock);
+          out_rows[a].assign((size_t)j.rank, P->n);
+        } else {
+          out_cols[a] = tiled_table(j.out, j.rank, eb);
+          out_rbs[a].assign((size_t)j.rank, tiled_rbs(j.m));
+          out_rows[a].assign((size_t)j.rank, j.n);
+        }
+        if (j.rank == 0 && out_buf[a]) {
+          P->pool.free(out_buf[a]);
+          out_buf[a] = nullptr;
+        }
+      }
+      // the children of this group are consumed
+      for (int32_t a : grp)
+        for (int32_t b : P->children[a])
+          if (out_buf[b]) {
+            P->pool.free(out_buf[b]);
+            out_buf[b] = nullptr;
+          }
     }
     P->level_ms[l] = {lt.gram, lt.eig, lt.trunc, lt.lift};
     pt.gram += lt.gram;
     pt.eig += lt.eig;
     pt.trunc += lt.trunc;
     pt.lift += lt.lift;
-    for (size_t k = 0; k < jobs.size(); ++k) {
-      const int32_t a = job_node[k];
-      const PodJob& j = jobs[k];
-      P->rank[a] = j.rank;
-      P->sigma[a] = j.sigma;
-      P->lam1[a] = j.info[1];
-      P->lam_min[a] = j.info[2];
-      P->n_neg[a] = (int64_t)j.info[3];
-      if (a == P->root) {
-        out_cols[a] = column_table(j.out, P->n, j.rank, eb);
-        out_rbs[a].assign((size_t)j.rank, kRowBlock);
-      } else {
-        out_cols[a] = tiled_table(j.out, j.rank, eb);
-        out_rbs[a].assign((size_t)j.rank, tiled_rbs(j.m));
-      }
-      if (j.rank == 0 && out_buf[a]) {
-        P->pool.free(out_buf[a]);
-        out_buf[a] = nullptr;
-      }
-    }
-    // the children of this level are consumed
-    for (int32_t a : P->by_level[l])
-      for (int32_t b : P->children[a])
-        if (out_buf[b]) {
-          P->pool.free(out_buf[b]);
-          out_buf[b] = nullptr;
-        }
   }
   HAPOD_HIP(hipEventRecord(t1, stream));
   // re-orthonormalise the root's modes
@@ -910,15 +978,19 @@ hapod_status hapod_modes(hapod_plan_t P, int32_t node, void* U, int64_t ldu, dou
     const int eb = elem_bytes(P->opts.prec);
     if (N > 0) {
       if (P->root_passthrough) {
-        void *dcols = nullptr, *drbs = nullptr;
+        void *dcols = nullptr, *drbs = nullptr, *drows = nullptr;
         HAPOD_TRY(P->pool.alloc(sizeof(void*) * N, &dcols));
         HAPOD_TRY(P->pool.alloc(sizeof(int64_t) * N, &drbs));
+        HAPOD_TRY(P->pool.alloc(sizeof(int64_t) * N, &drows));
         HAPOD_HIP(hipMemcpyAsync(dcols, P->root_cols.data(), sizeof(void*) * N, hipMemcpyHostToDevice, stream));
         HAPOD_HIP(hipMemcpyAsync(drbs, P->root_rbs.data(), sizeof(int64_t) * N, hipMemcpyHostToDevice, stream));
-        hapod_status s = launch_copy_cols(eb, P->n, N, (const void* const*)dcols, (const int64_t*)drbs, U, ldu, stream);
+        HAPOD_HIP(hipMemcpyAsync(drows, P->root_rows.data(), sizeof(int64_t) * N, hipMemcpyHostToDevice, stream));
+        hapod_status s = launch_copy_cols(eb, P->n, N, (const void* const*)dcols, (const int64_t*)drbs,
+                                          (const int64_t*)drows, U, ldu, stream);
         HAPOD_HIP(hipStreamSynchronize(stream));
         P->pool.free(dcols);
         P->pool.free(drbs);
+        P->pool.free(drows);
         HAPOD_TRY(s);
       } else {
         HAPOD_HIP(hipMemcpy2DAsync(U, (size_t)ldu * eb, P->root_U, (size_t)P->n * eb, (size_t)P->n * eb, (size_t)N,
@@ -992,10 +1064,12 @@ hapod_status gram_impl(int compute, int eb, int64_t n, int64_t m, const void* S,
   bool vec_ok = (cr % KB == 0);
   for (auto c : cols)
     if ((uintptr_t)c & 15u) vec_ok = false;
-  void *dcols = nullptr, *dpart = nullptr, *dblob = nullptr, *drbs = nullptr;
+  void *dcols = nullptr, *dpart = nullptr, *dblob = nullptr, *drbs = nullptr, *drows = nullptr;
   HAPOD_TRY(pool.alloc(sizeof(void*) * m, &dcols));
   HAPOD_TRY(pool.alloc(sizeof(int64_t) * m, &drbs));
+  HAPOD_TRY(pool.alloc(sizeof(int64_t) * m, &drows));
   HAPOD_TRY(launch_fill_i64((int64_t*)drbs, kRowBlock, m, stream));
+  HAPOD_TRY(launch_fill_i64((int64_t*)drows, n, m, stream));
   if (nch > 1) HAPOD_TRY(pool.alloc(sizeof(double) * pairs * nch * kGramTile * kGramTile, &dpart));
   // split-BF16 with several column tiles: read a split twin (as the level batch does)
   void* dsplit = nullptr;
@@ -1015,6 +1089,7 @@ hapod_status gram_impl(int compute, int eb, int64_t n, int64_t m, const void* S,
   GramNode g{};
   g.cols = (const void* const*)(presplit ? dcols_g : dcols);
   g.rbs = (const int64_t*)(presplit ? drbs_g : drbs);
+  g.crows = (const int64_t*)drows;  // the split twin holds n rows as well
   g.split = presplit ? 1 : 0;
   g.n = n;
   g.chunk_rows = cr;
@@ -1056,7 +1131,8 @@ hapod_status gram_impl(int compute, int eb, int64_t n, int64_t m, const void* S,
         st = HAPOD_E_DEVICE;
         break;
       }
-      st = launch_split_cols(n, m, (const void* const*)dcols, (const int64_t*)drbs, (float*)dsplit, stream);
+      st = launch_split_cols(n, m, (const void* const*)dcols, (const int64_t*)drbs, (const int64_t*)drows,
+                             (float*)dsplit, stream);
       if (st != HAPOD_OK) break;
     }
     if (n == 0) {
@@ -1078,6 +1154,7 @@ hapod_status gram_impl(int compute, int eb, int64_t n, int64_t m, const void* S,
   pool.free(dsplit);
   pool.free(dcols_g);
   pool.free(drbs_g);
+  pool.free(drows);
   return st;
 }
 }  // namespace hapod
@@ -1198,16 +1275,19 @@ hapod_status hapod_lift(hapod_precision prec, int64_t n, int64_t m, int64_t N, c
   const int eb = elem_bytes(prec);
   Pool& pool = step_pool();
   auto cols = column_table(S, lds, m, eb);
-  void *dcols = nullptr, *dB = nullptr, *drank = nullptr, *dn = nullptr, *drbs = nullptr;
+  void *dcols = nullptr, *dB = nullptr, *drank = nullptr, *dn = nullptr, *drbs = nullptr, *drows = nullptr;
   HAPOD_TRY(pool.alloc(sizeof(void*) * std::max<int64_t>(m, 1), &dcols));
   HAPOD_TRY(pool.alloc(sizeof(int64_t) * std::max<int64_t>(m, 1), &drbs));
+  HAPOD_TRY(pool.alloc(sizeof(int64_t) * std::max<int64_t>(m, 1), &drows));
   HAPOD_TRY(launch_fill_i64((int64_t*)drbs, kRowBlock, m, stream));
+  HAPOD_TRY(launch_fill_i64((int64_t*)drows, n, m, stream));
   HAPOD_TRY(pool.alloc(sizeof(double) * std::max<int64_t>(m * N, 1), &dB));
   HAPOD_TRY(pool.alloc(sizeof(int64_t), &drank));
   HAPOD_TRY(pool.alloc(sizeof(LiftNode), &dn));
   LiftNode l{};
   l.cols = (const void* const*)dcols;
   l.rbs = (const int64_t*)drbs;
+  l.crows = (const int64_t*)drows;
   l.B = (const double*)dB;
   l.rank = (const int64_t*)drank;
   l.out = out;
@@ -1240,6 +1320,7 @@ hapod_status hapod_lift(hapod_precision prec, int64_t n, int64_t m, int64_t N, c
   (void)hipStreamSynchronize(stream);
   pool.free(dcols);
   pool.free(drbs);
+  pool.free(drows);
   pool.free(dB);
   pool.free(drank);
   pool.free(dn);
@@ -1263,7 +1344,7 @@ hapod_status hapod_reorth(hapod_precision prec, int64_t n, int64_t N, void* U, i
   const int eb = elem_bytes(prec);
   Pool& pool = step_pool();
   void *W = nullptr, *Rinv = nullptr, *tmp = nullptr, *dcols = nullptr, *dn = nullptr, *drank = nullptr,
-       *dbad = nullptr, *drbs = nullptr;
+       *dbad = nullptr, *drbs = nullptr, *drows = nullptr;
   HAPOD_TRY(pool.alloc(sizeof(double) * N * N, &W));
   HAPOD_TRY(pool.alloc(sizeof(double) * N * N, &Rinv));
   HAPOD_TRY(pool.alloc((size_t)n * N * eb, &tmp));
@@ -1272,7 +1353,9 @@ hapod_status hapod_reorth(hapod_precision prec, int64_t n, int64_t N, void* U, i
   HAPOD_TRY(pool.alloc(sizeof(int64_t), &drank));
   HAPOD_TRY(pool.alloc(sizeof(int32_t), &dbad));
   HAPOD_TRY(pool.alloc(sizeof(int64_t) * N, &drbs));
+  HAPOD_TRY(pool.alloc(sizeof(int64_t) * N, &drows));
   HAPOD_TRY(launch_fill_i64((int64_t*)drbs, kRowBlock, N, stream));
+  HAPOD_TRY(launch_fill_i64((int64_t*)drows, n, N, stream));
   hapod_status st = HAPOD_OK;
   int64_t total_bad = 0;
   auto cols = column_table(U, ldu, N, eb);
@@ -1285,6 +1368,7 @@ hapod_status hapod_reorth(hapod_precision prec, int64_t n, int64_t N, void* U, i
     LiftNode l{};
     l.cols = (const void* const*)dcols;
     l.rbs = (const int64_t*)drbs;
+    l.crows = (const int64_t*)drows;
     l.B = (const double*)Rinv;
     l.rank = (const int64_t*)drank;
     l.out = tmp;
@@ -1317,7 +1401,7 @@ hapod_status hapod_reorth(hapod_precision prec, int64_t n, int64_t N, void* U, i
   }
   (void)hipStreamSynchronize(stream);
   if (bad) *bad = total_bad;
-  for (void* p : {W, Rinv, tmp, dcols, dn, drank, dbad, drbs}) pool.free(p);
+  for (void* p : {W, Rinv, tmp, dcols, dn, drank, dbad, drbs, drows}) pool.free(p);
   return st;
 }
 
@@ -1347,6 +1431,7 @@ hapod_status hapod_node_pod(hapod_precision prec, int64_t n, int64_t m, const vo
   std::vector<PodJob> jobs(1);
   jobs[0].cols = column_table(S, lds, m, eb);
   jobs[0].rbs.assign((size_t)m, kRowBlock);
+  jobs[0].crows.assign((size_t)m, n);
   jobs[0].n = n;
   jobs[0].m = m;
   jobs[0].eps = eps;

@@ -123,7 +123,7 @@ __global__ __launch_bounds__(256) void gram_tile_kernel(const GramNode* __restri
   // products land in accumulator entries that are never stored)
   const Elem* pa[NB];
   const Elem* pb[NB];
-  int64_t sa[NB], sb[NB];
+  int64_t sa[NB], sb[NB], ra[NB], rb[NB];
 #pragma unroll
   for (int a = 0; a < NB; ++a) {
     const int ca = min(cA0 + a * 16 + li, nd.m - 1), cb = min(cB0 + a * 16 + li, nd.m - 1);
@@ -131,6 +131,8 @@ __global__ __launch_bounds__(256) void gram_tile_kernel(const GramNode* __restri
     pb[a] = reinterpret_cast<const Elem*>(nd.cols[cb]);
     sa[a] = nd.rbs[ca];
     sb[a] = nd.rbs[cb];
+    ra[a] = nd.crows[ca];
+    rb[a] = nd.crows[cb];
   }
 
   Acc acc[NB][NB];
@@ -175,41 +177,50 @@ __global__ __launch_bounds__(256) void gram_tile_kernel(const GramNode* __restri
     }
   }
   {
-  // full 128-row blocks: constant offsets, no guards
-  const int64_t blk0 = r0 >> 7, nfull = (r1 - r0) >> 7;
-  for (int64_t bi = 0; bi < nfull; ++bi) {
-    gptr<Elem> qa[NB], qb[NB];
+  // 128-row blocks.  A block every column of the wavefront holds in full
+  // runs unguarded at constant offsets; a block some column holds only in
+  // part (its last one, or one past its rows) reads guarded.
+  const int64_t blk0 = r0 >> 7, nblk = (r1 - r0 + kRowBlock - 1) >> 7;
+  for (int64_t bi = 0; bi < nblk; ++bi) {
+    const int64_t blk = blk0 + bi;
+    const int64_t rend = (blk + 1) << 7;
+    int lane_full = 1;
 #pragma unroll
-    for (int a = 0; a < NB; ++a) {
-      qa[a] = as_global(pa[a] + (blk0 + bi) * sa[a] + R * g);
-      qb[a] = as_global(pb[a] + (blk0 + bi) * sb[a] + R * g);
-    }
-#pragma unroll
-    for (int bt = 0; bt < NBT; ++bt) {
-      Elem va[NB][R], vb[NB][R];
+    for (int a = 0; a < NB; ++a) lane_full &= (ra[a] >= rend) & (rb[a] >= rend);
+    if (__all(lane_full)) {
+      gptr<Elem> qa[NB], qb[NB];
 #pragma unroll
       for (int a = 0; a < NB; ++a) {
-        run_full<R, VEC>(qa[a] + bt * KB, va[a]);
-        run_full<R, VEC>(qb[a] + bt * KB, vb[a]);
+        qa[a] = as_global(pa[a] + blk * sa[a] + R * g);
+        qb[a] = as_global(pb[a] + blk * sb[a] + R * g);
       }
-      mfma_batch<C, Acc, R>(acc, va, vb);
-    }
-  }
-  // partial last block: guarded runs
-  for (int64_t k0 = r0 + (nfull << 7); k0 < r1; k0 += KB) {
-    const int64_t row = k0 + (int64_t)R * g;
-    Elem va[NB][R], vb[NB][R];
 #pragma unroll
-    for (int a = 0; a < NB; ++a) {
-      const Elem* xa = pa[a] + blk_off(row, sa[a]);
-      const Elem* xb = pb[a] + blk_off(row, sb[a]);
+      for (int bt = 0; bt < NBT; ++bt) {
+        Elem va[NB][R], vb[NB][R];
 #pragma unroll
-      for (int t = 0; t < R; ++t) {
-        va[a][t] = (row + t < r1) ? xa[t] : Elem(0);
-        vb[a][t] = (row + t < r1) ? xb[t] : Elem(0);
+        for (int a = 0; a < NB; ++a) {
+          run_full<R, VEC>(qa[a] + bt * KB, va[a]);
+          run_full<R, VEC>(qb[a] + bt * KB, vb[a]);
+        }
+        mfma_batch<C, Acc, R>(acc, va, vb);
+      }
+    } else {
+      for (int bt = 0; bt < NBT; ++bt) {
+        const int64_t row = (blk << 7) + bt * KB + (int64_t)R * g;
+        Elem va[NB][R], vb[NB][R];
+#pragma unroll
+        for (int a = 0; a < NB; ++a) {
+          const Elem* xa = pa[a] + blk * sa[a] + (row & (kRowBlock - 1));
+          const Elem* xb = pb[a] + blk * sb[a] + (row & (kRowBlock - 1));
+#pragma unroll
+          for (int t = 0; t < R; ++t) {
+            va[a][t] = (row + t < ra[a]) ? xa[t] : Elem(0);
+            vb[a][t] = (row + t < rb[a]) ? xb[t] : Elem(0);
+          }
+        }
+        mfma_batch<C, Acc, R>(acc, va, vb);
       }
     }
-    mfma_batch<C, Acc, R>(acc, va, vb);
   }
   }
 

@@ -52,6 +52,7 @@ constexpr int kGramTile = 128;
 struct GramNode {
   const void* const* cols;
   const int64_t* rbs;
+  const int64_t* crows; // rows held by each column (<= n); rows past it read as 0
   int64_t n;
   int64_t chunk_rows;
   double* G;
@@ -132,6 +133,7 @@ constexpr int kLiftTileN = 128;
 struct LiftNode {
   const void* const* cols;
   const int64_t* rbs;
+  const int64_t* crows;  // rows held by each column; rows past it read as 0
   const double* B;
   const int64_t* rank;   // device pointer to N
   void* out;             // element (r, c) at out[c * ocs + blk_off(r, obs)]
@@ -152,7 +154,9 @@ hapod_status launch_lift(int compute, const LiftNode* d_nodes, int num_nodes,
 hapod_status launch_fill_colptrs(const void* base, int64_t ld, int64_t m, int elem_bytes,
                                  const void** d_out, hipStream_t stream);
 hapod_status launch_copy_cols(int elem_bytes, int64_t n, int64_t m, const void* const* cols,
-                              const int64_t* rbs, void* out, int64_t ldo, hipStream_t stream);
+                              const int64_t* rbs, const int64_t* crows, void* out, int64_t ldo,
+                              hipStream_t stream);
+hapod_status launch_zero_bytes(void* p, size_t bytes, hipStream_t stream);
 hapod_status launch_check_diag(const double* G, int64_t ldg, int64_t m, int32_t* d_flag,
                                hipStream_t stream);
 hapod_status launch_set_scalar_i64(int64_t* p, int64_t v, hipStream_t stream);
@@ -161,8 +165,8 @@ hapod_status launch_fill_i64(int64_t* p, int64_t v, int64_t count, hipStream_t s
 // row-block-tiled buffer of capacity m: block b of column c occupies the 128
 // float slots at dst + (b * m + c) * 128 and holds 128 bf16 hi values followed
 // by 128 bf16 lo values (x = hi + lo + O(2^-17 |x|)); rows past n are zero.
-hapod_status launch_split_cols(int64_t n, int64_t m, const void* const* cols, const int64_t* rbs, float* dst,
-                               hipStream_t stream);
+hapod_status launch_split_cols(int64_t n, int64_t m, const void* const* cols, const int64_t* rbs,
+                               const int64_t* crows, float* dst, hipStream_t stream);
 
 // ---- Cholesky-QR re-orthonormalisation -------------------------------------
 hapod_status launch_chol_inv(double* W, int64_t ldw, int64_t N, double* Rinv, int64_t ldr,

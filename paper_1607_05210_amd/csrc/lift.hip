@@ -57,12 +57,13 @@ __global__ __launch_bounds__(256) void lift_kernel(const LiftNode* __restrict__ 
       const int k = k0 + g;
       const Elem* col = (k < m) ? reinterpret_cast<const Elem*>(nd.cols[k]) : nullptr;
       const int64_t rbs = (k < m) ? nd.rbs[k] : kRowBlock;
+      const int64_t rows = (k < m) ? nd.crows[k] : 0;
       Elem va[NB];
       double vb[NB];
 #pragma unroll
       for (int a = 0; a < NB; ++a) {
         const int64_t row = r0 + a * 16 + li;
-        va[a] = (col && row < nd.n) ? col[blk_off(row, rbs)] : Elem(0);
+        va[a] = (row < rows) ? col[blk_off(row, rbs)] : Elem(0);
       }
 #pragma unroll
       for (int b = 0; b < NB; ++b) {
@@ -84,10 +85,11 @@ __global__ __launch_bounds__(256) void lift_kernel(const LiftNode* __restrict__ 
         const int k = k0 + 8 * g + e;
         const float* col = (k < m) ? reinterpret_cast<const float*>(nd.cols[k]) : nullptr;
         const int64_t rbs = (k < m) ? nd.rbs[k] : kRowBlock;
+        const int64_t rows = (k < m) ? nd.crows[k] : 0;
 #pragma unroll
         for (int a = 0; a < NB; ++a) {
           const int64_t row = r0 + a * 16 + li;
-          xa[a][e] = (col && row < nd.n) ? col[blk_off(row, rbs)] : 0.f;
+          xa[a][e] = (row < rows) ? col[blk_off(row, rbs)] : 0.f;
         }
 #pragma unroll
         for (int b = 0; b < NB; ++b) {

@@ -8,11 +8,11 @@ namespace hapod {
 namespace {
 
 __global__ __launch_bounds__(128) void split_cols_kernel(int64_t n, int64_t m, const void* const* cols,
-                                                         const int64_t* rbs, float* dst) {
+                                                         const int64_t* rbs, const int64_t* crows, float* dst) {
   const int64_t b = blockIdx.x, c = blockIdx.y;
   const int64_t r = b * kRowBlock + threadIdx.x;
   const float* src = reinterpret_cast<const float*>(cols[c]);
-  const float x = (r < n) ? src[blk_off(r, rbs[c])] : 0.f;
+  const float x = (r < n && r < crows[c]) ? src[blk_off(r, rbs[c])] : 0.f;
   const uint16_t h = bf16_bits_rne(x);
   const uint16_t l = bf16_bits_rne(x - bf16_bits_to_float(h));
   uint16_t* blk = reinterpret_cast<uint16_t*>(dst + (b * m + c) * kRowBlock);
@@ -26,13 +26,18 @@ __global__ void fill_colptrs_kernel(const char* base, int64_t ld_bytes, int64_t 
 }
 
 template <typename E>
-__global__ void copy_cols_kernel(int64_t n, int64_t m, const void* const* cols, const int64_t* rbs, E* out,
-                                 int64_t ldo) {
+__global__ void copy_cols_kernel(int64_t n, int64_t m, const void* const* cols, const int64_t* rbs,
+                                 const int64_t* crows, E* out, int64_t ldo) {
   const int64_t j = blockIdx.y;
   const E* src = reinterpret_cast<const E*>(cols[j]);
-  const int64_t s = rbs[j];
+  const int64_t s = rbs[j], rows = crows[j];
   for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x)
-    out[j * ldo + r] = src[blk_off(r, s)];
+    out[j * ldo + r] = (r < rows) ? src[blk_off(r, s)] : E(0);
+}
+
+__global__ void zero_u32_kernel(uint32_t* p, size_t count) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x)
+    p[i] = 0u;
 }
 
 __global__ void check_diag_kernel(const double* G, int64_t ldg, int64_t m, int32_t* flag) {
@@ -116,8 +121,17 @@ hapod_status launch_fill_colptrs(const void* base, int64_t ld, int64_t m, int el
   return HAPOD_OK;
 }
 
+hapod_status launch_zero_bytes(void* p, size_t bytes, hipStream_t stream) {
+  if (bytes == 0) return HAPOD_OK;
+  const size_t words = bytes / 4;  // callers pass multiples of 4
+  hipLaunchKernelGGL(zero_u32_kernel, dim3((unsigned)std::min<size_t>((words + 255) / 256, 4096)), dim3(256), 0,
+                     stream, (uint32_t*)p, words);
+  HAPOD_HIP(hipGetLastError());
+  return HAPOD_OK;
+}
+
 hapod_status launch_copy_cols(int elem_bytes, int64_t n, int64_t m, const void* const* cols, const int64_t* rbs,
-                              void* out, int64_t ldo, hipStream_t stream) {
+                              const int64_t* crows, void* out, int64_t ldo, hipStream_t stream) {
   if (m <= 0 || n <= 0) return HAPOD_OK;
   if (m > 65535) {
     set_error("launch_copy_cols: too many columns");
@@ -126,9 +140,9 @@ hapod_status launch_copy_cols(int elem_bytes, int64_t n, int64_t m, const void* 
   const unsigned gx = (unsigned)std::min<int64_t>((n + 255) / 256, 1024);
   if (elem_bytes == 8)
     hipLaunchKernelGGL(copy_cols_kernel<double>, dim3(gx, (unsigned)m), dim3(256), 0, stream, n, m, cols, rbs,
-                       (double*)out, ldo);
+                       crows, (double*)out, ldo);
   else
-    hipLaunchKernelGGL(copy_cols_kernel<float>, dim3(gx, (unsigned)m), dim3(256), 0, stream, n, m, cols, rbs,
+    hipLaunchKernelGGL(copy_cols_kernel<float>, dim3(gx, (unsigned)m), dim3(256), 0, stream, n, m, cols, rbs, crows,
                        (float*)out, ldo);
   HAPOD_HIP(hipGetLastError());
   return HAPOD_OK;
@@ -156,15 +170,16 @@ hapod_status launch_fill_i64(int64_t* p, int64_t v, int64_t count, hipStream_t s
   return HAPOD_OK;
 }
 
-hapod_status launch_split_cols(int64_t n, int64_t m, const void* const* cols, const int64_t* rbs, float* dst,
-                               hipStream_t stream) {
+hapod_status launch_split_cols(int64_t n, int64_t m, const void* const* cols, const int64_t* rbs,
+                               const int64_t* crows, float* dst, hipStream_t stream) {
   if (n <= 0 || m <= 0) return HAPOD_OK;
   if (m > 65535) {
     set_error("launch_split_cols: too many columns");
     return HAPOD_E_UNSUPPORTED;
   }
   const unsigned nb = (unsigned)((n + kRowBlock - 1) / kRowBlock);
-  hipLaunchKernelGGL(split_cols_kernel, dim3(nb, (unsigned)m), dim3(kRowBlock), 0, stream, n, m, cols, rbs, dst);
+  hipLaunchKernelGGL(split_cols_kernel, dim3(nb, (unsigned)m), dim3(kRowBlock), 0, stream, n, m, cols, rbs, crows,
+                     dst);
   HAPOD_HIP(hipGetLastError());
   return HAPOD_OK;
 }

@@ -366,9 +366,10 @@ hapod_status wide_eigh(const double* G, int64_t ldg, int64_t m, double* lambda, 
   double* tr = (double*)get(sizeof(double));
   const void** qcols = (const void**)get(sizeof(void*) * k);
   int64_t* qrbs = (int64_t*)get(sizeof(int64_t) * k);
+  int64_t* qrows = (int64_t*)get(sizeof(int64_t) * k);
   int64_t* drank = (int64_t*)get(sizeof(int64_t));
   void* dnode = get(sizeof(LiftNode));
-  if (!Q || !w || !h || !alpha || !beta || !theta || !e2 || !Z || !last || !isc || !ipiv || !tr || !qcols || !qrbs || !drank ||
+  if (!Q || !w || !h || !alpha || !beta || !theta || !e2 || !Z || !last || !isc || !ipiv || !tr || !qcols || !qrbs || !qrows || !drank ||
       !dnode) {
     set_error("wide_eigh: scratch allocation failed");
     return HAPOD_E_NOMEM;
@@ -449,10 +450,12 @@ hapod_status wide_eigh(const double* G, int64_t ldg, int64_t m, double* lambda, 
   if (b > 0) {
     HAPOD_TRY(launch_fill_colptrs(Q, m, kk, 8, qcols, stream));
     HAPOD_TRY(launch_fill_i64(qrbs, kRowBlock, kk, stream));
+    HAPOD_TRY(launch_fill_i64(qrows, m, kk, stream));
     HAPOD_TRY(launch_set_scalar_i64(drank, b, stream));
     LiftNode l{};
     l.cols = (const void* const*)qcols;
     l.rbs = qrbs;
+    l.crows = qrows;
     l.B = Z;
     l.rank = drank;
     l.out = V;

@@ -20,8 +20,11 @@ for them):
   ``(u, v) = rng.random((m, 2))`` per column, ``c_j = u``,
   ``w_j = wmin + (wmax - wmin) * v``.
 
-Large device-resident inputs are produced by :mod:`synth.device` with the
-same coefficients (drawn here, on the host) and the same formulas.
+* uneven leaves: per-leaf heights, widths and family (sinusoid or bumps),
+  evaluated on the global grid; rows past a leaf's height are zero.
+
+The benchmark builds its large device-resident inputs from the same
+coefficient draws (made here, on the host) and the same formulas.
 """
 from __future__ import annotations
 
@@ -37,6 +40,8 @@ __all__ = [
     "sinusoid",
     "bump_params",
     "bumps",
+    "uneven_leaf_specs",
+    "uneven_leaf",
     "star_tree",
     "chain_tree",
     "balanced_tree",
@@ -95,6 +100,41 @@ def bumps(n: int, m: int, seed: int, wmin: float = 0.01, wmax: float = 0.05,
     c, w = bump_params(m, seed, wmin, wmax)
     x = grid(n)
     S = np.exp(-np.subtract.outer(x, c) ** 2 / (2.0 * w * w))
+    return np.asfortranarray(S.astype(dtype, copy=False))
+
+
+# --------------------------------------------------------------------------
+# uneven leaves: per-leaf heights, widths and families on one global grid
+# --------------------------------------------------------------------------
+def uneven_leaf_specs(num_leaves: int, seed: int, rows_range, cols_range):
+    """Per-leaf (rows, cols, family, seed): rows ~ U{rows_range}, cols ~
+    U{cols_range}, family 0 = sinusoid, 1 = Gaussian bumps (Bernoulli 1/2)."""
+    rng = np.random.default_rng(seed)
+    rows = rng.integers(rows_range[0], rows_range[1] + 1, num_leaves)
+    cols = rng.integers(cols_range[0], cols_range[1] + 1, num_leaves)
+    fam = rng.integers(0, 2, num_leaves)
+    seeds = rng.integers(0, 2 ** 31 - 1, num_leaves)
+    return [dict(rows=int(r), cols=int(c), family=int(f), seed=int(z))
+            for r, c, f, z in zip(rows, cols, fam, seeds)]
+
+
+def uneven_leaf(spec, n: int, K: int = 400, tau: float = 20.0, noise_std: float = 1e-10,
+                dtype=np.float64) -> np.ndarray:
+    """The first ``spec['rows']`` rows (of n on the grid x_i = i/(n+1)) of the
+    leaf's snapshots; rows beyond are zero by definition.  Fortran order."""
+    r, m = spec["rows"], spec["cols"]
+    x = grid(n)[:r]
+    rng = np.random.default_rng(spec["seed"])
+    if spec["family"] == 0:
+        C = rng.standard_normal((m, K))
+        k = np.arange(1, K + 1, dtype=np.float64)
+        S = (math.sqrt(2.0) * np.sin(np.pi * np.outer(x, k))) @ (C * np.exp(-k / tau)).T
+        if noise_std > 0:
+            S = S + rng.standard_normal((m, r)).T * noise_std
+    else:
+        u = rng.random((m, 2))
+        c, w = u[:, 0], 0.01 + 0.04 * u[:, 1]
+        S = np.exp(-np.subtract.outer(x, c) ** 2 / (2.0 * w * w))
     return np.asfortranarray(S.astype(dtype, copy=False))
 
 

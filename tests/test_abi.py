@@ -94,3 +94,11 @@ def test_modes_before_run_is_a_state_error():
     with pytest.raises(hp.HapodError) as e:
         plan.node_stats()
     assert e.value.status == 6
+
+
+def test_plan_rejects_bad_leaf_rows():
+    hp = pytest.importorskip("paper_1607_05210_amd")
+    with pytest.raises(hp.HapodError) as e:
+        hp.Plan(synth.star_tree(2), [3, 3, 0], 10, 1e-3, 0.5, leaf_rows=[5, 11, 0])
+    assert e.value.status == 1
+    hp.Plan(synth.star_tree(2), [3, 3, 0], 10, 1e-3, 0.5, leaf_rows=[5, 10, 0])

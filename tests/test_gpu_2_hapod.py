@@ -228,3 +228,73 @@ def test_star_wide_root_coefficient_oracle(hp, prec):
     print(f"  wide root {prec}: rank {len(sig)} (oracle {len(s_ref)}), r_res {r}, e_sub {e_sub:.2e}")
     assert r >= (150 if prec == "fp64" else 40)
     assert e_sub <= TAU[prec]
+
+
+@pytest.mark.parametrize("prec,wave", [("fp64", 0), ("fp64", 5), ("fp32", 7), ("bf16x3", 0)])
+def test_uneven_leaves_balanced_tree(hp, prec, wave):
+    """Leaves of different heights (implicit zero rows) and widths, mixed
+    families, under a 3-level balanced tree; optional launch waves."""
+    n = 6000
+    specs = synth.uneven_leaf_specs(16, seed=3, rows_range=(700, n), cols_range=(8, 40))
+    parent = synth.balanced_tree(16, 3)
+    cols = [sp["cols"] for sp in specs] + [0] * (len(parent) - 16)
+    rows = [sp["rows"] for sp in specs] + [0] * (len(parent) - 16)
+    data = {i: synth.uneven_leaf(sp, n) for i, sp in enumerate(specs)}
+    if prec != "fp64":
+        data = {i: d.astype(np.float32).astype(np.float64) for i, d in data.items()}
+    eps_star, omega = 1e-3, 0.75
+    plan = hp.Plan(parent, cols, n, eps_star, omega, prec=prec, leaf_rows=rows, leaf_wave=wave)
+    calls = []
+
+    def provider(leaf):
+        calls.append(leaf)
+        return dev_colmajor(data[leaf], ELEM[prec])
+    plan.run(provider)
+    assert sorted(calls) == list(range(16))
+    sig, U = plan.modes()
+    full = {i: np.vstack([d, np.zeros((n - d.shape[0], d.shape[1]))]) for i, d in data.items()}
+    eps = tolerances.hapod_tolerances(parent, cols, eps_star, omega)
+    ref = hapod.hapod(parent, full, eps)
+    root = tree.validate(parent)
+    s_ref, U_ref = ref[root]
+    r = metrics.resolved_rank(s_ref, len(sig), UP[prec], TAU[prec])
+    e_sub = metrics.subspace_error(U_ref, host(U), r)
+    print(f"  uneven {prec} wave {wave}: rank {len(sig)} (oracle {len(s_ref)}), r_res {r}, e_sub {e_sub:.2e}")
+    assert r >= 10 and e_sub <= TAU[prec]
+    if prec == "fp64":
+        S = np.hstack([full[i] for i in range(16)])
+        assert metrics.mean_projection_error(S, host(U)) <= eps_star ** 2
+
+
+def test_chain_streamed_through_one_buffer(hp):
+    """Incremental HAPOD whose provider copies each chunk into the same device
+    buffer: leaves are fetched just before the group that reads them."""
+    n, chunks, per = 4096, 12, 24
+    S = synth.bumps(n, chunks * per, seed=8)
+    parent, chunk = synth.chain_tree(chunks)
+    zero = [b for b in chunk if b != 0]
+    cols = [per if i in chunk else 0 for i in range(len(parent))]
+    ov = [-1.0] * len(parent)
+    for z in zero:
+        ov[z] = 0.0
+    eps_star = 1e-3 * math.sqrt(np.mean(np.sum(S * S, axis=0)))
+    plan = hp.Plan(parent, cols, n, eps_star, 0.75, prec="fp64", eps_override=ov, mem_cap_bytes=256 << 20)
+    buf = dev_colmajor(np.zeros((n, per)))
+    order = []
+
+    def provider(leaf):
+        c = chunk[leaf]
+        order.append(c)
+        buf.copy_(dev_colmajor(S[:, c * per:(c + 1) * per]))
+        return buf
+    plan.run(provider)
+    assert order == list(range(chunks))          # one chunk per level, in order
+    sig, U = plan.modes()
+    eps = tolerances.hapod_tolerances(parent, cols, eps_star, 0.75, zero_nodes=zero)
+    blocks = {leaf: S[:, c * per:(c + 1) * per] for leaf, c in chunk.items()}
+    ref = hapod.hapod(parent, blocks, eps)
+    root = tree.validate(parent)
+    s_ref, U_ref = ref[root]
+    r = metrics.resolved_rank(s_ref, len(sig), UP["fp64"], 1e-6)
+    assert metrics.subspace_error(U_ref, host(U), r) <= 1e-6
+    assert metrics.mean_projection_error(S, host(U)) <= eps_star ** 2
