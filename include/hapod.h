@@ -55,7 +55,9 @@ typedef enum {
   HAPOD_E_NUMERIC = 5,   /* non-finite Gram diagonal (NaN/Inf in the input)                 */
   HAPOD_E_STATE = 6,     /* plan not run yet / node has no result                           */
   HAPOD_E_CALLBACK = 7,  /* the leaf provider returned a non-zero code                      */
-  HAPOD_E_UNSUPPORTED = 8 /* size beyond a kernel's documented limit                        */
+  HAPOD_E_UNSUPPORTED = 8 /* size beyond a kernel's documented limit, or a node wider than
+                             the Jacobi limit whose Krylov eigensolve (at most 768 steps) did
+                             not resolve every eigenvalue its truncation needs             */
 } hapod_status;
 
 typedef enum {
@@ -169,8 +171,11 @@ typedef struct {
   int64_t mem_cap_bytes;           /* 0: no cap; else device bytes the plan may hold       */
   const double* node_eps_override; /* host, num_nodes values or NULL; an entry >= 0
                                       replaces the Thm. 3.5 tolerance of that node         */
-  int32_t jacobi_max;              /* 0: default (256); nodes with more input columns take
-                                      the Lanczos eigensolver                              */
+  int32_t jacobi_max;              /* k > 0: nodes with at most k input columns (k <= 1024)
+                                      take the Jacobi eigensolver, wider ones Lanczos.
+                                      0: automatic -- Jacobi up to 128 columns; 129..256
+                                      Jacobi when the launch group has 3 or more such
+                                      nodes, else Lanczos; Lanczos above 256          */
   int32_t leaf_wave;               /* 0: all leaves of a level in one launch group; k > 0:
                                       at most k leaves per group, so the provider needs at
                                       most k leaves resident at a time                     */

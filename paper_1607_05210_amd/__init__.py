@@ -244,9 +244,13 @@ class Plan:
                                      acc.ctypes.data_as(_pi64)), "hapod_plan_query")
         return eps, lev, acc
 
-    def run(self, leaves, stream=None):
+    def run(self, leaves, stream=None, hold=True):
         """``leaves``: dict leaf id -> column-major device tensor, or a
-        callable leaf id -> tensor (called once per leaf, in level order)."""
+        callable leaf id -> tensor (called once per leaf, in level order, just
+        before the launch group that first reads it).  With ``hold`` every
+        tensor handed over stays referenced until the run returns; a provider
+        that streams more data than fits passes ``hold=False`` and keeps each
+        tensor alive itself until the next group's leaves are requested."""
         elem = _elem(self.prec)
         held = {}
         err = []
@@ -255,7 +259,8 @@ class Plan:
             try:
                 t = leaves(leaf) if callable(leaves) else leaves[leaf]
                 p, n, m, ldt = _mat(t, f"leaf {leaf}", elem)
-                held[leaf] = t
+                if hold:
+                    held[leaf] = t
                 ptr[0] = p.value
                 ld[0] = ldt
                 return 0

@@ -116,6 +116,18 @@ class Pool {
   }
   void set_cap(size_t c) { cap_ = c; }
   size_t held() const { return held_; }
+  // bytes held in freed blocks, ready for reuse
+  size_t cached() const {
+    size_t c = 0;
+    for (auto& kv : free_) c += kv.first * kv.second.size();
+    return c;
+  }
+  // bytes the cap still allows (cached blocks count as available)
+  size_t room() const {
+    if (!cap_) return SIZE_MAX;
+    const size_t used = held_ - cached();
+    return cap_ > used ? cap_ - used : 0;
+  }
 
  private:
   std::map<size_t, std::vector<void*>> free_;
@@ -148,6 +160,12 @@ struct PodJob {
   double eps = 0.0;
   bool root = false;    // lift with Lambda^{-1/2}
   void* out = nullptr;  // n x m capacity; element (r, c) at out[c * ocs + blk_off(r, obs)]
+  // out == nullptr and alloc_rows > 0: the batch allocates the output from the
+  // pool once the rank N is known -- alloc_rows x N plain column-major
+  // (ocs = alloc_rows, rows past n zero-filled) when plain_out, else n x N
+  // row-block tiled (ocs = 128, obs = 128 N)
+  int64_t alloc_rows = 0;
+  bool plain_out = false;
   int64_t ocs = 0;
   int64_t obs = kRowBlock;
   // outputs (host, after sync)
@@ -156,6 +174,11 @@ struct PodJob {
   double info[6] = {0, 0, 0, 0, 0, 0};
   int32_t sweeps = 0;
   bool wide = false;
+  bool wide_full = false;      // Lanczos run to m steps: every eigenpair, as Jacobi gives
+  bool wide_exhausted = true;  // wide eigensolve reached the Gram's rounding level
+  double wide_missing = 0.0;   // energy of unconverged Ritz values above it
+  double wide_unresolved = 0.0;  // trace(G) minus the returned eigenvalues
+  double wide_slack = 0.0;       // rounding allowance of that difference
 };
 
 struct PhaseTimes {
@@ -182,6 +205,15 @@ int pick_chunks(int64_t n, int pairs, int target_items, int64_t min_rows) {
   return (int)std::max<int64_t>(1, std::min(want, maxc));
 }
 
+// Eigensolver choice.  jacobi_max > 0: Jacobi up to that width, Lanczos
+// above.  jacobi_max <= 0 (automatic): Jacobi in LDS up to kJacobiLdsMax;
+// between that and kAutoJacobiMax the global-memory Jacobi when the batch has
+// enough such nodes to run side by side (one workgroup each), else Lanczos,
+// whose cost grows with m instead of m^3 on one workgroup; Lanczos above.
+constexpr int kAutoJacobiMax = 256;
+constexpr int64_t kLiftTargetItems = 2048;  // lift workgroups per launch to aim for
+constexpr int kMinJacobiBatch = 3;
+
 hapod_status run_pod_batch(hapod_precision prec, std::vector<PodJob>& jobs, int policy_small, int policy_wide,
                            int jacobi_max, Pool& pool, hipStream_t stream, PhaseTimes* times) {
   const int compute = compute_mode(prec);
@@ -192,7 +224,7 @@ hapod_status run_pod_batch(hapod_precision prec, std::vector<PodJob>& jobs, int 
 
   // ---- sizes & scratch layout ---------------------------------------------
   struct Lay {
-    size_t cols, rbs, crows, cols2, rbs2, crows2, G, partial, lam, V, B, sigma, rank, info, jwork, vwork, sweeps;
+    size_t cols, rbs, crows, cols2, rbs2, crows2, G, partial, lam, V, B, B32, sigma, rank, info, jwork, vwork, sweeps;
     bool presplit;
     int ntiles, pairs, nchunks;
     int64_t chunk_rows;
@@ -208,11 +240,27 @@ hapod_status run_pod_batch(hapod_precision prec, std::vector<PodJob>& jobs, int 
     sum_pairs += nt * (nt + 1) / 2;
   }
   const int target_items = std::max(2048, sum_pairs);
+  int mid_nodes = 0;
+  for (auto& j : jobs) mid_nodes += (j.m > kJacobiLdsMax && j.m <= kAutoJacobiMax) ? 1 : 0;
+  // split twins take as much memory as their inputs: give them at most a
+  // third of what the device has free (and of what the plan's cap leaves);
+  // nodes beyond that split in registers instead
+  size_t twin_bytes = 0, twin_budget = 0;
+  if (compute == 2) {
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) == hipSuccess) twin_budget = (free_b + pool.cached()) / 3;
+    const size_t room = pool.room();
+    if (room < twin_budget) twin_budget = room / 3;
+  }
   for (int i = 0; i < nj; ++i) {
     PodJob& j = jobs[i];
     Lay& L = lay[i];
     const int64_t m = j.m;
-    j.wide = (m > jacobi_max);
+    j.wide = (jacobi_max > 0) ? (m > jacobi_max)
+                              : (m > kAutoJacobiMax || (m > kJacobiLdsMax && mid_nodes < kMinJacobiBatch));
+    // a node taken from Jacobi only for speed keeps Jacobi's result: all
+    // eigenpairs (a full Lanczos run) and the same truncation policy
+    j.wide_full = j.wide && jacobi_max <= 0 && m <= kAutoJacobiMax;
     L.ntiles = (int)((m + kGramTile - 1) / kGramTile);
     L.pairs = L.ntiles * (L.ntiles + 1) / 2;
     const int per_node_target = std::max(1, (int)((int64_t)target_items * L.pairs / std::max(sum_pairs, 1)));
@@ -232,7 +280,9 @@ hapod_status run_pod_batch(hapod_precision prec, std::vector<PodJob>& jobs, int 
     L.crows = take(sizeof(int64_t) * std::max<int64_t>(m, 1));
     // split-BF16: nodes with several column tiles get a split twin of their
     // input once, instead of splitting every element in each tile that reads it
-    L.presplit = (compute == 2 && m >= kPresplitMinCols && j.n > 0);
+    L.presplit = (compute == 2 && m >= kPresplitMinCols && j.n > 0 &&
+                  twin_bytes + tiled_bytes(j.n, m, 4) <= twin_budget);
+    if (L.presplit) twin_bytes += tiled_bytes(j.n, m, 4);
     L.cols2 = L.presplit ? take(sizeof(void*) * m) : 0;
     L.rbs2 = L.presplit ? take(sizeof(int64_t) * m) : 0;
     L.crows2 = L.presplit ? take(sizeof(int64_t) * m) : 0;
@@ -240,7 +290,10 @@ hapod_status run_pod_batch(hapod_precision prec, std::vector<PodJob>& jobs, int 
     L.partial = (L.nchunks > 1) ? take(sizeof(double) * (size_t)L.pairs * L.nchunks * kGramTile * kGramTile) : 0;
     L.lam = take(sizeof(double) * std::max<int64_t>(m, 1));
     L.V = take(sizeof(double) * m * m);
-    L.B = take(sizeof(double) * m * m);
+    // lift operand rows padded to a multiple of 4 entries: 16-byte aligned runs
+    const int64_t ldb = std::max<int64_t>((m + 3) / 4 * 4, 4);
+    L.B = take(sizeof(double) * m * ldb);
+    L.B32 = (compute != 0) ? take(sizeof(float) * m * ldb) : 0;
     L.sigma = take(sizeof(double) * std::max<int64_t>(m, 1));
     L.rank = take(sizeof(int64_t));
     L.info = take(sizeof(double) * 8);
@@ -340,15 +393,16 @@ hapod_status run_pod_batch(hapod_precision prec, std::vector<PodJob>& jobs, int 
     t.lambda = (double*)(scratch + L.lam);
     t.V = (double*)(scratch + L.V);
     t.B = (double*)(scratch + L.B);
+    t.B32 = (compute != 0) ? (float*)(scratch + L.B32) : nullptr;
     t.sigma = (double*)(scratch + L.sigma);
     t.rank = (int64_t*)(scratch + L.rank);
     t.info = (double*)(scratch + L.info);
     t.eps2 = j.eps * j.eps;
     t.floor_abs = 0.0;
     t.ldv = m;
-    t.ldb = std::max<int64_t>(m, 1);
+    t.ldb = std::max<int64_t>((m + 3) / 4 * 4, 4);
     t.m = (int32_t)m;
-    t.policy = j.wide ? policy_wide : policy_small;
+    t.policy = (j.wide && !j.wide_full) ? policy_wide : policy_small;
     t.root = j.root ? 1 : 0;
   }
 
@@ -416,11 +470,47 @@ hapod_status run_pod_batch(hapod_precision prec, std::vector<PodJob>& jobs, int 
     WideResult wr;
     HAPOD_TRY(wide_eigh(gnodes[i].G, jobs[i].m, jobs[i].m, (double*)(scratch + lay[i].lam),
                         (double*)(scratch + lay[i].V), jobs[i].m, u_p, &pool_alloc_cb, &pool_free_cb,
-                        &pool, stream, &wr));
+                        &pool, stream, &wr, jobs[i].wide_full));
     // eigenvalues beyond the computed block are set to zero by wide_eigh;
     // the floor of the truncation is the Gram's rounding level
     tnodes[i].floor_abs = wr.floor_abs;
     jobs[i].sweeps = wr.iterations;
+    jobs[i].wide_exhausted = wr.exhausted;
+    jobs[i].wide_missing = wr.missing;
+    jobs[i].wide_unresolved = wr.unresolved;
+    // the difference trace - sum(theta) carries the rounding of every
+    // eigenvalue and of the diagonal: allow 16 (block + sqrt(m)) u_p |trace|
+    jobs[i].wide_slack = 16.0 * (wr.block + std::sqrt((double)jobs[i].m)) * u_p * std::fabs(wr.trace);
+    if (jobs[i].wide_full && wr.unresolved > jobs[i].wide_slack) {
+      // the Krylov space broke down before spanning the matrix (an exact
+      // multiplicity): fall back to the dense Jacobi eigensolver
+      const int m = (int)jobs[i].m;
+      void *jw = nullptr, *vw = nullptr, *de = nullptr;
+      HAPOD_TRY(pool.alloc(sizeof(double) * jacobi_work_doubles(m), &jw));
+      hapod_status s = pool.alloc(sizeof(double) * jacobi_vwork_doubles(m), &vw);
+      if (s == HAPOD_OK) s = pool.alloc(sizeof(EigNode), &de);
+      if (s == HAPOD_OK) {
+        EigNode e{};
+        e.G = gnodes[i].G;
+        e.work = (double*)jw;
+        e.Vwork = (double*)vw;
+        e.lambda = (double*)(scratch + lay[i].lam);
+        e.V = (double*)(scratch + lay[i].V);
+        e.ldg = m;
+        e.ldv = m;
+        e.m = m;
+        s = hipMemcpyAsync(de, &e, sizeof(e), hipMemcpyHostToDevice, stream) == hipSuccess ? HAPOD_OK : HAPOD_E_DEVICE;
+        if (s == HAPOD_OK) s = launch_jacobi((const EigNode*)de, 1, m, stream);
+        if (s == HAPOD_OK && hipStreamSynchronize(stream) != hipSuccess) s = HAPOD_E_DEVICE;
+      }
+      if (de) pool.free(de);
+      if (vw) pool.free(vw);
+      pool.free(jw);
+      if (s != HAPOD_OK) return s;
+      jobs[i].wide_unresolved = 0.0;
+      jobs[i].wide_missing = 0.0;
+      jobs[i].wide_exhausted = true;
+    }
   }
   if (times && ev.ok) HAPOD_HIP(hipEventRecord(ev.e[2], stream));
   // wide nodes changed floor_abs on the host: refresh their descriptors
@@ -436,8 +526,31 @@ hapod_status run_pod_batch(hapod_precision prec, std::vector<PodJob>& jobs, int 
   HAPOD_HIP(hipStreamSynchronize(stream));
   for (int i = 0; i < nj; ++i)
     HAPOD_HIP(hipMemcpy(&ranks[i], scratch + lay[i].rank, sizeof(int64_t), hipMemcpyDeviceToHost));
+  // outputs sized by the ranks
+  for (int i = 0; i < nj; ++i) {
+    PodJob& j = jobs[i];
+    if (j.out || j.alloc_rows <= 0 || j.m <= 0 || ranks[i] <= 0) continue;
+    const int64_t N = ranks[i];
+    const size_t bytes = j.plain_out ? (size_t)j.alloc_rows * N * eb : tiled_bytes(j.n, N, eb);
+    HAPOD_TRY(pool.alloc(bytes, &j.out));
+    if (j.plain_out) {
+      j.ocs = j.alloc_rows;
+      j.obs = kRowBlock;
+      if (j.n < j.alloc_rows) HAPOD_TRY(launch_zero_bytes(j.out, bytes, stream));
+    } else {
+      j.ocs = kRowBlock;
+      j.obs = tiled_rbs(N);
+    }
+  }
   std::vector<LiftNode> lnodes;
   int lift_items = 0;
+  // several row tiles per workgroup when there are many: the column table
+  // and the node lookup are then paid once per group of tiles
+  int64_t lift_tiles = 0;
+  for (int i = 0; i < nj; ++i)
+    if (jobs[i].m > 0 && jobs[i].n > 0 && ranks[i] > 0)
+      lift_tiles += ((jobs[i].n + kLiftTileM - 1) / kLiftTileM) * ((ranks[i] + kLiftTileN - 1) / kLiftTileN);
+  const int rt_per = (int)std::max<int64_t>(1, std::min<int64_t>(16, lift_tiles / kLiftTargetItems));
   for (int i = 0; i < nj; ++i) {
     const PodJob& j = jobs[i];
     if (j.m <= 0 || j.n <= 0 || ranks[i] <= 0) continue;
@@ -446,6 +559,7 @@ hapod_status run_pod_batch(hapod_precision prec, std::vector<PodJob>& jobs, int 
     l.rbs = (const int64_t*)(scratch + lay[i].rbs);
     l.crows = (const int64_t*)(scratch + lay[i].crows);
     l.B = tnodes[i].B;
+    l.B32 = tnodes[i].B32;
     l.rank = tnodes[i].rank;
     l.out = j.out;
     l.n = j.n;
@@ -456,7 +570,8 @@ hapod_status run_pod_batch(hapod_precision prec, std::vector<PodJob>& jobs, int 
     l.row_tiles = (int32_t)((j.n + kLiftTileM - 1) / kLiftTileM);
     l.col_tiles = (int32_t)((ranks[i] + kLiftTileN - 1) / kLiftTileN);
     l.item_base = lift_items;
-    lift_items += l.row_tiles * l.col_tiles;
+    l.rt_per = rt_per;
+    lift_items += ((l.row_tiles + rt_per - 1) / rt_per) * l.col_tiles;
     lnodes.push_back(l);
   }
   char* dlift = nullptr;
@@ -490,6 +605,15 @@ hapod_status run_pod_batch(hapod_precision prec, std::vector<PodJob>& jobs, int 
       HAPOD_HIP(hipMemcpy(j.sigma.data(), scratch + lay[i].sigma, sizeof(double) * j.rank, hipMemcpyDeviceToHost));
     if (!j.wide && j.m > 0)
       HAPOD_HIP(hipMemcpy(&j.sweeps, scratch + lay[i].sweeps, sizeof(int32_t), hipMemcpyDeviceToHost));
+    // a wide node's truncation is trusted only if the eigenpairs it did not
+    // get cannot hold more than the budget eps^2 (Def. 2.5) allows
+    if (j.wide && (!j.wide_exhausted || j.info[0] + j.wide_missing > j.eps * j.eps ||
+                   j.info[0] + j.wide_unresolved > j.eps * j.eps + j.wide_slack)) {
+      set_error("wide eigensolver: " + std::to_string(j.sweeps) + " Krylov steps on an m = " +
+                std::to_string(j.m) + " Gram did not resolve every eigenvalue the truncation needs" +
+                (j.wide_exhausted ? " (unconverged energy above the budget)" : " (step limit reached)"));
+      return HAPOD_E_UNSUPPORTED;
+    }
   }
   if (times && ev.ok) {
     float a = 0;
@@ -721,7 +845,7 @@ hapod_status hapod_run(hapod_plan_t P, hapod_leaf_fn get_leaf, void* user, void*
   const hapod_precision prec = P->opts.prec;
   const int eb = elem_bytes(prec);
   const int32_t nn = P->num_nodes;
-  const int jmax = P->opts.jacobi_max > 0 ? std::min<int>(P->opts.jacobi_max, kJacobiMax) : 256;
+  const int jmax = P->opts.jacobi_max > 0 ? std::min<int>(P->opts.jacobi_max, kJacobiMax) : 0;
   const int wave = P->opts.leaf_wave > 0 ? P->opts.leaf_wave : INT32_MAX;
   P->has_result = false;
   if (P->root_U) {
@@ -854,24 +978,18 @@ hapod_status hapod_run(hapod_plan_t P, hapod_leaf_fn get_leaf, void* user, void*
         j.eps = P->eps[a];
         j.root = (a == P->root);
         // the root's modes go out plain column-major with n rows; every other
-        // node's scaled modes stay in a row-block-tiled buffer of its own rows
-        j.ocs = j.root ? P->n : kRowBlock;
-        j.obs = j.root ? kRowBlock : tiled_rbs(j.m);
-        if (j.m > 0) {
-          const size_t bytes = j.root ? (size_t)P->n * j.m * eb : tiled_bytes(j.n, j.m, eb);
-          s = P->pool.alloc(bytes, &j.out);
-          if (s == HAPOD_OK && j.root && j.n < P->n) s = launch_zero_bytes(j.out, bytes, stream);
-          if (s != HAPOD_OK) {
-            release_all();
-            return s;
-          }
-          out_buf[a] = j.out;
-        }
+        // node's scaled modes stay in a row-block-tiled buffer of its own rows;
+        // both are allocated once the rank is known
+        j.alloc_rows = j.root ? P->n : j.n;
+        j.plain_out = j.root;
         jobs.push_back(std::move(j));
         job_node.push_back(a);
       }
       hapod_status s = run_pod_batch(prec, jobs, 0, 1, jmax, P->pool, stream, &lt);
       if (s != HAPOD_OK) {
+        (void)hipStreamSynchronize(stream);
+        for (auto& j : jobs)
+          if (j.out) P->pool.free(j.out);
         release_all();
         return s;
       }
@@ -883,13 +1001,14 @@ hapod_status hapod_run(hapod_plan_t P, hapod_leaf_fn get_leaf, void* user, void*
         P->lam1[a] = j.info[1];
         P->lam_min[a] = j.info[2];
         P->n_neg[a] = (int64_t)j.info[3];
+        out_buf[a] = j.out;
         if (a == P->root) {
           out_cols[a] = column_table(j.out, P->n, j.rank, eb);
           out_rbs[a].assign((size_t)j.rank, kRowBlock);
           out_rows[a].assign((size_t)j.rank, P->n);
         } else {
           out_cols[a] = tiled_table(j.out, j.rank, eb);
-          out_rbs[a].assign((size_t)j.rank, tiled_rbs(j.m));
+          out_rbs[a].assign((size_t)j.rank, tiled_rbs(j.rank));
           out_rows[a].assign((size_t)j.rank, j.n);
         }
         if (j.rank == 0 && out_buf[a]) {
@@ -1275,13 +1394,15 @@ hapod_status hapod_lift(hapod_precision prec, int64_t n, int64_t m, int64_t N, c
   const int eb = elem_bytes(prec);
   Pool& pool = step_pool();
   auto cols = column_table(S, lds, m, eb);
-  void *dcols = nullptr, *dB = nullptr, *drank = nullptr, *dn = nullptr, *drbs = nullptr, *drows = nullptr;
+  void *dcols = nullptr, *dB = nullptr, *dB32 = nullptr, *drank = nullptr, *dn = nullptr, *drbs = nullptr,
+       *drows = nullptr;
   HAPOD_TRY(pool.alloc(sizeof(void*) * std::max<int64_t>(m, 1), &dcols));
   HAPOD_TRY(pool.alloc(sizeof(int64_t) * std::max<int64_t>(m, 1), &drbs));
   HAPOD_TRY(pool.alloc(sizeof(int64_t) * std::max<int64_t>(m, 1), &drows));
   HAPOD_TRY(launch_fill_i64((int64_t*)drbs, kRowBlock, m, stream));
   HAPOD_TRY(launch_fill_i64((int64_t*)drows, n, m, stream));
   HAPOD_TRY(pool.alloc(sizeof(double) * std::max<int64_t>(m * N, 1), &dB));
+  if (prec != HAPOD_FP64) HAPOD_TRY(pool.alloc(sizeof(float) * std::max<int64_t>(m * N, 1), &dB32));
   HAPOD_TRY(pool.alloc(sizeof(int64_t), &drank));
   HAPOD_TRY(pool.alloc(sizeof(LiftNode), &dn));
   LiftNode l{};
@@ -1289,6 +1410,7 @@ hapod_status hapod_lift(hapod_precision prec, int64_t n, int64_t m, int64_t N, c
   l.rbs = (const int64_t*)drbs;
   l.crows = (const int64_t*)drows;
   l.B = (const double*)dB;
+  l.B32 = (const float*)dB32;
   l.rank = (const int64_t*)drank;
   l.out = out;
   l.n = n;
@@ -1311,7 +1433,7 @@ hapod_status hapod_lift(hapod_precision prec, int64_t n, int64_t m, int64_t N, c
       st = HAPOD_E_DEVICE;
       break;
     }
-    st = launch_lift_operand(V, ldv, lambda, m, N, (double*)dB, N, stream);
+    st = launch_lift_operand(V, ldv, lambda, m, N, (double*)dB, (float*)dB32, N, stream);
     if (st != HAPOD_OK) break;
     st = launch_set_scalar_i64((int64_t*)drank, N, stream);
     if (st != HAPOD_OK) break;
@@ -1322,6 +1444,7 @@ hapod_status hapod_lift(hapod_precision prec, int64_t n, int64_t m, int64_t N, c
   pool.free(drbs);
   pool.free(drows);
   pool.free(dB);
+  if (dB32) pool.free(dB32);
   pool.free(drank);
   pool.free(dn);
   return st;
@@ -1343,10 +1466,12 @@ hapod_status hapod_reorth(hapod_precision prec, int64_t n, int64_t N, void* U, i
   hipStream_t stream = (hipStream_t)stream_;
   const int eb = elem_bytes(prec);
   Pool& pool = step_pool();
-  void *W = nullptr, *Rinv = nullptr, *tmp = nullptr, *dcols = nullptr, *dn = nullptr, *drank = nullptr,
+  void *W = nullptr, *Rinv = nullptr, *Rinv32 = nullptr, *tmp = nullptr, *dcols = nullptr, *dn = nullptr,
+       *drank = nullptr,
        *dbad = nullptr, *drbs = nullptr, *drows = nullptr;
   HAPOD_TRY(pool.alloc(sizeof(double) * N * N, &W));
   HAPOD_TRY(pool.alloc(sizeof(double) * N * N, &Rinv));
+  HAPOD_TRY(pool.alloc(sizeof(float) * N * N, &Rinv32));
   HAPOD_TRY(pool.alloc((size_t)n * N * eb, &tmp));
   HAPOD_TRY(pool.alloc(sizeof(void*) * N, &dcols));
   HAPOD_TRY(pool.alloc(sizeof(LiftNode), &dn));
@@ -1370,6 +1495,11 @@ hapod_status hapod_reorth(hapod_precision prec, int64_t n, int64_t N, void* U, i
     l.rbs = (const int64_t*)drbs;
     l.crows = (const int64_t*)drows;
     l.B = (const double*)Rinv;
+    l.B32 = (const float*)Rinv32;
+    if (prec != HAPOD_FP64) {
+      st = launch_to_f32((const double*)Rinv, (float*)Rinv32, N * N, stream);
+      if (st != HAPOD_OK) break;
+    }
     l.rank = (const int64_t*)drank;
     l.out = tmp;
     l.n = n;
@@ -1401,7 +1531,7 @@ hapod_status hapod_reorth(hapod_precision prec, int64_t n, int64_t N, void* U, i
   }
   (void)hipStreamSynchronize(stream);
   if (bad) *bad = total_bad;
-  for (void* p : {W, Rinv, tmp, dcols, dn, drank, dbad, drbs, drows}) pool.free(p);
+  for (void* p : {W, Rinv, Rinv32, tmp, dcols, dn, drank, dbad, drbs, drows}) pool.free(p);
   return st;
 }
 
@@ -1439,7 +1569,7 @@ hapod_status hapod_node_pod(hapod_precision prec, int64_t n, int64_t m, const vo
   jobs[0].out = out;
   jobs[0].ocs = ldo;
   jobs[0].obs = kRowBlock;
-  HAPOD_TRY(run_pod_batch(prec, jobs, 0, 1, 256, step_pool(), stream, nullptr));
+  HAPOD_TRY(run_pod_batch(prec, jobs, 0, 1, 0, step_pool(), stream, nullptr));
   *rank = jobs[0].rank;
   if (sigma && jobs[0].rank > 0) std::memcpy(sigma, jobs[0].sigma.data(), sizeof(double) * jobs[0].rank);
   return HAPOD_OK;

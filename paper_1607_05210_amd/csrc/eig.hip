@@ -24,7 +24,8 @@
 namespace hapod {
 namespace {
 
-constexpr int kThreads = 256;
+constexpr int kThreads = 256;         // LDS variant (m <= 128)
+constexpr int kThreadsGlobal = 1024;  // global variant: more loads in flight per round
 constexpr int kMaxSweeps = 60;
 constexpr double kTolRel = 1e-14;
 
@@ -194,11 +195,11 @@ __device__ void jacobi_body(const EigNode& nd, Store st, double* cs, double* sn,
   if (tid == 0 && nd.sweeps) *nd.sweeps = executed;
 }
 
-__global__ __launch_bounds__(kThreads) void jacobi_global_kernel(const EigNode* __restrict__ nodes) {
+__global__ __launch_bounds__(kThreadsGlobal) void jacobi_global_kernel(const EigNode* __restrict__ nodes) {
   __shared__ double cs[kJacobiMax / 2], sn[kJacobiMax / 2], tn[kJacobiMax / 2];
   __shared__ int lab0[kJacobiMax], lab1[kJacobiMax];
   __shared__ int nrot;
-  __shared__ double red[kThreads];
+  __shared__ double red[kThreadsGlobal];
   const EigNode nd = nodes[blockIdx.x];
   if (nd.m <= 0) return;
   const int m2 = nd.m + (nd.m & 1);
@@ -252,7 +253,7 @@ hapod_status launch_jacobi(const EigNode* d_nodes, int num_nodes, int max_m, hip
     }
     hipLaunchKernelGGL(jacobi_lds_kernel, dim3(num_nodes), dim3(kThreads), lds, stream, d_nodes);
   } else {
-    hipLaunchKernelGGL(jacobi_global_kernel, dim3(num_nodes), dim3(kThreads), 0, stream, d_nodes);
+    hipLaunchKernelGGL(jacobi_global_kernel, dim3(num_nodes), dim3(kThreadsGlobal), 0, stream, d_nodes);
   }
   HAPOD_HIP(hipGetLastError());
   return HAPOD_OK;

@@ -256,11 +256,16 @@ store:
   }
 }
 
-// One workgroup per (node, tile pair): sum the chunk partials in chunk order
-// and write the upper-triangle entries of the tile to both triangles of G.
-__global__ __launch_bounds__(256) void gram_reduce_kernel(const GramNode* __restrict__ nodes,
-                                                          const int32_t* __restrict__ pairs,
-                                                          const int32_t* __restrict__ pair_node) {
+// Chunk partials of one tile pair summed in chunk order (so the result does
+// not depend on scheduling); the upper-triangle entries are written to both
+// triangles of G.  Grid: (pair, slice of kReduceSlice tile entries); each
+// thread keeps kReduceUnroll chunk loads in flight.
+constexpr int kReduceSlice = 256;
+constexpr int kReduceUnroll = 8;
+
+__global__ __launch_bounds__(kReduceSlice) void gram_reduce_kernel(const GramNode* __restrict__ nodes,
+                                                                   const int32_t* __restrict__ pairs,
+                                                                   const int32_t* __restrict__ pair_node) {
   const int node = pair_node[blockIdx.x];
   const int pair = pairs[blockIdx.x];
   const GramNode nd = nodes[node];
@@ -269,16 +274,24 @@ __global__ __launch_bounds__(256) void gram_reduce_kernel(const GramNode* __rest
   int ti = 0, rem = lp, rowlen = nd.ntiles;
   while (rem >= rowlen) { rem -= rowlen; ++ti; --rowlen; }
   const int tj = ti + rem;
-  const double* P = nd.partial + (int64_t)lp * nd.nchunks * (T * T);
-  for (int e = threadIdx.x; e < T * T; e += blockDim.x) {
-    const int i = e & (T - 1), j = e / T;
-    const int row = ti * T + i, col = tj * T + j;
-    if (row >= nd.m || col >= nd.m || row > col) continue;
-    double s = 0.0;
-    for (int c = 0; c < nd.nchunks; ++c) s += P[(int64_t)c * (T * T) + j * T + i];
-    nd.G[(int64_t)col * nd.ldg + row] = s;
-    nd.G[(int64_t)row * nd.ldg + col] = s;
+  const int e = blockIdx.y * kReduceSlice + threadIdx.x;
+  const int i = e & (T - 1), j = e / T;
+  const int row = ti * T + i, col = tj * T + j;
+  if (row >= nd.m || col >= nd.m || row > col) return;
+  const double* P = nd.partial + (int64_t)lp * nd.nchunks * (T * T) + e;
+  const int nc = nd.nchunks;
+  double s = 0.0;
+  int c = 0;
+  for (; c + kReduceUnroll <= nc; c += kReduceUnroll) {
+    double v[kReduceUnroll];
+#pragma unroll
+    for (int u = 0; u < kReduceUnroll; ++u) v[u] = P[(int64_t)(c + u) * (T * T)];
+#pragma unroll
+    for (int u = 0; u < kReduceUnroll; ++u) s += v[u];
   }
+  for (; c < nc; ++c) s += P[(int64_t)c * (T * T)];
+  nd.G[(int64_t)col * nd.ldg + row] = s;
+  nd.G[(int64_t)row * nd.ldg + col] = s;
 }
 
 template <int C>
@@ -307,8 +320,8 @@ hapod_status launch_gram(int compute, const GramNode* d_nodes, const GramItem* d
     default: set_error("launch_gram: unknown compute mode"); return HAPOD_E_INVALID;
   }
   if (num_reduce > 0) {
-    hipLaunchKernelGGL(gram_reduce_kernel, dim3(num_reduce), dim3(256), 0, stream, d_nodes,
-                       d_reduce_pairs, d_reduce_node);
+    hipLaunchKernelGGL(gram_reduce_kernel, dim3(num_reduce, (T * T) / kReduceSlice), dim3(kReduceSlice), 0,
+                       stream, d_nodes, d_reduce_pairs, d_reduce_node);
     HAPOD_HIP(hipGetLastError());
   }
   return HAPOD_OK;

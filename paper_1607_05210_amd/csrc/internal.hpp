@@ -108,6 +108,8 @@ struct TruncNode {
   const double* lambda;   // m, descending
   const double* V;        // m x m, ld ldv (eigenvectors)
   double* B;              // lift operand, row-major m x ldb
+  float* B32;             // the same in FP32 (may be null): the FP32 and
+                          // split-BF16 lifts read this one
   double* sigma;          // m outputs (first N valid)
   int64_t* rank;          // 1 output
   double* info;           // 6 outputs: tail(N), lambda1, lambda_min, n_neg, theta, rank_clamp
@@ -121,9 +123,12 @@ struct TruncNode {
   int32_t pad;
 };
 hapod_status launch_truncate(const TruncNode* d_nodes, int num_nodes, hipStream_t stream);
-// B[k * ldb + n] = V[k][n] (lambda == nullptr) or V[k][n] / sqrt(lambda[n])
+// B[k * ldb + n] = V[k][n] (lambda == nullptr) or V[k][n] / sqrt(lambda[n]);
+// B32 (may be null) gets the same values rounded to FP32
 hapod_status launch_lift_operand(const double* V, int64_t ldv, const double* lambda, int64_t m, int64_t N,
-                                 double* B, int64_t ldb, hipStream_t stream);
+                                 double* B, float* B32, int64_t ldb, hipStream_t stream);
+// dst[i] = (float)src[i], i < count
+hapod_status launch_to_f32(const double* src, float* dst, int64_t count, hipStream_t stream);
 
 // ---- batched lift -----------------------------------------------------------
 // out = S * B[:, :N] where S is given by column pointers (m columns, n rows)
@@ -134,7 +139,8 @@ struct LiftNode {
   const void* const* cols;
   const int64_t* rbs;
   const int64_t* crows;  // rows held by each column; rows past it read as 0
-  const double* B;
+  const double* B;       // FP64 lift (compute 0): row-major, ldb
+  const float* B32;      // FP32 and split-BF16 lifts: the same operand in FP32
   const int64_t* rank;   // device pointer to N
   void* out;             // element (r, c) at out[c * ocs + blk_off(r, obs)]
   int64_t n;
@@ -145,6 +151,9 @@ struct LiftNode {
   int32_t row_tiles;
   int32_t col_tiles;     // worst case ceil(maxN / TN)
   int32_t item_base;
+  int32_t rt_per;        // row tiles per work item (0 or 1: one); the node's
+                         // items are ceil(row_tiles / rt_per) x col_tiles
+  int32_t pad;
 };
 // compute as for launch_gram (0, 1, 2); output storage = input storage
 hapod_status launch_lift(int compute, const LiftNode* d_nodes, int num_nodes,

@@ -3,10 +3,19 @@
 // N (the node's rank) read from device memory; tiles beyond N retire at once.
 //
 // Work item = (node, 128-row tile, 128-column tile); four wavefronts per
-// workgroup, each a 64 x 64 sub-tile of 16 x 16 MFMA blocks.  The MFMA rows
-// are snapshot rows (16 consecutive lanes read 16 consecutive doubles of one
-// column: coalesced), the reduction index is the snapshot column, and the
-// B operand is read along its rows (again 16 consecutive elements).
+// workgroup, each a 64 x 64 sub-tile held as 4 x 4 blocks of 16 x 16 MFMA
+// accumulators.  The MFMA row index is the snapshot row and the reduction
+// index the snapshot column.  Rows and output columns are permuted inside the
+// wavefront's sub-tile so that each lane reads contiguous runs: MFMA row i of
+// block a is sub-tile row 4 i + a (lane i loads rows 4 i .. 4 i + 3 of one
+// column in one vector load), and MFMA column j of block b is sub-tile column
+// 4 j + b (a run of 4 consecutive entries of a row of B).  The store undoes
+// both permutations.
+//
+// The column table (pointer, row-block stride, rows held) of the next 256
+// reduction indices is staged in LDS, so the data loads never wait on a
+// pointer load; data loads are double-buffered in registers: one batch of
+// reduction steps is fetched while the previous one runs on the matrix cores.
 #include "internal.hpp"
 #include "mfma.hpp"
 
@@ -14,36 +23,93 @@ namespace hapod {
 namespace {
 
 constexpr int TM = kLiftTileM, TN = kLiftTileN, WT = 64, NB = WT / 16;
+constexpr int KT = 256;  // reduction indices per LDS column-table chunk (= threads)
 
 template <int C> struct LiftTraits;
-template <> struct LiftTraits<0> { using Elem = double; using Acc = d4; static constexpr int KS = 4; };
-template <> struct LiftTraits<1> { using Elem = float; using Acc = f4; static constexpr int KS = 4; };
-template <> struct LiftTraits<2> { using Elem = float; using Acc = f4; static constexpr int KS = 32; };
+template <> struct LiftTraits<0> { using Elem = double; using Acc = d4; };
+template <> struct LiftTraits<1> { using Elem = float; using Acc = f4; };
+template <> struct LiftTraits<2> { using Elem = float; using Acc = f4; };
+
+// out[t] = p[t] for t < avail (at most 4), else 0; one vector load when the
+// run is whole and 16-byte aligned.
+__device__ __forceinline__ void run4(const double* p, int64_t avail, double (&out)[4]) {
+  if (avail >= 4 && (((uintptr_t)p & 15u) == 0)) {
+    const dv2 x = *(gptr<dv2>)as_global(p);
+    const dv2 y = *(gptr<dv2>)as_global(p + 2);
+    out[0] = x[0]; out[1] = x[1]; out[2] = y[0]; out[3] = y[1];
+  } else {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) out[t] = (t < avail) ? p[t] : 0.0;
+  }
+}
+__device__ __forceinline__ void run4(const float* p, int64_t avail, float (&out)[4]) {
+  if (avail >= 4 && (((uintptr_t)p & 15u) == 0)) {
+    const fv4 x = *(gptr<fv4>)as_global(p);
+    out[0] = x[0]; out[1] = x[1]; out[2] = x[2]; out[3] = x[3];
+  } else {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) out[t] = (t < avail) ? p[t] : 0.f;
+  }
+}
 
 template <int C>
 __global__ __launch_bounds__(256) void lift_kernel(const LiftNode* __restrict__ nodes, int num_nodes) {
   using Tr = LiftTraits<C>;
   using Elem = typename Tr::Elem;
   using Acc = typename Tr::Acc;
-  constexpr int KS = Tr::KS;
+  using BElem = Elem;  // the lift operand comes in the storage precision
 
   const int item = xcd_item(blockIdx.x, gridDim.x);
-  int ni = 0;
-  while (ni + 1 < num_nodes && nodes[ni + 1].item_base <= item) ++ni;
-  const LiftNode nd = nodes[ni];
+  // the node whose item range holds this item: last item_base <= item
+  int lo = 0, hi = num_nodes - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (nodes[mid].item_base <= item) lo = mid;
+    else hi = mid - 1;
+  }
+  const LiftNode nd = nodes[lo];
   // column tiles of one row stripe are adjacent: they land on the same XCD
   // and share that stripe of S through its L2
   const int local = item - nd.item_base;
-  const int rt = local / nd.col_tiles, ct = local % nd.col_tiles;
+  const int rg = local / nd.col_tiles, ct = local % nd.col_tiles;
   const int64_t N = *nd.rank;
-  if ((int64_t)ct * TN >= N) return;
+  if ((int64_t)ct * TN >= N) return;  // whole workgroup
+  const int rt_per = max(nd.rt_per, 1);
+  const int rt_begin = rg * rt_per, rt_end = min(rt_begin + rt_per, nd.row_tiles);
+
+  __shared__ const char* tcol[KT];
+  __shared__ int64_t trbs[KT];
+  __shared__ int64_t trows[KT];
 
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int wi = wave >> 1, wj = wave & 1;
   const int li = lane & 15, g = lane >> 4;
-  const int64_t r0 = (int64_t)rt * TM + wi * WT;
   const int64_t n0 = (int64_t)ct * TN + wj * WT;
-  if (r0 >= nd.n || n0 >= N) return;
+  const int64_t nl = n0 + 4 * li;   // first of the lane's 4 output columns
+  const int64_t bavail = N - nl;
+  const BElem* bop;
+  if constexpr (C == 0) bop = nd.B;
+  else bop = nd.B32;
+  const int m = nd.m;
+  auto load_table = [&](int kc) {
+    const int k = kc + (int)threadIdx.x;
+    const bool kv = k < m;
+    tcol[threadIdx.x] = kv ? reinterpret_cast<const char*>(nd.cols[k]) : nullptr;
+    trbs[threadIdx.x] = kv ? nd.rbs[k] : kRowBlock;
+    trows[threadIdx.x] = kv ? nd.crows[k] : 0;
+  };
+  // with at most KT reduction indices the table is loaded once for all tiles
+  const bool one_chunk = (m <= KT);
+  if (one_chunk) {
+    load_table(0);
+    __syncthreads();
+  }
+
+  for (int rt = rt_begin; rt < rt_end; ++rt) {
+  const int64_t r0 = (int64_t)rt * TM + wi * WT;
+  const bool active = (r0 < nd.n) && (n0 < N);
+  const int64_t rl = r0 + 4 * li;   // first of the lane's 4 rows (one row block)
+  const int64_t roff = rl & (kRowBlock - 1), rblk = rl >> 7;
 
   Acc acc[NB][NB];
 #pragma unroll
@@ -51,79 +117,150 @@ __global__ __launch_bounds__(256) void lift_kernel(const LiftNode* __restrict__ 
 #pragma unroll
     for (int b = 0; b < NB; ++b) acc[a][b] = Acc{0, 0, 0, 0};
 
-  const int m = nd.m;
-  for (int k0 = 0; k0 < m; k0 += KS) {
+  for (int kc = 0; kc < m; kc += KT) {
+    if (!one_chunk) {
+      __syncthreads();  // the previous chunk's table is no longer read
+      load_table(kc);
+      __syncthreads();
+    }
+    if (!active) continue;
+    const int kend = min(m, kc + KT);
+    // a lane's run of column k (table slot t): up to 4 rows from row rl
+    auto srun = [&](int t, Elem (&x)[4]) {
+      const int64_t avail = trows[t] - rl;
+      if (avail <= 0) {
+#pragma unroll
+        for (int a = 0; a < 4; ++a) x[a] = Elem(0);
+      } else {
+        run4(reinterpret_cast<const Elem*>(tcol[t]) + rblk * trbs[t] + roff, avail, x);
+      }
+    };
+    auto brun = [&](int k, BElem (&y)[4]) {
+      if (k < kend && bavail > 0) run4(bop + (int64_t)k * nd.ldb + nl, bavail, y);
+      else {
+#pragma unroll
+        for (int b = 0; b < 4; ++b) y[b] = BElem(0);
+      }
+    };
     if constexpr (C == 0 || C == 1) {
-      const int k = k0 + g;
-      const Elem* col = (k < m) ? reinterpret_cast<const Elem*>(nd.cols[k]) : nullptr;
-      const int64_t rbs = (k < m) ? nd.rbs[k] : kRowBlock;
-      const int64_t rows = (k < m) ? nd.crows[k] : 0;
-      Elem va[NB];
-      double vb[NB];
+      // batches of U MFMA steps of 4 reduction indices each
+      constexpr int U = 4, KB = 4 * U;
+      Elem xa[2][U][4];
+      BElem xb[2][U][4];
+      auto load = [&](int kb, Elem (&va)[U][4], BElem (&vb)[U][4]) {
 #pragma unroll
-      for (int a = 0; a < NB; ++a) {
-        const int64_t row = r0 + a * 16 + li;
-        va[a] = (row < rows) ? col[blk_off(row, rbs)] : Elem(0);
-      }
+        for (int t = 0; t < U; ++t) {
+          const int k = kb + 4 * t + g;
+          if (k < kend) srun(k - kc, va[t]);
+          else {
 #pragma unroll
-      for (int b = 0; b < NB; ++b) {
-        const int64_t nn = n0 + b * 16 + li;
-        vb[b] = (k < m && nn < N) ? nd.B[(int64_t)k * nd.ldb + nn] : 0.0;
-      }
-#pragma unroll
-      for (int a = 0; a < NB; ++a)
-#pragma unroll
-        for (int b = 0; b < NB; ++b) {
-          if constexpr (C == 0) acc[a][b] = mfma_f64(va[a], vb[b], acc[a][b]);
-          else acc[a][b] = mfma_f32(va[a], (float)vb[b], acc[a][b]);
+            for (int a = 0; a < 4; ++a) va[t][a] = Elem(0);
+          }
+          brun(k, vb[t]);
         }
-    } else {
-      // split-BF16: lane covers reduction slots 8g..8g+7 of this 32-wide step
-      float xa[NB][8], xb[NB][8];
+      };
+      auto compute = [&](Elem (&va)[U][4], BElem (&vb)[U][4]) {
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const int k = k0 + 8 * g + e;
-        const float* col = (k < m) ? reinterpret_cast<const float*>(nd.cols[k]) : nullptr;
-        const int64_t rbs = (k < m) ? nd.rbs[k] : kRowBlock;
-        const int64_t rows = (k < m) ? nd.crows[k] : 0;
+        for (int t = 0; t < U; ++t)
+#pragma unroll
+          for (int a = 0; a < NB; ++a)
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+              if constexpr (C == 0) acc[a][b] = mfma_f64(va[t][a], vb[t][b], acc[a][b]);
+              else acc[a][b] = mfma_f32(va[t][a], vb[t][b], acc[a][b]);
+            }
+      };
+      load(kc, xa[0], xb[0]);
+      for (int kb = kc; kb < kend; kb += 2 * KB) {
+        load(kb + KB, xa[1], xb[1]);
+        compute(xa[0], xb[0]);
+        if (kb + 2 * KB < kend) load(kb + 2 * KB, xa[0], xb[0]);
+        compute(xa[1], xb[1]);
+      }
+    } else {
+      // split-BF16: lane covers reduction slots 8g..8g+7 of each 32-wide step
+      constexpr int KS = 32;
+      float ya[2][8][4];
+      float yb[2][8][4];
+      auto load = [&](int k0, float (&xa)[8][4], float (&xb)[8][4]) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const int k = k0 + 8 * g + e;
+          if (k < kend) srun(k - kc, xa[e]);
+          else {
+#pragma unroll
+            for (int a = 0; a < 4; ++a) xa[e][a] = 0.f;
+          }
+          brun(k, xb[e]);
+        }
+      };
+      auto compute = [&](float (&xa)[8][4], float (&xb)[8][4]) {
+        bf8 ha[NB], la[NB], hb[NB], lb[NB];
 #pragma unroll
         for (int a = 0; a < NB; ++a) {
-          const int64_t row = r0 + a * 16 + li;
-          xa[a][e] = (row < rows) ? col[blk_off(row, rbs)] : 0.f;
+          float v[8];
+#pragma unroll
+          for (int e = 0; e < 8; ++e) v[e] = xa[e][a];
+          split_bf16x8(v, ha[a], la[a]);
         }
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
-          const int64_t nn = n0 + b * 16 + li;
-          xb[b][e] = (k < m && nn < N) ? (float)nd.B[(int64_t)k * nd.ldb + nn] : 0.f;
+          float v[8];
+#pragma unroll
+          for (int e = 0; e < 8; ++e) v[e] = xb[e][b];
+          split_bf16x8(v, hb[b], lb[b]);
         }
+#pragma unroll
+        for (int a = 0; a < NB; ++a)
+#pragma unroll
+          for (int b = 0; b < NB; ++b) {
+            acc[a][b] = mfma_bf16(la[a], hb[b], acc[a][b]);
+            acc[a][b] = mfma_bf16(ha[a], lb[b], acc[a][b]);
+            acc[a][b] = mfma_bf16(ha[a], hb[b], acc[a][b]);
+          }
+      };
+      load(kc, ya[0], yb[0]);
+      for (int k0 = kc; k0 < kend; k0 += 2 * KS) {
+        load(k0 + KS, ya[1], yb[1]);
+        compute(ya[0], yb[0]);
+        if (k0 + 2 * KS < kend) load(k0 + 2 * KS, ya[0], yb[0]);
+        compute(ya[1], yb[1]);
       }
-      bf8 ha[NB], la[NB], hb[NB], lb[NB];
-#pragma unroll
-      for (int a = 0; a < NB; ++a) split_bf16x8(xa[a], ha[a], la[a]);
-#pragma unroll
-      for (int b = 0; b < NB; ++b) split_bf16x8(xb[b], hb[b], lb[b]);
-#pragma unroll
-      for (int a = 0; a < NB; ++a)
-#pragma unroll
-        for (int b = 0; b < NB; ++b) {
-          acc[a][b] = mfma_bf16(la[a], hb[b], acc[a][b]);
-          acc[a][b] = mfma_bf16(ha[a], lb[b], acc[a][b]);
-          acc[a][b] = mfma_bf16(ha[a], hb[b], acc[a][b]);
-        }
     }
   }
+  if (!active) continue;
 
+  // lane (g, j) holds, for output column n0 + 4 j + b and accumulator
+  // register v, the rows r0 + 4 acc_row + a (a = 0..3): four consecutive
+  // rows, written as one vector store
   Elem* out = reinterpret_cast<Elem*>(nd.out);
 #pragma unroll
-  for (int a = 0; a < NB; ++a)
+  for (int b = 0; b < NB; ++b) {
+    const int64_t col = n0 + 4 * acc_col(lane) + b;
+    if (col >= N) continue;
 #pragma unroll
-    for (int b = 0; b < NB; ++b)
+    for (int v = 0; v < 4; ++v) {
+      const int64_t row = r0 + 4 * acc_row<Acc>(lane, v);
+      Elem* p = out + col * nd.ocs + blk_off(row, nd.obs);
+      Elem x[4];
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int64_t row = r0 + a * 16 + acc_row<Acc>(lane, v);
-        const int64_t col = n0 + b * 16 + acc_col(lane);
-        if (row < nd.n && col < N) out[col * nd.ocs + blk_off(row, nd.obs)] = (Elem)acc[a][b][v];
+      for (int a = 0; a < 4; ++a) x[a] = (Elem)acc[a][b][v];
+      if (row + 4 <= nd.n && (((uintptr_t)p & 15u) == 0)) {
+        if constexpr (C == 0) {
+          __attribute__((address_space(1))) dv2* q = (__attribute__((address_space(1))) dv2*)p;
+          q[0] = dv2{x[0], x[1]};
+          q[1] = dv2{x[2], x[3]};
+        } else {
+          *(__attribute__((address_space(1))) fv4*)p = fv4{x[0], x[1], x[2], x[3]};
+        }
+      } else {
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+          if (row + a < nd.n) p[a] = x[a];
       }
+    }
+  }
+  }  // row tiles
 }
 
 }  // namespace

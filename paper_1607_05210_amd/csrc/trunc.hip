@@ -136,19 +136,34 @@ __global__ __launch_bounds__(kThreads) void truncate_kernel(const TruncNode* __r
     }
   }
   for (int n = tid; n < N; n += kThreads) nd.sigma[n] = sqrt(nd.lambda[n]);
-  // lift operand, row-major B[k * ldb + n]
+  // lift operand, row-major B[k * ldb + n], transposed from V through LDS in
+  // 32 x 32 tiles so that reads of V and writes of B are both coalesced
   if (nd.V == nullptr) return;
-  const int64_t total = (int64_t)m * N;
-  for (int64_t idx = tid; idx < total; idx += kThreads) {
-    const int k = (int)(idx % m), n = (int)(idx / m);
-    double v = nd.V[(int64_t)n * nd.ldv + k];
-    if (nd.root) v /= sqrt(nd.lambda[n]);
-    nd.B[(int64_t)k * nd.ldb + n] = v;
-  }
+  __shared__ double tile[32][33];
+  const int tx = tid & 31, ty = tid >> 5;  // 32 x 8 threads
+  for (int n0 = 0; n0 < N; n0 += 32)
+    for (int k0 = 0; k0 < m; k0 += 32) {
+      const int n = n0 + tx;
+      const double sc = (nd.root && n < N) ? 1.0 / sqrt(nd.lambda[n]) : 1.0;
+      for (int r = ty; r < 32; r += 8) {   // column n0 + r of V, rows k0 .. k0 + 31
+        const int nn = n0 + r, k = k0 + tx;
+        tile[r][tx] = (nn < N && k < m) ? nd.V[(int64_t)nn * nd.ldv + k] : 0.0;
+      }
+      __syncthreads();
+      for (int r = ty; r < 32; r += 8) {   // row k0 + r of B, columns n0 .. n0 + 31
+        const int k = k0 + r;
+        if (k < m && n < N) {
+          const double v = tile[tx][r] * sc;
+          nd.B[(int64_t)k * nd.ldb + n] = v;
+          if (nd.B32) nd.B32[(int64_t)k * nd.ldb + n] = (float)v;
+        }
+      }
+      __syncthreads();
+    }
 }
 
 __global__ void lift_operand_kernel(const double* V, int64_t ldv, const double* lambda, int64_t m,
-                                    int64_t N, double* B, int64_t ldb) {
+                                    int64_t N, double* B, float* B32, int64_t ldb) {
   const int64_t total = m * N;
   for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
        idx += (int64_t)gridDim.x * blockDim.x) {
@@ -156,16 +171,30 @@ __global__ void lift_operand_kernel(const double* V, int64_t ldv, const double* 
     double v = V[n * ldv + k];
     if (lambda) v /= sqrt(lambda[n]);
     B[k * ldb + n] = v;
+    if (B32) B32[k * ldb + n] = (float)v;
   }
+}
+
+__global__ void to_f32_kernel(const double* src, float* dst, int64_t count) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = (float)src[i];
 }
 
 }  // namespace
 
 hapod_status launch_lift_operand(const double* V, int64_t ldv, const double* lambda, int64_t m, int64_t N,
-                                 double* B, int64_t ldb, hipStream_t stream) {
+                                 double* B, float* B32, int64_t ldb, hipStream_t stream) {
   if (m <= 0 || N <= 0) return HAPOD_OK;
   const unsigned g = (unsigned)std::min<int64_t>((m * N + 255) / 256, 4096);
-  hipLaunchKernelGGL(lift_operand_kernel, dim3(g), dim3(256), 0, stream, V, ldv, lambda, m, N, B, ldb);
+  hipLaunchKernelGGL(lift_operand_kernel, dim3(g), dim3(256), 0, stream, V, ldv, lambda, m, N, B, B32, ldb);
+  HAPOD_HIP(hipGetLastError());
+  return HAPOD_OK;
+}
+
+hapod_status launch_to_f32(const double* src, float* dst, int64_t count, hipStream_t stream) {
+  if (count <= 0) return HAPOD_OK;
+  const unsigned g = (unsigned)std::min<int64_t>((count + 255) / 256, 4096);
+  hipLaunchKernelGGL(to_f32_kernel, dim3(g), dim3(256), 0, stream, src, dst, count);
   HAPOD_HIP(hipGetLastError());
   return HAPOD_OK;
 }

@@ -15,7 +15,9 @@
 // Gram's rounding level or 1e-8 of their value; eigenvalues past them are reported
 // as 0, and the rounding level floor_abs = max(-theta_min, u_p trace(G) / 10)
 // is handed to the truncation, which counts eigenvalues at or below it as
-// zero energy.
+// zero energy.  The caller learns whether the Krylov space reached the
+// rounding level (else the spectrum past the block is unknown) and the energy
+// of Ritz values above that level that did not converge.
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -27,7 +29,7 @@
 namespace hapod {
 namespace {
 
-constexpr int kMaxSteps = 768;
+constexpr int kMaxSteps = kWideMaxSteps;
 constexpr int kMinSteps = 128;      // no stop before this many steps
 constexpr int kCheckEvery = 32;     // stopping test period
 constexpr double kPlateau = 0.7;    // beta_j >= 0.7 beta_{j-32}: plateau
@@ -333,8 +335,13 @@ __global__ void write_lambda_kernel(const double* theta, int b, double* lambda, 
 }  // namespace
 
 hapod_status wide_eigh(const double* G, int64_t ldg, int64_t m, double* lambda, double* V, int64_t ldv, double u_p,
-                       wide_alloc_fn alloc, wide_free_fn release, void* ctx, hipStream_t stream, WideResult* res) {
+                       wide_alloc_fn alloc, wide_free_fn release, void* ctx, hipStream_t stream, WideResult* res,
+                       bool full) {
   if (m <= 0) return HAPOD_OK;
+  if (full && m > kMaxSteps) {
+    set_error("wide_eigh: a full run needs m <= 768");
+    return HAPOD_E_UNSUPPORTED;
+  }
   const int k = (int)std::min<int64_t>(m, kMaxSteps);
   // ---- scratch ------------------------------------------------------------------
   std::vector<void*> owned;
@@ -387,6 +394,7 @@ hapod_status wide_eigh(const double* G, int64_t ldg, int64_t m, double* lambda, 
   HAPOD_HIP(hipStreamSynchronize(stream));
   const double floor_trace = 0.1 * u_p * std::fabs(trace);
   int steps = k;
+  bool stopped = (k == m);
   double prev_check = 0.0;
   const char* venv = std::getenv("HAPOD_VERBOSE");
   const bool verbose = venv && venv[0] == '1';
@@ -404,7 +412,7 @@ hapod_status wide_eigh(const double* G, int64_t ldg, int64_t m, double* lambda, 
     // that level).  Test every kCheckEvery steps: beta_j at or below
     // u_p trace(G) / 10, or beta_j fell less than kPlateau-fold over the last
     // period after having fallen 1000-fold from beta_0.
-    if ((j + 1) % kCheckEvery == 0 && j + 1 < k) {
+    if (!full && (j + 1) % kCheckEvery == 0 && j + 1 < k) {
       double bj = 0.0, b0 = 0.0;
       HAPOD_HIP(hipMemcpyAsync(&bj, beta + j, sizeof(double), hipMemcpyDeviceToHost, stream));
       HAPOD_HIP(hipMemcpyAsync(&b0, beta, sizeof(double), hipMemcpyDeviceToHost, stream));
@@ -416,6 +424,7 @@ hapod_status wide_eigh(const double* G, int64_t ldg, int64_t m, double* lambda, 
       prev_check = bj;
       if (j + 1 >= kMinSteps && (bj <= floor_trace || plateau)) {
         steps = j + 1;
+        stopped = true;
         break;
       }
     }
@@ -443,6 +452,14 @@ hapod_status wide_eigh(const double* G, int64_t ldg, int64_t m, double* lambda, 
   int b = 0;
   while (b < kk && std::fabs(bk * lz[b]) <= std::max(1e-8 * std::fabs(th[b]), floor_abs)) ++b;
   if (kk == m) b = kk;  // complete tridiagonalisation: every pair is exact
+  // an unconverged Ritz value within the last residual norm beta_{k-1} of
+  // zero cannot be told from zero (|lambda - theta| <= beta_{k-1} |z[k-1]|):
+  // only those above that level count as energy the block misses
+  const double noise = std::max(floor_abs, std::fabs(bk));
+  double missing = 0.0, captured = 0.0;
+  for (int i = b; i < kk; ++i)
+    if (th[i] > noise) missing += th[i];
+  for (int i = 0; i < b; ++i) captured += th[i];
   if (verbose)
     std::fprintf(stderr, "[hapod wide] m=%lld steps %d block %d theta_1 %.6e theta_min %.3e floor %.3e\n",
                  (long long)m, kk, b, th[0], theta_min, floor_abs);
@@ -478,6 +495,10 @@ hapod_status wide_eigh(const double* G, int64_t ldg, int64_t m, double* lambda, 
     res->iterations = kk;
     res->block = b;
     res->floor_abs = floor_abs;
+    res->exhausted = stopped;
+    res->missing = missing;
+    res->unresolved = std::max(0.0, trace - captured);
+    res->trace = trace;
   }
   return HAPOD_OK;
 }

@@ -22,6 +22,13 @@ for them):
 
 * uneven leaves: per-leaf heights, widths and family (sinusoid or bumps),
   evaluated on the global grid; rows past a leaf's height are zero.
+* chain chunks: chunk ``l`` (0-based) of an incremental (chain) workload is
+  ``bumps(n, cols, seed + l)``.
+* relative tolerances: where a workload fixes the accuracy relative to the
+  data, ``eps* = rel * sqrt(E ||s||^2)`` with the expected squared norm of a
+  snapshot taken analytically from the generator (bumps: ``r w sqrt(pi)``
+  for r grid rows and width w, interior approximation; sinusoid:
+  ``r sum_k exp(-2k/tau) + r noise_std^2``).
 
 The benchmark builds its large device-resident inputs from the same
 coefficient draws (made here, on the host) and the same formulas.
@@ -42,11 +49,16 @@ __all__ = [
     "bumps",
     "uneven_leaf_specs",
     "uneven_leaf",
+    "chain_chunk",
+    "bump_mean_energy",
+    "sinusoid_mean_energy",
+    "uneven_mean_energy",
     "star_tree",
     "chain_tree",
     "balanced_tree",
     "Workload",
     "WORKLOADS",
+    "UNEVEN_SPECS",
 ]
 
 
@@ -138,6 +150,34 @@ def uneven_leaf(spec, n: int, K: int = 400, tau: float = 20.0, noise_std: float 
     return np.asfortranarray(S.astype(dtype, copy=False))
 
 
+def chain_chunk(n: int, cols: int, seed: int, chunk: int, dtype=np.float64) -> np.ndarray:
+    """Chunk ``chunk`` of a chain workload: Gaussian bumps with seed+chunk."""
+    return bumps(n, cols, seed + chunk, dtype=dtype)
+
+
+def bump_mean_energy(rows: int, wmin: float = 0.01, wmax: float = 0.05) -> float:
+    """E||s||^2 of a bump over ``rows`` grid rows: rows * E[w] * sqrt(pi)."""
+    return rows * 0.5 * (wmin + wmax) * math.sqrt(math.pi)
+
+
+def sinusoid_mean_energy(rows: int, K: int, tau: float, noise_std: float = 0.0) -> float:
+    """E||s||^2 of a sinusoid snapshot over ``rows`` grid rows."""
+    k = np.arange(1, K + 1, dtype=np.float64)
+    return rows * float(np.exp(-2.0 * k / tau).sum()) + rows * noise_std ** 2
+
+
+def uneven_mean_energy(specs, K: int = 400, tau: float = 20.0, noise_std: float = 1e-10) -> float:
+    """Column-weighted mean of E||s||^2 over uneven leaves."""
+    tot = 0.0
+    cols = 0
+    for sp in specs:
+        e = (sinusoid_mean_energy(sp["rows"], K, tau, noise_std) if sp["family"] == 0
+             else bump_mean_energy(sp["rows"]))
+        tot += e * sp["cols"]
+        cols += sp["cols"]
+    return tot / max(cols, 1)
+
+
 # --------------------------------------------------------------------------
 # tree shapes (parent arrays; the root has parent -1)
 # --------------------------------------------------------------------------
@@ -218,6 +258,10 @@ class Workload:
         return int(sum(self.leaf_cols))
 
 
+_CHAIN_N = 1 << 22
+_UNEVEN_N = 1 << 20
+UNEVEN_SPECS = uneven_leaf_specs(1024, 5, (1 << 16, 1 << 20), (16, 256))
+
 WORKLOADS = {
     # n=4096, 4 leaves x 64 columns, star tree, sinusoid K=200, tau=10
     "star4096x256": Workload("star4096x256", 4096, (64,) * 4, "sinusoid",
@@ -225,4 +269,17 @@ WORKLOADS = {
     # n=2^20, 64 leaves x 128 columns, star tree, sinusoid K=400, tau=20
     "star1Mx8192": Workload("star1Mx8192", 1 << 20, (128,) * 64, "sinusoid",
                             1e-5, 0.75, K=400, tau=20.0, noise_std=1e-10),
+    # n=2^22 FP32, 256 chunks x 128 Gaussian bumps, chain tree (incremental
+    # HAPOD), eps* = 1e-3 sqrt(E||s||^2), device memory capped at 16 GiB
+    "chain4Mx32768": Workload("chain4Mx32768", _CHAIN_N, (128,) * 256, "bumps",
+                              1e-3 * math.sqrt(bump_mean_energy(_CHAIN_N)), 0.75, seed=7,
+                              precision="fp32", tree="chain",
+                              extra={"mem_cap": 16 << 30, "rel": 1e-3}),
+    # 1024 uneven leaves (rows U{2^16..2^20}, cols U{16..256}, sinusoid or
+    # bumps) on one 2^20 grid, balanced 3-level tree (arity 32), leaves run
+    # in waves of 256, eps* = 1e-3 sqrt(E||s||^2)
+    "uneven1024": Workload("uneven1024", _UNEVEN_N, tuple(sp["cols"] for sp in UNEVEN_SPECS), "mixed",
+                           1e-3 * math.sqrt(uneven_mean_energy(UNEVEN_SPECS)), 0.75, K=400, tau=20.0,
+                           noise_std=1e-10, seed=5, precision="bf16x3", tree="balanced3",
+                           extra={"leaf_wave": 256, "rel": 1e-3}),
 }

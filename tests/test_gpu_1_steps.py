@@ -203,7 +203,7 @@ def prescribed_svd(n, m, sigma, seed):
     return (U * sigma) @ W.T
 
 
-@pytest.mark.parametrize("n,m", [(8, 3), (64, 16), (33, 33), (16, 40), (500, 100), (4096, 64)])
+@pytest.mark.parametrize("n,m", [(8, 3), (64, 16), (33, 33), (16, 40), (500, 100), (4096, 64), (600, 200)])
 def test_node_pod_against_svd_oracle(hp, n, m):
     from oracle import metrics, pod
     r = min(n, m)
@@ -219,6 +219,23 @@ def test_node_pod_against_svd_oracle(hp, n, m):
     assert metrics.orthonormality_error(host(U)) < 1e-9
     s2, W = hp.hapod_node_pod("fp64", dev_colmajor(S), eps, scaled=True)
     np.testing.assert_allclose(host(W), host(U) * s, rtol=0, atol=1e-12 * sigma[0])
+
+
+def test_node_pod_exact_multiplicity(hp):
+    """A lone node of 129..256 columns takes the full-length Krylov
+    eigensolver; G = 4 I (every eigenvalue repeated) stops its Krylov space
+    after one step, which must be detected and handed to the dense Jacobi
+    eigensolver: all 200 modes, sigma = 2, the span of the inputs."""
+    from oracle import metrics
+    n, m = 256, 200
+    S = np.zeros((n, m))
+    S[np.arange(m), np.arange(m)] = 2.0
+    s, U = hp.hapod_node_pod("fp64", dev_colmajor(S), 1.0)
+    assert len(s) == m
+    np.testing.assert_allclose(s, 2.0, rtol=1e-13)
+    Uh = host(U)
+    assert metrics.subspace_error(np.eye(n)[:, :m], Uh, m) < 1e-12
+    assert metrics.orthonormality_error(Uh) < 1e-12
 
 
 def test_node_pod_passthrough(hp):
