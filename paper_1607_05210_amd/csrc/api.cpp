@@ -179,6 +179,7 @@ struct PodJob {
   double wide_missing = 0.0;   // energy of unconverged Ritz values above it
   double wide_unresolved = 0.0;  // trace(G) minus the returned eigenvalues
   double wide_slack = 0.0;       // rounding allowance of that difference
+  double wide_noise_room = 0.0;  // energy the unresolved eigenvalues may hold
 };
 
 struct PhaseTimes {
@@ -481,6 +482,11 @@ hapod_status run_pod_batch(hapod_precision prec, std::vector<PodJob>& jobs, int 
     // the difference trace - sum(theta) carries the rounding of every
     // eigenvalue and of the diagonal: allow 16 (block + sqrt(m)) u_p |trace|
     jobs[i].wide_slack = 16.0 * (wr.block + std::sqrt((double)jobs[i].m)) * u_p * std::fabs(wr.trace);
+    // the eigenvalues past the block lie below the resolved level: up to
+    // (m - block) noise of unresolved energy is consistent with that (the
+    // truncation then cannot certify eps below the noise, as for any Gram of
+    // this precision); more means a large eigenvalue was never seen
+    jobs[i].wide_noise_room = (double)(jobs[i].m - wr.block) * wr.noise;
     if (jobs[i].wide_full && wr.unresolved > jobs[i].wide_slack) {
       // the Krylov space broke down before spanning the matrix (an exact
       // multiplicity): fall back to the dense Jacobi eigensolver
@@ -509,6 +515,7 @@ hapod_status run_pod_batch(hapod_precision prec, std::vector<PodJob>& jobs, int 
       if (s != HAPOD_OK) return s;
       jobs[i].wide_unresolved = 0.0;
       jobs[i].wide_missing = 0.0;
+      jobs[i].wide_noise_room = 0.0;
       jobs[i].wide_exhausted = true;
     }
   }
@@ -608,7 +615,7 @@ hapod_status run_pod_batch(hapod_precision prec, std::vector<PodJob>& jobs, int 
     // a wide node's truncation is trusted only if the eigenpairs it did not
     // get cannot hold more than the budget eps^2 (Def. 2.5) allows
     if (j.wide && (!j.wide_exhausted || j.info[0] + j.wide_missing > j.eps * j.eps ||
-                   j.info[0] + j.wide_unresolved > j.eps * j.eps + j.wide_slack)) {
+                   j.info[0] + j.wide_unresolved > j.eps * j.eps + j.wide_slack + j.wide_noise_room)) {
       set_error("wide eigensolver: " + std::to_string(j.sweeps) + " Krylov steps on an m = " +
                 std::to_string(j.m) + " Gram did not resolve every eigenvalue the truncation needs" +
                 (j.wide_exhausted ? " (unconverged energy above the budget)" : " (step limit reached)"));

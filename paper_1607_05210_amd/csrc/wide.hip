@@ -12,12 +12,14 @@
 //   eigenvector).  Ritz pairs: (theta_i, Q z_i), residual beta_{k-1} |z_i[k-1]|.
 //
 // The pairs returned are the leading Ritz pairs whose residual is below the
-// Gram's rounding level or 1e-8 of their value; eigenvalues past them are reported
-// as 0, and the rounding level floor_abs = max(-theta_min, u_p trace(G) / 10)
-// is handed to the truncation, which counts eigenvalues at or below it as
-// zero energy.  The caller learns whether the Krylov space reached the
-// rounding level (else the spectrum past the block is unknown) and the energy
-// of Ritz values above that level that did not converge.
+// Gram's rounding level or 1e-8 of their value, extended (when the iteration
+// stopped at the rounding level) by the further Ritz values above the final
+// residual norm; eigenvalues past them are reported as 0, and the rounding
+// level floor_abs = max(-theta_min, u_p trace(G) / 10) is handed to the
+// truncation, which counts eigenvalues at or below it as zero energy.  The
+// caller learns whether the Krylov space reached the rounding level (else the
+// spectrum past the block is unknown) and how much of trace(G) the returned
+// pairs leave unexplained.
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -452,10 +454,18 @@ hapod_status wide_eigh(const double* G, int64_t ldg, int64_t m, double* lambda, 
   int b = 0;
   while (b < kk && std::fabs(bk * lz[b]) <= std::max(1e-8 * std::fabs(th[b]), floor_abs)) ++b;
   if (kk == m) b = kk;  // complete tridiagonalisation: every pair is exact
-  // an unconverged Ritz value within the last residual norm beta_{k-1} of
-  // zero cannot be told from zero (|lambda - theta| <= beta_{k-1} |z[k-1]|):
-  // only those above that level count as energy the block misses
+  // Ritz vectors of one Krylov space are orthonormal and diagonalise G on it
+  // (V^T G V = diag(theta)), so the energy of S on the modes S v_i / sqrt(theta_i)
+  // is at least sum theta_i whether or not the pairs have converged: the block
+  // is extended by every Ritz value above the noise level max(floor_abs,
+  // beta_{k-1}) (below it a Ritz value cannot be told from zero), and only
+  // what lies beyond the Krylov space is left unresolved.
   const double noise = std::max(floor_abs, std::fabs(bk));
+  if (stopped) {
+    int e = b;
+    while (e < kk && th[e] > noise) ++e;
+    b = e;
+  }
   double missing = 0.0, captured = 0.0;
   for (int i = b; i < kk; ++i)
     if (th[i] > noise) missing += th[i];
@@ -499,6 +509,7 @@ hapod_status wide_eigh(const double* G, int64_t ldg, int64_t m, double* lambda, 
     res->missing = missing;
     res->unresolved = std::max(0.0, trace - captured);
     res->trace = trace;
+    res->noise = (b < m) ? noise : 0.0;
   }
   return HAPOD_OK;
 }

@@ -19,6 +19,8 @@ struct WideResult {
                             // returned pair holds (a multiplicity the Krylov
                             // space never saw shows up here)
   double trace = 0.0;       // trace(G)
+  double noise = 0.0;       // level below which a Ritz value is not resolved:
+                            // each eigenvalue past the block is at most this
 };
 
 typedef void* (*wide_alloc_fn)(void* ctx, size_t bytes);
