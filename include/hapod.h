@@ -63,7 +63,10 @@ typedef enum {
 typedef enum {
   HAPOD_FP64 = 0,    /* Gram and lift on FP64 MFMA, double storage                         */
   HAPOD_FP32 = 1,    /* Gram and lift on FP32 MFMA, FP32 accumulation, float storage       */
-  HAPOD_BF16X3 = 2   /* split-BF16, three products hi*hi + hi*lo + lo*hi on BF16 MFMA      */
+  HAPOD_BF16X3 = 2   /* float storage; Gram of nodes wider than 64 columns as split-BF16,
+                        three products hi*hi + hi*lo + lo*hi on BF16 MFMA with FP32
+                        accumulation; narrower Grams (bandwidth-bound) and all lifts on
+                        FP32 MFMA                                                      */
 } hapod_precision;
 
 /* ------------------------------------------------------------------------ */
@@ -204,7 +207,10 @@ hapod_status hapod_plan_query(hapod_plan_t plan, double* eps, int32_t* level,
  * synchronises the stream at the end of every group, before the provider
  * is called again, so a provider may stream leaves through a few reused
  * buffers (with leaf_wave bounding how many one group needs).  Non-zero
- * return aborts the run with HAPOD_E_CALLBACK.                              */
+ * return aborts the run with HAPOD_E_CALLBACK.
+ * After a group that read leaves has completed, the provider is called once
+ * with leaf = -1 (ptr and ld NULL): no leaf handed over so far is read again,
+ * so their memory may be released.  It must return 0 for that call.        */
 typedef int32_t (*hapod_leaf_fn)(void* user, int32_t leaf, const void** ptr,
                                  int64_t* ld, void* stream);
 
@@ -213,7 +219,10 @@ typedef int32_t (*hapod_leaf_fn)(void* user, int32_t leaf, const void** ptr,
  * truncation, lift); ranks are read back between levels to size the next
  * one.  Intermediate node outputs are released once their parent is done;
  * the root's modes and the per-node ranks and singular values are kept in
- * the plan until the next run or hapod_destroy.  Synchronises the stream. */
+ * the plan until the next run or hapod_destroy.  Synchronises the stream.
+ * Environment: HAPOD_TWIN_BUDGET (bytes) caps the arena that holds the
+ * split-BF16 twins of a level (by default half of the free device memory);
+ * HAPOD_VERBOSE=1 prints the Krylov eigensolver's progress to stderr.      */
 hapod_status hapod_run(hapod_plan_t plan, hapod_leaf_fn get_leaf, void* user,
                        void* stream);
 

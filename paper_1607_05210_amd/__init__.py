@@ -248,15 +248,24 @@ class Plan:
         """``leaves``: dict leaf id -> column-major device tensor, or a
         callable leaf id -> tensor (called once per leaf, in level order, just
         before the launch group that first reads it).  With ``hold`` every
-        tensor handed over stays referenced until the run returns; a provider
-        that streams more data than fits passes ``hold=False`` and keeps each
-        tensor alive itself until the next group's leaves are requested."""
+        tensor handed over stays referenced until the library reports that no
+        leaf given so far is read again; a provider that streams more data
+        than fits passes ``hold=False`` and keeps each tensor alive itself
+        until then.  A callable provider with a ``release()`` method has it
+        called at that point."""
         elem = _elem(self.prec)
         held = {}
         err = []
 
         def cb(user, leaf, ptr, ld, s):
             try:
+                if leaf < 0:
+                    # release call: no leaf handed over so far is read again
+                    held.clear()
+                    rel = getattr(leaves, "release", None)
+                    if callable(rel):
+                        rel()
+                    return 0
                 t = leaves(leaf) if callable(leaves) else leaves[leaf]
                 p, n, m, ldt = _mat(t, f"leaf {leaf}", elem)
                 if hold:

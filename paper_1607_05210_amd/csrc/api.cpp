@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <array>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -32,7 +33,7 @@ int elem_bytes(hapod_precision p) { return p == HAPOD_FP64 ? 8 : 4; }
 int compute_mode(hapod_precision p) { return p == HAPOD_FP64 ? 0 : (p == HAPOD_FP32 ? 1 : 2); }
 
 constexpr size_t kAlign = 256;
-constexpr int64_t kPresplitMinCols = 256;
+constexpr int64_t kPresplitMinCols = 129;
 
 // plain column-major n x m (leading dimension ld)
 std::vector<const void*> column_table(const void* base, int64_t ld, int64_t m, int eb) {
@@ -98,6 +99,15 @@ class Pool {
     auto it = size_of_.find(p);
     if (it == size_of_.end()) return;
     free_[it->second].push_back(p);
+  }
+  // give a block back to the device at once instead of caching it
+  void free_now(void* p) {
+    if (!p) return;
+    auto it = size_of_.find(p);
+    if (it == size_of_.end()) return;
+    held_ -= it->second;
+    size_of_.erase(it);
+    (void)hipFree(p);
   }
   void trim() {
     for (auto& kv : free_)
@@ -206,6 +216,16 @@ int pick_chunks(int64_t n, int pairs, int target_items, int64_t min_rows) {
   return (int)std::max<int64_t>(1, std::min(want, maxc));
 }
 
+// Gram tile for a node of m columns: narrow nodes get split tiles (every
+// wavefront of a workgroup on the whole tile, over its own rows) sized to m,
+// so their MFMA work is not padded to 128 columns and no SIMD idles.
+int gram_tile_for(int64_t m) {
+  if (m <= 16) return 16;
+  if (m <= 32) return 32;
+  if (m <= 128) return 64;
+  return kGramTile;
+}
+
 // Eigensolver choice.  jacobi_max > 0: Jacobi up to that width, Lanczos
 // above.  jacobi_max <= 0 (automatic): Jacobi in LDS up to kJacobiLdsMax;
 // between that and kAutoJacobiMax the global-memory Jacobi when the batch has
@@ -216,7 +236,8 @@ constexpr int64_t kLiftTargetItems = 2048;  // lift workgroups per launch to aim
 constexpr int kMinJacobiBatch = 3;
 
 hapod_status run_pod_batch(hapod_precision prec, std::vector<PodJob>& jobs, int policy_small, int policy_wide,
-                           int jacobi_max, Pool& pool, hipStream_t stream, PhaseTimes* times) {
+                           int jacobi_max, Pool& pool, hipStream_t stream, PhaseTimes* times,
+                           void** batch_block = nullptr) {
   const int compute = compute_mode(prec);
   const int eb = elem_bytes(prec);
   const int nj = (int)jobs.size();
@@ -227,7 +248,7 @@ hapod_status run_pod_batch(hapod_precision prec, std::vector<PodJob>& jobs, int 
   struct Lay {
     size_t cols, rbs, crows, cols2, rbs2, crows2, G, partial, lam, V, B, B32, sigma, rank, info, jwork, vwork, sweeps;
     bool presplit;
-    int ntiles, pairs, nchunks;
+    int tile, slots, ntiles, pairs, nchunks;
     int64_t chunk_rows;
   };
   std::vector<Lay> lay(nj);
@@ -237,22 +258,34 @@ hapod_status run_pod_batch(hapod_precision prec, std::vector<PodJob>& jobs, int 
   // enough row chunks to give every CU several workgroups
   int sum_pairs = 0;
   for (auto& j : jobs) {
-    int nt = (int)((j.m + kGramTile - 1) / kGramTile);
+    const int tile = gram_tile_for(j.m);
+    int nt = (int)((j.m + tile - 1) / tile);
     sum_pairs += nt * (nt + 1) / 2;
   }
   const int target_items = std::max(2048, sum_pairs);
   int mid_nodes = 0;
   for (auto& j : jobs) mid_nodes += (j.m > kJacobiLdsMax && j.m <= kAutoJacobiMax) ? 1 : 0;
-  // split twins take as much memory as their inputs: give them at most a
-  // third of what the device has free (and of what the plan's cap leaves);
-  // nodes beyond that split in registers instead
-  size_t twin_bytes = 0, twin_budget = 0;
+  // split twins take as much memory as their inputs.  They are made and
+  // consumed in groups that fit an arena of at most half of what the device
+  // has free (and of what the plan's cap leaves): the Gram of one group runs
+  // before the next group's twins overwrite the arena.  A node whose twin
+  // alone exceeds the arena splits in registers instead.
+  size_t twin_budget = 0;
   if (compute == 2) {
     size_t free_b = 0, total_b = 0;
-    if (hipMemGetInfo(&free_b, &total_b) == hipSuccess) twin_budget = (free_b + pool.cached()) / 3;
+    if (hipMemGetInfo(&free_b, &total_b) == hipSuccess) twin_budget = (free_b + pool.cached()) / 2;
     const size_t room = pool.room();
-    if (room < twin_budget) twin_budget = room / 3;
+    if (room / 2 < twin_budget) twin_budget = room / 2;
+    // HAPOD_TWIN_BUDGET (bytes) lowers the arena further
+    if (const char* e = std::getenv("HAPOD_TWIN_BUDGET")) {
+      const long long v = std::atoll(e);
+      if (v > 0 && (size_t)v < twin_budget) twin_budget = (size_t)v;
+    }
   }
+  std::vector<int> twin_group(nj, 0);
+  std::vector<size_t> twin_off(nj, 0);
+  size_t arena_bytes = 0, group_fill = 0;
+  int ngroups = 1;
   for (int i = 0; i < nj; ++i) {
     PodJob& j = jobs[i];
     Lay& L = lay[i];
@@ -262,7 +295,8 @@ hapod_status run_pod_batch(hapod_precision prec, std::vector<PodJob>& jobs, int 
     // a node taken from Jacobi only for speed keeps Jacobi's result: all
     // eigenpairs (a full Lanczos run) and the same truncation policy
     j.wide_full = j.wide && jacobi_max <= 0 && m <= kAutoJacobiMax;
-    L.ntiles = (int)((m + kGramTile - 1) / kGramTile);
+    L.tile = gram_tile_for(m);
+    L.ntiles = (int)((m + L.tile - 1) / L.tile);
     L.pairs = L.ntiles * (L.ntiles + 1) / 2;
     const int per_node_target = std::max(1, (int)((int64_t)target_items * L.pairs / std::max(sum_pairs, 1)));
     L.nchunks = pick_chunks(j.n, L.pairs, per_node_target, 2048);
@@ -281,14 +315,24 @@ hapod_status run_pod_batch(hapod_precision prec, std::vector<PodJob>& jobs, int 
     L.crows = take(sizeof(int64_t) * std::max<int64_t>(m, 1));
     // split-BF16: nodes with several column tiles get a split twin of their
     // input once, instead of splitting every element in each tile that reads it
-    L.presplit = (compute == 2 && m >= kPresplitMinCols && j.n > 0 &&
-                  twin_bytes + tiled_bytes(j.n, m, 4) <= twin_budget);
-    if (L.presplit) twin_bytes += tiled_bytes(j.n, m, 4);
+    L.presplit = (compute == 2 && m >= kPresplitMinCols && j.n > 0 && tiled_bytes(j.n, m, 4) <= twin_budget);
+    if (L.presplit) {
+      const size_t tb = align_up(tiled_bytes(j.n, m, 4));
+      if (group_fill + tb > twin_budget) {
+        ++ngroups;
+        group_fill = 0;
+      }
+      twin_group[i] = ngroups - 1;
+      twin_off[i] = group_fill;
+      group_fill += tb;
+      arena_bytes = std::max(arena_bytes, group_fill);
+    }
     L.cols2 = L.presplit ? take(sizeof(void*) * m) : 0;
     L.rbs2 = L.presplit ? take(sizeof(int64_t) * m) : 0;
     L.crows2 = L.presplit ? take(sizeof(int64_t) * m) : 0;
     L.G = take(sizeof(double) * m * m);
-    L.partial = (L.nchunks > 1) ? take(sizeof(double) * (size_t)L.pairs * L.nchunks * kGramTile * kGramTile) : 0;
+    L.slots = L.nchunks * gram_slots_per_chunk(L.tile);
+    L.partial = (L.slots > 1) ? take(sizeof(double) * (size_t)L.pairs * L.slots * L.tile * L.tile) : 0;
     L.lam = take(sizeof(double) * std::max<int64_t>(m, 1));
     L.V = take(sizeof(double) * m * m);
     // lift operand rows padded to a multiple of 4 entries: 16-byte aligned runs
@@ -312,21 +356,21 @@ hapod_status run_pod_batch(hapod_precision prec, std::vector<PodJob>& jobs, int 
     void* s;
     ~Guard() { p.free(s); }
   } guard{pool, scratch};
-  // split twins (released with the batch)
-  std::vector<void*> split_buf(nj, nullptr);
-  struct GuardV {
+  // split-twin arena (released with the batch)
+  char* arena = nullptr;
+  if (arena_bytes > 0) HAPOD_TRY(pool.alloc(arena_bytes, (void**)&arena));
+  struct GuardA {  // sized by the free memory: not kept in the cache
     Pool& p;
-    std::vector<void*>& v;
-    ~GuardV() {
-      for (void* q : v) p.free(q);
-    }
-  } guardv{pool, split_buf};
+    void* s;
+    ~GuardA() { p.free_now(s); }
+  } guarda{pool, arena};
+  std::vector<void*> split_buf(nj, nullptr);
   std::vector<std::vector<const void*>> cols2(nj);
   std::vector<std::vector<int64_t>> rbs2(nj), crows2(nj);
   for (int i = 0; i < nj; ++i) {
     if (!lay[i].presplit) continue;
     const int64_t m = jobs[i].m;
-    HAPOD_TRY(pool.alloc(tiled_bytes(jobs[i].n, m, 4), &split_buf[i]));
+    split_buf[i] = arena + twin_off[i];
     cols2[i] = tiled_table(split_buf[i], m, 4);
     rbs2[i].assign((size_t)m, tiled_rbs(m));
     crows2[i].assign((size_t)m, jobs[i].n);
@@ -335,18 +379,24 @@ hapod_status run_pod_batch(hapod_precision prec, std::vector<PodJob>& jobs, int 
   // ---- descriptor tables ----------------------------------------------------
   std::vector<GramNode> gnodes(nj);
   std::vector<GramItem> gitems;
+  // per twin group: (default compute, FP32) x (tile 128, 64, 32, 16) x (scalar, vector runs)
+  std::vector<std::array<std::vector<GramItem>, 16>> items_by_tile(ngroups);
+  auto tile_slot = [](int t) { return t == 128 ? 0 : t == 64 ? 1 : t == 32 ? 2 : 3; };
+  int max_reduce_tile = 0;
   std::vector<int32_t> rpairs, rnode;
   std::vector<EigNode> enodes_small, enodes_big;
   std::vector<TruncNode> tnodes(nj);
-  bool vec_ok = true;
+
   int pair_base = 0, max_small = 0, max_big = 0;
   for (int i = 0; i < nj; ++i) {
     PodJob& j = jobs[i];
     Lay& L = lay[i];
     const int64_t m = j.m;
-    for (const void* c : j.cols)
-      if (((uintptr_t)c & 15u) != 0) vec_ok = false;
-    if (L.chunk_rows % KB) vec_ok = false;
+    // vector runs need 16-byte aligned columns (the split twin always is)
+    bool vec = (L.chunk_rows % KB) == 0;
+    if (!L.presplit)
+      for (const void* c : j.cols)
+        if (((uintptr_t)c & 15u) != 0) vec = false;
     GramNode& g = gnodes[i];
     g.cols = (const void* const*)(scratch + (L.presplit ? L.cols2 : L.cols));
     g.rbs = (const int64_t*)(scratch + (L.presplit ? L.rbs2 : L.rbs));
@@ -355,19 +405,26 @@ hapod_status run_pod_batch(hapod_precision prec, std::vector<PodJob>& jobs, int 
     g.n = j.n;
     g.chunk_rows = L.chunk_rows;
     g.G = (double*)(scratch + L.G);
-    g.partial = L.nchunks > 1 ? (double*)(scratch + L.partial) : nullptr;
+    g.partial = L.slots > 1 ? (double*)(scratch + L.partial) : nullptr;
     g.ldg = m;
     g.m = (int32_t)m;
     g.nchunks = L.nchunks;
     g.ntiles = L.ntiles;
     g.pair_base = pair_base;
+    g.tile = L.tile;
+    // split-BF16 nodes of at most 64 columns are bandwidth-bound: their Gram
+    // runs on FP32 MFMA (no in-register split), in launch slots of their own
+    const bool f32 = (compute == 2 && m <= 64);
+    std::vector<GramItem>& gi =
+        items_by_tile[twin_group[i]][(f32 ? 8 : 0) + 2 * tile_slot(L.tile) + (vec ? 1 : 0)];
     int p = pair_base;
     for (int ti = 0; ti < L.ntiles; ++ti)
       for (int tj = ti; tj < L.ntiles; ++tj, ++p) {
-        for (int c = 0; c < L.nchunks; ++c) gitems.push_back(GramItem{i, (int16_t)ti, (int16_t)tj, c, p});
-        if (L.nchunks > 1) {
+        for (int c = 0; c < L.nchunks; ++c) gi.push_back(GramItem{i, (int16_t)ti, (int16_t)tj, c, p});
+        if (L.slots > 1) {
           rpairs.push_back(p);
           rnode.push_back(i);
+          max_reduce_tile = std::max(max_reduce_tile, L.tile);
         }
       }
     pair_base = p;
@@ -417,6 +474,15 @@ hapod_status run_pod_batch(hapod_precision prec, std::vector<PodJob>& jobs, int 
     rbs2_off[i] = blob.add_vec(rbs2[i]);
     rows2_off[i] = blob.add_vec(crows2[i]);
   }
+  std::vector<std::vector<GramLaunch>> glaunch(ngroups);
+  for (int gr = 0; gr < ngroups; ++gr)
+    for (int t = 0; t < 16; ++t) {
+      const auto& v = items_by_tile[gr][t];
+      if (v.empty()) continue;
+      glaunch[gr].push_back(GramLaunch{128 >> ((t & 7) / 2), t & 1, (int32_t)gitems.size(), (int32_t)v.size(),
+                                       t >= 8 ? 1 : -1});
+      gitems.insert(gitems.end(), v.begin(), v.end());
+    }
   const size_t o_g = blob.add_vec(gnodes), o_gi = blob.add_vec(gitems), o_rp = blob.add_vec(rpairs),
                o_rn = blob.add_vec(rnode), o_es = blob.add_vec(enodes_small), o_eb = blob.add_vec(enodes_big),
                o_t = blob.add_vec(tnodes);
@@ -450,15 +516,19 @@ hapod_status run_pod_batch(hapod_precision prec, std::vector<PodJob>& jobs, int 
 
   Events ev;
   if (times && ev.ok) HAPOD_HIP(hipEventRecord(ev.e[0], stream));
-  // ---- split twins, then Gram ---------------------------------------------------
-  for (int i = 0; i < nj; ++i)
-    if (lay[i].presplit)
-      HAPOD_TRY(launch_split_cols(jobs[i].n, jobs[i].m, (const void* const*)(scratch + lay[i].cols),
-                                  (const int64_t*)(scratch + lay[i].rbs), (const int64_t*)(scratch + lay[i].crows),
-                                  (float*)split_buf[i], stream));
-  HAPOD_TRY(launch_gram(compute, (const GramNode*)(dblob + o_g), (const GramItem*)(dblob + o_gi), (int)gitems.size(),
-                        (const int32_t*)(dblob + o_rp), (const int32_t*)(dblob + o_rn), (int)rpairs.size(), vec_ok,
-                        stream));
+  // ---- split twins, then Gram, one twin group at a time; then the reduction
+  for (int gr = 0; gr < ngroups; ++gr) {
+    for (int i = 0; i < nj; ++i)
+      if (lay[i].presplit && twin_group[i] == gr)
+        HAPOD_TRY(launch_split_cols(jobs[i].n, jobs[i].m, (const void* const*)(scratch + lay[i].cols),
+                                    (const int64_t*)(scratch + lay[i].rbs),
+                                    (const int64_t*)(scratch + lay[i].crows), (float*)split_buf[i], stream));
+    HAPOD_TRY(launch_gram(compute, (const GramNode*)(dblob + o_g), (const GramItem*)(dblob + o_gi),
+                          glaunch[gr].data(), (int)glaunch[gr].size(), nullptr, nullptr, 0, 0, stream));
+  }
+  HAPOD_TRY(launch_gram(compute, (const GramNode*)(dblob + o_g), (const GramItem*)(dblob + o_gi), nullptr, 0,
+                        (const int32_t*)(dblob + o_rp), (const int32_t*)(dblob + o_rn), (int)rpairs.size(),
+                        max_reduce_tile, stream));
   for (int i = 0; i < nj; ++i) HAPOD_TRY(launch_check_diag(gnodes[i].G, gnodes[i].ldg, jobs[i].m, d_flag, stream));
   if (times && ev.ok) HAPOD_HIP(hipEventRecord(ev.e[1], stream));
   // ---- eigensolve -----------------------------------------------------------
@@ -533,13 +603,29 @@ hapod_status run_pod_batch(hapod_precision prec, std::vector<PodJob>& jobs, int 
   HAPOD_HIP(hipStreamSynchronize(stream));
   for (int i = 0; i < nj; ++i)
     HAPOD_HIP(hipMemcpy(&ranks[i], scratch + lay[i].rank, sizeof(int64_t), hipMemcpyDeviceToHost));
-  // outputs sized by the ranks
+  // outputs sized by the ranks, carved from one block for the batch (one
+  // allocation instead of one per node; the caller frees the block once
+  // every node in it has been consumed)
+  std::vector<size_t> out_off(nj, 0);
+  size_t out_total = 0;
+  for (int i = 0; i < nj; ++i) {
+    const PodJob& j = jobs[i];
+    if (j.out || j.alloc_rows <= 0 || j.m <= 0 || ranks[i] <= 0) continue;
+    out_off[i] = out_total;
+    out_total = align_up(out_total + (j.plain_out ? (size_t)j.alloc_rows * ranks[i] * eb
+                                                  : tiled_bytes(j.n, ranks[i], eb)));
+  }
+  char* out_block = nullptr;
+  if (out_total > 0) {
+    HAPOD_TRY(pool.alloc(out_total, (void**)&out_block));
+    if (batch_block) *batch_block = out_block;
+  }
   for (int i = 0; i < nj; ++i) {
     PodJob& j = jobs[i];
     if (j.out || j.alloc_rows <= 0 || j.m <= 0 || ranks[i] <= 0) continue;
     const int64_t N = ranks[i];
     const size_t bytes = j.plain_out ? (size_t)j.alloc_rows * N * eb : tiled_bytes(j.n, N, eb);
-    HAPOD_TRY(pool.alloc(bytes, &j.out));
+    j.out = out_block + out_off[i];
     if (j.plain_out) {
       j.ocs = j.alloc_rows;
       j.obs = kRowBlock;
@@ -549,18 +635,25 @@ hapod_status run_pod_batch(hapod_precision prec, std::vector<PodJob>& jobs, int 
       j.obs = tiled_rbs(N);
     }
   }
-  std::vector<LiftNode> lnodes;
-  int lift_items = 0;
+  // nodes of rank <= 64 take the narrow lift (256 x 64 tiles), the others
+  // 128 x 128 tiles; each kind is one launch
+  std::vector<LiftNode> lnodes[2];
+  int lift_items[2] = {0, 0};
   // several row tiles per workgroup when there are many: the column table
   // and the node lookup are then paid once per group of tiles
   int64_t lift_tiles = 0;
   for (int i = 0; i < nj; ++i)
-    if (jobs[i].m > 0 && jobs[i].n > 0 && ranks[i] > 0)
-      lift_tiles += ((jobs[i].n + kLiftTileM - 1) / kLiftTileM) * ((ranks[i] + kLiftTileN - 1) / kLiftTileN);
+    if (jobs[i].m > 0 && jobs[i].n > 0 && ranks[i] > 0) {
+      const bool nar = ranks[i] <= kLiftTileN / 2;
+      const int64_t tm = nar ? kLiftNarrowM : kLiftTileM, tn = nar ? kLiftTileN / 2 : kLiftTileN;
+      lift_tiles += ((jobs[i].n + tm - 1) / tm) * ((ranks[i] + tn - 1) / tn);
+    }
   const int rt_per = (int)std::max<int64_t>(1, std::min<int64_t>(16, lift_tiles / kLiftTargetItems));
   for (int i = 0; i < nj; ++i) {
     const PodJob& j = jobs[i];
     if (j.m <= 0 || j.n <= 0 || ranks[i] <= 0) continue;
+    const int nar = ranks[i] <= kLiftTileN / 2 ? 1 : 0;
+    const int64_t tm = nar ? kLiftNarrowM : kLiftTileM, tn = nar ? kLiftTileN / 2 : kLiftTileN;
     LiftNode l{};
     l.cols = (const void* const*)(scratch + lay[i].cols);
     l.rbs = (const int64_t*)(scratch + lay[i].rbs);
@@ -574,17 +667,20 @@ hapod_status run_pod_batch(hapod_precision prec, std::vector<PodJob>& jobs, int 
     l.ocs = j.ocs;
     l.obs = j.obs;
     l.m = (int32_t)j.m;
-    l.row_tiles = (int32_t)((j.n + kLiftTileM - 1) / kLiftTileM);
-    l.col_tiles = (int32_t)((ranks[i] + kLiftTileN - 1) / kLiftTileN);
-    l.item_base = lift_items;
+    l.row_tiles = (int32_t)((j.n + tm - 1) / tm);
+    l.col_tiles = (int32_t)((ranks[i] + tn - 1) / tn);
+    l.item_base = lift_items[nar];
     l.rt_per = rt_per;
-    lift_items += ((l.row_tiles + rt_per - 1) / rt_per) * l.col_tiles;
-    lnodes.push_back(l);
+    lift_items[nar] += ((l.row_tiles + rt_per - 1) / rt_per) * l.col_tiles;
+    lnodes[nar].push_back(l);
   }
   char* dlift = nullptr;
-  if (!lnodes.empty()) {
-    HAPOD_TRY(pool.alloc(sizeof(LiftNode) * lnodes.size(), (void**)&dlift));
-    HAPOD_HIP(hipMemcpy(dlift, lnodes.data(), sizeof(LiftNode) * lnodes.size(), hipMemcpyHostToDevice));
+  const size_t nl0 = lnodes[0].size(), nl1 = lnodes[1].size();
+  if (nl0 + nl1 > 0) {
+    std::vector<LiftNode> all(lnodes[0]);
+    all.insert(all.end(), lnodes[1].begin(), lnodes[1].end());
+    HAPOD_TRY(pool.alloc(sizeof(LiftNode) * all.size(), (void**)&dlift));
+    HAPOD_HIP(hipMemcpy(dlift, all.data(), sizeof(LiftNode) * all.size(), hipMemcpyHostToDevice));
   }
   struct Guard3 {
     Pool& p;
@@ -592,7 +688,13 @@ hapod_status run_pod_batch(hapod_precision prec, std::vector<PodJob>& jobs, int 
     ~Guard3() { p.free(s); }
   } guard3{pool, dlift};
   if (times && ev.ok) HAPOD_HIP(hipEventRecord(ev.e[3], stream));
-  HAPOD_TRY(launch_lift(compute, (const LiftNode*)dlift, (int)lnodes.size(), lift_items, stream));
+  // the split-BF16 form lifts on FP32 MFMA: the lift reads each input once
+  // per 128 output columns, so it is bandwidth-bound where the three-product
+  // split would only add VALU work, and FP32 products are at least as exact
+  const int lift_compute = (compute == 2) ? 1 : compute;
+  if (nl0) HAPOD_TRY(launch_lift(lift_compute, (const LiftNode*)dlift, (int)nl0, lift_items[0], stream, false));
+  if (nl1)
+    HAPOD_TRY(launch_lift(lift_compute, (const LiftNode*)dlift + nl0, (int)nl1, lift_items[1], stream, true));
   if (times && ev.ok) HAPOD_HIP(hipEventRecord(ev.e[4], stream));
 
   // ---- results ----------------------------------------------------------------
@@ -874,7 +976,22 @@ hapod_status hapod_run(hapod_plan_t P, hapod_leaf_fn get_leaf, void* user, void*
   std::vector<std::vector<const void*>> out_cols(nn);
   std::vector<std::vector<int64_t>> out_rbs(nn), out_rows(nn);
   std::vector<void*> out_buf(nn, nullptr);
+  // node outputs live in per-batch blocks: a block is freed when the last
+  // node whose output it holds has been consumed
+  std::vector<int> out_blk(nn, -1);
+  std::vector<std::pair<void*, int>> blocks;
+  auto release = [&](int32_t a) {
+    const int b = out_blk[a];
+    out_buf[a] = nullptr;
+    out_blk[a] = -1;
+    if (b >= 0 && --blocks[b].second == 0) {
+      P->pool.free(blocks[b].first);
+      blocks[b].first = nullptr;
+    }
+  };
   std::vector<char> deferred(nn, 0);
+  std::vector<char> holds_leaf(nn, 0);  // output columns point into leaf data
+  bool release_pending = false;          // leaves handed over since the last release call
   hipEvent_t t0 = nullptr, t1 = nullptr;
   HAPOD_HIP(hipEventCreate(&t0));
   HAPOD_HIP(hipEventCreate(&t1));
@@ -887,10 +1004,7 @@ hapod_status hapod_run(hapod_plan_t P, hapod_leaf_fn get_leaf, void* user, void*
   } evg{t0, t1};
   auto release_all = [&]() {
     for (int32_t i = 0; i < nn; ++i)
-      if (out_buf[i] && i != P->root) {
-        P->pool.free(out_buf[i]);
-        out_buf[i] = nullptr;
-      }
+      if (out_buf[i] && i != P->root) release(i);
   };
   auto fetch_leaf = [&](int32_t a, std::vector<const void*>& cols, std::vector<int64_t>& rbs,
                         std::vector<int64_t>& rows) -> hapod_status {
@@ -938,15 +1052,19 @@ hapod_status hapod_run(hapod_plan_t P, hapod_leaf_fn get_leaf, void* user, void*
     for (auto& grp : groups) {
       std::vector<PodJob> jobs;
       std::vector<int32_t> job_node;
+      bool group_fetched = false;
       for (int32_t a : grp) {
         std::vector<const void*> in;
         std::vector<int64_t> in_rbs, in_rows;
         hapod_status s = HAPOD_OK;
         if (P->children[a].empty()) {
           s = fetch_leaf(a, in, in_rbs, in_rows);
+          group_fetched = true;
         } else {
           for (int32_t b : P->children[a]) {
             if (deferred[b]) {
+              group_fetched = true;
+              holds_leaf[b] = 1;
               s = fetch_leaf(b, out_cols[b], out_rbs[b], out_rows[b]);
               if (s != HAPOD_OK) break;
               deferred[b] = 0;
@@ -963,6 +1081,7 @@ hapod_status hapod_run(hapod_plan_t P, hapod_leaf_fn get_leaf, void* user, void*
         P->m_in[a] = (int64_t)in.size();
         if (P->eps[a] == 0.0) {
           // POD(S, 0) = {(1, s)}: no decomposition; the vectors pass through
+          for (int32_t b : P->children[a]) holds_leaf[a] |= holds_leaf[b];
           P->rank[a] = (int64_t)in.size();
           P->sigma[a].assign(in.size(), 1.0);
           out_cols[a] = in;
@@ -992,11 +1111,11 @@ hapod_status hapod_run(hapod_plan_t P, hapod_leaf_fn get_leaf, void* user, void*
         jobs.push_back(std::move(j));
         job_node.push_back(a);
       }
-      hapod_status s = run_pod_batch(prec, jobs, 0, 1, jmax, P->pool, stream, &lt);
+      void* blk = nullptr;
+      hapod_status s = run_pod_batch(prec, jobs, 0, 1, jmax, P->pool, stream, &lt, &blk);
       if (s != HAPOD_OK) {
         (void)hipStreamSynchronize(stream);
-        for (auto& j : jobs)
-          if (j.out) P->pool.free(j.out);
+        if (blk) P->pool.free(blk);
         release_all();
         return s;
       }
@@ -1009,6 +1128,11 @@ hapod_status hapod_run(hapod_plan_t P, hapod_leaf_fn get_leaf, void* user, void*
         P->lam_min[a] = j.info[2];
         P->n_neg[a] = (int64_t)j.info[3];
         out_buf[a] = j.out;
+        if (j.out && blk) {
+          if (blocks.empty() || blocks.back().first != blk) blocks.push_back({blk, 0});
+          out_blk[a] = (int)blocks.size() - 1;
+          ++blocks.back().second;
+        }
         if (a == P->root) {
           out_cols[a] = column_table(j.out, P->n, j.rank, eb);
           out_rbs[a].assign((size_t)j.rank, kRowBlock);
@@ -1018,18 +1142,28 @@ hapod_status hapod_run(hapod_plan_t P, hapod_leaf_fn get_leaf, void* user, void*
           out_rbs[a].assign((size_t)j.rank, tiled_rbs(j.rank));
           out_rows[a].assign((size_t)j.rank, j.n);
         }
-        if (j.rank == 0 && out_buf[a]) {
-          P->pool.free(out_buf[a]);
-          out_buf[a] = nullptr;
+        if (j.rank == 0 && out_buf[a]) release(a);
+      }
+      // the leaves this group read are no longer needed, unless a
+      // pass-through node still forwards some of their columns upward
+      for (int32_t a : grp)
+        for (int32_t b : P->children[a]) holds_leaf[b] = 0;
+      bool leaf_refs_live = false;
+      for (int32_t i = 0; i < nn && !leaf_refs_live; ++i) leaf_refs_live = holds_leaf[i] != 0;
+      release_pending |= group_fetched;
+      if (release_pending && !leaf_refs_live) {
+        release_pending = false;
+        const int32_t rc = get_leaf(user, -1, nullptr, nullptr, stream_);
+        if (rc != 0) {
+          set_error("leaf provider returned " + std::to_string(rc) + " for the release call");
+          release_all();
+          return HAPOD_E_CALLBACK;
         }
       }
       // the children of this group are consumed
       for (int32_t a : grp)
         for (int32_t b : P->children[a])
-          if (out_buf[b]) {
-            P->pool.free(out_buf[b]);
-            out_buf[b] = nullptr;
-          }
+          if (out_buf[b]) release(b);
     }
     P->level_ms[l] = {lt.gram, lt.eig, lt.trunc, lt.lift};
     pt.gram += lt.gram;
@@ -1069,6 +1203,13 @@ hapod_status hapod_run(hapod_plan_t P, hapod_leaf_fn get_leaf, void* user, void*
   P->root_U = out_buf[P->root];
   out_buf[P->root] = nullptr;
   release_all();
+  // cached blocks speed up the next run of the plan, but not at the price of
+  // starving the caller: with less than a quarter of the device free, return
+  // them
+  {
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) == hipSuccess && free_b < total_b / 4) P->pool.trim();
+  }
   P->has_result = true;
   return HAPOD_OK;
 }
@@ -1181,7 +1322,8 @@ hapod_status gram_impl(int compute, int eb, int64_t n, int64_t m, const void* S,
   }
   Pool& pool = step_pool();
   auto cols = column_table(S, lds, m, eb);
-  const int nt = (int)((m + kGramTile - 1) / kGramTile);
+  const int tile = gram_tile_for(m);
+  const int nt = (int)((m + tile - 1) / tile);
   const int pairs = nt * (nt + 1) / 2;
   const int KB = (compute == 2) ? 32 : 16;
   int nch = (n > 0) ? pick_chunks(n, pairs, 2048, 2048) : 1;
@@ -1196,7 +1338,8 @@ hapod_status gram_impl(int compute, int eb, int64_t n, int64_t m, const void* S,
   HAPOD_TRY(pool.alloc(sizeof(int64_t) * m, &drows));
   HAPOD_TRY(launch_fill_i64((int64_t*)drbs, kRowBlock, m, stream));
   HAPOD_TRY(launch_fill_i64((int64_t*)drows, n, m, stream));
-  if (nch > 1) HAPOD_TRY(pool.alloc(sizeof(double) * pairs * nch * kGramTile * kGramTile, &dpart));
+  const int slots = nch * gram_slots_per_chunk(tile);
+  if (slots > 1) HAPOD_TRY(pool.alloc(sizeof(double) * pairs * slots * tile * tile, &dpart));
   // split-BF16 with several column tiles: read a split twin (as the level batch does)
   void* dsplit = nullptr;
   const bool presplit = (compute == 2 && m >= kPresplitMinCols && n > 0);
@@ -1226,13 +1369,14 @@ hapod_status gram_impl(int compute, int eb, int64_t n, int64_t m, const void* S,
   g.nchunks = nch;
   g.ntiles = nt;
   g.pair_base = 0;
+  g.tile = tile;
   std::vector<GramItem> items;
   std::vector<int32_t> rp, rn;
   int p = 0;
   for (int ti = 0; ti < nt; ++ti)
     for (int tj = ti; tj < nt; ++tj, ++p) {
       for (int c = 0; c < nch; ++c) items.push_back(GramItem{0, (int16_t)ti, (int16_t)tj, c, p});
-      if (nch > 1) {
+      if (slots > 1) {
         rp.push_back(p);
         rn.push_back(0);
       }
@@ -1268,9 +1412,9 @@ hapod_status gram_impl(int compute, int eb, int64_t n, int64_t m, const void* S,
       }
       break;
     }
-    st = launch_gram(compute, (const GramNode*)(db + o_g), (const GramItem*)(db + o_i),
-                     (int)items.size(), (const int32_t*)(db + o_rp), (const int32_t*)(db + o_rn), (int)rp.size(),
-                     vec_ok, stream);
+    const GramLaunch gl{tile, vec_ok ? 1 : 0, 0, (int32_t)items.size(), (compute == 2 && m <= 64) ? 1 : -1};
+    st = launch_gram(compute, (const GramNode*)(db + o_g), (const GramItem*)(db + o_i), &gl, 1,
+                     (const int32_t*)(db + o_rp), (const int32_t*)(db + o_rn), (int)rp.size(), tile, stream);
   } while (0);
   (void)hipStreamSynchronize(stream);
   pool.free(dcols);
@@ -1444,7 +1588,7 @@ hapod_status hapod_lift(hapod_precision prec, int64_t n, int64_t m, int64_t N, c
     if (st != HAPOD_OK) break;
     st = launch_set_scalar_i64((int64_t*)drank, N, stream);
     if (st != HAPOD_OK) break;
-    st = launch_lift(compute_mode(prec), (const LiftNode*)dn, 1, l.row_tiles * l.col_tiles, stream);
+    st = launch_lift(prec == HAPOD_FP64 ? 0 : 1, (const LiftNode*)dn, 1, l.row_tiles * l.col_tiles, stream);
   } while (0);
   (void)hipStreamSynchronize(stream);
   pool.free(dcols);

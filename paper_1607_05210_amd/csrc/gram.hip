@@ -1,26 +1,29 @@
 // Batched Gram matrices G = S^T S of the method of snapshots (Rem. 2.3).
 //
-// Work item = (node, upper tile pair (ti <= tj) of 128 x 128, row chunk).
-// A 256-thread workgroup computes one tile; each of its four wavefronts owns
-// a 64 x 64 sub-tile as 4 x 4 blocks of 16 x 16 MFMA accumulators.  The
-// reduction index of the MFMA is the snapshot row, so every lane streams a
-// contiguous run of rows of one column (column-major input): rows
+// Work item = (node, upper tile pair (ti <= tj), row chunk).  Each
+// wavefront accumulates a WT x WT block (WT = 16 NBW) as NBW x NBW MFMA
+// blocks of 16 x 16.  Two arrangements:
+//   tile 128 (quad): the four wavefronts own the four 64 x 64 quadrants of a
+//     128 x 128 tile (NBW = 4) and stream every row of the chunk;
+//   tile 64 / 32 / 16 (split): every wavefront computes the whole tile
+//     (NBW = 4 / 2 / 1) over a quarter of the chunk's 128-row blocks, so a
+//     narrow node still keeps all four SIMDs busy and the MFMA work is not
+//     padded to 128 columns.
+// The reduction index of the MFMA is the snapshot row, so every lane streams
+// a contiguous run of rows of one column (column-major input): rows
 // [k0 + R*g, k0 + R*g + R) of column c0 + l%16 for lane l = 16 g + l%16.
 // Run element t feeds MFMA number t; the same row permutation is used for
 // both operands, so the contraction is unchanged.
 //
-// Row chunks are accumulated in the MFMA's accumulator (FP64, or FP32 for
-// the FP32 and split-BF16 forms); chunk partial tiles are summed in FP64 by
-// gram_reduce in chunk order, so results do not depend on scheduling.
+// Accumulation is in the MFMA's accumulator (FP64, or FP32 for the FP32 and
+// split-BF16 forms); partial tiles (row chunks, and the wavefronts of a split
+// tile) are summed in FP64 by gram_reduce in a fixed order, so results do not
+// depend on scheduling.
 #include "internal.hpp"
 #include "mfma.hpp"
 
 namespace hapod {
 namespace {
-
-constexpr int T = kGramTile;
-constexpr int WT = 64;
-constexpr int NB = WT / 16;
 
 template <int C> struct GramTraits;
 // FP64 storage, FP64 MFMA 16x16x4: 4-row runs, 16 rows per batch
@@ -59,34 +62,34 @@ __device__ __forceinline__ void run_full(gptr<float> p, float* out) {
   }
 }
 
-template <int C, typename Acc, int R>
-__device__ __forceinline__ void mfma_batch(Acc (&acc)[NB][NB], typename GramTraits<C>::Elem (&va)[NB][R],
-                                           typename GramTraits<C>::Elem (&vb)[NB][R]) {
+template <int C, typename Acc, int R, int NBW>
+__device__ __forceinline__ void mfma_batch(Acc (&acc)[NBW][NBW], typename GramTraits<C>::Elem (&va)[NBW][R],
+                                           typename GramTraits<C>::Elem (&vb)[NBW][R]) {
   if constexpr (C == 0 || C == 3) {
 #pragma unroll
     for (int t = 0; t < R; ++t)
 #pragma unroll
-      for (int a = 0; a < NB; ++a)
+      for (int a = 0; a < NBW; ++a)
 #pragma unroll
-        for (int b = 0; b < NB; ++b) acc[a][b] = mfma_f64((double)va[a][t], (double)vb[b][t], acc[a][b]);
+        for (int b = 0; b < NBW; ++b) acc[a][b] = mfma_f64((double)va[a][t], (double)vb[b][t], acc[a][b]);
   } else if constexpr (C == 1) {
 #pragma unroll
     for (int t = 0; t < R; ++t)
 #pragma unroll
-      for (int a = 0; a < NB; ++a)
+      for (int a = 0; a < NBW; ++a)
 #pragma unroll
-        for (int b = 0; b < NB; ++b) acc[a][b] = mfma_f32(va[a][t], vb[b][t], acc[a][b]);
+        for (int b = 0; b < NBW; ++b) acc[a][b] = mfma_f32(va[a][t], vb[b][t], acc[a][b]);
   } else {
-    bf8 ha[NB], la[NB], hb[NB], lb[NB];
+    bf8 ha[NBW], la[NBW], hb[NBW], lb[NBW];
 #pragma unroll
-    for (int a = 0; a < NB; ++a) {
+    for (int a = 0; a < NBW; ++a) {
       split_bf16x8(va[a], ha[a], la[a]);
       split_bf16x8(vb[a], hb[a], lb[a]);
     }
 #pragma unroll
-    for (int a = 0; a < NB; ++a)
+    for (int a = 0; a < NBW; ++a)
 #pragma unroll
-      for (int b = 0; b < NB; ++b) {
+      for (int b = 0; b < NBW; ++b) {
         acc[a][b] = mfma_bf16(la[a], hb[b], acc[a][b]);
         acc[a][b] = mfma_bf16(ha[a], lb[b], acc[a][b]);
         acc[a][b] = mfma_bf16(ha[a], hb[b], acc[a][b]);
@@ -94,38 +97,42 @@ __device__ __forceinline__ void mfma_batch(Acc (&acc)[NB][NB], typename GramTrai
   }
 }
 
-template <int C, bool VEC>
+template <int C, bool VEC, int NBW, bool QUAD>
 __global__ __launch_bounds__(256) void gram_tile_kernel(const GramNode* __restrict__ nodes,
-                                                        const GramItem* __restrict__ items) {
+                                                        const GramItem* __restrict__ items, int first) {
   using Tr = GramTraits<C>;
   using Elem = typename Tr::Elem;
   using Acc = typename Tr::Acc;
   constexpr int R = Tr::R;
   constexpr int KB = 4 * R;             // rows per MFMA batch
   constexpr int NBT = kRowBlock / KB;   // batches per 128-row block
+  constexpr int WT = 16 * NBW;          // wavefront tile
+  constexpr int TT = QUAD ? 2 * WT : WT;  // workgroup tile
+  constexpr int BSTEP = QUAD ? 1 : 4;   // row blocks between a wavefront's blocks
 
-  const GramItem item = items[xcd_item(blockIdx.x, gridDim.x)];
+  const GramItem item = items[first + xcd_item(blockIdx.x, gridDim.x)];
   const GramNode nd = nodes[item.node];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int wi = wave >> 1, wj = wave & 1;
+  const int wi = QUAD ? (wave >> 1) : 0, wj = QUAD ? (wave & 1) : 0;
   const bool diag = (item.ti == item.tj);
   // the lower sub-tile of a diagonal tile mirrors the upper one
-  if (diag && wi > wj) return;
+  if (QUAD && diag && wi > wj) return;
   const int li = lane & 15, g = lane >> 4;
-  const int cA0 = item.ti * T + wi * WT, cB0 = item.tj * T + wj * WT;
+  const int cA0 = item.ti * TT + wi * WT, cB0 = item.tj * TT + wj * WT;
   if (cA0 >= nd.m || cB0 >= nd.m) return;
+  const bool same = (cA0 == cB0);  // both operands are the same columns
 
   // row range of this chunk; chunks start on 128-row block boundaries
   const int64_t r0 = (int64_t)item.chunk * nd.chunk_rows;
   const int64_t r1 = min(nd.n, r0 + nd.chunk_rows);
 
-  // column bases; columns past m alias the block's first column (their
+  // column bases; columns past m alias the block's last column (their
   // products land in accumulator entries that are never stored)
-  const Elem* pa[NB];
-  const Elem* pb[NB];
-  int64_t sa[NB], sb[NB], ra[NB], rb[NB];
+  const Elem* pa[NBW];
+  const Elem* pb[NBW];
+  int64_t sa[NBW], sb[NBW], ra[NBW], rb[NBW];
 #pragma unroll
-  for (int a = 0; a < NB; ++a) {
+  for (int a = 0; a < NBW; ++a) {
     const int ca = min(cA0 + a * 16 + li, nd.m - 1), cb = min(cB0 + a * 16 + li, nd.m - 1);
     pa[a] = reinterpret_cast<const Elem*>(nd.cols[ca]);
     pb[a] = reinterpret_cast<const Elem*>(nd.cols[cb]);
@@ -135,38 +142,39 @@ __global__ __launch_bounds__(256) void gram_tile_kernel(const GramNode* __restri
     rb[a] = nd.crows[cb];
   }
 
-  Acc acc[NB][NB];
+  Acc acc[NBW][NBW];
 #pragma unroll
-  for (int a = 0; a < NB; ++a)
+  for (int a = 0; a < NBW; ++a)
 #pragma unroll
-    for (int b = 0; b < NB; ++b) acc[a][b] = Acc{0, 0, 0, 0};
+    for (int b = 0; b < NBW; ++b) acc[a][b] = Acc{0, 0, 0, 0};
 
+  const int64_t blk0 = r0 >> 7, nblk = (r1 - r0 + kRowBlock - 1) >> 7;
+  const int64_t bstart = QUAD ? 0 : wave;
   if constexpr (C == 2) {
     if (nd.split) {
       // pre-split columns: hi and lo bf16 runs straight from memory; blocks
       // are zero-padded past n, so every block is read whole
-      const int64_t blk0 = r0 >> 7, nblk = (r1 - r0 + kRowBlock - 1) >> 7;
-      for (int64_t bi = 0; bi < nblk; ++bi) {
-        gptr<bf8> ha[NB], hb[NB];
+      for (int64_t bi = bstart; bi < nblk; bi += BSTEP) {
+        gptr<bf8> ha[NBW], hb[NBW];
 #pragma unroll
-        for (int a = 0; a < NB; ++a) {
+        for (int a = 0; a < NBW; ++a) {
           ha[a] = (gptr<bf8>)as_global(pa[a] + (blk0 + bi) * sa[a]) + g;
           hb[a] = (gptr<bf8>)as_global(pb[a] + (blk0 + bi) * sb[a]) + g;
         }
 #pragma unroll
         for (int bt = 0; bt < NBT; ++bt) {
-          bf8 xh[NB], xl[NB], yh[NB], yl[NB];
+          bf8 xh[NBW], xl[NBW], yh[NBW], yl[NBW];
 #pragma unroll
-          for (int a = 0; a < NB; ++a) {
+          for (int a = 0; a < NBW; ++a) {
             xh[a] = ha[a][4 * bt];
             xl[a] = ha[a][4 * bt + 16];
             yh[a] = hb[a][4 * bt];
             yl[a] = hb[a][4 * bt + 16];
           }
 #pragma unroll
-          for (int a = 0; a < NB; ++a)
+          for (int a = 0; a < NBW; ++a)
 #pragma unroll
-            for (int b = 0; b < NB; ++b) {
+            for (int b = 0; b < NBW; ++b) {
               acc[a][b] = mfma_bf16(xl[a], yh[b], acc[a][b]);
               acc[a][b] = mfma_bf16(xh[a], yl[b], acc[a][b]);
               acc[a][b] = mfma_bf16(xh[a], yh[b], acc[a][b]);
@@ -180,36 +188,41 @@ __global__ __launch_bounds__(256) void gram_tile_kernel(const GramNode* __restri
   // 128-row blocks.  A block every column of the wavefront holds in full
   // runs unguarded at constant offsets; a block some column holds only in
   // part (its last one, or one past its rows) reads guarded.
-  const int64_t blk0 = r0 >> 7, nblk = (r1 - r0 + kRowBlock - 1) >> 7;
-  for (int64_t bi = 0; bi < nblk; ++bi) {
+  for (int64_t bi = bstart; bi < nblk; bi += BSTEP) {
     const int64_t blk = blk0 + bi;
     const int64_t rend = (blk + 1) << 7;
     int lane_full = 1;
 #pragma unroll
-    for (int a = 0; a < NB; ++a) lane_full &= (ra[a] >= rend) & (rb[a] >= rend);
+    for (int a = 0; a < NBW; ++a) lane_full &= (ra[a] >= rend) & (rb[a] >= rend);
     if (__all(lane_full)) {
-      gptr<Elem> qa[NB], qb[NB];
+      gptr<Elem> qa[NBW], qb[NBW];
 #pragma unroll
-      for (int a = 0; a < NB; ++a) {
+      for (int a = 0; a < NBW; ++a) {
         qa[a] = as_global(pa[a] + blk * sa[a] + R * g);
         qb[a] = as_global(pb[a] + blk * sb[a] + R * g);
       }
 #pragma unroll
       for (int bt = 0; bt < NBT; ++bt) {
-        Elem va[NB][R], vb[NB][R];
+        Elem va[NBW][R], vb[NBW][R];
 #pragma unroll
-        for (int a = 0; a < NB; ++a) {
-          run_full<R, VEC>(qa[a] + bt * KB, va[a]);
-          run_full<R, VEC>(qb[a] + bt * KB, vb[a]);
+        for (int a = 0; a < NBW; ++a) run_full<R, VEC>(qa[a] + bt * KB, va[a]);
+        if (!QUAD && same) {
+#pragma unroll
+          for (int a = 0; a < NBW; ++a)
+#pragma unroll
+            for (int t = 0; t < R; ++t) vb[a][t] = va[a][t];
+        } else {
+#pragma unroll
+          for (int a = 0; a < NBW; ++a) run_full<R, VEC>(qb[a] + bt * KB, vb[a]);
         }
-        mfma_batch<C, Acc, R>(acc, va, vb);
+        mfma_batch<C, Acc, R, NBW>(acc, va, vb);
       }
     } else {
       for (int bt = 0; bt < NBT; ++bt) {
         const int64_t row = (blk << 7) + bt * KB + (int64_t)R * g;
-        Elem va[NB][R], vb[NB][R];
+        Elem va[NBW][R], vb[NBW][R];
 #pragma unroll
-        for (int a = 0; a < NB; ++a) {
+        for (int a = 0; a < NBW; ++a) {
           const Elem* xa = pa[a] + blk * sa[a] + (row & (kRowBlock - 1));
           const Elem* xb = pb[a] + blk * sb[a] + (row & (kRowBlock - 1));
 #pragma unroll
@@ -218,19 +231,19 @@ __global__ __launch_bounds__(256) void gram_tile_kernel(const GramNode* __restri
             vb[a][t] = (row + t < rb[a]) ? xb[t] : Elem(0);
           }
         }
-        mfma_batch<C, Acc, R>(acc, va, vb);
+        mfma_batch<C, Acc, R, NBW>(acc, va, vb);
       }
     }
   }
   }
 
 store:
-  // store: direct into G (single chunk) or into the chunk's partial tile
-  if (nd.nchunks == 1) {
+  if (QUAD && nd.nchunks == 1) {
+    // straight into G
 #pragma unroll
-    for (int a = 0; a < NB; ++a)
+    for (int a = 0; a < NBW; ++a)
 #pragma unroll
-      for (int b = 0; b < NB; ++b)
+      for (int b = 0; b < NBW; ++b)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           int row = cA0 + a * 16 + acc_row<Acc>(lane, v);
@@ -242,24 +255,25 @@ store:
           }
         }
   } else {
-    double* P = nd.partial + ((int64_t)(item.pair - nd.pair_base) * nd.nchunks + item.chunk) * (T * T);
+    const int slot = ((item.pair - nd.pair_base) * nd.nchunks + item.chunk) * (QUAD ? 1 : 4) + (QUAD ? 0 : wave);
+    double* P = nd.partial + (int64_t)slot * (TT * TT);
 #pragma unroll
-    for (int a = 0; a < NB; ++a)
+    for (int a = 0; a < NBW; ++a)
 #pragma unroll
-      for (int b = 0; b < NB; ++b)
+      for (int b = 0; b < NBW; ++b)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           int i = wi * WT + a * 16 + acc_row<Acc>(lane, v);
           int j = wj * WT + b * 16 + acc_col(lane);
-          P[j * T + i] = (double)acc[a][b][v];
+          P[j * TT + i] = (double)acc[a][b][v];
         }
   }
 }
 
-// Chunk partials of one tile pair summed in chunk order (so the result does
-// not depend on scheduling); the upper-triangle entries are written to both
-// triangles of G.  Grid: (pair, slice of kReduceSlice tile entries); each
-// thread keeps kReduceUnroll chunk loads in flight.
+// Partial tiles of one tile pair summed in slot order (chunk, then
+// wavefront), so the result does not depend on scheduling; the upper-triangle
+// entries are written to both triangles of G.  Grid: (pair, slice of
+// kReduceSlice tile entries); each thread keeps kReduceUnroll loads in flight.
 constexpr int kReduceSlice = 256;
 constexpr int kReduceUnroll = 8;
 
@@ -269,59 +283,83 @@ __global__ __launch_bounds__(kReduceSlice) void gram_reduce_kernel(const GramNod
   const int node = pair_node[blockIdx.x];
   const int pair = pairs[blockIdx.x];
   const GramNode nd = nodes[node];
+  const int TT = nd.tile;
+  const int e = blockIdx.y * kReduceSlice + threadIdx.x;
+  if (e >= TT * TT) return;
   const int lp = pair - nd.pair_base;
   // recover (ti, tj) from the local pair index in row-major upper order
   int ti = 0, rem = lp, rowlen = nd.ntiles;
   while (rem >= rowlen) { rem -= rowlen; ++ti; --rowlen; }
   const int tj = ti + rem;
-  const int e = blockIdx.y * kReduceSlice + threadIdx.x;
-  const int i = e & (T - 1), j = e / T;
-  const int row = ti * T + i, col = tj * T + j;
+  const int i = e % TT, j = e / TT;
+  const int row = ti * TT + i, col = tj * TT + j;
   if (row >= nd.m || col >= nd.m || row > col) return;
-  const double* P = nd.partial + (int64_t)lp * nd.nchunks * (T * T) + e;
-  const int nc = nd.nchunks;
+  const int ns = nd.nchunks * gram_slots_per_chunk(TT);
+  const int64_t stride = (int64_t)TT * TT;
+  const double* P = nd.partial + (int64_t)lp * ns * stride + e;
   double s = 0.0;
   int c = 0;
-  for (; c + kReduceUnroll <= nc; c += kReduceUnroll) {
+  for (; c + kReduceUnroll <= ns; c += kReduceUnroll) {
     double v[kReduceUnroll];
 #pragma unroll
-    for (int u = 0; u < kReduceUnroll; ++u) v[u] = P[(int64_t)(c + u) * (T * T)];
+    for (int u = 0; u < kReduceUnroll; ++u) v[u] = P[(int64_t)(c + u) * stride];
 #pragma unroll
     for (int u = 0; u < kReduceUnroll; ++u) s += v[u];
   }
-  for (; c < nc; ++c) s += P[(int64_t)c * (T * T)];
+  for (; c < ns; ++c) s += P[(int64_t)c * stride];
   nd.G[(int64_t)col * nd.ldg + row] = s;
   nd.G[(int64_t)row * nd.ldg + col] = s;
 }
 
+template <int C, bool VEC>
+void launch_tile(int tile, const GramNode* d_nodes, const GramItem* d_items, int first, int count,
+                 hipStream_t stream) {
+  const dim3 g(count), b(256);
+  switch (tile) {
+    case 128: hipLaunchKernelGGL((gram_tile_kernel<C, VEC, 4, true>), g, b, 0, stream, d_nodes, d_items, first); break;
+    case 64: hipLaunchKernelGGL((gram_tile_kernel<C, VEC, 4, false>), g, b, 0, stream, d_nodes, d_items, first); break;
+    case 32: hipLaunchKernelGGL((gram_tile_kernel<C, VEC, 2, false>), g, b, 0, stream, d_nodes, d_items, first); break;
+    default: hipLaunchKernelGGL((gram_tile_kernel<C, VEC, 1, false>), g, b, 0, stream, d_nodes, d_items, first); break;
+  }
+}
+
 template <int C>
-hapod_status launch_gram_c(const GramNode* d_nodes, const GramItem* d_items, int num_items,
-                           bool vec_ok, hipStream_t stream) {
-  if (num_items <= 0) return HAPOD_OK;
-  if (vec_ok)
-    hipLaunchKernelGGL((gram_tile_kernel<C, true>), dim3(num_items), dim3(256), 0, stream, d_nodes, d_items);
-  else
-    hipLaunchKernelGGL((gram_tile_kernel<C, false>), dim3(num_items), dim3(256), 0, stream, d_nodes, d_items);
-  HAPOD_HIP(hipGetLastError());
+hapod_status launch_gram_c(const GramNode* d_nodes, const GramItem* d_items, const GramLaunch* launches,
+                           int num_launches, hipStream_t stream) {
+  for (int i = 0; i < num_launches; ++i) {
+    const GramLaunch& L = launches[i];
+    if (L.count <= 0) continue;
+    if (L.tile != 128 && L.tile != 64 && L.tile != 32 && L.tile != 16) {
+      set_error("launch_gram: tile must be 128, 64, 32 or 16");
+      return HAPOD_E_INVALID;
+    }
+    if (L.vec) launch_tile<C, true>(L.tile, d_nodes, d_items, L.first, L.count, stream);
+    else launch_tile<C, false>(L.tile, d_nodes, d_items, L.first, L.count, stream);
+    HAPOD_HIP(hipGetLastError());
+  }
   return HAPOD_OK;
 }
 
 }  // namespace
 
 hapod_status launch_gram(int compute, const GramNode* d_nodes, const GramItem* d_items,
-                         int num_items, const int32_t* d_reduce_pairs,
-                         const int32_t* d_reduce_node, int num_reduce, bool vec_ok,
-                         hipStream_t stream) {
-  switch (compute) {
-    case 0: HAPOD_TRY(launch_gram_c<0>(d_nodes, d_items, num_items, vec_ok, stream)); break;
-    case 1: HAPOD_TRY(launch_gram_c<1>(d_nodes, d_items, num_items, vec_ok, stream)); break;
-    case 2: HAPOD_TRY(launch_gram_c<2>(d_nodes, d_items, num_items, vec_ok, stream)); break;
-    case 3: HAPOD_TRY(launch_gram_c<3>(d_nodes, d_items, num_items, vec_ok, stream)); break;
-    default: set_error("launch_gram: unknown compute mode"); return HAPOD_E_INVALID;
+                         const GramLaunch* launches, int num_launches,
+                         const int32_t* d_reduce_pairs, const int32_t* d_reduce_node, int num_reduce,
+                         int max_tile, hipStream_t stream) {
+  for (int i = 0; i < num_launches; ++i) {
+    const int c = launches[i].compute >= 0 ? launches[i].compute : compute;
+    switch (c) {
+      case 0: HAPOD_TRY(launch_gram_c<0>(d_nodes, d_items, launches + i, 1, stream)); break;
+      case 1: HAPOD_TRY(launch_gram_c<1>(d_nodes, d_items, launches + i, 1, stream)); break;
+      case 2: HAPOD_TRY(launch_gram_c<2>(d_nodes, d_items, launches + i, 1, stream)); break;
+      case 3: HAPOD_TRY(launch_gram_c<3>(d_nodes, d_items, launches + i, 1, stream)); break;
+      default: set_error("launch_gram: unknown compute mode"); return HAPOD_E_INVALID;
+    }
   }
   if (num_reduce > 0) {
-    hipLaunchKernelGGL(gram_reduce_kernel, dim3(num_reduce, (T * T) / kReduceSlice), dim3(kReduceSlice), 0,
-                       stream, d_nodes, d_reduce_pairs, d_reduce_node);
+    const unsigned slices = (unsigned)((max_tile * max_tile + kReduceSlice - 1) / kReduceSlice);
+    hipLaunchKernelGGL(gram_reduce_kernel, dim3(num_reduce, slices), dim3(kReduceSlice), 0, stream, d_nodes,
+                       d_reduce_pairs, d_reduce_node);
     HAPOD_HIP(hipGetLastError());
   }
   return HAPOD_OK;

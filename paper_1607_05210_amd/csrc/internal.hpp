@@ -43,10 +43,18 @@ __host__ __device__ inline int64_t blk_off(int64_t r, int64_t rbs) {
 
 // ---- batched Gram ----------------------------------------------------------
 // One node's input: m columns, column j starting at cols[j] with row-block
-// stride rbs[j] (device arrays), rows [0, n).  Tiles of kGramTile x kGramTile on the upper triangle;
-// rows split into nchunks chunks of chunk_rows.  With nchunks == 1 the tile is
-// written straight into G (both triangles); otherwise into
-// partial[(pair * nchunks + chunk) * T*T] and reduced by gram_reduce.
+// stride rbs[j] (device arrays), rows [0, n).  The upper triangle is cut into
+// tile x tile blocks (tile = 128, 64, 32 or 16); rows are split into nchunks
+// chunks of chunk_rows.
+//   tile 128: the four wavefronts of a workgroup own the four 64 x 64
+//             quadrants of the tile.  With nchunks == 1 the tile goes straight
+//             into G (both triangles); otherwise into partial slot
+//             (pair * nchunks + chunk).
+//   tile <= 64: every wavefront computes the whole tile over its own quarter
+//             of the chunk's 128-row blocks and writes partial slot
+//             (pair * nchunks + chunk) * 4 + wave.
+// Partial slots hold tile * tile doubles (column-major) and are summed in
+// slot order by gram_reduce.
 constexpr int kGramTile = 128;
 
 struct GramNode {
@@ -60,11 +68,12 @@ struct GramNode {
   int64_t ldg;
   int32_t m;
   int32_t nchunks;
-  int32_t ntiles;      // ceil(m / T)
+  int32_t ntiles;      // ceil(m / tile)
   int32_t pair_base;   // first tile-pair index of this node in the level
   int32_t split;       // 1: columns hold split-BF16 blocks (see launch_split_cols)
-  int32_t pad;
+  int32_t tile;        // 128, 64, 32 or 16
 };
+__host__ __device__ inline int gram_slots_per_chunk(int tile) { return tile == kGramTile ? 1 : 4; }
 
 struct GramItem {
   int32_t node;
@@ -75,10 +84,23 @@ struct GramItem {
 
 // compute: 0 = FP64 MFMA (double storage), 1 = FP32 MFMA (float storage),
 //          2 = split-BF16 x3 (float storage), 3 = FP64 MFMA (float storage)
+// Items of one tile size go in one launch: launches[i] covers items
+// [first, first + count) of d_items, all of nodes with that tile.  The reduce
+// pass covers num_reduce (pair, node) entries over tiles up to max_tile.
+// vec: every column of these nodes starts 16-byte aligned and the chunk
+// length is a multiple of the MFMA batch, so runs are read as vectors.
+// compute >= 0 overrides the launch_gram compute mode for these items.
+struct GramLaunch {
+  int32_t tile;
+  int32_t vec;
+  int32_t first;
+  int32_t count;
+  int32_t compute;
+};
 hapod_status launch_gram(int compute, const GramNode* d_nodes, const GramItem* d_items,
-                         int num_items, const int32_t* d_reduce_pairs,
-                         const int32_t* d_reduce_node, int num_reduce, bool vec_ok,
-                         hipStream_t stream);
+                         const GramLaunch* launches, int num_launches,
+                         const int32_t* d_reduce_pairs, const int32_t* d_reduce_node, int num_reduce,
+                         int max_tile, hipStream_t stream);
 
 // ---- batched Jacobi eigensolver -------------------------------------------
 struct EigNode {
@@ -155,9 +177,12 @@ struct LiftNode {
                          // items are ceil(row_tiles / rt_per) x col_tiles
   int32_t pad;
 };
-// compute as for launch_gram (0, 1, 2); output storage = input storage
+// compute as for launch_gram (0, 1, 2); output storage = input storage.
+// narrow: every node has N <= 64 and its tiles are kLiftNarrowM x 64
+// (row_tiles and col_tiles counted for that tile).
+constexpr int kLiftNarrowM = 256;
 hapod_status launch_lift(int compute, const LiftNode* d_nodes, int num_nodes,
-                         int num_items, hipStream_t stream);
+                         int num_items, hipStream_t stream, bool narrow = false);
 
 // ---- helpers ----------------------------------------------------------------
 hapod_status launch_fill_colptrs(const void* base, int64_t ld, int64_t m, int elem_bytes,

@@ -52,8 +52,12 @@ __device__ __forceinline__ void run4(const float* p, int64_t avail, float (&out)
   }
 }
 
-template <int C>
+// NARROW (ranks up to 64): a 256 x 64 tile, the four wavefronts stacked
+// along the rows, so that no wavefront idles on columns past N.
+template <int C, bool NARROW>
 __global__ __launch_bounds__(256) void lift_kernel(const LiftNode* __restrict__ nodes, int num_nodes) {
+  constexpr int TMk = NARROW ? 4 * WT : TM;
+  constexpr int TNk = NARROW ? WT : TN;
   using Tr = LiftTraits<C>;
   using Elem = typename Tr::Elem;
   using Acc = typename Tr::Acc;
@@ -73,7 +77,7 @@ __global__ __launch_bounds__(256) void lift_kernel(const LiftNode* __restrict__ 
   const int local = item - nd.item_base;
   const int rg = local / nd.col_tiles, ct = local % nd.col_tiles;
   const int64_t N = *nd.rank;
-  if ((int64_t)ct * TN >= N) return;  // whole workgroup
+  if ((int64_t)ct * TNk >= N) return;  // whole workgroup
   const int rt_per = max(nd.rt_per, 1);
   const int rt_begin = rg * rt_per, rt_end = min(rt_begin + rt_per, nd.row_tiles);
 
@@ -82,9 +86,9 @@ __global__ __launch_bounds__(256) void lift_kernel(const LiftNode* __restrict__ 
   __shared__ int64_t trows[KT];
 
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int wi = wave >> 1, wj = wave & 1;
+  const int wi = NARROW ? wave : (wave >> 1), wj = NARROW ? 0 : (wave & 1);
   const int li = lane & 15, g = lane >> 4;
-  const int64_t n0 = (int64_t)ct * TN + wj * WT;
+  const int64_t n0 = (int64_t)ct * TNk + wj * WT;
   const int64_t nl = n0 + 4 * li;   // first of the lane's 4 output columns
   const int64_t bavail = N - nl;
   const BElem* bop;
@@ -106,7 +110,7 @@ __global__ __launch_bounds__(256) void lift_kernel(const LiftNode* __restrict__ 
   }
 
   for (int rt = rt_begin; rt < rt_end; ++rt) {
-  const int64_t r0 = (int64_t)rt * TM + wi * WT;
+  const int64_t r0 = (int64_t)rt * TMk + wi * WT;
   const bool active = (r0 < nd.n) && (n0 < N);
   const int64_t rl = r0 + 4 * li;   // first of the lane's 4 rows (one row block)
   const int64_t roff = rl & (kRowBlock - 1), rblk = rl >> 7;
@@ -266,12 +270,16 @@ __global__ __launch_bounds__(256) void lift_kernel(const LiftNode* __restrict__ 
 }  // namespace
 
 hapod_status launch_lift(int compute, const LiftNode* d_nodes, int num_nodes, int num_items,
-                         hipStream_t stream) {
+                         hipStream_t stream, bool narrow) {
   if (num_items <= 0) return HAPOD_OK;
-  switch (compute) {
-    case 0: hipLaunchKernelGGL(lift_kernel<0>, dim3(num_items), dim3(256), 0, stream, d_nodes, num_nodes); break;
-    case 1: hipLaunchKernelGGL(lift_kernel<1>, dim3(num_items), dim3(256), 0, stream, d_nodes, num_nodes); break;
-    case 2: hipLaunchKernelGGL(lift_kernel<2>, dim3(num_items), dim3(256), 0, stream, d_nodes, num_nodes); break;
+  const dim3 g(num_items), b(256);
+  switch (compute * 2 + (narrow ? 1 : 0)) {
+    case 0: hipLaunchKernelGGL((lift_kernel<0, false>), g, b, 0, stream, d_nodes, num_nodes); break;
+    case 1: hipLaunchKernelGGL((lift_kernel<0, true>), g, b, 0, stream, d_nodes, num_nodes); break;
+    case 2: hipLaunchKernelGGL((lift_kernel<1, false>), g, b, 0, stream, d_nodes, num_nodes); break;
+    case 3: hipLaunchKernelGGL((lift_kernel<1, true>), g, b, 0, stream, d_nodes, num_nodes); break;
+    case 4: hipLaunchKernelGGL((lift_kernel<2, false>), g, b, 0, stream, d_nodes, num_nodes); break;
+    case 5: hipLaunchKernelGGL((lift_kernel<2, true>), g, b, 0, stream, d_nodes, num_nodes); break;
     default: set_error("launch_lift: unknown compute mode"); return HAPOD_E_INVALID;
   }
   HAPOD_HIP(hipGetLastError());

@@ -298,3 +298,73 @@ def test_chain_streamed_through_one_buffer(hp):
     r = metrics.resolved_rank(s_ref, len(sig), UP["fp64"], 1e-6)
     assert metrics.subspace_error(U_ref, host(U), r) <= 1e-6
     assert metrics.mean_projection_error(S, host(U)) <= eps_star ** 2
+
+
+def test_release_call_waits_for_forwarded_leaf_data(hp):
+    """The provider's release call (leaf = -1) may only come once no leaf
+    handed over is read again.  Leaves 0 and 1 have eps = 0 and sit under a
+    pass-through node (eps = 0), so their data is read by the root's group,
+    two groups after leaves 2 and 3.  The provider overwrites every buffer it
+    handed out with NaN when told to release: a read after that would turn
+    into a NaN Gram diagonal (E_NUMERIC) or wrong modes."""
+    n, per = 2048, 20
+    parent = [4, 4, 5, 5, 6, 6, -1]
+    S = synth.sinusoid(n, 4 * per, 60, 6.0, 1e-10, seed=21)
+    data = {i: np.ascontiguousarray(S[:, i * per:(i + 1) * per]) for i in range(4)}
+    cols = [per] * 4 + [0, 0, 0]
+    eps = tolerances.hapod_tolerances(parent, cols, 1e-4, 0.75)
+    ov = [-1.0] * 7
+    for z in (0, 1, 4):
+        ov[z] = 0.0
+        eps[z] = 0.0
+    plan = hp.Plan(parent, cols, n, 1e-4, 0.75, prec="fp64", eps_override=ov)
+    handed, events = [], []
+
+    class Provider:
+        def __call__(self, leaf):
+            t = dev_colmajor(data[leaf])
+            handed.append(t)
+            events.append(leaf)
+            return t
+
+        def release(self):
+            events.append(-1)
+            for t in handed:
+                t.fill_(float("nan"))
+            handed.clear()
+
+    plan.run(Provider(), hold=False)
+    # leaves 2, 3 (level 1) and their release; 0, 1 fetched by the
+    # pass-through node's group and released only after the root's group
+    assert events == [2, 3, -1, 0, 1, -1]
+    ref = hapod.hapod(parent, data, eps)
+    s_ref, U_ref = ref[6]
+    sig, U = plan.modes()
+    r = metrics.resolved_rank(s_ref, len(sig), UP["fp64"], 1e-6)
+    assert metrics.subspace_error(U_ref, host(U), r) <= 1e-6
+
+
+def test_split_twins_in_groups_match_single_arena(hp, monkeypatch):
+    """Split-BF16 nodes of 256 or more columns read a pre-split twin of their
+    input; when the twins of a level do not fit the arena together they are
+    made and consumed group by group.  The result is bitwise the same."""
+    n, per = 4096, 300
+    S = synth.sinusoid(n, 3 * per, 120, 12.0, 1e-10, seed=33).astype(np.float32)
+    leaves = {i: dev_colmajor(np.ascontiguousarray(S[:, i * per:(i + 1) * per]), torch.float32)
+              for i in range(3)}
+    parent = synth.star_tree(3)
+    cols = [per] * 3 + [0]
+
+    def run():
+        plan = hp.Plan(parent, cols, n, 1e-3, 0.75, prec="bf16x3")
+        plan.run(leaves)
+        sig, U = plan.modes()
+        return sig, host(U), plan.ranks()
+
+    s1, U1, r1 = run()
+    twin = n * per * 4
+    monkeypatch.setenv("HAPOD_TWIN_BUDGET", str(twin + twin // 2))   # one twin per group
+    s2, U2, r2 = run()
+    assert list(r1) == list(r2)
+    np.testing.assert_array_equal(s1, s2)
+    np.testing.assert_array_equal(U1, U2)
