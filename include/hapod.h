@@ -63,10 +63,9 @@ typedef enum {
 typedef enum {
   HAPOD_FP64 = 0,    /* Gram and lift on FP64 MFMA, double storage                         */
   HAPOD_FP32 = 1,    /* Gram and lift on FP32 MFMA, FP32 accumulation, float storage       */
-  HAPOD_BF16X3 = 2   /* float storage; Gram of nodes wider than 64 columns as split-BF16,
+  HAPOD_BF16X3 = 2   /* float storage; Gram of nodes of 256 or more columns as split-BF16,
                         three products hi*hi + hi*lo + lo*hi on BF16 MFMA with FP32
-                        accumulation; narrower Grams (bandwidth-bound) and all lifts on
-                        FP32 MFMA                                                      */
+                        accumulation; narrower Grams and all lifts on FP32 MFMA        */
 } hapod_precision;
 
 /* ------------------------------------------------------------------------ */
@@ -177,8 +176,9 @@ typedef struct {
   int32_t jacobi_max;              /* k > 0: nodes with at most k input columns (k <= 1024)
                                       take the Jacobi eigensolver, wider ones Lanczos.
                                       0: automatic -- Jacobi up to 128 columns; 129..256
-                                      Jacobi when the launch group has 3 or more such
-                                      nodes, else Lanczos; Lanczos above 256          */
+                                      a full-length Lanczos run (every eigenpair, as
+                                      Jacobi gives); above 256 Lanczos stopped at the
+                                      Gram's rounding level                          */
   int32_t leaf_wave;               /* 0: all leaves of a level in one launch group; k > 0:
                                       at most k leaves per group, so the provider needs at
                                       most k leaves resident at a time                     */

@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <array>
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <map>
@@ -33,7 +34,7 @@ int elem_bytes(hapod_precision p) { return p == HAPOD_FP64 ? 8 : 4; }
 int compute_mode(hapod_precision p) { return p == HAPOD_FP64 ? 0 : (p == HAPOD_FP32 ? 1 : 2); }
 
 constexpr size_t kAlign = 256;
-constexpr int64_t kPresplitMinCols = 129;
+constexpr int64_t kPresplitMinCols = 256;
 
 // plain column-major n x m (leading dimension ld)
 std::vector<const void*> column_table(const void* base, int64_t ld, int64_t m, int eb) {
@@ -228,12 +229,12 @@ int gram_tile_for(int64_t m) {
 
 // Eigensolver choice.  jacobi_max > 0: Jacobi up to that width, Lanczos
 // above.  jacobi_max <= 0 (automatic): Jacobi in LDS up to kJacobiLdsMax;
-// between that and kAutoJacobiMax the global-memory Jacobi when the batch has
-// enough such nodes to run side by side (one workgroup each), else Lanczos,
-// whose cost grows with m instead of m^3 on one workgroup; Lanczos above.
+// between that and kAutoJacobiMax a full-length Lanczos run (every
+// eigenpair, as Jacobi gives, at a cost growing with m instead of m^3 on one
+// workgroup; all such nodes of a batch iterate together); above, Lanczos
+// stopped at the Gram's rounding level.
 constexpr int kAutoJacobiMax = 256;
 constexpr int64_t kLiftTargetItems = 2048;  // lift workgroups per launch to aim for
-constexpr int kMinJacobiBatch = 3;
 
 hapod_status run_pod_batch(hapod_precision prec, std::vector<PodJob>& jobs, int policy_small, int policy_wide,
                            int jacobi_max, Pool& pool, hipStream_t stream, PhaseTimes* times,
@@ -263,8 +264,6 @@ hapod_status run_pod_batch(hapod_precision prec, std::vector<PodJob>& jobs, int 
     sum_pairs += nt * (nt + 1) / 2;
   }
   const int target_items = std::max(2048, sum_pairs);
-  int mid_nodes = 0;
-  for (auto& j : jobs) mid_nodes += (j.m > kJacobiLdsMax && j.m <= kAutoJacobiMax) ? 1 : 0;
   // split twins take as much memory as their inputs.  They are made and
   // consumed in groups that fit an arena of at most half of what the device
   // has free (and of what the plan's cap leaves): the Gram of one group runs
@@ -290,8 +289,7 @@ hapod_status run_pod_batch(hapod_precision prec, std::vector<PodJob>& jobs, int 
     PodJob& j = jobs[i];
     Lay& L = lay[i];
     const int64_t m = j.m;
-    j.wide = (jacobi_max > 0) ? (m > jacobi_max)
-                              : (m > kAutoJacobiMax || (m > kJacobiLdsMax && mid_nodes < kMinJacobiBatch));
+    j.wide = (jacobi_max > 0) ? (m > jacobi_max) : (m > kJacobiLdsMax);
     // a node taken from Jacobi only for speed keeps Jacobi's result: all
     // eigenpairs (a full Lanczos run) and the same truncation policy
     j.wide_full = j.wide && jacobi_max <= 0 && m <= kAutoJacobiMax;
@@ -412,9 +410,10 @@ hapod_status run_pod_batch(hapod_precision prec, std::vector<PodJob>& jobs, int 
     g.ntiles = L.ntiles;
     g.pair_base = pair_base;
     g.tile = L.tile;
-    // split-BF16 nodes of at most 64 columns are bandwidth-bound: their Gram
-    // runs on FP32 MFMA (no in-register split), in launch slots of their own
-    const bool f32 = (compute == 2 && m <= 64);
+    // split-BF16 nodes narrower than the pre-split threshold run their Gram on
+    // FP32 MFMA: splitting in registers costs more VALU time than the three
+    // BF16 products save at these widths (launch slots of their own)
+    const bool f32 = (compute == 2 && m < kPresplitMinCols);
     std::vector<GramItem>& gi =
         items_by_tile[twin_group[i]][(f32 ? 8 : 0) + 2 * tile_slot(L.tile) + (vec ? 1 : 0)];
     int p = pair_base;
@@ -536,12 +535,20 @@ hapod_status run_pod_batch(hapod_precision prec, std::vector<PodJob>& jobs, int 
     HAPOD_TRY(launch_jacobi((const EigNode*)(dblob + o_es), (int)enodes_small.size(), max_small, stream));
   if (!enodes_big.empty())
     HAPOD_TRY(launch_jacobi((const EigNode*)(dblob + o_eb), (int)enodes_big.size(), max_big, stream));
+  // wide nodes: one batched Krylov eigensolve for all of them
+  std::vector<WideResult> wres(nj);
+  {
+    std::vector<WideJob> wj;
+    for (int i = 0; i < nj; ++i) {
+      if (!jobs[i].wide || jobs[i].m <= 0) continue;
+      wj.push_back(WideJob{gnodes[i].G, jobs[i].m, jobs[i].m, (double*)(scratch + lay[i].lam),
+                           (double*)(scratch + lay[i].V), jobs[i].m, jobs[i].wide_full, &wres[i]});
+    }
+    if (!wj.empty()) HAPOD_TRY(wide_eigh_batch(wj, u_p, &pool_alloc_cb, &pool_free_cb, &pool, stream));
+  }
   for (int i = 0; i < nj; ++i) {
-    if (!jobs[i].wide) continue;
-    WideResult wr;
-    HAPOD_TRY(wide_eigh(gnodes[i].G, jobs[i].m, jobs[i].m, (double*)(scratch + lay[i].lam),
-                        (double*)(scratch + lay[i].V), jobs[i].m, u_p, &pool_alloc_cb, &pool_free_cb,
-                        &pool, stream, &wr, jobs[i].wide_full));
+    if (!jobs[i].wide || jobs[i].m <= 0) continue;
+    const WideResult& wr = wres[i];
     // eigenvalues beyond the computed block are set to zero by wide_eigh;
     // the floor of the truncation is the Gram's rounding level
     tnodes[i].floor_abs = wr.floor_abs;
@@ -561,6 +568,10 @@ hapod_status run_pod_batch(hapod_precision prec, std::vector<PodJob>& jobs, int 
       // the Krylov space broke down before spanning the matrix (an exact
       // multiplicity): fall back to the dense Jacobi eigensolver
       const int m = (int)jobs[i].m;
+      if (const char* v = std::getenv("HAPOD_VERBOSE"))
+        if (v[0] == '1')
+          std::fprintf(stderr, "[hapod] m=%d: Krylov run left %.3e of trace %.3e unresolved (slack %.3e): Jacobi\n",
+                       m, wr.unresolved, wr.trace, jobs[i].wide_slack);
       void *jw = nullptr, *vw = nullptr, *de = nullptr;
       HAPOD_TRY(pool.alloc(sizeof(double) * jacobi_work_doubles(m), &jw));
       hapod_status s = pool.alloc(sizeof(double) * jacobi_vwork_doubles(m), &vw);
@@ -1412,7 +1423,7 @@ hapod_status gram_impl(int compute, int eb, int64_t n, int64_t m, const void* S,
       }
       break;
     }
-    const GramLaunch gl{tile, vec_ok ? 1 : 0, 0, (int32_t)items.size(), (compute == 2 && m <= 64) ? 1 : -1};
+    const GramLaunch gl{tile, vec_ok ? 1 : 0, 0, (int32_t)items.size(), (compute == 2 && m < kPresplitMinCols) ? 1 : -1};
     st = launch_gram(compute, (const GramNode*)(db + o_g), (const GramItem*)(db + o_i), &gl, 1,
                      (const int32_t*)(db + o_rp), (const int32_t*)(db + o_rn), (int)rp.size(), tile, stream);
   } while (0);

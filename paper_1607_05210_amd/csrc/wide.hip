@@ -6,10 +6,14 @@
 //   step j: w = G q_j; two passes of classical Gram-Schmidt against
 //           q_0..q_j (h = Q^T w, w -= Q h); alpha_j = sum of the two
 //           coefficients of q_j; beta_j = ||w||; q_{j+1} = w / beta_j.
+//           If beta_j <= 1e-10 ||G q_j|| the space is numerically invariant:
+//           beta_j = 0 and q_{j+1} is a fresh random vector orthogonalised
+//           (two passes) against q_0..q_j.
 //   T = tridiag(beta, alpha, beta) (k x k).  Its eigenvalues theta_i come from
-//   Sturm-sequence bisection (one thread per eigenvalue), its eigenvectors
-//   z_i from inverse iteration with a pivoted tridiagonal LU (one thread per
-//   eigenvector).  Ritz pairs: (theta_i, Q z_i), residual beta_{k-1} |z_i[k-1]|.
+//   Sturm-sequence multisection (one wavefront per eigenvalue), its
+//   eigenvectors z_i from inverse iteration with a pivoted tridiagonal LU
+//   (one thread per eigenvector; one thread per cluster of equal
+//   eigenvalues, orthogonalising within the cluster).  Ritz pairs: (theta_i, Q z_i), residual beta_{k-1} |z_i[k-1]|.
 //
 // The pairs returned are the leading Ritz pairs whose residual is below the
 // Gram's rounding level or 1e-8 of their value, extended (when the iteration
@@ -20,6 +24,13 @@
 // caller learns whether the Krylov space reached the rounding level (else the
 // spectrum past the block is unknown) and how much of trace(G) the returned
 // pairs leave unexplained.
+//
+// Several matrices are solved together: every kernel of a step takes the list
+// of matrices still iterating (grid z), so a level with many wide nodes costs
+// one launch per kernel per step instead of one per node; a matrix leaves the
+// list when its own stopping test is met.  Each matrix's arithmetic is the
+// same as when it is solved alone.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -35,6 +46,7 @@ constexpr int kMaxSteps = kWideMaxSteps;
 constexpr int kMinSteps = 128;      // no stop before this many steps
 constexpr int kCheckEvery = 32;     // stopping test period
 constexpr double kPlateau = 0.7;    // beta_j >= 0.7 beta_{j-32}: plateau
+constexpr double kBreakdownTol = 1e-10;  // beta_j <= 1e-10 ||G q_j||: restart
 
 __device__ __forceinline__ double hash_unit(uint64_t x) {
   // splitmix64 finaliser -> uniform in [-0.5, 0.5)
@@ -51,44 +63,80 @@ __device__ double wave_sum(double v) {
   return v;
 }
 
+// Per-matrix state of the batched Lanczos iteration (device array).
+struct LzNode {
+  const double* G;
+  int64_t ldg;
+  int64_t m;
+  double* Q;       // m x (k + 1) Lanczos vectors, column-major
+  double* w;       // m
+  double* h;       // (k + 1) x nrc projection partials
+  double* alpha;   // k
+  double* beta;    // k + 1
+  double* theta;   // k Ritz values (descending)
+  double* e2;      // k x ceil(k / 4) bisection scratch
+  double* Z;       // k x k eigenvectors of T, Z[r * kk + i]
+  double* last;    // k: last components of the z_i
+  double* isc;     // 5 k^2 inverse-iteration scratch
+  int* ipiv;       // k^2
+  double* tr;      // trace(G)
+  double* wn;      // nrc partial sums of ||G q_j||^2
+  double* V;       // outputs
+  double* lambda;
+  int64_t ldv;
+  int32_t nrc;
+  int32_t kk;      // steps taken (tridiagonal phase)
+  int32_t b;       // eigenpairs returned
+  int32_t pad;
+};
+
 // q = random, unnormalised (normalised by the finish kernel)
-__global__ void lanczos_init_kernel(double* w, int64_t m) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x)
-    w[i] = hash_unit((uint64_t)i * 7919u + 17u);
+__global__ void lanczos_init_kernel(const LzNode* __restrict__ nodes) {
+  const LzNode n = nodes[blockIdx.z];
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n.m; i += (int64_t)gridDim.x * blockDim.x)
+    n.w[i] = hash_unit((uint64_t)i * 7919u + 17u);
 }
 
-// w[c] = G[:, c] . q  (G symmetric), one wavefront per column
-__global__ __launch_bounds__(256) void matvec_kernel(const double* __restrict__ G, int64_t ldg, int64_t m,
-                                                     const double* __restrict__ q, double* __restrict__ w) {
+// w[c] = G[:, c] . q_j  (G symmetric), one wavefront per column
+__global__ __launch_bounds__(256) void matvec_kernel(const LzNode* __restrict__ nodes, const int* __restrict__ act,
+                                                     int j) {
+  const LzNode n = nodes[act[blockIdx.z]];
   const int64_t c = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
-  if (c >= m) return;
-  const double* col = G + c * ldg;
+  if (c >= n.m) return;
+  const double* col = n.G + c * n.ldg;
+  const double* q = n.Q + (int64_t)j * n.m;
   double s = 0.0;
-  for (int64_t r = lane; r < m; r += 64) s += col[r] * q[r];
+  for (int64_t r = lane; r < n.m; r += 64) s += col[r] * q[r];
   s = wave_sum(s);
-  if (lane == 0) w[c] = s;
+  if (lane == 0) n.w[c] = s;
 }
 
 constexpr int kProjCols = 16;    // Lanczos vectors per projection workgroup
 constexpr int kProjRows = 1024;  // rows per projection workgroup
 
-// partial[c * nrc + rc] = Q[rows of chunk rc, c] . w[rows of chunk rc], c <= j
-__global__ __launch_bounds__(256) void proj_partial_kernel(const double* __restrict__ Q, int64_t m, int j,
-                                                           const double* __restrict__ w,
-                                                           double* __restrict__ partial, int nrc) {
+// h[c * nrc + rc] = Q[rows of chunk rc, c] . w[rows of chunk rc], c <= j
+__global__ __launch_bounds__(256) void proj_partial_kernel(const LzNode* __restrict__ nodes,
+                                                           const int* __restrict__ act, int j, int wn_pass) {
+  const LzNode n = nodes[act[blockIdx.z]];
   __shared__ double red[kProjCols][4];
+  __shared__ double rn[4];
   const int c0 = blockIdx.x * kProjCols, rc = blockIdx.y;
+  if (rc >= n.nrc) return;
   const int ncols = min(kProjCols, j + 1 - c0);
-  const int64_t r0 = (int64_t)rc * kProjRows, r1 = min(m, r0 + kProjRows);
+  const int64_t r0 = (int64_t)rc * kProjRows, r1 = min(n.m, r0 + kProjRows);
+  // the first pass of a step also records ||w||^2 = ||G q_j||^2 per row chunk
+  const bool norm = (blockIdx.x == 0) && (wn_pass != 0);
   double acc[kProjCols];
+  double ww = 0.0;
 #pragma unroll
   for (int c = 0; c < kProjCols; ++c) acc[c] = 0.0;
   for (int64_t r = r0 + threadIdx.x; r < r1; r += blockDim.x) {
-    const double wr = w[r];
+    const double wr = n.w[r];
+    ww += wr * wr;
 #pragma unroll
     for (int c = 0; c < kProjCols; ++c)
-      if (c < ncols) acc[c] += Q[(int64_t)(c0 + c) * m + r] * wr;
+      if (c < ncols) acc[c] += n.Q[(int64_t)(c0 + c) * n.m + r] * wr;
   }
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
@@ -96,42 +144,50 @@ __global__ __launch_bounds__(256) void proj_partial_kernel(const double* __restr
     const double v = wave_sum(acc[c]);
     if (lane == 0) red[c][wave] = v;
   }
+  if (norm) {
+    const double v = wave_sum(ww);
+    if (lane == 0) rn[wave] = v;
+  }
   __syncthreads();
+  if (norm && threadIdx.x == 0) n.wn[rc] = rn[0] + rn[1] + rn[2] + rn[3];
   if (threadIdx.x < ncols)
-    partial[(int64_t)(c0 + threadIdx.x) * nrc + rc] =
+    n.h[(int64_t)(c0 + threadIdx.x) * n.nrc + rc] =
         red[threadIdx.x][0] + red[threadIdx.x][1] + red[threadIdx.x][2] + red[threadIdx.x][3];
 }
 
-// h[c] = sum over row chunks of partial[c] (fixed order); w -= Q[:, 0..j] h;
-// alpha_j += h[j].  64 rows per workgroup, columns split over 4 wavefronts.
-__global__ __launch_bounds__(256) void update_kernel(const double* __restrict__ Q, int64_t m, int j,
-                                                     double* __restrict__ w, const double* __restrict__ partial,
-                                                     int nrc, double* __restrict__ alpha) {
+// hc = sum over row chunks of h[c] (fixed order); w -= Q[:, 0..j] hc;
+// alpha_j += hc[j].  64 rows per workgroup, columns split over 4 wavefronts.
+__global__ __launch_bounds__(256) void update_kernel(const LzNode* __restrict__ nodes, const int* __restrict__ act,
+                                                     int j) {
+  const LzNode n = nodes[act[blockIdx.z]];
+  if ((int64_t)blockIdx.x * 64 >= n.m) return;  // whole workgroup
   __shared__ double hs[kMaxSteps + 1];
   __shared__ double part[4][64];
   for (int c = threadIdx.x; c <= j; c += blockDim.x) {
     double t = 0.0;
-    for (int rc = 0; rc < nrc; ++rc) t += partial[(int64_t)c * nrc + rc];
+    for (int rc = 0; rc < n.nrc; ++rc) t += n.h[(int64_t)c * n.nrc + rc];
     hs[c] = t;
   }
   __syncthreads();
-  if (blockIdx.x == 0 && threadIdx.x == 0) alpha[j] += hs[j];
+  if (blockIdx.x == 0 && threadIdx.x == 0) n.alpha[j] += hs[j];
   const int rl = threadIdx.x & 63, cg = threadIdx.x >> 6;
   const int64_t i = (int64_t)blockIdx.x * 64 + rl;
   double t = 0.0;
-  if (i < m)
-    for (int c = cg; c <= j; c += 4) t += Q[(int64_t)c * m + i] * hs[c];
+  if (i < n.m)
+    for (int c = cg; c <= j; c += 4) t += n.Q[(int64_t)c * n.m + i] * hs[c];
   part[cg][rl] = t;
   __syncthreads();
-  if (cg == 0 && i < m) w[i] -= part[0][rl] + part[1][rl] + part[2][rl] + part[3][rl];
+  if (cg == 0 && i < n.m) n.w[i] -= part[0][rl] + part[1][rl] + part[2][rl] + part[3][rl];
 }
 
-// beta = ||w||, q_next = w / beta (single workgroup)
-__global__ __launch_bounds__(1024) void finish_kernel(const double* __restrict__ w, int64_t m,
-                                                      double* __restrict__ q_next, double* __restrict__ beta_out) {
+// beta_j = ||w||, q_{j+1} = w / beta_j (one workgroup per matrix); j = -1
+// normalises the start vector into q_0
+__global__ __launch_bounds__(1024) void finish_kernel(const LzNode* __restrict__ nodes, const int* __restrict__ act,
+                                                      int j) {
+  const LzNode n = act ? nodes[act[blockIdx.z]] : nodes[blockIdx.z];
   __shared__ double part[16];
   double s = 0.0;
-  for (int64_t i = threadIdx.x; i < m; i += blockDim.x) s += w[i] * w[i];
+  for (int64_t i = threadIdx.x; i < n.m; i += blockDim.x) s += n.w[i] * n.w[i];
   s = wave_sum(s);
   if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
   __syncthreads();
@@ -139,26 +195,84 @@ __global__ __launch_bounds__(1024) void finish_kernel(const double* __restrict__
   for (int i = 0; i < (int)(blockDim.x >> 6); ++i) tot += part[i];
   const double beta = sqrt(tot);
   const double inv = beta > 0.0 ? 1.0 / beta : 0.0;
-  for (int64_t i = threadIdx.x; i < m; i += blockDim.x) q_next[i] = w[i] * inv;
-  if (threadIdx.x == 0 && beta_out) *beta_out = beta;
+  double* q_next = n.Q + (int64_t)(j + 1) * n.m;
+  for (int64_t i = threadIdx.x; i < n.m; i += blockDim.x) q_next[i] = n.w[i] * inv;
+  if (threadIdx.x == 0 && j >= 0) n.beta[j] = beta;
 }
 
-__global__ void zero_kernel(double* p, int64_t count) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
-    p[i] = 0.0;
+// Breakdown: beta_j this small against ||G q_j|| means the Krylov space is
+// (numerically) invariant, and w / beta_j would be rounding noise that the
+// two Gram-Schmidt passes could not make orthogonal to Q.  Restart: a fresh
+// pseudo-random vector, orthogonalised against q_0..q_j by two classical
+// Gram-Schmidt passes, becomes q_{j+1}, and beta_j = 0 (T splits into
+// independent blocks).  One workgroup per matrix; the others return at once.
+__global__ __launch_bounds__(1024) void breakdown_kernel(const LzNode* __restrict__ nodes,
+                                                         const int* __restrict__ act, int j, double rel_tol) {
+  const LzNode n = nodes[act[blockIdx.z]];
+  double w2 = 0.0;
+  for (int rc = 0; rc < n.nrc; ++rc) w2 += n.wn[rc];
+  if (!(n.beta[j] <= rel_tol * sqrt(w2))) return;
+  __shared__ double hs[kMaxSteps + 1];
+  __shared__ double part[16];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  double* w = n.w;
+  for (int64_t i = threadIdx.x; i < n.m; i += blockDim.x)
+    w[i] = hash_unit((uint64_t)i * 7919u + 104729u * (uint64_t)(j + 1) + 17u);
+  __syncthreads();
+  for (int pass = 0; pass < 2; ++pass) {
+    for (int c = wave; c <= j; c += nw) {  // h = Q^T w, one wavefront per column
+      const double* q = n.Q + (int64_t)c * n.m;
+      double t = 0.0;
+      for (int64_t i = lane; i < n.m; i += 64) t += q[i] * w[i];
+      t = wave_sum(t);
+      if (lane == 0) hs[c] = t;
+    }
+    __syncthreads();
+    for (int64_t i = threadIdx.x; i < n.m; i += blockDim.x) {  // w -= Q h
+      double t = 0.0;
+      for (int c = 0; c <= j; ++c) t += n.Q[(int64_t)c * n.m + i] * hs[c];
+      w[i] -= t;
+    }
+    __syncthreads();
+  }
+  double s2 = 0.0;
+  for (int64_t i = threadIdx.x; i < n.m; i += blockDim.x) s2 += w[i] * w[i];
+  s2 = wave_sum(s2);
+  if (lane == 0) part[wave] = s2;
+  __syncthreads();
+  double tot = 0.0;
+  for (int i = 0; i < nw; ++i) tot += part[i];
+  const double nrm = sqrt(tot);
+  const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
+  double* q_next = n.Q + (int64_t)(j + 1) * n.m;
+  for (int64_t i = threadIdx.x; i < n.m; i += blockDim.x) q_next[i] = w[i] * inv;
+  if (threadIdx.x == 0) n.beta[j] = 0.0;
 }
 
-__global__ void trace_kernel(const double* G, int64_t ldg, int64_t m, double* out) {
+// out[2 a] = beta_j, out[2 a + 1] = beta_0 of active matrix a
+__global__ void gather_beta_kernel(const LzNode* __restrict__ nodes, const int* __restrict__ act, int na, int j,
+                                   double* __restrict__ out) {
+  const int a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= na) return;
+  const LzNode n = nodes[act[a]];
+  out[2 * a] = n.beta[j];
+  out[2 * a + 1] = n.beta[0];
+}
+
+__global__ void setup_kernel(const LzNode* __restrict__ nodes) {
+  const LzNode n = nodes[blockIdx.z];
+  const int k = (int)min(n.m, (int64_t)kMaxSteps);
+  for (int i = threadIdx.x; i < k; i += blockDim.x) n.alpha[i] = 0.0;
   __shared__ double part[16];
   double s = 0.0;
-  for (int64_t i = threadIdx.x; i < m; i += blockDim.x) s += G[i * ldg + i];
+  for (int64_t i = threadIdx.x; i < n.m; i += blockDim.x) s += n.G[i * n.ldg + i];
   s = wave_sum(s);
   if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
   __syncthreads();
   if (threadIdx.x == 0) {
     double t = 0.0;
     for (int i = 0; i < (int)(blockDim.x >> 6); ++i) t += part[i];
-    *out = t;
+    *n.tr = t;
   }
 }
 
@@ -178,10 +292,14 @@ __device__ int sturm_count(const double* d, const double* e2, int k, double mu, 
 
 // theta[i] = i-th largest eigenvalue of T, by multisection: one wavefront
 // per eigenvalue, 64 Sturm counts per step shrink the bracket 65-fold.
-__global__ __launch_bounds__(256) void bisect_kernel(const double* __restrict__ d, const double* __restrict__ e,
-                                                     int k, double* __restrict__ e2all,
-                                                     double* __restrict__ theta) {
-  double* e2buf = e2all + (int64_t)blockIdx.x * k;
+__global__ __launch_bounds__(256) void bisect_kernel(const LzNode* __restrict__ nodes) {
+  const LzNode n = nodes[blockIdx.z];
+  const int k = n.kk;
+  if (blockIdx.x * 4 >= k) return;  // whole workgroup
+  const double* d = n.alpha;
+  const double* e = n.beta;
+  double* theta = n.theta;
+  double* e2buf = n.e2 + (int64_t)blockIdx.x * k;
   for (int j = threadIdx.x; j < k - 1; j += blockDim.x) e2buf[j] = e[j] * e[j];
   __syncthreads();
   const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -220,10 +338,17 @@ __global__ __launch_bounds__(256) void bisect_kernel(const double* __restrict__ 
 // inverse iteration: z_i solves (T - theta_i) z = z_prev (pivoted LU), three
 // times from a pseudo-random start; written as column i of Z (row-major,
 // Z[r * ldz + i]).  Scratch: 5 k doubles + k ints per thread.
-__global__ void inviter_kernel(const double* __restrict__ d, const double* __restrict__ e, int k,
-                               const double* __restrict__ theta, int nvec, double* __restrict__ scratch,
-                               int* __restrict__ iscratch, double* __restrict__ Z, int64_t ldz,
-                               double* __restrict__ last) {
+__global__ void inviter_kernel(const LzNode* __restrict__ nodes) {
+  const LzNode n = nodes[blockIdx.z];
+  const int k = n.kk, nvec = n.kk;
+  const int64_t ldz = n.kk;
+  const double* d = n.alpha;
+  const double* e = n.beta;
+  const double* theta = n.theta;
+  double* scratch = n.isc;
+  int* iscratch = n.ipiv;
+  double* Z = n.Z;
+  double* last = n.last;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nvec) return;
   // interleaved scratch: entry j of this thread's array X at X[j * nvec]
@@ -243,61 +368,81 @@ __global__ void inviter_kernel(const double* __restrict__ d, const double* __res
   double tnorm = 0.0;
   for (int j = 0; j < k; ++j) tnorm = fmax(tnorm, fabs(d[j]) + (j < k - 1 ? fabs(e[j]) : 0.0) + (j > 0 ? fabs(e[j - 1]) : 0.0));
   const double tiny = fmax(2.220446049250313e-16 * tnorm, 1e-300);
-  const double mu = theta[i];
-  // LU with partial pivoting of T - mu I (LAPACK gttrf layout)
-  for (int j = 0; j < k; ++j) {
-    DD(j) = d[j] - mu;
-    if (j < k - 1) { DL(j) = e[j]; DU(j) = e[j]; }
-    DU2(j) = 0.0;
-  }
-  for (int j = 0; j < k - 1; ++j) {
-    if (fabs(DD(j)) >= fabs(DL(j))) {
-      PIV(j) = j;
-      if (DD(j) == 0.0) DD(j) = tiny;
-      const double f = DL(j) / DD(j);
-      DL(j) = f;
-      DD(j + 1) -= f * DU(j);
-    } else {
-      PIV(j) = j + 1;
-      const double f = DD(j) / DL(j);
-      DD(j) = DL(j);
-      DL(j) = f;
-      const double tmp = DU(j);
-      DU(j) = DD(j + 1);
-      DD(j + 1) = tmp - f * DD(j + 1);
-      if (j < k - 2) {
-        DU2(j) = DU(j + 1);
-        DU(j + 1) = -f * DU(j + 1);
-      }
+  // Ritz values equal to 9 digits (and above the rounding level of T) form
+  // a cluster -- an eigenvalue the restarts found several times; inverse
+  // iteration alone would return nearly parallel vectors for them, so one
+  // thread (the cluster's first) computes them in turn, orthogonalising each
+  // iterate against the cluster's earlier vectors (modified Gram-Schmidt).
+  const double level = 1e3 * 2.220446049250313e-16 * tnorm;
+  auto same = [&](int a, int b2) {
+    return fabs(theta[b2]) > level && theta[a] - theta[b2] <= 1e-9 * fabs(theta[b2]);
+  };
+  if (i > 0 && same(i - 1, i)) return;
+  int cend = i + 1;
+  while (cend < nvec && same(cend - 1, cend)) ++cend;
+  for (int v = i; v < cend; ++v) {
+    const double mu = theta[v];
+    // LU with partial pivoting of T - mu I (LAPACK gttrf layout)
+    for (int j = 0; j < k; ++j) {
+      DD(j) = d[j] - mu;
+      if (j < k - 1) { DL(j) = e[j]; DU(j) = e[j]; }
+      DU2(j) = 0.0;
     }
-  }
-  if (DD(k - 1) == 0.0) DD(k - 1) = tiny;
-  for (int j = 0; j < k; ++j)
-    if (fabs(DD(j)) < tiny) DD(j) = (DD(j) < 0.0 ? -tiny : tiny);
-  for (int j = 0; j < k; ++j) BB(j) = hash_unit((uint64_t)i * 1000003u + j) + 1.0;
-  for (int it = 0; it < 3; ++it) {
-    // forward with L
     for (int j = 0; j < k - 1; ++j) {
-      if (PIV(j) == j) {
-        BB(j + 1) -= DL(j) * BB(j);
+      if (fabs(DD(j)) >= fabs(DL(j))) {
+        PIV(j) = j;
+        if (DD(j) == 0.0) DD(j) = tiny;
+        const double f = DL(j) / DD(j);
+        DL(j) = f;
+        DD(j + 1) -= f * DU(j);
       } else {
-        const double t = BB(j);
-        BB(j) = BB(j + 1);
-        BB(j + 1) = t - DL(j) * BB(j);
+        PIV(j) = j + 1;
+        const double f = DD(j) / DL(j);
+        DD(j) = DL(j);
+        DL(j) = f;
+        const double tmp = DU(j);
+        DU(j) = DD(j + 1);
+        DD(j + 1) = tmp - f * DD(j + 1);
+        if (j < k - 2) {
+          DU2(j) = DU(j + 1);
+          DU(j + 1) = -f * DU(j + 1);
+        }
       }
     }
-    // back substitution with U (diag DD, super DU, super-super DU2)
-    BB(k - 1) /= DD(k - 1);
-    if (k > 1) BB(k - 2) = (BB(k - 2) - DU(k - 2) * BB(k - 1)) / DD(k - 2);
-    for (int j = k - 3; j >= 0; --j) BB(j) = (BB(j) - DU(j) * BB(j + 1) - DU2(j) * BB(j + 2)) / DD(j);
-    double nrm = 0.0;
-    for (int j = 0; j < k; ++j) nrm += BB(j) * BB(j);
-    nrm = sqrt(nrm);
-    const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
-    for (int j = 0; j < k; ++j) BB(j) *= inv;
+    if (DD(k - 1) == 0.0) DD(k - 1) = tiny;
+    for (int j = 0; j < k; ++j)
+      if (fabs(DD(j)) < tiny) DD(j) = (DD(j) < 0.0 ? -tiny : tiny);
+    for (int j = 0; j < k; ++j) BB(j) = hash_unit((uint64_t)v * 1000003u + j) + 1.0;
+    for (int it = 0; it < 3; ++it) {
+      // forward with L
+      for (int j = 0; j < k - 1; ++j) {
+        if (PIV(j) == j) {
+          BB(j + 1) -= DL(j) * BB(j);
+        } else {
+          const double t = BB(j);
+          BB(j) = BB(j + 1);
+          BB(j + 1) = t - DL(j) * BB(j);
+        }
+      }
+      // back substitution with U (diag DD, super DU, super-super DU2)
+      BB(k - 1) /= DD(k - 1);
+      if (k > 1) BB(k - 2) = (BB(k - 2) - DU(k - 2) * BB(k - 1)) / DD(k - 2);
+      for (int j = k - 3; j >= 0; --j) BB(j) = (BB(j) - DU(j) * BB(j + 1) - DU2(j) * BB(j + 2)) / DD(j);
+      // against the cluster's earlier vectors
+      for (int c = i; c < v; ++c) {
+        double dot = 0.0;
+        for (int j = 0; j < k; ++j) dot += Z[(int64_t)j * ldz + c] * BB(j);
+        for (int j = 0; j < k; ++j) BB(j) -= dot * Z[(int64_t)j * ldz + c];
+      }
+      double nrm = 0.0;
+      for (int j = 0; j < k; ++j) nrm += BB(j) * BB(j);
+      nrm = sqrt(nrm);
+      const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
+      for (int j = 0; j < k; ++j) BB(j) *= inv;
+    }
+    for (int j = 0; j < k; ++j) Z[(int64_t)j * ldz + v] = BB(j);
+    last[v] = BB(k - 1);
   }
-  for (int j = 0; j < k; ++j) Z[(int64_t)j * ldz + i] = BB(j);
-  last[i] = BB(k - 1);
 #undef DL
 #undef DD
 #undef DU
@@ -307,7 +452,10 @@ __global__ void inviter_kernel(const double* __restrict__ d, const double* __res
 }
 
 // make the largest-magnitude entry of every column positive (one wave per column)
-__global__ __launch_bounds__(256) void sign_fix_kernel(double* V, int64_t ldv, int64_t m, int64_t ncols) {
+__global__ __launch_bounds__(256) void sign_fix_kernel(const LzNode* __restrict__ nodes) {
+  const LzNode n = nodes[blockIdx.z];
+  double* V = n.V;
+  const int64_t ldv = n.ldv, m = n.m, ncols = n.b;
   const int64_t c = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (c >= ncols) return;
@@ -329,153 +477,281 @@ __global__ __launch_bounds__(256) void sign_fix_kernel(double* V, int64_t ldv, i
     for (int64_t r = lane; r < m; r += 64) col[r] = -col[r];
 }
 
-__global__ void write_lambda_kernel(const double* theta, int b, double* lambda, int64_t m) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x)
-    lambda[i] = (i < b) ? theta[i] : 0.0;
+__global__ void write_lambda_kernel(const LzNode* __restrict__ nodes) {
+  const LzNode n = nodes[blockIdx.z];
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n.m; i += (int64_t)gridDim.x * blockDim.x)
+    n.lambda[i] = (i < n.b) ? n.theta[i] : 0.0;
 }
+
+
+
+size_t al(size_t x) { return (x + 255) / 256 * 256; }
 
 }  // namespace
 
-hapod_status wide_eigh(const double* G, int64_t ldg, int64_t m, double* lambda, double* V, int64_t ldv, double u_p,
-                       wide_alloc_fn alloc, wide_free_fn release, void* ctx, hipStream_t stream, WideResult* res,
-                       bool full) {
-  if (m <= 0) return HAPOD_OK;
-  if (full && m > kMaxSteps) {
-    set_error("wide_eigh: a full run needs m <= 768");
-    return HAPOD_E_UNSUPPORTED;
-  }
-  const int k = (int)std::min<int64_t>(m, kMaxSteps);
-  // ---- scratch ------------------------------------------------------------------
-  std::vector<void*> owned;
-  auto get = [&](size_t bytes) -> void* {
-    void* p = alloc(ctx, bytes);
-    if (p) owned.push_back(p);
-    return p;
-  };
-  struct Rel {
-    std::vector<void*>& o;
-    wide_free_fn f;
-    void* c;
-    ~Rel() {
-      for (void* p : o) f(c, p);
+hapod_status wide_eigh_batch(std::vector<WideJob>& jobs, double u_p, wide_alloc_fn alloc, wide_free_fn release,
+                             void* ctx, hipStream_t stream) {
+  const int nn = (int)jobs.size();
+  if (nn == 0) return HAPOD_OK;
+  for (auto& jb : jobs)
+    if (jb.full && jb.m > kMaxSteps) {
+      set_error("wide_eigh: a full run needs m <= 768");
+      return HAPOD_E_UNSUPPORTED;
     }
-  } rel{owned, release, ctx};
-  double* Q = (double*)get(sizeof(double) * m * (k + 1));
-  double* w = (double*)get(sizeof(double) * m);
-  const int nrc = (int)((m + kProjRows - 1) / kProjRows);
-  double* h = (double*)get(sizeof(double) * (size_t)(k + 1) * nrc);
-  double* alpha = (double*)get(sizeof(double) * k);
-  double* beta = (double*)get(sizeof(double) * (k + 1));
-  double* theta = (double*)get(sizeof(double) * k);
-  double* e2 = (double*)get(sizeof(double) * (size_t)k * ((k + 3) / 4));
-  double* Z = (double*)get(sizeof(double) * (size_t)k * k);
-  double* last = (double*)get(sizeof(double) * k);
-  double* isc = (double*)get(sizeof(double) * (size_t)5 * k * k);
-  int* ipiv = (int*)get(sizeof(int) * (size_t)k * k);
-  double* tr = (double*)get(sizeof(double));
-  const void** qcols = (const void**)get(sizeof(void*) * k);
-  int64_t* qrbs = (int64_t*)get(sizeof(int64_t) * k);
-  int64_t* qrows = (int64_t*)get(sizeof(int64_t) * k);
-  int64_t* drank = (int64_t*)get(sizeof(int64_t));
-  void* dnode = get(sizeof(LiftNode));
-  if (!Q || !w || !h || !alpha || !beta || !theta || !e2 || !Z || !last || !isc || !ipiv || !tr || !qcols || !qrbs || !qrows || !drank ||
-      !dnode) {
+  // ---- scratch: one block for every matrix -----------------------------------------
+  std::vector<size_t> off(nn);
+  std::vector<int> kmax(nn), nrc(nn);
+  size_t total = 0;
+  auto sizes = [&](int i, bool assign, char* base, LzNode* nd) {
+    const int64_t m = jobs[i].m;
+    const int k = (int)std::min<int64_t>(m, kMaxSteps);
+    size_t o = assign ? off[i] : total;
+    auto take = [&](size_t bytes) {
+      char* p = base ? base + o : nullptr;
+      o += al(bytes);
+      return p;
+    };
+    double* Q = (double*)take(sizeof(double) * m * (k + 1));
+    double* w = (double*)take(sizeof(double) * m);
+    const int nr = (int)((m + kProjRows - 1) / kProjRows);
+    double* h = (double*)take(sizeof(double) * (size_t)(k + 1) * nr);
+    double* alpha = (double*)take(sizeof(double) * k);
+    double* beta = (double*)take(sizeof(double) * (k + 1));
+    double* theta = (double*)take(sizeof(double) * k);
+    double* e2 = (double*)take(sizeof(double) * (size_t)k * ((k + 3) / 4));
+    double* Z = (double*)take(sizeof(double) * (size_t)k * k);
+    double* last = (double*)take(sizeof(double) * k);
+    double* isc = (double*)take(sizeof(double) * (size_t)5 * k * k);
+    int* ipiv = (int*)take(sizeof(int) * (size_t)k * k);
+    double* tr = (double*)take(sizeof(double));
+    take(sizeof(void*) * k);     // Ritz-lift column table
+    take(sizeof(int64_t) * k);   // its row-block strides
+    take(sizeof(int64_t) * k);   // its row counts
+    take(sizeof(int64_t));       // its rank
+    double* wn = (double*)take(sizeof(double) * nr);
+    if (nd) {
+      *nd = LzNode{};
+      nd->G = jobs[i].G;
+      nd->ldg = jobs[i].ldg;
+      nd->m = m;
+      nd->Q = Q; nd->w = w; nd->h = h; nd->alpha = alpha; nd->beta = beta; nd->theta = theta; nd->e2 = e2;
+      nd->Z = Z; nd->last = last; nd->isc = isc; nd->ipiv = ipiv; nd->tr = tr; nd->wn = wn;
+      nd->V = jobs[i].V;
+      nd->lambda = jobs[i].lambda;
+      nd->ldv = jobs[i].ldv;
+      nd->nrc = nr;
+    }
+    kmax[i] = k;
+    nrc[i] = nr;
+    if (!assign) {
+      off[i] = total;
+      total = o;
+    }
+    return o;
+  };
+  for (int i = 0; i < nn; ++i) sizes(i, false, nullptr, nullptr);
+  const size_t o_nodes = total;
+  total = al(total + sizeof(LzNode) * nn);
+  const size_t o_act = total;
+  total = al(total + sizeof(int) * nn);
+  const size_t o_gb = total;
+  total = al(total + sizeof(double) * 2 * nn);
+  const size_t o_lift = total;
+  total = al(total + sizeof(LiftNode) * nn);
+  char* blk = (char*)alloc(ctx, total);
+  if (!blk) {
     set_error("wide_eigh: scratch allocation failed");
     return HAPOD_E_NOMEM;
   }
-  hipLaunchKernelGGL(zero_kernel, dim3(4), dim3(256), 0, stream, alpha, (int64_t)k);
-  hipLaunchKernelGGL(trace_kernel, dim3(1), dim3(1024), 0, stream, G, ldg, m, tr);
-  // q_0
-  hipLaunchKernelGGL(lanczos_init_kernel, dim3(64), dim3(256), 0, stream, w, m);
-  hipLaunchKernelGGL(finish_kernel, dim3(1), dim3(1024), 0, stream, w, m, Q, (double*)nullptr);
-  const unsigned mv_blocks = (unsigned)((m + 3) / 4);
-  const unsigned up_blocks = (unsigned)((m + 63) / 64);
-  // the rounding level of G's spectrum, for the stopping test
-  double trace = 0.0;
-  HAPOD_HIP(hipMemcpyAsync(&trace, tr, sizeof(double), hipMemcpyDeviceToHost, stream));
+  struct Rel {
+    wide_free_fn f;
+    void* c;
+    void* p;
+    ~Rel() { f(c, p); }
+  } rel{release, ctx, blk};
+  std::vector<LzNode> hn(nn);
+  for (int i = 0; i < nn; ++i) sizes(i, true, blk, &hn[i]);
+  LzNode* dn = (LzNode*)(blk + o_nodes);
+  int* dact = (int*)(blk + o_act);
+  double* dgb = (double*)(blk + o_gb);
+  int64_t m_max = 0;
+  int kmax_all = 0, nrc_max = 1;
+  for (int i = 0; i < nn; ++i) {
+    m_max = std::max(m_max, jobs[i].m);
+    kmax_all = std::max(kmax_all, kmax[i]);
+    nrc_max = std::max(nrc_max, nrc[i]);
+  }
+  HAPOD_HIP(hipMemcpyAsync(dn, hn.data(), sizeof(LzNode) * nn, hipMemcpyHostToDevice, stream));
+  hipLaunchKernelGGL(setup_kernel, dim3(1, 1, nn), dim3(1024), 0, stream, dn);
+  hipLaunchKernelGGL(lanczos_init_kernel, dim3(64, 1, nn), dim3(256), 0, stream, dn);
+  hipLaunchKernelGGL(finish_kernel, dim3(1, 1, nn), dim3(1024), 0, stream, dn, (const int*)nullptr, -1);
+  HAPOD_HIP(hipGetLastError());
+  // the rounding level of each G's spectrum, for the stopping test
+  std::vector<double> trace(nn, 0.0), floor_trace(nn);
+  for (int i = 0; i < nn; ++i)
+    HAPOD_HIP(hipMemcpyAsync(&trace[i], hn[i].tr, sizeof(double), hipMemcpyDeviceToHost, stream));
   HAPOD_HIP(hipStreamSynchronize(stream));
-  const double floor_trace = 0.1 * u_p * std::fabs(trace);
-  int steps = k;
-  bool stopped = (k == m);
-  double prev_check = 0.0;
+  for (int i = 0; i < nn; ++i) floor_trace[i] = 0.1 * u_p * std::fabs(trace[i]);
+  std::vector<int> steps(kmax), act;
+  std::vector<char> stopped(nn, 0);
+  std::vector<double> prev_check(nn, 0.0);
+  for (int i = 0; i < nn; ++i) {
+    stopped[i] = (kmax[i] == jobs[i].m);
+    if (jobs[i].m > 0) act.push_back(i);
+  }
   const char* venv = std::getenv("HAPOD_VERBOSE");
   const bool verbose = venv && venv[0] == '1';
-  for (int j = 0; j < k; ++j) {
-    const double* qj = Q + (int64_t)j * m;
-    hipLaunchKernelGGL(matvec_kernel, dim3(mv_blocks), dim3(256), 0, stream, G, ldg, m, qj, w);
-    for (int pass = 0; pass < 2; ++pass) {
-      hipLaunchKernelGGL(proj_partial_kernel, dim3((unsigned)((j + kProjCols) / kProjCols), (unsigned)nrc),
-                         dim3(256), 0, stream, Q, m, j, w, h, nrc);
-      hipLaunchKernelGGL(update_kernel, dim3(up_blocks), dim3(256), 0, stream, Q, m, j, w, h, nrc, alpha);
+  bool act_dirty = true;
+  for (int j = 0; j < kmax_all && !act.empty(); ++j) {
+    // matrices whose Krylov space is complete (j = k) leave the list
+    {
+      std::vector<int> keep;
+      for (int i : act)
+        if (j < kmax[i]) keep.push_back(i);
+      if (keep.size() != act.size()) {
+        act.swap(keep);
+        act_dirty = true;
+        if (act.empty()) break;
+      }
     }
-    hipLaunchKernelGGL(finish_kernel, dim3(1), dim3(1024), 0, stream, w, m, Q + (int64_t)(j + 1) * m, beta + j);
+    if (act_dirty) {
+      HAPOD_HIP(hipMemcpyAsync(dact, act.data(), sizeof(int) * act.size(), hipMemcpyHostToDevice, stream));
+      act_dirty = false;
+    }
+    const unsigned na = (unsigned)act.size();
+    int64_t am = 0;
+    int anrc = 1;
+    for (int i : act) {
+      am = std::max(am, jobs[i].m);
+      anrc = std::max(anrc, nrc[i]);
+    }
+    hipLaunchKernelGGL(matvec_kernel, dim3((unsigned)((am + 3) / 4), 1, na), dim3(256), 0, stream, dn, dact, j);
+    for (int pass = 0; pass < 2; ++pass) {
+      hipLaunchKernelGGL(proj_partial_kernel, dim3((unsigned)((j + kProjCols) / kProjCols), (unsigned)anrc, na),
+                         dim3(256), 0, stream, dn, dact, j, pass == 0 ? 1 : 0);
+      hipLaunchKernelGGL(update_kernel, dim3((unsigned)((am + 63) / 64), 1, na), dim3(256), 0, stream, dn, dact, j);
+    }
+    hipLaunchKernelGGL(finish_kernel, dim3(1, 1, na), dim3(1024), 0, stream, dn, dact, j);
+    // restart the matrices whose step broke down
+    hipLaunchKernelGGL(breakdown_kernel, dim3(1, 1, na), dim3(1024), 0, stream, dn, dact, j, kBreakdownTol);
     // Stop once the Krylov space has taken in everything above the rounding
     // level of G: the residual norms beta_j then stop falling (they sit at
     // that level).  Test every kCheckEvery steps: beta_j at or below
     // u_p trace(G) / 10, or beta_j fell less than kPlateau-fold over the last
-    // period after having fallen 1000-fold from beta_0.
-    if (!full && (j + 1) % kCheckEvery == 0 && j + 1 < k) {
-      double bj = 0.0, b0 = 0.0;
-      HAPOD_HIP(hipMemcpyAsync(&bj, beta + j, sizeof(double), hipMemcpyDeviceToHost, stream));
-      HAPOD_HIP(hipMemcpyAsync(&b0, beta, sizeof(double), hipMemcpyDeviceToHost, stream));
+    // period after having fallen 1000-fold from beta_0.  Full runs never stop.
+    if ((j + 1) % kCheckEvery == 0) {
+      bool any = false;
+      for (int i : act) any |= !jobs[i].full && j + 1 < kmax[i];
+      if (!any) continue;
+      hipLaunchKernelGGL(gather_beta_kernel, dim3((na + 255) / 256), dim3(256), 0, stream, dn, dact, (int)na, j, dgb);
+      std::vector<double> gb(2 * na);
+      HAPOD_HIP(hipMemcpyAsync(gb.data(), dgb, sizeof(double) * 2 * na, hipMemcpyDeviceToHost, stream));
       HAPOD_HIP(hipStreamSynchronize(stream));
-      if (verbose)
-        std::fprintf(stderr, "[hapod wide] m=%lld step %d beta %.3e floor_trace %.3e\n", (long long)m, j + 1, bj,
-                     floor_trace);
-      const bool plateau = prev_check > 0.0 && bj >= kPlateau * prev_check && bj <= 1e-3 * b0;
-      prev_check = bj;
-      if (j + 1 >= kMinSteps && (bj <= floor_trace || plateau)) {
-        steps = j + 1;
-        stopped = true;
-        break;
+      std::vector<int> keep;
+      for (unsigned a = 0; a < na; ++a) {
+        const int i = act[a];
+        const double bj = gb[2 * a], b0 = gb[2 * a + 1];
+        bool stop = false;
+        if (!jobs[i].full && j + 1 < kmax[i]) {
+          if (verbose)
+            std::fprintf(stderr, "[hapod wide] m=%lld step %d beta %.3e floor_trace %.3e\n", (long long)jobs[i].m,
+                         j + 1, bj, floor_trace[i]);
+          const bool plateau = prev_check[i] > 0.0 && bj >= kPlateau * prev_check[i] && bj <= 1e-3 * b0;
+          prev_check[i] = bj;
+          stop = j + 1 >= kMinSteps && (bj <= floor_trace[i] || plateau);
+        }
+        if (stop) {
+          steps[i] = j + 1;
+          stopped[i] = 1;
+        } else {
+          keep.push_back(i);
+        }
+      }
+      if (keep.size() != act.size()) {
+        act.swap(keep);
+        act_dirty = true;
       }
     }
   }
   HAPOD_HIP(hipGetLastError());
-  // ---- tridiagonal eigenproblem of the steps taken ---------------------------------
-  const int kk = steps;
-  hipLaunchKernelGGL(bisect_kernel, dim3((unsigned)((kk + 3) / 4)), dim3(256), 0, stream, alpha, beta, kk, e2, theta);
-  HAPOD_HIP(hipGetLastError());
-  const unsigned bblocks = (unsigned)((kk + 255) / 256);
-  hipLaunchKernelGGL(inviter_kernel, dim3(bblocks), dim3(256), 0, stream, alpha, beta, kk, theta, kk, isc, ipiv, Z,
-                     (int64_t)kk, last);
-  HAPOD_HIP(hipGetLastError());
-  // ---- choose the converged leading block (host) ----------------------------------
-  std::vector<double> th(kk), lz(kk), bet(kk);
-  HAPOD_HIP(hipMemcpyAsync(th.data(), theta, sizeof(double) * kk, hipMemcpyDeviceToHost, stream));
-  HAPOD_HIP(hipMemcpyAsync(lz.data(), last, sizeof(double) * kk, hipMemcpyDeviceToHost, stream));
-  HAPOD_HIP(hipMemcpyAsync(bet.data(), beta, sizeof(double) * kk, hipMemcpyDeviceToHost, stream));
-  HAPOD_HIP(hipStreamSynchronize(stream));
-  const double bk = bet[kk - 1];
-  const double theta_min = *std::min_element(th.begin(), th.end());
-  const double floor_abs = std::max(std::max(-theta_min, 0.0), floor_trace);
-  // a Ritz pair counts as converged when its residual is below 1e-8 of its
-  // own value or below the Gram's rounding level
-  int b = 0;
-  while (b < kk && std::fabs(bk * lz[b]) <= std::max(1e-8 * std::fabs(th[b]), floor_abs)) ++b;
-  if (kk == m) b = kk;  // complete tridiagonalisation: every pair is exact
-  // Ritz vectors of one Krylov space are orthonormal and diagonalise G on it
-  // (V^T G V = diag(theta)), so the energy of S on the modes S v_i / sqrt(theta_i)
-  // is at least sum theta_i whether or not the pairs have converged: the block
-  // is extended by every Ritz value above the noise level max(floor_abs,
-  // beta_{k-1}) (below it a Ritz value cannot be told from zero), and only
-  // what lies beyond the Krylov space is left unresolved.
-  const double noise = std::max(floor_abs, std::fabs(bk));
-  if (stopped) {
-    int e = b;
-    while (e < kk && th[e] > noise) ++e;
-    b = e;
+  // ---- tridiagonal eigenproblems of the steps taken ----------------------------------
+  int kk_max = 0;
+  for (int i = 0; i < nn; ++i) {
+    hn[i].kk = jobs[i].m > 0 ? steps[i] : 0;
+    kk_max = std::max(kk_max, hn[i].kk);
   }
-  double missing = 0.0, captured = 0.0;
-  for (int i = b; i < kk; ++i)
-    if (th[i] > noise) missing += th[i];
-  for (int i = 0; i < b; ++i) captured += th[i];
-  if (verbose)
-    std::fprintf(stderr, "[hapod wide] m=%lld steps %d block %d theta_1 %.6e theta_min %.3e floor %.3e\n",
-                 (long long)m, kk, b, th[0], theta_min, floor_abs);
-  // ---- Ritz vectors V[:, :b] = Q_k Z[:, :b] (FP64 lift GEMM) ------------------------
-  if (b > 0) {
-    HAPOD_TRY(launch_fill_colptrs(Q, m, kk, 8, qcols, stream));
+  HAPOD_HIP(hipMemcpyAsync(dn, hn.data(), sizeof(LzNode) * nn, hipMemcpyHostToDevice, stream));
+  hipLaunchKernelGGL(bisect_kernel, dim3((unsigned)((kk_max + 3) / 4), 1, nn), dim3(256), 0, stream, dn);
+  HAPOD_HIP(hipGetLastError());
+  hipLaunchKernelGGL(inviter_kernel, dim3((unsigned)((kk_max + 255) / 256), 1, nn), dim3(256), 0, stream, dn);
+  HAPOD_HIP(hipGetLastError());
+  // ---- choose each converged leading block (host) ----------------------------------
+  std::vector<std::vector<double>> th(nn), lz(nn), bet(nn);
+  for (int i = 0; i < nn; ++i) {
+    const int kk = hn[i].kk;
+    th[i].resize(kk);
+    lz[i].resize(kk);
+    bet[i].resize(kk);
+    if (kk == 0) continue;
+    HAPOD_HIP(hipMemcpyAsync(th[i].data(), hn[i].theta, sizeof(double) * kk, hipMemcpyDeviceToHost, stream));
+    HAPOD_HIP(hipMemcpyAsync(lz[i].data(), hn[i].last, sizeof(double) * kk, hipMemcpyDeviceToHost, stream));
+    HAPOD_HIP(hipMemcpyAsync(bet[i].data(), hn[i].beta, sizeof(double) * kk, hipMemcpyDeviceToHost, stream));
+  }
+  HAPOD_HIP(hipStreamSynchronize(stream));
+  std::vector<LiftNode> lifts;
+  int items = 0, b_max = 0;
+  for (int i = 0; i < nn; ++i) {
+    const int kk = hn[i].kk;
+    const int64_t m = jobs[i].m;
+    if (kk == 0) continue;
+    const double bk = bet[i][kk - 1];
+    const double theta_min = *std::min_element(th[i].begin(), th[i].end());
+    const double floor_abs = std::max(std::max(-theta_min, 0.0), floor_trace[i]);
+    // a Ritz pair counts as converged when its residual is below 1e-8 of its
+    // own value or below the Gram's rounding level
+    int b = 0;
+    while (b < kk && std::fabs(bk * lz[i][b]) <= std::max(1e-8 * std::fabs(th[i][b]), floor_abs)) ++b;
+    if (kk == m) b = kk;  // complete tridiagonalisation: every pair is exact
+    // Ritz vectors of one Krylov space are orthonormal and diagonalise G on it
+    // (V^T G V = diag(theta)), so the energy of S on the modes S v_i / sqrt(theta_i)
+    // is at least sum theta_i whether or not the pairs have converged: the block
+    // is extended by every Ritz value above the noise level max(floor_abs,
+    // beta_{k-1}) (below it a Ritz value cannot be told from zero), and only
+    // what lies beyond the Krylov space is left unresolved.
+    const double noise = std::max(floor_abs, std::fabs(bk));
+    if (stopped[i]) {
+      int e = b;
+      while (e < kk && th[i][e] > noise) ++e;
+      b = e;
+    }
+    double missing = 0.0, captured = 0.0;
+    for (int t = b; t < kk; ++t)
+      if (th[i][t] > noise) missing += th[i][t];
+    for (int t = 0; t < b; ++t) captured += th[i][t];
+    if (verbose)
+      std::fprintf(stderr, "[hapod wide] m=%lld steps %d block %d theta_1 %.6e theta_min %.3e floor %.3e\n",
+                   (long long)m, kk, b, th[i][0], theta_min, floor_abs);
+    hn[i].b = b;
+    b_max = std::max(b_max, b);
+    if (jobs[i].res) {
+      WideResult& r = *jobs[i].res;
+      r.iterations = kk;
+      r.block = b;
+      r.floor_abs = floor_abs;
+      r.exhausted = stopped[i] != 0;
+      r.missing = missing;
+      r.unresolved = std::max(0.0, trace[i] - captured);
+      r.trace = trace[i];
+      r.noise = (b < m) ? noise : 0.0;
+    }
+    if (b == 0) continue;
+    // Ritz vectors V[:, :b] = Q_k Z[:, :b] (FP64 lift GEMM, all matrices in one launch)
+    char* tbl = (char*)(hn[i].tr) + al(sizeof(double));
+    const void** qcols = (const void**)tbl;
+    int64_t* qrbs = (int64_t*)(tbl + al(sizeof(void*) * kmax[i]));
+    int64_t* qrows = (int64_t*)((char*)qrbs + al(sizeof(int64_t) * kmax[i]));
+    int64_t* drank = (int64_t*)((char*)qrows + al(sizeof(int64_t) * kmax[i]));
+    HAPOD_TRY(launch_fill_colptrs(hn[i].Q, m, kk, 8, qcols, stream));
     HAPOD_TRY(launch_fill_i64(qrbs, kRowBlock, kk, stream));
     HAPOD_TRY(launch_fill_i64(qrows, m, kk, stream));
     HAPOD_TRY(launch_set_scalar_i64(drank, b, stream));
@@ -483,35 +759,40 @@ hapod_status wide_eigh(const double* G, int64_t ldg, int64_t m, double* lambda, 
     l.cols = (const void* const*)qcols;
     l.rbs = qrbs;
     l.crows = qrows;
-    l.B = Z;
+    l.B = hn[i].Z;
     l.rank = drank;
-    l.out = V;
+    l.out = jobs[i].V;
     l.n = m;
     l.ldb = kk;
-    l.ocs = ldv;
+    l.ocs = jobs[i].ldv;
     l.obs = kRowBlock;
     l.m = kk;
     l.row_tiles = (int32_t)((m + kLiftTileM - 1) / kLiftTileM);
     l.col_tiles = (int32_t)((b + kLiftTileN - 1) / kLiftTileN);
-    l.item_base = 0;
-    HAPOD_HIP(hipMemcpyAsync(dnode, &l, sizeof(l), hipMemcpyHostToDevice, stream));
-    HAPOD_TRY(launch_lift(0, (const LiftNode*)dnode, 1, l.row_tiles * l.col_tiles, stream));
-    hipLaunchKernelGGL(sign_fix_kernel, dim3((unsigned)((b + 3) / 4)), dim3(256), 0, stream, V, ldv, m, (int64_t)b);
+    l.item_base = items;
+    items += l.row_tiles * l.col_tiles;
+    lifts.push_back(l);
   }
-  hipLaunchKernelGGL(write_lambda_kernel, dim3(64), dim3(256), 0, stream, theta, b, lambda, m);
+  HAPOD_HIP(hipMemcpyAsync(dn, hn.data(), sizeof(LzNode) * nn, hipMemcpyHostToDevice, stream));
+  if (!lifts.empty()) {
+    LiftNode* dl = (LiftNode*)(blk + o_lift);
+    HAPOD_HIP(hipMemcpyAsync(dl, lifts.data(), sizeof(LiftNode) * lifts.size(), hipMemcpyHostToDevice, stream));
+    HAPOD_TRY(launch_lift(0, dl, (int)lifts.size(), items, stream));
+    hipLaunchKernelGGL(sign_fix_kernel, dim3((unsigned)((b_max + 3) / 4), 1, nn), dim3(256), 0, stream, dn);
+  }
+  hipLaunchKernelGGL(write_lambda_kernel, dim3(64, 1, nn), dim3(256), 0, stream, dn);
   HAPOD_HIP(hipGetLastError());
   HAPOD_HIP(hipStreamSynchronize(stream));
-  if (res) {
-    res->iterations = kk;
-    res->block = b;
-    res->floor_abs = floor_abs;
-    res->exhausted = stopped;
-    res->missing = missing;
-    res->unresolved = std::max(0.0, trace - captured);
-    res->trace = trace;
-    res->noise = (b < m) ? noise : 0.0;
-  }
   return HAPOD_OK;
+}
+
+hapod_status wide_eigh(const double* G, int64_t ldg, int64_t m, double* lambda, double* V, int64_t ldv, double u_p,
+                       wide_alloc_fn alloc, wide_free_fn release, void* ctx, hipStream_t stream, WideResult* res,
+                       bool full) {
+  if (m <= 0) return HAPOD_OK;
+  std::vector<WideJob> jobs(1);
+  jobs[0] = WideJob{G, ldg, m, lambda, V, ldv, full, res};
+  return wide_eigh_batch(jobs, u_p, alloc, release, ctx, stream);
 }
 
 }  // namespace hapod

@@ -2,6 +2,8 @@
 // kernel: the leading part of the spectrum by a Krylov method on the GPU.
 #pragma once
 
+#include <vector>
+
 #include "internal.hpp"
 
 namespace hapod {
@@ -36,5 +38,20 @@ hapod_status wide_eigh(const double* G, int64_t ldg, int64_t m, double* lambda, 
                        double u_p, wide_alloc_fn alloc, wide_free_fn release, void* ctx, hipStream_t stream,
                        WideResult* res, bool full = false);
 constexpr int kWideMaxSteps = 768;
+
+// Several matrices at once (same results as one call each): every step of
+// the iteration is one launch per kernel for all matrices still iterating.
+struct WideJob {
+  const double* G;
+  int64_t ldg;
+  int64_t m;
+  double* lambda;
+  double* V;
+  int64_t ldv;
+  bool full;
+  WideResult* res;
+};
+hapod_status wide_eigh_batch(std::vector<WideJob>& jobs, double u_p, wide_alloc_fn alloc, wide_free_fn release,
+                             void* ctx, hipStream_t stream);
 
 }  // namespace hapod

@@ -368,3 +368,10 @@ def test_split_twins_in_groups_match_single_arena(hp, monkeypatch):
     assert list(r1) == list(r2)
     np.testing.assert_array_equal(s1, s2)
     np.testing.assert_array_equal(U1, U2)
+    # no room for any twin: the leaves split in registers, into the same
+    # hi/lo pairs and the same product order
+    monkeypatch.setenv("HAPOD_TWIN_BUDGET", "1")
+    s3, U3, r3 = run()
+    assert list(r1) == list(r3)
+    np.testing.assert_array_equal(s1, s3)
+    np.testing.assert_array_equal(U1, U3)
