@@ -179,6 +179,10 @@ typedef struct {
                                       a full-length Lanczos run (every eigenpair, as
                                       Jacobi gives); above 256 Lanczos stopped at the
                                       Gram's rounding level                          */
+  int32_t autotune;                /* 1: the first time a node class (precision, width,
+                                      height class) is met, time the candidate Gram tiles
+                                      on a buffer of its shape and keep the fastest for
+                                      the process; 0: fixed tile rule                   */
   int32_t leaf_wave;               /* 0: all leaves of a level in one launch group; k > 0:
                                       at most k leaves per group, so the provider needs at
                                       most k leaves resident at a time                     */

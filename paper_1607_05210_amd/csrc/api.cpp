@@ -10,6 +10,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -26,7 +27,7 @@ void set_error(const std::string& msg) { g_last_error = msg; }
 void* pool_alloc_cb(void* pool, size_t bytes);
 void pool_free_cb(void* pool, void* p);
 hapod_status gram_impl(int compute, int eb, int64_t n, int64_t m, const void* S, int64_t lds, double* G, int64_t ldg,
-                       hipStream_t stream);
+                       hipStream_t stream, int tile = 0);
 
 namespace {
 
@@ -223,8 +224,92 @@ int pick_chunks(int64_t n, int pairs, int target_items, int64_t min_rows) {
 int gram_tile_for(int64_t m) {
   if (m <= 16) return 16;
   if (m <= 32) return 32;
-  if (m <= 128) return 64;
+  if (m <= 64) return 64;
   return kGramTile;
+}
+
+// Tile autotuning.  For a node class of at most 256 columns (compute mode,
+// width rounded up to a multiple of 16, height class 2^ceil(log2 n)) seen for
+// the first time, the candidate tiles -- the default and its neighbours --
+// are timed on a zero buffer of the node's width and up to 2^20 of its rows
+// (the kernels' speed does not depend on the values), and the fastest is kept
+// for the rest of the process.  Tuning is on when the plan asks for it;
+// results are then deterministic for a given tuning table.
+constexpr int64_t kTuneMaxCols = 256;
+struct TileKey {
+  int compute;
+  int64_t m;
+  int nlog;
+  bool operator<(const TileKey& o) const {
+    return compute != o.compute ? compute < o.compute : m != o.m ? m < o.m : nlog < o.nlog;
+  }
+};
+std::map<TileKey, int>& tile_table() {
+  static std::map<TileKey, int> t;
+  return t;
+}
+std::mutex& tile_mutex() {
+  static std::mutex mu;
+  return mu;
+}
+int64_t width_class(int64_t m) { return (m + 15) / 16 * 16; }
+int tile_for_node(int compute, int64_t n, int64_t m) {
+  int nlog = 0;
+  while ((int64_t(1) << nlog) < n && nlog < 62) ++nlog;
+  std::lock_guard<std::mutex> lk(tile_mutex());
+  auto it = tile_table().find(TileKey{compute, width_class(m), nlog});
+  return it != tile_table().end() ? it->second : gram_tile_for(m);
+}
+hapod_status autotune_tile(int compute, int eb, int64_t n, int64_t m_node, Pool& pool, hipStream_t stream) {
+  // wide nodes always take the 128 quad tile: the choice only matters for
+  // nodes of a few tiles, whose Gram a short sample represents well
+  if (n <= 0 || m_node <= 1 || m_node > kTuneMaxCols) return HAPOD_OK;
+  const int64_t m = width_class(m_node);
+  int nlog = 0;
+  while ((int64_t(1) << nlog) < n && nlog < 62) ++nlog;
+  const TileKey key{compute, m, nlog};
+  {
+    std::lock_guard<std::mutex> lk(tile_mutex());
+    if (tile_table().count(key)) return HAPOD_OK;
+  }
+  const int def = gram_tile_for(m);
+  std::vector<int> cand{def};
+  if (def > 16) cand.push_back(def / 2);
+  if (def < kGramTile) cand.push_back(def * 2);
+  // full height up to 2^20 rows and 2 GiB
+  const int64_t ns = std::max<int64_t>(
+      std::min<int64_t>(std::min<int64_t>(n, int64_t(1) << 20), (int64_t(2) << 30) / (m * eb)) / kRowBlock * kRowBlock,
+      std::min<int64_t>(n, kRowBlock));
+  void *S = nullptr, *G = nullptr;
+  HAPOD_TRY(pool.alloc((size_t)ns * m * eb, &S));
+  hapod_status st = pool.alloc(sizeof(double) * m * m, &G);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  int best = def;
+  float best_ms = 1e30f;
+  if (st == HAPOD_OK && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)) st = HAPOD_E_DEVICE;
+  if (st == HAPOD_OK) st = launch_zero_bytes(S, (size_t)ns * m * eb, stream);
+  for (int t : cand) {
+    if (st != HAPOD_OK) break;
+    st = gram_impl(compute, eb, ns, m, S, ns, (double*)G, m, stream, t);  // warm-up
+    float ms = 0.f;
+    if (st == HAPOD_OK && hipEventRecord(e0, stream) != hipSuccess) st = HAPOD_E_DEVICE;
+    for (int r = 0; r < 2 && st == HAPOD_OK; ++r) st = gram_impl(compute, eb, ns, m, S, ns, (double*)G, m, stream, t);
+    if (st == HAPOD_OK && (hipEventRecord(e1, stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                           hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+      st = HAPOD_E_DEVICE;
+    if (st == HAPOD_OK && ms < best_ms) {
+      best_ms = ms;
+      best = t;
+    }
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  pool.free_now(S);
+  if (G) pool.free_now(G);
+  if (st != HAPOD_OK) return st;
+  std::lock_guard<std::mutex> lk(tile_mutex());
+  tile_table()[key] = best;
+  return HAPOD_OK;
 }
 
 // Eigensolver choice.  jacobi_max > 0: Jacobi up to that width, Lanczos
@@ -238,7 +323,7 @@ constexpr int64_t kLiftTargetItems = 2048;  // lift workgroups per launch to aim
 
 hapod_status run_pod_batch(hapod_precision prec, std::vector<PodJob>& jobs, int policy_small, int policy_wide,
                            int jacobi_max, Pool& pool, hipStream_t stream, PhaseTimes* times,
-                           void** batch_block = nullptr) {
+                           void** batch_block = nullptr, bool autotune = false) {
   const int compute = compute_mode(prec);
   const int eb = elem_bytes(prec);
   const int nj = (int)jobs.size();
@@ -258,8 +343,13 @@ hapod_status run_pod_batch(hapod_precision prec, std::vector<PodJob>& jobs, int 
   const int KB = (compute == 2) ? 32 : 16;
   // enough row chunks to give every CU several workgroups
   int sum_pairs = 0;
+  // the Gram compute mode of a node: split-BF16 nodes below the pre-split
+  // width run on FP32 MFMA
+  auto node_compute = [&](int64_t m) { return (compute == 2 && m < kPresplitMinCols) ? 1 : compute; };
+  if (autotune)
+    for (auto& j : jobs) HAPOD_TRY(autotune_tile(node_compute(j.m), eb, j.n, j.m, pool, stream));
   for (auto& j : jobs) {
-    const int tile = gram_tile_for(j.m);
+    const int tile = tile_for_node(node_compute(j.m), j.n, j.m);
     int nt = (int)((j.m + tile - 1) / tile);
     sum_pairs += nt * (nt + 1) / 2;
   }
@@ -293,7 +383,7 @@ hapod_status run_pod_batch(hapod_precision prec, std::vector<PodJob>& jobs, int 
     // a node taken from Jacobi only for speed keeps Jacobi's result: all
     // eigenpairs (a full Lanczos run) and the same truncation policy
     j.wide_full = j.wide && jacobi_max <= 0 && m <= kAutoJacobiMax;
-    L.tile = gram_tile_for(m);
+    L.tile = tile_for_node(node_compute(m), j.n, m);
     L.ntiles = (int)((m + L.tile - 1) / L.tile);
     L.pairs = L.ntiles * (L.ntiles + 1) / 2;
     const int per_node_target = std::max(1, (int)((int64_t)target_items * L.pairs / std::max(sum_pairs, 1)));
@@ -413,7 +503,7 @@ hapod_status run_pod_batch(hapod_precision prec, std::vector<PodJob>& jobs, int 
     // split-BF16 nodes narrower than the pre-split threshold run their Gram on
     // FP32 MFMA: splitting in registers costs more VALU time than the three
     // BF16 products save at these widths (launch slots of their own)
-    const bool f32 = (compute == 2 && m < kPresplitMinCols);
+    const bool f32 = (node_compute(m) != compute);
     std::vector<GramItem>& gi =
         items_by_tile[twin_group[i]][(f32 ? 8 : 0) + 2 * tile_slot(L.tile) + (vec ? 1 : 0)];
     int p = pair_base;
@@ -1123,7 +1213,7 @@ hapod_status hapod_run(hapod_plan_t P, hapod_leaf_fn get_leaf, void* user, void*
         job_node.push_back(a);
       }
       void* blk = nullptr;
-      hapod_status s = run_pod_batch(prec, jobs, 0, 1, jmax, P->pool, stream, &lt, &blk);
+      hapod_status s = run_pod_batch(prec, jobs, 0, 1, jmax, P->pool, stream, &lt, &blk, P->opts.autotune != 0);
       if (s != HAPOD_OK) {
         (void)hipStreamSynchronize(stream);
         if (blk) P->pool.free(blk);
@@ -1320,7 +1410,7 @@ hapod_status hapod_gram(hapod_precision prec, int64_t n, int64_t m, const void* 
 
 namespace hapod {
 hapod_status gram_impl(int compute, int eb, int64_t n, int64_t m, const void* S, int64_t lds, double* G, int64_t ldg,
-                       hipStream_t stream) {
+                       hipStream_t stream, int tile_override) {
   if (n < 0 || m < 0 || (m > 0 && (!G || (n > 0 && !S))) || lds < std::max<int64_t>(n, 1) ||
       ldg < std::max<int64_t>(m, 1)) {
     set_error("hapod_gram: bad sizes or NULL pointer");
@@ -1333,7 +1423,7 @@ hapod_status gram_impl(int compute, int eb, int64_t n, int64_t m, const void* S,
   }
   Pool& pool = step_pool();
   auto cols = column_table(S, lds, m, eb);
-  const int tile = gram_tile_for(m);
+  const int tile = tile_override > 0 ? tile_override : gram_tile_for(m);
   const int nt = (int)((m + tile - 1) / tile);
   const int pairs = nt * (nt + 1) / 2;
   const int KB = (compute == 2) ? 32 : 16;

@@ -77,15 +77,18 @@ def run_both(hp, parent, leaf_data, n, eps_star, omega, prec, zero=(), reorth=Tr
     return plan, sig, host(U), ref, eps, leaf_cols, data64
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
-def test_star_4096x256(hp, prec):
-    """The 4096 x 256 star workload: 4 leaves x 64 sinusoid snapshots."""
-    print(f"star4096x256 {prec}", flush=True)
+@pytest.mark.parametrize("prec,autotune", [("fp64", False), ("fp32", False), ("bf16x3", False),
+                                           ("fp64", True), ("fp32", True)])
+def test_star_4096x256(hp, prec, autotune):
+    """The 4096 x 256 star workload: 4 leaves x 64 sinusoid snapshots (also
+    with the Gram tiles chosen by timing)."""
+    print(f"star4096x256 {prec} autotune {autotune}", flush=True)
     w = synth.WORKLOADS["star4096x256"]
     S = synth.sinusoid(w.n, w.num_snapshots, w.K, w.tau, w.noise_std, w.seed)
     parent = synth.star_tree(4)
     data = dict(enumerate(split_cols(S, w.leaf_cols)))
-    plan, sig, U, ref, eps, cols, data64 = run_both(hp, parent, data, w.n, w.eps_star, w.omega, prec)
+    plan, sig, U, ref, eps, cols, data64 = run_both(hp, parent, data, w.n, w.eps_star, w.omega, prec,
+                                                     autotune=autotune)
     root = 4
     s_ref, U_ref = ref[root]
     ranks = plan.ranks()
