@@ -36,6 +36,7 @@ int compute_mode(hapod_precision p) { return p == HAPOD_FP64 ? 0 : (p == HAPOD_F
 
 constexpr size_t kAlign = 256;
 constexpr int64_t kPresplitMinCols = 256;
+constexpr int kSuperI = 4, kSuperJ = 8;  // Gram tile pairs per super-tile (32 = CUs of an XCD)
 
 // plain column-major n x m (leading dimension ld)
 std::vector<const void*> column_table(const void* base, int64_t ld, int64_t m, int eb) {
@@ -506,17 +507,27 @@ hapod_status run_pod_batch(hapod_precision prec, std::vector<PodJob>& jobs, int 
     const bool f32 = (node_compute(m) != compute);
     std::vector<GramItem>& gi =
         items_by_tile[twin_group[i]][(f32 ? 8 : 0) + 2 * tile_slot(L.tile) + (vec ? 1 : 0)];
-    int p = pair_base;
-    for (int ti = 0; ti < L.ntiles; ++ti)
-      for (int tj = ti; tj < L.ntiles; ++tj, ++p) {
-        for (int c = 0; c < L.nchunks; ++c) gi.push_back(GramItem{i, (int16_t)ti, (int16_t)tj, c, p});
-        if (L.slots > 1) {
-          rpairs.push_back(p);
-          rnode.push_back(i);
-          max_reduce_tile = std::max(max_reduce_tile, L.tile);
-        }
+    // Item order.  The workgroups an XCD runs at once take consecutive items
+    // (see xcd_item), so consecutive items should share column blocks: for
+    // each row chunk, the tile pairs go in super-tiles of kSuperI x kSuperJ
+    // pairs, whose concurrent workgroups read kSuperI + kSuperJ column blocks
+    // of a row stripe instead of about one block per workgroup.  Pair indices
+    // stay row-major over the upper triangle (partial slots, reduction).
+    const int nt = L.ntiles;
+    auto pair_of = [nt](int ti, int tj) { return ti * nt - ti * (ti - 1) / 2 + (tj - ti); };
+    for (int c = 0; c < L.nchunks; ++c)
+      for (int I = 0; I < nt; I += kSuperI)
+        for (int J = (I / kSuperJ) * kSuperJ; J < nt; J += kSuperJ)
+          for (int ti = I; ti < std::min(I + kSuperI, nt); ++ti)
+            for (int tj = std::max(J, ti); tj < std::min(J + kSuperJ, nt); ++tj)
+              gi.push_back(GramItem{i, (int16_t)ti, (int16_t)tj, c, pair_base + pair_of(ti, tj)});
+    if (L.slots > 1)
+      for (int q = 0; q < L.pairs; ++q) {
+        rpairs.push_back(pair_base + q);
+        rnode.push_back(i);
+        max_reduce_tile = std::max(max_reduce_tile, L.tile);
       }
-    pair_base = p;
+    pair_base += L.pairs;
     if (!j.wide && m > 0) {
       EigNode e{};
       e.G = g.G;
