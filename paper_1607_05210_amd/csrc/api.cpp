@@ -354,7 +354,16 @@ hapod_status run_pod_batch(hapod_precision prec, std::vector<PodJob>& jobs, int 
     int nt = (int)((j.m + tile - 1) / tile);
     sum_pairs += nt * (nt + 1) / 2;
   }
-  const int target_items = std::max(2048, sum_pairs);
+  // work items per Gram launch to aim for (row chunks are added until the
+  // tile pairs reach it): 8192 measured best on the 2^20 x 8192 star (FP64
+  // root Gram 1232 -> 1156 ms against 2048) and the 2^22-row chain (1542 ->
+  // 1210 ms); HAPOD_GRAM_ITEMS overrides it
+  int item_goal = 8192;
+  if (const char* e = std::getenv("HAPOD_GRAM_ITEMS")) {
+    const int v = std::atoi(e);
+    if (v > 0) item_goal = v;
+  }
+  const int target_items = std::max(item_goal, sum_pairs);
   // split twins take as much memory as their inputs.  They are made and
   // consumed in groups that fit an arena of at most half of what the device
   // has free (and of what the plan's cap leaves): the Gram of one group runs

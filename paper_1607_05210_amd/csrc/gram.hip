@@ -150,35 +150,58 @@ __global__ __launch_bounds__(256) void gram_tile_kernel(const GramNode* __restri
 
   const int64_t blk0 = r0 >> 7, nblk = (r1 - r0 + kRowBlock - 1) >> 7;
   const int64_t bstart = QUAD ? 0 : wave;
+  // the wavefront's blocks are bstart, bstart + BSTEP, ... < nblk
+  const int64_t nwb = (bstart < nblk) ? (nblk - bstart + BSTEP - 1) / BSTEP : 0;
   if constexpr (C == 2) {
     if (nd.split) {
       // pre-split columns: hi and lo bf16 runs straight from memory; blocks
-      // are zero-padded past n, so every block is read whole
-      for (int64_t bi = bstart; bi < nblk; bi += BSTEP) {
-        gptr<bf8> ha[NBW], hb[NBW];
+      // are zero-padded past n, so every block is read whole.  Batches of
+      // KB rows go through a two-deep register pipeline: the loads of batch
+      // s + 1 are issued before the MFMAs of batch s, also across 128-row
+      // blocks (the batches run in order, so the sums do not change).
+      const int64_t S = nwb * NBT;
+      bf8 xh[2][NBW], xl[2][NBW], yh[2][NBW], yl[2][NBW];
+      auto ld = [&](int64_t st, int buf) {
+        const int64_t blk = blk0 + bstart + (st / NBT) * BSTEP;
+        const int bt = (int)(st % NBT);
 #pragma unroll
         for (int a = 0; a < NBW; ++a) {
-          ha[a] = (gptr<bf8>)as_global(pa[a] + (blk0 + bi) * sa[a]) + g;
-          hb[a] = (gptr<bf8>)as_global(pb[a] + (blk0 + bi) * sb[a]) + g;
+          gptr<bf8> ha = (gptr<bf8>)as_global(pa[a] + blk * sa[a]) + g;
+          xh[buf][a] = ha[4 * bt];
+          xl[buf][a] = ha[4 * bt + 16];
         }
-#pragma unroll
-        for (int bt = 0; bt < NBT; ++bt) {
-          bf8 xh[NBW], xl[NBW], yh[NBW], yl[NBW];
+        if (!QUAD && same) {
 #pragma unroll
           for (int a = 0; a < NBW; ++a) {
-            xh[a] = ha[a][4 * bt];
-            xl[a] = ha[a][4 * bt + 16];
-            yh[a] = hb[a][4 * bt];
-            yl[a] = hb[a][4 * bt + 16];
+            yh[buf][a] = xh[buf][a];
+            yl[buf][a] = xl[buf][a];
           }
+        } else {
 #pragma unroll
-          for (int a = 0; a < NBW; ++a)
+          for (int a = 0; a < NBW; ++a) {
+            gptr<bf8> hb = (gptr<bf8>)as_global(pb[a] + blk * sb[a]) + g;
+            yh[buf][a] = hb[4 * bt];
+            yl[buf][a] = hb[4 * bt + 16];
+          }
+        }
+      };
+      auto mm = [&](int buf) {
 #pragma unroll
-            for (int b = 0; b < NBW; ++b) {
-              acc[a][b] = mfma_bf16(xl[a], yh[b], acc[a][b]);
-              acc[a][b] = mfma_bf16(xh[a], yl[b], acc[a][b]);
-              acc[a][b] = mfma_bf16(xh[a], yh[b], acc[a][b]);
-            }
+        for (int a = 0; a < NBW; ++a)
+#pragma unroll
+          for (int b = 0; b < NBW; ++b) {
+            acc[a][b] = mfma_bf16(xl[buf][a], yh[buf][b], acc[a][b]);
+            acc[a][b] = mfma_bf16(xh[buf][a], yl[buf][b], acc[a][b]);
+            acc[a][b] = mfma_bf16(xh[buf][a], yh[buf][b], acc[a][b]);
+          }
+      };
+      if (S > 0) ld(0, 0);
+      for (int64_t st = 0; st < S; st += 2) {
+        if (st + 1 < S) ld(st + 1, 1);
+        mm(0);
+        if (st + 1 < S) {
+          if (st + 2 < S) ld(st + 2, 0);
+          mm(1);
         }
       }
       goto store;

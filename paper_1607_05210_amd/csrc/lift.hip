@@ -12,7 +12,7 @@
 // 4 j + b (a run of 4 consecutive entries of a row of B).  The store undoes
 // both permutations.
 //
-// The column table (pointer, row-block stride, rows held) of the next 256
+// The column table (pointer, row-block stride, rows held) of the next 1024
 // reduction indices is staged in LDS, so the data loads never wait on a
 // pointer load; data loads are double-buffered in registers: one batch of
 // reduction steps is fetched while the previous one runs on the matrix cores.
@@ -23,7 +23,7 @@ namespace hapod {
 namespace {
 
 constexpr int TM = kLiftTileM, TN = kLiftTileN, WT = 64, NB = WT / 16;
-constexpr int KT = 256;  // reduction indices per LDS column-table chunk (= threads)
+constexpr int KT = 1024;  // reduction indices per LDS column-table chunk (4 per thread)
 
 template <int C> struct LiftTraits;
 template <> struct LiftTraits<0> { using Elem = double; using Acc = d4; };
@@ -96,11 +96,13 @@ __global__ __launch_bounds__(256) void lift_kernel(const LiftNode* __restrict__ 
   else bop = nd.B32;
   const int m = nd.m;
   auto load_table = [&](int kc) {
-    const int k = kc + (int)threadIdx.x;
-    const bool kv = k < m;
-    tcol[threadIdx.x] = kv ? reinterpret_cast<const char*>(nd.cols[k]) : nullptr;
-    trbs[threadIdx.x] = kv ? nd.rbs[k] : kRowBlock;
-    trows[threadIdx.x] = kv ? nd.crows[k] : 0;
+    for (int t = threadIdx.x; t < KT; t += blockDim.x) {
+      const int k = kc + t;
+      const bool kv = k < m;
+      tcol[t] = kv ? reinterpret_cast<const char*>(nd.cols[k]) : nullptr;
+      trbs[t] = kv ? nd.rbs[k] : kRowBlock;
+      trows[t] = kv ? nd.crows[k] : 0;
+    }
   };
   // with at most KT reduction indices the table is loaded once for all tiles
   const bool one_chunk = (m <= KT);
