@@ -224,6 +224,10 @@ typedef int32_t (*hapod_leaf_fn)(void* user, int32_t leaf, const void** ptr,
  * one.  Intermediate node outputs are released once their parent is done;
  * the root's modes and the per-node ranks and singular values are kept in
  * the plan until the next run or hapod_destroy.  Synchronises the stream.
+ * Device memory comes from a pool owned by the plan: blocks a run frees stay
+ * cached for the next run (a repeated run maps no new memory), bounded by
+ * mem_cap_bytes when set; they are returned to the device when an
+ * allocation fails, and by hapod_destroy.
  * Environment: HAPOD_TWIN_BUDGET (bytes) caps the arena that holds the
  * split-BF16 twins of a level (by default half of the free device memory);
  * HAPOD_GRAM_ITEMS sets the work items a Gram launch aims for (default

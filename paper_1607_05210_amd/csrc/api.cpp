@@ -63,6 +63,8 @@ size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 // ---------------------------------------------------------------------------
 class Pool {
  public:
+  static constexpr size_t kBestFitMin = size_t(256) << 20;
+  static constexpr size_t kReserve = size_t(2) << 30;
   ~Pool() { release_all(); }
   hapod_status alloc(size_t bytes, void** out) {
     bytes = align_up(std::max<size_t>(bytes, kAlign));
@@ -72,6 +74,16 @@ class Pool {
       it->second.pop_back();
       return HAPOD_OK;
     }
+    // a large request may take the smallest cached block of up to twice its
+    // size: mapping fresh device memory costs about 20 ms per GiB, so reusing
+    // a held block beats returning it and allocating anew
+    if (bytes >= kBestFitMin)
+      for (auto jt = free_.lower_bound(bytes); jt != free_.end() && jt->first <= 2 * bytes; ++jt)
+        if (!jt->second.empty()) {
+          *out = jt->second.back();
+          jt->second.pop_back();
+          return HAPOD_OK;
+        }
     if (cap_ && held_ + bytes > cap_) {
       // give cached blocks back before failing
       trim();
@@ -81,9 +93,18 @@ class Pool {
         return HAPOD_E_NOMEM;
       }
     }
+    // keep some device memory free for the runtime and the caller: below
+    // that, cached blocks go back before mapping more
+    if (!free_.empty()) {
+      size_t fr = 0, tot = 0;
+      if (hipMemGetInfo(&fr, &tot) == hipSuccess && fr < bytes + kReserve) trim();
+    }
     void* p = nullptr;
     hipError_t e = hipMalloc(&p, bytes);
     if (e != hipSuccess) {
+      // a failed hipMalloc also sets the thread's last error: clear it, or
+      // the launch check after the next kernel would report it
+      (void)hipGetLastError();
       trim();
       e = hipMalloc(&p, bytes);
       if (e != hipSuccess) {
@@ -372,9 +393,15 @@ hapod_status run_pod_batch(hapod_precision prec, std::vector<PodJob>& jobs, int 
   size_t twin_budget = 0;
   if (compute == 2) {
     size_t free_b = 0, total_b = 0;
-    if (hipMemGetInfo(&free_b, &total_b) == hipSuccess) twin_budget = (free_b + pool.cached()) / 2;
+    if (hipMemGetInfo(&free_b, &total_b) == hipSuccess) {
+      const size_t avail = free_b + pool.cached();
+      twin_budget = avail > Pool::kReserve ? (avail - Pool::kReserve) / 2 : 0;
+    }
     const size_t room = pool.room();
     if (room / 2 < twin_budget) twin_budget = room / 2;
+    // whole GiB: the same level of the next run then asks for the same arena
+    // and finds it in the pool's cache
+    if (twin_budget >= (size_t(2) << 30)) twin_budget &= ~((size_t(1) << 30) - 1);
     // HAPOD_TWIN_BUDGET (bytes) lowers the arena further
     if (const char* e = std::getenv("HAPOD_TWIN_BUDGET")) {
       const long long v = std::atoll(e);
@@ -457,10 +484,10 @@ hapod_status run_pod_batch(hapod_precision prec, std::vector<PodJob>& jobs, int 
   // split-twin arena (released with the batch)
   char* arena = nullptr;
   if (arena_bytes > 0) HAPOD_TRY(pool.alloc(arena_bytes, (void**)&arena));
-  struct GuardA {  // sized by the free memory: not kept in the cache
+  struct GuardA {
     Pool& p;
     void* s;
-    ~GuardA() { p.free_now(s); }
+    ~GuardA() { p.free(s); }
   } guarda{pool, arena};
   std::vector<void*> split_buf(nj, nullptr);
   std::vector<std::vector<const void*>> cols2(nj);
@@ -1324,13 +1351,8 @@ hapod_status hapod_run(hapod_plan_t P, hapod_leaf_fn get_leaf, void* user, void*
   P->root_U = out_buf[P->root];
   out_buf[P->root] = nullptr;
   release_all();
-  // cached blocks speed up the next run of the plan, but not at the price of
-  // starving the caller: with less than a quarter of the device free, return
-  // them
-  {
-    size_t free_b = 0, total_b = 0;
-    if (hipMemGetInfo(&free_b, &total_b) == hipSuccess && free_b < total_b / 4) P->pool.trim();
-  }
+  // the blocks freed by this run stay cached for the next one (mem_cap_bytes
+  // bounds them; a failed device allocation returns them first)
   P->has_result = true;
   return HAPOD_OK;
 }

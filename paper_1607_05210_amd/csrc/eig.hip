@@ -39,17 +39,19 @@ __device__ __forceinline__ int slot_next(int s, int h) {
   return (k == 0) ? 2 : 2 * (k - 1) + 1;
 }
 
+// The two buffers are picked with a select, not by indexing a two-entry
+// array: a dynamically indexed array would live in per-lane scratch memory.
 struct GlobalStore {
   double* buf[2];
   int ld;
   __device__ __forceinline__ double& at(int b, int i, int j) const {  // i <= j
-    return buf[b][(int64_t)j * ld + i];
+    return (b ? buf[1] : buf[0])[(int64_t)j * ld + i];
   }
 };
 struct LdsStore {
   double* buf[2];
   __device__ __forceinline__ double& at(int b, int i, int j) const {  // i <= j
-    return buf[b][(j * (j + 1) >> 1) + i];
+    return (b ? buf[1] : buf[0])[(j * (j + 1) >> 1) + i];
   }
 };
 

@@ -177,7 +177,8 @@ struct LiftNode {
                          // items are ceil(row_tiles / rt_per) x col_tiles
   int32_t pad;
 };
-// compute as for launch_gram (0, 1, 2); output storage = input storage.
+// compute: 0 FP64 MFMA, 1 FP32 MFMA (the split-BF16 form lifts on FP32
+// MFMA); output storage = input storage.
 // narrow: every node has N <= 64 and its tiles are kLiftNarrowM x 64
 // (row_tiles and col_tiles counted for that tile).
 constexpr int kLiftNarrowM = 256;

@@ -28,7 +28,6 @@ constexpr int KT = 1024;  // reduction indices per LDS column-table chunk (4 per
 template <int C> struct LiftTraits;
 template <> struct LiftTraits<0> { using Elem = double; using Acc = d4; };
 template <> struct LiftTraits<1> { using Elem = float; using Acc = f4; };
-template <> struct LiftTraits<2> { using Elem = float; using Acc = f4; };
 
 // out[t] = p[t] for t < avail (at most 4), else 0; one vector load when the
 // run is whole and 16-byte aligned.
@@ -148,90 +147,39 @@ __global__ __launch_bounds__(256) void lift_kernel(const LiftNode* __restrict__ 
         for (int b = 0; b < 4; ++b) y[b] = BElem(0);
       }
     };
-    if constexpr (C == 0 || C == 1) {
-      // batches of U MFMA steps of 4 reduction indices each
-      constexpr int U = 4, KB = 4 * U;
-      Elem xa[2][U][4];
-      BElem xb[2][U][4];
-      auto load = [&](int kb, Elem (&va)[U][4], BElem (&vb)[U][4]) {
+    // batches of U MFMA steps of 4 reduction indices each
+    constexpr int U = 4, KB = 4 * U;
+    Elem xa[2][U][4];
+    BElem xb[2][U][4];
+    auto load = [&](int kb, Elem (&va)[U][4], BElem (&vb)[U][4]) {
 #pragma unroll
-        for (int t = 0; t < U; ++t) {
-          const int k = kb + 4 * t + g;
-          if (k < kend) srun(k - kc, va[t]);
-          else {
+      for (int t = 0; t < U; ++t) {
+        const int k = kb + 4 * t + g;
+        if (k < kend) srun(k - kc, va[t]);
+        else {
 #pragma unroll
-            for (int a = 0; a < 4; ++a) va[t][a] = Elem(0);
-          }
-          brun(k, vb[t]);
+          for (int a = 0; a < 4; ++a) va[t][a] = Elem(0);
         }
-      };
-      auto compute = [&](Elem (&va)[U][4], BElem (&vb)[U][4]) {
-#pragma unroll
-        for (int t = 0; t < U; ++t)
-#pragma unroll
-          for (int a = 0; a < NB; ++a)
-#pragma unroll
-            for (int b = 0; b < NB; ++b) {
-              if constexpr (C == 0) acc[a][b] = mfma_f64(va[t][a], vb[t][b], acc[a][b]);
-              else acc[a][b] = mfma_f32(va[t][a], vb[t][b], acc[a][b]);
-            }
-      };
-      load(kc, xa[0], xb[0]);
-      for (int kb = kc; kb < kend; kb += 2 * KB) {
-        load(kb + KB, xa[1], xb[1]);
-        compute(xa[0], xb[0]);
-        if (kb + 2 * KB < kend) load(kb + 2 * KB, xa[0], xb[0]);
-        compute(xa[1], xb[1]);
+        brun(k, vb[t]);
       }
-    } else {
-      // split-BF16: lane covers reduction slots 8g..8g+7 of each 32-wide step
-      constexpr int KS = 32;
-      float ya[2][8][4];
-      float yb[2][8][4];
-      auto load = [&](int k0, float (&xa)[8][4], float (&xb)[8][4]) {
+    };
+    auto compute = [&](Elem (&va)[U][4], BElem (&vb)[U][4]) {
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          const int k = k0 + 8 * g + e;
-          if (k < kend) srun(k - kc, xa[e]);
-          else {
-#pragma unroll
-            for (int a = 0; a < 4; ++a) xa[e][a] = 0.f;
-          }
-          brun(k, xb[e]);
-        }
-      };
-      auto compute = [&](float (&xa)[8][4], float (&xb)[8][4]) {
-        bf8 ha[NB], la[NB], hb[NB], lb[NB];
-#pragma unroll
-        for (int a = 0; a < NB; ++a) {
-          float v[8];
-#pragma unroll
-          for (int e = 0; e < 8; ++e) v[e] = xa[e][a];
-          split_bf16x8(v, ha[a], la[a]);
-        }
-#pragma unroll
-        for (int b = 0; b < NB; ++b) {
-          float v[8];
-#pragma unroll
-          for (int e = 0; e < 8; ++e) v[e] = xb[e][b];
-          split_bf16x8(v, hb[b], lb[b]);
-        }
+      for (int t = 0; t < U; ++t)
 #pragma unroll
         for (int a = 0; a < NB; ++a)
 #pragma unroll
           for (int b = 0; b < NB; ++b) {
-            acc[a][b] = mfma_bf16(la[a], hb[b], acc[a][b]);
-            acc[a][b] = mfma_bf16(ha[a], lb[b], acc[a][b]);
-            acc[a][b] = mfma_bf16(ha[a], hb[b], acc[a][b]);
+            if constexpr (C == 0) acc[a][b] = mfma_f64(va[t][a], vb[t][b], acc[a][b]);
+            else acc[a][b] = mfma_f32(va[t][a], vb[t][b], acc[a][b]);
           }
-      };
-      load(kc, ya[0], yb[0]);
-      for (int k0 = kc; k0 < kend; k0 += 2 * KS) {
-        load(k0 + KS, ya[1], yb[1]);
-        compute(ya[0], yb[0]);
-        if (k0 + 2 * KS < kend) load(k0 + 2 * KS, ya[0], yb[0]);
-        compute(ya[1], yb[1]);
-      }
+    };
+    load(kc, xa[0], xb[0]);
+    for (int kb = kc; kb < kend; kb += 2 * KB) {
+      load(kb + KB, xa[1], xb[1]);
+      compute(xa[0], xb[0]);
+      if (kb + 2 * KB < kend) load(kb + 2 * KB, xa[0], xb[0]);
+      compute(xa[1], xb[1]);
     }
   }
   if (!active) continue;
@@ -280,8 +228,6 @@ hapod_status launch_lift(int compute, const LiftNode* d_nodes, int num_nodes, in
     case 1: hipLaunchKernelGGL((lift_kernel<0, true>), g, b, 0, stream, d_nodes, num_nodes); break;
     case 2: hipLaunchKernelGGL((lift_kernel<1, false>), g, b, 0, stream, d_nodes, num_nodes); break;
     case 3: hipLaunchKernelGGL((lift_kernel<1, true>), g, b, 0, stream, d_nodes, num_nodes); break;
-    case 4: hipLaunchKernelGGL((lift_kernel<2, false>), g, b, 0, stream, d_nodes, num_nodes); break;
-    case 5: hipLaunchKernelGGL((lift_kernel<2, true>), g, b, 0, stream, d_nodes, num_nodes); break;
     default: set_error("launch_lift: unknown compute mode"); return HAPOD_E_INVALID;
   }
   HAPOD_HIP(hipGetLastError());
