@@ -232,7 +232,8 @@ typedef int32_t (*hapod_leaf_fn)(void* user, int32_t leaf, const void** ptr,
  * split-BF16 twins of a level (by default half of the free device memory);
  * HAPOD_GRAM_ITEMS sets the work items a Gram launch aims for (default
  * 8192; row chunks are added until the tile pairs reach it);
- * HAPOD_VERBOSE=1 prints the Krylov eigensolver's progress to stderr.      */
+ * HAPOD_VERBOSE=1 prints the Krylov eigensolver's progress and the device
+ * memory the plan maps and returns to stderr.      */
 hapod_status hapod_run(hapod_plan_t plan, hapod_leaf_fn get_leaf, void* user,
                        void* stream);
 

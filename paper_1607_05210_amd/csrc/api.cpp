@@ -94,12 +94,13 @@ class Pool {
       }
     }
     // keep some device memory free for the runtime and the caller: below
-    // that, cached blocks go back before mapping more
-    if (!free_.empty()) {
-      size_t fr = 0, tot = 0;
-      if (hipMemGetInfo(&fr, &tot) == hipSuccess && fr < bytes + kReserve) trim();
-    }
+    // that, cached blocks go back (largest first, only as many as needed)
+    // before mapping more
+    size_t fr = 0, tot = 0;
+    if (!free_.empty() && hipMemGetInfo(&fr, &tot) == hipSuccess && fr < bytes + kReserve)
+      trim_until(bytes + kReserve - fr);
     void* p = nullptr;
+    if (verbose_) std::fprintf(stderr, "[hapod pool] map %zu bytes (free %zu)\n", bytes, fr);
     hipError_t e = hipMalloc(&p, bytes);
     if (e != hipSuccess) {
       // a failed hipMalloc also sets the thread's last error: clear it, or
@@ -133,6 +134,27 @@ class Pool {
     size_of_.erase(it);
     (void)hipFree(p);
   }
+  // Return cached blocks until at least `bytes` went back: the smallest
+  // block that covers what is still missing, else the largest and repeat.
+  // Large blocks are the expensive ones to map again, and the next run of
+  // the plan asks for the same sizes.
+  void trim_until(size_t bytes) {
+    size_t freed = 0;
+    while (freed < bytes) {
+      for (auto it = free_.begin(); it != free_.end();)
+        it = it->second.empty() ? free_.erase(it) : std::next(it);
+      if (free_.empty()) break;
+      auto it = free_.lower_bound(bytes - freed);
+      if (it == free_.end()) it = std::prev(free_.end());
+      void* p = it->second.back();
+      it->second.pop_back();
+      freed += it->first;
+      held_ -= it->first;
+      size_of_.erase(p);
+      (void)hipFree(p);
+      if (verbose_) std::fprintf(stderr, "[hapod pool] return %zu bytes\n", it->first);
+    }
+  }
   void trim() {
     for (auto& kv : free_)
       for (void* p : kv.second) {
@@ -147,6 +169,27 @@ class Pool {
     size_of_.clear();
     free_.clear();
     held_ = 0;
+    if (pinned_) (void)hipHostFree(pinned_);
+    pinned_ = nullptr;
+    pinned_bytes_ = 0;
+  }
+  // Pinned host staging of at least `bytes` (grown on demand; its contents
+  // do not survive growth).  Small descriptor uploads and readbacks go
+  // through it: copies from pageable memory can stall the host for a long
+  // and varying time.  The caller orders its uses on one stream.
+  char* pinned(size_t bytes) {
+    if (bytes <= pinned_bytes_) return (char*)pinned_;
+    if (pinned_) (void)hipHostFree(pinned_);
+    pinned_ = nullptr;
+    pinned_bytes_ = 0;
+    const size_t want = std::max<size_t>(align_up(bytes), size_t(64) << 10);
+    if (hipHostMalloc(&pinned_, want, hipHostMallocDefault) != hipSuccess) {
+      (void)hipGetLastError();
+      pinned_ = nullptr;
+      return nullptr;
+    }
+    pinned_bytes_ = want;
+    return (char*)pinned_;
   }
   void set_cap(size_t c) { cap_ = c; }
   size_t held() const { return held_; }
@@ -155,6 +198,13 @@ class Pool {
     size_t c = 0;
     for (auto& kv : free_) c += kv.first * kv.second.size();
     return c;
+  }
+  // size of the largest cached block within [lo, hi], 0 if none
+  size_t cached_within(size_t lo, size_t hi) const {
+    size_t best = 0;
+    for (auto it = free_.lower_bound(lo); it != free_.end() && it->first <= hi; ++it)
+      if (!it->second.empty()) best = it->first;
+    return best;
   }
   // bytes the cap still allows (cached blocks count as available)
   size_t room() const {
@@ -167,6 +217,12 @@ class Pool {
   std::map<size_t, std::vector<void*>> free_;
   std::map<void*, size_t> size_of_;
   size_t held_ = 0, cap_ = 0;
+  void* pinned_ = nullptr;
+  size_t pinned_bytes_ = 0;
+  bool verbose_ = [] {
+    const char* v = std::getenv("HAPOD_VERBOSE");
+    return v && v[0] == '1';
+  }();
 };
 
 // Host staging blob that becomes one device blob (descriptor tables).
@@ -402,6 +458,10 @@ hapod_status run_pod_batch(hapod_precision prec, std::vector<PodJob>& jobs, int 
     // whole GiB: the same level of the next run then asks for the same arena
     // and finds it in the pool's cache
     if (twin_budget >= (size_t(2) << 30)) twin_budget &= ~((size_t(1) << 30) - 1);
+    // a cached block near that size (an earlier run's arena) becomes the
+    // arena: free memory drifts between runs, and an arena a little larger
+    // than every cached block would map memory anew each run
+    if (const size_t c = pool.cached_within(twin_budget / 2, twin_budget + twin_budget / 2)) twin_budget = c;
     // HAPOD_TWIN_BUDGET (bytes) lowers the arena further
     if (const char* e = std::getenv("HAPOD_TWIN_BUDGET")) {
       const long long v = std::atoll(e);
@@ -504,8 +564,9 @@ hapod_status run_pod_batch(hapod_precision prec, std::vector<PodJob>& jobs, int 
   // ---- descriptor tables ----------------------------------------------------
   std::vector<GramNode> gnodes(nj);
   std::vector<GramItem> gitems;
-  // per twin group: (default compute, FP32) x (tile 128, 64, 32, 16) x (scalar, vector runs)
-  std::vector<std::array<std::vector<GramItem>, 16>> items_by_tile(ngroups);
+  // per twin group: (default compute, FP32) x (tile 128, 64, 32, 16) x (scalar,
+  // vector runs), and slot 16: pre-split 128-column tiles staged through LDS
+  std::vector<std::array<std::vector<GramItem>, 17>> items_by_tile(ngroups);
   auto tile_slot = [](int t) { return t == 128 ? 0 : t == 64 ? 1 : t == 32 ? 2 : 3; };
   int max_reduce_tile = 0;
   std::vector<int32_t> rpairs, rnode;
@@ -541,8 +602,9 @@ hapod_status run_pod_batch(hapod_precision prec, std::vector<PodJob>& jobs, int 
     // FP32 MFMA: splitting in registers costs more VALU time than the three
     // BF16 products save at these widths (launch slots of their own)
     const bool f32 = (node_compute(m) != compute);
+    const bool staged = L.presplit && !f32 && L.tile == 128;
     std::vector<GramItem>& gi =
-        items_by_tile[twin_group[i]][(f32 ? 8 : 0) + 2 * tile_slot(L.tile) + (vec ? 1 : 0)];
+        items_by_tile[twin_group[i]][staged ? 16 : (f32 ? 8 : 0) + 2 * tile_slot(L.tile) + (vec ? 1 : 0)];
     // Item order.  The workgroups an XCD runs at once take consecutive items
     // (see xcd_item), so consecutive items should share column blocks: for
     // each row chunk, the tile pairs go in super-tiles of kSuperI x kSuperJ
@@ -612,11 +674,14 @@ hapod_status run_pod_batch(hapod_precision prec, std::vector<PodJob>& jobs, int 
   }
   std::vector<std::vector<GramLaunch>> glaunch(ngroups);
   for (int gr = 0; gr < ngroups; ++gr)
-    for (int t = 0; t < 16; ++t) {
+    for (int t = 0; t < 17; ++t) {
       const auto& v = items_by_tile[gr][t];
       if (v.empty()) continue;
-      glaunch[gr].push_back(GramLaunch{128 >> ((t & 7) / 2), t & 1, (int32_t)gitems.size(), (int32_t)v.size(),
-                                       t >= 8 ? 1 : -1});
+      if (t == 16)
+        glaunch[gr].push_back(GramLaunch{128, 2, (int32_t)gitems.size(), (int32_t)v.size(), -1});
+      else
+        glaunch[gr].push_back(GramLaunch{128 >> ((t & 7) / 2), t & 1, (int32_t)gitems.size(), (int32_t)v.size(),
+                                         t >= 8 ? 1 : -1});
       gitems.insert(gitems.end(), v.begin(), v.end());
     }
   const size_t o_g = blob.add_vec(gnodes), o_gi = blob.add_vec(gitems), o_rp = blob.add_vec(rpairs),
@@ -738,19 +803,31 @@ hapod_status run_pod_batch(hapod_precision prec, std::vector<PodJob>& jobs, int 
     }
   }
   if (times && ev.ok) HAPOD_HIP(hipEventRecord(ev.e[2], stream));
-  // wide nodes changed floor_abs on the host: refresh their descriptors
-  for (int i = 0; i < nj; ++i)
-    if (jobs[i].wide)
-      HAPOD_HIP(hipMemcpyAsync(dblob + o_t + i * sizeof(TruncNode), &tnodes[i], sizeof(TruncNode),
-                               hipMemcpyHostToDevice, stream));
+  // wide nodes changed floor_abs on the host: refresh the descriptors (one
+  // copy through pinned staging)
+  bool any_wide = false;
+  for (int i = 0; i < nj; ++i) any_wide |= jobs[i].wide;
+  char* pin = pool.pinned(std::max(sizeof(TruncNode), sizeof(int64_t)) * (size_t)nj);
+  if (!pin) {
+    set_error("hipHostMalloc of the descriptor staging failed");
+    return HAPOD_E_NOMEM;
+  }
+  if (any_wide) {
+    std::memcpy(pin, tnodes.data(), sizeof(TruncNode) * nj);
+    HAPOD_HIP(hipMemcpyAsync(dblob + o_t, pin, sizeof(TruncNode) * nj, hipMemcpyHostToDevice, stream));
+  }
   // ---- truncation -----------------------------------------------------------
   HAPOD_TRY(launch_truncate((const TruncNode*)(dblob + o_t), nj, stream));
   if (times && ev.ok) HAPOD_HIP(hipEventRecord(ev.e[3], stream));
   // ---- lift, sized by the ranks just computed ---------------------------------
+  // (the ranks come back through the same staging: stream order puts these
+  // copies after the descriptor upload that read it)
   std::vector<int64_t> ranks(nj, 0);
-  HAPOD_HIP(hipStreamSynchronize(stream));
   for (int i = 0; i < nj; ++i)
-    HAPOD_HIP(hipMemcpy(&ranks[i], scratch + lay[i].rank, sizeof(int64_t), hipMemcpyDeviceToHost));
+    HAPOD_HIP(hipMemcpyAsync(pin + i * sizeof(int64_t), scratch + lay[i].rank, sizeof(int64_t),
+                             hipMemcpyDeviceToHost, stream));
+  HAPOD_HIP(hipStreamSynchronize(stream));
+  std::memcpy(ranks.data(), pin, sizeof(int64_t) * nj);
   // outputs sized by the ranks, carved from one block for the batch (one
   // allocation instead of one per node; the caller frees the block once
   // every node in it has been consumed)
@@ -1555,7 +1632,8 @@ hapod_status gram_impl(int compute, int eb, int64_t n, int64_t m, const void* S,
       }
       break;
     }
-    const GramLaunch gl{tile, vec_ok ? 1 : 0, 0, (int32_t)items.size(), (compute == 2 && m < kPresplitMinCols) ? 1 : -1};
+    const int vec_mode = (presplit && tile == 128) ? 2 : (vec_ok ? 1 : 0);
+    const GramLaunch gl{tile, vec_mode, 0, (int32_t)items.size(), (compute == 2 && m < kPresplitMinCols) ? 1 : -1};
     st = launch_gram(compute, (const GramNode*)(db + o_g), (const GramItem*)(db + o_i), &gl, 1,
                      (const int32_t*)(db + o_rp), (const int32_t*)(db + o_rn), (int)rp.size(), tile, stream);
   } while (0);

@@ -97,9 +97,13 @@ __device__ __forceinline__ void mfma_batch(Acc (&acc)[NBW][NBW], typename GramTr
   }
 }
 
-template <int C, bool VEC, int NBW, bool QUAD>
+// STAGED: the pre-split split-BF16 128 x 128 tile through LDS (every node of
+// the launch pre-split); its own instantiation, so the register paths do not
+// set its register budget.
+template <int C, bool VEC, int NBW, bool QUAD, bool STAGED = false>
 __global__ __launch_bounds__(256) void gram_tile_kernel(const GramNode* __restrict__ nodes,
                                                         const GramItem* __restrict__ items, int first) {
+  static_assert(!STAGED || (C == 2 && QUAD && NBW == 4), "staged path: split-BF16 quad tiles only");
   using Tr = GramTraits<C>;
   using Elem = typename Tr::Elem;
   using Acc = typename Tr::Acc;
@@ -115,11 +119,14 @@ __global__ __launch_bounds__(256) void gram_tile_kernel(const GramNode* __restri
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int wi = QUAD ? (wave >> 1) : 0, wj = QUAD ? (wave & 1) : 0;
   const bool diag = (item.ti == item.tj);
-  // the lower sub-tile of a diagonal tile mirrors the upper one
-  if (QUAD && diag && wi > wj) return;
   const int li = lane & 15, g = lane >> 4;
   const int cA0 = item.ti * TT + wi * WT, cB0 = item.tj * TT + wj * WT;
-  if (cA0 >= nd.m || cB0 >= nd.m) return;
+  // the lower sub-tile of a diagonal tile mirrors the upper one; sub-tiles
+  // past m hold nothing
+  const bool idle = (QUAD && diag && wi > wj) || cA0 >= nd.m || cB0 >= nd.m;
+  // the staged path keeps every wavefront for its barriers
+  constexpr bool kStaged = STAGED;
+  if (idle && !kStaged) return;
   const bool same = (cA0 == cB0);  // both operands are the same columns
 
   // row range of this chunk; chunks start on 128-row block boundaries
@@ -152,6 +159,84 @@ __global__ __launch_bounds__(256) void gram_tile_kernel(const GramNode* __restri
   const int64_t bstart = QUAD ? 0 : wave;
   // the wavefront's blocks are bstart, bstart + BSTEP, ... < nblk
   const int64_t nwb = (bstart < nblk) ? (nblk - bstart + BSTEP - 1) / BSTEP : 0;
+  if constexpr (kStaged) {
+    {
+      // Pre-split columns, 128 x 128 tile: the workgroup stages 32 rows of
+      // its 256 columns (128 when ti = tj) through LDS, double-buffered, so
+      // every value is fetched from global memory once per workgroup
+      // instead of once per wavefront that reads it (two of four); the next
+      // stage's loads are in flight while the current one runs on the
+      // matrix cores.  Thread t always loads part t % 8 of a column (hi
+      // runs 0..3, lo runs 4..7 of the 32-row step) for columns
+      // 32 i + t / 8, i = 0..7.  Same products in the same order as the
+      // register path below, so the sums are identical.
+      constexpr int kColB = 8 * 16 + 16;  // LDS bytes per column and stage (padded)
+      __shared__ __attribute__((aligned(16))) char stage[2][256 * kColB];
+      const int t = threadIdx.x, part = t & 7;
+      const int ncl = diag ? 128 : 256;  // columns staged
+      const int nld = ncl / 32;          // loads per thread and stage
+      const float* cp[8];
+      int64_t cs[8];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int cl = 32 * i + (t >> 3);
+        const int base = (cl < 128) ? item.ti * TT + cl : item.tj * TT + (cl - 128);
+        const int c = min(base, nd.m - 1);  // columns past m alias the last one
+        cp[i] = reinterpret_cast<const float*>(nd.cols[c]);
+        cs[i] = nd.rbs[c];
+      }
+      const int poff = (part < 4) ? part : 16 + (part - 4);  // bf8 offset in the step
+      const int64_t S = nblk * NBT;  // 32-row steps of the chunk
+      bf8 pre[8];
+      auto gload = [&](int64_t st) {
+        const int64_t blk = blk0 + st / NBT;
+        const int bt = (int)(st % NBT);
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+          if (i < nld) pre[i] = ((gptr<bf8>)as_global(cp[i] + blk * cs[i]))[4 * bt + poff];
+      };
+      auto lstore = [&](int buf) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+          if (i < nld) *(bf8*)(stage[buf] + (32 * i + (t >> 3)) * kColB + part * 16) = pre[i];
+      };
+      const int la = wi * 64, lb = diag ? wj * 64 : 128 + wj * 64;  // staged column bases
+      auto compute = [&](int buf) {
+        const char* sb = stage[buf];
+        bf8 yh[NBW], yl[NBW];
+#pragma unroll
+        for (int b = 0; b < NBW; ++b) {
+          const char* q = sb + (lb + b * 16 + li) * kColB + g * 16;
+          yh[b] = *(const bf8*)q;
+          yl[b] = *(const bf8*)(q + 64);
+        }
+#pragma unroll
+        for (int a = 0; a < NBW; ++a) {
+          const char* q = sb + (la + a * 16 + li) * kColB + g * 16;
+          const bf8 xh = *(const bf8*)q;
+          const bf8 xl = *(const bf8*)(q + 64);
+#pragma unroll
+          for (int b = 0; b < NBW; ++b) {
+            acc[a][b] = mfma_bf16(xl, yh[b], acc[a][b]);
+            acc[a][b] = mfma_bf16(xh, yl[b], acc[a][b]);
+            acc[a][b] = mfma_bf16(xh, yh[b], acc[a][b]);
+          }
+        }
+      };
+      if (S > 0) {
+        gload(0);
+        lstore(0);
+      }
+      __syncthreads();
+      for (int64_t st = 0; st < S; ++st) {
+        if (st + 1 < S) gload(st + 1);
+        if (!idle) compute((int)(st & 1));
+        if (st + 1 < S) lstore((int)((st + 1) & 1));
+        __syncthreads();
+      }
+      if (idle) return;
+    }
+  } else {
   if constexpr (C == 2) {
     if (nd.split) {
       // pre-split columns: hi and lo bf16 runs straight from memory; blocks
@@ -259,6 +344,7 @@ __global__ __launch_bounds__(256) void gram_tile_kernel(const GramNode* __restri
     }
   }
   }
+  }  // register paths
 
 store:
   if (QUAD && nd.nchunks == 1) {
@@ -356,8 +442,23 @@ hapod_status launch_gram_c(const GramNode* d_nodes, const GramItem* d_items, con
       set_error("launch_gram: tile must be 128, 64, 32 or 16");
       return HAPOD_E_INVALID;
     }
-    if (L.vec) launch_tile<C, true>(L.tile, d_nodes, d_items, L.first, L.count, stream);
-    else launch_tile<C, false>(L.tile, d_nodes, d_items, L.first, L.count, stream);
+    if (L.vec == 2) {
+      if constexpr (C == 2) {
+        if (L.tile != 128) {
+          set_error("launch_gram: staged launches take 128-column tiles");
+          return HAPOD_E_INVALID;
+        }
+        hipLaunchKernelGGL((gram_tile_kernel<2, true, 4, true, true>), dim3(L.count), dim3(256), 0, stream, d_nodes,
+                           d_items, L.first);
+      } else {
+        set_error("launch_gram: staged launches are split-BF16 only");
+        return HAPOD_E_INVALID;
+      }
+    } else if (L.vec) {
+      launch_tile<C, true>(L.tile, d_nodes, d_items, L.first, L.count, stream);
+    } else {
+      launch_tile<C, false>(L.tile, d_nodes, d_items, L.first, L.count, stream);
+    }
     HAPOD_HIP(hipGetLastError());
   }
   return HAPOD_OK;

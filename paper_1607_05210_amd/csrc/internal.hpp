@@ -88,7 +88,9 @@ struct GramItem {
 // [first, first + count) of d_items, all of nodes with that tile.  The reduce
 // pass covers num_reduce (pair, node) entries over tiles up to max_tile.
 // vec: every column of these nodes starts 16-byte aligned and the chunk
-// length is a multiple of the MFMA batch, so runs are read as vectors.
+// length is a multiple of the MFMA batch, so runs are read as vectors;
+// vec = 2: every node is pre-split split-BF16 with 128-column tiles, staged
+// through LDS.
 // compute >= 0 overrides the launch_gram compute mode for these items.
 struct GramLaunch {
   int32_t tile;

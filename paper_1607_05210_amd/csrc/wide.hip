@@ -28,8 +28,10 @@
 // Several matrices are solved together: every kernel of a step takes the list
 // of matrices still iterating (grid z), so a level with many wide nodes costs
 // one launch per kernel per step instead of one per node; a matrix leaves the
-// list when its own stopping test is met.  Each matrix's arithmetic is the
-// same as when it is solved alone.
+// list when its own stopping test is met.  Small matrices (see kFusedMaxM)
+// instead run a whole period of steps in one workgroup of their own
+// (lanczos_fused_kernel): the same steps, with sums taken in another order,
+// so a matrix's result depends on the path to rounding level only.
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
@@ -247,6 +249,231 @@ __global__ __launch_bounds__(1024) void breakdown_kernel(const LzNode* __restric
   double* q_next = n.Q + (int64_t)(j + 1) * n.m;
   for (int64_t i = threadIdx.x; i < n.m; i += blockDim.x) q_next[i] = w[i] * inv;
   if (threadIdx.x == 0) n.beta[j] = 0.0;
+}
+
+// One workgroup runs steps j0 .. j1-1 of one small matrix (m <= kFusedMaxM)
+// with the arithmetic of the step kernels above: w = G q_j, two classical
+// Gram-Schmidt passes (alpha_j collects both coefficients of q_j), beta_j =
+// ||w||, and the breakdown restart.  q_j, w, the projection coefficients and
+// the first Lanczos vectors (as many as kFusedQCache doubles hold) live in
+// LDS; G and the later vectors are read from global memory (L2 at these
+// sizes).  For small matrices one launch per period of steps replaces seven
+// launches per step, whose fixed cost dominated.  One workgroup streams L2
+// data at a few tens of GB/s, so above kFusedAloneMaxM columns the step
+// kernels, spread over many workgroups, are faster for a matrix alone (about
+// 35 us against 33 us per step at 243 columns, 37 against 129 at 512); with
+// kFusedBatchMin or more such matrices in the batch, the fused workgroups run
+// side by side on their own compute units and win again.
+constexpr int kFusedMaxM = 512;
+constexpr int kFusedAloneMaxM = 224;
+constexpr int kFusedBatchMin = 8;
+constexpr int kFusedThreads = 512;
+constexpr int kFusedQCache = 16384;  // doubles of LDS for leading Lanczos vectors
+// Loads go through global-address-space pointers in explicit batches:
+// generic (flat) loads mixed with LDS reads would make the compiler wait for
+// every load before the next.
+constexpr int kFusedBatch = 8;
+
+// Column c of Q: the LDS copy for c < nq, else global memory.
+struct FusedQ {
+  const double* g;   // global, column-major, ld m
+  const double* l;   // LDS copy of columns 0 .. nq-1
+  int64_t m;
+  int nq;
+};
+
+// sum over c = c0, c0 + stride, ... < cend of X[c * ldx + r] * v[c] (v in LDS)
+__device__ __forceinline__ double fused_rowdot(const double* __restrict__ X, int64_t ldx, int64_t r, int c0,
+                                               int cend, int stride, const double* v) {
+  const gptr<double> Xg = as_global(X);
+  double acc = 0.0;
+  for (int c = c0; c < cend; c += kFusedBatch * stride) {
+    double x[kFusedBatch];
+#pragma unroll
+    for (int u = 0; u < kFusedBatch; ++u) {
+      const int cc = c + u * stride;
+      x[u] = (cc < cend) ? Xg[(int64_t)cc * ldx + r] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kFusedBatch; ++u) {
+      const int cc = c + u * stride;
+      if (cc < cend) acc += x[u] * v[cc];
+    }
+  }
+  return acc;
+}
+
+// the same sum over columns of Q (LDS part first, then global memory)
+__device__ __forceinline__ double fused_qrowdot(const FusedQ& Q, int64_t r, int c0, int cend, int stride,
+                                                const double* v) {
+  double acc = 0.0;
+  const int lend = min(cend, Q.nq);
+  int c = c0;
+  for (; c < lend; c += stride) acc += Q.l[(int64_t)c * Q.m + r] * v[c];
+  return acc + fused_rowdot(Q.g, Q.m, r, c, cend, stride, v);
+}
+
+// 64-lane sums of four values: lane 16 u holds the sum of t[u] (u = 0..3);
+// halving exchanges take 7 shuffles instead of 24.
+__device__ __forceinline__ double wave_sum4(const double (&t)[4], int lane) {
+  const bool a = (lane & 32) != 0, b = (lane & 16) != 0;
+  double k0 = a ? t[2] : t[0], k1 = a ? t[3] : t[1];
+  const double s0 = a ? t[0] : t[2], s1 = a ? t[1] : t[3];
+  k0 += __shfl_xor(s0, 32, 64);
+  k1 += __shfl_xor(s1, 32, 64);
+  double k = b ? k1 : k0;
+  k += __shfl_xor(b ? k0 : k1, 16, 64);
+#pragma unroll
+  for (int off = 8; off > 0; off >>= 1) k += __shfl_xor(k, off, 64);
+  return k;
+}
+
+// h = Q[:, 0..j]^T w, then w -= Q h.  Projection: each wavefront takes
+// every nw-th column, four at a time, its lanes striding the rows.  Update:
+// the rows split over groups of threads, each group summing every groups-th
+// column, the groups' partial sums added in a fixed order.  Returns h[j].
+__device__ double fused_cgs_pass(const FusedQ& Q, int j, double* w_s, double* hs, double* part, int rows_pad) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  constexpr int nw = kFusedThreads / 64;
+  const int64_t m = Q.m;
+  const gptr<double> Qg = as_global(Q.g);
+  for (int c0 = wave; c0 <= j; c0 += 4 * nw) {
+    double t[4] = {0.0, 0.0, 0.0, 0.0};
+    if (c0 + 3 * nw < Q.nq) {  // all four columns in LDS
+      for (int64_t r = lane; r < m; r += 64) {
+        const double wr = w_s[r];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int c = c0 + u * nw;
+          if (c <= j) t[u] += Q.l[(int64_t)c * m + r] * wr;
+        }
+      }
+    } else {
+      for (int64_t r0 = 0; r0 < m; r0 += 128) {
+        double x[2][4], wr[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int64_t r = r0 + lane + 64 * h;
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int c = c0 + u * nw;
+            x[h][u] = (c <= j && r < m) ? (c < Q.nq ? Q.l[(int64_t)c * m + r] : Qg[(int64_t)c * m + r]) : 0.0;
+          }
+        }
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int64_t r = r0 + lane + 64 * h;
+          wr[h] = (r < m) ? w_s[r] : 0.0;
+        }
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+          for (int u = 0; u < 4; ++u) t[u] += x[h][u] * wr[h];
+      }
+    }
+    const double sum = wave_sum4(t, lane);
+    const int u = lane >> 4;
+    if ((lane & 15) == 0 && c0 + u * nw <= j) hs[c0 + u * nw] = sum;
+  }
+  __syncthreads();
+  const int groups = kFusedThreads / rows_pad;
+  const int r = tid % rows_pad, grp = tid / rows_pad;
+  part[tid] = (r < m) ? fused_qrowdot(Q, r, grp, j + 1, groups, hs) : 0.0;
+  __syncthreads();
+  if (tid < m) {
+    double u = 0.0;
+    for (int g = 0; g < groups; ++g) u += part[g * rows_pad + tid];
+    w_s[tid] -= u;
+  }
+  const double hj = hs[j];
+  __syncthreads();
+  return hj;
+}
+
+__device__ double fused_block_sum(double v, double* red) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  v = wave_sum(v);
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  double t = 0.0;
+  for (int i = 0; i < kFusedThreads / 64; ++i) t += red[i];
+  __syncthreads();
+  return t;
+}
+
+__global__ __launch_bounds__(kFusedThreads) void lanczos_fused_kernel(const LzNode* __restrict__ nodes,
+                                                                       const int* __restrict__ act, int j0, int j1,
+                                                                       double rel_tol) {
+  const LzNode n = nodes[act[blockIdx.z]];
+  const int64_t m = n.m;
+  const int k = (int)min(m, (int64_t)kMaxSteps);
+  const int jend = min(j1, k);
+  extern __shared__ double qcache[];
+  __shared__ double q_s[kFusedMaxM], w_s[kFusedMaxM];
+  __shared__ double hs[kMaxSteps + 1];
+  __shared__ double part[kFusedThreads];
+  __shared__ double red[kFusedThreads / 64];
+  const int tid = threadIdx.x;
+  const int rows_pad = m <= 64 ? 64 : m <= 128 ? 128 : m <= 256 ? 256 : 512;
+  if (j0 >= jend) return;
+  FusedQ Q{n.Q, qcache, m, (int)min((int64_t)(k + 1), (int64_t)kFusedQCache / m)};
+  // the cached columns written by earlier launches
+  const int64_t have = (int64_t)min(j0 + 1, Q.nq) * m;
+  for (int64_t e = tid; e < have; e += kFusedThreads) qcache[e] = n.Q[e];
+  for (int64_t r = tid; r < m; r += kFusedThreads) q_s[r] = n.Q[(int64_t)j0 * m + r];
+  __syncthreads();
+  for (int j = j0; j < jend; ++j) {
+    // w = G q_j = sum_c G[:, c] q_j[c] (G symmetric): the rows split over
+    // groups of threads, each group summing every groups-th column
+    {
+      const int groups = kFusedThreads / rows_pad;
+      const int r = tid % rows_pad, grp = tid / rows_pad;
+      part[tid] = (r < m) ? fused_rowdot(n.G, n.ldg, r, grp, (int)m, groups, q_s) : 0.0;
+      __syncthreads();
+      if (tid < m) {
+        double u = 0.0;
+        for (int g = 0; g < groups; ++g) u += part[g * rows_pad + tid];
+        w_s[tid] = u;
+      }
+      __syncthreads();
+    }
+    double wv = (tid < m) ? w_s[tid] : 0.0;
+    const double gq2 = fused_block_sum(wv * wv, red);  // ||G q_j||^2
+    double alpha = 0.0;
+    alpha += fused_cgs_pass(Q, j, w_s, hs, part, rows_pad);
+    alpha += fused_cgs_pass(Q, j, w_s, hs, part, rows_pad);
+    wv = (tid < m) ? w_s[tid] : 0.0;
+    const double beta = sqrt(fused_block_sum(wv * wv, red));
+    double* q_next = n.Q + (int64_t)(j + 1) * m;
+    double* l_next = (j + 1 < Q.nq) ? qcache + (int64_t)(j + 1) * m : nullptr;
+    double beta_out = beta;
+    double inv;
+    if (beta <= rel_tol * sqrt(gq2)) {
+      // breakdown: a fresh pseudo-random vector orthogonalised twice
+      for (int64_t r = tid; r < m; r += kFusedThreads)
+        w_s[r] = hash_unit((uint64_t)r * 7919u + 104729u * (uint64_t)(j + 1) + 17u);
+      __syncthreads();
+      fused_cgs_pass(Q, j, w_s, hs, part, rows_pad);
+      fused_cgs_pass(Q, j, w_s, hs, part, rows_pad);
+      wv = (tid < m) ? w_s[tid] : 0.0;
+      const double nrm = sqrt(fused_block_sum(wv * wv, red));
+      inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
+      beta_out = 0.0;
+    } else {
+      inv = beta > 0.0 ? 1.0 / beta : 0.0;
+    }
+    for (int64_t r = tid; r < m; r += kFusedThreads) {
+      const double x = w_s[r] * inv;
+      q_next[r] = x;
+      q_s[r] = x;
+      if (l_next) l_next[r] = x;
+    }
+    if (tid == 0) {
+      n.alpha[j] = alpha;
+      n.beta[j] = beta_out;
+    }
+    __syncthreads();
+  }
 }
 
 // out[2 a] = beta_j, out[2 a + 1] = beta_0 of active matrix a
@@ -595,10 +822,17 @@ hapod_status wide_eigh_batch(std::vector<WideJob>& jobs, double u_p, wide_alloc_
   std::vector<int> steps(kmax), act;
   std::vector<char> stopped(nn, 0);
   std::vector<double> prev_check(nn, 0.0);
-  for (int i = 0; i < nn; ++i) {
-    stopped[i] = (kmax[i] == jobs[i].m);
-    if (jobs[i].m > 0) act.push_back(i);
-  }
+  // small matrices first: they run in the fused kernel, the list's prefix
+  int n_small = 0;
+  for (auto& jb : jobs) n_small += (jb.m > 0 && jb.m <= kFusedMaxM);
+  auto fused_node = [&](int i) {
+    return jobs[i].m <= kFusedMaxM && (jobs[i].m <= kFusedAloneMaxM || n_small >= kFusedBatchMin);
+  };
+  for (int i = 0; i < nn; ++i) stopped[i] = (kmax[i] == jobs[i].m);
+  for (int i = 0; i < nn; ++i)
+    if (jobs[i].m > 0 && fused_node(i)) act.push_back(i);
+  for (int i = 0; i < nn; ++i)
+    if (jobs[i].m > 0 && !fused_node(i)) act.push_back(i);
   const char* venv = std::getenv("HAPOD_VERBOSE");
   const bool verbose = venv && venv[0] == '1';
   bool act_dirty = true;
@@ -619,21 +853,40 @@ hapod_status wide_eigh_batch(std::vector<WideJob>& jobs, double u_p, wide_alloc_
       act_dirty = false;
     }
     const unsigned na = (unsigned)act.size();
+    unsigned nf = 0;
+    while (nf < na && fused_node(act[nf])) ++nf;
+    // small matrices: one fused launch per period of kCheckEvery steps (each
+    // stops at its own k)
+    if (nf > 0 && j % kCheckEvery == 0) {
+      static bool attr_set = false;
+      if (!attr_set) {
+        HAPOD_HIP(hipFuncSetAttribute((const void*)lanczos_fused_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      (int)(kFusedQCache * sizeof(double))));
+        attr_set = true;
+      }
+      hipLaunchKernelGGL(lanczos_fused_kernel, dim3(1, 1, nf), dim3(kFusedThreads), kFusedQCache * sizeof(double),
+                         stream, dn, dact, j, j + kCheckEvery, kBreakdownTol);
+    }
+    const unsigned nr = na - nf;
+    const int* dact_r = dact + nf;
     int64_t am = 0;
     int anrc = 1;
-    for (int i : act) {
-      am = std::max(am, jobs[i].m);
-      anrc = std::max(anrc, nrc[i]);
+    for (unsigned a = nf; a < na; ++a) {
+      am = std::max(am, jobs[act[a]].m);
+      anrc = std::max(anrc, nrc[act[a]]);
     }
-    hipLaunchKernelGGL(matvec_kernel, dim3((unsigned)((am + 3) / 4), 1, na), dim3(256), 0, stream, dn, dact, j);
-    for (int pass = 0; pass < 2; ++pass) {
-      hipLaunchKernelGGL(proj_partial_kernel, dim3((unsigned)((j + kProjCols) / kProjCols), (unsigned)anrc, na),
-                         dim3(256), 0, stream, dn, dact, j, pass == 0 ? 1 : 0);
-      hipLaunchKernelGGL(update_kernel, dim3((unsigned)((am + 63) / 64), 1, na), dim3(256), 0, stream, dn, dact, j);
+    if (nr > 0) {
+      hipLaunchKernelGGL(matvec_kernel, dim3((unsigned)((am + 3) / 4), 1, nr), dim3(256), 0, stream, dn, dact_r, j);
+      for (int pass = 0; pass < 2; ++pass) {
+        hipLaunchKernelGGL(proj_partial_kernel, dim3((unsigned)((j + kProjCols) / kProjCols), (unsigned)anrc, nr),
+                           dim3(256), 0, stream, dn, dact_r, j, pass == 0 ? 1 : 0);
+        hipLaunchKernelGGL(update_kernel, dim3((unsigned)((am + 63) / 64), 1, nr), dim3(256), 0, stream, dn, dact_r,
+                           j);
+      }
+      hipLaunchKernelGGL(finish_kernel, dim3(1, 1, nr), dim3(1024), 0, stream, dn, dact_r, j);
+      // restart the matrices whose step broke down
+      hipLaunchKernelGGL(breakdown_kernel, dim3(1, 1, nr), dim3(1024), 0, stream, dn, dact_r, j, kBreakdownTol);
     }
-    hipLaunchKernelGGL(finish_kernel, dim3(1, 1, na), dim3(1024), 0, stream, dn, dact, j);
-    // restart the matrices whose step broke down
-    hipLaunchKernelGGL(breakdown_kernel, dim3(1, 1, na), dim3(1024), 0, stream, dn, dact, j, kBreakdownTol);
     // Stop once the Krylov space has taken in everything above the rounding
     // level of G: the residual norms beta_j then stop falling (they sit at
     // that level).  Test every kCheckEvery steps: beta_j at or below
