@@ -301,10 +301,10 @@ __global__ __launch_bounds__(256, 2) void lift_staged_kernel(const LiftNode* __r
     for (int a = 0; a < NB; ++a)
 #pragma unroll
       for (int b = 0; b < NB; ++b) acc[a][b] = Acc{0, 0, 0, 0};
-    i4 ps[NLS], pb[NLB];
+    i4 ps0[NLS], pb0[NLB], ps1[NLS], pb1[NLB];  // two stages in flight
     // chunk q = i * 256 + t: S column q / CPC, rows of part q % CPC; B row
     // q / CPR, columns of part q % CPR
-    auto gload = [&](int st) {
+    auto gload = [&](int st, i4 (&ps)[NLS], i4 (&pb)[NLB]) {
       const int kfirst = st * KS;
 #pragma unroll
       for (int i = 0; i < NLS; ++i) {
@@ -342,7 +342,7 @@ __global__ __launch_bounds__(256, 2) void lift_staged_kernel(const LiftNode* __r
         }
       }
     };
-    auto lstore = [&](int buf) {
+    auto lstore = [&](int buf, const i4 (&ps)[NLS], const i4 (&pb)[NLB]) {
 #pragma unroll
       for (int i = 0; i < NLS; ++i) {
         const int q = i * 256 + t;
@@ -375,21 +375,55 @@ __global__ __launch_bounds__(256, 2) void lift_staged_kernel(const LiftNode* __r
           }
       }
     };
+    if constexpr (!NARROW) {
+      // one stage in flight (a second set of registers would spill here)
+      if (stages > 0) {
+        ensure_table(0);
+        gload(0, ps0, pb0);
+        lstore(0, ps0, pb0);
+      }
+      __syncthreads();
+      for (int st = 0; st < stages; ++st) {
+        const bool more = st + 1 < stages;
+        if (more) {
+          ensure_table((st + 1) * KS);
+          gload(st + 1, ps0, pb0);
+        }
+        if (active) compute(st & 1);
+        if (more) lstore((st + 1) & 1, ps0, pb0);
+        __syncthreads();
+      }
+    } else {
+    // stage s sits in LDS buffer s & 1; the loads of stage s + 2 are issued
+    // before stage s is computed, so two stages are in flight (the loop is
+    // unrolled by two to keep the register sets static)
     if (stages > 0) {
       ensure_table(0);
-      gload(0);
-      lstore(0);
+      gload(0, ps0, pb0);
+      lstore(0, ps0, pb0);
+    }
+    if (stages > 1) {
+      ensure_table(KS);
+      gload(1, ps1, pb1);
     }
     __syncthreads();
-    for (int st = 0; st < stages; ++st) {
-      const bool more = st + 1 < stages;
-      if (more) {
-        ensure_table((st + 1) * KS);
-        gload(st + 1);
+    for (int st = 0; st < stages; st += 2) {
+      if (st + 2 < stages) {
+        ensure_table((st + 2) * KS);
+        gload(st + 2, ps0, pb0);
       }
-      if (active) compute(st & 1);
-      if (more) lstore((st + 1) & 1);
+      if (active) compute(0);
+      if (st + 1 < stages) lstore(1, ps1, pb1);
       __syncthreads();
+      if (st + 1 >= stages) break;
+      if (st + 3 < stages) {
+        ensure_table((st + 3) * KS);
+        gload(st + 3, ps1, pb1);
+      }
+      if (active) compute(1);
+      if (st + 2 < stages) lstore(0, ps0, pb0);
+      __syncthreads();
+    }
     }
     if (!active) continue;
     Elem* out = reinterpret_cast<Elem*>(nd.out);
