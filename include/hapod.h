@@ -63,7 +63,7 @@ typedef enum {
 typedef enum {
   HAPOD_FP64 = 0,    /* Gram and lift on FP64 MFMA, double storage                         */
   HAPOD_FP32 = 1,    /* Gram and lift on FP32 MFMA, FP32 accumulation, float storage       */
-  HAPOD_BF16X3 = 2   /* float storage; Gram of nodes of 256 or more columns as split-BF16,
+  HAPOD_BF16X3 = 2   /* float storage; Gram of nodes of more than 64 columns as split-BF16,
                         three products hi*hi + hi*lo + lo*hi on BF16 MFMA with FP32
                         accumulation; narrower Grams and all lifts on FP32 MFMA        */
 } hapod_precision;
@@ -229,7 +229,8 @@ typedef int32_t (*hapod_leaf_fn)(void* user, int32_t leaf, const void** ptr,
  * mem_cap_bytes when set; they are returned to the device when an
  * allocation fails, and by hapod_destroy.
  * Environment: HAPOD_TWIN_BUDGET (bytes) caps the arena that holds the
- * split-BF16 twins of a level (by default half of the free device memory);
+ * pre-split twins of a level's split-BF16 nodes whose tuned Gram tile is
+ * narrower than 128 columns (by default half of the free device memory);
  * HAPOD_GRAM_ITEMS sets the work items a Gram launch aims for (default
  * 8192; row chunks are added until the tile pairs reach it);
  * HAPOD_VERBOSE=1 prints the Krylov eigensolver's progress and the device

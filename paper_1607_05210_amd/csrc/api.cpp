@@ -35,7 +35,15 @@ int elem_bytes(hapod_precision p) { return p == HAPOD_FP64 ? 8 : 4; }
 int compute_mode(hapod_precision p) { return p == HAPOD_FP64 ? 0 : (p == HAPOD_FP32 ? 1 : 2); }
 
 constexpr size_t kAlign = 256;
-constexpr int64_t kPresplitMinCols = 256;
+// the split-BF16 form computes the Gram of nodes wider than 64 columns with
+// split-BF16 products (128-column tiles that split FP32 values into hi / lo
+// as they are staged through LDS); narrower nodes, whose tiles are too small
+// to pay for the splitting, use FP32 MFMA
+constexpr int64_t kBf16MinCols = 65;
+// widest split-BF16 node whose 128-column tiles split while staging (two
+// column blocks); wider nodes read a pre-split twin (measured on the 2^20 x
+// 8192 root: 319 ms from the twin, 638 ms splitting in every tile)
+constexpr int64_t kStageSplitMaxCols = 256;
 constexpr int kSuperI = 4, kSuperJ = 8;  // Gram tile pairs per super-tile (32 = CUs of an XCD)
 
 // plain column-major n x m (leading dimension ld)
@@ -423,7 +431,7 @@ hapod_status run_pod_batch(hapod_precision prec, std::vector<PodJob>& jobs, int 
   int sum_pairs = 0;
   // the Gram compute mode of a node: split-BF16 nodes below the pre-split
   // width run on FP32 MFMA
-  auto node_compute = [&](int64_t m) { return (compute == 2 && m < kPresplitMinCols) ? 1 : compute; };
+  auto node_compute = [&](int64_t m) { return (compute == 2 && m < kBf16MinCols) ? 1 : compute; };
   if (autotune)
     for (auto& j : jobs) HAPOD_TRY(autotune_tile(node_compute(j.m), eb, j.n, j.m, pool, stream));
   for (auto& j : jobs) {
@@ -500,7 +508,12 @@ hapod_status run_pod_batch(hapod_precision prec, std::vector<PodJob>& jobs, int 
     L.crows = take(sizeof(int64_t) * std::max<int64_t>(m, 1));
     // split-BF16: nodes with several column tiles get a split twin of their
     // input once, instead of splitting every element in each tile that reads it
-    L.presplit = (compute == 2 && m >= kPresplitMinCols && j.n > 0 && tiled_bytes(j.n, m, 4) <= twin_budget);
+    // a pre-split twin (every value split once, in a pass of its own) pays
+    // when each column block is read by several tiles: above 256 columns, or
+    // with tiles narrower than 128 (chosen by the tile tuner); below, the
+    // 128-column tiles split the FP32 values as they stage them
+    L.presplit = (compute == 2 && m >= kBf16MinCols && (L.tile != 128 || m > kStageSplitMaxCols) && j.n > 0 &&
+                  tiled_bytes(j.n, m, 4) <= twin_budget);
     if (L.presplit) {
       const size_t tb = align_up(tiled_bytes(j.n, m, 4));
       if (group_fill + tb > twin_budget) {
@@ -602,7 +615,7 @@ hapod_status run_pod_batch(hapod_precision prec, std::vector<PodJob>& jobs, int 
     // FP32 MFMA: splitting in registers costs more VALU time than the three
     // BF16 products save at these widths (launch slots of their own)
     const bool f32 = (node_compute(m) != compute);
-    const bool staged = L.presplit && !f32 && L.tile == 128;
+    const bool staged = !f32 && compute == 2 && L.tile == 128;
     std::vector<GramItem>& gi =
         items_by_tile[twin_group[i]][staged ? 16 : (f32 ? 8 : 0) + 2 * tile_slot(L.tile) + (vec ? 1 : 0)];
     // Item order.  The workgroups an XCD runs at once take consecutive items
@@ -1562,7 +1575,8 @@ hapod_status gram_impl(int compute, int eb, int64_t n, int64_t m, const void* S,
   if (slots > 1) HAPOD_TRY(pool.alloc(sizeof(double) * pairs * slots * tile * tile, &dpart));
   // split-BF16 with several column tiles: read a split twin (as the level batch does)
   void* dsplit = nullptr;
-  const bool presplit = (compute == 2 && m >= kPresplitMinCols && n > 0);
+  const int gc = (compute == 2 && m < kBf16MinCols) ? 1 : compute;
+  const bool presplit = (gc == 2 && (tile != 128 || m > kStageSplitMaxCols) && n > 0);
   std::vector<const void*> cols_g = cols;
   std::vector<int64_t> rbs_g;
   if (presplit) {
@@ -1632,8 +1646,8 @@ hapod_status gram_impl(int compute, int eb, int64_t n, int64_t m, const void* S,
       }
       break;
     }
-    const int vec_mode = (presplit && tile == 128) ? 2 : (vec_ok ? 1 : 0);
-    const GramLaunch gl{tile, vec_mode, 0, (int32_t)items.size(), (compute == 2 && m < kPresplitMinCols) ? 1 : -1};
+    const int vec_mode = (gc == 2 && tile == 128) ? 2 : (vec_ok ? 1 : 0);
+    const GramLaunch gl{tile, vec_mode, 0, (int32_t)items.size(), gc != compute ? gc : -1};
     st = launch_gram(compute, (const GramNode*)(db + o_g), (const GramItem*)(db + o_i), &gl, 1,
                      (const int32_t*)(db + o_rp), (const int32_t*)(db + o_rn), (int)rp.size(), tile, stream);
   } while (0);

@@ -161,22 +161,26 @@ __global__ __launch_bounds__(256) void gram_tile_kernel(const GramNode* __restri
   const int64_t nwb = (bstart < nblk) ? (nblk - bstart + BSTEP - 1) / BSTEP : 0;
   if constexpr (kStaged) {
     {
-      // Pre-split columns, 128 x 128 tile: the workgroup stages 32 rows of
-      // its 256 columns (128 when ti = tj) through LDS, double-buffered, so
-      // every value is fetched from global memory once per workgroup
-      // instead of once per wavefront that reads it (two of four); the next
-      // stage's loads are in flight while the current one runs on the
-      // matrix cores.  Thread t always loads part t % 8 of a column (hi
-      // runs 0..3, lo runs 4..7 of the 32-row step) for columns
-      // 32 i + t / 8, i = 0..7.  Same products in the same order as the
-      // register path below, so the sums are identical.
+      // Split-BF16, 128 x 128 tile: the workgroup stages 32 rows of its 256
+      // columns (128 when ti = tj) through LDS as hi and lo bfloat16 runs,
+      // double-buffered, so every value is fetched from global memory once
+      // per workgroup instead of once per wavefront that reads it (two of
+      // four); the next stage's loads are in flight while the current one
+      // runs on the matrix cores.  Thread t always loads part t % 8 of a
+      // column for columns 32 i + t / 8, i = 0..7: from a pre-split twin,
+      // hi runs 0..3 or lo runs 4..7 of the 32-row step; from the FP32
+      // columns, rows 4 part .. 4 part + 3, split into hi and lo as they go
+      // to LDS (each value split once per workgroup; rows past a column's
+      // own read as zero).  Same hi/lo pairs and products in the same order
+      // as the register path below, so the sums are identical.
       constexpr int kColB = 8 * 16 + 16;  // LDS bytes per column and stage (padded)
       __shared__ __attribute__((aligned(16))) char stage[2][256 * kColB];
       const int t = threadIdx.x, part = t & 7;
       const int ncl = diag ? 128 : 256;  // columns staged
       const int nld = ncl / 32;          // loads per thread and stage
+      const bool twin = nd.split != 0;
       const float* cp[8];
-      int64_t cs[8];
+      int64_t cs[8], cr[8];
 #pragma unroll
       for (int i = 0; i < 8; ++i) {
         const int cl = 32 * i + (t >> 3);
@@ -184,21 +188,60 @@ __global__ __launch_bounds__(256) void gram_tile_kernel(const GramNode* __restri
         const int c = min(base, nd.m - 1);  // columns past m alias the last one
         cp[i] = reinterpret_cast<const float*>(nd.cols[c]);
         cs[i] = nd.rbs[c];
+        cr[i] = nd.crows[c];
       }
       const int poff = (part < 4) ? part : 16 + (part - 4);  // bf8 offset in the step
       const int64_t S = nblk * NBT;  // 32-row steps of the chunk
-      bf8 pre[8];
+      typedef __attribute__((ext_vector_type(4))) int i4;
+      i4 pre[8];
       auto gload = [&](int64_t st) {
         const int64_t blk = blk0 + st / NBT;
         const int bt = (int)(st % NBT);
+        if (twin) {
 #pragma unroll
-        for (int i = 0; i < 8; ++i)
-          if (i < nld) pre[i] = ((gptr<bf8>)as_global(cp[i] + blk * cs[i]))[4 * bt + poff];
+          for (int i = 0; i < 8; ++i)
+            if (i < nld) pre[i] = ((gptr<i4>)as_global(cp[i] + blk * cs[i]))[4 * bt + poff];
+        } else {
+          const int roff = 32 * bt + 4 * part;  // row in the block
+          const int64_t row = (blk << 7) + roff;
+#pragma unroll
+          for (int i = 0; i < 8; ++i) {
+            if (i >= nld) continue;
+            const float* p = cp[i] + blk * cs[i] + roff;
+            const int64_t avail = cr[i] - row;
+            if (avail >= 4 && (((uintptr_t)p & 15u) == 0)) {
+              pre[i] = *(gptr<i4>)as_global(reinterpret_cast<const i4*>(p));
+            } else {
+              float x[4];
+#pragma unroll
+              for (int e = 0; e < 4; ++e) x[e] = (e < avail) ? p[e] : 0.f;
+              pre[i] = *reinterpret_cast<const i4*>(x);
+            }
+          }
+        }
       };
       auto lstore = [&](int buf) {
+        if (twin) {
 #pragma unroll
-        for (int i = 0; i < 8; ++i)
-          if (i < nld) *(bf8*)(stage[buf] + (32 * i + (t >> 3)) * kColB + part * 16) = pre[i];
+          for (int i = 0; i < 8; ++i)
+            if (i < nld) *(i4*)(stage[buf] + (32 * i + (t >> 3)) * kColB + part * 16) = pre[i];
+        } else {
+#pragma unroll
+          for (int i = 0; i < 8; ++i) {
+            if (i >= nld) continue;
+            const float* x = reinterpret_cast<const float*>(&pre[i]);
+            uint16_t h[4], l[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+              h[e] = bf16_bits_rne(x[e]);
+              l[e] = bf16_bits_rne(x[e] - bf16_bits_to_float(h[e]));
+            }
+            char* q = stage[buf] + (32 * i + (t >> 3)) * kColB + part * 8;
+            typedef __attribute__((ext_vector_type(2))) int i2;
+            *(i2*)q = i2{(int)(h[0] | ((uint32_t)h[1] << 16)), (int)(h[2] | ((uint32_t)h[3] << 16))};
+            *(i2*)(q + 64) = i2{(int)(l[0] | ((uint32_t)l[1] << 16)), (int)(l[2] | ((uint32_t)l[3] << 16))};
+          }
+        }
       };
       const int la = wi * 64, lb = diag ? wj * 64 : 128 + wj * 64;  // staged column bases
       auto compute = [&](int buf) {
