@@ -76,11 +76,11 @@ struct LzNode {
   double* alpha;   // k
   double* beta;    // k + 1
   double* theta;   // k Ritz values (descending)
-  double* e2;      // k x ceil(k / 4) bisection scratch
+  double* e2;      // unused
   double* Z;       // k x k eigenvectors of T, Z[r * kk + i]
   double* last;    // k: last components of the z_i
-  double* isc;     // 5 k^2 inverse-iteration scratch
-  int* ipiv;       // k^2
+  double* isc;     // unused
+  int* ipiv;       // unused
   double* tr;      // trace(G)
   double* wn;      // nrc partial sums of ||G q_j||^2
   double* V;       // outputs
@@ -89,7 +89,10 @@ struct LzNode {
   int32_t nrc;
   int32_t kk;      // steps taken (tridiagonal phase)
   int32_t b;       // eigenpairs returned
-  int32_t pad;
+  int32_t coop_p;  // workgroups of the cooperative step kernel (0: not used)
+  double* xbuf;    // cooperative kernel: three exchange buffers of xlen doubles
+  unsigned* bar;   // cooperative kernel: barrier counter (zeroed per launch)
+  int64_t xlen;
 };
 
 // q = random, unnormalised (normalised by the finish kernel)
@@ -476,6 +479,213 @@ __global__ __launch_bounds__(kFusedThreads) void lanczos_fused_kernel(const LzNo
   }
 }
 
+// Mid-size matrices alone (or a few of them): the steps of the fused kernel
+// spread over coop_p workgroups, each holding in LDS its slice of rows of G
+// (as columns: G is symmetric) and of the Lanczos vectors.  Per step three
+// exchanges through global memory, each closed by a barrier among the
+// matrix's workgroups: the projection partials of the two Gram-Schmidt
+// passes (with ||G q_j||^2 in the first) and the new w with the partial
+// norms.  Every workgroup adds the partials in the same fixed order, so all
+// take the same branches.  A barrier waits a bounded time; if it runs out
+// (it cannot when the launch is cooperative, i.e. every workgroup resident)
+// the error flag is set and every workgroup leaves.
+constexpr int kCoopMaxM = 512;
+constexpr int kCoopThreads = 256;
+constexpr long kCoopSpinLimit = 1L << 22;
+
+__host__ __device__ __forceinline__ int coop_pick(int64_t m) { return m <= 320 ? 16 : 32; }
+__device__ __host__ __forceinline__ size_t coop_lds_doubles(int64_t m, int P) {
+  const int64_t k = m < kMaxSteps ? m : kMaxSteps;
+  const int64_t R = (m + P - 1) / P;
+  return (size_t)(R * m + R * (k + 1) + m + (k + 1) + R);
+}
+
+// all workgroups of one matrix meet; false when the wait ran out (or another
+// workgroup's did)
+__device__ bool coop_barrier(unsigned* bar, unsigned target, int* err, int* flag) {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    long spins = 0;
+    int bad = 0;
+    while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 || ++spins > kCoopSpinLimit) {
+        bad = 1;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+    if (bad) __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    *flag = bad;
+  }
+  __syncthreads();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  return *flag == 0;
+}
+
+__global__ __launch_bounds__(kCoopThreads) void lanczos_coop_kernel(const LzNode* __restrict__ nodes,
+                                                                     const int* __restrict__ act, int j0, int j1,
+                                                                     double rel_tol, int* err) {
+  const LzNode n = nodes[act[blockIdx.z]];
+  const int P = n.coop_p;
+  const int p = blockIdx.x;
+  if (p >= P) return;  // not one of this matrix's workgroups (no barrier met)
+  const int64_t m = n.m;
+  const int k = (int)min(m, (int64_t)kMaxSteps);
+  const int jend = min(j1, k);
+  if (j0 >= jend) return;  // the same for all of the matrix's workgroups
+  const int R = (int)((m + P - 1) / P);
+  const int r0 = p * R;
+  const int nr = (int)max((int64_t)0, min(m, (int64_t)r0 + R) - r0);
+  const int kq = k + 1;
+  const int K2 = k + 2;  // stride of one workgroup's partials
+  extern __shared__ double lds[];
+  double* Gs = lds;                       // R x m: row rr = column r0 + rr of G
+  double* Qs = Gs + (size_t)R * m;        // R x kq: rows r0.. of the Lanczos vectors
+  double* qf = Qs + (size_t)R * kq;       // m: q_j
+  double* hh = qf + m;                    // kq: summed projection coefficients
+  double* wl = hh + kq;                   // R: this slice of w
+  __shared__ double sc[2];
+  __shared__ int flag;
+  __shared__ double part[kCoopThreads];
+  __shared__ double rsum[kCoopThreads / 8];
+  const int t = threadIdx.x;
+  // rsum[rr] = sum over c < len of A[rr * lda + c] v[c], rr < nr: thread
+  // rr + nr g takes every ng-th c from g, the ng partial sums are added in a
+  // fixed order (no cross-lane shuffles)
+  const int ng = kCoopThreads / max(nr, 1);
+  auto rowdot = [&](const double* A, int lda, int len, const double* v) {
+    const int rr = t % max(nr, 1), g = t / max(nr, 1);
+    double u = 0.0;
+    if (g < ng && rr < nr)
+      for (int c = g; c < len; c += ng) u += A[(size_t)rr * lda + c] * v[c];
+    part[t] = u;
+    __syncthreads();
+    if (t < nr) {
+      double w = 0.0;
+      for (int q = 0; q < ng; ++q) w += part[q * nr + t];
+      rsum[t] = w;
+    }
+    __syncthreads();
+  };
+  unsigned nbar = 0;
+  int ex = 0;
+  auto xb = [&](int e) { return n.xbuf + (size_t)(e % 3) * n.xlen; };
+
+  for (int rr = 0; rr < nr; ++rr)
+    for (int64_t c = t; c < m; c += kCoopThreads) Gs[(size_t)rr * m + c] = n.G[(int64_t)(r0 + rr) * n.ldg + c];
+  for (int e = t; e < nr * (j0 + 1); e += kCoopThreads) {
+    const int rr = e % nr, c = e / nr;
+    Qs[(size_t)rr * kq + c] = n.Q[(int64_t)c * m + r0 + rr];
+  }
+  for (int64_t c = t; c < m; c += kCoopThreads) qf[c] = n.Q[(int64_t)j0 * m + c];
+  __syncthreads();
+
+  // one classical Gram-Schmidt pass of wl against q_0..q_j; returns h_j.
+  // extra (>= 0) travels with the partials; its sum lands in sc[0]
+  auto cgs = [&](int j, double extra, bool with_extra, bool& ok) -> double {
+    double* X = xb(ex++);
+    for (int c = t; c <= j; c += kCoopThreads) {
+      double hp = 0.0;
+      for (int rr = 0; rr < nr; ++rr) hp += Qs[(size_t)rr * kq + c] * wl[rr];
+      X[(size_t)p * K2 + c] = hp;
+    }
+    if (with_extra && t == 0) X[(size_t)p * K2 + k + 1] = extra;
+    ok = coop_barrier(n.bar, (unsigned)P * ++nbar, err, &flag);
+    if (!ok) return 0.0;
+    const gptr<double> Xg = as_global(X);
+    for (int c = t; c <= j; c += kCoopThreads) {
+      double hs = 0.0;
+#pragma unroll 8
+      for (int q = 0; q < P; ++q) hs += Xg[(size_t)q * K2 + c];
+      hh[c] = hs;
+    }
+    if (with_extra && t == 0) {
+      double e2 = 0.0;
+#pragma unroll 8
+      for (int q = 0; q < P; ++q) e2 += Xg[(size_t)q * K2 + k + 1];
+      sc[0] = e2;
+    }
+    __syncthreads();
+    rowdot(Qs, kq, j + 1, hh);
+    if (t < nr) wl[t] -= rsum[t];
+    const double hj = hh[j];
+    __syncthreads();
+    return hj;
+  };
+  // w goes out whole with the slices' squared norms; returns ||w||, the
+  // buffer holding w in *Xw
+  auto share_w = [&](double** Xw, bool& ok) -> double {
+    double* X = xb(ex++);
+    for (int rr = t; rr < nr; rr += kCoopThreads) X[r0 + rr] = wl[rr];
+    if (t == 0) {
+      double s2 = 0.0;
+      for (int rr = 0; rr < nr; ++rr) s2 += wl[rr] * wl[rr];
+      X[m + p] = s2;
+    }
+    ok = coop_barrier(n.bar, (unsigned)P * ++nbar, err, &flag);
+    if (!ok) return 0.0;
+    const gptr<double> Xg = as_global(X);
+    double tot = 0.0;
+#pragma unroll 8
+    for (int q = 0; q < P; ++q) tot += Xg[m + q];
+    *Xw = X;
+    return sqrt(tot);
+  };
+
+  for (int j = j0; j < jend; ++j) {
+    // w = G q_j on this slice of rows
+    rowdot(Gs, (int)m, (int)m, qf);
+    if (t < nr) wl[t] = rsum[t];
+    __syncthreads();
+    double gq = 0.0;
+    if (t == 0)
+      for (int rr = 0; rr < nr; ++rr) gq += wl[rr] * wl[rr];
+    bool ok = true;
+    double alpha = cgs(j, gq, true, ok);
+    if (!ok) return;
+    const double gq2 = sc[0];
+    alpha += cgs(j, 0.0, false, ok);
+    if (!ok) return;
+    double* Xw = nullptr;
+    const double beta = share_w(&Xw, ok);
+    if (!ok) return;
+    double beta_out = beta, inv;
+    if (beta <= rel_tol * sqrt(gq2)) {
+      // breakdown: a fresh pseudo-random vector orthogonalised twice
+      for (int rr = t; rr < nr; rr += kCoopThreads)
+        wl[rr] = hash_unit((uint64_t)(r0 + rr) * 7919u + 104729u * (uint64_t)(j + 1) + 17u);
+      __syncthreads();
+      cgs(j, 0.0, false, ok);
+      if (!ok) return;
+      cgs(j, 0.0, false, ok);
+      if (!ok) return;
+      const double nrm = share_w(&Xw, ok);
+      if (!ok) return;
+      inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
+      beta_out = 0.0;
+    } else {
+      inv = beta > 0.0 ? 1.0 / beta : 0.0;
+    }
+    {
+      const gptr<double> Xg = as_global(Xw);
+      for (int64_t c = t; c < m; c += kCoopThreads) qf[c] = Xg[c] * inv;
+    }
+    __syncthreads();
+    for (int rr = t; rr < nr; rr += kCoopThreads) {
+      const double v = qf[r0 + rr];
+      Qs[(size_t)rr * kq + j + 1] = v;
+      n.Q[(int64_t)(j + 1) * m + r0 + rr] = v;
+    }
+    if (p == 0 && t == 0) {
+      n.alpha[j] = alpha;
+      n.beta[j] = beta_out;
+    }
+    __syncthreads();
+  }
+}
+
 // out[2 a] = beta_j, out[2 a + 1] = beta_0 of active matrix a
 __global__ void gather_beta_kernel(const LzNode* __restrict__ nodes, const int* __restrict__ act, int na, int j,
                                    double* __restrict__ out) {
@@ -523,11 +733,19 @@ __global__ __launch_bounds__(256) void bisect_kernel(const LzNode* __restrict__ 
   const LzNode n = nodes[blockIdx.z];
   const int k = n.kk;
   if (blockIdx.x * 4 >= k) return;  // whole workgroup
-  const double* d = n.alpha;
-  const double* e = n.beta;
+  // T (diagonal, off-diagonal and its squares) staged in LDS: every Sturm
+  // count reads all of it
+  extern __shared__ double bs[];
+  double* d = bs;
+  double* e = bs + k;
+  double* e2buf = bs + 2 * k;
   double* theta = n.theta;
-  double* e2buf = n.e2 + (int64_t)blockIdx.x * k;
-  for (int j = threadIdx.x; j < k - 1; j += blockDim.x) e2buf[j] = e[j] * e[j];
+  for (int j = threadIdx.x; j < k; j += blockDim.x) {
+    d[j] = n.alpha[j];
+    const double ej = (j < k - 1) ? n.beta[j] : 0.0;
+    e[j] = ej;
+    e2buf[j] = ej * ej;
+  }
   __syncthreads();
   const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
@@ -565,27 +783,28 @@ __global__ __launch_bounds__(256) void bisect_kernel(const LzNode* __restrict__ 
 // inverse iteration: z_i solves (T - theta_i) z = z_prev (pivoted LU), three
 // times from a pseudo-random start; written as column i of Z (row-major,
 // Z[r * ldz + i]).  Scratch: 5 k doubles + k ints per thread.
-__global__ void inviter_kernel(const LzNode* __restrict__ nodes) {
+// One workgroup (one wavefront, its first lane working) per eigenvector:
+// the LU factors and the iterate live in LDS (5 k doubles and k ints),
+// so the serial recurrences wait on LDS rather than on global memory.
+__global__ __launch_bounds__(64) void inviter_kernel(const LzNode* __restrict__ nodes) {
   const LzNode n = nodes[blockIdx.z];
   const int k = n.kk, nvec = n.kk;
   const int64_t ldz = n.kk;
   const double* d = n.alpha;
   const double* e = n.beta;
   const double* theta = n.theta;
-  double* scratch = n.isc;
-  int* iscratch = n.ipiv;
   double* Z = n.Z;
   double* last = n.last;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nvec) return;
-  // interleaved scratch: entry j of this thread's array X at X[j * nvec]
-  const int64_t st = nvec;
-  double* dl = scratch + i;
-  double* dd = dl + st * k;
-  double* du = dd + st * k;
-  double* du2 = du + st * k;
-  double* b = du2 + st * k;
-  int* piv = iscratch + i;
+  const int i = blockIdx.x;
+  if (i >= nvec || threadIdx.x != 0) return;
+  extern __shared__ double ivs[];
+  const int64_t st = 1;
+  double* dl = ivs;
+  double* dd = dl + k;
+  double* du = dd + k;
+  double* du2 = du + k;
+  double* b = du2 + k;
+  int* piv = reinterpret_cast<int*>(b + k);
 #define DL(x) dl[(int64_t)(x) * st]
 #define DD(x) dd[(int64_t)(x) * st]
 #define DU(x) du[(int64_t)(x) * st]
@@ -725,6 +944,36 @@ hapod_status wide_eigh_batch(std::vector<WideJob>& jobs, double u_p, wide_alloc_
       set_error("wide_eigh: a full run needs m <= 768");
       return HAPOD_E_UNSUPPORTED;
     }
+  // ---- which matrices take which step kernels ---------------------------------------
+  // small matrices: the fused one-workgroup kernel; mid-size ones alone or
+  // few: the cooperative kernel (as many as the compute units hold, one
+  // workgroup each); the rest: the step kernels
+  int n_small = 0;
+  for (auto& jb : jobs) n_small += (jb.m > 0 && jb.m <= kFusedMaxM);
+  auto fused_node = [&](int i) {
+    return jobs[i].m <= kFusedMaxM && (jobs[i].m <= kFusedAloneMaxM || n_small >= kFusedBatchMin);
+  };
+  static int n_cu = 0;
+  if (n_cu == 0) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+      n_cu = 0;
+    (void)hipGetLastError();
+    if (n_cu <= 0) n_cu = 1;
+  }
+  // (the cooperative grid is the widest matrix's workgroup count times the
+  // number of matrices, one workgroup per CU by its LDS: all must be resident)
+  std::vector<char> coop(nn, 0);
+  {
+    int count = 0;
+    for (int i = 0; i < nn; ++i) {
+      const int64_t m = jobs[i].m;
+      if (m <= 0 || fused_node(i) || m > kCoopMaxM) continue;
+      if ((count + 1) * coop_pick(kCoopMaxM) > n_cu) break;
+      coop[i] = 1;
+      ++count;
+    }
+  }
   // ---- scratch: one block for every matrix -----------------------------------------
   std::vector<size_t> off(nn);
   std::vector<int> kmax(nn), nrc(nn);
@@ -745,17 +994,20 @@ hapod_status wide_eigh_batch(std::vector<WideJob>& jobs, double u_p, wide_alloc_
     double* alpha = (double*)take(sizeof(double) * k);
     double* beta = (double*)take(sizeof(double) * (k + 1));
     double* theta = (double*)take(sizeof(double) * k);
-    double* e2 = (double*)take(sizeof(double) * (size_t)k * ((k + 3) / 4));
+    double* e2 = nullptr;  // bisection works in LDS
     double* Z = (double*)take(sizeof(double) * (size_t)k * k);
     double* last = (double*)take(sizeof(double) * k);
-    double* isc = (double*)take(sizeof(double) * (size_t)5 * k * k);
-    int* ipiv = (int*)take(sizeof(int) * (size_t)k * k);
+    double* isc = nullptr;  // inverse iteration works in LDS
+    int* ipiv = nullptr;
     double* tr = (double*)take(sizeof(double));
     take(sizeof(void*) * k);     // Ritz-lift column table
     take(sizeof(int64_t) * k);   // its row-block strides
     take(sizeof(int64_t) * k);   // its row counts
     take(sizeof(int64_t));       // its rank
     double* wn = (double*)take(sizeof(double) * nr);
+    const int cp = coop_pick(m);
+    const int64_t xlen = std::max<int64_t>((int64_t)cp * (k + 2), m + cp);
+    double* xbuf = (coop[i] ? (double*)take(sizeof(double) * 3 * xlen) : nullptr);
     if (nd) {
       *nd = LzNode{};
       nd->G = jobs[i].G;
@@ -767,6 +1019,9 @@ hapod_status wide_eigh_batch(std::vector<WideJob>& jobs, double u_p, wide_alloc_
       nd->lambda = jobs[i].lambda;
       nd->ldv = jobs[i].ldv;
       nd->nrc = nr;
+      nd->coop_p = coop[i] ? cp : 0;
+      nd->xbuf = xbuf;
+      nd->xlen = xlen;
     }
     kmax[i] = k;
     nrc[i] = nr;
@@ -785,6 +1040,8 @@ hapod_status wide_eigh_batch(std::vector<WideJob>& jobs, double u_p, wide_alloc_
   total = al(total + sizeof(double) * 2 * nn);
   const size_t o_lift = total;
   total = al(total + sizeof(LiftNode) * nn);
+  const size_t o_bar = total;  // barrier counters, then the error flag
+  total = al(total + sizeof(unsigned) * (nn + 1));
   char* blk = (char*)alloc(ctx, total);
   if (!blk) {
     set_error("wide_eigh: scratch allocation failed");
@@ -797,7 +1054,13 @@ hapod_status wide_eigh_batch(std::vector<WideJob>& jobs, double u_p, wide_alloc_
     ~Rel() { f(c, p); }
   } rel{release, ctx, blk};
   std::vector<LzNode> hn(nn);
-  for (int i = 0; i < nn; ++i) sizes(i, true, blk, &hn[i]);
+  unsigned* dbar = (unsigned*)(blk + o_bar);
+  int* derr = (int*)(dbar + nn);
+  for (int i = 0; i < nn; ++i) {
+    sizes(i, true, blk, &hn[i]);
+    hn[i].bar = dbar + i;
+  }
+  HAPOD_TRY(launch_zero_bytes(dbar, sizeof(unsigned) * (nn + 1), stream));
   LzNode* dn = (LzNode*)(blk + o_nodes);
   int* dact = (int*)(blk + o_act);
   double* dgb = (double*)(blk + o_gb);
@@ -822,17 +1085,14 @@ hapod_status wide_eigh_batch(std::vector<WideJob>& jobs, double u_p, wide_alloc_
   std::vector<int> steps(kmax), act;
   std::vector<char> stopped(nn, 0);
   std::vector<double> prev_check(nn, 0.0);
-  // small matrices first: they run in the fused kernel, the list's prefix
-  int n_small = 0;
-  for (auto& jb : jobs) n_small += (jb.m > 0 && jb.m <= kFusedMaxM);
-  auto fused_node = [&](int i) {
-    return jobs[i].m <= kFusedMaxM && (jobs[i].m <= kFusedAloneMaxM || n_small >= kFusedBatchMin);
-  };
+  // the active list: fused matrices, then cooperative ones, then the rest
   for (int i = 0; i < nn; ++i) stopped[i] = (kmax[i] == jobs[i].m);
   for (int i = 0; i < nn; ++i)
     if (jobs[i].m > 0 && fused_node(i)) act.push_back(i);
   for (int i = 0; i < nn; ++i)
-    if (jobs[i].m > 0 && !fused_node(i)) act.push_back(i);
+    if (jobs[i].m > 0 && coop[i]) act.push_back(i);
+  for (int i = 0; i < nn; ++i)
+    if (jobs[i].m > 0 && !fused_node(i) && !coop[i]) act.push_back(i);
   const char* venv = std::getenv("HAPOD_VERBOSE");
   const bool verbose = venv && venv[0] == '1';
   bool act_dirty = true;
@@ -867,11 +1127,35 @@ hapod_status wide_eigh_batch(std::vector<WideJob>& jobs, double u_p, wide_alloc_
       hipLaunchKernelGGL(lanczos_fused_kernel, dim3(1, 1, nf), dim3(kFusedThreads), kFusedQCache * sizeof(double),
                          stream, dn, dact, j, j + kCheckEvery, kBreakdownTol);
     }
-    const unsigned nr = na - nf;
-    const int* dact_r = dact + nf;
+    unsigned nc = 0;
+    while (nf + nc < na && coop[act[nf + nc]]) ++nc;
+    if (nc > 0 && j % kCheckEvery == 0) {
+      static bool coop_attr = false;
+      if (!coop_attr) {
+        HAPOD_HIP(hipFuncSetAttribute((const void*)lanczos_coop_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      (int)(coop_lds_doubles(kCoopMaxM, coop_pick(kCoopMaxM)) * sizeof(double))));
+        coop_attr = true;
+      }
+      size_t shm = 0;
+      int pmax = 0;
+      for (unsigned a = nf; a < nf + nc; ++a) {
+        const int64_t m = jobs[act[a]].m;
+        shm = std::max(shm, coop_lds_doubles(m, coop_pick(m)) * sizeof(double));
+        pmax = std::max(pmax, coop_pick(m));
+      }
+      HAPOD_TRY(launch_zero_bytes(dbar, sizeof(unsigned) * nn, stream));
+      const int* dact_c = dact + nf;
+      int j0 = j, j1 = j + kCheckEvery;
+      double tol = kBreakdownTol;
+      void* args[] = {(void*)&dn, (void*)&dact_c, (void*)&j0, (void*)&j1, (void*)&tol, (void*)&derr};
+      HAPOD_HIP(hipLaunchCooperativeKernel((const void*)lanczos_coop_kernel, dim3((unsigned)pmax, 1, nc),
+                                           dim3(kCoopThreads), args, (unsigned)shm, stream));
+    }
+    const unsigned nr = na - nf - nc;
+    const int* dact_r = dact + nf + nc;
     int64_t am = 0;
     int anrc = 1;
-    for (unsigned a = nf; a < na; ++a) {
+    for (unsigned a = nf + nc; a < na; ++a) {
       am = std::max(am, jobs[act[a]].m);
       anrc = std::max(anrc, nrc[act[a]]);
     }
@@ -927,6 +1211,15 @@ hapod_status wide_eigh_batch(std::vector<WideJob>& jobs, double u_p, wide_alloc_
     }
   }
   HAPOD_HIP(hipGetLastError());
+  {
+    int e = 0;
+    HAPOD_HIP(hipMemcpyAsync(&e, derr, sizeof(int), hipMemcpyDeviceToHost, stream));
+    HAPOD_HIP(hipStreamSynchronize(stream));
+    if (e) {
+      set_error("wide_eigh: a barrier of the cooperative Lanczos kernel timed out");
+      return HAPOD_E_DEVICE;
+    }
+  }
   // ---- tridiagonal eigenproblems of the steps taken ----------------------------------
   int kk_max = 0;
   for (int i = 0; i < nn; ++i) {
@@ -934,9 +1227,11 @@ hapod_status wide_eigh_batch(std::vector<WideJob>& jobs, double u_p, wide_alloc_
     kk_max = std::max(kk_max, hn[i].kk);
   }
   HAPOD_HIP(hipMemcpyAsync(dn, hn.data(), sizeof(LzNode) * nn, hipMemcpyHostToDevice, stream));
-  hipLaunchKernelGGL(bisect_kernel, dim3((unsigned)((kk_max + 3) / 4), 1, nn), dim3(256), 0, stream, dn);
+  hipLaunchKernelGGL(bisect_kernel, dim3((unsigned)((kk_max + 3) / 4), 1, nn), dim3(256),
+                     sizeof(double) * 3 * (size_t)kk_max, stream, dn);
   HAPOD_HIP(hipGetLastError());
-  hipLaunchKernelGGL(inviter_kernel, dim3((unsigned)((kk_max + 255) / 256), 1, nn), dim3(256), 0, stream, dn);
+  hipLaunchKernelGGL(inviter_kernel, dim3((unsigned)kk_max, 1, nn), dim3(64),
+                     (sizeof(double) * 5 + sizeof(int)) * (size_t)kk_max, stream, dn);
   HAPOD_HIP(hipGetLastError());
   // ---- choose each converged leading block (host) ----------------------------------
   std::vector<std::vector<double>> th(nn), lz(nn), bet(nn);
