@@ -203,7 +203,11 @@ def prescribed_svd(n, m, sigma, seed):
     return (U * sigma) @ W.T
 
 
-@pytest.mark.parametrize("n,m", [(8, 3), (64, 16), (33, 33), (16, 40), (500, 100), (4096, 64), (600, 200)])
+# m = 200: one-workgroup Krylov steps; 250, 300, 450: a matrix alone above
+# 224 columns takes the cooperative multi-workgroup steps (16 workgroups up
+# to 320 columns, 32 above)
+@pytest.mark.parametrize("n,m", [(8, 3), (64, 16), (33, 33), (16, 40), (500, 100), (4096, 64), (600, 200),
+                                 (500, 250), (700, 300), (900, 450)])
 def test_node_pod_against_svd_oracle(hp, n, m):
     from oracle import metrics, pod
     r = min(n, m)
@@ -221,13 +225,14 @@ def test_node_pod_against_svd_oracle(hp, n, m):
     np.testing.assert_allclose(host(W), host(U) * s, rtol=0, atol=1e-12 * sigma[0])
 
 
-def test_node_pod_exact_multiplicity(hp):
+@pytest.mark.parametrize("m", [200, 250])
+def test_node_pod_exact_multiplicity(hp, m):
     """A lone node of 129..256 columns takes the full-length Krylov
-    eigensolver; G = 4 I (every eigenvalue repeated) stops its Krylov space
-    after one step, which must be detected and handed to the dense Jacobi
-    eigensolver: all 200 modes, sigma = 2, the span of the inputs."""
+    eigensolver (one workgroup at 200 columns, cooperative workgroups at
+    250); G = 4 I (every eigenvalue repeated) breaks its Krylov space down at
+    every step: all m modes, sigma = 2, the span of the inputs."""
     from oracle import metrics
-    n, m = 256, 200
+    n = 256
     S = np.zeros((n, m))
     S[np.arange(m), np.arange(m)] = 2.0
     s, U = hp.hapod_node_pod("fp64", dev_colmajor(S), 1.0)
