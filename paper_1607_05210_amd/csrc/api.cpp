@@ -489,9 +489,23 @@ hapod_status run_pod_batch(hapod_precision prec, std::vector<PodJob>& jobs, int 
     // eigenpairs (a full Lanczos run) and the same truncation policy
     j.wide_full = j.wide && jacobi_max <= 0 && m <= kAutoJacobiMax;
     L.tile = tile_for_node(node_compute(m), j.n, m);
+    // split-BF16: nodes with several column tiles get a split twin of their
+    // input once, instead of splitting every element in each tile that reads
+    // it; a pre-split twin (every value split once, in a pass of its own)
+    // pays when each column block is read by several tiles: above 256
+    // columns, or with tiles narrower than 128 (chosen by the tile tuner);
+    // below, the 128-column tiles split the FP32 values as they stage them
+    L.presplit = (compute == 2 && m >= kBf16MinCols && (L.tile != 128 || m > kStageSplitMaxCols) && j.n > 0 &&
+                  tiled_bytes(j.n, m, 4) <= twin_budget);
+    // pre-split nodes above 256 columns take 256-column tiles (eight
+    // wavefronts of 128 x 64: half the LDS reads per product)
+    if (L.presplit && m > kStageSplitMaxCols && L.tile == 128) L.tile = 256;
     L.ntiles = (int)((m + L.tile - 1) / L.tile);
     L.pairs = L.ntiles * (L.ntiles + 1) / 2;
-    const int per_node_target = std::max(1, (int)((int64_t)target_items * L.pairs / std::max(sum_pairs, 1)));
+    // (sum_pairs counts 128-column pairs: a node on 256-column tiles, whose
+    // items carry four times the work, aims at a quarter of the items)
+    const int64_t node_items = (int64_t)target_items * L.pairs / std::max(sum_pairs, 1);
+    const int per_node_target = std::max(1, (int)node_items);
     L.nchunks = pick_chunks(j.n, L.pairs, per_node_target, 2048);
     int64_t cr = (j.n + L.nchunks - 1) / L.nchunks;
     cr = (cr + kRowBlock - 1) / kRowBlock * kRowBlock;
@@ -506,14 +520,6 @@ hapod_status run_pod_batch(hapod_precision prec, std::vector<PodJob>& jobs, int 
     L.cols = take(sizeof(void*) * std::max<int64_t>(m, 1));
     L.rbs = take(sizeof(int64_t) * std::max<int64_t>(m, 1));
     L.crows = take(sizeof(int64_t) * std::max<int64_t>(m, 1));
-    // split-BF16: nodes with several column tiles get a split twin of their
-    // input once, instead of splitting every element in each tile that reads it
-    // a pre-split twin (every value split once, in a pass of its own) pays
-    // when each column block is read by several tiles: above 256 columns, or
-    // with tiles narrower than 128 (chosen by the tile tuner); below, the
-    // 128-column tiles split the FP32 values as they stage them
-    L.presplit = (compute == 2 && m >= kBf16MinCols && (L.tile != 128 || m > kStageSplitMaxCols) && j.n > 0 &&
-                  tiled_bytes(j.n, m, 4) <= twin_budget);
     if (L.presplit) {
       const size_t tb = align_up(tiled_bytes(j.n, m, 4));
       if (group_fill + tb > twin_budget) {
@@ -578,8 +584,9 @@ hapod_status run_pod_batch(hapod_precision prec, std::vector<PodJob>& jobs, int 
   std::vector<GramNode> gnodes(nj);
   std::vector<GramItem> gitems;
   // per twin group: (default compute, FP32) x (tile 128, 64, 32, 16) x (scalar,
-  // vector runs), and slot 16: pre-split 128-column tiles staged through LDS
-  std::vector<std::array<std::vector<GramItem>, 17>> items_by_tile(ngroups);
+  // vector runs), slot 16: split-BF16 128-column tiles staged through LDS,
+  // slot 17: pre-split 256-column tiles
+  std::vector<std::array<std::vector<GramItem>, 18>> items_by_tile(ngroups);
   auto tile_slot = [](int t) { return t == 128 ? 0 : t == 64 ? 1 : t == 32 ? 2 : 3; };
   int max_reduce_tile = 0;
   std::vector<int32_t> rpairs, rnode;
@@ -617,7 +624,7 @@ hapod_status run_pod_batch(hapod_precision prec, std::vector<PodJob>& jobs, int 
     const bool f32 = (node_compute(m) != compute);
     const bool staged = !f32 && compute == 2 && L.tile == 128;
     std::vector<GramItem>& gi =
-        items_by_tile[twin_group[i]][staged ? 16 : (f32 ? 8 : 0) + 2 * tile_slot(L.tile) + (vec ? 1 : 0)];
+        items_by_tile[twin_group[i]][L.tile == 256 ? 17 : staged ? 16 : (f32 ? 8 : 0) + 2 * tile_slot(L.tile) + (vec ? 1 : 0)];
     // Item order.  The workgroups an XCD runs at once take consecutive items
     // (see xcd_item), so consecutive items should share column blocks: for
     // each row chunk, the tile pairs go in super-tiles of kSuperI x kSuperJ
@@ -687,11 +694,11 @@ hapod_status run_pod_batch(hapod_precision prec, std::vector<PodJob>& jobs, int 
   }
   std::vector<std::vector<GramLaunch>> glaunch(ngroups);
   for (int gr = 0; gr < ngroups; ++gr)
-    for (int t = 0; t < 17; ++t) {
+    for (int t = 0; t < 18; ++t) {
       const auto& v = items_by_tile[gr][t];
       if (v.empty()) continue;
-      if (t == 16)
-        glaunch[gr].push_back(GramLaunch{128, 2, (int32_t)gitems.size(), (int32_t)v.size(), -1});
+      if (t >= 16)
+        glaunch[gr].push_back(GramLaunch{t == 17 ? 256 : 128, 2, (int32_t)gitems.size(), (int32_t)v.size(), -1});
       else
         glaunch[gr].push_back(GramLaunch{128 >> ((t & 7) / 2), t & 1, (int32_t)gitems.size(), (int32_t)v.size(),
                                          t >= 8 ? 1 : -1});
@@ -1555,7 +1562,10 @@ hapod_status gram_impl(int compute, int eb, int64_t n, int64_t m, const void* S,
   }
   Pool& pool = step_pool();
   auto cols = column_table(S, lds, m, eb);
-  const int tile = tile_override > 0 ? tile_override : gram_tile_for(m);
+  int tile = tile_override > 0 ? tile_override : gram_tile_for(m);
+  // split-BF16 above 256 columns: pre-split twin and 256-column tiles, as in
+  // the level batches
+  if (tile_override <= 0 && compute == 2 && m > kStageSplitMaxCols && n > 0) tile = 256;
   const int nt = (int)((m + tile - 1) / tile);
   const int pairs = nt * (nt + 1) / 2;
   const int KB = (compute == 2) ? 32 : 16;
@@ -1646,7 +1656,7 @@ hapod_status gram_impl(int compute, int eb, int64_t n, int64_t m, const void* S,
       }
       break;
     }
-    const int vec_mode = (gc == 2 && tile == 128) ? 2 : (vec_ok ? 1 : 0);
+    const int vec_mode = (gc == 2 && tile >= 128) ? 2 : (vec_ok ? 1 : 0);
     const GramLaunch gl{tile, vec_mode, 0, (int32_t)items.size(), gc != compute ? gc : -1};
     st = launch_gram(compute, (const GramNode*)(db + o_g), (const GramItem*)(db + o_i), &gl, 1,
                      (const int32_t*)(db + o_rp), (const int32_t*)(db + o_rn), (int)rp.size(), tile, stream);

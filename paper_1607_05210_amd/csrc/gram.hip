@@ -422,6 +422,133 @@ store:
   }
 }
 
+// Split-BF16 256 x 256 tiles of pre-split nodes: eight wavefronts, each a
+// 128 x 64 block (8 x 4 MFMA blocks of 16 x 16), operands staged through LDS
+// as in the 128-column staged path (32-row steps, double-buffered; one
+// 512-thread workgroup per CU by its LDS).  Each value read from LDS feeds
+// more products than with 64 x 64 quadrants (96 MFMAs per 24 fragment reads
+// instead of 48 per 16), which relieves the LDS bandwidth that bounds the
+// 128-column tiles.  Same products in the same order for every entry of G,
+// so a row chunk's partial sums are those of the 128-column path.
+__global__ __launch_bounds__(512, 1) void gram_bf16_t256_kernel(const GramNode* __restrict__ nodes,
+                                                                const GramItem* __restrict__ items, int first) {
+  constexpr int TT = 256, NBA = 8, NBB = 4, NBT = kRowBlock / 32;
+  constexpr int kColB = 8 * 16 + 16;  // LDS bytes per column and step (padded)
+  const GramItem item = items[first + xcd_item(blockIdx.x, gridDim.x)];
+  const GramNode nd = nodes[item.node];
+  const int t = threadIdx.x;
+  const int wave = t >> 6, lane = t & 63;
+  const int wi = wave >> 2, wj = wave & 3;  // 128-row half, 64-column quarter
+  const bool diag = (item.ti == item.tj);
+  const int li = lane & 15, g = lane >> 4;
+  const int cA0 = item.ti * TT + wi * 128, cB0 = item.tj * TT + wj * 64;
+  // on a diagonal tile the blocks wholly below the diagonal mirror others
+  const bool idle = (diag && wi * 128 >= wj * 64 + 64) || cA0 >= nd.m || cB0 >= nd.m;
+  const int64_t r0 = (int64_t)item.chunk * nd.chunk_rows;
+  const int64_t r1 = min(nd.n, r0 + nd.chunk_rows);
+  const int64_t blk0 = r0 >> 7, nblk = (r1 - r0 + kRowBlock - 1) >> 7;
+
+  __shared__ __attribute__((aligned(16))) char stage[2][512 * kColB];
+  typedef __attribute__((ext_vector_type(4))) int i4;
+  const int part = t & 7;
+  const int ncl = diag ? 256 : 512;  // columns staged
+  const int nld = ncl / 64;          // loads per thread and step
+  // the pre-split twin is row-block tiled: column c of block b at
+  // base + b rbs + 128 c (one stride for all columns)
+  const float* tw = reinterpret_cast<const float*>(nd.cols[0]);
+  const int64_t trb = nd.rbs[0];
+  const int poff = (part < 4) ? part : 16 + (part - 4);  // bf8 offset in the step
+  const int64_t S = nblk * NBT;
+  i4 pre[8];
+  auto gload = [&](int64_t st) {
+    const int64_t blk = blk0 + st / NBT;
+    const int bt = (int)(st % NBT);
+    const float* bp = tw + blk * trb;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      if (i >= nld) continue;
+      const int cl = 64 * i + (t >> 3);
+      const int base = (cl < 256) ? item.ti * TT + cl : item.tj * TT + (cl - 256);
+      const int c = min(base, nd.m - 1);  // columns past m alias the last one
+      pre[i] = ((gptr<i4>)as_global(bp + (int64_t)c * kRowBlock))[4 * bt + poff];
+    }
+  };
+  auto lstore = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+      if (i < nld) *(i4*)(stage[buf] + (64 * i + (t >> 3)) * kColB + part * 16) = pre[i];
+  };
+  f4 acc[NBA][NBB];
+#pragma unroll
+  for (int a = 0; a < NBA; ++a)
+#pragma unroll
+    for (int b = 0; b < NBB; ++b) acc[a][b] = f4{0, 0, 0, 0};
+  const int la = wi * 128, lb = (diag ? 0 : 256) + wj * 64;
+  auto compute = [&](int buf) {
+    const char* sb = stage[buf];
+    bf8 yh[NBB], yl[NBB];
+#pragma unroll
+    for (int b = 0; b < NBB; ++b) {
+      const char* q = sb + (lb + b * 16 + li) * kColB + g * 16;
+      yh[b] = *(const bf8*)q;
+      yl[b] = *(const bf8*)(q + 64);
+    }
+#pragma unroll
+    for (int a = 0; a < NBA; ++a) {
+      const char* q = sb + (la + a * 16 + li) * kColB + g * 16;
+      const bf8 xh = *(const bf8*)q;
+      const bf8 xl = *(const bf8*)(q + 64);
+#pragma unroll
+      for (int b = 0; b < NBB; ++b) {
+        acc[a][b] = mfma_bf16(xl, yh[b], acc[a][b]);
+        acc[a][b] = mfma_bf16(xh, yl[b], acc[a][b]);
+        acc[a][b] = mfma_bf16(xh, yh[b], acc[a][b]);
+      }
+    }
+  };
+  if (S > 0) {
+    gload(0);
+    lstore(0);
+  }
+  __syncthreads();
+  for (int64_t st = 0; st < S; ++st) {
+    if (st + 1 < S) gload(st + 1);
+    if (!idle) compute((int)(st & 1));
+    if (st + 1 < S) lstore((int)((st + 1) & 1));
+    __syncthreads();
+  }
+  if (idle) return;
+  if (nd.nchunks == 1) {
+#pragma unroll
+    for (int a = 0; a < NBA; ++a)
+#pragma unroll
+      for (int b = 0; b < NBB; ++b)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = cA0 + a * 16 + acc_row<f4>(lane, v);
+          const int col = cB0 + b * 16 + acc_col(lane);
+          if (row < nd.m && col < nd.m && row <= col) {
+            const double x = (double)acc[a][b][v];
+            nd.G[(int64_t)col * nd.ldg + row] = x;
+            nd.G[(int64_t)row * nd.ldg + col] = x;
+          }
+        }
+  } else {
+    const int slot = (item.pair - nd.pair_base) * nd.nchunks + item.chunk;
+    double* Pp = nd.partial + (int64_t)slot * (TT * TT);
+#pragma unroll
+    for (int a = 0; a < NBA; ++a)
+#pragma unroll
+      for (int b = 0; b < NBB; ++b)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int i = wi * 128 + a * 16 + acc_row<f4>(lane, v);
+          const int j = wj * 64 + b * 16 + acc_col(lane);
+          Pp[j * TT + i] = (double)acc[a][b][v];
+        }
+  }
+}
+
 // Partial tiles of one tile pair summed in slot order (chunk, then
 // wavefront), so the result does not depend on scheduling; the upper-triangle
 // entries are written to both triangles of G.  Grid: (pair, slice of
@@ -481,11 +608,18 @@ hapod_status launch_gram_c(const GramNode* d_nodes, const GramItem* d_items, con
   for (int i = 0; i < num_launches; ++i) {
     const GramLaunch& L = launches[i];
     if (L.count <= 0) continue;
-    if (L.tile != 128 && L.tile != 64 && L.tile != 32 && L.tile != 16) {
-      set_error("launch_gram: tile must be 128, 64, 32 or 16");
+    if (L.tile != 256 && L.tile != 128 && L.tile != 64 && L.tile != 32 && L.tile != 16) {
+      set_error("launch_gram: tile must be 256, 128, 64, 32 or 16");
       return HAPOD_E_INVALID;
     }
-    if (L.vec == 2) {
+    if (L.vec == 2 && L.tile == 256) {
+      if constexpr (C == 2) {
+        hipLaunchKernelGGL(gram_bf16_t256_kernel, dim3(L.count), dim3(512), 0, stream, d_nodes, d_items, L.first);
+      } else {
+        set_error("launch_gram: 256-column tiles are split-BF16 only");
+        return HAPOD_E_INVALID;
+      }
+    } else if (L.vec == 2) {
       if constexpr (C == 2) {
         if (L.tile != 128) {
           set_error("launch_gram: staged launches take 128-column tiles");

@@ -73,7 +73,7 @@ struct GramNode {
   int32_t split;       // 1: columns hold split-BF16 blocks (see launch_split_cols)
   int32_t tile;        // 128, 64, 32 or 16
 };
-__host__ __device__ inline int gram_slots_per_chunk(int tile) { return tile == kGramTile ? 1 : 4; }
+__host__ __device__ inline int gram_slots_per_chunk(int tile) { return tile >= kGramTile ? 1 : 4; }
 
 struct GramItem {
   int32_t node;
