@@ -175,7 +175,7 @@ typedef struct {
                                       replaces the Thm. 3.5 tolerance of that node         */
   int32_t jacobi_max;              /* k > 0: nodes with at most k input columns (k <= 1024)
                                       take the Jacobi eigensolver, wider ones Lanczos.
-                                      0: automatic -- Jacobi up to 128 columns; 129..256
+                                      0: automatic -- Jacobi up to 64 columns; 65..256
                                       a full-length Lanczos run (every eigenpair, as
                                       Jacobi gives); above 256 Lanczos stopped at the
                                       Gram's rounding level                          */

@@ -399,11 +399,13 @@ hapod_status autotune_tile(int compute, int eb, int64_t n, int64_t m_node, Pool&
 }
 
 // Eigensolver choice.  jacobi_max > 0: Jacobi up to that width, Lanczos
-// above.  jacobi_max <= 0 (automatic): Jacobi in LDS up to kJacobiLdsMax;
+// above.  jacobi_max <= 0 (automatic): Jacobi in LDS up to kAutoJacobiMin;
 // between that and kAutoJacobiMax a full-length Lanczos run (every
-// eigenpair, as Jacobi gives, at a cost growing with m instead of m^3 on one
-// workgroup; all such nodes of a batch iterate together); above, Lanczos
-// stopped at the Gram's rounding level.
+// eigenpair, as Jacobi gives, at a cost growing with m^2 instead of m^3 on
+// one workgroup: 2 ms against 32 ms at 128 columns; all such nodes of a
+// batch iterate together); above, Lanczos stopped at the Gram's rounding
+// level.
+constexpr int kAutoJacobiMin = 64;
 constexpr int kAutoJacobiMax = 256;
 constexpr int64_t kLiftTargetItems = 2048;  // lift workgroups per launch to aim for
 
@@ -484,7 +486,7 @@ hapod_status run_pod_batch(hapod_precision prec, std::vector<PodJob>& jobs, int 
     PodJob& j = jobs[i];
     Lay& L = lay[i];
     const int64_t m = j.m;
-    j.wide = (jacobi_max > 0) ? (m > jacobi_max) : (m > kJacobiLdsMax);
+    j.wide = (jacobi_max > 0) ? (m > jacobi_max) : (m > kAutoJacobiMin);
     // a node taken from Jacobi only for speed keeps Jacobi's result: all
     // eigenpairs (a full Lanczos run) and the same truncation policy
     j.wide_full = j.wide && jacobi_max <= 0 && m <= kAutoJacobiMax;
