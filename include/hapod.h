@@ -186,6 +186,15 @@ typedef struct {
   int32_t leaf_wave;               /* 0: all leaves of a level in one launch group; k > 0:
                                       at most k leaves per group, so the provider needs at
                                       most k leaves resident at a time                     */
+  int32_t block_gram;              /* 1: block-structured Gram at inner nodes -- a computed
+                                      child's scaled modes sigma_k u_k have the Gram block
+                                      diag(sigma_k^2) (orthonormal u_k), so column-tile
+                                      pairs that lie inside one such child's block are not
+                                      computed but set to it; the node's raw (pass-through)
+                                      columns go first so the children's blocks start on
+                                      tile boundaries.  FP64 form only (HAPOD_E_INVALID
+                                      otherwise: FP32 modes are not orthonormal enough).
+                                      0: every Gram entry computed                      */
 } hapod_options;
 
 /* Validate the tree (Def. 3.1), compute levels (height: leaves are level 1),

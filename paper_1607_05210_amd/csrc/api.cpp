@@ -278,6 +278,10 @@ struct PodJob {
   double wide_unresolved = 0.0;  // trace(G) minus the returned eigenvalues
   double wide_slack = 0.0;       // rounding allowance of that difference
   double wide_noise_room = 0.0;  // energy the unresolved eigenvalues may hold
+  // block-structured Gram: column ranges [lo, hi) of computed children's
+  // scaled modes and sigma^2 of every column (0 outside those ranges)
+  std::vector<std::pair<int64_t, int64_t>> sblk;
+  std::vector<double> s2;
 };
 
 struct PhaseTimes {
@@ -592,6 +596,8 @@ hapod_status run_pod_batch(hapod_precision prec, std::vector<PodJob>& jobs, int 
   auto tile_slot = [](int t) { return t == 128 ? 0 : t == 64 ? 1 : t == 32 ? 2 : 3; };
   int max_reduce_tile = 0;
   std::vector<int32_t> rpairs, rnode;
+  std::vector<GramFill> fills;
+  std::vector<double> s2_all;
   std::vector<EigNode> enodes_small, enodes_big;
   std::vector<TruncNode> tnodes(nj);
 
@@ -635,18 +641,37 @@ hapod_status run_pod_batch(hapod_precision prec, std::vector<PodJob>& jobs, int 
     // stay row-major over the upper triangle (partial slots, reduction).
     const int nt = L.ntiles;
     auto pair_of = [nt](int ti, int tj) { return ti * nt - ti * (ti - 1) / 2 + (tj - ti); };
+    // block-structured Gram: a tile wholly inside one computed child's
+    // columns carries that child's id; pairs of tiles of one child are set
+    // to diag(sigma^2) instead of computed (Def. 3.2: the child's inputs to
+    // this node are its scaled orthonormal modes)
+    std::vector<int> tile_blk(nt, -1);
+    for (size_t q = 0; q < j.sblk.size(); ++q)
+      for (int ti = 0; ti < nt; ++ti) {
+        const int64_t lo = (int64_t)ti * L.tile, hi = std::min<int64_t>(m, lo + L.tile);
+        if (lo >= j.sblk[q].first && hi <= j.sblk[q].second) tile_blk[ti] = (int)q;
+      }
+    auto set_pair = [&](int ti, int tj) { return tile_blk[ti] >= 0 && tile_blk[ti] == tile_blk[tj]; };
     for (int c = 0; c < L.nchunks; ++c)
       for (int I = 0; I < nt; I += kSuperI)
         for (int J = (I / kSuperJ) * kSuperJ; J < nt; J += kSuperJ)
           for (int ti = I; ti < std::min(I + kSuperI, nt); ++ti)
             for (int tj = std::max(J, ti); tj < std::min(J + kSuperJ, nt); ++tj)
-              gi.push_back(GramItem{i, (int16_t)ti, (int16_t)tj, c, pair_base + pair_of(ti, tj)});
-    if (L.slots > 1)
-      for (int q = 0; q < L.pairs; ++q) {
-        rpairs.push_back(pair_base + q);
-        rnode.push_back(i);
-        max_reduce_tile = std::max(max_reduce_tile, L.tile);
+              if (!set_pair(ti, tj))
+                gi.push_back(GramItem{i, (int16_t)ti, (int16_t)tj, c, pair_base + pair_of(ti, tj)});
+    for (int ti = 0; ti < nt; ++ti)
+      for (int tj = ti; tj < nt; ++tj) {
+        if (set_pair(ti, tj)) {
+          const int r0 = ti * L.tile, c0 = tj * L.tile;
+          fills.push_back(GramFill{g.G, m, (int64_t)s2_all.size(), r0, c0, (int)std::min<int64_t>(L.tile, m - r0),
+                                   (int)std::min<int64_t>(L.tile, m - c0)});
+        } else if (L.slots > 1) {
+          rpairs.push_back(pair_base + pair_of(ti, tj));
+          rnode.push_back(i);
+          max_reduce_tile = std::max(max_reduce_tile, L.tile);
+        }
       }
+    if (!j.s2.empty()) s2_all.insert(s2_all.end(), j.s2.begin(), j.s2.end());
     pair_base += L.pairs;
     if (!j.wide && m > 0) {
       EigNode e{};
@@ -708,7 +733,7 @@ hapod_status run_pod_batch(hapod_precision prec, std::vector<PodJob>& jobs, int 
     }
   const size_t o_g = blob.add_vec(gnodes), o_gi = blob.add_vec(gitems), o_rp = blob.add_vec(rpairs),
                o_rn = blob.add_vec(rnode), o_es = blob.add_vec(enodes_small), o_eb = blob.add_vec(enodes_big),
-               o_t = blob.add_vec(tnodes);
+               o_t = blob.add_vec(tnodes), o_fill = blob.add_vec(fills), o_s2 = blob.add_vec(s2_all);
   char* dblob = nullptr;
   HAPOD_TRY(pool.alloc(blob.host.size(), (void**)&dblob));
   struct Guard2 {
@@ -752,6 +777,8 @@ hapod_status run_pod_batch(hapod_precision prec, std::vector<PodJob>& jobs, int 
   HAPOD_TRY(launch_gram(compute, (const GramNode*)(dblob + o_g), (const GramItem*)(dblob + o_gi), nullptr, 0,
                         (const int32_t*)(dblob + o_rp), (const int32_t*)(dblob + o_rn), (int)rpairs.size(),
                         max_reduce_tile, stream));
+  HAPOD_TRY(launch_gram_fill((const GramFill*)(dblob + o_fill), (int)fills.size(), (const double*)(dblob + o_s2),
+                             stream));
   for (int i = 0; i < nj; ++i) HAPOD_TRY(launch_check_diag(gnodes[i].G, gnodes[i].ldg, jobs[i].m, d_flag, stream));
   if (times && ev.ok) HAPOD_HIP(hipEventRecord(ev.e[1], stream));
   // ---- eigensolve -----------------------------------------------------------
@@ -1055,6 +1082,13 @@ hapod_status hapod_plan(const hapod_tree* tree, double eps_star, double omega, c
     return HAPOD_E_INVALID;
   }
   if (opts) HAPOD_TRY(check_prec(opts->prec));
+  if (opts && opts->block_gram && opts->prec != HAPOD_FP64) {
+    // the set blocks assume children's modes orthonormal to working accuracy;
+    // FP32 modes are not, and mixing exact blocks with computed FP32 ones
+    // moves ranks at the noise floor far more than the rounding itself
+    set_error("hapod_plan: block_gram needs the FP64 form");
+    return HAPOD_E_INVALID;
+  }
   auto P = std::make_unique<hapod_plan_s>();
   const int32_t nn = tree->num_nodes;
   P->num_nodes = nn;
@@ -1303,12 +1337,18 @@ hapod_status hapod_run(hapod_plan_t P, hapod_leaf_fn get_leaf, void* user, void*
       for (int32_t a : grp) {
         std::vector<const void*> in;
         std::vector<int64_t> in_rbs, in_rows;
+        std::vector<std::pair<int64_t, int32_t>> sblk;  // (first column, child)
         hapod_status s = HAPOD_OK;
         if (P->children[a].empty()) {
           s = fetch_leaf(a, in, in_rbs, in_rows);
           group_fetched = true;
         } else {
-          for (int32_t b : P->children[a]) {
+          // block-structured Gram: raw columns (pass-through children) first,
+          // so that each computed child's scaled modes start on a tile edge
+          std::vector<int32_t> order(P->children[a]);
+          if (P->opts.block_gram)
+            std::stable_partition(order.begin(), order.end(), [&](int32_t b) { return P->eps[b] == 0.0; });
+          for (int32_t b : order) {
             if (deferred[b]) {
               group_fetched = true;
               holds_leaf[b] = 1;
@@ -1316,6 +1356,8 @@ hapod_status hapod_run(hapod_plan_t P, hapod_leaf_fn get_leaf, void* user, void*
               if (s != HAPOD_OK) break;
               deferred[b] = 0;
             }
+            if (P->opts.block_gram && P->eps[b] > 0.0 && !out_cols[b].empty())
+              sblk.push_back({(int64_t)in.size(), b});
             in.insert(in.end(), out_cols[b].begin(), out_cols[b].end());
             in_rbs.insert(in_rbs.end(), out_rbs[b].begin(), out_rbs[b].end());
             in_rows.insert(in_rows.end(), out_rows[b].begin(), out_rows[b].end());
@@ -1343,6 +1385,15 @@ hapod_status hapod_run(hapod_plan_t P, hapod_leaf_fn get_leaf, void* user, void*
           continue;
         }
         PodJob j;
+        if (!sblk.empty()) {
+          j.s2.assign(in.size(), 0.0);
+          for (auto& bb : sblk) {
+            const std::vector<double>& sg = P->sigma[bb.second];
+            const int64_t len = (int64_t)out_cols[bb.second].size();
+            for (int64_t k = 0; k < len && k < (int64_t)sg.size(); ++k) j.s2[bb.first + k] = sg[k] * sg[k];
+            j.sblk.push_back({bb.first, bb.first + len});
+          }
+        }
         j.cols = std::move(in);
         j.rbs = std::move(in_rbs);
         j.crows = std::move(in_rows);

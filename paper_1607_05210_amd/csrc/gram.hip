@@ -549,6 +549,21 @@ __global__ __launch_bounds__(512, 1) void gram_bf16_t256_kernel(const GramNode* 
   }
 }
 
+// Block-structured Gram: the tile pairs inside one child's diag(sigma^2)
+// block, set rather than computed.  Grid: (fill, slice of 256 entries).
+__global__ __launch_bounds__(256) void gram_fill_kernel(const GramFill* __restrict__ fills,
+                                                        const double* __restrict__ s2) {
+  const GramFill f = fills[blockIdx.x];
+  const int64_t e = (int64_t)blockIdx.y * 256 + threadIdx.x;
+  if (e >= (int64_t)f.rn * f.cn) return;
+  const int i = (int)(e % f.rn), jj = (int)(e / f.rn);
+  const int64_t row = f.r0 + i, col = f.c0 + jj;
+  if (row > col) return;
+  const double v = (row == col) ? s2[f.s2_off + row] : 0.0;
+  f.G[col * f.ldg + row] = v;
+  f.G[row * f.ldg + col] = v;
+}
+
 // Partial tiles of one tile pair summed in slot order (chunk, then
 // wavefront), so the result does not depend on scheduling; the upper-triangle
 // entries are written to both triangles of G.  Grid: (pair, slice of
@@ -642,6 +657,14 @@ hapod_status launch_gram_c(const GramNode* d_nodes, const GramItem* d_items, con
 }
 
 }  // namespace
+
+hapod_status launch_gram_fill(const GramFill* d_fills, int count, const double* s2_base, hipStream_t stream) {
+  if (count <= 0) return HAPOD_OK;
+  // tiles are at most 256 x 256
+  hipLaunchKernelGGL(gram_fill_kernel, dim3((unsigned)count, 256), dim3(256), 0, stream, d_fills, s2_base);
+  HAPOD_HIP(hipGetLastError());
+  return HAPOD_OK;
+}
 
 hapod_status launch_gram(int compute, const GramNode* d_nodes, const GramItem* d_items,
                          const GramLaunch* launches, int num_launches,

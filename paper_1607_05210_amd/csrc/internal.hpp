@@ -99,6 +99,18 @@ struct GramLaunch {
   int32_t count;
   int32_t compute;
 };
+// Gram entries set instead of computed (block-structured inner-node Gram):
+// rows [r0, r0 + rn) x columns [c0, c0 + cn) of G lie inside one child's
+// block diag(sigma^2); entries with row <= col get sigma_row^2 on the
+// diagonal and 0 elsewhere, written to both triangles.  s2_base[s2_off + c]
+// is sigma_c^2 for the node's column c.
+struct GramFill {
+  double* G;
+  int64_t ldg;
+  int64_t s2_off;
+  int32_t r0, c0, rn, cn;
+};
+hapod_status launch_gram_fill(const GramFill* d_fills, int count, const double* s2_base, hipStream_t stream);
 hapod_status launch_gram(int compute, const GramNode* d_nodes, const GramItem* d_items,
                          const GramLaunch* launches, int num_launches,
                          const int32_t* d_reduce_pairs, const int32_t* d_reduce_node, int num_reduce,

@@ -129,6 +129,38 @@ def test_chain_bumps_fp64(hp):
     assert metrics.mean_projection_error(S, U) <= eps_star ** 2
 
 
+def test_chain_block_structured_gram(hp):
+    """Chain of 128-column chunks with the block-structured Gram (FP64): the
+    raw chunk goes first, the previous node's scaled modes fill the next
+    tile, whose Gram block is set to diag(sigma^2) instead of computed.  Same
+    oracle bounds as the literal Gram, and the same ranks."""
+    from oracle import metrics
+    n, chunks, cols = 4096, 6, 128
+    S = synth.bumps(n, chunks * cols, seed=11)
+    parent, chunk = synth.chain_tree(chunks)
+    blocks = split_cols(S, [cols] * chunks)
+    data = {leaf: blocks[c] for leaf, c in chunk.items()}
+    zero = tuple(b for b in chunk if b != 0)
+    eps_star = 1e-3 * math.sqrt(np.mean(np.sum(S * S, axis=0)))
+    plan, sig, U, ref, eps, leaf_cols, data64 = run_both(hp, parent, data, n, eps_star, 0.75, "fp64", zero=zero,
+                                                         block_gram=True)
+    plan0, sig0, U0, *_ = run_both(hp, parent, data, n, eps_star, 0.75, "fp64", zero=zero)
+    root = tree.validate(parent)
+    s_ref, U_ref = ref[root]
+    r = metrics.resolved_rank(s_ref, len(sig), UP["fp64"], TAU["fp64"])
+    assert metrics.subspace_error(U_ref, U, r) <= TAU["fp64"]
+    assert list(plan.ranks()) == list(plan0.ranks())
+    assert metrics.subspace_error(U0, U, r) <= TAU["fp64"]
+    assert sigma_within_bound(s_ref, sig, r, UP["fp64"], n, eps, root)
+    assert metrics.mean_projection_error(S, U) <= eps_star ** 2
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_block_structured_gram_needs_fp64(hp, prec):
+    with pytest.raises(hp.HapodError):
+        hp.Plan(synth.star_tree(2), [4, 4, 0], 64, 1e-3, 0.5, prec=prec, block_gram=True)
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_balanced_three_levels(hp, prec):
     n = 3000
