@@ -195,6 +195,8 @@ typedef struct {
                                       tile boundaries.  FP64 form only (HAPOD_E_INVALID
                                       otherwise: FP32 modes are not orthonormal enough).
                                       0: every Gram entry computed                      */
+  int32_t right_vectors;           /* 1: keep every computed node's right singular vectors
+                                      (eigenvectors V[:, :N]) for hapod_right_vectors   */
 } hapod_options;
 
 /* Validate the tree (Def. 3.1), compute levels (height: leaves are level 1),
@@ -257,6 +259,18 @@ hapod_status hapod_run(hapod_plan_t plan, hapod_leaf_fn get_leaf, void* user,
  * Synchronises the stream.                                                  */
 hapod_status hapod_modes(hapod_plan_t plan, int32_t node, void* U, int64_t ldu,
                          double* sigma, int64_t* rank, void* stream);
+
+/* Right factor of the low-rank factorisation of the snapshot map (Rem. 3.8,
+ * Def. 3.9): S ~ U diag(sigma) W^T with W^T W = I and the squared Frobenius
+ * error at most the sum of eps(gamma)^2 over all nodes.  W is composed from
+ * the nodes' right singular vectors, Lambda~ = diag(Lambda~_children)
+ * Lambda_node (identity for eps = 0), on the device.
+ *   W    device, |S| x N_root double, column-major, ld ldw >= |S|; row i
+ *        belongs to snapshot i counted over the leaves in ascending node id,
+ *        each leaf's columns in order.
+ * Needs a completed run of a plan made with right_vectors = 1
+ * (HAPOD_E_INVALID otherwise).  Synchronises the stream.                   */
+hapod_status hapod_right_vectors(hapod_plan_t plan, double* W, int64_t ldw, void* stream);
 
 /* Per-node diagnostics of the last run, host, num_nodes entries each, any may
  * be NULL: input columns m, negative Gram eigenvalues, lambda_1, lambda_min. */

@@ -42,7 +42,7 @@ class HapodTree(C.Structure):
 class HapodOptions(C.Structure):
     _fields_ = [("prec", _i32), ("reorth", _i32), ("mem_cap_bytes", _i64),
                 ("node_eps_override", _pdbl), ("jacobi_max", _i32), ("autotune", _i32),
-                ("leaf_wave", _i32), ("block_gram", _i32)]
+                ("leaf_wave", _i32), ("block_gram", _i32), ("right_vectors", _i32)]
 
 
 LEAF_FN = C.CFUNCTYPE(_i32, _vp, _i32, C.POINTER(_vp), _pi64, _vp)
@@ -59,6 +59,7 @@ _SIGS = {
     "hapod_run": [_vp, LEAF_FN, _vp, _vp],
     "hapod_modes": [_vp, _i32, _vp, _i64, _pdbl, _pi64, _vp],
     "hapod_node_stats": [_vp, _pi64, _pi64, _pdbl, _pdbl],
+    "hapod_right_vectors": [_vp, _vp, _i64, _vp],
     "hapod_run_timing": [_vp, _pdbl],
     "hapod_level_timing": [_vp, _i32, _pdbl],
 }
@@ -208,7 +209,7 @@ class Plan:
 
     def __init__(self, parent, leaf_cols, n, eps_star, omega, prec="fp64", reorth=False,
                  mem_cap_bytes=0, eps_override=None, jacobi_max=0, leaf_rows=None, leaf_wave=0,
-                 autotune=False, block_gram=False):
+                 autotune=False, block_gram=False, right_vectors=False):
         import numpy as np
         self.num_nodes = len(parent)
         self.n = int(n)
@@ -224,7 +225,8 @@ class Plan:
             arr = np.asarray(eps_override, dtype=np.float64)
             ov = arr.ctypes.data_as(_pdbl)
         opts = HapodOptions(self.prec, int(bool(reorth)), int(mem_cap_bytes), ov, int(jacobi_max),
-                            int(bool(autotune)), int(leaf_wave), int(bool(block_gram)))
+                            int(bool(autotune)), int(leaf_wave), int(bool(block_gram)),
+                            int(bool(right_vectors)))
         h = C.c_void_p()
         _check(_lib.hapod_plan(C.byref(tree), float(eps_star), float(omega), C.byref(opts), C.byref(h)),
                "hapod_plan")
@@ -297,6 +299,21 @@ class Plan:
         _check(_lib.hapod_modes(self._h, node, pu, self.n, sig.ctypes.data_as(_pdbl), C.byref(r),
                                 _stream(stream)), "hapod_modes")
         return sig[:N].copy(), U
+
+    def right_vectors(self, stream=None):
+        """W of the factorisation S ~ U diag(sigma) W^T (Rem. 3.8, Def. 3.9):
+        float64 device tensor, one row per snapshot (leaves in ascending node
+        id, each leaf's columns in order), one column per root mode."""
+        r = C.c_int64(0)
+        _check(_lib.hapod_modes(self._h, -1, None, self.n, None, C.byref(r), None), "hapod_modes")
+        nr = r.value
+        inner = set(int(p) for p in self._parent if int(p) >= 0)
+        ns = sum(int(self._cols[a]) for a in range(self.num_nodes) if a not in inner)
+        W = colmajor(max(ns, 1), nr, torch.float64)[:ns]
+        if nr > 0 and ns > 0:
+            _check(_lib.hapod_right_vectors(self._h, C.c_void_p(W.data_ptr()), max(ns, 1), _stream(stream)),
+                   "hapod_right_vectors")
+        return W
 
     def node_stats(self):
         import numpy as np

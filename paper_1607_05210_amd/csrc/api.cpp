@@ -282,6 +282,8 @@ struct PodJob {
   // scaled modes and sigma^2 of every column (0 outside those ranges)
   std::vector<std::pair<int64_t, int64_t>> sblk;
   std::vector<double> s2;
+  bool keep_v = false;      // copy V[:, :N] to a pool block of its own
+  double* vkeep = nullptr;  // that block (m x N, ld m)
 };
 
 struct PhaseTimes {
@@ -877,6 +879,15 @@ hapod_status run_pod_batch(hapod_precision prec, std::vector<PodJob>& jobs, int 
                              hipMemcpyDeviceToHost, stream));
   HAPOD_HIP(hipStreamSynchronize(stream));
   std::memcpy(ranks.data(), pin, sizeof(int64_t) * nj);
+  // right singular vectors kept for the factorisation of the snapshot map:
+  // the first N eigenvectors (columns of V, ld m) are contiguous
+  for (int i = 0; i < nj; ++i) {
+    PodJob& j = jobs[i];
+    if (!j.keep_v || ranks[i] <= 0 || j.m <= 0) continue;
+    const size_t bytes = sizeof(double) * (size_t)j.m * ranks[i];
+    HAPOD_TRY(pool.alloc(bytes, (void**)&j.vkeep));
+    HAPOD_HIP(hipMemcpyAsync(j.vkeep, scratch + lay[i].V, bytes, hipMemcpyDeviceToDevice, stream));
+  }
   // outputs sized by the ranks, carved from one block for the batch (one
   // allocation instead of one per node; the caller frees the block once
   // every node in it has been consumed)
@@ -1062,6 +1073,10 @@ struct hapod_plan_s {
   std::vector<const void*> root_cols;  // pass-through root: its input columns
   std::vector<int64_t> root_rbs, root_rows;
   std::vector<int64_t> rows;           // rows each node's vectors hold
+  // right_vectors: per computed node its eigenvectors V[:, :N] (m x N, pool
+  // block), and per inner node the children in the order of its input
+  std::vector<double*> vkeep;
+  std::vector<std::vector<int32_t>> in_order;
   double timing[6] = {0, 0, 0, 0, 0, 0};
   std::vector<std::array<double, 4>> level_ms;  // {gram, eig, trunc, lift} per level
   Pool pool;
@@ -1204,6 +1219,110 @@ hapod_status hapod_plan_query(hapod_plan_t plan, double* eps, int32_t* level, in
   return HAPOD_OK;
 }
 
+hapod_status hapod_right_vectors(hapod_plan_t P, double* W, int64_t ldw, void* stream_) {
+  if (!P || !W) {
+    set_error("hapod_right_vectors: NULL argument");
+    return HAPOD_E_INVALID;
+  }
+  if (!P->has_result || !P->opts.right_vectors) {
+    set_error("hapod_right_vectors: no completed run of a plan made with right_vectors = 1");
+    return HAPOD_E_INVALID;
+  }
+  hipStream_t stream = (hipStream_t)stream_;
+  // snapshot rows: leaves in ascending node id, each leaf's columns in order
+  const int32_t nn = P->num_nodes;
+  std::vector<int64_t> leaf_off(nn, -1);
+  int64_t total = 0;
+  for (int32_t a = 0; a < nn; ++a)
+    if (P->children[a].empty()) {
+      leaf_off[a] = total;
+      total += P->leaf_cols[a];
+    }
+  if (ldw < std::max<int64_t>(total, 1)) {
+    set_error("hapod_right_vectors: ldw below the number of snapshots");
+    return HAPOD_E_INVALID;
+  }
+  const int64_t Nr = P->rank[P->root];
+  if (Nr <= 0) return HAPOD_OK;
+  // Def. 3.9: Lambda~_rho = diag(Lambda~_beta) Lambda_rho, Lambda_alpha the
+  // node's right singular vectors (its eigenvectors V[:, :N]) or the identity
+  // for eps = 0.  Top-down: T_rho = I (N_rho x N_rho); a child beta whose
+  // modes are input columns [c, c + N_beta) of alpha gets
+  // T_beta = Lambda_alpha[c : c + N_beta, :] T_alpha; a leaf gamma's rows of
+  // W are Lambda_gamma T_gamma.
+  struct View {
+    const double* p;
+    int64_t ld;
+  };
+  std::vector<void*> owned;
+  auto cleanup = [&]() {
+    (void)hipStreamSynchronize(stream);
+    for (void* q : owned) P->pool.free(q);
+  };
+  auto alloc_T = [&](int64_t rows, double** out) -> hapod_status {
+    void* q = nullptr;
+    hapod_status st = P->pool.alloc(sizeof(double) * std::max<int64_t>(rows, 1) * Nr, &q);
+    if (st != HAPOD_OK) return st;
+    owned.push_back(q);
+    *out = (double*)q;
+    return HAPOD_OK;
+  };
+  // rows of leaves below a child of rank 0 stay zero
+  if (hipMemset2DAsync(W, sizeof(double) * ldw, 0, sizeof(double) * total, (size_t)Nr, stream) != hipSuccess) {
+    set_error("hapod_right_vectors: clearing W failed");
+    return HAPOD_E_DEVICE;
+  }
+  double* Troot = nullptr;
+  hapod_status st = alloc_T(Nr, &Troot);
+  if (st == HAPOD_OK) st = launch_set_identity(Troot, Nr, Nr, stream);
+  std::vector<std::pair<int32_t, View>> stack{{P->root, View{Troot, Nr}}};
+  while (st == HAPOD_OK && !stack.empty()) {
+    const int32_t a = stack.back().first;
+    const View T = stack.back().second;
+    stack.pop_back();
+    const bool computed = P->eps[a] > 0.0;
+    const int64_t m = P->m_in[a];
+    if (computed && P->rank[a] > 0 && !P->vkeep[a]) {
+      set_error("hapod_right_vectors: eigenvectors of a node were not kept");
+      st = HAPOD_E_INVALID;
+      break;
+    }
+    if (P->children[a].empty()) {
+      double* out = W + leaf_off[a];
+      if (computed) {
+        st = launch_dgemm_nn(m, Nr, P->rank[a], P->vkeep[a], m, T.p, T.ld, out, ldw, stream);
+      } else {
+        // Lambda = I: the rows of W are T itself
+        st = (hipMemcpy2DAsync(out, sizeof(double) * ldw, T.p, sizeof(double) * T.ld, sizeof(double) * m, (size_t)Nr,
+                               hipMemcpyDeviceToDevice, stream) == hipSuccess) ? HAPOD_OK : HAPOD_E_DEVICE;
+      }
+      continue;
+    }
+    const std::vector<int32_t>& order = P->in_order[a].empty() ? P->children[a] : P->in_order[a];
+    int64_t c = 0;
+    for (int32_t b : order) {
+      const int64_t wb = P->rank[b];
+      if (wb <= 0) continue;
+      if (computed) {
+        double* Tb = nullptr;
+        st = alloc_T(wb, &Tb);
+        if (st == HAPOD_OK) st = launch_dgemm_nn(wb, Nr, P->rank[a], P->vkeep[a] + c, m, T.p, T.ld, Tb, wb, stream);
+        if (st != HAPOD_OK) break;
+        stack.push_back({b, View{Tb, wb}});
+      } else {
+        stack.push_back({b, View{T.p + c, T.ld}});  // Lambda = I: a slice of T
+      }
+      c += wb;
+    }
+  }
+  if (st != HAPOD_OK) {
+    cleanup();
+    return st;
+  }
+  cleanup();
+  return HAPOD_OK;
+}
+
 void hapod_destroy(hapod_plan_t plan) { delete plan; }
 
 hapod_status hapod_level_timing(hapod_plan_t P, int32_t level, double* ms4) {
@@ -1238,6 +1357,13 @@ hapod_status hapod_run(hapod_plan_t P, hapod_leaf_fn get_leaf, void* user, void*
   const int jmax = P->opts.jacobi_max > 0 ? std::min<int>(P->opts.jacobi_max, kJacobiMax) : 0;
   const int wave = P->opts.leaf_wave > 0 ? P->opts.leaf_wave : INT32_MAX;
   P->has_result = false;
+  for (double*& v : P->vkeep)
+    if (v) {
+      P->pool.free(v);
+      v = nullptr;
+    }
+  P->vkeep.assign(P->num_nodes, nullptr);
+  P->in_order.assign(P->num_nodes, {});
   if (P->root_U) {
     P->pool.free(P->root_U);
     P->root_U = nullptr;
@@ -1348,6 +1474,7 @@ hapod_status hapod_run(hapod_plan_t P, hapod_leaf_fn get_leaf, void* user, void*
           std::vector<int32_t> order(P->children[a]);
           if (P->opts.block_gram)
             std::stable_partition(order.begin(), order.end(), [&](int32_t b) { return P->eps[b] == 0.0; });
+          P->in_order[a] = order;
           for (int32_t b : order) {
             if (deferred[b]) {
               group_fetched = true;
@@ -1394,6 +1521,7 @@ hapod_status hapod_run(hapod_plan_t P, hapod_leaf_fn get_leaf, void* user, void*
             j.sblk.push_back({bb.first, bb.first + len});
           }
         }
+        j.keep_v = P->opts.right_vectors != 0;
         j.cols = std::move(in);
         j.rbs = std::move(in_rbs);
         j.crows = std::move(in_rows);
@@ -1414,6 +1542,8 @@ hapod_status hapod_run(hapod_plan_t P, hapod_leaf_fn get_leaf, void* user, void*
       if (s != HAPOD_OK) {
         (void)hipStreamSynchronize(stream);
         if (blk) P->pool.free(blk);
+        for (auto& jj : jobs)
+          if (jj.vkeep) P->pool.free(jj.vkeep);
         release_all();
         return s;
       }
@@ -1422,6 +1552,7 @@ hapod_status hapod_run(hapod_plan_t P, hapod_leaf_fn get_leaf, void* user, void*
         const PodJob& j = jobs[k];
         P->rank[a] = j.rank;
         P->sigma[a] = j.sigma;
+        P->vkeep[a] = j.vkeep;
         P->lam1[a] = j.info[1];
         P->lam_min[a] = j.info[2];
         P->n_neg[a] = (int64_t)j.info[3];

@@ -206,6 +206,11 @@ hapod_status launch_copy_cols(int elem_bytes, int64_t n, int64_t m, const void* 
                               const int64_t* rbs, const int64_t* crows, void* out, int64_t ldo,
                               hipStream_t stream);
 hapod_status launch_zero_bytes(void* p, size_t bytes, hipStream_t stream);
+// C = A B (column-major FP64, M x K times K x N; ld >= rows)
+hapod_status launch_dgemm_nn(int64_t M, int64_t N, int64_t K, const double* A, int64_t lda, const double* B,
+                             int64_t ldb, double* C, int64_t ldc, hipStream_t stream);
+// T = I (n x n, ld ld)
+hapod_status launch_set_identity(double* T, int64_t n, int64_t ld, hipStream_t stream);
 hapod_status launch_check_diag(const double* G, int64_t ldg, int64_t m, int32_t* d_flag,
                                hipStream_t stream);
 hapod_status launch_set_scalar_i64(int64_t* p, int64_t v, hipStream_t stream);

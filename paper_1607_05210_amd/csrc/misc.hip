@@ -110,6 +110,34 @@ __global__ void copy_diag_kernel(const double* W, int64_t ldw, int64_t N, double
   if (k < N) R[k * ldr + k] = W[k * ldw + k];
 }
 
+// C = A B, column-major FP64 (M x K times K x N), 16 x 16 tiles through LDS;
+// for the small products that compose right singular vectors.
+__global__ __launch_bounds__(256) void dgemm_nn_kernel(int64_t M, int64_t N, int64_t K, const double* __restrict__ A,
+                                                       int64_t lda, const double* __restrict__ B, int64_t ldb,
+                                                       double* __restrict__ C, int64_t ldc) {
+  __shared__ double As[16][17], Bs[16][17];
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  const int64_t row = (int64_t)blockIdx.x * 16 + tx, col = (int64_t)blockIdx.y * 16 + ty;
+  double acc = 0.0;
+  for (int64_t k0 = 0; k0 < K; k0 += 16) {
+    const int64_t ka = k0 + ty, kb = k0 + tx;
+    As[ty][tx] = (row < M && ka < K) ? A[ka * lda + row] : 0.0;
+    Bs[ty][tx] = (kb < K && col < N) ? B[col * ldb + kb] : 0.0;
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 16; ++k) acc += As[k][tx] * Bs[ty][k];
+    __syncthreads();
+  }
+  if (row < M && col < N) C[col * ldc + row] = acc;
+}
+
+__global__ void set_identity_kernel(double* T, int64_t n, int64_t ld) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * n) return;
+  const int64_t i = e % n, j = e / n;
+  T[j * ld + i] = (i == j) ? 1.0 : 0.0;
+}
+
 }  // namespace
 
 hapod_status launch_fill_colptrs(const void* base, int64_t ld, int64_t m, int elem_bytes,
@@ -190,6 +218,22 @@ hapod_status launch_chol_inv(double* W, int64_t ldw, int64_t N, double* Rinv, in
   hipLaunchKernelGGL(copy_diag_kernel, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, stream, W, ldw, N, Rinv,
                      ldr);
   hipLaunchKernelGGL(chol_inv_kernel, dim3(1), dim3(256), 0, stream, W, ldw, N, Rinv, ldr, d_bad);
+  HAPOD_HIP(hipGetLastError());
+  return HAPOD_OK;
+}
+
+hapod_status launch_dgemm_nn(int64_t M, int64_t N, int64_t K, const double* A, int64_t lda, const double* B,
+                             int64_t ldb, double* C, int64_t ldc, hipStream_t stream) {
+  if (M <= 0 || N <= 0) return HAPOD_OK;
+  const dim3 g((unsigned)((M + 15) / 16), (unsigned)((N + 15) / 16));
+  hipLaunchKernelGGL(dgemm_nn_kernel, g, dim3(256), 0, stream, M, N, K, A, lda, B, ldb, C, ldc);
+  HAPOD_HIP(hipGetLastError());
+  return HAPOD_OK;
+}
+
+hapod_status launch_set_identity(double* T, int64_t n, int64_t ld, hipStream_t stream) {
+  if (n <= 0) return HAPOD_OK;
+  hipLaunchKernelGGL(set_identity_kernel, dim3((unsigned)((n * n + 255) / 256)), dim3(256), 0, stream, T, n, ld);
   HAPOD_HIP(hipGetLastError());
   return HAPOD_OK;
 }

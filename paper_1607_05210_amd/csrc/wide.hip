@@ -93,6 +93,7 @@ struct LzNode {
   double* xbuf;    // cooperative kernel: three exchange buffers of xlen doubles
   unsigned* bar;   // cooperative kernel: barrier counter (zeroed per launch)
   int64_t xlen;
+  double* Z2;      // k x k: the eigenvectors between the two orthogonalisation sweeps
 };
 
 // q = random, unnormalised (normalised by the finish kernel)
@@ -897,6 +898,59 @@ __global__ __launch_bounds__(64) void inviter_kernel(const LzNode* __restrict__ 
 #undef PIV
 }
 
+// Inverse iteration leaves each z_v off by about u |T| / gap along the
+// eigenvectors of nearby eigenvalues, so vectors of close but unequal
+// eigenvalues overlap far above the rounding level (a sine/cosine pair of a
+// wave-like snapshot set: ~1e-8).  One sweep replaces every z_v at once by
+// z_v - sum_{c < v} (z_c . z_v) z_c, normalised, with the z_c of the sweep's
+// input (eigenvalues descending, so the larger eigenvalue's vector leads);
+// an overlap e drops to O(e^2), and two sweeps reach the rounding level.
+// Each vector's correction is a combination of vectors of nearby
+// eigenvalues (the overlaps with the rest are already at rounding level),
+// so the residuals stay as they are.  One workgroup per vector; pass 0 reads
+// Z and writes Z2, pass 1 reads Z2, writes Z and refreshes last[].
+__global__ __launch_bounds__(256) void ortho_sweep_kernel(const LzNode* __restrict__ nodes, int pass) {
+  const LzNode n = nodes[blockIdx.z];
+  const int k = n.kk;
+  const int v = blockIdx.x;
+  if (v >= k) return;
+  const double* __restrict__ src = pass == 0 ? n.Z : n.Z2;
+  double* __restrict__ dst = pass == 0 ? n.Z2 : n.Z;
+  const int64_t ldz = k;
+  extern __shared__ double osh[];
+  double* zv = osh;      // k
+  double* d = osh + k;   // v overlaps
+  __shared__ double red[4];
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  for (int r = t; r < k; r += 256) zv[r] = src[(int64_t)r * ldz + v];
+  __syncthreads();
+  for (int c = t; c < v; c += 256) {
+    double s = 0.0;
+    for (int r = 0; r < k; ++r) s += src[(int64_t)r * ldz + c] * zv[r];
+    d[c] = s;
+  }
+  __syncthreads();
+  // row r of the correction: sum_c Z[r, c] d[c], one wave per row
+  for (int r = wv; r < k; r += 4) {
+    double s = 0.0;
+    for (int c = lane; c < v; c += 64) s += src[(int64_t)r * ldz + c] * d[c];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    if (lane == 0) zv[r] -= s;
+  }
+  __syncthreads();
+  double nrm = 0.0;
+  for (int r = t; r < k; r += 256) nrm += zv[r] * zv[r];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) nrm += __shfl_xor(nrm, off, 64);
+  if (lane == 0) red[wv] = nrm;
+  __syncthreads();
+  nrm = red[0] + red[1] + red[2] + red[3];
+  const double inv = nrm > 0.0 ? 1.0 / sqrt(nrm) : 0.0;
+  for (int r = t; r < k; r += 256) dst[(int64_t)r * ldz + v] = zv[r] * inv;
+  if (pass == 1 && t == 0) n.last[v] = zv[k - 1] * inv;
+}
+
 // make the largest-magnitude entry of every column positive (one wave per column)
 __global__ __launch_bounds__(256) void sign_fix_kernel(const LzNode* __restrict__ nodes) {
   const LzNode n = nodes[blockIdx.z];
@@ -997,6 +1051,7 @@ hapod_status wide_eigh_batch(std::vector<WideJob>& jobs, double u_p, wide_alloc_
     double* e2 = nullptr;  // bisection works in LDS
     double* Z = (double*)take(sizeof(double) * (size_t)k * k);
     double* last = (double*)take(sizeof(double) * k);
+    double* Z2 = (double*)take(sizeof(double) * (size_t)k * k);
     double* isc = nullptr;  // inverse iteration works in LDS
     int* ipiv = nullptr;
     double* tr = (double*)take(sizeof(double));
@@ -1022,6 +1077,7 @@ hapod_status wide_eigh_batch(std::vector<WideJob>& jobs, double u_p, wide_alloc_
       nd->coop_p = coop[i] ? cp : 0;
       nd->xbuf = xbuf;
       nd->xlen = xlen;
+      nd->Z2 = Z2;
     }
     kmax[i] = k;
     nrc[i] = nr;
@@ -1233,6 +1289,11 @@ hapod_status wide_eigh_batch(std::vector<WideJob>& jobs, double u_p, wide_alloc_
   hipLaunchKernelGGL(inviter_kernel, dim3((unsigned)kk_max, 1, nn), dim3(64),
                      (sizeof(double) * 5 + sizeof(int)) * (size_t)kk_max, stream, dn);
   HAPOD_HIP(hipGetLastError());
+  for (int pass = 0; pass < 2; ++pass) {
+    hipLaunchKernelGGL(ortho_sweep_kernel, dim3((unsigned)kk_max, 1, nn), dim3(256),
+                       sizeof(double) * 2 * (size_t)kk_max, stream, dn, pass);
+    HAPOD_HIP(hipGetLastError());
+  }
   // ---- choose each converged leading block (host) ----------------------------------
   std::vector<std::vector<double>> th(nn), lz(nn), bet(nn);
   for (int i = 0; i < nn; ++i) {

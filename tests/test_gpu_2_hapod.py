@@ -410,3 +410,70 @@ def test_split_twins_in_groups_match_single_arena(hp, monkeypatch):
     assert list(r1) == list(r3)
     np.testing.assert_array_equal(s1, s3)
     np.testing.assert_array_equal(U1, U3)
+
+
+def _right_vector_case(name):
+    if name == "star":
+        n = 2048
+        S = synth.sinusoid(n, 256, 90, 6.0, 1e-9, seed=21)
+        parent = synth.star_tree(5)
+        data = dict(enumerate(split_cols(S, [64] * 4)))
+        data[4] = np.zeros((n, 16))  # a leaf of rank 0: its rows of W are zero
+        return parent, data, n, 1e-4, 0.5, (), {}
+    if name in ("chain", "chain_block"):
+        n, chunks, cols = 2048, 5, 48
+        S = synth.bumps(n, chunks * cols, seed=5)
+        parent, chunk = synth.chain_tree(chunks)
+        blocks = split_cols(S, [cols] * chunks)
+        data = {leaf: blocks[c] for leaf, c in chunk.items()}
+        zero = tuple(b for b in chunk if b != 0)
+        eps_star = 1e-3 * math.sqrt(np.mean(np.sum(S * S, axis=0)))
+        return parent, data, n, eps_star, 0.75, zero, {"block_gram": name == "chain_block"}
+    n, leaves, per = 1500, 27, 12
+    S = synth.sinusoid(n, leaves * per, 60, 8.0, 1e-10, seed=9)
+    parent = synth.balanced_tree(leaves, 4)
+    return parent, dict(enumerate(split_cols(S, [per] * leaves))), n, 1e-4, 0.5, (), {}
+
+
+@pytest.mark.parametrize("name", ["star", "chain", "chain_block", "balanced"])
+def test_right_singular_vectors(hp, name):
+    """Rem. 3.8 / Def. 3.9: W composed on the device from the nodes' kept
+    eigenvectors.  Pinned three ways: W^T W = I (Lem. 3.10); U diag(sigma) =
+    S~ W, which the method of snapshots makes hold to rounding at every node
+    and hence for the composition; the squared Frobenius error of
+    U diag(sigma) W^T at most the sum of eps(gamma)^2.  Against the oracle's
+    factorisation: the span of the resolved columns of W."""
+    from oracle import factor
+    print(f"right vectors {name}", flush=True)
+    parent, data, n, eps_star, omega, zero, kw = _right_vector_case(name)
+    plan, sig, U, ref, eps, leaf_cols, data64 = run_both(hp, parent, data, n, eps_star, omega, "fp64", zero=zero,
+                                                         reorth=False, right_vectors=True, **kw)
+    W = host(plan.right_vectors())
+    S = np.hstack([data64[k] for k in sorted(data)])
+    N = len(sig)
+    assert W.shape == (S.shape[1], N)
+    assert metrics.orthonormality_error(W) <= 1e-10
+    norm_s = np.linalg.norm(S)
+    assert np.linalg.norm(U * sig - S @ W) <= 1e-10 * norm_s
+    err2 = np.linalg.norm(S - (U * sig) @ W.T) ** 2
+    assert err2 <= sum(e * e for e in eps) * (1 + 1e-6) + metrics.rounding_slack(S)
+    if name == "star":
+        np.testing.assert_array_equal(W[256:], 0.0)
+    root = tree.validate(parent)
+    fac = factor.hapod_factor(parent, data64, eps)
+    W_ref = factor.rows_in_leaf_order(fac[root][2], fac[root][3])
+    assert W_ref.shape[1] == len(ref[root][0])
+    r = metrics.resolved_rank(ref[root][0], N, UP["fp64"], TAU["fp64"])
+    assert r >= 10
+    assert metrics.subspace_error(W_ref, W, r) <= TAU["fp64"]
+    print(f"  N {N} (oracle {W_ref.shape[1]}), r {r}, err^2/bound {err2 / sum(e * e for e in eps):.3f}")
+
+
+def test_right_vectors_need_the_option(hp):
+    S = synth.sinusoid(256, 16, 10, 5.0, 0.0, seed=3)
+    plan = hp.Plan(synth.star_tree(2), [8, 8, 0], 256, 1e-3, 0.5, prec="fp64")
+    with pytest.raises(hp.HapodError):
+        plan.right_vectors()  # no run yet
+    plan.run({0: dev_colmajor(S[:, :8]), 1: dev_colmajor(S[:, 8:])})
+    with pytest.raises(hp.HapodError):
+        plan.right_vectors()  # plan made without right_vectors
