@@ -143,6 +143,30 @@ hapod_status hapod_node_pod(hapod_precision prec, int64_t n, int64_t m,
                             void* out, int64_t ldo, double* sigma, int64_t* rank,
                             void* stream);
 
+/* One local POD(S, eps) (Def. 2.5) without the method of snapshots' Gram
+ * eigenproblem, whose squared condition number (Rem. 2.3) limits the
+ * singular values to about sqrt(u) sigma_1 (absolute): S = Q R by
+ * Cholesky-QR passes Q <- Q R_p^-1, each shifted (Q^T Q + s I = R_p^T R_p
+ * with s = 11 (n m + m (m + 1)) u trace(Q^T Q), Fukaya et al., SIAM J. Sci.
+ * Comput. 2020) while m max|Q^T Q - I| > 1/2, until two plain passes
+ * follow each other; the SVD R V = U_R diag(sigma) by one-sided Jacobi;
+ * the modes Q U_R.  The sigma_k are accurate to about u sigma_1,
+ * rank-deficient S included.
+ * FP64 only; m <= 512 and m <= n (HAPOD_E_UNSUPPORTED otherwise, eps > 0).
+ *   S, lds, eps, scaled, out, ldo, sigma, rank   as hapod_node_pod (double).
+ *   passes  host, may be NULL: Cholesky-QR passes taken (3 for a
+ *           well-conditioned S, up to about 7 at condition 1e14 or rank
+ *           loss).
+ *   sweeps  host, may be NULL: Jacobi sweeps taken.
+ * HAPOD_E_NUMERIC: a pivot was not positive (non-finite input), or no
+ * orthonormal Q in 12 passes, or no Jacobi convergence in 60 sweeps.
+ * Scratch: two n x m double buffers and a few m x m ones from the library's
+ * pool.  Synchronises the stream (twice per pass).                         */
+hapod_status hapod_node_pod_qr(int64_t n, int64_t m, const double* S, int64_t lds,
+                               double eps, int32_t scaled, double* out, int64_t ldo,
+                               double* sigma, int64_t* rank, int32_t* passes,
+                               int32_t* sweeps, void* stream);
+
 /* ------------------------------------------------------------------------ */
 /* Tree-level entry points.                                                 */
 /* ------------------------------------------------------------------------ */

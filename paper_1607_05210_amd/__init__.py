@@ -60,6 +60,7 @@ _SIGS = {
     "hapod_modes": [_vp, _i32, _vp, _i64, _pdbl, _pi64, _vp],
     "hapod_node_stats": [_vp, _pi64, _pi64, _pdbl, _pdbl],
     "hapod_right_vectors": [_vp, _vp, _i64, _vp],
+    "hapod_node_pod_qr": [_i64, _i64, _vp, _i64, C.c_double, _i32, _vp, _i64, _pdbl, _pi64, _pi32, _pi32, _vp],
     "hapod_run_timing": [_vp, _pdbl],
     "hapod_level_timing": [_vp, _i32, _pdbl],
 }
@@ -197,6 +198,24 @@ def hapod_node_pod(prec, S, eps, scaled=False, out=None, stream=None):
     _check(_lib.hapod_node_pod(prec, n, m, ps, lds, float(eps), int(bool(scaled)), po, ldo,
                                sig.ctypes.data_as(_pdbl), C.byref(r), _stream(stream)), "hapod_node_pod")
     return sig[:r.value].copy(), out[:, :r.value]
+
+
+def hapod_node_pod_qr(S, eps, scaled=False, out=None, stream=None):
+    """POD(S, eps) from a QR factor of S (FP64): returns (sigma[rank] numpy,
+    out[:, :rank], {"passes": Cholesky-QR passes, "sweeps": Jacobi sweeps})."""
+    import numpy as np
+    ps, n, m, lds = _mat(S, "S", torch.float64)
+    if out is None:
+        out = colmajor(n, m, torch.float64, S.device)
+    po, _, _, ldo = _mat(out, "out", torch.float64)
+    sig = np.zeros(max(m, 1))
+    r = C.c_int64(0)
+    npass = C.c_int32(0)
+    sw = C.c_int32(0)
+    _check(_lib.hapod_node_pod_qr(n, m, ps, lds, float(eps), int(bool(scaled)), po, ldo,
+                                  sig.ctypes.data_as(_pdbl), C.byref(r), C.byref(npass), C.byref(sw),
+                                  _stream(stream)), "hapod_node_pod_qr")
+    return sig[:r.value].copy(), out[:, :r.value], {"passes": npass.value, "sweeps": sw.value}
 
 
 # ---------------------------------------------------------------------------

@@ -2155,4 +2155,179 @@ hapod_status hapod_node_pod(hapod_precision prec, int64_t n, int64_t m, const vo
   return HAPOD_OK;
 }
 
+hapod_status hapod_node_pod_qr(int64_t n, int64_t m, const double* S, int64_t lds, double eps, int32_t scaled,
+                               double* out, int64_t ldo, double* sigma, int64_t* rank, int32_t* passes,
+                               int32_t* sweeps, void* stream_) {
+  if (n < 0 || m < 0 || !(eps >= 0.0) || !rank || lds < std::max<int64_t>(n, 1) || ldo < std::max<int64_t>(n, 1) ||
+      (n > 0 && m > 0 && (!S || !out))) {
+    set_error("hapod_node_pod_qr: bad argument");
+    return HAPOD_E_INVALID;
+  }
+  if (m > kQrMaxM) {
+    set_error("hapod_node_pod_qr: m above 512");
+    return HAPOD_E_UNSUPPORTED;
+  }
+  if (m > n && eps > 0.0) {
+    set_error("hapod_node_pod_qr: more columns than rows (no orthonormal Q of m columns)");
+    return HAPOD_E_UNSUPPORTED;
+  }
+  hipStream_t stream = (hipStream_t)stream_;
+  if (sweeps) *sweeps = 0;
+  if (passes) *passes = 0;
+  if (eps == 0.0) {  // POD(S, 0) = {(1, s)}
+    if (n > 0 && m > 0)
+      HAPOD_HIP(hipMemcpy2DAsync(out, ldo * 8, S, lds * 8, n * 8, m, hipMemcpyDeviceToDevice, stream));
+    HAPOD_HIP(hipStreamSynchronize(stream));
+    *rank = m;
+    if (sigma)
+      for (int64_t i = 0; i < m; ++i) sigma[i] = 1.0;
+    return HAPOD_OK;
+  }
+  *rank = 0;
+  if (m == 0 || n == 0) return HAPOD_OK;
+  Pool& pool = step_pool();
+  const size_t mm = sizeof(double) * (size_t)m * m;
+  void *G = nullptr, *Rinv = nullptr, *Rk = nullptr, *Racc = nullptr, *Rtmp = nullptr, *Bm = nullptr, *dsig = nullptr,
+       *QA = nullptr, *QB = nullptr, *dcols = nullptr, *dn = nullptr, *drank = nullptr, *dbad = nullptr,
+       *drbs = nullptr, *drows = nullptr, *dinfo = nullptr;
+  std::vector<void*> held;
+  auto finish = [&](hapod_status st) {
+    (void)hipStreamSynchronize(stream);
+    for (void* q : held) pool.free(q);
+    return st;
+  };
+  const std::pair<size_t, void**> want[] = {
+      {mm, &G}, {mm, &Rinv}, {mm, &Rk}, {mm, &Racc}, {mm, &Rtmp}, {mm, &Bm}, {sizeof(double) * 2 * m, &dsig},
+      {sizeof(double) * (size_t)n * m, &QA}, {sizeof(double) * (size_t)n * m, &QB},
+      {sizeof(void*) * (kQrMaxPasses + 1) * m, &dcols}, {sizeof(LiftNode) * (kQrMaxPasses + 1), &dn},
+      {sizeof(int64_t), &drank}, {sizeof(int32_t) * kQrMaxPasses, &dbad}, {sizeof(int64_t) * m, &drbs},
+      {sizeof(int64_t) * m, &drows}, {sizeof(int32_t), &dinfo}};
+  for (const auto& w : want) {
+    hapod_status st = pool.alloc(w.first, w.second);
+    if (st != HAPOD_OK) return finish(st);
+    held.push_back(*w.second);
+  }
+  hapod_status st = HAPOD_OK;
+  if ((st = launch_fill_i64((int64_t*)drbs, kRowBlock, m, stream)) != HAPOD_OK ||
+      (st = launch_fill_i64((int64_t*)drows, n, m, stream)) != HAPOD_OK)
+    return finish(st);
+  // the lift operands of the three passes and of the modes, uploaded from
+  // host tables that live until the end of the call
+  std::vector<std::vector<const void*>> tables(kQrMaxPasses + 1);
+  std::vector<LiftNode> lifts(kQrMaxPasses + 1);
+  auto lift = [&](int slot, const double* src, int64_t ld, const double* B, int64_t N, double* dst,
+                  int64_t ldd) -> hapod_status {
+    tables[slot] = column_table(src, ld, m, 8);
+    LiftNode& l = lifts[slot];
+    l = LiftNode{};
+    l.cols = (const void* const*)dcols + (size_t)slot * m;
+    l.rbs = (const int64_t*)drbs;
+    l.crows = (const int64_t*)drows;
+    l.B = B;
+    l.rank = (const int64_t*)drank;
+    l.out = dst;
+    l.n = n;
+    l.ldb = m;
+    l.ocs = ldd;
+    l.obs = kRowBlock;
+    l.m = (int32_t)m;
+    l.row_tiles = (int32_t)((n + kLiftTileM - 1) / kLiftTileM);
+    l.col_tiles = (int32_t)((N + kLiftTileN - 1) / kLiftTileN);
+    if (hipMemcpyAsync((void*)l.cols, tables[slot].data(), sizeof(void*) * m, hipMemcpyHostToDevice, stream) !=
+            hipSuccess ||
+        hipMemcpyAsync((LiftNode*)dn + slot, &l, sizeof(l), hipMemcpyHostToDevice, stream) != hipSuccess) {
+      set_error("hapod_node_pod_qr: upload failed");
+      return HAPOD_E_DEVICE;
+    }
+    hapod_status s2 = launch_set_scalar_i64((int64_t*)drank, N, stream);
+    if (s2 != HAPOD_OK) return s2;
+    return launch_lift(0, (const LiftNode*)dn + slot, 1, l.row_tiles * l.col_tiles, stream);
+  };
+  // Cholesky-QR passes Q <- Q R_p^-1 (Q = S first), R = ... R_2 R_1, so that
+  // S = Q R holds to rounding after every pass.  A pass whose Q^T Q is not
+  // within 1/2 of the identity by Gershgorin (m max |Q^T Q - I| > 1/2) is
+  // shifted: Q^T Q + s I = R_p^T R_p, s = 11 (n m + m (m + 1)) u tr(Q^T Q),
+  // the shift of shifted Cholesky-QR (tr >= ||Q||_2^2), which lifts the
+  // directions S nearly lacks by about s^-1/2 per pass; the others are
+  // plain.  Two plain passes in a row leave Q orthonormal to rounding.
+  const double u = 1.1102230246251565e-16;
+  const double* src = S;
+  int64_t ld = lds;
+  double* dst = (double*)QA;
+  double* d_dev = (double*)dsig;
+  int plain_run = 0, pass = 0;
+  for (; pass < kQrMaxPasses && plain_run < 2; ++pass) {
+    if ((st = gram_impl(0, 8, n, m, src, ld, (double*)G, m, stream)) != HAPOD_OK ||
+        (st = launch_identity_dev((double*)G, m, m, d_dev, stream)) != HAPOD_OK)
+      return finish(st);
+    double dev = 0.0;
+    if (hipMemcpyAsync(&dev, d_dev, sizeof(double), hipMemcpyDeviceToHost, stream) != hipSuccess ||
+        hipStreamSynchronize(stream) != hipSuccess) {
+      set_error("hapod_node_pod_qr: readback failed");
+      return finish(HAPOD_E_DEVICE);
+    }
+    const bool shifted = !((double)m * dev <= 0.5);
+    if (shifted &&
+        (st = launch_shift_diag((double*)G, m, m, 11.0 * ((double)n * m + (double)m * (m + 1)) * u, stream)) != HAPOD_OK)
+      return finish(st);
+    if ((st = launch_chol_inv((double*)G, m, m, (double*)Rinv, m, (int32_t*)dbad + pass, stream, 0.0)) != HAPOD_OK ||
+        (st = launch_triu((double*)G, m, m, pass == 0 ? (double*)Racc : (double*)Rk, m, stream)) != HAPOD_OK)
+      return finish(st);
+    if (pass > 0) {
+      if ((st = launch_dgemm_nn(m, m, m, (double*)Rk, m, (double*)Racc, m, (double*)Rtmp, m, stream)) != HAPOD_OK)
+        return finish(st);
+      std::swap(Racc, Rtmp);
+    }
+    if ((st = lift(pass, src, ld, (double*)Rinv, m, dst, n)) != HAPOD_OK) return finish(st);
+    src = dst;
+    ld = n;
+    dst = (dst == (double*)QA) ? (double*)QB : (double*)QA;
+    int32_t bad = 0;
+    if (hipMemcpyAsync(&bad, (int32_t*)dbad + pass, sizeof(bad), hipMemcpyDeviceToHost, stream) != hipSuccess ||
+        hipStreamSynchronize(stream) != hipSuccess) {
+      set_error("hapod_node_pod_qr: readback failed");
+      return finish(HAPOD_E_DEVICE);
+    }
+    if (bad) {
+      set_error("hapod_node_pod_qr: a Cholesky pivot was not positive (non-finite input?)");
+      return finish(HAPOD_E_NUMERIC);
+    }
+    plain_run = shifted ? 0 : plain_run + 1;
+  }
+  if (plain_run < 2) {
+    set_error("hapod_node_pod_qr: Cholesky-QR did not reach an orthonormal factor in 12 passes");
+    return finish(HAPOD_E_NUMERIC);
+  }
+  if (passes) *passes = pass;
+  // one-sided Jacobi SVD of R: R V = U_R diag(sigma); B = U_R (diag(sigma))
+  if ((st = launch_osj((double*)Racc, m, (double*)dsig, (double*)Bm, scaled ? 1 : 0, (int32_t*)dinfo, stream)) !=
+      HAPOD_OK)
+    return finish(st);
+  int32_t info = 0;
+  std::vector<double> sg((size_t)m);
+  if (hipMemcpyAsync(&info, dinfo, sizeof(info), hipMemcpyDeviceToHost, stream) != hipSuccess ||
+      hipMemcpyAsync(sg.data(), dsig, sizeof(double) * m, hipMemcpyDeviceToHost, stream) != hipSuccess ||
+      hipStreamSynchronize(stream) != hipSuccess) {
+    set_error("hapod_node_pod_qr: readback failed");
+    return finish(HAPOD_E_DEVICE);
+  }
+  if (info < 0) {
+    set_error("hapod_node_pod_qr: the Jacobi SVD did not converge");
+    return finish(HAPOD_E_NUMERIC);
+  }
+  if (sweeps) *sweeps = info;
+  // Def. 2.5: the smallest N whose discarded squared singular values sum to at most eps^2
+  int64_t N = m;
+  double tail = 0.0;
+  const double e2 = eps * eps;
+  while (N > 0 && tail + sg[(size_t)N - 1] * sg[(size_t)N - 1] <= e2) {
+    tail += sg[(size_t)N - 1] * sg[(size_t)N - 1];
+    --N;
+  }
+  if (N > 0 && (st = lift(3, src, ld, (const double*)Bm, N, out, ldo)) != HAPOD_OK) return finish(st);
+  *rank = N;
+  if (sigma && N > 0) std::memcpy(sigma, sg.data(), sizeof(double) * N);
+  return finish(HAPOD_OK);
+}
+
 }  // extern "C"

@@ -224,6 +224,23 @@ hapod_status launch_split_cols(int64_t n, int64_t m, const void* const* cols, co
 
 // ---- Cholesky-QR re-orthonormalisation -------------------------------------
 hapod_status launch_chol_inv(double* W, int64_t ldw, int64_t N, double* Rinv, int64_t ldr,
-                             int32_t* d_bad, hipStream_t stream);
+                             int32_t* d_bad, hipStream_t stream, double rel_floor = 1e-12);
+
+// ---- accuracy-preserving local POD (qr.hip) -------------------------------------
+constexpr int64_t kQrMaxM = 512;     // widest node of the QR-based POD
+constexpr int64_t kOsjLdsMaxM = 128; // the Jacobi SVD keeps R in LDS up to this width
+constexpr int kQrMaxPasses = 12;     // Cholesky-QR passes before giving up
+// G[k][k] += coef * trace(G)
+hapod_status launch_shift_diag(double* G, int64_t ldg, int64_t m, double coef, hipStream_t stream);
+// out[0] = max over the upper triangle of |G_ij - delta_ij|
+hapod_status launch_identity_dev(const double* G, int64_t ldg, int64_t m, double* out, hipStream_t stream);
+// R = upper triangle of W, zeros below (both column-major)
+hapod_status launch_triu(const double* W, int64_t ldw, int64_t N, double* R, int64_t ldr, hipStream_t stream);
+// one-sided Jacobi SVD of A (m x m, column-major, ld m, overwritten): sigma
+// (device, m, descending), B (device, row-major m x m): column p is the
+// p-th left singular vector times sigma_p (scaled) or alone; info[0] =
+// sweeps taken or -1 without convergence
+hapod_status launch_osj(double* A, int64_t m, double* sigma, double* B, int scaled, int32_t* info,
+                        hipStream_t stream);
 
 }  // namespace hapod

@@ -55,10 +55,11 @@ __global__ void fill_i64_kernel(int64_t* p, int64_t v, int64_t count) {
 }
 
 // W (N x N, symmetric, upper used) = R^T R in place (upper R), then Rinv =
-// R^{-1} (upper, row-major).  A pivot <= 1e-12 of its original diagonal marks the column
-// as dependent: its row of R becomes e_k (the column is left unchanged).
+// R^{-1} (upper, row-major).  A pivot <= rel_floor of its original diagonal
+// (or not positive) marks the column as dependent: its row of R becomes e_k
+// (the column is left unchanged).
 __global__ __launch_bounds__(256) void chol_inv_kernel(double* W, int64_t ldw, int64_t N, double* Rinv,
-                                                       int64_t ldr, int32_t* bad) {
+                                                       int64_t ldr, int32_t* bad, double rel_floor) {
   __shared__ double piv;
   __shared__ int nbad;
   const int tid = threadIdx.x;
@@ -69,7 +70,7 @@ __global__ __launch_bounds__(256) void chol_inv_kernel(double* W, int64_t ldw, i
       const double d = W[k * ldw + k];
       // the original diagonal of column k is kept in Rinv's diagonal slot
       const double d0 = Rinv[k * ldr + k];
-      if (!(d > 1e-12 * d0) || !isfinite(d)) {
+      if (!(d > rel_floor * d0) || !(d > 0.0) || !isfinite(d)) {
         piv = 0.0;
         ++nbad;
       } else {
@@ -213,11 +214,11 @@ hapod_status launch_split_cols(int64_t n, int64_t m, const void* const* cols, co
 }
 
 hapod_status launch_chol_inv(double* W, int64_t ldw, int64_t N, double* Rinv, int64_t ldr, int32_t* d_bad,
-                             hipStream_t stream) {
+                             hipStream_t stream, double rel_floor) {
   if (N <= 0) return HAPOD_OK;
   hipLaunchKernelGGL(copy_diag_kernel, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, stream, W, ldw, N, Rinv,
                      ldr);
-  hipLaunchKernelGGL(chol_inv_kernel, dim3(1), dim3(256), 0, stream, W, ldw, N, Rinv, ldr, d_bad);
+  hipLaunchKernelGGL(chol_inv_kernel, dim3(1), dim3(256), 0, stream, W, ldw, N, Rinv, ldr, d_bad, rel_floor);
   HAPOD_HIP(hipGetLastError());
   return HAPOD_OK;
 }
