@@ -230,6 +230,9 @@ hapod_status launch_chol_inv(double* W, int64_t ldw, int64_t N, double* Rinv, in
 constexpr int64_t kQrMaxM = 512;     // widest node of the QR-based POD
 constexpr int64_t kOsjLdsMaxM = 128; // the Jacobi SVD keeps R in LDS up to this width
 constexpr int kQrMaxPasses = 12;     // Cholesky-QR passes before giving up
+constexpr int kCholLdsMaxN = 128;    // launch_chol_inv keeps both triangles in LDS up to this N
+hapod_status launch_chol_inv_lds(double* W, int64_t ldw, int64_t N, double* Rinv, int64_t ldr, int32_t* d_bad,
+                                 hipStream_t stream, double rel_floor);
 // G[k][k] += coef * trace(G)
 hapod_status launch_shift_diag(double* G, int64_t ldg, int64_t m, double coef, hipStream_t stream);
 // out[0] = max over the upper triangle of |G_ij - delta_ij|

@@ -216,6 +216,7 @@ hapod_status launch_split_cols(int64_t n, int64_t m, const void* const* cols, co
 hapod_status launch_chol_inv(double* W, int64_t ldw, int64_t N, double* Rinv, int64_t ldr, int32_t* d_bad,
                              hipStream_t stream, double rel_floor) {
   if (N <= 0) return HAPOD_OK;
+  if (N <= kCholLdsMaxN) return launch_chol_inv_lds(W, ldw, N, Rinv, ldr, d_bad, stream, rel_floor);
   hipLaunchKernelGGL(copy_diag_kernel, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, stream, W, ldw, N, Rinv,
                      ldr);
   hipLaunchKernelGGL(chol_inv_kernel, dim3(1), dim3(256), 0, stream, W, ldw, N, Rinv, ldr, d_bad, rel_floor);

@@ -21,6 +21,8 @@ namespace {
 constexpr int kOsjThreads = 1024;
 constexpr int kOsjWaves = kOsjThreads / 64;
 constexpr int kOsjMaxSweeps = 60;
+constexpr int kOsjGroup = 16;                       // lanes per column pair
+constexpr int kOsjGroups = kOsjThreads / kOsjGroup;
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -62,10 +64,11 @@ __global__ void triu_kernel(const double* __restrict__ W, int64_t ldw, int64_t N
 
 // One-sided Jacobi on the columns of X (m x m, column-major, ld m): plane
 // rotations on column pairs until every pair is orthogonal to m u of its
-// norms; the pairs of a round are disjoint (round-robin order), one
-// wavefront per pair.  Then sigma_c = ||x_c||, sorted descending, and
-// B (row-major, ld m) column p = x_c (scaled) or x_c / sigma_c.
-// info: sweeps taken, or -1 without convergence.
+// norms; the pairs of a round are disjoint (round-robin order), a group of
+// 16 lanes per pair (four pairs per wavefront at once).  Then
+// sigma_c = ||x_c||, sorted descending, and B (row-major, ld m) column p =
+// x_c (scaled) or x_c / sigma_c.  info: sweeps taken, or -1 without
+// convergence.
 template <bool kLds>
 __global__ __launch_bounds__(kOsjThreads) void osj_kernel(double* A, int64_t m, double* sigma, double* B, int scaled,
                                                           int32_t* info) {
@@ -75,6 +78,7 @@ __global__ __launch_bounds__(kOsjThreads) void osj_kernel(double* A, int64_t m, 
   __shared__ int nrot;
   double* X = kLds ? osj_lds : A;
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const int gl = t & (kOsjGroup - 1), grp = t / kOsjGroup;
   if (kLds) {
     for (int64_t e = t; e < m * m; e += kOsjThreads) X[e] = A[e];
   }
@@ -86,7 +90,7 @@ __global__ __launch_bounds__(kOsjThreads) void osj_kernel(double* A, int64_t m, 
     if (t == 0) nrot = 0;
     __syncthreads();
     for (int64_t r = 0; r < mm - 1; ++r) {
-      for (int64_t p = wv; p < mm / 2; p += kOsjWaves) {
+      for (int64_t p = grp; p < mm / 2; p += kOsjGroups) {
         int64_t i, j;
         if (p == 0) {
           i = mm - 1;
@@ -99,27 +103,30 @@ __global__ __launch_bounds__(kOsjThreads) void osj_kernel(double* A, int64_t m, 
         double* ci = X + i * m;
         double* cj = X + j * m;
         double a = 0.0, b = 0.0, g = 0.0;
-        for (int64_t k = lane; k < m; k += 64) {
+        for (int64_t k = gl; k < m; k += kOsjGroup) {
           const double x = ci[k], y = cj[k];
           a += x * x;
           b += y * y;
           g += x * y;
         }
-        a = wave_sum(a);
-        b = wave_sum(b);
-        g = wave_sum(g);
+#pragma unroll
+        for (int off = kOsjGroup / 2; off > 0; off >>= 1) {
+          a += __shfl_xor(a, off, kOsjGroup);
+          b += __shfl_xor(b, off, kOsjGroup);
+          g += __shfl_xor(g, off, kOsjGroup);
+        }
         if (!(a > 0.0) || !(b > 0.0) || fabs(g) <= tol * sqrt(a) * sqrt(b)) continue;
         // rotation [c s; -s c] that makes the pair orthogonal, the smaller angle
         const double zeta = (b - a) / (2.0 * g);
         const double tt = fabs(zeta) > 1e150 ? 0.5 / zeta
                                              : (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
         const double c = 1.0 / sqrt(1.0 + tt * tt), s = c * tt;
-        for (int64_t k = lane; k < m; k += 64) {
+        for (int64_t k = gl; k < m; k += kOsjGroup) {
           const double x = ci[k], y = cj[k];
           ci[k] = c * x - s * y;
           cj[k] = s * x + c * y;
         }
-        if (lane == 0) atomicAdd(&nrot, 1);
+        if (gl == 0) atomicAdd(&nrot, 1);
       }
       __syncthreads();
     }
@@ -148,7 +155,96 @@ __global__ __launch_bounds__(kOsjThreads) void osj_kernel(double* A, int64_t m, 
   if (t == 0) info[0] = done ? sweep : -1;
 }
 
+// chol_inv_kernel's operation for N <= kCholLdsMaxN with both triangles in
+// LDS (column-packed upper, (i, j) at j (j + 1) / 2 + i): W = R^T R in place
+// (upper R), Rinv = R^-1 (row-major, upper); a pivot <= rel_floor of its
+// original diagonal, or not positive, marks the column as dependent (its row
+// of R becomes e_k).  Same elimination order as the global-memory kernel;
+// the inverse's dot products are split over 8 lanes.
+__global__ __launch_bounds__(1024) void chol_inv_lds_kernel(double* W, int64_t ldw, int N, double* Rinv, int64_t ldr,
+                                                            int32_t* bad, double rel_floor) {
+  extern __shared__ double ch_lds[];
+  const int np = N * (N + 1) / 2;
+  double* P = ch_lds;
+  double* Iv = ch_lds + np;
+  __shared__ double d0s[kCholLdsMaxN];
+  __shared__ double piv;
+  __shared__ int nbad;
+  const int t = threadIdx.x;
+  auto idx = [](int i, int j) { return j * (j + 1) / 2 + i; };
+  for (int e = t; e < np; e += 1024) {
+    int j = (int)((sqrtf(8.0f * (float)e + 1.0f) - 1.0f) * 0.5f);
+    while (j * (j + 1) / 2 > e) --j;
+    while ((j + 1) * (j + 2) / 2 <= e) ++j;
+    const int i = e - j * (j + 1) / 2;
+    P[e] = W[(int64_t)j * ldw + i];
+  }
+  for (int k = t; k < N; k += 1024) d0s[k] = W[(int64_t)k * ldw + k];
+  if (t == 0) nbad = 0;
+  __syncthreads();
+  for (int k = 0; k < N; ++k) {
+    if (t == 0) {
+      const double d = P[idx(k, k)];
+      if (!(d > rel_floor * d0s[k]) || !(d > 0.0) || !isfinite(d)) {
+        piv = 0.0;
+        ++nbad;
+      } else {
+        piv = sqrt(d);
+      }
+    }
+    __syncthreads();
+    const double p = piv;
+    for (int j = k + 1 + t; j < N; j += 1024) P[idx(k, j)] = (p > 0.0) ? P[idx(k, j)] / p : 0.0;
+    __syncthreads();
+    if (t == 0) P[idx(k, k)] = (p > 0.0) ? p : 1.0;
+    // trailing update of the upper triangle: (i, j), k < i <= j
+    const int rem = N - k - 1;
+    const int tot = rem * (rem + 1) / 2;
+    for (int e = t; e < tot; e += 1024) {
+      int jj = (int)((sqrtf(8.0f * (float)e + 1.0f) - 1.0f) * 0.5f);
+      while (jj * (jj + 1) / 2 > e) --jj;
+      while ((jj + 1) * (jj + 2) / 2 <= e) ++jj;
+      const int i = k + 1 + (e - jj * (jj + 1) / 2), j = k + 1 + jj;
+      P[idx(i, j)] -= P[idx(k, i)] * P[idx(k, j)];
+    }
+    __syncthreads();
+  }
+  // R^-1 row by row from the bottom: Rinv[i][j] = -(sum_{i<l<=j} R[i][l] Rinv[l][j]) / R[i][i]
+  const int sub = t & 7;
+  for (int i = N - 1; i >= 0; --i) {
+    for (int j = i + (t >> 3); j < N; j += 128) {
+      double s = 0.0;
+      for (int l = i + 1 + sub; l <= j; l += 8) s += P[idx(i, l)] * Iv[idx(l, j)];
+#pragma unroll
+      for (int off = 4; off > 0; off >>= 1) s += __shfl_xor(s, off, 8);
+      if (sub == 0) Iv[idx(i, j)] = (j == i) ? 1.0 / P[idx(i, i)] : -s / P[idx(i, i)];
+    }
+    __syncthreads();
+  }
+  for (int e = t; e < N * N; e += 1024) {
+    const int j = e / N, i = e - j * N;
+    if (i <= j) W[(int64_t)j * ldw + i] = P[idx(i, j)];
+    Rinv[(int64_t)i * ldr + j] = (i <= j) ? Iv[idx(i, j)] : 0.0;
+  }
+  if (t == 0 && bad) *bad = nbad;
+}
+
 }  // namespace
+
+hapod_status launch_chol_inv_lds(double* W, int64_t ldw, int64_t N, double* Rinv, int64_t ldr, int32_t* d_bad,
+                                 hipStream_t stream, double rel_floor) {
+  if (N <= 0) return HAPOD_OK;
+  static bool attr = false;
+  if (!attr) {
+    HAPOD_HIP(hipFuncSetAttribute((const void*)chol_inv_lds_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)(sizeof(double) * kCholLdsMaxN * (kCholLdsMaxN + 1))));
+    attr = true;
+  }
+  hipLaunchKernelGGL(chol_inv_lds_kernel, dim3(1), dim3(1024), sizeof(double) * N * (N + 1), stream, W, ldw, (int)N,
+                     Rinv, ldr, d_bad, rel_floor);
+  HAPOD_HIP(hipGetLastError());
+  return HAPOD_OK;
+}
 
 hapod_status launch_shift_diag(double* G, int64_t ldg, int64_t m, double coef, hipStream_t stream) {
   if (m <= 0) return HAPOD_OK;
