@@ -221,6 +221,13 @@ typedef struct {
                                       0: every Gram entry computed                      */
   int32_t right_vectors;           /* 1: keep every computed node's right singular vectors
                                       (eigenvectors V[:, :N]) for hapod_right_vectors   */
+  int32_t qr_pod;                  /* 1: computed nodes of at most 512 inputs and no more
+                                      inputs than rows take the QR route of
+                                      hapod_node_pod_qr (their singular values to ~u
+                                      sigma_1); the others the method of snapshots.
+                                      FP64 only, not with right_vectors
+                                      (HAPOD_E_INVALID otherwise).  A QR node's time
+                                      counts as Gram time in the phase timings.        */
 } hapod_options;
 
 /* Validate the tree (Def. 3.1), compute levels (height: leaves are level 1),

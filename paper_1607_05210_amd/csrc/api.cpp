@@ -12,6 +12,7 @@
 #include <memory>
 #include <mutex>
 #include <string>
+#include <functional>
 #include <vector>
 
 #include "internal.hpp"
@@ -1082,6 +1083,167 @@ struct hapod_plan_s {
   Pool pool;
 };
 
+// The QR route for one node with eps > 0, 0 < m <= kQrMaxM, m <= n, S plain
+// column-major (n x m, ld lds).  With s_scratch, S may be overwritten (it
+// serves as one of the two Q buffers).  out_for_rank(N, &out, &ocs, &obs)
+// names where the N modes go (called once N is known, N > 0).
+hapod_status qr_pod_core(Pool& pool, int64_t n, int64_t m, double* S, int64_t lds, bool s_scratch, double eps,
+                         bool scaled, const std::function<hapod_status(int64_t, double**, int64_t*, int64_t*)>& out_for_rank,
+                         std::vector<double>& sigma, int64_t* rank, int32_t* passes, int32_t* sweeps,
+                         hipStream_t stream) {
+  *rank = 0;
+  const size_t mm = sizeof(double) * (size_t)m * m;
+  void *G = nullptr, *Rinv = nullptr, *Rk = nullptr, *Racc = nullptr, *Rtmp = nullptr, *Bm = nullptr, *dsig = nullptr,
+       *QA = nullptr, *QB = nullptr, *dcols = nullptr, *dn = nullptr, *drank = nullptr, *dbad = nullptr,
+       *drbs = nullptr, *drows = nullptr, *dinfo = nullptr;
+  std::vector<void*> held;
+  auto finish = [&](hapod_status st) {
+    (void)hipStreamSynchronize(stream);
+    for (void* q : held) pool.free(q);
+    return st;
+  };
+  const std::pair<size_t, void**> want[] = {
+      {mm, &G}, {mm, &Rinv}, {mm, &Rk}, {mm, &Racc}, {mm, &Rtmp}, {mm, &Bm}, {sizeof(double) * 2 * m, &dsig},
+      {s_scratch ? 0 : sizeof(double) * (size_t)n * m, &QA}, {sizeof(double) * (size_t)n * m, &QB},
+      {sizeof(void*) * (kQrMaxPasses + 1) * m, &dcols}, {sizeof(LiftNode) * (kQrMaxPasses + 1), &dn},
+      {sizeof(int64_t), &drank}, {sizeof(int32_t) * kQrMaxPasses, &dbad}, {sizeof(int64_t) * m, &drbs},
+      {sizeof(int64_t) * m, &drows}, {sizeof(int32_t), &dinfo}};
+  for (const auto& w : want) {
+    if (w.first == 0) continue;
+    hapod_status st = pool.alloc(w.first, w.second);
+    if (st != HAPOD_OK) return finish(st);
+    held.push_back(*w.second);
+  }
+  hapod_status st = HAPOD_OK;
+  if ((st = launch_fill_i64((int64_t*)drbs, kRowBlock, m, stream)) != HAPOD_OK ||
+      (st = launch_fill_i64((int64_t*)drows, n, m, stream)) != HAPOD_OK)
+    return finish(st);
+  // the lift operands of the three passes and of the modes, uploaded from
+  // host tables that live until the end of the call
+  std::vector<std::vector<const void*>> tables(kQrMaxPasses + 1);
+  std::vector<LiftNode> lifts(kQrMaxPasses + 1);
+  auto lift = [&](int slot, const double* src, int64_t ld, const double* B, int64_t N, double* dst, int64_t ldd,
+                  int64_t obs) -> hapod_status {
+    tables[slot] = column_table(src, ld, m, 8);
+    LiftNode& l = lifts[slot];
+    l = LiftNode{};
+    l.cols = (const void* const*)dcols + (size_t)slot * m;
+    l.rbs = (const int64_t*)drbs;
+    l.crows = (const int64_t*)drows;
+    l.B = B;
+    l.rank = (const int64_t*)drank;
+    l.out = dst;
+    l.n = n;
+    l.ldb = m;
+    l.ocs = ldd;
+    l.obs = obs;
+    l.m = (int32_t)m;
+    l.row_tiles = (int32_t)((n + kLiftTileM - 1) / kLiftTileM);
+    l.col_tiles = (int32_t)((N + kLiftTileN - 1) / kLiftTileN);
+    if (hipMemcpyAsync((void*)l.cols, tables[slot].data(), sizeof(void*) * m, hipMemcpyHostToDevice, stream) !=
+            hipSuccess ||
+        hipMemcpyAsync((LiftNode*)dn + slot, &l, sizeof(l), hipMemcpyHostToDevice, stream) != hipSuccess) {
+      set_error("hapod_node_pod_qr: upload failed");
+      return HAPOD_E_DEVICE;
+    }
+    hapod_status s2 = launch_set_scalar_i64((int64_t*)drank, N, stream);
+    if (s2 != HAPOD_OK) return s2;
+    return launch_lift(0, (const LiftNode*)dn + slot, 1, l.row_tiles * l.col_tiles, stream);
+  };
+  // Cholesky-QR passes Q <- Q R_p^-1 (Q = S first), R = ... R_2 R_1, so that
+  // S = Q R holds to rounding after every pass.  A pass whose Q^T Q is not
+  // within 1/2 of the identity by Gershgorin (m max |Q^T Q - I| > 1/2) is
+  // shifted: Q^T Q + s I = R_p^T R_p, s = 11 (n m + m (m + 1)) u tr(Q^T Q),
+  // the shift of shifted Cholesky-QR (tr >= ||Q||_2^2), which lifts the
+  // directions S nearly lacks by about s^-1/2 per pass; the others are
+  // plain.  Two plain passes in a row leave Q orthonormal to rounding.
+  const double u = 1.1102230246251565e-16;
+  if (s_scratch) QA = S;  // pass 0 writes QB, pass 1 may overwrite S
+  const double* src = S;
+  int64_t ld = lds;
+  double* dst = s_scratch ? (double*)QB : (double*)QA;
+  double* d_dev = (double*)dsig;
+  int plain_run = 0, pass = 0;
+  for (; pass < kQrMaxPasses && plain_run < 2; ++pass) {
+    if ((st = gram_impl(0, 8, n, m, src, ld, (double*)G, m, stream)) != HAPOD_OK ||
+        (st = launch_identity_dev((double*)G, m, m, d_dev, stream)) != HAPOD_OK)
+      return finish(st);
+    double dev = 0.0;
+    if (hipMemcpyAsync(&dev, d_dev, sizeof(double), hipMemcpyDeviceToHost, stream) != hipSuccess ||
+        hipStreamSynchronize(stream) != hipSuccess) {
+      set_error("hapod_node_pod_qr: readback failed");
+      return finish(HAPOD_E_DEVICE);
+    }
+    const bool shifted = !((double)m * dev <= 0.5);
+    if (shifted &&
+        (st = launch_shift_diag((double*)G, m, m, 11.0 * ((double)n * m + (double)m * (m + 1)) * u, stream)) != HAPOD_OK)
+      return finish(st);
+    if ((st = launch_chol_inv((double*)G, m, m, (double*)Rinv, m, (int32_t*)dbad + pass, stream, 0.0)) != HAPOD_OK ||
+        (st = launch_triu((double*)G, m, m, pass == 0 ? (double*)Racc : (double*)Rk, m, stream)) != HAPOD_OK)
+      return finish(st);
+    if (pass > 0) {
+      if ((st = launch_dgemm_nn(m, m, m, (double*)Rk, m, (double*)Racc, m, (double*)Rtmp, m, stream)) != HAPOD_OK)
+        return finish(st);
+      std::swap(Racc, Rtmp);
+    }
+    if ((st = lift(pass, src, ld, (double*)Rinv, m, dst, n, kRowBlock)) != HAPOD_OK) return finish(st);
+    src = dst;
+    ld = n;
+    dst = (dst == (double*)QA) ? (double*)QB : (double*)QA;
+    int32_t bad = 0;
+    if (hipMemcpyAsync(&bad, (int32_t*)dbad + pass, sizeof(bad), hipMemcpyDeviceToHost, stream) != hipSuccess ||
+        hipStreamSynchronize(stream) != hipSuccess) {
+      set_error("hapod_node_pod_qr: readback failed");
+      return finish(HAPOD_E_DEVICE);
+    }
+    if (bad) {
+      set_error("hapod_node_pod_qr: a Cholesky pivot was not positive (non-finite input?)");
+      return finish(HAPOD_E_NUMERIC);
+    }
+    plain_run = shifted ? 0 : plain_run + 1;
+  }
+  if (plain_run < 2) {
+    set_error("hapod_node_pod_qr: Cholesky-QR did not reach an orthonormal factor in 12 passes");
+    return finish(HAPOD_E_NUMERIC);
+  }
+  if (passes) *passes = pass;
+  // one-sided Jacobi SVD of R: R V = U_R diag(sigma); B = U_R (diag(sigma))
+  if ((st = launch_osj((double*)Racc, m, (double*)dsig, (double*)Bm, scaled ? 1 : 0, (int32_t*)dinfo, stream)) !=
+      HAPOD_OK)
+    return finish(st);
+  int32_t info = 0;
+  std::vector<double> sg((size_t)m);
+  if (hipMemcpyAsync(&info, dinfo, sizeof(info), hipMemcpyDeviceToHost, stream) != hipSuccess ||
+      hipMemcpyAsync(sg.data(), dsig, sizeof(double) * m, hipMemcpyDeviceToHost, stream) != hipSuccess ||
+      hipStreamSynchronize(stream) != hipSuccess) {
+    set_error("hapod_node_pod_qr: readback failed");
+    return finish(HAPOD_E_DEVICE);
+  }
+  if (info < 0) {
+    set_error("hapod_node_pod_qr: the Jacobi SVD did not converge");
+    return finish(HAPOD_E_NUMERIC);
+  }
+  if (sweeps) *sweeps = info;
+  // Def. 2.5: the smallest N whose discarded squared singular values sum to at most eps^2
+  int64_t N = m;
+  double tail = 0.0;
+  const double e2 = eps * eps;
+  while (N > 0 && tail + sg[(size_t)N - 1] * sg[(size_t)N - 1] <= e2) {
+    tail += sg[(size_t)N - 1] * sg[(size_t)N - 1];
+    --N;
+  }
+  if (N > 0) {
+    double* out = nullptr;
+    int64_t ocs = 0, obs = 0;
+    if ((st = out_for_rank(N, &out, &ocs, &obs)) != HAPOD_OK) return finish(st);
+    if ((st = lift(kQrMaxPasses, src, ld, (const double*)Bm, N, out, ocs, obs)) != HAPOD_OK) return finish(st);
+  }
+  *rank = N;
+  sigma.assign(sg.begin(), sg.begin() + N);
+  return finish(HAPOD_OK);
+}
+
+
 extern "C" {
 
 const char* hapod_last_error(void) { return g_last_error.c_str(); }
@@ -1102,6 +1264,11 @@ hapod_status hapod_plan(const hapod_tree* tree, double eps_star, double omega, c
     // FP32 modes are not, and mixing exact blocks with computed FP32 ones
     // moves ranks at the noise floor far more than the rounding itself
     set_error("hapod_plan: block_gram needs the FP64 form");
+    return HAPOD_E_INVALID;
+  }
+  if (opts && opts->qr_pod && (opts->prec != HAPOD_FP64 || opts->right_vectors)) {
+    // the QR route computes in double and keeps no right singular vectors
+    set_error("hapod_plan: qr_pod needs the FP64 form and excludes right_vectors");
     return HAPOD_E_INVALID;
   }
   auto P = std::make_unique<hapod_plan_s>();
@@ -1431,6 +1598,87 @@ hapod_status hapod_run(hapod_plan_t P, hapod_leaf_fn get_leaf, void* user, void*
     rows.assign(cols.size(), P->rows[a]);
     return HAPOD_OK;
   };
+  // one node through the QR route: its input columns gathered into a plain
+  // buffer, the modes written where the batched path would put them (plain
+  // n-row columns at the root, row-block-tiled elsewhere) in a pool block of
+  // their own; its time counts as Gram time
+  auto qr_node = [&](int32_t a, PodJob& j, PhaseTimes& ph) -> hapod_status {
+    hipEvent_t q0 = nullptr, q1 = nullptr;
+    HAPOD_HIP(hipEventCreate(&q0));
+    HAPOD_HIP(hipEventCreate(&q1));
+    EvGuard qg{q0, q1};
+    HAPOD_HIP(hipEventRecord(q0, stream));
+    void *Sg = nullptr, *dc = nullptr, *dr = nullptr, *dw = nullptr;
+    auto drop = [&]() {
+      (void)hipStreamSynchronize(stream);
+      for (void* q : {Sg, dc, dr, dw})
+        if (q) P->pool.free(q);
+    };
+    hapod_status st = P->pool.alloc(sizeof(double) * (size_t)j.n * j.m, &Sg);
+    if (st == HAPOD_OK) st = P->pool.alloc(sizeof(void*) * j.m, &dc);
+    if (st == HAPOD_OK) st = P->pool.alloc(sizeof(int64_t) * j.m, &dr);
+    if (st == HAPOD_OK) st = P->pool.alloc(sizeof(int64_t) * j.m, &dw);
+    if (st == HAPOD_OK &&
+        (hipMemcpyAsync(dc, j.cols.data(), sizeof(void*) * j.m, hipMemcpyHostToDevice, stream) != hipSuccess ||
+         hipMemcpyAsync(dr, j.rbs.data(), sizeof(int64_t) * j.m, hipMemcpyHostToDevice, stream) != hipSuccess ||
+         hipMemcpyAsync(dw, j.crows.data(), sizeof(int64_t) * j.m, hipMemcpyHostToDevice, stream) != hipSuccess)) {
+      set_error("hapod_run: upload failed");
+      st = HAPOD_E_DEVICE;
+    }
+    if (st == HAPOD_OK)
+      st = launch_gather_cols((const void* const*)dc, (const int64_t*)dr, (const int64_t*)dw, j.n, j.m, (double*)Sg,
+                              stream);
+    void* outp = nullptr;
+    auto out_for = [&](int64_t N, double** o, int64_t* ocs, int64_t* obs) -> hapod_status {
+      const size_t bytes = j.root ? sizeof(double) * (size_t)P->n * N : tiled_bytes(j.n, N, 8);
+      HAPOD_TRY(P->pool.alloc(bytes, &outp));
+      if (j.root) {
+        *ocs = P->n;
+        *obs = kRowBlock;
+        if (j.n < P->n) HAPOD_TRY(launch_zero_bytes(outp, bytes, stream));
+      } else {
+        *ocs = kRowBlock;
+        *obs = tiled_rbs(N);
+      }
+      *o = (double*)outp;
+      return HAPOD_OK;
+    };
+    std::vector<double> sg;
+    int64_t N = 0;
+    if (st == HAPOD_OK)
+      st = qr_pod_core(P->pool, j.n, j.m, (double*)Sg, j.n, true, j.eps, !j.root, out_for, sg, &N, nullptr, nullptr,
+                       stream);
+    drop();
+    if (st != HAPOD_OK) {
+      if (outp) P->pool.free(outp);
+      return st;
+    }
+    float ms = 0.f;
+    (void)hipEventRecord(q1, stream);
+    (void)hipEventSynchronize(q1);
+    (void)hipEventElapsedTime(&ms, q0, q1);
+    ph.gram += ms;
+    P->rank[a] = N;
+    P->sigma[a] = sg;
+    P->lam1[a] = sg.empty() ? 0.0 : sg.front() * sg.front();
+    P->lam_min[a] = sg.empty() ? 0.0 : sg.back() * sg.back();
+    P->n_neg[a] = 0;
+    out_buf[a] = outp;
+    if (outp) {
+      blocks.push_back({outp, 1});
+      out_blk[a] = (int)blocks.size() - 1;
+    }
+    if (a == P->root) {
+      out_cols[a] = column_table(outp, P->n, N, eb);
+      out_rbs[a].assign((size_t)N, kRowBlock);
+      out_rows[a].assign((size_t)N, P->n);
+    } else {
+      out_cols[a] = tiled_table(outp, N, eb);
+      out_rbs[a].assign((size_t)N, tiled_rbs(N));
+      out_rows[a].assign((size_t)N, j.n);
+    }
+    return HAPOD_OK;
+  };
   HAPOD_HIP(hipEventRecord(t0, stream));
   PhaseTimes pt;
   const int32_t LT = (int32_t)P->by_level.size();
@@ -1537,8 +1785,33 @@ hapod_status hapod_run(hapod_plan_t P, hapod_leaf_fn get_leaf, void* user, void*
         jobs.push_back(std::move(j));
         job_node.push_back(a);
       }
+      // the QR route (qr_pod) takes the computed nodes it covers one by one;
+      // the rest are batched below
+      if (P->opts.qr_pod) {
+        std::vector<PodJob> rest;
+        std::vector<int32_t> rest_node;
+        for (size_t k = 0; k < jobs.size(); ++k) {
+          PodJob& j = jobs[k];
+          const int32_t a = job_node[k];
+          if (j.m <= 0 || j.m > kQrMaxM || j.m > j.n) {
+            rest.push_back(std::move(j));
+            rest_node.push_back(a);
+            continue;
+          }
+          hapod_status qs = qr_node(a, j, lt);
+          if (qs != HAPOD_OK) {
+            (void)hipStreamSynchronize(stream);
+            release_all();
+            return qs;
+          }
+        }
+        jobs.swap(rest);
+        job_node.swap(rest_node);
+      }
       void* blk = nullptr;
-      hapod_status s = run_pod_batch(prec, jobs, 0, 1, jmax, P->pool, stream, &lt, &blk, P->opts.autotune != 0);
+      hapod_status s = jobs.empty() ? HAPOD_OK
+                                    : run_pod_batch(prec, jobs, 0, 1, jmax, P->pool, stream, &lt, &blk,
+                                                    P->opts.autotune != 0);
       if (s != HAPOD_OK) {
         (void)hipStreamSynchronize(stream);
         if (blk) P->pool.free(blk);
@@ -2185,149 +2458,17 @@ hapod_status hapod_node_pod_qr(int64_t n, int64_t m, const double* S, int64_t ld
   }
   *rank = 0;
   if (m == 0 || n == 0) return HAPOD_OK;
-  Pool& pool = step_pool();
-  const size_t mm = sizeof(double) * (size_t)m * m;
-  void *G = nullptr, *Rinv = nullptr, *Rk = nullptr, *Racc = nullptr, *Rtmp = nullptr, *Bm = nullptr, *dsig = nullptr,
-       *QA = nullptr, *QB = nullptr, *dcols = nullptr, *dn = nullptr, *drank = nullptr, *dbad = nullptr,
-       *drbs = nullptr, *drows = nullptr, *dinfo = nullptr;
-  std::vector<void*> held;
-  auto finish = [&](hapod_status st) {
-    (void)hipStreamSynchronize(stream);
-    for (void* q : held) pool.free(q);
-    return st;
+  std::vector<double> sg;
+  auto to_caller = [&](int64_t, double** o, int64_t* ocs, int64_t* obs) {
+    *o = out;
+    *ocs = ldo;
+    *obs = kRowBlock;
+    return HAPOD_OK;
   };
-  const std::pair<size_t, void**> want[] = {
-      {mm, &G}, {mm, &Rinv}, {mm, &Rk}, {mm, &Racc}, {mm, &Rtmp}, {mm, &Bm}, {sizeof(double) * 2 * m, &dsig},
-      {sizeof(double) * (size_t)n * m, &QA}, {sizeof(double) * (size_t)n * m, &QB},
-      {sizeof(void*) * (kQrMaxPasses + 1) * m, &dcols}, {sizeof(LiftNode) * (kQrMaxPasses + 1), &dn},
-      {sizeof(int64_t), &drank}, {sizeof(int32_t) * kQrMaxPasses, &dbad}, {sizeof(int64_t) * m, &drbs},
-      {sizeof(int64_t) * m, &drows}, {sizeof(int32_t), &dinfo}};
-  for (const auto& w : want) {
-    hapod_status st = pool.alloc(w.first, w.second);
-    if (st != HAPOD_OK) return finish(st);
-    held.push_back(*w.second);
-  }
-  hapod_status st = HAPOD_OK;
-  if ((st = launch_fill_i64((int64_t*)drbs, kRowBlock, m, stream)) != HAPOD_OK ||
-      (st = launch_fill_i64((int64_t*)drows, n, m, stream)) != HAPOD_OK)
-    return finish(st);
-  // the lift operands of the three passes and of the modes, uploaded from
-  // host tables that live until the end of the call
-  std::vector<std::vector<const void*>> tables(kQrMaxPasses + 1);
-  std::vector<LiftNode> lifts(kQrMaxPasses + 1);
-  auto lift = [&](int slot, const double* src, int64_t ld, const double* B, int64_t N, double* dst,
-                  int64_t ldd) -> hapod_status {
-    tables[slot] = column_table(src, ld, m, 8);
-    LiftNode& l = lifts[slot];
-    l = LiftNode{};
-    l.cols = (const void* const*)dcols + (size_t)slot * m;
-    l.rbs = (const int64_t*)drbs;
-    l.crows = (const int64_t*)drows;
-    l.B = B;
-    l.rank = (const int64_t*)drank;
-    l.out = dst;
-    l.n = n;
-    l.ldb = m;
-    l.ocs = ldd;
-    l.obs = kRowBlock;
-    l.m = (int32_t)m;
-    l.row_tiles = (int32_t)((n + kLiftTileM - 1) / kLiftTileM);
-    l.col_tiles = (int32_t)((N + kLiftTileN - 1) / kLiftTileN);
-    if (hipMemcpyAsync((void*)l.cols, tables[slot].data(), sizeof(void*) * m, hipMemcpyHostToDevice, stream) !=
-            hipSuccess ||
-        hipMemcpyAsync((LiftNode*)dn + slot, &l, sizeof(l), hipMemcpyHostToDevice, stream) != hipSuccess) {
-      set_error("hapod_node_pod_qr: upload failed");
-      return HAPOD_E_DEVICE;
-    }
-    hapod_status s2 = launch_set_scalar_i64((int64_t*)drank, N, stream);
-    if (s2 != HAPOD_OK) return s2;
-    return launch_lift(0, (const LiftNode*)dn + slot, 1, l.row_tiles * l.col_tiles, stream);
-  };
-  // Cholesky-QR passes Q <- Q R_p^-1 (Q = S first), R = ... R_2 R_1, so that
-  // S = Q R holds to rounding after every pass.  A pass whose Q^T Q is not
-  // within 1/2 of the identity by Gershgorin (m max |Q^T Q - I| > 1/2) is
-  // shifted: Q^T Q + s I = R_p^T R_p, s = 11 (n m + m (m + 1)) u tr(Q^T Q),
-  // the shift of shifted Cholesky-QR (tr >= ||Q||_2^2), which lifts the
-  // directions S nearly lacks by about s^-1/2 per pass; the others are
-  // plain.  Two plain passes in a row leave Q orthonormal to rounding.
-  const double u = 1.1102230246251565e-16;
-  const double* src = S;
-  int64_t ld = lds;
-  double* dst = (double*)QA;
-  double* d_dev = (double*)dsig;
-  int plain_run = 0, pass = 0;
-  for (; pass < kQrMaxPasses && plain_run < 2; ++pass) {
-    if ((st = gram_impl(0, 8, n, m, src, ld, (double*)G, m, stream)) != HAPOD_OK ||
-        (st = launch_identity_dev((double*)G, m, m, d_dev, stream)) != HAPOD_OK)
-      return finish(st);
-    double dev = 0.0;
-    if (hipMemcpyAsync(&dev, d_dev, sizeof(double), hipMemcpyDeviceToHost, stream) != hipSuccess ||
-        hipStreamSynchronize(stream) != hipSuccess) {
-      set_error("hapod_node_pod_qr: readback failed");
-      return finish(HAPOD_E_DEVICE);
-    }
-    const bool shifted = !((double)m * dev <= 0.5);
-    if (shifted &&
-        (st = launch_shift_diag((double*)G, m, m, 11.0 * ((double)n * m + (double)m * (m + 1)) * u, stream)) != HAPOD_OK)
-      return finish(st);
-    if ((st = launch_chol_inv((double*)G, m, m, (double*)Rinv, m, (int32_t*)dbad + pass, stream, 0.0)) != HAPOD_OK ||
-        (st = launch_triu((double*)G, m, m, pass == 0 ? (double*)Racc : (double*)Rk, m, stream)) != HAPOD_OK)
-      return finish(st);
-    if (pass > 0) {
-      if ((st = launch_dgemm_nn(m, m, m, (double*)Rk, m, (double*)Racc, m, (double*)Rtmp, m, stream)) != HAPOD_OK)
-        return finish(st);
-      std::swap(Racc, Rtmp);
-    }
-    if ((st = lift(pass, src, ld, (double*)Rinv, m, dst, n)) != HAPOD_OK) return finish(st);
-    src = dst;
-    ld = n;
-    dst = (dst == (double*)QA) ? (double*)QB : (double*)QA;
-    int32_t bad = 0;
-    if (hipMemcpyAsync(&bad, (int32_t*)dbad + pass, sizeof(bad), hipMemcpyDeviceToHost, stream) != hipSuccess ||
-        hipStreamSynchronize(stream) != hipSuccess) {
-      set_error("hapod_node_pod_qr: readback failed");
-      return finish(HAPOD_E_DEVICE);
-    }
-    if (bad) {
-      set_error("hapod_node_pod_qr: a Cholesky pivot was not positive (non-finite input?)");
-      return finish(HAPOD_E_NUMERIC);
-    }
-    plain_run = shifted ? 0 : plain_run + 1;
-  }
-  if (plain_run < 2) {
-    set_error("hapod_node_pod_qr: Cholesky-QR did not reach an orthonormal factor in 12 passes");
-    return finish(HAPOD_E_NUMERIC);
-  }
-  if (passes) *passes = pass;
-  // one-sided Jacobi SVD of R: R V = U_R diag(sigma); B = U_R (diag(sigma))
-  if ((st = launch_osj((double*)Racc, m, (double*)dsig, (double*)Bm, scaled ? 1 : 0, (int32_t*)dinfo, stream)) !=
-      HAPOD_OK)
-    return finish(st);
-  int32_t info = 0;
-  std::vector<double> sg((size_t)m);
-  if (hipMemcpyAsync(&info, dinfo, sizeof(info), hipMemcpyDeviceToHost, stream) != hipSuccess ||
-      hipMemcpyAsync(sg.data(), dsig, sizeof(double) * m, hipMemcpyDeviceToHost, stream) != hipSuccess ||
-      hipStreamSynchronize(stream) != hipSuccess) {
-    set_error("hapod_node_pod_qr: readback failed");
-    return finish(HAPOD_E_DEVICE);
-  }
-  if (info < 0) {
-    set_error("hapod_node_pod_qr: the Jacobi SVD did not converge");
-    return finish(HAPOD_E_NUMERIC);
-  }
-  if (sweeps) *sweeps = info;
-  // Def. 2.5: the smallest N whose discarded squared singular values sum to at most eps^2
-  int64_t N = m;
-  double tail = 0.0;
-  const double e2 = eps * eps;
-  while (N > 0 && tail + sg[(size_t)N - 1] * sg[(size_t)N - 1] <= e2) {
-    tail += sg[(size_t)N - 1] * sg[(size_t)N - 1];
-    --N;
-  }
-  if (N > 0 && (st = lift(3, src, ld, (const double*)Bm, N, out, ldo)) != HAPOD_OK) return finish(st);
-  *rank = N;
-  if (sigma && N > 0) std::memcpy(sigma, sg.data(), sizeof(double) * N);
-  return finish(HAPOD_OK);
+  hapod_status st = qr_pod_core(step_pool(), n, m, const_cast<double*>(S), lds, false, eps, scaled != 0, to_caller, sg,
+                                rank, passes, sweeps, stream);
+  if (st == HAPOD_OK && sigma && *rank > 0) std::memcpy(sigma, sg.data(), sizeof(double) * *rank);
+  return st;
 }
 
 }  // extern "C"

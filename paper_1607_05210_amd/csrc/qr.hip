@@ -13,6 +13,8 @@
 // Kernels: the diagonal shift, the distance of a Gram matrix from I, the
 // upper-triangle copy and the Jacobi SVD.
 
+#include <algorithm>
+
 #include "internal.hpp"
 
 namespace hapod {
@@ -229,7 +231,31 @@ __global__ __launch_bounds__(1024) void chol_inv_lds_kernel(double* W, int64_t l
   if (t == 0 && bad) *bad = nbad;
 }
 
+// dst (n x m, plain column-major) = the columns of a column table, rows past
+// a column's own row count zero
+__global__ void gather_cols_kernel(const void* const* __restrict__ cols, const int64_t* __restrict__ rbs,
+                                   const int64_t* __restrict__ crows, int64_t n, double* __restrict__ dst) {
+  const int64_t c = blockIdx.y;
+  const double* src = (const double*)cols[c];
+  const int64_t rows = crows[c], rb = rbs[c];
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x)
+    dst[c * n + r] = r < rows ? src[blk_off(r, rb)] : 0.0;
+}
+
 }  // namespace
+
+hapod_status launch_gather_cols(const void* const* d_cols, const int64_t* d_rbs, const int64_t* d_rows, int64_t n,
+                                int64_t m, double* dst, hipStream_t stream) {
+  if (n <= 0 || m <= 0) return HAPOD_OK;
+  if (m > 65535) {
+    set_error("gather: too many columns");
+    return HAPOD_E_UNSUPPORTED;
+  }
+  const unsigned gx = (unsigned)std::min<int64_t>((n + 255) / 256, 1024);
+  hipLaunchKernelGGL(gather_cols_kernel, dim3(gx, (unsigned)m), dim3(256), 0, stream, d_cols, d_rbs, d_rows, n, dst);
+  HAPOD_HIP(hipGetLastError());
+  return HAPOD_OK;
+}
 
 hapod_status launch_chol_inv_lds(double* W, int64_t ldw, int64_t N, double* Rinv, int64_t ldr, int32_t* d_bad,
                                  hipStream_t stream, double rel_floor) {

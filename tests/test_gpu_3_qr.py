@@ -160,3 +160,103 @@ def test_passthrough_and_limits(hp):
         bad = S.copy()
         bad[3, 2] = np.nan
         hp.hapod_node_pod_qr(dev_colmajor(bad), 1e-3)
+
+
+# ------------------------------------------------------------ tree level ----
+def _tree_run(hp, parent, data, n, eps_star, omega, zero=(), **kw):
+    from oracle import tolerances
+    leaf_cols = [data[i].shape[1] if i in data else 0 for i in range(len(parent))]
+    ov = None
+    if zero:
+        ov = [-1.0] * len(parent)
+        for z in zero:
+            ov[z] = 0.0
+    plan = hp.Plan(parent, leaf_cols, n, eps_star, omega, prec="fp64", eps_override=ov, **kw)
+    plan.run({k: dev_colmajor(v) for k, v in data.items()})
+    sig, U = plan.modes()
+    eps = tolerances.hapod_tolerances(parent, leaf_cols, eps_star, omega, zero_nodes=zero)
+    return plan, sig, host(U), eps
+
+
+def _split(S, cols):
+    out, c0 = [], 0
+    for c in cols:
+        out.append(S[:, c0:c0 + c])
+        c0 += c
+    return out
+
+
+@pytest.mark.parametrize("shape", ["balanced", "star", "chain"])
+def test_tree_qr_route_matches_oracle_below_the_gram_floor(hp, shape):
+    """A graded spectrum down to 1e-13 and eps* = 1e-9: every node's
+    truncation falls where the method of snapshots cannot resolve.  With
+    qr_pod every node's rank is the oracle's (literal Def. 3.2 recursion with
+    LAPACK SVDs), the root's sigma agree to 1e-13 sigma_1, and the mean
+    squared projection error meets Thm. 3.5's eps*^2."""
+    from oracle import hapod, tree
+    n = 3000
+    if shape == "balanced":
+        leaves, per = 27, 12
+        parent = synth.balanced_tree(leaves, 4)
+        cols, zero = [per] * leaves, ()
+    elif shape == "star":
+        leaves, per = 4, 64
+        parent = synth.star_tree(leaves)
+        cols, zero = [per] * leaves, ()
+    else:
+        leaves, per = 6, 40
+        parent, chunk = synth.chain_tree(leaves)
+        cols, zero = [per] * leaves, tuple(b for b in chunk if b != 0)
+    m = sum(cols)
+    sig = 10.0 ** (-13.0 * np.arange(m) / (m - 1))
+    S = prescribed(n, sig, seed=m + len(parent))
+    blocks = _split(S, cols)
+    if shape == "chain":
+        data = {leaf: blocks[c] for leaf, c in chunk.items()}
+    else:
+        data = dict(enumerate(blocks))
+    eps_star, omega = 1e-9, 0.75
+    print(f"tree qr {shape}", flush=True)
+    plan, s_gpu, U, eps = _tree_run(hp, parent, data, n, eps_star, omega, zero=zero, qr_pod=True)
+    data64 = {k: np.asarray(v) for k, v in data.items()}
+    ref = hapod.hapod(parent, data64, eps)
+    root = tree.validate(parent)
+    ranks = plan.ranks()
+    want = [len(ref[a][0]) for a in range(len(parent))]
+    assert list(ranks) == want
+    s_ref = ref[root][0]
+    assert np.max(np.abs(s_gpu - s_ref)) <= 1e-13 * s_ref[0]
+    assert metrics.orthonormality_error(U) <= 1e-13
+    S_all = np.hstack([data64[k] for k in sorted(data64)])
+    err_qr = metrics.mean_projection_error(S_all, U)
+    plan_g, s_g, U_g, _ = _tree_run(hp, parent, data, n, eps_star, omega, zero=zero)
+    err_g = metrics.mean_projection_error(S_all, U_g)
+    print(f"  root rank {len(s_gpu)} (Gram route {len(s_g)}), mean error / eps*^2: QR {err_qr / eps_star**2:.3f}, "
+          f"Gram {err_g / eps_star**2:.3f}, ranks off in the Gram route: "
+          f"{sum(int(a != b) for a, b in zip(plan_g.ranks(), want))}")
+    assert err_qr <= eps_star ** 2
+
+
+def test_tree_qr_route_wide_root_takes_the_gram_route(hp):
+    """Leaves of 128 columns take the QR route; the 640-column root is
+    beyond it and takes the method of snapshots; the leaves' ranks are the
+    oracle's and the root's modes span the oracle's leading ones."""
+    from oracle import hapod, tree
+    n, leaves, per = 2048, 5, 128
+    S = synth.sinusoid(n, leaves * per, 400, 40.0, 1e-10, seed=4)
+    parent = synth.star_tree(leaves)
+    data = dict(enumerate(_split(S, [per] * leaves)))
+    plan, s_gpu, U, eps = _tree_run(hp, parent, data, n, 1e-7, 0.75, qr_pod=True)
+    ref = hapod.hapod(parent, data, eps)
+    ranks = plan.ranks()
+    assert list(ranks[:leaves]) == [len(ref[a][0]) for a in range(leaves)]
+    assert plan.node_stats()["m_in"][leaves] > 512
+    root = tree.validate(parent)
+    r = metrics.resolved_rank(ref[root][0], len(s_gpu), U64, 1e-6)
+    assert metrics.subspace_error(ref[root][1], U, r) <= 1e-6
+
+
+def test_tree_qr_route_plan_rules(hp):
+    for kw in ({"prec": "fp32"}, {"prec": "bf16x3"}, {"prec": "fp64", "right_vectors": True}):
+        with pytest.raises(hp.HapodError):
+            hp.Plan(synth.star_tree(2), [4, 4, 0], 64, 1e-3, 0.5, qr_pod=True, **kw)
