@@ -28,7 +28,7 @@ void set_error(const std::string& msg) { g_last_error = msg; }
 void* pool_alloc_cb(void* pool, size_t bytes);
 void pool_free_cb(void* pool, void* p);
 hapod_status gram_impl(int compute, int eb, int64_t n, int64_t m, const void* S, int64_t lds, double* G, int64_t ldg,
-                       hipStream_t stream, int tile = 0);
+                       hipStream_t stream, int tile = 0, int64_t in_rbs = 0);
 
 namespace {
 
@@ -1084,10 +1084,12 @@ struct hapod_plan_s {
 };
 
 // The QR route for one node with eps > 0, 0 < m <= kQrMaxM, m <= n, S plain
-// column-major (n x m, ld lds).  With s_scratch, S may be overwritten (it
-// serves as one of the two Q buffers).  out_for_rank(N, &out, &ocs, &obs)
+// column-major (n x m, ld lds) or row-block-tiled (s_tiled, n x m).  The Q
+// of the passes is row-block-tiled (contiguous 128-row blocks stream faster
+// than columns 8 n bytes apart).  With s_scratch, S (then tiled) may be
+// overwritten: it serves as one of the two Q buffers.  out_for_rank(N, &out, &ocs, &obs)
 // names where the N modes go (called once N is known, N > 0).
-hapod_status qr_pod_core(Pool& pool, int64_t n, int64_t m, double* S, int64_t lds, bool s_scratch, double eps,
+hapod_status qr_pod_core(Pool& pool, int64_t n, int64_t m, double* S, int64_t lds, bool s_tiled, bool s_scratch, double eps,
                          bool scaled, const std::function<hapod_status(int64_t, double**, int64_t*, int64_t*)>& out_for_rank,
                          std::vector<double>& sigma, int64_t* rank, int32_t* passes, int32_t* sweeps,
                          hipStream_t stream) {
@@ -1095,7 +1097,7 @@ hapod_status qr_pod_core(Pool& pool, int64_t n, int64_t m, double* S, int64_t ld
   const size_t mm = sizeof(double) * (size_t)m * m;
   void *G = nullptr, *Rinv = nullptr, *Rk = nullptr, *Racc = nullptr, *Rtmp = nullptr, *Bm = nullptr, *dsig = nullptr,
        *QA = nullptr, *QB = nullptr, *dcols = nullptr, *dn = nullptr, *drank = nullptr, *dbad = nullptr,
-       *drbs = nullptr, *drows = nullptr, *dinfo = nullptr;
+       *drbs = nullptr, *drows = nullptr, *dinfo = nullptr, *drbs_t = nullptr;
   std::vector<void*> held;
   auto finish = [&](hapod_status st) {
     (void)hipStreamSynchronize(stream);
@@ -1104,10 +1106,10 @@ hapod_status qr_pod_core(Pool& pool, int64_t n, int64_t m, double* S, int64_t ld
   };
   const std::pair<size_t, void**> want[] = {
       {mm, &G}, {mm, &Rinv}, {mm, &Rk}, {mm, &Racc}, {mm, &Rtmp}, {mm, &Bm}, {sizeof(double) * 2 * m, &dsig},
-      {s_scratch ? 0 : sizeof(double) * (size_t)n * m, &QA}, {sizeof(double) * (size_t)n * m, &QB},
+      {s_scratch ? 0 : tiled_bytes(n, m, 8), &QA}, {tiled_bytes(n, m, 8), &QB},
       {sizeof(void*) * (kQrMaxPasses + 1) * m, &dcols}, {sizeof(LiftNode) * (kQrMaxPasses + 1), &dn},
       {sizeof(int64_t), &drank}, {sizeof(int32_t) * kQrMaxPasses, &dbad}, {sizeof(int64_t) * m, &drbs},
-      {sizeof(int64_t) * m, &drows}, {sizeof(int32_t), &dinfo}};
+      {sizeof(int64_t) * m, &drows}, {sizeof(int32_t), &dinfo}, {sizeof(int64_t) * m, &drbs_t}};
   for (const auto& w : want) {
     if (w.first == 0) continue;
     hapod_status st = pool.alloc(w.first, w.second);
@@ -1115,20 +1117,22 @@ hapod_status qr_pod_core(Pool& pool, int64_t n, int64_t m, double* S, int64_t ld
     held.push_back(*w.second);
   }
   hapod_status st = HAPOD_OK;
+  const int64_t trbs = tiled_rbs(m);
   if ((st = launch_fill_i64((int64_t*)drbs, kRowBlock, m, stream)) != HAPOD_OK ||
+      (st = launch_fill_i64((int64_t*)drbs_t, trbs, m, stream)) != HAPOD_OK ||
       (st = launch_fill_i64((int64_t*)drows, n, m, stream)) != HAPOD_OK)
     return finish(st);
   // the lift operands of the three passes and of the modes, uploaded from
   // host tables that live until the end of the call
   std::vector<std::vector<const void*>> tables(kQrMaxPasses + 1);
   std::vector<LiftNode> lifts(kQrMaxPasses + 1);
-  auto lift = [&](int slot, const double* src, int64_t ld, const double* B, int64_t N, double* dst, int64_t ldd,
-                  int64_t obs) -> hapod_status {
-    tables[slot] = column_table(src, ld, m, 8);
+  auto lift = [&](int slot, const double* src, bool src_tiled, int64_t ld, const double* B, int64_t N, double* dst,
+                  int64_t ldd, int64_t obs) -> hapod_status {
+    tables[slot] = src_tiled ? tiled_table(src, m, 8) : column_table(src, ld, m, 8);
     LiftNode& l = lifts[slot];
     l = LiftNode{};
     l.cols = (const void* const*)dcols + (size_t)slot * m;
-    l.rbs = (const int64_t*)drbs;
+    l.rbs = (const int64_t*)(src_tiled ? drbs_t : drbs);
     l.crows = (const int64_t*)drows;
     l.B = B;
     l.rank = (const int64_t*)drank;
@@ -1160,12 +1164,13 @@ hapod_status qr_pod_core(Pool& pool, int64_t n, int64_t m, double* S, int64_t ld
   const double u = 1.1102230246251565e-16;
   if (s_scratch) QA = S;  // pass 0 writes QB, pass 1 may overwrite S
   const double* src = S;
+  bool src_tiled = s_tiled;
   int64_t ld = lds;
   double* dst = s_scratch ? (double*)QB : (double*)QA;
   double* d_dev = (double*)dsig;
   int plain_run = 0, pass = 0;
   for (; pass < kQrMaxPasses && plain_run < 2; ++pass) {
-    if ((st = gram_impl(0, 8, n, m, src, ld, (double*)G, m, stream)) != HAPOD_OK ||
+    if ((st = gram_impl(0, 8, n, m, src, ld, (double*)G, m, stream, 0, src_tiled ? trbs : 0)) != HAPOD_OK ||
         (st = launch_identity_dev((double*)G, m, m, d_dev, stream)) != HAPOD_OK)
       return finish(st);
     double dev = 0.0;
@@ -1186,8 +1191,9 @@ hapod_status qr_pod_core(Pool& pool, int64_t n, int64_t m, double* S, int64_t ld
         return finish(st);
       std::swap(Racc, Rtmp);
     }
-    if ((st = lift(pass, src, ld, (double*)Rinv, m, dst, n, kRowBlock)) != HAPOD_OK) return finish(st);
+    if ((st = lift(pass, src, src_tiled, ld, (double*)Rinv, m, dst, kRowBlock, trbs)) != HAPOD_OK) return finish(st);
     src = dst;
+    src_tiled = true;
     ld = n;
     dst = (dst == (double*)QA) ? (double*)QB : (double*)QA;
     int32_t bad = 0;
@@ -1236,7 +1242,8 @@ hapod_status qr_pod_core(Pool& pool, int64_t n, int64_t m, double* S, int64_t ld
     double* out = nullptr;
     int64_t ocs = 0, obs = 0;
     if ((st = out_for_rank(N, &out, &ocs, &obs)) != HAPOD_OK) return finish(st);
-    if ((st = lift(kQrMaxPasses, src, ld, (const double*)Bm, N, out, ocs, obs)) != HAPOD_OK) return finish(st);
+    if ((st = lift(kQrMaxPasses, src, src_tiled, ld, (const double*)Bm, N, out, ocs, obs)) != HAPOD_OK)
+      return finish(st);
   }
   *rank = N;
   sigma.assign(sg.begin(), sg.begin() + N);
@@ -1598,8 +1605,8 @@ hapod_status hapod_run(hapod_plan_t P, hapod_leaf_fn get_leaf, void* user, void*
     rows.assign(cols.size(), P->rows[a]);
     return HAPOD_OK;
   };
-  // one node through the QR route: its input columns gathered into a plain
-  // buffer, the modes written where the batched path would put them (plain
+  // one node through the QR route: its input columns gathered into a
+  // row-block-tiled buffer, the modes written where the batched path would put them (plain
   // n-row columns at the root, row-block-tiled elsewhere) in a pool block of
   // their own; its time counts as Gram time
   auto qr_node = [&](int32_t a, PodJob& j, PhaseTimes& ph) -> hapod_status {
@@ -1614,7 +1621,7 @@ hapod_status hapod_run(hapod_plan_t P, hapod_leaf_fn get_leaf, void* user, void*
       for (void* q : {Sg, dc, dr, dw})
         if (q) P->pool.free(q);
     };
-    hapod_status st = P->pool.alloc(sizeof(double) * (size_t)j.n * j.m, &Sg);
+    hapod_status st = P->pool.alloc(tiled_bytes(j.n, j.m, 8), &Sg);
     if (st == HAPOD_OK) st = P->pool.alloc(sizeof(void*) * j.m, &dc);
     if (st == HAPOD_OK) st = P->pool.alloc(sizeof(int64_t) * j.m, &dr);
     if (st == HAPOD_OK) st = P->pool.alloc(sizeof(int64_t) * j.m, &dw);
@@ -1627,7 +1634,7 @@ hapod_status hapod_run(hapod_plan_t P, hapod_leaf_fn get_leaf, void* user, void*
     }
     if (st == HAPOD_OK)
       st = launch_gather_cols((const void* const*)dc, (const int64_t*)dr, (const int64_t*)dw, j.n, j.m, (double*)Sg,
-                              stream);
+                              tiled_rbs(j.m), stream);
     void* outp = nullptr;
     auto out_for = [&](int64_t N, double** o, int64_t* ocs, int64_t* obs) -> hapod_status {
       const size_t bytes = j.root ? sizeof(double) * (size_t)P->n * N : tiled_bytes(j.n, N, 8);
@@ -1646,7 +1653,7 @@ hapod_status hapod_run(hapod_plan_t P, hapod_leaf_fn get_leaf, void* user, void*
     std::vector<double> sg;
     int64_t N = 0;
     if (st == HAPOD_OK)
-      st = qr_pod_core(P->pool, j.n, j.m, (double*)Sg, j.n, true, j.eps, !j.root, out_for, sg, &N, nullptr, nullptr,
+      st = qr_pod_core(P->pool, j.n, j.m, (double*)Sg, j.n, true, true, j.eps, !j.root, out_for, sg, &N, nullptr, nullptr,
                        stream);
     drop();
     if (st != HAPOD_OK) {
@@ -2005,8 +2012,10 @@ hapod_status hapod_gram(hapod_precision prec, int64_t n, int64_t m, const void* 
 }  // extern "C"
 
 namespace hapod {
+// in_rbs > 0: S is row-block-tiled (column j at S + kRowBlock j elements,
+// row-block stride in_rbs) instead of plain with leading dimension lds
 hapod_status gram_impl(int compute, int eb, int64_t n, int64_t m, const void* S, int64_t lds, double* G, int64_t ldg,
-                       hipStream_t stream, int tile_override) {
+                       hipStream_t stream, int tile_override, int64_t in_rbs) {
   if (n < 0 || m < 0 || (m > 0 && (!G || (n > 0 && !S))) || lds < std::max<int64_t>(n, 1) ||
       ldg < std::max<int64_t>(m, 1)) {
     set_error("hapod_gram: bad sizes or NULL pointer");
@@ -2018,7 +2027,7 @@ hapod_status gram_impl(int compute, int eb, int64_t n, int64_t m, const void* S,
     return HAPOD_E_UNSUPPORTED;
   }
   Pool& pool = step_pool();
-  auto cols = column_table(S, lds, m, eb);
+  auto cols = in_rbs > 0 ? tiled_table(S, m, eb) : column_table(S, lds, m, eb);
   int tile = tile_override > 0 ? tile_override : gram_tile_for(m);
   // split-BF16 above 256 columns: pre-split twin and 256-column tiles, as in
   // the level batches
@@ -2026,7 +2035,9 @@ hapod_status gram_impl(int compute, int eb, int64_t n, int64_t m, const void* S,
   const int nt = (int)((m + tile - 1) / tile);
   const int pairs = nt * (nt + 1) / 2;
   const int KB = (compute == 2) ? 32 : 16;
-  int nch = (n > 0) ? pick_chunks(n, pairs, 2048, 2048) : 1;
+  // the level batches' work-item goal (8192, measured there on 2^20- and
+  // 2^22-row nodes)
+  int nch = (n > 0) ? pick_chunks(n, pairs, std::max(8192, pairs), 2048) : 1;
   int64_t cr = (n > 0) ? ((n + nch - 1) / nch + kRowBlock - 1) / kRowBlock * kRowBlock : kRowBlock;
   nch = (n > 0) ? (int)((n + cr - 1) / cr) : 1;
   bool vec_ok = (cr % KB == 0);
@@ -2036,7 +2047,7 @@ hapod_status gram_impl(int compute, int eb, int64_t n, int64_t m, const void* S,
   HAPOD_TRY(pool.alloc(sizeof(void*) * m, &dcols));
   HAPOD_TRY(pool.alloc(sizeof(int64_t) * m, &drbs));
   HAPOD_TRY(pool.alloc(sizeof(int64_t) * m, &drows));
-  HAPOD_TRY(launch_fill_i64((int64_t*)drbs, kRowBlock, m, stream));
+  HAPOD_TRY(launch_fill_i64((int64_t*)drbs, in_rbs > 0 ? in_rbs : kRowBlock, m, stream));
   HAPOD_TRY(launch_fill_i64((int64_t*)drows, n, m, stream));
   const int slots = nch * gram_slots_per_chunk(tile);
   if (slots > 1) HAPOD_TRY(pool.alloc(sizeof(double) * pairs * slots * tile * tile, &dpart));
@@ -2465,7 +2476,7 @@ hapod_status hapod_node_pod_qr(int64_t n, int64_t m, const double* S, int64_t ld
     *obs = kRowBlock;
     return HAPOD_OK;
   };
-  hapod_status st = qr_pod_core(step_pool(), n, m, const_cast<double*>(S), lds, false, eps, scaled != 0, to_caller, sg,
+  hapod_status st = qr_pod_core(step_pool(), n, m, const_cast<double*>(S), lds, false, false, eps, scaled != 0, to_caller, sg,
                                 rank, passes, sweeps, stream);
   if (st == HAPOD_OK && sigma && *rank > 0) std::memcpy(sigma, sg.data(), sizeof(double) * *rank);
   return st;

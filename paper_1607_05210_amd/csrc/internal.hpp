@@ -235,10 +235,11 @@ hapod_status launch_chol_inv_lds(double* W, int64_t ldw, int64_t N, double* Rinv
                                  hipStream_t stream, double rel_floor);
 // G[k][k] += coef * trace(G)
 hapod_status launch_shift_diag(double* G, int64_t ldg, int64_t m, double coef, hipStream_t stream);
-// dst (n x m plain, ld n) = the columns of a column table (device arrays),
-// rows past a column's row count zero
+// dst (n x m) = the columns of a column table (device arrays), rows past a
+// column's row count zero; dst plain (ld n) for dst_rbs == 0, else
+// row-block-tiled with that row-block stride
 hapod_status launch_gather_cols(const void* const* d_cols, const int64_t* d_rbs, const int64_t* d_rows, int64_t n,
-                                int64_t m, double* dst, hipStream_t stream);
+                                int64_t m, double* dst, int64_t dst_rbs, hipStream_t stream);
 // out[0] = max over the upper triangle of |G_ij - delta_ij|
 hapod_status launch_identity_dev(const double* G, int64_t ldg, int64_t m, double* out, hipStream_t stream);
 // R = upper triangle of W, zeros below (both column-major)

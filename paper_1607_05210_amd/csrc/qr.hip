@@ -231,28 +231,33 @@ __global__ __launch_bounds__(1024) void chol_inv_lds_kernel(double* W, int64_t l
   if (t == 0 && bad) *bad = nbad;
 }
 
-// dst (n x m, plain column-major) = the columns of a column table, rows past
-// a column's own row count zero
+// dst (n x m) = the columns of a column table, rows past a column's own row
+// count zero; dst plain column-major (ld n) for dst_rbs == 0, else
+// row-block-tiled with row-block stride dst_rbs
 __global__ void gather_cols_kernel(const void* const* __restrict__ cols, const int64_t* __restrict__ rbs,
-                                   const int64_t* __restrict__ crows, int64_t n, double* __restrict__ dst) {
+                                   const int64_t* __restrict__ crows, int64_t n, double* __restrict__ dst,
+                                   int64_t dst_rbs) {
   const int64_t c = blockIdx.y;
   const double* src = (const double*)cols[c];
   const int64_t rows = crows[c], rb = rbs[c];
+  double* out = dst_rbs > 0 ? dst + c * kRowBlock : dst + c * n;
+  const int64_t orb = dst_rbs > 0 ? dst_rbs : kRowBlock;
   for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x)
-    dst[c * n + r] = r < rows ? src[blk_off(r, rb)] : 0.0;
+    out[blk_off(r, orb)] = r < rows ? src[blk_off(r, rb)] : 0.0;
 }
 
 }  // namespace
 
 hapod_status launch_gather_cols(const void* const* d_cols, const int64_t* d_rbs, const int64_t* d_rows, int64_t n,
-                                int64_t m, double* dst, hipStream_t stream) {
+                                int64_t m, double* dst, int64_t dst_rbs, hipStream_t stream) {
   if (n <= 0 || m <= 0) return HAPOD_OK;
   if (m > 65535) {
     set_error("gather: too many columns");
     return HAPOD_E_UNSUPPORTED;
   }
   const unsigned gx = (unsigned)std::min<int64_t>((n + 255) / 256, 1024);
-  hipLaunchKernelGGL(gather_cols_kernel, dim3(gx, (unsigned)m), dim3(256), 0, stream, d_cols, d_rbs, d_rows, n, dst);
+  hipLaunchKernelGGL(gather_cols_kernel, dim3(gx, (unsigned)m), dim3(256), 0, stream, d_cols, d_rbs, d_rows, n, dst,
+                     dst_rbs);
   HAPOD_HIP(hipGetLastError());
   return HAPOD_OK;
 }
