@@ -231,8 +231,9 @@ constexpr int64_t kQrMaxM = 512;     // widest node of the QR-based POD
 constexpr int64_t kOsjLdsMaxM = 128; // the Jacobi SVD keeps R in LDS up to this width
 constexpr int kQrMaxPasses = 12;     // Cholesky-QR passes before giving up
 constexpr int kCholLdsMaxN = 128;    // launch_chol_inv keeps both triangles in LDS up to this N
-hapod_status launch_chol_inv_lds(double* W, int64_t ldw, int64_t N, double* Rinv, int64_t ldr, int32_t* d_bad,
-                                 hipStream_t stream, double rel_floor);
+constexpr int kCholWgMaxN = 1024;    // and works in place in global memory up to this N
+hapod_status launch_chol_inv_wg(double* W, int64_t ldw, int64_t N, double* Rinv, int64_t ldr, int32_t* d_bad,
+                                hipStream_t stream, double rel_floor);
 // G[k][k] += coef * trace(G)
 hapod_status launch_shift_diag(double* G, int64_t ldg, int64_t m, double coef, hipStream_t stream);
 // dst (n x m) = the columns of a column table (device arrays), rows past a

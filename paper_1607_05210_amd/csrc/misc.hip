@@ -54,63 +54,6 @@ __global__ void fill_i64_kernel(int64_t* p, int64_t v, int64_t count) {
     p[i] = v;
 }
 
-// W (N x N, symmetric, upper used) = R^T R in place (upper R), then Rinv =
-// R^{-1} (upper, row-major).  A pivot <= rel_floor of its original diagonal
-// (or not positive) marks the column as dependent: its row of R becomes e_k
-// (the column is left unchanged).
-__global__ __launch_bounds__(256) void chol_inv_kernel(double* W, int64_t ldw, int64_t N, double* Rinv,
-                                                       int64_t ldr, int32_t* bad, double rel_floor) {
-  __shared__ double piv;
-  __shared__ int nbad;
-  const int tid = threadIdx.x;
-  if (tid == 0) nbad = 0;
-  __syncthreads();
-  for (int64_t k = 0; k < N; ++k) {
-    if (tid == 0) {
-      const double d = W[k * ldw + k];
-      // the original diagonal of column k is kept in Rinv's diagonal slot
-      const double d0 = Rinv[k * ldr + k];
-      if (!(d > rel_floor * d0) || !(d > 0.0) || !isfinite(d)) {
-        piv = 0.0;
-        ++nbad;
-      } else {
-        piv = sqrt(d);
-      }
-    }
-    __syncthreads();
-    const double p = piv;
-    for (int64_t j = k + 1 + tid; j < N; j += blockDim.x)
-      W[j * ldw + k] = (p > 0.0) ? W[j * ldw + k] / p : 0.0;
-    __syncthreads();
-    if (tid == 0) W[k * ldw + k] = (p > 0.0) ? p : 1.0;
-    // trailing update of the upper triangle: W[i][j] -= R[k][i] R[k][j], k < i <= j
-    const int64_t rem = N - k - 1;
-    for (int64_t e = tid; e < rem * rem; e += blockDim.x) {
-      const int64_t i = k + 1 + e % rem, j = k + 1 + e / rem;
-      if (i > j) continue;
-      W[j * ldw + i] -= W[i * ldw + k] * W[j * ldw + k];
-    }
-    __syncthreads();
-  }
-  // Rinv (row-major, element (i, j) at i * ldr + j): column j solves
-  // R x = e_j by back substitution
-  for (int64_t j = tid; j < N; j += blockDim.x) {
-    for (int64_t i = j + 1; i < N; ++i) Rinv[i * ldr + j] = 0.0;
-    Rinv[j * ldr + j] = 1.0 / W[j * ldw + j];
-    for (int64_t i = j - 1; i >= 0; --i) {
-      double s = 0.0;
-      for (int64_t l = i + 1; l <= j; ++l) s += W[l * ldw + i] * Rinv[l * ldr + j];
-      Rinv[i * ldr + j] = -s / W[i * ldw + i];
-    }
-  }
-  if (tid == 0 && bad) *bad = nbad;
-}
-
-__global__ void copy_diag_kernel(const double* W, int64_t ldw, int64_t N, double* R, int64_t ldr) {
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k < N) R[k * ldr + k] = W[k * ldw + k];
-}
-
 // C = A B, column-major FP64 (M x K times K x N), 16 x 16 tiles through LDS;
 // for the small products that compose right singular vectors.
 __global__ __launch_bounds__(256) void dgemm_nn_kernel(int64_t M, int64_t N, int64_t K, const double* __restrict__ A,
@@ -215,13 +158,7 @@ hapod_status launch_split_cols(int64_t n, int64_t m, const void* const* cols, co
 
 hapod_status launch_chol_inv(double* W, int64_t ldw, int64_t N, double* Rinv, int64_t ldr, int32_t* d_bad,
                              hipStream_t stream, double rel_floor) {
-  if (N <= 0) return HAPOD_OK;
-  if (N <= kCholLdsMaxN) return launch_chol_inv_lds(W, ldw, N, Rinv, ldr, d_bad, stream, rel_floor);
-  hipLaunchKernelGGL(copy_diag_kernel, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, stream, W, ldw, N, Rinv,
-                     ldr);
-  hipLaunchKernelGGL(chol_inv_kernel, dim3(1), dim3(256), 0, stream, W, ldw, N, Rinv, ldr, d_bad, rel_floor);
-  HAPOD_HIP(hipGetLastError());
-  return HAPOD_OK;
+  return launch_chol_inv_wg(W, ldw, N, Rinv, ldr, d_bad, stream, rel_floor);
 }
 
 hapod_status launch_dgemm_nn(int64_t M, int64_t N, int64_t K, const double* A, int64_t lda, const double* B,

@@ -157,36 +157,48 @@ __global__ __launch_bounds__(kOsjThreads) void osj_kernel(double* A, int64_t m, 
   if (t == 0) info[0] = done ? sweep : -1;
 }
 
-// chol_inv_kernel's operation for N <= kCholLdsMaxN with both triangles in
-// LDS (column-packed upper, (i, j) at j (j + 1) / 2 + i): W = R^T R in place
-// (upper R), Rinv = R^-1 (row-major, upper); a pivot <= rel_floor of its
-// original diagonal, or not positive, marks the column as dependent (its row
-// of R becomes e_k).  Same elimination order as the global-memory kernel;
-// the inverse's dot products are split over 8 lanes.
-__global__ __launch_bounds__(1024) void chol_inv_lds_kernel(double* W, int64_t ldw, int N, double* Rinv, int64_t ldr,
-                                                            int32_t* bad, double rel_floor) {
+// W = R^T R in place (upper R, column-major), Rinv = R^-1 (row-major, upper,
+// zeros below); a pivot <= rel_floor of its original diagonal, or not
+// positive, marks the column as dependent (its row of R becomes e_k).
+// Right-looking elimination over all (i, j) of the trailing triangle at
+// once, then R^-1 row by row from the bottom with each dot product split
+// over 8 lanes.  kLds: both triangles packed in LDS (column-packed upper,
+// (i, j) at j (j + 1) / 2 + i), N <= kCholLdsMaxN; otherwise in place in W
+// and Rinv (workgroup-scope barriers order the global reads and writes).
+template <bool kLds>
+__global__ __launch_bounds__(1024) void chol_inv_wg_kernel(double* W, int64_t ldw, int N, double* Rinv, int64_t ldr,
+                                                           int32_t* bad, double rel_floor) {
   extern __shared__ double ch_lds[];
   const int np = N * (N + 1) / 2;
-  double* P = ch_lds;
-  double* Iv = ch_lds + np;
-  __shared__ double d0s[kCholLdsMaxN];
+  __shared__ double d0s[kCholWgMaxN];
   __shared__ double piv;
   __shared__ int nbad;
   const int t = threadIdx.x;
-  auto idx = [](int i, int j) { return j * (j + 1) / 2 + i; };
-  for (int e = t; e < np; e += 1024) {
-    int j = (int)((sqrtf(8.0f * (float)e + 1.0f) - 1.0f) * 0.5f);
+  auto P = [&](int i, int j) -> double& {
+    return kLds ? ch_lds[j * (j + 1) / 2 + i] : W[(int64_t)j * ldw + i];
+  };
+  auto Iv = [&](int i, int j) -> double& {
+    return kLds ? ch_lds[np + j * (j + 1) / 2 + i] : Rinv[(int64_t)i * ldr + j];
+  };
+  auto unpack = [](int e, int& i, int& j) {
+    j = (int)((sqrtf(8.0f * (float)e + 1.0f) - 1.0f) * 0.5f);
     while (j * (j + 1) / 2 > e) --j;
     while ((j + 1) * (j + 2) / 2 <= e) ++j;
-    const int i = e - j * (j + 1) / 2;
-    P[e] = W[(int64_t)j * ldw + i];
+    i = e - j * (j + 1) / 2;
+  };
+  if (kLds) {
+    for (int e = t; e < np; e += 1024) {
+      int i, j;
+      unpack(e, i, j);
+      ch_lds[e] = W[(int64_t)j * ldw + i];
+    }
   }
   for (int k = t; k < N; k += 1024) d0s[k] = W[(int64_t)k * ldw + k];
   if (t == 0) nbad = 0;
   __syncthreads();
   for (int k = 0; k < N; ++k) {
     if (t == 0) {
-      const double d = P[idx(k, k)];
+      const double d = P(k, k);
       if (!(d > rel_floor * d0s[k]) || !(d > 0.0) || !isfinite(d)) {
         piv = 0.0;
         ++nbad;
@@ -196,18 +208,18 @@ __global__ __launch_bounds__(1024) void chol_inv_lds_kernel(double* W, int64_t l
     }
     __syncthreads();
     const double p = piv;
-    for (int j = k + 1 + t; j < N; j += 1024) P[idx(k, j)] = (p > 0.0) ? P[idx(k, j)] / p : 0.0;
+    for (int j = k + 1 + t; j < N; j += 1024) P(k, j) = (p > 0.0) ? P(k, j) / p : 0.0;
     __syncthreads();
-    if (t == 0) P[idx(k, k)] = (p > 0.0) ? p : 1.0;
+    if (t == 0) P(k, k) = (p > 0.0) ? p : 1.0;
     // trailing update of the upper triangle: (i, j), k < i <= j
     const int rem = N - k - 1;
     const int tot = rem * (rem + 1) / 2;
     for (int e = t; e < tot; e += 1024) {
-      int jj = (int)((sqrtf(8.0f * (float)e + 1.0f) - 1.0f) * 0.5f);
-      while (jj * (jj + 1) / 2 > e) --jj;
-      while ((jj + 1) * (jj + 2) / 2 <= e) ++jj;
-      const int i = k + 1 + (e - jj * (jj + 1) / 2), j = k + 1 + jj;
-      P[idx(i, j)] -= P[idx(k, i)] * P[idx(k, j)];
+      int i, j;
+      unpack(e, i, j);
+      i += k + 1;
+      j += k + 1;
+      P(i, j) -= P(k, i) * P(k, j);
     }
     __syncthreads();
   }
@@ -216,17 +228,24 @@ __global__ __launch_bounds__(1024) void chol_inv_lds_kernel(double* W, int64_t l
   for (int i = N - 1; i >= 0; --i) {
     for (int j = i + (t >> 3); j < N; j += 128) {
       double s = 0.0;
-      for (int l = i + 1 + sub; l <= j; l += 8) s += P[idx(i, l)] * Iv[idx(l, j)];
+      for (int l = i + 1 + sub; l <= j; l += 8) s += P(i, l) * Iv(l, j);
 #pragma unroll
       for (int off = 4; off > 0; off >>= 1) s += __shfl_xor(s, off, 8);
-      if (sub == 0) Iv[idx(i, j)] = (j == i) ? 1.0 / P[idx(i, i)] : -s / P[idx(i, i)];
+      if (sub == 0) Iv(i, j) = (j == i) ? 1.0 / P(i, i) : -s / P(i, i);
     }
     __syncthreads();
   }
-  for (int e = t; e < N * N; e += 1024) {
-    const int j = e / N, i = e - j * N;
-    if (i <= j) W[(int64_t)j * ldw + i] = P[idx(i, j)];
-    Rinv[(int64_t)i * ldr + j] = (i <= j) ? Iv[idx(i, j)] : 0.0;
+  if (kLds) {
+    for (int e = t; e < N * N; e += 1024) {
+      const int j = e / N, i = e - j * N;
+      if (i <= j) W[(int64_t)j * ldw + i] = P(i, j);
+      Rinv[(int64_t)i * ldr + j] = (i <= j) ? Iv(i, j) : 0.0;
+    }
+  } else {
+    for (int e = t; e < N * N; e += 1024) {
+      const int j = e / N, i = e - j * N;
+      if (i > j) Rinv[(int64_t)i * ldr + j] = 0.0;
+    }
   }
   if (t == 0 && bad) *bad = nbad;
 }
@@ -262,17 +281,26 @@ hapod_status launch_gather_cols(const void* const* d_cols, const int64_t* d_rbs,
   return HAPOD_OK;
 }
 
-hapod_status launch_chol_inv_lds(double* W, int64_t ldw, int64_t N, double* Rinv, int64_t ldr, int32_t* d_bad,
-                                 hipStream_t stream, double rel_floor) {
+hapod_status launch_chol_inv_wg(double* W, int64_t ldw, int64_t N, double* Rinv, int64_t ldr, int32_t* d_bad,
+                                hipStream_t stream, double rel_floor) {
   if (N <= 0) return HAPOD_OK;
-  static bool attr = false;
-  if (!attr) {
-    HAPOD_HIP(hipFuncSetAttribute((const void*)chol_inv_lds_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  (int)(sizeof(double) * kCholLdsMaxN * (kCholLdsMaxN + 1))));
-    attr = true;
+  if (N > kCholWgMaxN) {
+    set_error("Cholesky: N above 1024");
+    return HAPOD_E_UNSUPPORTED;
   }
-  hipLaunchKernelGGL(chol_inv_lds_kernel, dim3(1), dim3(1024), sizeof(double) * N * (N + 1), stream, W, ldw, (int)N,
-                     Rinv, ldr, d_bad, rel_floor);
+  if (N <= kCholLdsMaxN) {
+    static bool attr = false;
+    if (!attr) {
+      HAPOD_HIP(hipFuncSetAttribute((const void*)chol_inv_wg_kernel<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)(sizeof(double) * kCholLdsMaxN * (kCholLdsMaxN + 1))));
+      attr = true;
+    }
+    hipLaunchKernelGGL(chol_inv_wg_kernel<true>, dim3(1), dim3(1024), sizeof(double) * N * (N + 1), stream, W, ldw,
+                       (int)N, Rinv, ldr, d_bad, rel_floor);
+  } else {
+    hipLaunchKernelGGL(chol_inv_wg_kernel<false>, dim3(1), dim3(1024), 0, stream, W, ldw, (int)N, Rinv, ldr, d_bad,
+                       rel_floor);
+  }
   HAPOD_HIP(hipGetLastError());
   return HAPOD_OK;
 }
