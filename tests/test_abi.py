@@ -102,3 +102,37 @@ def test_plan_rejects_bad_leaf_rows():
         hp.Plan(synth.star_tree(2), [3, 3, 0], 10, 1e-3, 0.5, leaf_rows=[5, 11, 0])
     assert e.value.status == 1
     hp.Plan(synth.star_tree(2), [3, 3, 0], 10, 1e-3, 0.5, leaf_rows=[5, 10, 0])
+
+
+def test_header_declares_the_next_rows():
+    names = header_functions()
+    for must in ["hapod_right_vectors", "hapod_node_pod_qr"]:
+        assert must in names
+
+
+@pytest.mark.parametrize("kw", [
+    {"prec": "fp32", "block_gram": True},
+    {"prec": "bf16x3", "block_gram": True},
+    {"prec": "fp32", "qr_pod": True},
+    {"prec": "bf16x3", "qr_pod": True},
+    {"prec": "fp64", "qr_pod": True, "right_vectors": True},
+])
+def test_plan_rejects_option_combinations(kw):
+    """Host-side plan rules: the block-structured Gram and the QR route need
+    the FP64 form; the QR route keeps no right singular vectors."""
+    hp = pytest.importorskip("paper_1607_05210_amd")
+    with pytest.raises(hp.HapodError):
+        hp.Plan(synth.star_tree(2), [4, 4, 0], 64, 1e-3, 0.5, **kw)
+
+
+def test_plan_accepts_the_fp64_options():
+    hp = pytest.importorskip("paper_1607_05210_amd")
+    hp.Plan(synth.star_tree(2), [4, 4, 0], 64, 1e-3, 0.5, prec="fp64", qr_pod=True, block_gram=True)
+    hp.Plan(synth.star_tree(2), [4, 4, 0], 64, 1e-3, 0.5, prec="fp64", right_vectors=True)
+
+
+def test_right_vectors_before_a_run_is_an_error():
+    hp = pytest.importorskip("paper_1607_05210_amd")
+    plan = hp.Plan(synth.star_tree(2), [4, 4, 0], 64, 1e-3, 0.5, prec="fp64", right_vectors=True)
+    with pytest.raises(hp.HapodError):
+        plan.right_vectors()
