@@ -428,7 +428,7 @@ hapod_status run_pod_batch(hapod_precision prec, std::vector<PodJob>& jobs, int 
   // ---- sizes & scratch layout ---------------------------------------------
   struct Lay {
     size_t cols, rbs, crows, cols2, rbs2, crows2, G, partial, lam, V, B, B32, sigma, rank, info, jwork, vwork, sweeps;
-    bool presplit;
+    bool presplit, own256;
     int tile, slots, ntiles, pairs, nchunks;
     int64_t chunk_rows;
   };
@@ -509,6 +509,11 @@ hapod_status run_pod_batch(hapod_precision prec, std::vector<PodJob>& jobs, int 
     // pre-split nodes above 256 columns take 256-column tiles (eight
     // wavefronts of 128 x 64: half the LDS reads per product)
     if (L.presplit && m > kStageSplitMaxCols && L.tile == 128) L.tile = 256;
+    // split-BF16 nodes of 129 .. 256 columns: one 256-column tile staged from
+    // their own FP32 columns, each value read once (three 128-column tile
+    // pairs read every column twice)
+    L.own256 = (compute == 2 && !L.presplit && L.tile == 128 && m > 128 && m <= kStageSplitMaxCols);
+    if (L.own256) L.tile = 256;
     L.ntiles = (int)((m + L.tile - 1) / L.tile);
     L.pairs = L.ntiles * (L.ntiles + 1) / 2;
     // (sum_pairs counts 128-column pairs: a node on 256-column tiles, whose
@@ -594,8 +599,9 @@ hapod_status run_pod_batch(hapod_precision prec, std::vector<PodJob>& jobs, int 
   std::vector<GramItem> gitems;
   // per twin group: (default compute, FP32) x (tile 128, 64, 32, 16) x (scalar,
   // vector runs), slot 16: split-BF16 128-column tiles staged through LDS,
-  // slot 17: pre-split 256-column tiles
-  std::vector<std::array<std::vector<GramItem>, 18>> items_by_tile(ngroups);
+  // slot 17: pre-split 256-column tiles, slot 18: 256-column tiles staged
+  // from FP32 columns
+  std::vector<std::array<std::vector<GramItem>, 19>> items_by_tile(ngroups);
   auto tile_slot = [](int t) { return t == 128 ? 0 : t == 64 ? 1 : t == 32 ? 2 : 3; };
   int max_reduce_tile = 0;
   std::vector<int32_t> rpairs, rnode;
@@ -635,7 +641,8 @@ hapod_status run_pod_batch(hapod_precision prec, std::vector<PodJob>& jobs, int 
     const bool f32 = (node_compute(m) != compute);
     const bool staged = !f32 && compute == 2 && L.tile == 128;
     std::vector<GramItem>& gi =
-        items_by_tile[twin_group[i]][L.tile == 256 ? 17 : staged ? 16 : (f32 ? 8 : 0) + 2 * tile_slot(L.tile) + (vec ? 1 : 0)];
+        items_by_tile[twin_group[i]][L.tile == 256 ? (L.own256 ? 18 : 17)
+                                     : staged ? 16 : (f32 ? 8 : 0) + 2 * tile_slot(L.tile) + (vec ? 1 : 0)];
     // Item order.  The workgroups an XCD runs at once take consecutive items
     // (see xcd_item), so consecutive items should share column blocks: for
     // each row chunk, the tile pairs go in super-tiles of kSuperI x kSuperJ
@@ -724,11 +731,12 @@ hapod_status run_pod_batch(hapod_precision prec, std::vector<PodJob>& jobs, int 
   }
   std::vector<std::vector<GramLaunch>> glaunch(ngroups);
   for (int gr = 0; gr < ngroups; ++gr)
-    for (int t = 0; t < 18; ++t) {
+    for (int t = 0; t < 19; ++t) {
       const auto& v = items_by_tile[gr][t];
       if (v.empty()) continue;
       if (t >= 16)
-        glaunch[gr].push_back(GramLaunch{t == 17 ? 256 : 128, 2, (int32_t)gitems.size(), (int32_t)v.size(), -1});
+        glaunch[gr].push_back(GramLaunch{t == 16 ? 128 : 256, t == 18 ? 3 : 2, (int32_t)gitems.size(),
+                                         (int32_t)v.size(), -1});
       else
         glaunch[gr].push_back(GramLaunch{128 >> ((t & 7) / 2), t & 1, (int32_t)gitems.size(), (int32_t)v.size(),
                                          t >= 8 ? 1 : -1});

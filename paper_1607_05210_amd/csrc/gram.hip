@@ -430,6 +430,12 @@ store:
 // instead of 48 per 16), which relieves the LDS bandwidth that bounds the
 // 128-column tiles.  Same products in the same order for every entry of G,
 // so a row chunk's partial sums are those of the 128-column path.
+// kTwin = false: a node of at most 256 columns (one diagonal tile pair) read
+// from its own FP32 columns; each thread loads rows 4 part .. 4 part + 3 of
+// a 32-row step of four columns and splits them into hi and lo as they go to
+// LDS (rows past a column's own read as zero), as the 128-column staged path
+// does, so every value leaves HBM once.
+template <bool kTwin>
 __global__ __launch_bounds__(512, 1) void gram_bf16_t256_kernel(const GramNode* __restrict__ nodes,
                                                                 const GramItem* __restrict__ items, int first) {
   constexpr int TT = 256, NBA = 8, NBB = 4, NBT = kRowBlock / 32;
@@ -460,23 +466,72 @@ __global__ __launch_bounds__(512, 1) void gram_bf16_t256_kernel(const GramNode* 
   const int poff = (part < 4) ? part : 16 + (part - 4);  // bf8 offset in the step
   const int64_t S = nblk * NBT;
   i4 pre[8];
+  // FP32 columns (kTwin = false, diagonal tile of a node of <= 256 columns:
+  // four columns per thread)
+  constexpr int kOwn = kTwin ? 1 : 4;
+  const float* cp[kOwn];
+  int64_t cs[kOwn], cr[kOwn];
+  if constexpr (!kTwin) {
+#pragma unroll
+    for (int i = 0; i < kOwn; ++i) {
+      const int c = min(item.ti * TT + 64 * i + (t >> 3), nd.m - 1);  // columns past m alias the last one
+      cp[i] = reinterpret_cast<const float*>(nd.cols[c]);
+      cs[i] = nd.rbs[c];
+      cr[i] = nd.crows[c];
+    }
+  }
   auto gload = [&](int64_t st) {
     const int64_t blk = blk0 + st / NBT;
     const int bt = (int)(st % NBT);
-    const float* bp = tw + blk * trb;
+    if constexpr (kTwin) {
+      const float* bp = tw + blk * trb;
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      if (i >= nld) continue;
-      const int cl = 64 * i + (t >> 3);
-      const int base = (cl < 256) ? item.ti * TT + cl : item.tj * TT + (cl - 256);
-      const int c = min(base, nd.m - 1);  // columns past m alias the last one
-      pre[i] = ((gptr<i4>)as_global(bp + (int64_t)c * kRowBlock))[4 * bt + poff];
+      for (int i = 0; i < 8; ++i) {
+        if (i >= nld) continue;
+        const int cl = 64 * i + (t >> 3);
+        const int base = (cl < 256) ? item.ti * TT + cl : item.tj * TT + (cl - 256);
+        const int c = min(base, nd.m - 1);  // columns past m alias the last one
+        pre[i] = ((gptr<i4>)as_global(bp + (int64_t)c * kRowBlock))[4 * bt + poff];
+      }
+    } else {
+      const int roff = 32 * bt + 4 * part;  // row in the block
+      const int64_t row = (blk << 7) + roff;
+#pragma unroll
+      for (int i = 0; i < kOwn; ++i) {
+        const float* p = cp[i] + blk * cs[i] + roff;
+        const int64_t avail = cr[i] - row;
+        if (avail >= 4 && (((uintptr_t)p & 15u) == 0)) {
+          pre[i] = *(gptr<i4>)as_global(reinterpret_cast<const i4*>(p));
+        } else {
+          float x[4];
+#pragma unroll
+          for (int e = 0; e < 4; ++e) x[e] = (e < avail) ? p[e] : 0.f;
+          pre[i] = *reinterpret_cast<const i4*>(x);
+        }
+      }
     }
   };
   auto lstore = [&](int buf) {
+    if constexpr (kTwin) {
 #pragma unroll
-    for (int i = 0; i < 8; ++i)
-      if (i < nld) *(i4*)(stage[buf] + (64 * i + (t >> 3)) * kColB + part * 16) = pre[i];
+      for (int i = 0; i < 8; ++i)
+        if (i < nld) *(i4*)(stage[buf] + (64 * i + (t >> 3)) * kColB + part * 16) = pre[i];
+    } else {
+#pragma unroll
+      for (int i = 0; i < kOwn; ++i) {
+        const float* x = reinterpret_cast<const float*>(&pre[i]);
+        uint16_t h[4], l[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          h[e] = bf16_bits_rne(x[e]);
+          l[e] = bf16_bits_rne(x[e] - bf16_bits_to_float(h[e]));
+        }
+        char* q = stage[buf] + (64 * i + (t >> 3)) * kColB + part * 8;
+        typedef __attribute__((ext_vector_type(2))) int i2;
+        *(i2*)q = i2{(int)(h[0] | ((uint32_t)h[1] << 16)), (int)(h[2] | ((uint32_t)h[3] << 16))};
+        *(i2*)(q + 64) = i2{(int)(l[0] | ((uint32_t)l[1] << 16)), (int)(l[2] | ((uint32_t)l[3] << 16))};
+      }
+    }
   };
   f4 acc[NBA][NBB];
 #pragma unroll
@@ -627,9 +682,14 @@ hapod_status launch_gram_c(const GramNode* d_nodes, const GramItem* d_items, con
       set_error("launch_gram: tile must be 256, 128, 64, 32 or 16");
       return HAPOD_E_INVALID;
     }
-    if (L.vec == 2 && L.tile == 256) {
+    if ((L.vec == 2 || L.vec == 3) && L.tile == 256) {
       if constexpr (C == 2) {
-        hipLaunchKernelGGL(gram_bf16_t256_kernel, dim3(L.count), dim3(512), 0, stream, d_nodes, d_items, L.first);
+        if (L.vec == 2)
+          hipLaunchKernelGGL(gram_bf16_t256_kernel<true>, dim3(L.count), dim3(512), 0, stream, d_nodes, d_items,
+                             L.first);
+        else
+          hipLaunchKernelGGL(gram_bf16_t256_kernel<false>, dim3(L.count), dim3(512), 0, stream, d_nodes, d_items,
+                             L.first);
       } else {
         set_error("launch_gram: 256-column tiles are split-BF16 only");
         return HAPOD_E_INVALID;

@@ -243,6 +243,30 @@ def test_node_pod_against_svd_oracle(hp, n, m):
     np.testing.assert_allclose(host(W), host(U) * s, rtol=0, atol=1e-12 * sigma[0])
 
 
+@pytest.mark.parametrize("n,m", [(1000, 129), (4099, 200), (3000, 256), (5003, 130)])
+def test_node_pod_split_bf16_one_256_tile(hp, n, m):
+    """Split-BF16 nodes of 129..256 columns run their Gram as one 256-column
+    tile staged from their own FP32 columns (odd row counts: unaligned
+    column starts and a ragged last row block).  Against the SVD oracle on
+    the FP32-rounded input: sigma within the Gram perturbation bound
+    4 sqrt(n) u_p sigma_1^2 / sigma_k (u_p = 2^-17 for the split products),
+    the resolved leading modes' span, the rank within one."""
+    from oracle import metrics, pod
+    sigma = 10.0 * 0.8 ** np.arange(m)
+    S = prescribed_svd(n, m, sigma, n + m).astype(np.float32).astype(np.float64)
+    eps = math.sqrt(np.sum(sigma[30:] ** 2)) * 1.0001
+    s_ref, U_ref = pod.pod(S, eps)
+    s, U = hp.hapod_node_pod("bf16x3", dev_colmajor(S, torch.float32), eps)
+    assert abs(len(s) - len(s_ref)) <= 1
+    up = 2.0 ** -17
+    k = min(len(s), len(s_ref))
+    tol = 4.0 * math.sqrt(n) * up * s_ref[0] ** 2 / s_ref[:k]
+    assert np.all(np.abs(s[:k] - s_ref[:k]) <= tol)
+    r = metrics.resolved_rank(s_ref, len(s), up, 1e-2)
+    assert r >= 8
+    assert metrics.subspace_error(U_ref, host(U).astype(np.float64), r) <= 1e-2
+
+
 @pytest.mark.parametrize("m", [200, 250])
 def test_node_pod_exact_multiplicity(hp, m):
     """A lone node of 129..256 columns takes the full-length Krylov
