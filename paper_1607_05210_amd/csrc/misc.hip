@@ -7,17 +7,37 @@
 namespace hapod {
 namespace {
 
-__global__ __launch_bounds__(128) void split_cols_kernel(int64_t n, int64_t m, const void* const* cols,
+// The pre-split twin: for row block b and column c, 128 hi then 128 lo
+// bfloat16 values at dst + (b m + c) 128.  A thread splits a run of 4 rows
+// (one 16-byte load, two 8-byte stores); a 256-thread block covers 8 columns
+// of one row block.
+__global__ __launch_bounds__(256) void split_cols_kernel(int64_t n, int64_t m, const void* const* cols,
                                                          const int64_t* rbs, const int64_t* crows, float* dst) {
-  const int64_t b = blockIdx.x, c = blockIdx.y;
-  const int64_t r = b * kRowBlock + threadIdx.x;
-  const float* src = reinterpret_cast<const float*>(cols[c]);
-  const float x = (r < n && r < crows[c]) ? src[blk_off(r, rbs[c])] : 0.f;
-  const uint16_t h = bf16_bits_rne(x);
-  const uint16_t l = bf16_bits_rne(x - bf16_bits_to_float(h));
+  const int64_t b = blockIdx.x;
+  const int64_t c = (int64_t)blockIdx.y * 8 + (threadIdx.x >> 5);
+  if (c >= m) return;
+  const int q = threadIdx.x & 31;
+  const int64_t r = b * kRowBlock + 4 * q;
+  const float* src = reinterpret_cast<const float*>(cols[c]) + blk_off(r, rbs[c]);
+  const int64_t avail = min(n, crows[c]) - r;
+  float x[4];
+  if (avail >= 4 && (((uintptr_t)src & 15u) == 0)) {
+    const float4 v = *reinterpret_cast<const float4*>(src);
+    x[0] = v.x; x[1] = v.y; x[2] = v.z; x[3] = v.w;
+  } else {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) x[e] = (e < avail) ? src[e] : 0.f;
+  }
+  uint16_t h[4], l[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    h[e] = bf16_bits_rne(x[e]);
+    l[e] = bf16_bits_rne(x[e] - bf16_bits_to_float(h[e]));
+  }
   uint16_t* blk = reinterpret_cast<uint16_t*>(dst + (b * m + c) * kRowBlock);
-  blk[threadIdx.x] = h;
-  blk[kRowBlock + threadIdx.x] = l;
+  typedef __attribute__((ext_vector_type(2))) uint32_t u2;
+  *reinterpret_cast<u2*>(blk + 4 * q) = u2{h[0] | ((uint32_t)h[1] << 16), h[2] | ((uint32_t)h[3] << 16)};
+  *reinterpret_cast<u2*>(blk + kRowBlock + 4 * q) = u2{l[0] | ((uint32_t)l[1] << 16), l[2] | ((uint32_t)l[3] << 16)};
 }
 
 __global__ void fill_colptrs_kernel(const char* base, int64_t ld_bytes, int64_t m, const void** out) {
@@ -150,8 +170,8 @@ hapod_status launch_split_cols(int64_t n, int64_t m, const void* const* cols, co
     return HAPOD_E_UNSUPPORTED;
   }
   const unsigned nb = (unsigned)((n + kRowBlock - 1) / kRowBlock);
-  hipLaunchKernelGGL(split_cols_kernel, dim3(nb, (unsigned)m), dim3(kRowBlock), 0, stream, n, m, cols, rbs, crows,
-                     dst);
+  hipLaunchKernelGGL(split_cols_kernel, dim3(nb, (unsigned)((m + 7) / 8)), dim3(256), 0, stream, n, m, cols, rbs,
+                     crows, dst);
   HAPOD_HIP(hipGetLastError());
   return HAPOD_OK;
 }
