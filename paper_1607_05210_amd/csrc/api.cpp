@@ -662,13 +662,21 @@ hapod_status run_pod_batch(hapod_precision prec, std::vector<PodJob>& jobs, int 
         if (lo >= j.sblk[q].first && hi <= j.sblk[q].second) tile_blk[ti] = (int)q;
       }
     auto set_pair = [&](int ti, int tj) { return tile_blk[ti] >= 0 && tile_blk[ti] == tile_blk[tj]; };
+    // the rows a tile holds: the most of its columns' (inputs of uneven height
+    // leave whole row chunks zero for some tile pairs)
+    std::vector<int64_t> tile_rows(nt, 0);
+    for (int64_t c = 0; c < m; ++c) {
+      int64_t& tr = tile_rows[c / L.tile];
+      tr = std::max(tr, j.crows[(size_t)c]);
+    }
     for (int c = 0; c < L.nchunks; ++c)
       for (int I = 0; I < nt; I += kSuperI)
         for (int J = (I / kSuperJ) * kSuperJ; J < nt; J += kSuperJ)
           for (int ti = I; ti < std::min(I + kSuperI, nt); ++ti)
             for (int tj = std::max(J, ti); tj < std::min(J + kSuperJ, nt); ++tj)
               if (!set_pair(ti, tj))
-                gi.push_back(GramItem{i, (int16_t)ti, (int16_t)tj, c, pair_base + pair_of(ti, tj)});
+                gi.push_back(GramItem{i, (int16_t)ti, (int16_t)tj, c, pair_base + pair_of(ti, tj),
+                                      std::min(tile_rows[ti], tile_rows[tj])});
     for (int ti = 0; ti < nt; ++ti)
       for (int tj = ti; tj < nt; ++tj) {
         if (set_pair(ti, tj)) {
@@ -2040,6 +2048,11 @@ hapod_status gram_impl(int compute, int eb, int64_t n, int64_t m, const void* S,
   // split-BF16 above 256 columns: pre-split twin and 256-column tiles, as in
   // the level batches
   if (tile_override <= 0 && compute == 2 && m > kStageSplitMaxCols && n > 0) tile = 256;
+  // split-BF16 at 129 .. 256 columns on 128-column tiles: one 256-column tile
+  // staged from the FP32 columns, as the level batches run it (so the tile
+  // tuner times what the batches would run)
+  const bool own256 = (compute == 2 && tile == 128 && m > 128 && m <= kStageSplitMaxCols && n > 0);
+  if (own256) tile = 256;
   const int nt = (int)((m + tile - 1) / tile);
   const int pairs = nt * (nt + 1) / 2;
   const int KB = (compute == 2) ? 32 : 16;
@@ -2062,7 +2075,7 @@ hapod_status gram_impl(int compute, int eb, int64_t n, int64_t m, const void* S,
   // split-BF16 with several column tiles: read a split twin (as the level batch does)
   void* dsplit = nullptr;
   const int gc = (compute == 2 && m < kBf16MinCols) ? 1 : compute;
-  const bool presplit = (gc == 2 && (tile != 128 || m > kStageSplitMaxCols) && n > 0);
+  const bool presplit = (gc == 2 && !own256 && (tile != 128 || m > kStageSplitMaxCols) && n > 0);
   std::vector<const void*> cols_g = cols;
   std::vector<int64_t> rbs_g;
   if (presplit) {
@@ -2132,7 +2145,7 @@ hapod_status gram_impl(int compute, int eb, int64_t n, int64_t m, const void* S,
       }
       break;
     }
-    const int vec_mode = (gc == 2 && tile >= 128) ? 2 : (vec_ok ? 1 : 0);
+    const int vec_mode = own256 ? 3 : (gc == 2 && tile >= 128) ? 2 : (vec_ok ? 1 : 0);
     const GramLaunch gl{tile, vec_mode, 0, (int32_t)items.size(), gc != compute ? gc : -1};
     st = launch_gram(compute, (const GramNode*)(db + o_g), (const GramItem*)(db + o_i), &gl, 1,
                      (const int32_t*)(db + o_rp), (const int32_t*)(db + o_rn), (int)rp.size(), tile, stream);

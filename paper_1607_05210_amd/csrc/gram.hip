@@ -131,7 +131,7 @@ __global__ __launch_bounds__(256) void gram_tile_kernel(const GramNode* __restri
 
   // row range of this chunk; chunks start on 128-row block boundaries
   const int64_t r0 = (int64_t)item.chunk * nd.chunk_rows;
-  const int64_t r1 = min(nd.n, r0 + nd.chunk_rows);
+  const int64_t r1 = max(r0, min(min(nd.n, r0 + nd.chunk_rows), item.rlim));
 
   // column bases; columns past m alias the block's last column (their
   // products land in accumulator entries that are never stored)
@@ -451,7 +451,7 @@ __global__ __launch_bounds__(512, 1) void gram_bf16_t256_kernel(const GramNode* 
   // on a diagonal tile the blocks wholly below the diagonal mirror others
   const bool idle = (diag && wi * 128 >= wj * 64 + 64) || cA0 >= nd.m || cB0 >= nd.m;
   const int64_t r0 = (int64_t)item.chunk * nd.chunk_rows;
-  const int64_t r1 = min(nd.n, r0 + nd.chunk_rows);
+  const int64_t r1 = max(r0, min(min(nd.n, r0 + nd.chunk_rows), item.rlim));
   const int64_t blk0 = r0 >> 7, nblk = (r1 - r0 + kRowBlock - 1) >> 7;
 
   __shared__ __attribute__((aligned(16))) char stage[2][512 * kColB];

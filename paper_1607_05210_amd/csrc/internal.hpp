@@ -80,6 +80,10 @@ struct GramItem {
   int16_t ti, tj;
   int32_t chunk;
   int32_t pair;        // tile-pair index within the level
+  // rows past this are zero in every column of one of the two tiles (each
+  // column's rows past its own count read as zero): the item's row range is
+  // clipped to it; an item that starts past it writes a zero partial
+  int64_t rlim = INT64_MAX;
 };
 
 // compute: 0 = FP64 MFMA (double storage), 1 = FP32 MFMA (float storage),
