@@ -737,6 +737,35 @@ hapod_status run_pod_batch(hapod_precision prec, std::vector<PodJob>& jobs, int 
     rbs2_off[i] = blob.add_vec(rbs2[i]);
     rows2_off[i] = blob.add_vec(crows2[i]);
   }
+  // Launches whose nodes each have one tile pair (no column blocks to share
+  // in L2, so the super-tile order does not matter): nodes of very different
+  // heights give items of very different lengths.  Largest first on every
+  // XCD: xcd_item hands XCD x a contiguous range of the launch's items, so
+  // the k-th largest item goes to XCD k % 8, position k / 8 of its range.
+  for (int gr = 0; gr < ngroups; ++gr)
+  for (int slot = 0; slot < 19; ++slot) {
+    auto& v = items_by_tile[gr][slot];
+    const size_t N = v.size();
+    if (N < 16) continue;
+    bool single = true;
+    for (const GramItem& it : v) single = single && lay[it.node].pairs == 1;
+    if (!single) continue;
+    auto rows = [&](const GramItem& it) {
+      const Lay& L = lay[it.node];
+      const int64_t r0 = (int64_t)it.chunk * L.chunk_rows;
+      const int64_t r1 = std::min(std::min<int64_t>(jobs[it.node].n, r0 + L.chunk_rows), it.rlim);
+      return std::max<int64_t>(0, r1 - r0);
+    };
+    std::vector<GramItem> by_rows(v);
+    std::stable_sort(by_rows.begin(), by_rows.end(),
+                     [&](const GramItem& a, const GramItem& b) { return rows(a) > rows(b); });
+    const size_t q = N / 8, r = N % 8;
+    for (size_t k = 0; k < N; ++k) {
+      const size_t x = k % 8, pos = k / 8;
+      const size_t start = x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q;
+      v[start + pos] = by_rows[k];
+    }
+  }
   std::vector<std::vector<GramLaunch>> glaunch(ngroups);
   for (int gr = 0; gr < ngroups; ++gr)
     for (int t = 0; t < 19; ++t) {

@@ -467,8 +467,10 @@ __global__ __launch_bounds__(512, 1) void gram_bf16_t256_kernel(const GramNode* 
   const int64_t S = nblk * NBT;
   i4 pre[8];
   // FP32 columns (kTwin = false, diagonal tile of a node of <= 256 columns:
-  // four columns per thread)
+  // four columns per thread); their loads run two steps ahead (register
+  // slots 0 and 1), the twin's one (it has no registers to spare)
   constexpr int kOwn = kTwin ? 1 : 4;
+  i4 own[2][kOwn];
   const float* cp[kOwn];
   int64_t cs[kOwn], cr[kOwn];
   if constexpr (!kTwin) {
@@ -480,7 +482,7 @@ __global__ __launch_bounds__(512, 1) void gram_bf16_t256_kernel(const GramNode* 
       cr[i] = nd.crows[c];
     }
   }
-  auto gload = [&](int64_t st) {
+  auto gload = [&](int64_t st, int slot) {
     const int64_t blk = blk0 + st / NBT;
     const int bt = (int)(st % NBT);
     if constexpr (kTwin) {
@@ -500,18 +502,21 @@ __global__ __launch_bounds__(512, 1) void gram_bf16_t256_kernel(const GramNode* 
       for (int i = 0; i < kOwn; ++i) {
         const float* p = cp[i] + blk * cs[i] + roff;
         const int64_t avail = cr[i] - row;
+        i4 v;
         if (avail >= 4 && (((uintptr_t)p & 15u) == 0)) {
-          pre[i] = *(gptr<i4>)as_global(reinterpret_cast<const i4*>(p));
+          v = *(gptr<i4>)as_global(reinterpret_cast<const i4*>(p));
         } else {
           float x[4];
 #pragma unroll
           for (int e = 0; e < 4; ++e) x[e] = (e < avail) ? p[e] : 0.f;
-          pre[i] = *reinterpret_cast<const i4*>(x);
+          v = *reinterpret_cast<const i4*>(x);
         }
+        if (slot == 0) own[0][i] = v;
+        else own[1][i] = v;
       }
     }
   };
-  auto lstore = [&](int buf) {
+  auto lstore = [&](int buf, int slot) {
     if constexpr (kTwin) {
 #pragma unroll
       for (int i = 0; i < 8; ++i)
@@ -519,7 +524,8 @@ __global__ __launch_bounds__(512, 1) void gram_bf16_t256_kernel(const GramNode* 
     } else {
 #pragma unroll
       for (int i = 0; i < kOwn; ++i) {
-        const float* x = reinterpret_cast<const float*>(&pre[i]);
+        const i4 v = (slot == 0) ? own[0][i] : own[1][i];
+        const float* x = reinterpret_cast<const float*>(&v);
         uint16_t h[4], l[4];
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
@@ -561,16 +567,38 @@ __global__ __launch_bounds__(512, 1) void gram_bf16_t256_kernel(const GramNode* 
       }
     }
   };
-  if (S > 0) {
-    gload(0);
-    lstore(0);
-  }
-  __syncthreads();
-  for (int64_t st = 0; st < S; ++st) {
-    if (st + 1 < S) gload(st + 1);
-    if (!idle) compute((int)(st & 1));
-    if (st + 1 < S) lstore((int)((st + 1) & 1));
+  if constexpr (kTwin) {
+    if (S > 0) {
+      gload(0, 0);
+      lstore(0, 0);
+    }
     __syncthreads();
+    for (int64_t st = 0; st < S; ++st) {
+      if (st + 1 < S) gload(st + 1, 0);
+      if (!idle) compute((int)(st & 1));
+      if (st + 1 < S) lstore((int)((st + 1) & 1), 0);
+      __syncthreads();
+    }
+  } else {
+    // step s is staged in LDS buffer s & 1 from register slot s & 1; the
+    // loop takes two steps per turn so every slot index is a constant
+    if (S > 0) {
+      gload(0, 0);
+      if (S > 1) gload(1, 1);
+      lstore(0, 0);
+    }
+    __syncthreads();
+    for (int64_t st = 0; st < S; st += 2) {
+      if (st + 2 < S) gload(st + 2, 0);
+      if (!idle) compute(0);
+      if (st + 1 < S) lstore(1, 1);
+      __syncthreads();
+      if (st + 1 >= S) break;
+      if (st + 3 < S) gload(st + 3, 1);
+      if (!idle) compute(1);
+      if (st + 2 < S) lstore(0, 0);
+      __syncthreads();
+    }
   }
   if (idle) return;
   if (nd.nchunks == 1) {
