@@ -1142,7 +1142,7 @@ hapod_status qr_pod_core(Pool& pool, int64_t n, int64_t m, double* S, int64_t ld
   const size_t mm = sizeof(double) * (size_t)m * m;
   void *G = nullptr, *Rinv = nullptr, *Rk = nullptr, *Racc = nullptr, *Rtmp = nullptr, *Bm = nullptr, *dsig = nullptr,
        *QA = nullptr, *QB = nullptr, *dcols = nullptr, *dn = nullptr, *drank = nullptr, *dbad = nullptr,
-       *drbs = nullptr, *drows = nullptr, *dinfo = nullptr, *drbs_t = nullptr;
+       *drbs = nullptr, *drows = nullptr, *dinfo = nullptr, *drbs_t = nullptr, *dzero = nullptr, *dD = nullptr;
   std::vector<void*> held;
   auto finish = [&](hapod_status st) {
     (void)hipStreamSynchronize(stream);
@@ -1154,7 +1154,8 @@ hapod_status qr_pod_core(Pool& pool, int64_t n, int64_t m, double* S, int64_t ld
       {s_scratch ? 0 : tiled_bytes(n, m, 8), &QA}, {tiled_bytes(n, m, 8), &QB},
       {sizeof(void*) * (kQrMaxPasses + 1) * m, &dcols}, {sizeof(LiftNode) * (kQrMaxPasses + 1), &dn},
       {sizeof(int64_t), &drank}, {sizeof(int32_t) * kQrMaxPasses, &dbad}, {sizeof(int64_t) * m, &drbs},
-      {sizeof(int64_t) * m, &drows}, {sizeof(int32_t), &dinfo}, {sizeof(int64_t) * m, &drbs_t}};
+      {sizeof(int64_t) * m, &drows}, {sizeof(int32_t), &dinfo}, {sizeof(int64_t) * m, &drbs_t},
+      {sizeof(int32_t) * m, &dzero}, {sizeof(double) * m, &dD}};
   for (const auto& w : want) {
     if (w.first == 0) continue;
     hapod_status st = pool.alloc(w.first, w.second);
@@ -1163,7 +1164,8 @@ hapod_status qr_pod_core(Pool& pool, int64_t n, int64_t m, double* S, int64_t ld
   }
   hapod_status st = HAPOD_OK;
   const int64_t trbs = tiled_rbs(m);
-  if ((st = launch_fill_i64((int64_t*)drbs, kRowBlock, m, stream)) != HAPOD_OK ||
+  if ((st = launch_zero_bytes(dzero, sizeof(int32_t) * m, stream)) != HAPOD_OK ||
+      (st = launch_fill_i64((int64_t*)drbs, kRowBlock, m, stream)) != HAPOD_OK ||
       (st = launch_fill_i64((int64_t*)drbs_t, trbs, m, stream)) != HAPOD_OK ||
       (st = launch_fill_i64((int64_t*)drows, n, m, stream)) != HAPOD_OK)
     return finish(st);
@@ -1206,6 +1208,12 @@ hapod_status qr_pod_core(Pool& pool, int64_t n, int64_t m, double* S, int64_t ld
   // the shift of shifted Cholesky-QR (tr >= ||Q||_2^2), which lifts the
   // directions S nearly lacks by about s^-1/2 per pass; the others are
   // plain.  Two plain passes in a row leave Q orthonormal to rounding.
+  // The first pass factors the equilibrated Gram D^-1 S^T S D^-1 (D the
+  // column norms), so columns of very different size (a bump far from a
+  // short leaf's rows is 1e-100 of its neighbours) start on equal terms:
+  // R_1 = R_1' D, R_1^-1 = D^-1 R_1'^-1.  A column with a zero Gram diagonal
+  // factors as a unit column, stays zero in every Q, and its row of R is
+  // cleared before the SVD (singular value 0).
   const double u = 1.1102230246251565e-16;
   if (s_scratch) QA = S;  // pass 0 writes QB, pass 1 may overwrite S
   const double* src = S;
@@ -1216,6 +1224,8 @@ hapod_status qr_pod_core(Pool& pool, int64_t n, int64_t m, double* S, int64_t ld
   int plain_run = 0, pass = 0;
   for (; pass < kQrMaxPasses && plain_run < 2; ++pass) {
     if ((st = gram_impl(0, 8, n, m, src, ld, (double*)G, m, stream, 0, src_tiled ? trbs : 0)) != HAPOD_OK ||
+        (st = launch_gram_zero_scale((double*)G, m, m, (int32_t*)dzero, pass == 0 ? (double*)dD : nullptr,
+                                     stream)) != HAPOD_OK ||
         (st = launch_identity_dev((double*)G, m, m, d_dev, stream)) != HAPOD_OK)
       return finish(st);
     double dev = 0.0;
@@ -1230,6 +1240,8 @@ hapod_status qr_pod_core(Pool& pool, int64_t n, int64_t m, double* S, int64_t ld
       return finish(st);
     if ((st = launch_chol_inv((double*)G, m, m, (double*)Rinv, m, (int32_t*)dbad + pass, stream, 0.0)) != HAPOD_OK ||
         (st = launch_triu((double*)G, m, m, pass == 0 ? (double*)Racc : (double*)Rk, m, stream)) != HAPOD_OK)
+      return finish(st);
+    if (pass == 0 && (st = launch_unscale_factors((double*)Racc, m, (double*)Rinv, m, m, (double*)dD, stream)) != HAPOD_OK)
       return finish(st);
     if (pass > 0) {
       if ((st = launch_dgemm_nn(m, m, m, (double*)Rk, m, (double*)Racc, m, (double*)Rtmp, m, stream)) != HAPOD_OK)
@@ -1258,6 +1270,7 @@ hapod_status qr_pod_core(Pool& pool, int64_t n, int64_t m, double* S, int64_t ld
     return finish(HAPOD_E_NUMERIC);
   }
   if (passes) *passes = pass;
+  if ((st = launch_zero_rows((double*)Racc, m, m, (int32_t*)dzero, stream)) != HAPOD_OK) return finish(st);
   // one-sided Jacobi SVD of R: R V = U_R diag(sigma); B = U_R (diag(sigma))
   if ((st = launch_osj((double*)Racc, m, (double*)dsig, (double*)Bm, scaled ? 1 : 0, (int32_t*)dinfo, stream)) !=
       HAPOD_OK)

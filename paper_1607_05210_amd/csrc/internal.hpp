@@ -247,6 +247,14 @@ hapod_status launch_gather_cols(const void* const* d_cols, const int64_t* d_rbs,
                                 int64_t m, double* dst, int64_t dst_rbs, hipStream_t stream);
 // out[0] = max over the upper triangle of |G_ij - delta_ij|
 hapod_status launch_identity_dev(const double* G, int64_t ldg, int64_t m, double* out, hipStream_t stream);
+// zero[j] |= (G_jj == 0); with D (non-null): D_j = sqrt(G_jj) (1 for zero
+// columns) and G <- D^-1 G D^-1; zero columns' diagonal set to 1
+hapod_status launch_gram_zero_scale(double* G, int64_t ldg, int64_t m, int32_t* zero, double* D, hipStream_t stream);
+// R (column-major) column j *= D_j, Rinv (row-major) row i /= D_i
+hapod_status launch_unscale_factors(double* R, int64_t ldr, double* Rinv, int64_t ldi, int64_t m, const double* D,
+                                    hipStream_t stream);
+// row j of R (column-major) = 0 where zero[j]
+hapod_status launch_zero_rows(double* R, int64_t ldr, int64_t m, const int32_t* zero, hipStream_t stream);
 // R = upper triangle of W, zeros below (both column-major)
 hapod_status launch_triu(const double* W, int64_t ldw, int64_t N, double* R, int64_t ldr, hipStream_t stream);
 // one-sided Jacobi SVD of A (m x m, column-major, ld m, overwritten): sigma

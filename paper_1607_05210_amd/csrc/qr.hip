@@ -58,6 +58,46 @@ __global__ __launch_bounds__(256) void identity_dev_kernel(const double* __restr
   if (threadIdx.x == 0) out[0] = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
 }
 
+// Column equilibration and zero columns of a Gram matrix G = Q^T Q (upper
+// triangle used).  zero[j] |= (G_jj == 0); with D: D_j = sqrt(G_jj) (1 for a
+// zero column) and G <- D^-1 G D^-1; then every zero column's diagonal is
+// set to 1, so that it factors as a unit column (its Q column stays zero).
+__global__ __launch_bounds__(256) void gram_zero_scale_kernel(double* G, int64_t ldg, int64_t m, int32_t* zero,
+                                                              double* D) {
+  for (int64_t j = threadIdx.x; j < m; j += 256) {
+    const double d = G[j * ldg + j];
+    if (d == 0.0) zero[j] = 1;
+    if (D) D[j] = d > 0.0 ? sqrt(d) : 1.0;
+  }
+  __syncthreads();
+  for (int64_t e = threadIdx.x; e < m * m; e += 256) {
+    const int64_t j = e / m, i = e - j * m;
+    if (i > j) continue;
+    double g = G[j * ldg + i];
+    if (D) g = g / (D[i] * D[j]);
+    if (i == j && zero[j]) g = 1.0;
+    G[j * ldg + i] = g;
+  }
+}
+
+// R (column-major) column j *= D_j; Rinv (row-major) row i *= 1 / D_i
+__global__ void unscale_factors_kernel(double* R, int64_t ldr, double* Rinv, int64_t ldi, int64_t m,
+                                       const double* D) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= m * m) return;
+  const int64_t j = e / m, i = e - j * m;
+  R[j * ldr + i] *= D[j];
+  Rinv[i * ldi + j] /= D[i];
+}
+
+// row j of R (column-major m x m) = 0 for every zero column j
+__global__ void zero_rows_kernel(double* R, int64_t ldr, int64_t m, const int32_t* zero) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= m * m) return;
+  const int64_t c = e / m, j = e - c * m;
+  if (zero[j]) R[c * ldr + j] = 0.0;
+}
+
 // R = upper triangle of W (column-major), zeros below
 __global__ void triu_kernel(const double* __restrict__ W, int64_t ldw, int64_t N, double* __restrict__ R, int64_t ldr) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y;
@@ -315,6 +355,29 @@ hapod_status launch_shift_diag(double* G, int64_t ldg, int64_t m, double coef, h
 hapod_status launch_identity_dev(const double* G, int64_t ldg, int64_t m, double* out, hipStream_t stream) {
   if (m <= 0) return HAPOD_OK;
   hipLaunchKernelGGL(identity_dev_kernel, dim3(1), dim3(256), 0, stream, G, ldg, m, out);
+  HAPOD_HIP(hipGetLastError());
+  return HAPOD_OK;
+}
+
+hapod_status launch_gram_zero_scale(double* G, int64_t ldg, int64_t m, int32_t* zero, double* D, hipStream_t stream) {
+  if (m <= 0) return HAPOD_OK;
+  hipLaunchKernelGGL(gram_zero_scale_kernel, dim3(1), dim3(256), 0, stream, G, ldg, m, zero, D);
+  HAPOD_HIP(hipGetLastError());
+  return HAPOD_OK;
+}
+
+hapod_status launch_unscale_factors(double* R, int64_t ldr, double* Rinv, int64_t ldi, int64_t m, const double* D,
+                                    hipStream_t stream) {
+  if (m <= 0) return HAPOD_OK;
+  hipLaunchKernelGGL(unscale_factors_kernel, dim3((unsigned)((m * m + 255) / 256)), dim3(256), 0, stream, R, ldr, Rinv,
+                     ldi, m, D);
+  HAPOD_HIP(hipGetLastError());
+  return HAPOD_OK;
+}
+
+hapod_status launch_zero_rows(double* R, int64_t ldr, int64_t m, const int32_t* zero, hipStream_t stream) {
+  if (m <= 0) return HAPOD_OK;
+  hipLaunchKernelGGL(zero_rows_kernel, dim3((unsigned)((m * m + 255) / 256)), dim3(256), 0, stream, R, ldr, m, zero);
   HAPOD_HIP(hipGetLastError());
   return HAPOD_OK;
 }

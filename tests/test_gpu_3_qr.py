@@ -145,6 +145,24 @@ def test_shapes(hp, n, m):
     print(f"  rank {len(s_qr)}, passes {info['passes']}, sweeps {info['sweeps']}")
 
 
+def test_zero_tiny_and_duplicate_columns(hp):
+    """An exactly zero column, a column whose Gram diagonal underflows, a
+    column 1e-98 of its neighbours and an exact duplicate: the first pass
+    works on the equilibrated Gram, zero columns factor as unit columns
+    (singular value 0); the result is the oracle's."""
+    rng = np.random.default_rng(0)
+    n, m = 1500, 40
+    S = rng.standard_normal((n, m)) * (0.7 ** np.arange(m))
+    S[:, 5] = 0.0
+    S[:, 9] *= 1e-98
+    S[:, 17] *= 1e-170
+    S[:, 20] = S[:, 3]
+    eps = 1e-12 * np.linalg.norm(S)
+    s_qr, U_qr, info = hp.hapod_node_pod_qr(dev_colmajor(S), eps)
+    print(f"  zero/tiny/duplicate: rank {len(s_qr)}, passes {info['passes']}, sweeps {info['sweeps']}")
+    check_against_oracle(S, s_qr, host(U_qr), eps, "zero/tiny")
+
+
 def test_passthrough_and_limits(hp):
     S = np.random.default_rng(0).standard_normal((40, 6))
     s, U, info = hp.hapod_node_pod_qr(dev_colmajor(S), 0.0)
@@ -260,3 +278,34 @@ def test_tree_qr_route_plan_rules(hp):
     for kw in ({"prec": "fp32"}, {"prec": "bf16x3"}, {"prec": "fp64", "right_vectors": True}):
         with pytest.raises(hp.HapodError):
             hp.Plan(synth.star_tree(2), [4, 4, 0], 64, 1e-3, 0.5, qr_pod=True, **kw)
+
+
+def test_tree_qr_route_uneven_leaf_heights(hp):
+    """Leaves of different heights (implicit zero rows below each) under a
+    3-level tree, every node on the QR route: the gathered inputs read only
+    the rows each column holds, inner nodes hold the most of their
+    children's, and the root's modes are zero-filled below its own height.
+    Every node's rank is the oracle's (zero-padded leaves), the root's sigma
+    within 1e-12 sigma_1, and the modes orthonormal."""
+    from oracle import hapod, tolerances, tree
+    n = 6000
+    specs = synth.uneven_leaf_specs(16, seed=5, rows_range=(700, 4000), cols_range=(8, 40))
+    parent = synth.balanced_tree(16, 3)
+    cols = [sp["cols"] for sp in specs] + [0] * (len(parent) - 16)
+    rows = [sp["rows"] for sp in specs] + [0] * (len(parent) - 16)
+    data = {i: synth.uneven_leaf(sp, n) for i, sp in enumerate(specs)}
+    eps_star, omega = 1e-6, 0.75
+    plan = hp.Plan(parent, cols, n, eps_star, omega, prec="fp64", leaf_rows=rows, qr_pod=True)
+    plan.run({i: dev_colmajor(d) for i, d in data.items()})
+    sig, U = plan.modes()
+    U = host(U)
+    full = {i: np.vstack([d, np.zeros((n - d.shape[0], d.shape[1]))]) for i, d in data.items()}
+    eps = tolerances.hapod_tolerances(parent, cols, eps_star, omega)
+    ref = hapod.hapod(parent, full, eps)
+    root = tree.validate(parent)
+    assert plan.node_stats()["m_in"].max() <= 512  # every node within the QR route
+    assert list(plan.ranks()) == [len(ref[a][0]) for a in range(len(parent))]
+    s_ref = ref[root][0]
+    assert np.max(np.abs(sig - s_ref)) <= 1e-12 * s_ref[0]
+    assert metrics.orthonormality_error(U) <= 1e-13
+    assert np.all(U[max(rows):] == 0.0)
