@@ -149,7 +149,9 @@ hapod_status hapod_node_pod(hapod_precision prec, int64_t n, int64_t m,
  * Cholesky-QR passes Q <- Q R_p^-1, each shifted (Q^T Q + s I = R_p^T R_p
  * with s = 11 (n m + m (m + 1)) u trace(Q^T Q), Fukaya et al., SIAM J. Sci.
  * Comput. 2020) while m max|Q^T Q - I| > 1/2, until two plain passes
- * follow each other; the SVD R V = U_R diag(sigma) by one-sided Jacobi;
+ * follow each other, the first on the column-equilibrated Gram (columns of
+ * any size start on equal terms; a column with a zero Gram diagonal gives
+ * singular value 0); the SVD R V = U_R diag(sigma) by one-sided Jacobi;
  * the modes Q U_R.  The sigma_k are accurate to about u sigma_1,
  * rank-deficient S included.
  * FP64 only; m <= 512 and m <= n (HAPOD_E_UNSUPPORTED otherwise, eps > 0).
