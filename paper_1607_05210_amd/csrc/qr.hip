@@ -107,7 +107,8 @@ __global__ void triu_kernel(const double* __restrict__ W, int64_t ldw, int64_t N
 // One-sided Jacobi on the columns of X (m x m, column-major, ld m): plane
 // rotations on column pairs until every pair is orthogonal to m u of its
 // norms; the pairs of a round are disjoint (round-robin order), a group of
-// 16 lanes per pair (four pairs per wavefront at once).  Then
+// 16 lanes per pair (four pairs per wavefront at once), the squared norms
+// carried across the rotations of a sweep.  Then
 // sigma_c = ||x_c||, sorted descending, and B (row-major, ld m) column p =
 // x_c (scaled) or x_c / sigma_c.  info: sweeps taken, or -1 without
 // convergence.
@@ -117,6 +118,7 @@ __global__ __launch_bounds__(kOsjThreads) void osj_kernel(double* A, int64_t m, 
   extern __shared__ double osj_lds[];
   __shared__ double sg[kQrMaxM];
   __shared__ int32_t pos[kQrMaxM];
+  __shared__ double nrm[kQrMaxM];  // squared column norms, carried across rotations
   __shared__ int nrot;
   double* X = kLds ? osj_lds : A;
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
@@ -131,6 +133,17 @@ __global__ __launch_bounds__(kOsjThreads) void osj_kernel(double* A, int64_t m, 
   for (; sweep < kOsjMaxSweeps && !done; ++sweep) {
     if (t == 0) nrot = 0;
     __syncthreads();
+    // exact squared norms at the start of every sweep; within it a rotation
+    // updates them (||x'||^2 = a - t g, ||y'||^2 = b + t g), so a pair needs
+    // one dot product instead of three
+    for (int64_t c = grp; c < m; c += kOsjGroups) {
+      double q = 0.0;
+      for (int64_t k = gl; k < m; k += kOsjGroup) q += X[c * m + k] * X[c * m + k];
+#pragma unroll
+      for (int off = kOsjGroup / 2; off > 0; off >>= 1) q += __shfl_xor(q, off, kOsjGroup);
+      if (gl == 0) nrm[c] = q;
+    }
+    __syncthreads();
     for (int64_t r = 0; r < mm - 1; ++r) {
       for (int64_t p = grp; p < mm / 2; p += kOsjGroups) {
         int64_t i, j;
@@ -144,19 +157,11 @@ __global__ __launch_bounds__(kOsjThreads) void osj_kernel(double* A, int64_t m, 
         if (i >= m || j >= m) continue;  // the padding index of an odd m
         double* ci = X + i * m;
         double* cj = X + j * m;
-        double a = 0.0, b = 0.0, g = 0.0;
-        for (int64_t k = gl; k < m; k += kOsjGroup) {
-          const double x = ci[k], y = cj[k];
-          a += x * x;
-          b += y * y;
-          g += x * y;
-        }
+        const double a = nrm[i], b = nrm[j];
+        double g = 0.0;
+        for (int64_t k = gl; k < m; k += kOsjGroup) g += ci[k] * cj[k];
 #pragma unroll
-        for (int off = kOsjGroup / 2; off > 0; off >>= 1) {
-          a += __shfl_xor(a, off, kOsjGroup);
-          b += __shfl_xor(b, off, kOsjGroup);
-          g += __shfl_xor(g, off, kOsjGroup);
-        }
+        for (int off = kOsjGroup / 2; off > 0; off >>= 1) g += __shfl_xor(g, off, kOsjGroup);
         if (!(a > 0.0) || !(b > 0.0) || fabs(g) <= tol * sqrt(a) * sqrt(b)) continue;
         // rotation [c s; -s c] that makes the pair orthogonal, the smaller angle
         const double zeta = (b - a) / (2.0 * g);
@@ -168,7 +173,11 @@ __global__ __launch_bounds__(kOsjThreads) void osj_kernel(double* A, int64_t m, 
           ci[k] = c * x - s * y;
           cj[k] = s * x + c * y;
         }
-        if (gl == 0) atomicAdd(&nrot, 1);
+        if (gl == 0) {
+          atomicAdd(&nrot, 1);
+          nrm[i] = fmax(a - tt * g, 0.0);
+          nrm[j] = b + tt * g;
+        }
       }
       __syncthreads();
     }
