@@ -126,7 +126,8 @@ __global__ __launch_bounds__(kOsjThreads) void osj_kernel(double* A, int64_t m, 
   if (kLds) {
     for (int64_t e = t; e < m * m; e += kOsjThreads) X[e] = A[e];
   }
-  const int64_t mm = m + (m & 1);
+  const int mi = (int)m;             // m <= 512: pair indices in 32-bit arithmetic
+  const int mm = mi + (mi & 1);
   const double tol = (double)m * 1.1102230246251565e-16;
   int sweep = 0;
   bool done = false;
@@ -144,22 +145,24 @@ __global__ __launch_bounds__(kOsjThreads) void osj_kernel(double* A, int64_t m, 
       if (gl == 0) nrm[c] = q;
     }
     __syncthreads();
-    for (int64_t r = 0; r < mm - 1; ++r) {
-      for (int64_t p = grp; p < mm / 2; p += kOsjGroups) {
-        int64_t i, j;
+    for (int r = 0; r < mm - 1; ++r) {
+      for (int p = grp; p < mm / 2; p += kOsjGroups) {
+        int i, j;
         if (p == 0) {
           i = mm - 1;
           j = r;
         } else {
-          i = (r + p) % (mm - 1);
-          j = (r - p + mm - 1) % (mm - 1);
+          i = r + p;
+          if (i >= mm - 1) i -= mm - 1;
+          j = r - p;
+          if (j < 0) j += mm - 1;
         }
-        if (i >= m || j >= m) continue;  // the padding index of an odd m
-        double* ci = X + i * m;
-        double* cj = X + j * m;
+        if (i >= mi || j >= mi) continue;  // the padding index of an odd m
+        double* ci = X + i * mi;
+        double* cj = X + j * mi;
         const double a = nrm[i], b = nrm[j];
         double g = 0.0;
-        for (int64_t k = gl; k < m; k += kOsjGroup) g += ci[k] * cj[k];
+        for (int k = gl; k < mi; k += kOsjGroup) g += ci[k] * cj[k];
 #pragma unroll
         for (int off = kOsjGroup / 2; off > 0; off >>= 1) g += __shfl_xor(g, off, kOsjGroup);
         if (!(a > 0.0) || !(b > 0.0) || fabs(g) <= tol * sqrt(a) * sqrt(b)) continue;
@@ -168,7 +171,7 @@ __global__ __launch_bounds__(kOsjThreads) void osj_kernel(double* A, int64_t m, 
         const double tt = fabs(zeta) > 1e150 ? 0.5 / zeta
                                              : (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
         const double c = 1.0 / sqrt(1.0 + tt * tt), s = c * tt;
-        for (int64_t k = gl; k < m; k += kOsjGroup) {
+        for (int k = gl; k < mi; k += kOsjGroup) {
           const double x = ci[k], y = cj[k];
           ci[k] = c * x - s * y;
           cj[k] = s * x + c * y;
