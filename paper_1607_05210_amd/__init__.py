@@ -14,6 +14,7 @@ from __future__ import annotations
 
 import ctypes as C
 import os
+import sys as _sys
 
 import torch
 
@@ -254,10 +255,18 @@ class Plan:
         self._keep = []
 
     def __del__(self):
+        # no HIP calls while the interpreter shuts down: the device memory a
+        # plan still holds goes back with the process
+        if _sys.is_finalizing():
+            return
+        self.close()
+
+    def close(self):
+        """Return the plan's device memory now (``hapod_destroy``)."""
         h = getattr(self, "_h", None)
         if h is not None and h.value:
             Plan._destroy(h)
-            self._h = None
+        self._h = None
 
     def query(self):
         import numpy as np

@@ -1074,10 +1074,13 @@ hapod_status check_prec(hapod_precision p) {
   return HAPOD_OK;
 }
 
-// Pool used by the step-level entry points (no plan).
+// Pool used by the step-level entry points (no plan).  Never destroyed: a
+// static object's destructor would call hipFree from the process's exit
+// handlers, after the HIP runtime (or a profiler attached to it) may already
+// have been torn down; the device memory goes back with the process.
 Pool& step_pool() {
-  static Pool p;
-  return p;
+  static Pool* p = new Pool;
+  return *p;
 }
 
 }  // namespace

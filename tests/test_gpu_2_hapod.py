@@ -17,7 +17,7 @@ pytestmark = pytest.mark.gpu
 
 import synth  # noqa: E402
 from gpu_util import dev_colmajor, host  # noqa: E402
-from oracle import hapod, metrics, tolerances, tree  # noqa: E402
+from oracle import hapod, metrics, pod, tolerances, tree  # noqa: E402
 
 
 @pytest.fixture(scope="module")
@@ -94,6 +94,10 @@ def test_star_4096x256(hp, prec, autotune):
     ranks = plan.ranks()
     if prec == "fp64":
         assert list(ranks[:4]) == [len(ref[i][0]) for i in range(4)]
+        # the root's last kept mode sits at the FP64 Gram's rounding floor:
+        # the clamped rule on the computed spectrum keeps the oracle's rank
+        # within one
+        assert abs(int(ranks[root]) - len(s_ref)) <= 1, (ranks[root], len(s_ref))
     r = metrics.resolved_rank(s_ref, len(sig), UP[prec], TAU[prec])
     assert r >= (100 if prec == "fp64" else 20)
     e_sub = metrics.subspace_error(U_ref, U, r)
@@ -174,10 +178,24 @@ def test_balanced_three_levels(hp, prec):
     r = metrics.resolved_rank(s_ref, len(sig), UP[prec], TAU[prec])
     assert metrics.subspace_error(U_ref, U, r) <= TAU[prec]
     if prec == "fp64":
-        # intermediate ranks agree with the oracle at every node
+        # A rank may differ from the oracle's only where the decision is below
+        # what an FP64 Gram resolves: each of a node's m computed eigenvalues
+        # carries an absolute error of about u lambda_1 (backward error of the
+        # eigensolver on a Gram formed in FP64), so its tail sums are known to
+        # m u lambda_1, and the oracle's tail at the GPU's rank must lie that
+        # close to eps^2.
         ranks = plan.ranks()
-        mism = [a for a in range(len(parent)) if ranks[a] != len(ref[a][0])]
-        assert len(mism) <= 2, mism
+        for a in range(len(parent)):
+            No, Ng = len(ref[a][0]), int(ranks[a])
+            if No == Ng:
+                continue
+            s_full = pod.pod_full(hapod.node_input(parent, ref, a, data64))[0]
+            tail = pod.tail_sums(s_full)
+            m_a = len(s_full)
+            band = m_a * UP["fp64"] * s_full[0] ** 2
+            gap = abs(tail[min(Ng, m_a)] - eps[a] ** 2)
+            print(f"  node {a}: rank {Ng} (oracle {No}), |tail - eps^2| = {gap:.3e}, m u lambda_1 = {band:.3e}")
+            assert gap <= band, (a, Ng, No, gap, band)
 
 
 def test_single_node_tree_equals_node_pod(hp):
