@@ -169,6 +169,33 @@ hapod_status hapod_node_pod_qr(int64_t n, int64_t m, const double* S, int64_t ld
                                double* sigma, int64_t* rank, int32_t* passes,
                                int32_t* sweeps, void* stream);
 
+/* One local POD(S, eps) (Def. 2.5) of a wide S (many more columns than its
+ * rank) by a randomized range finder (Halko, Martinsson & Tropp, SIAM Review
+ * 2011), without the Gram eigenproblem whose squared condition number
+ * (Rem. 2.3) limits the method of snapshots to sigma_k^2 above about
+ * u sigma_1^2:
+ *   Y = S Omega (Omega m x ell Gaussian from a counter-based generator and
+ *   `seed`), Q = orth(Y) by Cholesky-QR passes (as hapod_node_pod_qr), B =
+ *   Q^T S, r = ||S - Q B||_F^2 summed from the residual columns themselves,
+ *   the SVD of B from the QR factor of B^T (Cholesky-QR passes, one-sided
+ *   Jacobi on R'^T), modes Q U_B.
+ * Rank: the smallest N with r + sum_{k>N} sigma_k(B)^2 <= eps^2, so the
+ * modes' projection error ||S - U U^T S||_F^2 = r + sum_{k>N} sigma_k(B)^2
+ * is at most eps^2 (Def. 2.5's requirement, as used by Thm. 3.3 - 3.5).
+ * FP64 only.  ell in {128, 256, 384, 512}, ell <= m, ell <= n
+ * (HAPOD_E_UNSUPPORTED otherwise); eps > 0 (HAPOD_E_INVALID otherwise).
+ *   S, lds, eps, scaled, out, ldo, sigma, rank   as hapod_node_pod (double);
+ *           sigma and out need ell entries / columns of capacity.
+ *   info6   host, may be NULL: {r, passes on Y, passes on B^T, Jacobi sweeps,
+ *           device ms, ell}.
+ * r > eps^2 (the rank of S within eps exceeds what ell columns capture):
+ * HAPOD_E_UNSUPPORTED, info6 still filled.
+ * Scratch: two n x ell double buffers, an m x ell Gaussian and B^T, partial
+ * sums, from the library's pool.  Synchronises the stream.                 */
+hapod_status hapod_node_pod_sketch(int64_t n, int64_t m, const double* S, int64_t lds, double eps,
+                                   int32_t scaled, int64_t ell, uint64_t seed, double* out, int64_t ldo,
+                                   double* sigma, int64_t* rank, double* info6, void* stream);
+
 /* ------------------------------------------------------------------------ */
 /* Tree-level entry points.                                                 */
 /* ------------------------------------------------------------------------ */
@@ -230,6 +257,17 @@ typedef struct {
                                       FP64 only, not with right_vectors
                                       (HAPOD_E_INVALID otherwise).  A QR node's time
                                       counts as Gram time in the phase timings.        */
+  int32_t sketch_cols;             /* ell > 0 (128, 256, 384 or 512): computed nodes of at
+                                      least 2 ell inputs and ell rows take the sketched
+                                      route of hapod_node_pod_sketch with ell sketch
+                                      columns (seed fixed per node id), whose truncation
+                                      is certified from the residual itself instead of a
+                                      Gram spectrum; a node whose rank the sketch cannot
+                                      hold fails the run with HAPOD_E_UNSUPPORTED.  FP64
+                                      only, not with right_vectors (HAPOD_E_INVALID
+                                      otherwise).  0: off.  Timings: sketch, Q, B and
+                                      residual count as Gram, the small SVD as
+                                      eigensolve, the modes' product as lift.          */
 } hapod_options;
 
 /* Validate the tree (Def. 3.1), compute levels (height: leaves are level 1),
@@ -304,6 +342,13 @@ hapod_status hapod_modes(hapod_plan_t plan, int32_t node, void* U, int64_t ldu,
  * Needs a completed run of a plan made with right_vectors = 1
  * (HAPOD_E_INVALID otherwise).  Synchronises the stream.                   */
 hapod_status hapod_right_vectors(hapod_plan_t plan, double* W, int64_t ldw, void* stream);
+
+/* Diagnostics of a node that took the sketched route in the last run
+ * (node = -1: the root).  out11: host, 11 doubles {ell, residual energy r,
+ * Cholesky-QR passes on Y, passes on B^T, Jacobi sweeps, then device ms of:
+ * sketch Y = S Omega, Q = orth(Y), B = Q^T S, residual, small SVD, modes}.
+ * HAPOD_E_STATE if there is no completed run or the node took another route. */
+hapod_status hapod_sketch_stats(hapod_plan_t plan, int32_t node, double* out11);
 
 /* Per-node diagnostics of the last run, host, num_nodes entries each, any may
  * be NULL: input columns m, negative Gram eigenvalues, lambda_1, lambda_min. */

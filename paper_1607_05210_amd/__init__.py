@@ -44,7 +44,7 @@ class HapodOptions(C.Structure):
     _fields_ = [("prec", _i32), ("reorth", _i32), ("mem_cap_bytes", _i64),
                 ("node_eps_override", _pdbl), ("jacobi_max", _i32), ("autotune", _i32),
                 ("leaf_wave", _i32), ("block_gram", _i32), ("right_vectors", _i32),
-                ("qr_pod", _i32)]
+                ("qr_pod", _i32), ("sketch_cols", _i32)]
 
 
 LEAF_FN = C.CFUNCTYPE(_i32, _vp, _i32, C.POINTER(_vp), _pi64, _vp)
@@ -63,6 +63,9 @@ _SIGS = {
     "hapod_node_stats": [_vp, _pi64, _pi64, _pdbl, _pdbl],
     "hapod_right_vectors": [_vp, _vp, _i64, _vp],
     "hapod_node_pod_qr": [_i64, _i64, _vp, _i64, C.c_double, _i32, _vp, _i64, _pdbl, _pi64, _pi32, _pi32, _vp],
+    "hapod_node_pod_sketch": [_i64, _i64, _vp, _i64, _dbl, _i32, _i64, C.c_uint64, _vp, _i64, _pdbl, _pi64, _pdbl,
+                              _vp],
+    "hapod_sketch_stats": [_vp, _i32, _pdbl],
     "hapod_run_timing": [_vp, _pdbl],
     "hapod_level_timing": [_vp, _i32, _pdbl],
 }
@@ -220,6 +223,25 @@ def hapod_node_pod_qr(S, eps, scaled=False, out=None, stream=None):
     return sig[:r.value].copy(), out[:, :r.value], {"passes": npass.value, "sweeps": sw.value}
 
 
+def hapod_node_pod_sketch(S, eps, ell, seed=0, scaled=False, out=None, stream=None):
+    """POD(S, eps) of a wide S by a randomized range finder with ell sketch
+    columns (FP64): returns (sigma[rank] numpy, out[:, :rank], {"residual",
+    "passes_y", "passes_b", "sweeps", "ms", "ell"})."""
+    import numpy as np
+    ps, n, m, lds = _mat(S, "S", torch.float64)
+    if out is None:
+        out = colmajor(n, int(ell), torch.float64, S.device)
+    po, _, _, ldo = _mat(out, "out", torch.float64)
+    sig = np.zeros(max(int(ell), 1))
+    r = C.c_int64(0)
+    info = np.zeros(6)
+    _check(_lib.hapod_node_pod_sketch(n, m, ps, lds, float(eps), int(bool(scaled)), int(ell), int(seed), po, ldo,
+                                      sig.ctypes.data_as(_pdbl), C.byref(r), info.ctypes.data_as(_pdbl),
+                                      _stream(stream)), "hapod_node_pod_sketch")
+    keys = ("residual", "passes_y", "passes_b", "sweeps", "ms", "ell")
+    return sig[:r.value].copy(), out[:, :r.value], dict(zip(keys, info.tolist()))
+
+
 # ---------------------------------------------------------------------------
 # plans
 # ---------------------------------------------------------------------------
@@ -230,7 +252,7 @@ class Plan:
 
     def __init__(self, parent, leaf_cols, n, eps_star, omega, prec="fp64", reorth=False,
                  mem_cap_bytes=0, eps_override=None, jacobi_max=0, leaf_rows=None, leaf_wave=0,
-                 autotune=False, block_gram=False, right_vectors=False, qr_pod=False):
+                 autotune=False, block_gram=False, right_vectors=False, qr_pod=False, sketch_cols=0):
         import numpy as np
         self.num_nodes = len(parent)
         self.n = int(n)
@@ -247,7 +269,7 @@ class Plan:
             ov = arr.ctypes.data_as(_pdbl)
         opts = HapodOptions(self.prec, int(bool(reorth)), int(mem_cap_bytes), ov, int(jacobi_max),
                             int(bool(autotune)), int(leaf_wave), int(bool(block_gram)),
-                            int(bool(right_vectors)), int(bool(qr_pod)))
+                            int(bool(right_vectors)), int(bool(qr_pod)), int(sketch_cols))
         h = C.c_void_p()
         _check(_lib.hapod_plan(C.byref(tree), float(eps_star), float(omega), C.byref(opts), C.byref(h)),
                "hapod_plan")
@@ -354,6 +376,17 @@ class Plan:
         _check(_lib.hapod_node_stats(self._h, m_in.ctypes.data_as(_pi64), nneg.ctypes.data_as(_pi64),
                                      l1.ctypes.data_as(_pdbl), lmin.ctypes.data_as(_pdbl)), "hapod_node_stats")
         return dict(m_in=m_in, n_negative=nneg, lambda1=l1, lambda_min=lmin)
+
+    def sketch_stats(self, node=-1):
+        """Diagnostics of a node that took the sketched route (dict), or None."""
+        out = (C.c_double * 11)()
+        st = _lib.hapod_sketch_stats(self._h, int(node), out)
+        if st == 6:
+            return None
+        _check(st, "hapod_sketch_stats")
+        v = list(out)
+        return dict(ell=int(v[0]), residual=v[1], passes_y=int(v[2]), passes_b=int(v[3]), sweeps=int(v[4]),
+                    ms=dict(zip(["sketch", "orth", "cross", "residual", "small_svd", "lift"], v[5:11])))
 
     def ranks(self):
         import numpy as np

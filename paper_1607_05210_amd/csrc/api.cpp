@@ -1097,6 +1097,16 @@ void pool_free_cb(void* pool, void* p) { static_cast<Pool*>(pool)->free(p); }
 
 using namespace hapod;
 
+// Diagnostics of one sketched local POD.
+struct SketchInfo {
+  int64_t ell = 0;         // sketch columns
+  double residual = 0.0;   // ||S - Q Q^T S||_F^2, computed from the residual itself
+  int32_t passes_y = 0;    // Cholesky-QR passes on the sketch Y = S Omega
+  int32_t passes_b = 0;    // and on B^T = S^T Q
+  int32_t sweeps = 0;      // Jacobi sweeps on the small factor
+  float ms[6] = {0, 0, 0, 0, 0, 0};  // sketch, orthonormalisation, B, residual, small SVD, lift
+};
+
 // ===========================================================================
 // Plan
 // ===========================================================================
@@ -1128,24 +1138,186 @@ struct hapod_plan_s {
   std::vector<std::vector<int32_t>> in_order;
   double timing[6] = {0, 0, 0, 0, 0, 0};
   std::vector<std::array<double, 4>> level_ms;  // {gram, eig, trunc, lift} per level
+  // nodes that took the sketched route: their diagnostics (ell = 0 otherwise)
+  std::vector<SketchInfo> sketch;
   Pool pool;
 };
 
+// out = A B[:, :N] in FP64: A is n x m (plain column-major with ld lda, or
+// row-block-tiled when a_tiled), B row-major m x N (ld ldb); out element
+// (r, c) at out[c * ocs + blk_off(r, obs)].  The descriptors come from the
+// pool and go back to it once the launch is queued (all work of the caller is
+// ordered on one stream).
+hapod_status lift_fp64(Pool& pool, int64_t n, int64_t m, const double* A, int64_t lda, bool a_tiled, const double* B,
+                       int64_t ldb, int64_t N, double* out, int64_t ocs, int64_t obs, hipStream_t stream) {
+  if (n <= 0 || m <= 0 || N <= 0) return HAPOD_OK;
+  const std::vector<const void*> table = a_tiled ? tiled_table(A, m, 8) : column_table(A, lda, m, 8);
+  void *dc = nullptr, *dr = nullptr, *dw = nullptr, *dn = nullptr, *dk = nullptr;
+  hapod_status st = HAPOD_OK;
+  for (auto w : {std::make_pair(sizeof(void*) * m, &dc), std::make_pair(sizeof(int64_t) * m, &dr),
+                 std::make_pair(sizeof(int64_t) * m, &dw), std::make_pair(sizeof(LiftNode), &dn),
+                 std::make_pair(sizeof(int64_t), &dk)})
+    if (st == HAPOD_OK) st = pool.alloc(w.first, w.second);
+  LiftNode l{};
+  if (st == HAPOD_OK) {
+    const int64_t row_tiles = (n + kLiftTileM - 1) / kLiftTileM, col_tiles = (N + kLiftTileN - 1) / kLiftTileN;
+    const int rt_per = (int)std::max<int64_t>(1, std::min<int64_t>(16, row_tiles * col_tiles / kLiftTargetItems));
+    l.cols = (const void* const*)dc;
+    l.rbs = (const int64_t*)dr;
+    l.crows = (const int64_t*)dw;
+    l.B = B;
+    l.rank = (const int64_t*)dk;
+    l.out = out;
+    l.n = n;
+    l.ldb = ldb;
+    l.ocs = ocs;
+    l.obs = obs;
+    l.m = (int32_t)m;
+    l.row_tiles = (int32_t)row_tiles;
+    l.col_tiles = (int32_t)col_tiles;
+    l.rt_per = rt_per;
+    const int items = (int)(((row_tiles + rt_per - 1) / rt_per) * col_tiles);
+    if (hipMemcpyAsync(dc, table.data(), sizeof(void*) * m, hipMemcpyHostToDevice, stream) != hipSuccess ||
+        hipMemcpyAsync(dn, &l, sizeof(l), hipMemcpyHostToDevice, stream) != hipSuccess) {
+      set_error("lift: descriptor upload failed");
+      st = HAPOD_E_DEVICE;
+    }
+    if (st == HAPOD_OK) st = launch_fill_i64((int64_t*)dr, a_tiled ? tiled_rbs(m) : kRowBlock, m, stream);
+    if (st == HAPOD_OK) st = launch_fill_i64((int64_t*)dw, n, m, stream);
+    if (st == HAPOD_OK) st = launch_set_scalar_i64((int64_t*)dk, N, stream);
+    if (st == HAPOD_OK) st = launch_lift(0, (const LiftNode*)dn, 1, items, stream);
+    // the host copies above read `table` and `l`: complete them before
+    // those go out of scope
+    if (hipStreamSynchronize(stream) != hipSuccess && st == HAPOD_OK) {
+      set_error("lift: stream synchronisation failed");
+      st = HAPOD_E_DEVICE;
+    }
+  }
+  for (void* q : {dc, dr, dw, dn, dk})
+    if (q) pool.free(q);
+  return st;
+}
+
+// Cholesky-QR passes Q <- Q R_p^-1 on an n x m FP64 matrix A (plain, ld lda,
+// or row-block-tiled), until Q^T Q is the identity to rounding.  A pass whose
+// Q^T Q is not within 1/2 of the identity by Gershgorin (m max |Q^T Q - I| >
+// 1/2) is shifted: Q^T Q + s I = R_p^T R_p, s = 11 (n m + m (m + 1)) u
+// tr(Q^T Q), the shift of shifted Cholesky-QR (tr >= ||Q||_2^2), which lifts
+// the directions A nearly lacks by about s^-1/2 per pass; the others are
+// plain.  Two plain passes in a row leave Q orthonormal to rounding.  The
+// first pass factors the equilibrated Gram D^-1 A^T A D^-1 (D the column
+// norms), so columns of very different size (a bump far from a short leaf's
+// rows is 1e-100 of its neighbours) start on equal terms: R_1 = R_1' D,
+// R_1^-1 = D^-1 R_1'^-1.  A column with a zero Gram diagonal factors as a
+// unit column, stays zero in every Q, and is flagged in zero[] (device, m).
+// QA, QB: two row-block-tiled n x m buffers the passes alternate between (QA
+// may be A itself, then overwritten).  *Q: the buffer holding the final Q.
+// R (device, m x m column-major, may be null): A = Q R with R = R_p ... R_1.
+hapod_status cholqr_core(Pool& pool, int64_t n, int64_t m, const double* A, int64_t lda, bool a_tiled, double* QA,
+                         double* QB, double* R, int32_t* zero, const double** Q, int32_t* passes,
+                         hipStream_t stream) {
+  const size_t mm = sizeof(double) * (size_t)m * m;
+  void *G = nullptr, *Rinv = nullptr, *Rk = nullptr, *Racc = nullptr, *Rtmp = nullptr, *ddev = nullptr,
+       *dbad = nullptr, *dD = nullptr;
+  std::vector<void*> held;
+  auto finish = [&](hapod_status st) {
+    (void)hipStreamSynchronize(stream);
+    for (void* q : held) pool.free(q);
+    return st;
+  };
+  const bool acc = R != nullptr;
+  const std::pair<size_t, void**> want[] = {
+      {mm, &G}, {mm, &Rinv}, {acc ? mm : 0, &Rk}, {acc ? mm : 0, &Racc}, {acc ? mm : 0, &Rtmp},
+      {sizeof(double), &ddev}, {sizeof(int32_t) * kQrMaxPasses, &dbad}, {sizeof(double) * m, &dD}};
+  for (const auto& w : want) {
+    if (w.first == 0) continue;
+    hapod_status st = pool.alloc(w.first, w.second);
+    if (st != HAPOD_OK) return finish(st);
+    held.push_back(*w.second);
+  }
+  hapod_status st = launch_zero_bytes(zero, sizeof(int32_t) * m, stream);
+  if (st != HAPOD_OK) return finish(st);
+  const double u = 1.1102230246251565e-16;
+  const int64_t trbs = tiled_rbs(m);
+  const double* src = A;
+  bool src_tiled = a_tiled;
+  int64_t ld = lda;
+  double* dst = (QA == A) ? QB : QA;
+  int plain_run = 0, pass = 0;
+  for (; pass < kQrMaxPasses && plain_run < 2; ++pass) {
+    if ((st = gram_impl(0, 8, n, m, src, ld, (double*)G, m, stream, 0, src_tiled ? trbs : 0)) != HAPOD_OK ||
+        (st = launch_gram_zero_scale((double*)G, m, m, zero, pass == 0 ? (double*)dD : nullptr, stream)) !=
+            HAPOD_OK ||
+        (st = launch_identity_dev((double*)G, m, m, (double*)ddev, stream)) != HAPOD_OK)
+      return finish(st);
+    double dev = 0.0;
+    if (hipMemcpyAsync(&dev, ddev, sizeof(double), hipMemcpyDeviceToHost, stream) != hipSuccess ||
+        hipStreamSynchronize(stream) != hipSuccess) {
+      set_error("Cholesky-QR: readback failed");
+      return finish(HAPOD_E_DEVICE);
+    }
+    const bool shifted = !((double)m * dev <= 0.5);
+    if (shifted &&
+        (st = launch_shift_diag((double*)G, m, m, 11.0 * ((double)n * m + (double)m * (m + 1)) * u, stream)) != HAPOD_OK)
+      return finish(st);
+    if ((st = launch_chol_inv((double*)G, m, m, (double*)Rinv, m, (int32_t*)dbad + pass, stream, 0.0)) != HAPOD_OK)
+      return finish(st);
+    if (acc && (st = launch_triu((double*)G, m, m, pass == 0 ? (double*)Racc : (double*)Rk, m, stream)) != HAPOD_OK)
+      return finish(st);
+    if (pass == 0 && (st = launch_unscale_factors(acc ? (double*)Racc : nullptr, m, (double*)Rinv, m, m, (double*)dD,
+                                                  stream)) != HAPOD_OK)
+      return finish(st);
+    if (acc && pass > 0) {
+      if ((st = launch_dgemm_nn(m, m, m, (double*)Rk, m, (double*)Racc, m, (double*)Rtmp, m, stream)) != HAPOD_OK)
+        return finish(st);
+      std::swap(Racc, Rtmp);
+    }
+    if ((st = lift_fp64(pool, n, m, src, ld, src_tiled, (double*)Rinv, m, m, dst, kRowBlock, trbs, stream)) != HAPOD_OK)
+      return finish(st);
+    src = dst;
+    src_tiled = true;
+    ld = n;
+    dst = (dst == QA) ? QB : QA;
+    int32_t bad = 0;
+    if (hipMemcpyAsync(&bad, (int32_t*)dbad + pass, sizeof(bad), hipMemcpyDeviceToHost, stream) != hipSuccess ||
+        hipStreamSynchronize(stream) != hipSuccess) {
+      set_error("Cholesky-QR: readback failed");
+      return finish(HAPOD_E_DEVICE);
+    }
+    if (bad) {
+      set_error("Cholesky-QR: a Cholesky pivot was not positive (non-finite input?)");
+      return finish(HAPOD_E_NUMERIC);
+    }
+    plain_run = shifted ? 0 : plain_run + 1;
+  }
+  if (plain_run < 2) {
+    set_error("Cholesky-QR did not reach an orthonormal factor in 12 passes");
+    return finish(HAPOD_E_NUMERIC);
+  }
+  if (passes) *passes = pass;
+  *Q = src;
+  if (acc && hipMemcpyAsync(R, Racc, mm, hipMemcpyDeviceToDevice, stream) != hipSuccess) {
+    set_error("Cholesky-QR: copy of R failed");
+    return finish(HAPOD_E_DEVICE);
+  }
+  return finish(HAPOD_OK);
+}
+
 // The QR route for one node with eps > 0, 0 < m <= kQrMaxM, m <= n, S plain
-// column-major (n x m, ld lds) or row-block-tiled (s_tiled, n x m).  The Q
-// of the passes is row-block-tiled (contiguous 128-row blocks stream faster
-// than columns 8 n bytes apart).  With s_scratch, S (then tiled) may be
-// overwritten: it serves as one of the two Q buffers.  out_for_rank(N, &out, &ocs, &obs)
-// names where the N modes go (called once N is known, N > 0).
+// column-major (n x m, ld lds) or row-block-tiled (s_tiled, n x m): S = Q R
+// by cholqr_core (Q row-block-tiled: contiguous 128-row blocks stream faster
+// than columns 8 n bytes apart), R's rows of zero columns cleared (singular
+// value 0), the SVD R V = U_R diag(sigma) by one-sided Jacobi, the modes
+// Q U_R.  With s_scratch, S (then tiled) may be overwritten: it serves as one
+// of the two Q buffers.  out_for_rank(N, &out, &ocs, &obs) names where the N
+// modes go (called once N is known, N > 0).
 hapod_status qr_pod_core(Pool& pool, int64_t n, int64_t m, double* S, int64_t lds, bool s_tiled, bool s_scratch, double eps,
                          bool scaled, const std::function<hapod_status(int64_t, double**, int64_t*, int64_t*)>& out_for_rank,
                          std::vector<double>& sigma, int64_t* rank, int32_t* passes, int32_t* sweeps,
                          hipStream_t stream) {
   *rank = 0;
   const size_t mm = sizeof(double) * (size_t)m * m;
-  void *G = nullptr, *Rinv = nullptr, *Rk = nullptr, *Racc = nullptr, *Rtmp = nullptr, *Bm = nullptr, *dsig = nullptr,
-       *QA = nullptr, *QB = nullptr, *dcols = nullptr, *dn = nullptr, *drank = nullptr, *dbad = nullptr,
-       *drbs = nullptr, *drows = nullptr, *dinfo = nullptr, *drbs_t = nullptr, *dzero = nullptr, *dD = nullptr;
+  void *R = nullptr, *Bm = nullptr, *dsig = nullptr, *QA = nullptr, *QB = nullptr, *dinfo = nullptr, *dzero = nullptr;
   std::vector<void*> held;
   auto finish = [&](hapod_status st) {
     (void)hipStreamSynchronize(stream);
@@ -1153,129 +1325,22 @@ hapod_status qr_pod_core(Pool& pool, int64_t n, int64_t m, double* S, int64_t ld
     return st;
   };
   const std::pair<size_t, void**> want[] = {
-      {mm, &G}, {mm, &Rinv}, {mm, &Rk}, {mm, &Racc}, {mm, &Rtmp}, {mm, &Bm}, {sizeof(double) * 2 * m, &dsig},
-      {s_scratch ? 0 : tiled_bytes(n, m, 8), &QA}, {tiled_bytes(n, m, 8), &QB},
-      {sizeof(void*) * (kQrMaxPasses + 1) * m, &dcols}, {sizeof(LiftNode) * (kQrMaxPasses + 1), &dn},
-      {sizeof(int64_t), &drank}, {sizeof(int32_t) * kQrMaxPasses, &dbad}, {sizeof(int64_t) * m, &drbs},
-      {sizeof(int64_t) * m, &drows}, {sizeof(int32_t), &dinfo}, {sizeof(int64_t) * m, &drbs_t},
-      {sizeof(int32_t) * m, &dzero}, {sizeof(double) * m, &dD}};
+      {mm, &R}, {mm, &Bm}, {sizeof(double) * m, &dsig}, {s_scratch ? 0 : tiled_bytes(n, m, 8), &QA},
+      {tiled_bytes(n, m, 8), &QB}, {sizeof(int32_t), &dinfo}, {sizeof(int32_t) * m, &dzero}};
   for (const auto& w : want) {
     if (w.first == 0) continue;
     hapod_status st = pool.alloc(w.first, w.second);
     if (st != HAPOD_OK) return finish(st);
     held.push_back(*w.second);
   }
-  hapod_status st = HAPOD_OK;
-  const int64_t trbs = tiled_rbs(m);
-  if ((st = launch_zero_bytes(dzero, sizeof(int32_t) * m, stream)) != HAPOD_OK ||
-      (st = launch_fill_i64((int64_t*)drbs, kRowBlock, m, stream)) != HAPOD_OK ||
-      (st = launch_fill_i64((int64_t*)drbs_t, trbs, m, stream)) != HAPOD_OK ||
-      (st = launch_fill_i64((int64_t*)drows, n, m, stream)) != HAPOD_OK)
-    return finish(st);
-  // the lift operands of the three passes and of the modes, uploaded from
-  // host tables that live until the end of the call
-  std::vector<std::vector<const void*>> tables(kQrMaxPasses + 1);
-  std::vector<LiftNode> lifts(kQrMaxPasses + 1);
-  auto lift = [&](int slot, const double* src, bool src_tiled, int64_t ld, const double* B, int64_t N, double* dst,
-                  int64_t ldd, int64_t obs) -> hapod_status {
-    tables[slot] = src_tiled ? tiled_table(src, m, 8) : column_table(src, ld, m, 8);
-    LiftNode& l = lifts[slot];
-    l = LiftNode{};
-    l.cols = (const void* const*)dcols + (size_t)slot * m;
-    l.rbs = (const int64_t*)(src_tiled ? drbs_t : drbs);
-    l.crows = (const int64_t*)drows;
-    l.B = B;
-    l.rank = (const int64_t*)drank;
-    l.out = dst;
-    l.n = n;
-    l.ldb = m;
-    l.ocs = ldd;
-    l.obs = obs;
-    l.m = (int32_t)m;
-    l.row_tiles = (int32_t)((n + kLiftTileM - 1) / kLiftTileM);
-    l.col_tiles = (int32_t)((N + kLiftTileN - 1) / kLiftTileN);
-    if (hipMemcpyAsync((void*)l.cols, tables[slot].data(), sizeof(void*) * m, hipMemcpyHostToDevice, stream) !=
-            hipSuccess ||
-        hipMemcpyAsync((LiftNode*)dn + slot, &l, sizeof(l), hipMemcpyHostToDevice, stream) != hipSuccess) {
-      set_error("hapod_node_pod_qr: upload failed");
-      return HAPOD_E_DEVICE;
-    }
-    hapod_status s2 = launch_set_scalar_i64((int64_t*)drank, N, stream);
-    if (s2 != HAPOD_OK) return s2;
-    return launch_lift(0, (const LiftNode*)dn + slot, 1, l.row_tiles * l.col_tiles, stream);
-  };
-  // Cholesky-QR passes Q <- Q R_p^-1 (Q = S first), R = ... R_2 R_1, so that
-  // S = Q R holds to rounding after every pass.  A pass whose Q^T Q is not
-  // within 1/2 of the identity by Gershgorin (m max |Q^T Q - I| > 1/2) is
-  // shifted: Q^T Q + s I = R_p^T R_p, s = 11 (n m + m (m + 1)) u tr(Q^T Q),
-  // the shift of shifted Cholesky-QR (tr >= ||Q||_2^2), which lifts the
-  // directions S nearly lacks by about s^-1/2 per pass; the others are
-  // plain.  Two plain passes in a row leave Q orthonormal to rounding.
-  // The first pass factors the equilibrated Gram D^-1 S^T S D^-1 (D the
-  // column norms), so columns of very different size (a bump far from a
-  // short leaf's rows is 1e-100 of its neighbours) start on equal terms:
-  // R_1 = R_1' D, R_1^-1 = D^-1 R_1'^-1.  A column with a zero Gram diagonal
-  // factors as a unit column, stays zero in every Q, and its row of R is
-  // cleared before the SVD (singular value 0).
-  const double u = 1.1102230246251565e-16;
-  if (s_scratch) QA = S;  // pass 0 writes QB, pass 1 may overwrite S
-  const double* src = S;
-  bool src_tiled = s_tiled;
-  int64_t ld = lds;
-  double* dst = s_scratch ? (double*)QB : (double*)QA;
-  double* d_dev = (double*)dsig;
-  int plain_run = 0, pass = 0;
-  for (; pass < kQrMaxPasses && plain_run < 2; ++pass) {
-    if ((st = gram_impl(0, 8, n, m, src, ld, (double*)G, m, stream, 0, src_tiled ? trbs : 0)) != HAPOD_OK ||
-        (st = launch_gram_zero_scale((double*)G, m, m, (int32_t*)dzero, pass == 0 ? (double*)dD : nullptr,
-                                     stream)) != HAPOD_OK ||
-        (st = launch_identity_dev((double*)G, m, m, d_dev, stream)) != HAPOD_OK)
-      return finish(st);
-    double dev = 0.0;
-    if (hipMemcpyAsync(&dev, d_dev, sizeof(double), hipMemcpyDeviceToHost, stream) != hipSuccess ||
-        hipStreamSynchronize(stream) != hipSuccess) {
-      set_error("hapod_node_pod_qr: readback failed");
-      return finish(HAPOD_E_DEVICE);
-    }
-    const bool shifted = !((double)m * dev <= 0.5);
-    if (shifted &&
-        (st = launch_shift_diag((double*)G, m, m, 11.0 * ((double)n * m + (double)m * (m + 1)) * u, stream)) != HAPOD_OK)
-      return finish(st);
-    if ((st = launch_chol_inv((double*)G, m, m, (double*)Rinv, m, (int32_t*)dbad + pass, stream, 0.0)) != HAPOD_OK ||
-        (st = launch_triu((double*)G, m, m, pass == 0 ? (double*)Racc : (double*)Rk, m, stream)) != HAPOD_OK)
-      return finish(st);
-    if (pass == 0 && (st = launch_unscale_factors((double*)Racc, m, (double*)Rinv, m, m, (double*)dD, stream)) != HAPOD_OK)
-      return finish(st);
-    if (pass > 0) {
-      if ((st = launch_dgemm_nn(m, m, m, (double*)Rk, m, (double*)Racc, m, (double*)Rtmp, m, stream)) != HAPOD_OK)
-        return finish(st);
-      std::swap(Racc, Rtmp);
-    }
-    if ((st = lift(pass, src, src_tiled, ld, (double*)Rinv, m, dst, kRowBlock, trbs)) != HAPOD_OK) return finish(st);
-    src = dst;
-    src_tiled = true;
-    ld = n;
-    dst = (dst == (double*)QA) ? (double*)QB : (double*)QA;
-    int32_t bad = 0;
-    if (hipMemcpyAsync(&bad, (int32_t*)dbad + pass, sizeof(bad), hipMemcpyDeviceToHost, stream) != hipSuccess ||
-        hipStreamSynchronize(stream) != hipSuccess) {
-      set_error("hapod_node_pod_qr: readback failed");
-      return finish(HAPOD_E_DEVICE);
-    }
-    if (bad) {
-      set_error("hapod_node_pod_qr: a Cholesky pivot was not positive (non-finite input?)");
-      return finish(HAPOD_E_NUMERIC);
-    }
-    plain_run = shifted ? 0 : plain_run + 1;
-  }
-  if (plain_run < 2) {
-    set_error("hapod_node_pod_qr: Cholesky-QR did not reach an orthonormal factor in 12 passes");
-    return finish(HAPOD_E_NUMERIC);
-  }
-  if (passes) *passes = pass;
-  if ((st = launch_zero_rows((double*)Racc, m, m, (int32_t*)dzero, stream)) != HAPOD_OK) return finish(st);
+  if (s_scratch) QA = S;
+  const double* Q = nullptr;
+  hapod_status st = cholqr_core(pool, n, m, S, lds, s_tiled, (double*)QA, (double*)QB, (double*)R, (int32_t*)dzero,
+                                &Q, passes, stream);
+  if (st != HAPOD_OK) return finish(st);
+  if ((st = launch_zero_rows((double*)R, m, m, (int32_t*)dzero, stream)) != HAPOD_OK) return finish(st);
   // one-sided Jacobi SVD of R: R V = U_R diag(sigma); B = U_R (diag(sigma))
-  if ((st = launch_osj((double*)Racc, m, (double*)dsig, (double*)Bm, scaled ? 1 : 0, (int32_t*)dinfo, stream)) !=
+  if ((st = launch_osj((double*)R, m, (double*)dsig, (double*)Bm, scaled ? 1 : 0, (int32_t*)dinfo, stream)) !=
       HAPOD_OK)
     return finish(st);
   int32_t info = 0;
@@ -1303,11 +1368,285 @@ hapod_status qr_pod_core(Pool& pool, int64_t n, int64_t m, double* S, int64_t ld
     double* out = nullptr;
     int64_t ocs = 0, obs = 0;
     if ((st = out_for_rank(N, &out, &ocs, &obs)) != HAPOD_OK) return finish(st);
-    if ((st = lift(kQrMaxPasses, src, src_tiled, ld, (const double*)Bm, N, out, ocs, obs)) != HAPOD_OK)
+    if ((st = lift_fp64(pool, n, m, Q, n, true, (const double*)Bm, m, N, out, ocs, obs, stream)) != HAPOD_OK)
       return finish(st);
   }
   *rank = N;
   sigma.assign(sg.begin(), sg.begin() + N);
+  return finish(HAPOD_OK);
+}
+
+
+// Sketched local POD of a wide node (FP64), for nodes whose Gram matrix
+// cannot resolve the truncation (Rem. 2.3: the method of snapshots knows
+// sigma_k^2 only to about u sigma_1^2).  A randomized range finder (Halko,
+// Martinsson & Tropp, SIAM Review 2011, Alg. 4.1 and Sec. 5.1):
+//   Y = S Omega        Omega m x ell Gaussian (counter-based, seeded)
+//   Y = Q R_Y          cholqr_core: Q orthonormal to rounding
+//   B = Q^T S          ell x m (cross-product mode of the Gram kernel; stored
+//                      as B^T, m x ell)
+//   r = ||S - Q B||_F^2  from the residual itself (residual mode of the lift)
+//   B^T = Q' R'        cholqr_core; then B = R'^T Q'^T and the left singular
+//                      vectors and singular values of B are those of R'^T:
+//                      one-sided Jacobi on the columns of R'^T
+//   U = Q U_B          (scaled: Q U_B diag(sigma))
+// Truncation (Def. 2.5 with the sketch's residual counted as discarded
+// energy): N = min{N' : r + sum_{k > N'} sigma_k(B)^2 <= eps^2}.  Then
+// ||S - U U^T S||_F^2 = r + sum_{k > N} sigma_k(B)^2 <= eps^2 exactly (the
+// residual is orthogonal to span(Q)), the property the HAPOD bounds
+// (Thm. 3.3 - 3.5) use.  Every quantity is formed from S or Q themselves,
+// never from S^T S, so it carries absolute errors of about u ||s_j|| per
+// column instead of u sigma_1^2 per eigenvalue.  r > eps^2 (the node's rank
+// exceeds what ell columns capture) fails with HAPOD_E_UNSUPPORTED.
+// cols/rbs/crows: the node's input columns (host copies of device pointers).
+hapod_status sketch_pod_core(Pool& pool, int64_t n, int64_t m, const std::vector<const void*>& cols,
+                             const std::vector<int64_t>& rbs, const std::vector<int64_t>& crows, int64_t ell,
+                             uint64_t seed, double eps, bool scaled,
+                             const std::function<hapod_status(int64_t, double**, int64_t*, int64_t*)>& out_for_rank,
+                             std::vector<double>& sigma, int64_t* rank, SketchInfo* info, hipStream_t stream) {
+  *rank = 0;
+  SketchInfo si;
+  si.ell = ell;
+  const int tq = (int)(ell / kGramTile);
+  const int64_t mt = m + ell;                            // cross-product columns [Q, S]
+  const int ntiles = (int)((mt + kGramTile - 1) / kGramTile);
+  const int nr = ntiles - tq;                            // tiles of S
+  const int pairs = tq * nr;
+  const int nch = pick_chunks(n, pairs, 8192, 2048);
+  int64_t cr = ((n + nch - 1) / nch + kRowBlock - 1) / kRowBlock * kRowBlock;
+  const int nchunks = (int)((n + cr - 1) / cr);
+  const int64_t row_tiles = (n + kLiftTileM - 1) / kLiftTileM, col_tiles = (m + kLiftTileN - 1) / kLiftTileN;
+  const int rt_per = (int)std::max<int64_t>(1, std::min<int64_t>(16, row_tiles * col_tiles / kLiftTargetItems));
+  const int64_t rgroups = (row_tiles + rt_per - 1) / rt_per;
+  const size_t ll = sizeof(double) * (size_t)ell * ell;
+  void *dsc = nullptr, *dsr = nullptr, *dsw = nullptr, *Om = nullptr, *QA = nullptr, *QB = nullptr, *Bt = nullptr,
+       *dxc = nullptr, *dxr = nullptr, *dxw = nullptr, *part = nullptr, *blob = nullptr, *rpart = nullptr,
+       *res = nullptr, *dln = nullptr, *dk = nullptr, *PA = nullptr, *PB = nullptr, *Rb = nullptr, *M = nullptr,
+       *UB = nullptr, *dsig = nullptr, *dinfo = nullptr, *dzy = nullptr, *dzb = nullptr;
+  std::vector<void*> held;
+  hipEvent_t ev[7] = {};
+  auto finish = [&](hapod_status st) {
+    (void)hipStreamSynchronize(stream);
+    for (void* q : held) pool.free(q);
+    for (hipEvent_t& e : ev)
+      if (e) (void)hipEventDestroy(e);
+    return st;
+  };
+  for (hipEvent_t& e : ev)
+    if (hipEventCreate(&e) != hipSuccess) {
+      e = nullptr;
+      set_error("sketched POD: hipEventCreate failed");
+      return finish(HAPOD_E_DEVICE);
+    }
+  const std::pair<size_t, void**> want[] = {
+      {sizeof(void*) * m, &dsc}, {sizeof(int64_t) * m, &dsr}, {sizeof(int64_t) * m, &dsw},
+      {sizeof(double) * (size_t)m * ell, &Om}, {tiled_bytes(n, ell, 8), &QA}, {tiled_bytes(n, ell, 8), &QB},
+      {sizeof(double) * (size_t)m * ell, &Bt}, {sizeof(void*) * mt, &dxc}, {sizeof(int64_t) * mt, &dxr},
+      {sizeof(int64_t) * mt, &dxw},
+      {nchunks > 1 ? sizeof(double) * (size_t)pairs * nchunks * kGramTile * kGramTile : 0, &part},
+      {sizeof(double) * (size_t)rgroups * 2 * m, &rpart}, {sizeof(double) * m, &res}, {sizeof(LiftNode), &dln},
+      {sizeof(int64_t), &dk}, {tiled_bytes(m, ell, 8), &PA}, {tiled_bytes(m, ell, 8), &PB}, {ll, &Rb}, {ll, &M},
+      {ll, &UB}, {sizeof(double) * ell, &dsig}, {sizeof(int32_t), &dinfo}, {sizeof(int32_t) * ell, &dzy},
+      {sizeof(int32_t) * ell, &dzb}};
+  for (const auto& w : want) {
+    if (w.first == 0) continue;
+    hapod_status st = pool.alloc(w.first, w.second);
+    if (st != HAPOD_OK) return finish(st);
+    held.push_back(*w.second);
+  }
+  hapod_status st = HAPOD_OK;
+  auto up = [&](void* dst, const void* src, size_t bytes) {
+    return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, stream) == hipSuccess;
+  };
+  if (!up(dsc, cols.data(), sizeof(void*) * m) || !up(dsr, rbs.data(), sizeof(int64_t) * m) ||
+      !up(dsw, crows.data(), sizeof(int64_t) * m)) {
+    set_error("sketched POD: upload failed");
+    return finish(HAPOD_E_DEVICE);
+  }
+  (void)hipEventRecord(ev[0], stream);
+  // ---- Y = S Omega ------------------------------------------------------------
+  if ((st = launch_normal_fill((double*)Om, m * ell, seed, stream)) != HAPOD_OK) return finish(st);
+  LiftNode ly{};
+  ly.cols = (const void* const*)dsc;
+  ly.rbs = (const int64_t*)dsr;
+  ly.crows = (const int64_t*)dsw;
+  ly.B = (const double*)Om;
+  ly.rank = (const int64_t*)dk;
+  ly.out = QA;
+  ly.n = n;
+  ly.ldb = ell;
+  ly.ocs = kRowBlock;
+  ly.obs = tiled_rbs(ell);
+  ly.m = (int32_t)m;
+  ly.row_tiles = (int32_t)row_tiles;
+  ly.col_tiles = (int32_t)((ell + kLiftTileN - 1) / kLiftTileN);
+  ly.rt_per = (int)std::max<int64_t>(1, std::min<int64_t>(16, row_tiles * ly.col_tiles / kLiftTargetItems));
+  const int y_items = (int)(((row_tiles + ly.rt_per - 1) / ly.rt_per) * ly.col_tiles);
+  if (!up(dln, &ly, sizeof(ly))) {
+    set_error("sketched POD: upload failed");
+    return finish(HAPOD_E_DEVICE);
+  }
+  if ((st = launch_set_scalar_i64((int64_t*)dk, ell, stream)) != HAPOD_OK ||
+      (st = launch_lift(0, (const LiftNode*)dln, 1, y_items, stream)) != HAPOD_OK)
+    return finish(st);
+  (void)hipEventRecord(ev[1], stream);
+  // ---- Q = orth(Y) ---------------------------------------------------------------
+  const double* Q = nullptr;
+  if ((st = cholqr_core(pool, n, ell, (const double*)QA, n, true, (double*)QA, (double*)QB, nullptr, (int32_t*)dzy,
+                        &Q, &si.passes_y, stream)) != HAPOD_OK)
+    return finish(st);
+  (void)hipEventRecord(ev[2], stream);
+  // ---- B^T = S^T Q: cross product of [Q, S] ------------------------------------------
+  {
+    std::vector<const void*> xc = tiled_table(Q, ell, 8);
+    std::vector<int64_t> xr((size_t)ell, tiled_rbs(ell)), xw((size_t)ell, n);
+    xc.insert(xc.end(), cols.begin(), cols.end());
+    xr.insert(xr.end(), rbs.begin(), rbs.end());
+    xw.insert(xw.end(), crows.begin(), crows.end());
+    bool vec = (cr % 16) == 0;
+    for (const void* c : xc) vec = vec && (((uintptr_t)c & 15u) == 0);
+    GramNode g{};
+    g.cols = (const void* const*)dxc;
+    g.rbs = (const int64_t*)dxr;
+    g.crows = (const int64_t*)dxw;
+    g.n = n;
+    g.chunk_rows = cr;
+    g.G = (double*)Bt;
+    g.partial = (double*)part;
+    g.ldg = m;
+    g.m = (int32_t)mt;
+    g.nchunks = nchunks;
+    g.ntiles = ntiles;
+    g.tile = kGramTile;
+    g.cross = (int32_t)ell;
+    // rows each tile holds (inputs of uneven height end early)
+    std::vector<int64_t> tile_rows((size_t)ntiles, 0);
+    for (int64_t c = 0; c < mt; ++c) tile_rows[(size_t)(c / kGramTile)] = std::max(tile_rows[(size_t)(c / kGramTile)], xw[(size_t)c]);
+    // consecutive items (one XCD's concurrent workgroups) share the Q tiles
+    // and a run of 8 S tiles of one row chunk
+    std::vector<GramItem> items;
+    std::vector<int32_t> rp, rn;
+    for (int c = 0; c < nchunks; ++c)
+      for (int J = tq; J < ntiles; J += 8)
+        for (int ti = 0; ti < tq; ++ti)
+          for (int tj = J; tj < std::min(J + 8, ntiles); ++tj)
+            items.push_back(GramItem{0, (int16_t)ti, (int16_t)tj, c, ti * nr + (tj - tq),
+                                     std::min(tile_rows[(size_t)ti], tile_rows[(size_t)tj])});
+    if (nchunks > 1)
+      for (int p = 0; p < pairs; ++p) {
+        rp.push_back(p);
+        rn.push_back(0);
+      }
+    Blob b;
+    const size_t o_g = b.add(&g, sizeof(g)), o_i = b.add_vec(items), o_rp = b.add_vec(rp), o_rn = b.add_vec(rn);
+    if ((st = pool.alloc(b.host.size(), &blob)) != HAPOD_OK) return finish(st);
+    held.push_back(blob);
+    char* db = (char*)blob;
+    if (!up(db, b.host.data(), b.host.size()) || !up(dxc, xc.data(), sizeof(void*) * mt) ||
+        !up(dxr, xr.data(), sizeof(int64_t) * mt) || !up(dxw, xw.data(), sizeof(int64_t) * mt)) {
+      set_error("sketched POD: upload failed");
+      return finish(HAPOD_E_DEVICE);
+    }
+    const GramLaunch gl{kGramTile, vec ? 1 : 0, 0, (int32_t)items.size(), 0};
+    if ((st = launch_gram(0, (const GramNode*)(db + o_g), (const GramItem*)(db + o_i), &gl, 1,
+                          (const int32_t*)(db + o_rp), (const int32_t*)(db + o_rn), (int)rp.size(), kGramTile,
+                          stream)) != HAPOD_OK)
+      return finish(st);
+    // the uploads read host vectors of this scope
+    if (hipStreamSynchronize(stream) != hipSuccess) {
+      set_error("sketched POD: synchronisation failed");
+      return finish(HAPOD_E_DEVICE);
+    }
+  }
+  (void)hipEventRecord(ev[3], stream);
+  // ---- residual energy per column: ||s_j - Q b_j||^2 --------------------------------
+  {
+    LiftNode lr{};
+    lr.cols = (const void* const*)dxc;  // the first ell entries: Q's columns
+    lr.rbs = (const int64_t*)dxr;
+    lr.crows = (const int64_t*)dxw;
+    lr.B = (const double*)Bt;          // B row-major ell x m = B^T column-major
+    lr.rank = (const int64_t*)dk;
+    lr.n = n;
+    lr.ldb = m;
+    lr.m = (int32_t)ell;
+    lr.row_tiles = (int32_t)row_tiles;
+    lr.col_tiles = (int32_t)col_tiles;
+    lr.rt_per = rt_per;
+    lr.rcols = (const void* const*)dsc;
+    lr.rrbs = (const int64_t*)dsr;
+    lr.rrows = (const int64_t*)dsw;
+    lr.rpart = (double*)rpart;
+    if (!up(dln, &lr, sizeof(lr))) {
+      set_error("sketched POD: upload failed");
+      return finish(HAPOD_E_DEVICE);
+    }
+    if ((st = launch_set_scalar_i64((int64_t*)dk, m, stream)) != HAPOD_OK ||
+        (st = launch_lift_residual((const LiftNode*)dln, (int)(rgroups * col_tiles), stream)) != HAPOD_OK ||
+        (st = launch_sum_partials((const double*)rpart, rgroups * 2, m, (double*)res, stream)) != HAPOD_OK)
+      return finish(st);
+    if (hipStreamSynchronize(stream) != hipSuccess) {
+      set_error("sketched POD: synchronisation failed");
+      return finish(HAPOD_E_DEVICE);
+    }
+  }
+  (void)hipEventRecord(ev[4], stream);
+  // ---- SVD of B through B^T = Q' R' -----------------------------------------------------
+  const double* Qb = nullptr;
+  if ((st = cholqr_core(pool, m, ell, (const double*)Bt, m, false, (double*)PA, (double*)PB, (double*)Rb,
+                        (int32_t*)dzb, &Qb, &si.passes_b, stream)) != HAPOD_OK)
+    return finish(st);
+  if ((st = launch_zero_rows((double*)Rb, ell, ell, (int32_t*)dzb, stream)) != HAPOD_OK ||
+      (st = launch_transpose((const double*)Rb, ell, ell, (double*)M, ell, stream)) != HAPOD_OK ||
+      (st = launch_osj((double*)M, ell, (double*)dsig, (double*)UB, scaled ? 1 : 0, (int32_t*)dinfo, stream)) !=
+          HAPOD_OK)
+    return finish(st);
+  (void)hipEventRecord(ev[5], stream);
+  std::vector<double> sg((size_t)ell), rs((size_t)m);
+  int32_t jinfo = 0;
+  if (hipMemcpyAsync(sg.data(), dsig, sizeof(double) * ell, hipMemcpyDeviceToHost, stream) != hipSuccess ||
+      hipMemcpyAsync(rs.data(), res, sizeof(double) * m, hipMemcpyDeviceToHost, stream) != hipSuccess ||
+      hipMemcpyAsync(&jinfo, dinfo, sizeof(int32_t), hipMemcpyDeviceToHost, stream) != hipSuccess ||
+      hipStreamSynchronize(stream) != hipSuccess) {
+    set_error("sketched POD: readback failed");
+    return finish(HAPOD_E_DEVICE);
+  }
+  if (jinfo < 0) {
+    set_error("sketched POD: the Jacobi SVD of the small factor did not converge");
+    return finish(HAPOD_E_NUMERIC);
+  }
+  si.sweeps = jinfo;
+  double r2 = 0.0;
+  for (double v : rs) r2 += v;
+  si.residual = r2;
+  const double e2 = eps * eps;
+  if (!(r2 <= e2)) {
+    set_error("sketched POD: the residual energy " + std::to_string(r2) + " of a " + std::to_string(ell) +
+              "-column sketch exceeds eps^2 = " + std::to_string(e2) +
+              " (the node's rank is beyond the sketch: use a wider sketch or the method of snapshots)");
+    if (info) *info = si;
+    return finish(HAPOD_E_UNSUPPORTED);
+  }
+  // Def. 2.5 with the residual as discarded energy
+  int64_t N = ell;
+  double tail = r2;
+  while (N > 0 && tail + sg[(size_t)N - 1] * sg[(size_t)N - 1] <= e2) {
+    tail += sg[(size_t)N - 1] * sg[(size_t)N - 1];
+    --N;
+  }
+  if (N > 0) {
+    double* out = nullptr;
+    int64_t ocs = 0, obs = 0;
+    if ((st = out_for_rank(N, &out, &ocs, &obs)) != HAPOD_OK) return finish(st);
+    if ((st = lift_fp64(pool, n, ell, Q, n, true, (const double*)UB, ell, N, out, ocs, obs, stream)) != HAPOD_OK)
+      return finish(st);
+  }
+  (void)hipEventRecord(ev[6], stream);
+  (void)hipEventSynchronize(ev[6]);
+  for (int k = 0; k < 6; ++k) (void)hipEventElapsedTime(&si.ms[k], ev[k], ev[k + 1]);
+  *rank = N;
+  sigma.assign(sg.begin(), sg.begin() + N);
+  if (info) *info = si;
   return finish(HAPOD_OK);
 }
 
@@ -1337,6 +1676,15 @@ hapod_status hapod_plan(const hapod_tree* tree, double eps_star, double omega, c
   if (opts && opts->qr_pod && (opts->prec != HAPOD_FP64 || opts->right_vectors)) {
     // the QR route computes in double and keeps no right singular vectors
     set_error("hapod_plan: qr_pod needs the FP64 form and excludes right_vectors");
+    return HAPOD_E_INVALID;
+  }
+  if (opts && opts->sketch_cols != 0 &&
+      (opts->prec != HAPOD_FP64 || opts->right_vectors || opts->sketch_cols < kGramTile ||
+       opts->sketch_cols > kSketchMaxCols || opts->sketch_cols % kGramTile != 0)) {
+    // the sketched route computes in double, keeps no right singular
+    // vectors, and its sketch is whole 128-column tiles up to the Jacobi
+    // SVD's 512 columns
+    set_error("hapod_plan: sketch_cols needs the FP64 form, excludes right_vectors, and must be 128, 256, 384 or 512");
     return HAPOD_E_INVALID;
   }
   auto P = std::make_unique<hapod_plan_s>();
@@ -1610,6 +1958,7 @@ hapod_status hapod_run(hapod_plan_t P, hapod_leaf_fn get_leaf, void* user, void*
   P->lam1.assign(nn, 0.0);
   P->lam_min.assign(nn, 0.0);
   P->sigma.assign(nn, {});
+  P->sketch.assign(nn, SketchInfo{});
   for (double& t : P->timing) t = 0.0;
 
   // Per node: the columns it hands to its parent (pointer, row-block stride,
@@ -1747,6 +2096,62 @@ hapod_status hapod_run(hapod_plan_t P, hapod_leaf_fn get_leaf, void* user, void*
     }
     return HAPOD_OK;
   };
+  // one wide node through the sketched route: its input columns read where
+  // they are (no gather), the modes written as the batched path would put
+  // them; sketch, orthonormalisation, cross product and residual count as
+  // Gram time, the small SVD as eigensolve time, the final product as lift
+  auto sketch_node = [&](int32_t a, PodJob& j, PhaseTimes& ph) -> hapod_status {
+    void* outp = nullptr;
+    auto out_for = [&](int64_t N, double** o, int64_t* ocs, int64_t* obs) -> hapod_status {
+      const size_t bytes = j.root ? sizeof(double) * (size_t)P->n * N : tiled_bytes(j.n, N, 8);
+      HAPOD_TRY(P->pool.alloc(bytes, &outp));
+      if (j.root) {
+        *ocs = P->n;
+        *obs = kRowBlock;
+        if (j.n < P->n) HAPOD_TRY(launch_zero_bytes(outp, bytes, stream));
+      } else {
+        *ocs = kRowBlock;
+        *obs = tiled_rbs(N);
+      }
+      *o = (double*)outp;
+      return HAPOD_OK;
+    };
+    std::vector<double> sg;
+    int64_t N = 0;
+    SketchInfo si;
+    // one seed per node: reruns draw the same test matrix
+    const uint64_t seed = 0x6a09e667f3bcc909ull ^ ((uint64_t)a * 0x9e3779b97f4a7c15ull);
+    hapod_status st = sketch_pod_core(P->pool, j.n, j.m, j.cols, j.rbs, j.crows, P->opts.sketch_cols, seed, j.eps,
+                                      !j.root, out_for, sg, &N, &si, stream);
+    if (st != HAPOD_OK) {
+      if (outp) P->pool.free(outp);
+      return st;
+    }
+    ph.gram += si.ms[0] + si.ms[1] + si.ms[2] + si.ms[3];
+    ph.eig += si.ms[4];
+    ph.lift += si.ms[5];
+    P->sketch[a] = si;
+    P->rank[a] = N;
+    P->sigma[a] = sg;
+    P->lam1[a] = sg.empty() ? 0.0 : sg.front() * sg.front();
+    P->lam_min[a] = sg.empty() ? 0.0 : sg.back() * sg.back();
+    P->n_neg[a] = 0;
+    out_buf[a] = outp;
+    if (outp) {
+      blocks.push_back({outp, 1});
+      out_blk[a] = (int)blocks.size() - 1;
+    }
+    if (a == P->root) {
+      out_cols[a] = column_table(outp, P->n, N, eb);
+      out_rbs[a].assign((size_t)N, kRowBlock);
+      out_rows[a].assign((size_t)N, P->n);
+    } else {
+      out_cols[a] = tiled_table(outp, N, eb);
+      out_rbs[a].assign((size_t)N, tiled_rbs(N));
+      out_rows[a].assign((size_t)N, j.n);
+    }
+    return HAPOD_OK;
+  };
   HAPOD_HIP(hipEventRecord(t0, stream));
   PhaseTimes pt;
   const int32_t LT = (int32_t)P->by_level.size();
@@ -1852,6 +2257,30 @@ hapod_status hapod_run(hapod_plan_t P, hapod_leaf_fn get_leaf, void* user, void*
         j.plain_out = j.root;
         jobs.push_back(std::move(j));
         job_node.push_back(a);
+      }
+      // the sketched route (sketch_cols = ell) takes the computed nodes of at
+      // least 2 ell inputs and ell rows, one by one
+      if (P->opts.sketch_cols > 0) {
+        const int64_t ell = P->opts.sketch_cols;
+        std::vector<PodJob> rest;
+        std::vector<int32_t> rest_node;
+        for (size_t k = 0; k < jobs.size(); ++k) {
+          PodJob& j = jobs[k];
+          const int32_t a = job_node[k];
+          if (j.m < 2 * ell || j.n < ell) {
+            rest.push_back(std::move(j));
+            rest_node.push_back(a);
+            continue;
+          }
+          hapod_status ks = sketch_node(a, j, lt);
+          if (ks != HAPOD_OK) {
+            (void)hipStreamSynchronize(stream);
+            release_all();
+            return ks;
+          }
+        }
+        jobs.swap(rest);
+        job_node.swap(rest_node);
       }
       // the QR route (qr_pod) takes the computed nodes it covers one by one;
       // the rest are batched below
@@ -2031,6 +2460,27 @@ hapod_status hapod_modes(hapod_plan_t P, int32_t node, void* U, int64_t ldu, dou
     }
     HAPOD_HIP(hipStreamSynchronize(stream));
   }
+  return HAPOD_OK;
+}
+
+hapod_status hapod_sketch_stats(hapod_plan_t P, int32_t node, double* out11) {
+  if (!P || !out11) {
+    set_error("hapod_sketch_stats: NULL argument");
+    return HAPOD_E_INVALID;
+  }
+  if (!P->has_result) {
+    set_error("hapod_sketch_stats: no completed run");
+    return HAPOD_E_STATE;
+  }
+  const int32_t a = node < 0 ? P->root : node;
+  if (a >= P->num_nodes || P->sketch[a].ell == 0) {
+    set_error("hapod_sketch_stats: the node did not take the sketched route");
+    return HAPOD_E_STATE;
+  }
+  const SketchInfo& k = P->sketch[a];
+  const double v[11] = {(double)k.ell, k.residual, (double)k.passes_y, (double)k.passes_b, (double)k.sweeps,
+                        k.ms[0], k.ms[1], k.ms[2], k.ms[3], k.ms[4], k.ms[5]};
+  std::memcpy(out11, v, sizeof(v));
   return HAPOD_OK;
 }
 
@@ -2544,6 +2994,41 @@ hapod_status hapod_node_pod_qr(int64_t n, int64_t m, const double* S, int64_t ld
   };
   hapod_status st = qr_pod_core(step_pool(), n, m, const_cast<double*>(S), lds, false, false, eps, scaled != 0, to_caller, sg,
                                 rank, passes, sweeps, stream);
+  if (st == HAPOD_OK && sigma && *rank > 0) std::memcpy(sigma, sg.data(), sizeof(double) * *rank);
+  return st;
+}
+
+hapod_status hapod_node_pod_sketch(int64_t n, int64_t m, const double* S, int64_t lds, double eps, int32_t scaled,
+                                   int64_t ell, uint64_t seed, double* out, int64_t ldo, double* sigma, int64_t* rank,
+                                   double* info6, void* stream_) {
+  if (n < 0 || m < 0 || !(eps > 0.0) || !rank || lds < std::max<int64_t>(n, 1) || (m > 0 && n > 0 && (!S || !out)) ||
+      ldo < std::max<int64_t>(n, 1)) {
+    set_error("hapod_node_pod_sketch: bad sizes, eps <= 0 or NULL pointer");
+    return HAPOD_E_INVALID;
+  }
+  if (ell < kGramTile || ell > kSketchMaxCols || ell % kGramTile != 0 || m < ell || n < ell) {
+    set_error("hapod_node_pod_sketch: ell must be 128, 256, 384 or 512 and at most m and n");
+    return HAPOD_E_UNSUPPORTED;
+  }
+  hipStream_t stream = (hipStream_t)stream_;
+  *rank = 0;
+  auto to_caller = [&](int64_t, double** o, int64_t* ocs, int64_t* obs) {
+    *o = out;
+    *ocs = ldo;
+    *obs = kRowBlock;
+    return HAPOD_OK;
+  };
+  std::vector<const void*> cols = column_table(S, lds, m, 8);
+  std::vector<int64_t> rbs((size_t)m, kRowBlock), rows((size_t)m, n);
+  std::vector<double> sg;
+  SketchInfo si;
+  hapod_status st = sketch_pod_core(step_pool(), n, m, cols, rbs, rows, ell, seed, eps, scaled != 0, to_caller, sg,
+                                    rank, &si, stream);
+  if (info6) {
+    const double v[6] = {si.residual, (double)si.passes_y, (double)si.passes_b, (double)si.sweeps,
+                         (double)(si.ms[0] + si.ms[1] + si.ms[2] + si.ms[3] + si.ms[4] + si.ms[5]), (double)si.ell};
+    std::memcpy(info6, v, sizeof(v));
+  }
   if (st == HAPOD_OK && sigma && *rank > 0) std::memcpy(sigma, sg.data(), sizeof(double) * *rank);
   return st;
 }

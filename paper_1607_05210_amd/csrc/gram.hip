@@ -400,7 +400,10 @@ store:
         for (int v = 0; v < 4; ++v) {
           int row = cA0 + a * 16 + acc_row<Acc>(lane, v);
           int col = cB0 + b * 16 + acc_col(lane);
-          if (row < nd.m && col < nd.m && row <= col) {
+          if (nd.cross > 0) {
+            if (row < nd.cross && col >= nd.cross && col < nd.m)
+              nd.G[(int64_t)row * nd.ldg + (col - nd.cross)] = (double)acc[a][b][v];
+          } else if (row < nd.m && col < nd.m && row <= col) {
             double x = (double)acc[a][b][v];
             nd.G[(int64_t)col * nd.ldg + row] = x;
             nd.G[(int64_t)row * nd.ldg + col] = x;
@@ -664,10 +667,18 @@ __global__ __launch_bounds__(kReduceSlice) void gram_reduce_kernel(const GramNod
   const int e = blockIdx.y * kReduceSlice + threadIdx.x;
   if (e >= TT * TT) return;
   const int lp = pair - nd.pair_base;
-  // recover (ti, tj) from the local pair index in row-major upper order
-  int ti = 0, rem = lp, rowlen = nd.ntiles;
-  while (rem >= rowlen) { rem -= rowlen; ++ti; --rowlen; }
-  const int tj = ti + rem;
+  int ti = 0, tj = 0;
+  if (nd.cross > 0) {
+    // cross product: compact (left tile, right tile) numbering
+    const int tq = nd.cross / TT, nr = nd.ntiles - tq;
+    ti = lp / nr;
+    tj = tq + lp % nr;
+  } else {
+    // recover (ti, tj) from the local pair index in row-major upper order
+    int rem = lp, rowlen = nd.ntiles;
+    while (rem >= rowlen) { rem -= rowlen; ++ti; --rowlen; }
+    tj = ti + rem;
+  }
   const int i = e % TT, j = e / TT;
   const int row = ti * TT + i, col = tj * TT + j;
   if (row >= nd.m || col >= nd.m || row > col) return;
@@ -684,6 +695,10 @@ __global__ __launch_bounds__(kReduceSlice) void gram_reduce_kernel(const GramNod
     for (int u = 0; u < kReduceUnroll; ++u) s += v[u];
   }
   for (; c < ns; ++c) s += P[(int64_t)c * stride];
+  if (nd.cross > 0) {
+    nd.G[(int64_t)row * nd.ldg + (col - nd.cross)] = s;
+    return;
+  }
   nd.G[(int64_t)col * nd.ldg + row] = s;
   nd.G[(int64_t)row * nd.ldg + col] = s;
 }

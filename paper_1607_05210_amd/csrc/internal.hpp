@@ -72,6 +72,15 @@ struct GramNode {
   int32_t pair_base;   // first tile-pair index of this node in the level
   int32_t split;       // 1: columns hold split-BF16 blocks (see launch_split_cols)
   int32_t tile;        // 128, 64, 32 or 16
+  // cross > 0: a cross product instead of a Gram matrix.  Columns [0, cross)
+  // are the left operand L, columns [cross, m) the right operand Rt; items
+  // cover only tile pairs (ti < cross / tile <= tj), numbered compactly
+  // (local pair = ti * (ntiles - cross / tile) + tj - cross / tile), and
+  // entry (i, j) of L^T Rt goes to G[i * ldg + j] (that is, (L^T Rt)^T
+  // column-major with leading dimension ldg, or L^T Rt row-major).
+  // cross is a multiple of tile (128-column tiles only).
+  int32_t cross;
+  int32_t pad;
 };
 __host__ __device__ inline int gram_slots_per_chunk(int tile) { return tile >= kGramTile ? 1 : 4; }
 
@@ -194,6 +203,16 @@ struct LiftNode {
   int32_t rt_per;        // row tiles per work item (0 or 1: one); the node's
                          // items are ceil(row_tiles / rt_per) x col_tiles
   int32_t pad;
+  // Residual mode (launch_lift_residual, FP64 only): instead of storing the
+  // product P = S B, every output column c is compared with column c of a
+  // second matrix T (column table rcols / rrbs / rrows, N columns, n rows):
+  // the sum over the work item's rows of (T - P)^2 goes to
+  // rpart[(row_group * 2 + h) * N + c], h the half (64 rows) of each
+  // 128-row tile.  Row groups are the items' ceil(row_tiles / rt_per).
+  const void* const* rcols;
+  const int64_t* rrbs;
+  const int64_t* rrows;
+  double* rpart;
 };
 // compute: 0 FP64 MFMA, 1 FP32 MFMA (the split-BF16 form lifts on FP32
 // MFMA); output storage = input storage.
@@ -202,6 +221,10 @@ struct LiftNode {
 constexpr int kLiftNarrowM = 256;
 hapod_status launch_lift(int compute, const LiftNode* d_nodes, int num_nodes,
                          int num_items, hipStream_t stream, bool narrow = false);
+// Residual mode of the FP64 lift (see LiftNode::rcols), one node.
+hapod_status launch_lift_residual(const LiftNode* d_node, int num_items, hipStream_t stream);
+// res[c] = sum over g < groups of rpart[g * N + c], in order of g
+hapod_status launch_sum_partials(const double* rpart, int64_t groups, int64_t N, double* res, hipStream_t stream);
 
 // ---- helpers ----------------------------------------------------------------
 hapod_status launch_fill_colptrs(const void* base, int64_t ld, int64_t m, int elem_bytes,
@@ -263,5 +286,13 @@ hapod_status launch_triu(const double* W, int64_t ldw, int64_t N, double* R, int
 // sweeps taken or -1 without convergence
 hapod_status launch_osj(double* A, int64_t m, double* sigma, double* B, int scaled, int32_t* info,
                         hipStream_t stream);
+
+// ---- sketched local POD (sketch.hip) -----------------------------------------
+// out[i] ~ N(0, 1), i < count, from a counter-based generator (deterministic
+// for a seed, independent of the launch shape)
+hapod_status launch_normal_fill(double* out, int64_t count, uint64_t seed, hipStream_t stream);
+// T = A^T for a square m x m matrix (both column-major)
+hapod_status launch_transpose(const double* A, int64_t lda, int64_t m, double* T, int64_t ldt, hipStream_t stream);
+constexpr int64_t kSketchMaxCols = 512;  // widest sketch (the Jacobi SVD's limit)
 
 }  // namespace hapod

@@ -53,8 +53,11 @@ __device__ __forceinline__ void run4(const float* p, int64_t avail, float (&out)
 
 // NARROW (ranks up to 64): a 256 x 64 tile, the four wavefronts stacked
 // along the rows, so that no wavefront idles on columns past N.
-template <int C, bool NARROW>
+// RES: the residual mode (LiftNode::rcols): the product is compared with the
+// node's second matrix instead of being stored.
+template <int C, bool NARROW, bool RES = false>
 __global__ __launch_bounds__(256) void lift_kernel(const LiftNode* __restrict__ nodes, int num_nodes) {
+  static_assert(!RES || (C == 0 && !NARROW), "residual mode: FP64 128 x 128 tiles");
   constexpr int TMk = NARROW ? 4 * WT : TM;
   constexpr int TNk = NARROW ? WT : TN;
   using Tr = LiftTraits<C>;
@@ -79,6 +82,11 @@ __global__ __launch_bounds__(256) void lift_kernel(const LiftNode* __restrict__ 
   if ((int64_t)ct * TNk >= N) return;  // whole workgroup
   const int rt_per = max(nd.rt_per, 1);
   const int rt_begin = rg * rt_per, rt_end = min(rt_begin + rt_per, nd.row_tiles);
+  // residual mode: per output column of the lane (b), the squared differences
+  // over every row the lane sees, in a fixed order
+  double ssq[NB];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) ssq[b] = 0.0;
 
   __shared__ const char* tcol[KT];
   __shared__ int64_t trbs[KT];
@@ -184,6 +192,35 @@ __global__ __launch_bounds__(256) void lift_kernel(const LiftNode* __restrict__ 
   }
   if (!active) continue;
 
+  if constexpr (RES) {
+    // T - P over the lane's rows r0 + 4 acc_row + a of its columns
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      const int64_t col = n0 + 4 * acc_col(lane) + b;
+      if (col >= N) continue;
+      const double* tc = reinterpret_cast<const double*>(nd.rcols[col]);
+      const int64_t trb = nd.rrbs[col];
+      const int64_t tr = min(nd.rrows[col], nd.n);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t row = r0 + 4 * acc_row<Acc>(lane, v);
+        if (row >= nd.n) continue;
+        double t4[4];
+        if (row < tr) run4(tc + blk_off(row, trb), tr - row, t4);
+        else {
+#pragma unroll
+          for (int a = 0; a < 4; ++a) t4[a] = 0.0;
+        }
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+          const double d = (row + a < nd.n) ? t4[a] - (double)acc[a][b][v] : 0.0;
+          ssq[b] += d * d;
+        }
+      }
+    }
+    continue;
+  }
+
   // lane (g, j) holds, for output column n0 + 4 j + b and accumulator
   // register v, the rows r0 + 4 acc_row + a (a = 0..3): four consecutive
   // rows, written as one vector store
@@ -215,6 +252,27 @@ __global__ __launch_bounds__(256) void lift_kernel(const LiftNode* __restrict__ 
     }
   }
   }  // row tiles
+  if constexpr (RES) {
+    // the four lanes of a column (lane / 16 = 0..3) hold its rows in four
+    // interleaved sets: sum them, then one write per (row half, column)
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      double x = ssq[b];
+      x += __shfl_xor(x, 16);
+      x += __shfl_xor(x, 32);
+      const int64_t col = n0 + 4 * acc_col(lane) + b;
+      if (g == 0 && col < N) nd.rpart[((int64_t)rg * 2 + wi) * N + col] = x;
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void sum_partials_kernel(const double* __restrict__ rpart, int64_t groups, int64_t N,
+                                                           double* __restrict__ res) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= N) return;
+  double s = 0.0;
+  for (int64_t g = 0; g < groups; ++g) s += rpart[g * N + c];
+  res[c] = s;
 }
 
 // FP32 tiles with both operands staged through LDS: per stage KS reduction
@@ -262,6 +320,11 @@ __global__ __launch_bounds__(256, 2) void lift_staged_kernel(const LiftNode* __r
   if ((int64_t)ct * TNk >= N) return;  // whole workgroup
   const int rt_per = max(nd.rt_per, 1);
   const int rt_begin = rg * rt_per, rt_end = min(rt_begin + rt_per, nd.row_tiles);
+  // residual mode: per output column of the lane (b), the squared differences
+  // over every row the lane sees, in a fixed order
+  double ssq[NB];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) ssq[b] = 0.0;
 
   __shared__ __attribute__((aligned(16))) char sS[2][KS * SB];
   __shared__ __attribute__((aligned(16))) char sB[2][KS * BBy];
@@ -470,6 +533,21 @@ hapod_status launch_lift(int compute, const LiftNode* d_nodes, int num_nodes, in
     case 3: hipLaunchKernelGGL((lift_staged_kernel<1, true>), g, b, 0, stream, d_nodes, num_nodes); break;
     default: set_error("launch_lift: unknown compute mode"); return HAPOD_E_INVALID;
   }
+  HAPOD_HIP(hipGetLastError());
+  return HAPOD_OK;
+}
+
+hapod_status launch_lift_residual(const LiftNode* d_node, int num_items, hipStream_t stream) {
+  if (num_items <= 0) return HAPOD_OK;
+  hipLaunchKernelGGL((lift_kernel<0, false, true>), dim3(num_items), dim3(256), 0, stream, d_node, 1);
+  HAPOD_HIP(hipGetLastError());
+  return HAPOD_OK;
+}
+
+hapod_status launch_sum_partials(const double* rpart, int64_t groups, int64_t N, double* res, hipStream_t stream) {
+  if (N <= 0) return HAPOD_OK;
+  hipLaunchKernelGGL(sum_partials_kernel, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, stream, rpart, groups, N,
+                     res);
   HAPOD_HIP(hipGetLastError());
   return HAPOD_OK;
 }

@@ -80,13 +80,13 @@ __global__ __launch_bounds__(256) void gram_zero_scale_kernel(double* G, int64_t
   }
 }
 
-// R (column-major) column j *= D_j; Rinv (row-major) row i *= 1 / D_i
+// R (column-major, may be null) column j *= D_j; Rinv (row-major) row i *= 1 / D_i
 __global__ void unscale_factors_kernel(double* R, int64_t ldr, double* Rinv, int64_t ldi, int64_t m,
                                        const double* D) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= m * m) return;
   const int64_t j = e / m, i = e - j * m;
-  R[j * ldr + i] *= D[j];
+  if (R) R[j * ldr + i] *= D[j];
   Rinv[i * ldi + j] /= D[i];
 }
 
