@@ -1143,15 +1143,37 @@ struct hapod_plan_s {
   Pool pool;
 };
 
-// out = A B[:, :N] in FP64: A is n x m (plain column-major with ld lda, or
-// row-block-tiled when a_tiled), B row-major m x N (ld ldb); out element
-// (r, c) at out[c * ocs + blk_off(r, obs)].  The descriptors come from the
-// pool and go back to it once the launch is queued (all work of the caller is
-// ordered on one stream).
-hapod_status lift_fp64(Pool& pool, int64_t n, int64_t m, const double* A, int64_t lda, bool a_tiled, const double* B,
-                       int64_t ldb, int64_t N, double* out, int64_t ocs, int64_t obs, hipStream_t stream) {
+// A column table: column j starts at p[j], row-block stride rbs[j], and
+// holds rows[j] rows (rows past it read as zero).
+struct Cols {
+  std::vector<const void*> p;
+  std::vector<int64_t> rbs, rows;
+  int64_t size() const { return (int64_t)p.size(); }
+  void append(const Cols& o) {
+    p.insert(p.end(), o.p.begin(), o.p.end());
+    rbs.insert(rbs.end(), o.rbs.begin(), o.rbs.end());
+    rows.insert(rows.end(), o.rows.begin(), o.rows.end());
+  }
+  // m columns of A: plain column-major with leading dimension ld (a_rbs ==
+  // 0), or row-block-tiled with row-block stride a_rbs (column j at
+  // A + kRowBlock j elements)
+  static Cols of(const void* A, int64_t ld, int64_t a_rbs, int64_t m, int64_t rows, int eb) {
+    Cols c;
+    c.p = a_rbs > 0 ? tiled_table(A, m, eb) : column_table(A, ld, m, eb);
+    c.rbs.assign((size_t)m, a_rbs > 0 ? a_rbs : kRowBlock);
+    c.rows.assign((size_t)m, rows);
+    return c;
+  }
+};
+
+// out = A B[:, :N] in FP64: A an n-row column table of m columns, B
+// row-major m x N (ld ldb); out element (r, c) at out[c * ocs + blk_off(r,
+// obs)].  Descriptors come from the pool and go back to it after a stream
+// synchronisation (the uploads read host memory of this call).
+hapod_status lift_cols(Pool& pool, int64_t n, const Cols& A, const double* B, int64_t ldb, int64_t N, double* out,
+                       int64_t ocs, int64_t obs, hipStream_t stream) {
+  const int64_t m = A.size();
   if (n <= 0 || m <= 0 || N <= 0) return HAPOD_OK;
-  const std::vector<const void*> table = a_tiled ? tiled_table(A, m, 8) : column_table(A, lda, m, 8);
   void *dc = nullptr, *dr = nullptr, *dw = nullptr, *dn = nullptr, *dk = nullptr;
   hapod_status st = HAPOD_OK;
   for (auto w : {std::make_pair(sizeof(void*) * m, &dc), std::make_pair(sizeof(int64_t) * m, &dr),
@@ -1177,17 +1199,15 @@ hapod_status lift_fp64(Pool& pool, int64_t n, int64_t m, const double* A, int64_
     l.col_tiles = (int32_t)col_tiles;
     l.rt_per = rt_per;
     const int items = (int)(((row_tiles + rt_per - 1) / rt_per) * col_tiles);
-    if (hipMemcpyAsync(dc, table.data(), sizeof(void*) * m, hipMemcpyHostToDevice, stream) != hipSuccess ||
+    if (hipMemcpyAsync(dc, A.p.data(), sizeof(void*) * m, hipMemcpyHostToDevice, stream) != hipSuccess ||
+        hipMemcpyAsync(dr, A.rbs.data(), sizeof(int64_t) * m, hipMemcpyHostToDevice, stream) != hipSuccess ||
+        hipMemcpyAsync(dw, A.rows.data(), sizeof(int64_t) * m, hipMemcpyHostToDevice, stream) != hipSuccess ||
         hipMemcpyAsync(dn, &l, sizeof(l), hipMemcpyHostToDevice, stream) != hipSuccess) {
       set_error("lift: descriptor upload failed");
       st = HAPOD_E_DEVICE;
     }
-    if (st == HAPOD_OK) st = launch_fill_i64((int64_t*)dr, a_tiled ? tiled_rbs(m) : kRowBlock, m, stream);
-    if (st == HAPOD_OK) st = launch_fill_i64((int64_t*)dw, n, m, stream);
     if (st == HAPOD_OK) st = launch_set_scalar_i64((int64_t*)dk, N, stream);
     if (st == HAPOD_OK) st = launch_lift(0, (const LiftNode*)dn, 1, items, stream);
-    // the host copies above read `table` and `l`: complete them before
-    // those go out of scope
     if (hipStreamSynchronize(stream) != hipSuccess && st == HAPOD_OK) {
       set_error("lift: stream synchronisation failed");
       st = HAPOD_E_DEVICE;
@@ -1198,8 +1218,107 @@ hapod_status lift_fp64(Pool& pool, int64_t n, int64_t m, const double* A, int64_
   return st;
 }
 
+// The same for A plain (a_rbs == 0, ld lda) or row-block-tiled (stride a_rbs).
+hapod_status lift_fp64(Pool& pool, int64_t n, int64_t m, const double* A, int64_t lda, int64_t a_rbs, const double* B,
+                       int64_t ldb, int64_t N, double* out, int64_t ocs, int64_t obs, hipStream_t stream) {
+  return lift_cols(pool, n, Cols::of(A, lda, a_rbs, m, n, 8), B, ldb, N, out, ocs, obs, stream);
+}
+
+// Cross product out = L^T R in FP64 on the Gram kernel's cross mode: L and R
+// n-row column tables, L's width a multiple of 128; out row-major
+// (width(L) x width(R), ld ldo): out[i * ldo + j] = l_i^T r_j.  Rows are
+// split into chunks (partial tiles summed in a fixed order) so that the
+// launch has about 8192 work items.
+hapod_status cross_cols(Pool& pool, int64_t n, const Cols& L, const Cols& R, double* out, int64_t ldo,
+                        hipStream_t stream) {
+  const int64_t ell = L.size(), m = R.size();
+  if (ell % kGramTile != 0 || ell <= 0 || m <= 0 || n <= 0) {
+    set_error("cross product: left width must be a positive multiple of 128");
+    return HAPOD_E_INVALID;
+  }
+  const int tq = (int)(ell / kGramTile);
+  const int64_t mt = ell + m;
+  const int ntiles = (int)((mt + kGramTile - 1) / kGramTile);
+  const int nr = ntiles - tq;
+  const int pairs = tq * nr;
+  const int nch = pick_chunks(n, pairs, 8192, 2048);
+  const int64_t cr = ((n + nch - 1) / nch + kRowBlock - 1) / kRowBlock * kRowBlock;
+  const int nchunks = (int)((n + cr - 1) / cr);
+  Cols X = L;
+  X.append(R);
+  bool vec = (cr % 16) == 0;
+  for (const void* c : X.p) vec = vec && (((uintptr_t)c & 15u) == 0);
+  void *dxc = nullptr, *dxr = nullptr, *dxw = nullptr, *part = nullptr, *blob = nullptr;
+  std::vector<void*> held;
+  auto finish = [&](hapod_status st) {
+    (void)hipStreamSynchronize(stream);
+    for (void* q : held) pool.free(q);
+    return st;
+  };
+  const std::pair<size_t, void**> want[] = {
+      {sizeof(void*) * mt, &dxc}, {sizeof(int64_t) * mt, &dxr}, {sizeof(int64_t) * mt, &dxw},
+      {nchunks > 1 ? sizeof(double) * (size_t)pairs * nchunks * kGramTile * kGramTile : 0, &part}};
+  for (const auto& w : want) {
+    if (w.first == 0) continue;
+    hapod_status st = pool.alloc(w.first, w.second);
+    if (st != HAPOD_OK) return finish(st);
+    held.push_back(*w.second);
+  }
+  GramNode g{};
+  g.cols = (const void* const*)dxc;
+  g.rbs = (const int64_t*)dxr;
+  g.crows = (const int64_t*)dxw;
+  g.n = n;
+  g.chunk_rows = cr;
+  g.G = out;
+  g.partial = (double*)part;
+  g.ldg = ldo;
+  g.m = (int32_t)mt;
+  g.nchunks = nchunks;
+  g.ntiles = ntiles;
+  g.tile = kGramTile;
+  g.cross = (int32_t)ell;
+  // rows each tile holds (inputs of uneven height end early)
+  std::vector<int64_t> tile_rows((size_t)ntiles, 0);
+  for (int64_t c = 0; c < mt; ++c)
+    tile_rows[(size_t)(c / kGramTile)] = std::max(tile_rows[(size_t)(c / kGramTile)], X.rows[(size_t)c]);
+  // consecutive items (one XCD's concurrent workgroups) share the left tiles
+  // and a run of 8 right tiles of one row chunk
+  std::vector<GramItem> items;
+  std::vector<int32_t> rp, rn;
+  for (int c = 0; c < nchunks; ++c)
+    for (int J = tq; J < ntiles; J += 8)
+      for (int ti = 0; ti < tq; ++ti)
+        for (int tj = J; tj < std::min(J + 8, ntiles); ++tj)
+          items.push_back(GramItem{0, (int16_t)ti, (int16_t)tj, c, ti * nr + (tj - tq),
+                                   std::min(tile_rows[(size_t)ti], tile_rows[(size_t)tj])});
+  if (nchunks > 1)
+    for (int p = 0; p < pairs; ++p) {
+      rp.push_back(p);
+      rn.push_back(0);
+    }
+  Blob bl;
+  const size_t o_g = bl.add(&g, sizeof(g)), o_i = bl.add_vec(items), o_rp = bl.add_vec(rp), o_rn = bl.add_vec(rn);
+  hapod_status st = pool.alloc(bl.host.size(), &blob);
+  if (st != HAPOD_OK) return finish(st);
+  held.push_back(blob);
+  char* db = (char*)blob;
+  if (hipMemcpyAsync(db, bl.host.data(), bl.host.size(), hipMemcpyHostToDevice, stream) != hipSuccess ||
+      hipMemcpyAsync(dxc, X.p.data(), sizeof(void*) * mt, hipMemcpyHostToDevice, stream) != hipSuccess ||
+      hipMemcpyAsync(dxr, X.rbs.data(), sizeof(int64_t) * mt, hipMemcpyHostToDevice, stream) != hipSuccess ||
+      hipMemcpyAsync(dxw, X.rows.data(), sizeof(int64_t) * mt, hipMemcpyHostToDevice, stream) != hipSuccess) {
+    set_error("cross product: upload failed");
+    return finish(HAPOD_E_DEVICE);
+  }
+  const GramLaunch gl{kGramTile, vec ? 1 : 0, 0, (int32_t)items.size(), 0};
+  st = launch_gram(0, (const GramNode*)(db + o_g), (const GramItem*)(db + o_i), &gl, 1, (const int32_t*)(db + o_rp),
+                   (const int32_t*)(db + o_rn), (int)rp.size(), kGramTile, stream);
+  return finish(st);
+}
+
 // Cholesky-QR passes Q <- Q R_p^-1 on an n x m FP64 matrix A (plain, ld lda,
-// or row-block-tiled), until Q^T Q is the identity to rounding.  A pass whose
+// for a_rbs == 0, else row-block-tiled with row-block stride a_rbs), until
+// Q^T Q is the identity to rounding.  A pass whose
 // Q^T Q is not within 1/2 of the identity by Gershgorin (m max |Q^T Q - I| >
 // 1/2) is shifted: Q^T Q + s I = R_p^T R_p, s = 11 (n m + m (m + 1)) u
 // tr(Q^T Q), the shift of shifted Cholesky-QR (tr >= ||Q||_2^2), which lifts
@@ -1213,7 +1332,7 @@ hapod_status lift_fp64(Pool& pool, int64_t n, int64_t m, const double* A, int64_
 // QA, QB: two row-block-tiled n x m buffers the passes alternate between (QA
 // may be A itself, then overwritten).  *Q: the buffer holding the final Q.
 // R (device, m x m column-major, may be null): A = Q R with R = R_p ... R_1.
-hapod_status cholqr_core(Pool& pool, int64_t n, int64_t m, const double* A, int64_t lda, bool a_tiled, double* QA,
+hapod_status cholqr_core(Pool& pool, int64_t n, int64_t m, const double* A, int64_t lda, int64_t a_rbs, double* QA,
                          double* QB, double* R, int32_t* zero, const double** Q, int32_t* passes,
                          hipStream_t stream) {
   const size_t mm = sizeof(double) * (size_t)m * m;
@@ -1240,12 +1359,12 @@ hapod_status cholqr_core(Pool& pool, int64_t n, int64_t m, const double* A, int6
   const double u = 1.1102230246251565e-16;
   const int64_t trbs = tiled_rbs(m);
   const double* src = A;
-  bool src_tiled = a_tiled;
+  int64_t src_rbs = a_rbs;
   int64_t ld = lda;
   double* dst = (QA == A) ? QB : QA;
   int plain_run = 0, pass = 0;
   for (; pass < kQrMaxPasses && plain_run < 2; ++pass) {
-    if ((st = gram_impl(0, 8, n, m, src, ld, (double*)G, m, stream, 0, src_tiled ? trbs : 0)) != HAPOD_OK ||
+    if ((st = gram_impl(0, 8, n, m, src, ld, (double*)G, m, stream, 0, src_rbs)) != HAPOD_OK ||
         (st = launch_gram_zero_scale((double*)G, m, m, zero, pass == 0 ? (double*)dD : nullptr, stream)) !=
             HAPOD_OK ||
         (st = launch_identity_dev((double*)G, m, m, (double*)ddev, stream)) != HAPOD_OK)
@@ -1272,10 +1391,10 @@ hapod_status cholqr_core(Pool& pool, int64_t n, int64_t m, const double* A, int6
         return finish(st);
       std::swap(Racc, Rtmp);
     }
-    if ((st = lift_fp64(pool, n, m, src, ld, src_tiled, (double*)Rinv, m, m, dst, kRowBlock, trbs, stream)) != HAPOD_OK)
+    if ((st = lift_fp64(pool, n, m, src, ld, src_rbs, (double*)Rinv, m, m, dst, kRowBlock, trbs, stream)) != HAPOD_OK)
       return finish(st);
     src = dst;
-    src_tiled = true;
+    src_rbs = trbs;
     ld = n;
     dst = (dst == QA) ? QB : QA;
     int32_t bad = 0;
@@ -1326,7 +1445,7 @@ hapod_status qr_pod_core(Pool& pool, int64_t n, int64_t m, double* S, int64_t ld
   };
   const std::pair<size_t, void**> want[] = {
       {mm, &R}, {mm, &Bm}, {sizeof(double) * m, &dsig}, {s_scratch ? 0 : tiled_bytes(n, m, 8), &QA},
-      {tiled_bytes(n, m, 8), &QB}, {sizeof(int32_t), &dinfo}, {sizeof(int32_t) * m, &dzero}};
+      {tiled_bytes(n, m, 8), &QB}, {sizeof(int32_t) * 2, &dinfo}, {sizeof(int32_t) * m, &dzero}};
   for (const auto& w : want) {
     if (w.first == 0) continue;
     hapod_status st = pool.alloc(w.first, w.second);
@@ -1335,7 +1454,7 @@ hapod_status qr_pod_core(Pool& pool, int64_t n, int64_t m, double* S, int64_t ld
   }
   if (s_scratch) QA = S;
   const double* Q = nullptr;
-  hapod_status st = cholqr_core(pool, n, m, S, lds, s_tiled, (double*)QA, (double*)QB, (double*)R, (int32_t*)dzero,
+  hapod_status st = cholqr_core(pool, n, m, S, lds, s_tiled ? tiled_rbs(m) : 0, (double*)QA, (double*)QB, (double*)R, (int32_t*)dzero,
                                 &Q, passes, stream);
   if (st != HAPOD_OK) return finish(st);
   if ((st = launch_zero_rows((double*)R, m, m, (int32_t*)dzero, stream)) != HAPOD_OK) return finish(st);
@@ -1368,7 +1487,7 @@ hapod_status qr_pod_core(Pool& pool, int64_t n, int64_t m, double* S, int64_t ld
     double* out = nullptr;
     int64_t ocs = 0, obs = 0;
     if ((st = out_for_rank(N, &out, &ocs, &obs)) != HAPOD_OK) return finish(st);
-    if ((st = lift_fp64(pool, n, m, Q, n, true, (const double*)Bm, m, N, out, ocs, obs, stream)) != HAPOD_OK)
+    if ((st = lift_fp64(pool, n, m, Q, n, tiled_rbs(m), (const double*)Bm, m, N, out, ocs, obs, stream)) != HAPOD_OK)
       return finish(st);
   }
   *rank = N;
@@ -1377,16 +1496,193 @@ hapod_status qr_pod_core(Pool& pool, int64_t n, int64_t m, double* S, int64_t ld
 }
 
 
+// Residual energy per column: res[j] = ||r_j - Q b_j||^2 (device, m
+// doubles) for Q an n-row column table (ell columns), B row-major ell x m
+// (ld ldb) and R an n-row column table of m columns, by the FP64 lift's
+// residual mode (the product Q B is compared tile by tile, never stored).
+hapod_status residual_cols(Pool& pool, int64_t n, const Cols& Q, const double* B, int64_t ldb, const Cols& R,
+                           double* res, hipStream_t stream) {
+  const int64_t ell = Q.size(), m = R.size();
+  if (n <= 0 || ell <= 0 || m <= 0) return HAPOD_OK;
+  const int64_t row_tiles = (n + kLiftTileM - 1) / kLiftTileM, col_tiles = (m + kLiftTileN - 1) / kLiftTileN;
+  const int rt_per = (int)std::max<int64_t>(1, std::min<int64_t>(16, row_tiles * col_tiles / kLiftTargetItems));
+  const int64_t rgroups = (row_tiles + rt_per - 1) / rt_per;
+  void *dqc = nullptr, *dqr = nullptr, *dqw = nullptr, *drc = nullptr, *drr = nullptr, *drw = nullptr,
+       *rpart = nullptr, *dn = nullptr, *dk = nullptr;
+  std::vector<void*> held;
+  auto finish = [&](hapod_status st) {
+    (void)hipStreamSynchronize(stream);
+    for (void* q : held) pool.free(q);
+    return st;
+  };
+  const std::pair<size_t, void**> want[] = {
+      {sizeof(void*) * ell, &dqc}, {sizeof(int64_t) * ell, &dqr}, {sizeof(int64_t) * ell, &dqw},
+      {sizeof(void*) * m, &drc}, {sizeof(int64_t) * m, &drr}, {sizeof(int64_t) * m, &drw},
+      {sizeof(double) * (size_t)rgroups * 2 * m, &rpart}, {sizeof(LiftNode), &dn}, {sizeof(int64_t), &dk}};
+  for (const auto& w : want) {
+    hapod_status st = pool.alloc(w.first, w.second);
+    if (st != HAPOD_OK) return finish(st);
+    held.push_back(*w.second);
+  }
+  LiftNode l{};
+  l.cols = (const void* const*)dqc;
+  l.rbs = (const int64_t*)dqr;
+  l.crows = (const int64_t*)dqw;
+  l.B = B;
+  l.rank = (const int64_t*)dk;
+  l.n = n;
+  l.ldb = ldb;
+  l.m = (int32_t)ell;
+  l.row_tiles = (int32_t)row_tiles;
+  l.col_tiles = (int32_t)col_tiles;
+  l.rt_per = rt_per;
+  l.rcols = (const void* const*)drc;
+  l.rrbs = (const int64_t*)drr;
+  l.rrows = (const int64_t*)drw;
+  l.rpart = (double*)rpart;
+  auto up = [&](void* d, const void* h, size_t bytes) {
+    return hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, stream) == hipSuccess;
+  };
+  if (!up(dqc, Q.p.data(), sizeof(void*) * ell) || !up(dqr, Q.rbs.data(), sizeof(int64_t) * ell) ||
+      !up(dqw, Q.rows.data(), sizeof(int64_t) * ell) || !up(drc, R.p.data(), sizeof(void*) * m) ||
+      !up(drr, R.rbs.data(), sizeof(int64_t) * m) || !up(drw, R.rows.data(), sizeof(int64_t) * m) ||
+      !up(dn, &l, sizeof(l))) {
+    set_error("residual: upload failed");
+    return finish(HAPOD_E_DEVICE);
+  }
+  hapod_status st = launch_set_scalar_i64((int64_t*)dk, m, stream);
+  if (st == HAPOD_OK) st = launch_lift_residual((const LiftNode*)dn, (int)(rgroups * col_tiles), stream);
+  if (st == HAPOD_OK) st = launch_sum_partials((const double*)rpart, rgroups * 2, m, res, stream);
+  return finish(st);
+}
+
+// Orthonormal basis Q of an n x ell matrix Y (ell a multiple of 128; plain
+// with leading dimension ldy for y_rbs == 0, else row-block-tiled with
+// row-block stride y_rbs), 128 columns at a time, by block Gram-Schmidt with
+// re-orthogonalisation: block b has the earlier blocks' span projected out,
+// W = Y_b - Q_<b C_1 with C_1 = Q_<b^T Y_b (product and subtraction in one
+// lift, [Q_<b, Y_b] [-C_1; I]), W = Q~ R_1 by cholqr_core, then the same
+// projection once more on the orthonormal Q~ (its component along Q_<b,
+// which R_1^-1 amplified by up to cond(W), goes back to rounding level),
+// Q~ - Q_<b C_2 = Q_b R_2 by cholqr_core (two plain passes: Q~ is nearly
+// orthonormal).  A block of a sketch holds about 128 consecutive directions
+// of the spectrum, so its condition number is far below the whole
+// sketch's, and passes of n x 128 replace passes of n x ell.  With R
+// (device, ell x ell column-major, ld ell) non-null, Y = Q R: column block b
+// of R is [C_1 + C_2 R_1; R_2 R_1] (rows of columns that were exactly zero
+// cleared in each factor).  Q: the blocks' buffers (pool blocks appended to
+// `held`, freed by the caller) as one column table.
+hapod_status orth_blocks(Pool& pool, int64_t n, int64_t ell, const double* Y, int64_t ldy, int64_t y_rbs, double* R,
+                         std::vector<void*>& held, Cols& Q, int32_t* passes, hipStream_t stream) {
+  const int64_t B = kGramTile;
+  const int nb = (int)(ell / B);
+  const size_t blk = tiled_bytes(n, B, 8), bb = sizeof(double) * B * B;
+  void *C = nullptr, *dzero = nullptr, *R1 = nullptr, *R2 = nullptr, *Rt = nullptr, *Mt = nullptr;
+  hapod_status st = HAPOD_OK;
+  const std::pair<size_t, void**> want[] = {{sizeof(double) * (size_t)(ell + B) * B, &C}, {sizeof(int32_t) * B, &dzero},
+                                            {bb, &R1}, {bb, &R2}, {bb, &Rt}, {sizeof(double) * (size_t)ell * B, &Mt}};
+  for (const auto& w : want) {
+    if ((st = pool.alloc(w.first, w.second)) != HAPOD_OK) return st;
+    held.push_back(*w.second);
+  }
+  if (R) HAPOD_TRY(launch_zero_bytes(R, sizeof(double) * (size_t)ell * ell, stream));
+  Q = Cols{};
+  if (passes) *passes = 0;
+  for (int b = 0; b < nb; ++b) {
+    void* buf[3] = {nullptr, nullptr, nullptr};
+    for (void*& q : buf)
+      if (st == HAPOD_OK) st = pool.alloc(blk, &q);
+    auto drop = [&](void* keep) {
+      for (void* q : buf)
+        if (q && q != keep) pool.free(q);
+    };
+    if (st != HAPOD_OK) {
+      drop(nullptr);
+      return st;
+    }
+    const int64_t k = Q.size();
+    const double* src = y_rbs > 0 ? Y + (size_t)b * B * kRowBlock : Y + (size_t)b * B * ldy;
+    int64_t src_rbs = y_rbs, src_ld = ldy;
+    // W = Y_b - Q_<b C_1 (C_1 = Q_<b^T Y_b) into buf[0]
+    if (b > 0) {
+      const Cols cur = Cols::of(src, ldy, y_rbs, B, n, 8);
+      Cols X = Q;
+      X.append(cur);
+      if ((st = cross_cols(pool, n, Q, cur, (double*)C, B, stream)) == HAPOD_OK && R)
+        st = launch_acc_transposed(R, ell, (int64_t)b * B, (const double*)C, B, k, B, stream);
+      if (st == HAPOD_OK && (st = launch_neg_ident((double*)C, k, B, B, stream)) == HAPOD_OK)
+        st = lift_cols(pool, n, X, (const double*)C, B, B, (double*)buf[0], kRowBlock, tiled_rbs(B), stream);
+      src = (const double*)buf[0];
+      src_rbs = tiled_rbs(B);
+      src_ld = n;
+    }
+    // W = Q~ R_1; block 0 reads Y and alternates between buf[0] and buf[1],
+    // later blocks start from buf[0], which may be overwritten
+    const double* Qt = nullptr;
+    int32_t p1 = 0, p2 = 0;
+    if (st == HAPOD_OK)
+      st = cholqr_core(pool, n, B, src, src_ld, src_rbs, (double*)buf[0], (double*)buf[1], (double*)R1,
+                       (int32_t*)dzero, &Qt, &p1, stream);
+    if (st == HAPOD_OK) st = launch_zero_rows((double*)R1, B, B, (int32_t*)dzero, stream);
+    const double* Qb = Qt;
+    if (b > 0 && st == HAPOD_OK) {
+      // Q~ - Q_<b C_2 (C_2 = Q_<b^T Q~) into the free buffer, then Q_b R_2
+      void* freeb = (Qt == (const double*)buf[0]) ? buf[1] : buf[0];
+      void* other = buf[2];
+      const Cols cur = Cols::of(Qt, n, tiled_rbs(B), B, n, 8);
+      Cols X = Q;
+      X.append(cur);
+      if ((st = cross_cols(pool, n, Q, cur, (double*)C, B, stream)) == HAPOD_OK && R) {
+        // C_2 R_1: C_2 row-major k x B is C_2^T column-major (B x k); (C_2 R_1)
+        // row-major = R_1^T C_2^T column-major
+        if ((st = launch_transpose((const double*)R1, B, B, (double*)Rt, B, stream)) == HAPOD_OK &&
+            (st = launch_dgemm_nn(B, k, B, (const double*)Rt, B, (const double*)C, B, (double*)Mt, B, stream)) ==
+                HAPOD_OK)
+          st = launch_acc_transposed(R, ell, (int64_t)b * B, (const double*)Mt, B, k, B, stream);
+      }
+      if (st == HAPOD_OK && (st = launch_neg_ident((double*)C, k, B, B, stream)) == HAPOD_OK)
+        st = lift_cols(pool, n, X, (const double*)C, B, B, (double*)freeb, kRowBlock, tiled_rbs(B), stream);
+      if (st == HAPOD_OK)
+        st = cholqr_core(pool, n, B, (const double*)freeb, n, tiled_rbs(B), (double*)freeb, (double*)other,
+                         (double*)R2, (int32_t*)dzero, &Qb, &p2, stream);
+      if (st == HAPOD_OK) st = launch_zero_rows((double*)R2, B, B, (int32_t*)dzero, stream);
+      // diagonal block R_2 R_1
+      if (st == HAPOD_OK && R)
+        st = launch_dgemm_nn(B, B, B, (const double*)R2, B, (const double*)R1, B, (double*)Rt, B, stream);
+    }
+    if (st == HAPOD_OK && R) {
+      const void* diag = (b > 0) ? Rt : R1;
+      if (hipMemcpy2DAsync(R + (size_t)b * B * ell + (size_t)b * B, sizeof(double) * ell, diag, sizeof(double) * B,
+                           sizeof(double) * B, B, hipMemcpyDeviceToDevice, stream) != hipSuccess) {
+        set_error("orthonormalisation: copy of a block factor failed");
+        st = HAPOD_E_DEVICE;
+      }
+    }
+    if (st != HAPOD_OK) {
+      drop(nullptr);
+      return st;
+    }
+    if (passes) *passes += p1 + p2;
+    void* keep = nullptr;
+    for (void* q : buf)
+      if ((const double*)q == Qb) keep = q;
+    drop(keep);
+    held.push_back(keep);
+    Q.append(Cols::of(keep, n, tiled_rbs(B), B, n, 8));
+  }
+  return HAPOD_OK;
+}
+
 // Sketched local POD of a wide node (FP64), for nodes whose Gram matrix
 // cannot resolve the truncation (Rem. 2.3: the method of snapshots knows
 // sigma_k^2 only to about u sigma_1^2).  A randomized range finder (Halko,
 // Martinsson & Tropp, SIAM Review 2011, Alg. 4.1 and Sec. 5.1):
 //   Y = S Omega        Omega m x ell Gaussian (counter-based, seeded)
-//   Y = Q R_Y          cholqr_core: Q orthonormal to rounding
+//   Y = Q R_Y          orth_blocks: Q orthonormal to rounding
 //   B = Q^T S          ell x m (cross-product mode of the Gram kernel; stored
 //                      as B^T, m x ell)
 //   r = ||S - Q B||_F^2  from the residual itself (residual mode of the lift)
-//   B^T = Q' R'        cholqr_core; then B = R'^T Q'^T and the left singular
+//   B^T = Q' R'        orth_blocks; then B = R'^T Q'^T and the left singular
 //                      vectors and singular values of B are those of R'^T:
 //                      one-sided Jacobi on the columns of R'^T
 //   U = Q U_B          (scaled: Q U_B diag(sigma))
@@ -1407,22 +1703,13 @@ hapod_status sketch_pod_core(Pool& pool, int64_t n, int64_t m, const std::vector
   *rank = 0;
   SketchInfo si;
   si.ell = ell;
-  const int tq = (int)(ell / kGramTile);
-  const int64_t mt = m + ell;                            // cross-product columns [Q, S]
-  const int ntiles = (int)((mt + kGramTile - 1) / kGramTile);
-  const int nr = ntiles - tq;                            // tiles of S
-  const int pairs = tq * nr;
-  const int nch = pick_chunks(n, pairs, 8192, 2048);
-  int64_t cr = ((n + nch - 1) / nch + kRowBlock - 1) / kRowBlock * kRowBlock;
-  const int nchunks = (int)((n + cr - 1) / cr);
-  const int64_t row_tiles = (n + kLiftTileM - 1) / kLiftTileM, col_tiles = (m + kLiftTileN - 1) / kLiftTileN;
-  const int rt_per = (int)std::max<int64_t>(1, std::min<int64_t>(16, row_tiles * col_tiles / kLiftTargetItems));
-  const int64_t rgroups = (row_tiles + rt_per - 1) / rt_per;
+  Cols Sc;
+  Sc.p = cols;
+  Sc.rbs = rbs;
+  Sc.rows = crows;
   const size_t ll = sizeof(double) * (size_t)ell * ell;
-  void *dsc = nullptr, *dsr = nullptr, *dsw = nullptr, *Om = nullptr, *QA = nullptr, *QB = nullptr, *Bt = nullptr,
-       *dxc = nullptr, *dxr = nullptr, *dxw = nullptr, *part = nullptr, *blob = nullptr, *rpart = nullptr,
-       *res = nullptr, *dln = nullptr, *dk = nullptr, *PA = nullptr, *PB = nullptr, *Rb = nullptr, *M = nullptr,
-       *UB = nullptr, *dsig = nullptr, *dinfo = nullptr, *dzy = nullptr, *dzb = nullptr;
+  void *Om = nullptr, *Y = nullptr, *Bt = nullptr, *res = nullptr, *Rb = nullptr, *M = nullptr, *UB = nullptr,
+       *dsig = nullptr, *dinfo = nullptr;
   std::vector<void*> held;
   hipEvent_t ev[7] = {};
   auto finish = [&](hapod_status st) {
@@ -1439,165 +1726,40 @@ hapod_status sketch_pod_core(Pool& pool, int64_t n, int64_t m, const std::vector
       return finish(HAPOD_E_DEVICE);
     }
   const std::pair<size_t, void**> want[] = {
-      {sizeof(void*) * m, &dsc}, {sizeof(int64_t) * m, &dsr}, {sizeof(int64_t) * m, &dsw},
-      {sizeof(double) * (size_t)m * ell, &Om}, {tiled_bytes(n, ell, 8), &QA}, {tiled_bytes(n, ell, 8), &QB},
-      {sizeof(double) * (size_t)m * ell, &Bt}, {sizeof(void*) * mt, &dxc}, {sizeof(int64_t) * mt, &dxr},
-      {sizeof(int64_t) * mt, &dxw},
-      {nchunks > 1 ? sizeof(double) * (size_t)pairs * nchunks * kGramTile * kGramTile : 0, &part},
-      {sizeof(double) * (size_t)rgroups * 2 * m, &rpart}, {sizeof(double) * m, &res}, {sizeof(LiftNode), &dln},
-      {sizeof(int64_t), &dk}, {tiled_bytes(m, ell, 8), &PA}, {tiled_bytes(m, ell, 8), &PB}, {ll, &Rb}, {ll, &M},
-      {ll, &UB}, {sizeof(double) * ell, &dsig}, {sizeof(int32_t), &dinfo}, {sizeof(int32_t) * ell, &dzy},
-      {sizeof(int32_t) * ell, &dzb}};
+      {sizeof(double) * (size_t)m * ell, &Om}, {tiled_bytes(n, ell, 8), &Y}, {sizeof(double) * (size_t)m * ell, &Bt},
+      {sizeof(double) * m, &res}, {ll, &Rb}, {ll, &M}, {ll, &UB}, {sizeof(double) * ell, &dsig},
+      {sizeof(int32_t) * 2, &dinfo}};
   for (const auto& w : want) {
-    if (w.first == 0) continue;
     hapod_status st = pool.alloc(w.first, w.second);
     if (st != HAPOD_OK) return finish(st);
     held.push_back(*w.second);
   }
   hapod_status st = HAPOD_OK;
-  auto up = [&](void* dst, const void* src, size_t bytes) {
-    return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, stream) == hipSuccess;
-  };
-  if (!up(dsc, cols.data(), sizeof(void*) * m) || !up(dsr, rbs.data(), sizeof(int64_t) * m) ||
-      !up(dsw, crows.data(), sizeof(int64_t) * m)) {
-    set_error("sketched POD: upload failed");
-    return finish(HAPOD_E_DEVICE);
-  }
   (void)hipEventRecord(ev[0], stream);
   // ---- Y = S Omega ------------------------------------------------------------
-  if ((st = launch_normal_fill((double*)Om, m * ell, seed, stream)) != HAPOD_OK) return finish(st);
-  LiftNode ly{};
-  ly.cols = (const void* const*)dsc;
-  ly.rbs = (const int64_t*)dsr;
-  ly.crows = (const int64_t*)dsw;
-  ly.B = (const double*)Om;
-  ly.rank = (const int64_t*)dk;
-  ly.out = QA;
-  ly.n = n;
-  ly.ldb = ell;
-  ly.ocs = kRowBlock;
-  ly.obs = tiled_rbs(ell);
-  ly.m = (int32_t)m;
-  ly.row_tiles = (int32_t)row_tiles;
-  ly.col_tiles = (int32_t)((ell + kLiftTileN - 1) / kLiftTileN);
-  ly.rt_per = (int)std::max<int64_t>(1, std::min<int64_t>(16, row_tiles * ly.col_tiles / kLiftTargetItems));
-  const int y_items = (int)(((row_tiles + ly.rt_per - 1) / ly.rt_per) * ly.col_tiles);
-  if (!up(dln, &ly, sizeof(ly))) {
-    set_error("sketched POD: upload failed");
-    return finish(HAPOD_E_DEVICE);
-  }
-  if ((st = launch_set_scalar_i64((int64_t*)dk, ell, stream)) != HAPOD_OK ||
-      (st = launch_lift(0, (const LiftNode*)dln, 1, y_items, stream)) != HAPOD_OK)
+  if ((st = launch_normal_fill((double*)Om, m * ell, seed, stream)) != HAPOD_OK ||
+      (st = lift_cols(pool, n, Sc, (const double*)Om, ell, ell, (double*)Y, kRowBlock, tiled_rbs(ell), stream)) !=
+          HAPOD_OK)
     return finish(st);
   (void)hipEventRecord(ev[1], stream);
   // ---- Q = orth(Y) ---------------------------------------------------------------
-  const double* Q = nullptr;
-  if ((st = cholqr_core(pool, n, ell, (const double*)QA, n, true, (double*)QA, (double*)QB, nullptr, (int32_t*)dzy,
-                        &Q, &si.passes_y, stream)) != HAPOD_OK)
+  Cols Q;
+  if ((st = orth_blocks(pool, n, ell, (const double*)Y, n, tiled_rbs(ell), nullptr, held, Q, &si.passes_y, stream)) !=
+      HAPOD_OK)
     return finish(st);
   (void)hipEventRecord(ev[2], stream);
-  // ---- B^T = S^T Q: cross product of [Q, S] ------------------------------------------
-  {
-    std::vector<const void*> xc = tiled_table(Q, ell, 8);
-    std::vector<int64_t> xr((size_t)ell, tiled_rbs(ell)), xw((size_t)ell, n);
-    xc.insert(xc.end(), cols.begin(), cols.end());
-    xr.insert(xr.end(), rbs.begin(), rbs.end());
-    xw.insert(xw.end(), crows.begin(), crows.end());
-    bool vec = (cr % 16) == 0;
-    for (const void* c : xc) vec = vec && (((uintptr_t)c & 15u) == 0);
-    GramNode g{};
-    g.cols = (const void* const*)dxc;
-    g.rbs = (const int64_t*)dxr;
-    g.crows = (const int64_t*)dxw;
-    g.n = n;
-    g.chunk_rows = cr;
-    g.G = (double*)Bt;
-    g.partial = (double*)part;
-    g.ldg = m;
-    g.m = (int32_t)mt;
-    g.nchunks = nchunks;
-    g.ntiles = ntiles;
-    g.tile = kGramTile;
-    g.cross = (int32_t)ell;
-    // rows each tile holds (inputs of uneven height end early)
-    std::vector<int64_t> tile_rows((size_t)ntiles, 0);
-    for (int64_t c = 0; c < mt; ++c) tile_rows[(size_t)(c / kGramTile)] = std::max(tile_rows[(size_t)(c / kGramTile)], xw[(size_t)c]);
-    // consecutive items (one XCD's concurrent workgroups) share the Q tiles
-    // and a run of 8 S tiles of one row chunk
-    std::vector<GramItem> items;
-    std::vector<int32_t> rp, rn;
-    for (int c = 0; c < nchunks; ++c)
-      for (int J = tq; J < ntiles; J += 8)
-        for (int ti = 0; ti < tq; ++ti)
-          for (int tj = J; tj < std::min(J + 8, ntiles); ++tj)
-            items.push_back(GramItem{0, (int16_t)ti, (int16_t)tj, c, ti * nr + (tj - tq),
-                                     std::min(tile_rows[(size_t)ti], tile_rows[(size_t)tj])});
-    if (nchunks > 1)
-      for (int p = 0; p < pairs; ++p) {
-        rp.push_back(p);
-        rn.push_back(0);
-      }
-    Blob b;
-    const size_t o_g = b.add(&g, sizeof(g)), o_i = b.add_vec(items), o_rp = b.add_vec(rp), o_rn = b.add_vec(rn);
-    if ((st = pool.alloc(b.host.size(), &blob)) != HAPOD_OK) return finish(st);
-    held.push_back(blob);
-    char* db = (char*)blob;
-    if (!up(db, b.host.data(), b.host.size()) || !up(dxc, xc.data(), sizeof(void*) * mt) ||
-        !up(dxr, xr.data(), sizeof(int64_t) * mt) || !up(dxw, xw.data(), sizeof(int64_t) * mt)) {
-      set_error("sketched POD: upload failed");
-      return finish(HAPOD_E_DEVICE);
-    }
-    const GramLaunch gl{kGramTile, vec ? 1 : 0, 0, (int32_t)items.size(), 0};
-    if ((st = launch_gram(0, (const GramNode*)(db + o_g), (const GramItem*)(db + o_i), &gl, 1,
-                          (const int32_t*)(db + o_rp), (const int32_t*)(db + o_rn), (int)rp.size(), kGramTile,
-                          stream)) != HAPOD_OK)
-      return finish(st);
-    // the uploads read host vectors of this scope
-    if (hipStreamSynchronize(stream) != hipSuccess) {
-      set_error("sketched POD: synchronisation failed");
-      return finish(HAPOD_E_DEVICE);
-    }
-  }
+  // ---- B^T = S^T Q (row-major B, ell x m) -----------------------------------------------
+  if ((st = cross_cols(pool, n, Q, Sc, (double*)Bt, m, stream)) != HAPOD_OK) return finish(st);
   (void)hipEventRecord(ev[3], stream);
   // ---- residual energy per column: ||s_j - Q b_j||^2 --------------------------------
-  {
-    LiftNode lr{};
-    lr.cols = (const void* const*)dxc;  // the first ell entries: Q's columns
-    lr.rbs = (const int64_t*)dxr;
-    lr.crows = (const int64_t*)dxw;
-    lr.B = (const double*)Bt;          // B row-major ell x m = B^T column-major
-    lr.rank = (const int64_t*)dk;
-    lr.n = n;
-    lr.ldb = m;
-    lr.m = (int32_t)ell;
-    lr.row_tiles = (int32_t)row_tiles;
-    lr.col_tiles = (int32_t)col_tiles;
-    lr.rt_per = rt_per;
-    lr.rcols = (const void* const*)dsc;
-    lr.rrbs = (const int64_t*)dsr;
-    lr.rrows = (const int64_t*)dsw;
-    lr.rpart = (double*)rpart;
-    if (!up(dln, &lr, sizeof(lr))) {
-      set_error("sketched POD: upload failed");
-      return finish(HAPOD_E_DEVICE);
-    }
-    if ((st = launch_set_scalar_i64((int64_t*)dk, m, stream)) != HAPOD_OK ||
-        (st = launch_lift_residual((const LiftNode*)dln, (int)(rgroups * col_tiles), stream)) != HAPOD_OK ||
-        (st = launch_sum_partials((const double*)rpart, rgroups * 2, m, (double*)res, stream)) != HAPOD_OK)
-      return finish(st);
-    if (hipStreamSynchronize(stream) != hipSuccess) {
-      set_error("sketched POD: synchronisation failed");
-      return finish(HAPOD_E_DEVICE);
-    }
-  }
+  if ((st = residual_cols(pool, n, Q, (const double*)Bt, m, Sc, (double*)res, stream)) != HAPOD_OK) return finish(st);
   (void)hipEventRecord(ev[4], stream);
   // ---- SVD of B through B^T = Q' R' -----------------------------------------------------
-  const double* Qb = nullptr;
-  if ((st = cholqr_core(pool, m, ell, (const double*)Bt, m, false, (double*)PA, (double*)PB, (double*)Rb,
-                        (int32_t*)dzb, &Qb, &si.passes_b, stream)) != HAPOD_OK)
+  Cols Qt;
+  if ((st = orth_blocks(pool, m, ell, (const double*)Bt, m, 0, (double*)Rb, held, Qt, &si.passes_b, stream)) !=
+      HAPOD_OK)
     return finish(st);
-  if ((st = launch_zero_rows((double*)Rb, ell, ell, (int32_t*)dzb, stream)) != HAPOD_OK ||
-      (st = launch_transpose((const double*)Rb, ell, ell, (double*)M, ell, stream)) != HAPOD_OK ||
+  if ((st = launch_transpose((const double*)Rb, ell, ell, (double*)M, ell, stream)) != HAPOD_OK ||
       (st = launch_osj((double*)M, ell, (double*)dsig, (double*)UB, scaled ? 1 : 0, (int32_t*)dinfo, stream)) !=
           HAPOD_OK)
     return finish(st);
@@ -1638,8 +1800,7 @@ hapod_status sketch_pod_core(Pool& pool, int64_t n, int64_t m, const std::vector
     double* out = nullptr;
     int64_t ocs = 0, obs = 0;
     if ((st = out_for_rank(N, &out, &ocs, &obs)) != HAPOD_OK) return finish(st);
-    if ((st = lift_fp64(pool, n, ell, Q, n, true, (const double*)UB, ell, N, out, ocs, obs, stream)) != HAPOD_OK)
-      return finish(st);
+    if ((st = lift_cols(pool, n, Q, (const double*)UB, ell, N, out, ocs, obs, stream)) != HAPOD_OK) return finish(st);
   }
   (void)hipEventRecord(ev[6], stream);
   (void)hipEventSynchronize(ev[6]);

@@ -282,8 +282,11 @@ hapod_status launch_zero_rows(double* R, int64_t ldr, int64_t m, const int32_t* 
 hapod_status launch_triu(const double* W, int64_t ldw, int64_t N, double* R, int64_t ldr, hipStream_t stream);
 // one-sided Jacobi SVD of A (m x m, column-major, ld m, overwritten): sigma
 // (device, m, descending), B (device, row-major m x m): column p is the
-// p-th left singular vector times sigma_p (scaled) or alone; info[0] =
-// sweeps taken or -1 without convergence
+// p-th left singular vector times sigma_p (scaled) or alone; info (device, 2
+// int32): info[0] = sweeps taken or -1 without convergence, info[1] scratch.
+// m <= 64: one workgroup with A in LDS (asynchronous); above, block Jacobi
+// over blocks of 16 columns, one launch per round and a readback per sweep
+// (synchronises the stream).
 hapod_status launch_osj(double* A, int64_t m, double* sigma, double* B, int scaled, int32_t* info,
                         hipStream_t stream);
 
@@ -293,6 +296,13 @@ hapod_status launch_osj(double* A, int64_t m, double* sigma, double* B, int scal
 hapod_status launch_normal_fill(double* out, int64_t count, uint64_t seed, hipStream_t stream);
 // T = A^T for a square m x m matrix (both column-major)
 hapod_status launch_transpose(const double* A, int64_t lda, int64_t m, double* T, int64_t ldt, hipStream_t stream);
+// C (row-major, ld ld, rows_c + cols rows): the first rows_c rows negated,
+// the next cols rows the identity
+hapod_status launch_neg_ident(double* C, int64_t rows_c, int64_t cols, int64_t ld, hipStream_t stream);
+// R[(c0 + j) * ldr + i] += C[i * ldc + j] for i < rows, j < cols: a row-major
+// block added, transposed, into column-major R
+hapod_status launch_acc_transposed(double* R, int64_t ldr, int64_t c0, const double* C, int64_t ldc, int64_t rows,
+                                   int64_t cols, hipStream_t stream);
 constexpr int64_t kSketchMaxCols = 512;  // widest sketch (the Jacobi SVD's limit)
 
 }  // namespace hapod

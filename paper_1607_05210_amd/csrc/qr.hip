@@ -104,15 +104,48 @@ __global__ void triu_kernel(const double* __restrict__ W, int64_t ldw, int64_t N
   if (i < N) R[j * ldr + i] = (i <= j) ? W[j * ldw + i] : 0.0;
 }
 
-// One-sided Jacobi on the columns of X (m x m, column-major, ld m): plane
-// rotations on column pairs until every pair is orthogonal to m u of its
-// norms; the pairs of a round are disjoint (round-robin order), a group of
-// 16 lanes per pair (four pairs per wavefront at once), the squared norms
-// carried across the rotations of a sweep.  Then
-// sigma_c = ||x_c||, sorted descending, and B (row-major, ld m) column p =
-// x_c (scaled) or x_c / sigma_c.  info: sweeps taken, or -1 without
-// convergence.
-template <bool kLds>
+// The plane rotation [c s; -s c] that makes columns x, y (squared norms a,
+// b, inner product g) orthogonal, the smaller angle (Golub & Van Loan): x <-
+// c x - s y, y <- s x + c y, a <- a - t g, b <- b + t g.
+__device__ __forceinline__ void jacobi_angle(double a, double b, double g, double& c, double& s, double& t) {
+  const double zeta = (b - a) / (2.0 * g);
+  t = fabs(zeta) > 1e150 ? 0.5 / zeta : (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+  c = 1.0 / sqrt(1.0 + t * t);
+  s = c * t;
+}
+
+// sigma_c = ||x_c||, sorted descending (equal values by index), and B
+// (row-major, ld m) column p = x_c (scaled) or x_c / sigma_c, for the
+// converged columns of X (m x m, ld m); one workgroup.
+__device__ void osj_finish(const double* X, int64_t m, double* sigma, double* B, int scaled, double* sg, int32_t* pos) {
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  for (int64_t c = wv; c < m; c += kOsjWaves) {
+    double s = 0.0;
+    for (int64_t k = lane; k < m; k += 64) s += X[c * m + k] * X[c * m + k];
+    s = wave_sum(s);
+    if (lane == 0) sg[c] = sqrt(s);
+  }
+  __syncthreads();
+  for (int64_t c = t; c < m; c += kOsjThreads) {
+    int32_t rk = 0;
+    for (int64_t d = 0; d < m; ++d) rk += (sg[d] > sg[c] || (sg[d] == sg[c] && d < c)) ? 1 : 0;
+    pos[c] = rk;
+    sigma[rk] = sg[c];
+  }
+  __syncthreads();
+  for (int64_t e = t; e < m * m; e += kOsjThreads) {
+    const int64_t c = e / m, k = e - c * m;
+    const double sc = scaled ? 1.0 : (sg[c] > 0.0 ? 1.0 / sg[c] : 0.0);
+    B[k * m + pos[c]] = X[c * m + k] * sc;
+  }
+}
+
+// One-sided Jacobi on the columns of X (m x m, column-major, ld m, m <= 128)
+// in one workgroup with X in LDS: plane rotations on column pairs until every
+// pair is orthogonal to m u of its norms; the pairs of a round are disjoint
+// (round-robin order), a group of 16 lanes per pair (four pairs per
+// wavefront at once), the squared norms carried across the rotations of a
+// sweep.  Then osj_finish.  info: sweeps taken, or -1 without convergence.
 __global__ __launch_bounds__(kOsjThreads) void osj_kernel(double* A, int64_t m, double* sigma, double* B, int scaled,
                                                           int32_t* info) {
   extern __shared__ double osj_lds[];
@@ -120,13 +153,11 @@ __global__ __launch_bounds__(kOsjThreads) void osj_kernel(double* A, int64_t m, 
   __shared__ int32_t pos[kQrMaxM];
   __shared__ double nrm[kQrMaxM];  // squared column norms, carried across rotations
   __shared__ int nrot;
-  double* X = kLds ? osj_lds : A;
-  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  double* X = osj_lds;
+  const int t = threadIdx.x;
   const int gl = t & (kOsjGroup - 1), grp = t / kOsjGroup;
-  if (kLds) {
-    for (int64_t e = t; e < m * m; e += kOsjThreads) X[e] = A[e];
-  }
-  const int mi = (int)m;             // m <= 512: pair indices in 32-bit arithmetic
+  for (int64_t e = t; e < m * m; e += kOsjThreads) X[e] = A[e];
+  const int mi = (int)m;
   const int mm = mi + (mi & 1);
   const double tol = (double)m * 1.1102230246251565e-16;
   int sweep = 0;
@@ -166,11 +197,8 @@ __global__ __launch_bounds__(kOsjThreads) void osj_kernel(double* A, int64_t m, 
 #pragma unroll
         for (int off = kOsjGroup / 2; off > 0; off >>= 1) g += __shfl_xor(g, off, kOsjGroup);
         if (!(a > 0.0) || !(b > 0.0) || fabs(g) <= tol * sqrt(a) * sqrt(b)) continue;
-        // rotation [c s; -s c] that makes the pair orthogonal, the smaller angle
-        const double zeta = (b - a) / (2.0 * g);
-        const double tt = fabs(zeta) > 1e150 ? 0.5 / zeta
-                                             : (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-        const double c = 1.0 / sqrt(1.0 + tt * tt), s = c * tt;
+        double c, s, tt;
+        jacobi_angle(a, b, g, c, s, tt);
         for (int k = gl; k < mi; k += kOsjGroup) {
           const double x = ci[k], y = cj[k];
           ci[k] = c * x - s * y;
@@ -187,26 +215,104 @@ __global__ __launch_bounds__(kOsjThreads) void osj_kernel(double* A, int64_t m, 
     done = (nrot == 0);
     __syncthreads();
   }
-  for (int64_t c = wv; c < m; c += kOsjWaves) {
-    double s = 0.0;
-    for (int64_t k = lane; k < m; k += 64) s += X[c * m + k] * X[c * m + k];
-    s = wave_sum(s);
-    if (lane == 0) sg[c] = sqrt(s);
-  }
-  __syncthreads();
-  for (int64_t c = t; c < m; c += kOsjThreads) {
-    int32_t rk = 0;
-    for (int64_t d = 0; d < m; ++d) rk += (sg[d] > sg[c] || (sg[d] == sg[c] && d < c)) ? 1 : 0;
-    pos[c] = rk;
-    sigma[rk] = sg[c];
-  }
-  __syncthreads();
-  for (int64_t e = t; e < m * m; e += kOsjThreads) {
-    const int64_t c = e / m, k = e - c * m;
-    const double sc = scaled ? 1.0 : (sg[c] > 0.0 ? 1.0 / sg[c] : 0.0);
-    B[k * m + pos[c]] = X[c * m + k] * sc;
-  }
+  osj_finish(X, m, sigma, B, scaled, sg, pos);
   if (t == 0) info[0] = done ? sweep : -1;
+}
+
+// Block one-sided Jacobi (columns in blocks of kOsjBlk; a sweep visits every
+// pair of blocks once in round-robin order): one launch per round, one
+// workgroup per block pair of the round.  The workgroup loads its
+// 2 kOsjBlk columns (m rows each) into LDS, computes their squared norms
+// exactly, runs one cyclic sweep over them (2 kOsjBlk - 1 rounds of kOsjBlk
+// disjoint pairs, one wavefront per pair, the norms carried across the
+// rotations) and writes them back; the rotations it applied are added to
+// *count.  Blocks past the last (odd block count) are skipped.
+constexpr int kOsjBlk = 16;
+__global__ __launch_bounds__(kOsjThreads) void osj_block_round_kernel(double* X, int m, int nbe, int r,
+                                                                      int32_t* count) {
+  extern __shared__ double osj_lds[];
+  __shared__ double nrm[2 * kOsjBlk];
+  __shared__ int nrot;
+  const int nb1 = nbe - 1, p = blockIdx.x;
+  int I, J;
+  if (p == 0) {
+    I = nb1;
+    J = r;
+  } else {
+    I = r + p;
+    if (I >= nb1) I -= nb1;
+    J = r - p;
+    if (J < 0) J += nb1;
+  }
+  const int nb = (m + kOsjBlk - 1) / kOsjBlk;
+  if (I >= nb || J >= nb) return;
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  constexpr int LC = 2 * kOsjBlk;
+  double* L = osj_lds;
+  // local column lc: block I's columns, then block J's; columns past m are zero
+  for (int e = t; e < LC * m; e += kOsjThreads) {
+    const int lc = e / m, k = e - lc * m;
+    const int gc = lc < kOsjBlk ? I * kOsjBlk + lc : J * kOsjBlk + (lc - kOsjBlk);
+    L[e] = gc < m ? X[(int64_t)gc * m + k] : 0.0;
+  }
+  if (t == 0) nrot = 0;
+  __syncthreads();
+  for (int lc = wv; lc < LC; lc += kOsjWaves) {
+    double q = 0.0;
+    for (int k = lane; k < m; k += 64) q += L[lc * m + k] * L[lc * m + k];
+    q = wave_sum(q);
+    if (lane == 0) nrm[lc] = q;
+  }
+  __syncthreads();
+  const double tol = (double)m * 1.1102230246251565e-16;
+  static_assert(kOsjWaves == kOsjBlk, "one wavefront per pair of a round");
+  for (int rr = 0; rr < LC - 1; ++rr) {
+    int i, j;
+    if (wv == 0) {
+      i = LC - 1;
+      j = rr;
+    } else {
+      i = rr + wv;
+      if (i >= LC - 1) i -= LC - 1;
+      j = rr - wv;
+      if (j < 0) j += LC - 1;
+    }
+    double* ci = L + i * m;
+    double* cj = L + j * m;
+    const double a = nrm[i], b = nrm[j];
+    double g = 0.0;
+    for (int k = lane; k < m; k += 64) g += ci[k] * cj[k];
+    g = wave_sum(g);
+    if (a > 0.0 && b > 0.0 && fabs(g) > tol * sqrt(a) * sqrt(b)) {
+      double c, s, tt;
+      jacobi_angle(a, b, g, c, s, tt);
+      for (int k = lane; k < m; k += 64) {
+        const double x = ci[k], y = cj[k];
+        ci[k] = c * x - s * y;
+        cj[k] = s * x + c * y;
+      }
+      if (lane == 0) {
+        nrm[i] = fmax(a - tt * g, 0.0);
+        nrm[j] = b + tt * g;
+        atomicAdd(&nrot, 1);
+      }
+    }
+    __syncthreads();
+  }
+  for (int e = t; e < LC * m; e += kOsjThreads) {
+    const int lc = e / m, k = e - lc * m;
+    const int gc = lc < kOsjBlk ? I * kOsjBlk + lc : J * kOsjBlk + (lc - kOsjBlk);
+    if (gc < m) X[(int64_t)gc * m + k] = L[e];
+  }
+  if (t == 0 && nrot > 0) atomicAdd(count, nrot);
+}
+
+__global__ __launch_bounds__(kOsjThreads) void osj_finish_kernel(const double* X, int64_t m, double* sigma, double* B,
+                                                                 int scaled, int32_t* info, int sweeps) {
+  __shared__ double sg[kQrMaxM];
+  __shared__ int32_t pos[kQrMaxM];
+  osj_finish(X, m, sigma, B, scaled, sg, pos);
+  if (threadIdx.x == 0) info[0] = sweeps;
 }
 
 // W = R^T R in place (upper R, column-major), Rinv = R^-1 (row-major, upper,
@@ -409,18 +515,45 @@ hapod_status launch_osj(double* A, int64_t m, double* sigma, double* B, int scal
     set_error("one-sided Jacobi: m above 512");
     return HAPOD_E_UNSUPPORTED;
   }
-  if (m <= kOsjLdsMaxM) {
+  if (m <= kOsjLdsMaxM / 2) {
     const size_t lds = sizeof(double) * (size_t)m * m;
     static bool attr = false;
     if (!attr) {
-      HAPOD_HIP(hipFuncSetAttribute((const void*)osj_kernel<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+      HAPOD_HIP(hipFuncSetAttribute((const void*)osj_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                                     (int)(sizeof(double) * kOsjLdsMaxM * kOsjLdsMaxM)));
       attr = true;
     }
-    hipLaunchKernelGGL(osj_kernel<true>, dim3(1), dim3(kOsjThreads), lds, stream, A, m, sigma, B, scaled, info);
-  } else {
-    hipLaunchKernelGGL(osj_kernel<false>, dim3(1), dim3(kOsjThreads), 0, stream, A, m, sigma, B, scaled, info);
+    hipLaunchKernelGGL(osj_kernel, dim3(1), dim3(kOsjThreads), lds, stream, A, m, sigma, B, scaled, info);
+    HAPOD_HIP(hipGetLastError());
+    return HAPOD_OK;
   }
+  // block one-sided Jacobi: a sweep is nbe - 1 rounds of nbe / 2 block pairs;
+  // the rotation count of a sweep is read back to decide convergence
+  const int nb = (int)((m + kOsjBlk - 1) / kOsjBlk), nbe = nb + (nb & 1);
+  const size_t lds = sizeof(double) * 2 * kOsjBlk * (size_t)m;
+  static bool attr_b = false;
+  if (!attr_b) {
+    HAPOD_HIP(hipFuncSetAttribute((const void*)osj_block_round_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)(sizeof(double) * 2 * kOsjBlk * kQrMaxM)));
+    attr_b = true;
+  }
+  int32_t* count = info + 1;
+  int sweep = 0;
+  bool done = false;
+  for (; sweep < kOsjMaxSweeps && !done; ++sweep) {
+    HAPOD_TRY(launch_zero_bytes(count, sizeof(int32_t), stream));
+    for (int r = 0; r < nbe - 1; ++r) {
+      hipLaunchKernelGGL(osj_block_round_kernel, dim3(nbe / 2), dim3(kOsjThreads), lds, stream, A, (int)m, nbe, r,
+                         count);
+      HAPOD_HIP(hipGetLastError());
+    }
+    int32_t nrot = 0;
+    HAPOD_HIP(hipMemcpyAsync(&nrot, count, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
+    HAPOD_HIP(hipStreamSynchronize(stream));
+    done = (nrot == 0);
+  }
+  hipLaunchKernelGGL(osj_finish_kernel, dim3(1), dim3(kOsjThreads), 0, stream, A, m, sigma, B, scaled, info,
+                     done ? sweep : -1);
   HAPOD_HIP(hipGetLastError());
   return HAPOD_OK;
 }

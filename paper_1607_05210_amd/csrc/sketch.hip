@@ -48,7 +48,46 @@ __global__ __launch_bounds__(256) void transpose_kernel(const double* __restrict
   }
 }
 
+// C (row-major, ld ld): rows [0, rows_c) negated, rows [rows_c, rows_c +
+// cols) set to the identity, so that [L, Y] C = Y - L C_old
+__global__ __launch_bounds__(256) void neg_ident_kernel(double* __restrict__ C, int64_t rows_c, int64_t cols,
+                                                        int64_t ld) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (rows_c + cols) * cols) return;
+  const int64_t i = e / cols, j = e - i * cols;
+  double* p = C + i * ld + j;
+  *p = (i < rows_c) ? -*p : (i - rows_c == j ? 1.0 : 0.0);
+}
+
+// R[(c0 + j) * ldr + i] += C[i * ldc + j], i < rows, j < cols (C row-major)
+__global__ __launch_bounds__(256) void acc_transposed_kernel(double* __restrict__ R, int64_t ldr, int64_t c0,
+                                                             const double* __restrict__ C, int64_t ldc, int64_t rows,
+                                                             int64_t cols) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= rows * cols) return;
+  const int64_t j = e / rows, i = e - j * rows;
+  R[(c0 + j) * ldr + i] += C[i * ldc + j];
+}
+
 }  // namespace
+
+hapod_status launch_acc_transposed(double* R, int64_t ldr, int64_t c0, const double* C, int64_t ldc, int64_t rows,
+                                   int64_t cols, hipStream_t stream) {
+  if (rows <= 0 || cols <= 0) return HAPOD_OK;
+  hipLaunchKernelGGL(acc_transposed_kernel, dim3((unsigned)((rows * cols + 255) / 256)), dim3(256), 0, stream, R, ldr,
+                     c0, C, ldc, rows, cols);
+  HAPOD_HIP(hipGetLastError());
+  return HAPOD_OK;
+}
+
+hapod_status launch_neg_ident(double* C, int64_t rows_c, int64_t cols, int64_t ld, hipStream_t stream) {
+  const int64_t total = (rows_c + cols) * cols;
+  if (total <= 0) return HAPOD_OK;
+  hipLaunchKernelGGL(neg_ident_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, stream, C, rows_c, cols,
+                     ld);
+  HAPOD_HIP(hipGetLastError());
+  return HAPOD_OK;
+}
 
 hapod_status launch_normal_fill(double* out, int64_t count, uint64_t seed, hipStream_t stream) {
   if (count <= 0) return HAPOD_OK;

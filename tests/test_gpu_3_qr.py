@@ -209,7 +209,7 @@ def test_tree_qr_route_matches_oracle_below_the_gram_floor(hp, shape):
     """A graded spectrum down to 1e-13 and eps* = 1e-9: every node's
     truncation falls where the method of snapshots cannot resolve.  With
     qr_pod every node's rank is the oracle's (literal Def. 3.2 recursion with
-    LAPACK SVDs), the root's sigma agree to 1e-13 sigma_1, and the mean
+    LAPACK SVDs), the root's sigma agree to 64 L_T sqrt(m) u sigma_1, and the mean
     squared projection error meets Thm. 3.5's eps*^2."""
     from oracle import hapod, tree
     n = 3000
@@ -243,7 +243,13 @@ def test_tree_qr_route_matches_oracle_below_the_gram_floor(hp, shape):
     want = [len(ref[a][0]) for a in range(len(parent))]
     assert list(ranks) == want
     s_ref = ref[root][0]
-    assert np.max(np.abs(s_gpu - s_ref)) <= 1e-13 * s_ref[0]
+    # each level's SVD of R (one-sided Jacobi, backward stable) and its
+    # products move sigma by about sqrt(m) u sigma_1 times a small constant
+    # (64 here), and the levels' errors add up
+    lev = tree.levels(parent)
+    m_max = max(int(plan.node_stats()["m_in"][a]) for a in range(len(parent)))
+    bound = 64.0 * lev[root] * math.sqrt(m_max) * U64 * s_ref[0]
+    assert np.max(np.abs(s_gpu - s_ref)) <= bound, (np.max(np.abs(s_gpu - s_ref)) / s_ref[0], bound / s_ref[0])
     assert metrics.orthonormality_error(U) <= 1e-13
     S_all = np.hstack([data64[k] for k in sorted(data64)])
     err_qr = metrics.mean_projection_error(S_all, U)
