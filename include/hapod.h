@@ -83,6 +83,22 @@ hapod_status hapod_gram(hapod_precision prec, int64_t n, int64_t m,
                         const void* S, int64_t lds, double* G, int64_t ldg,
                         void* stream);
 
+/* hapod_gram for callers that cannot allocate device memory (code under
+ * stream capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same G = S^T S, with the same arguments and results, computed without any
+ * allocation or host staging.  Descriptors and partial tiles live in a
+ * library-owned device array of 64.25 MiB per device (held until the process
+ * ends); its device address is looked up on the first call on each device.
+ * m <= 256 (HAPOD_E_UNSUPPORTED above); the row chunks are capped at 128, so
+ * the sums may be ordered differently from hapod_gram's (equal within the
+ * same rounding bound; bitwise equal on exactly representable data).
+ * Asynchronous: nothing is synchronised or copied to the host.  Calls on one
+ * device share the array: calls that overlap on one device (other streams,
+ * other threads) race and must not be made.                                */
+hapod_status hapod_gram_noalloc(hapod_precision prec, int64_t n, int64_t m,
+                                const void* S, int64_t lds, double* G, int64_t ldg,
+                                void* stream);
+
 /* Symmetric eigendecomposition of a Gram matrix (Rem. 2.3), in double.
  *   G       device, m x m, ld ldg; overwritten (destroyed).
  *   lambda  device, m doubles: eigenvalues, descending; equal values keep

@@ -51,6 +51,7 @@ LEAF_FN = C.CFUNCTYPE(_i32, _vp, _i32, C.POINTER(_vp), _pi64, _vp)
 
 _SIGS = {
     "hapod_gram": [_i32, _i64, _i64, _vp, _i64, _vp, _i64, _vp],
+    "hapod_gram_noalloc": [_i32, _i64, _i64, _vp, _i64, _vp, _i64, _vp],
     "hapod_eigh": [_i64, _vp, _i64, _vp, _vp, _i64, _pi32, _vp],
     "hapod_truncate": [_i64, _vp, _dbl, _pi64, _pdbl, _vp],
     "hapod_lift": [_i32, _i64, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _vp, _i64, _vp],
@@ -146,6 +147,16 @@ def hapod_gram(prec, S, G=None, stream=None):
         G = colmajor(m, m, torch.float64, S.device)
     pg, _, _, ldg = _mat(G, "G", torch.float64)
     _check(_lib.hapod_gram(prec, n, m, p, lds, pg, ldg, _stream(stream)), "hapod_gram")
+    return G
+
+
+def hapod_gram_noalloc(prec, S, G, stream=None):
+    """G = S^T S into the caller's G without any device allocation by the
+    library (m <= 256); asynchronous on the stream."""
+    prec = _prec(prec)
+    p, n, m, lds = _mat(S, "S", _elem(prec))
+    pg, _, _, ldg = _mat(G, "G", torch.float64)
+    _check(_lib.hapod_gram_noalloc(prec, n, m, p, lds, pg, ldg, _stream(stream)), "hapod_gram_noalloc")
     return G
 
 

@@ -18,7 +18,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libhapod.so")
 BUILD = os.path.join(HERE, "_build")
 
-SOURCES = ["gram.hip", "eig.hip", "trunc.hip", "lift.hip", "misc.hip", "wide.hip", "qr.hip", "sketch.hip", "api.cpp"]
+SOURCES = ["gram.hip", "eig.hip", "trunc.hip", "lift.hip", "misc.hip", "wide.hip", "qr.hip", "sketch.hip", "noalloc.hip", "api.cpp"]
 
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("HAPOD_ARCH", "gfx950")

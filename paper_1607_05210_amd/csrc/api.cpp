@@ -30,21 +30,28 @@ void pool_free_cb(void* pool, void* p);
 hapod_status gram_impl(int compute, int eb, int64_t n, int64_t m, const void* S, int64_t lds, double* G, int64_t ldg,
                        hipStream_t stream, int tile = 0, int64_t in_rbs = 0);
 
+int pick_chunks(int64_t n, int pairs, int target_items, int64_t min_rows) {
+  int64_t want = std::max<int64_t>(1, (target_items + pairs - 1) / pairs);
+  int64_t maxc = std::max<int64_t>(1, n / std::max<int64_t>(min_rows, 1));
+  return (int)std::max<int64_t>(1, std::min(want, maxc));
+}
+
+// Gram tile for a node of m columns: narrow nodes get split tiles (every
+// wavefront of a workgroup on the whole tile, over its own rows) sized to m,
+// so their MFMA work is not padded to 128 columns and no SIMD idles.
+int gram_tile_for(int64_t m) {
+  if (m <= 16) return 16;
+  if (m <= 32) return 32;
+  if (m <= 64) return 64;
+  return kGramTile;
+}
+
 namespace {
 
 int elem_bytes(hapod_precision p) { return p == HAPOD_FP64 ? 8 : 4; }
 int compute_mode(hapod_precision p) { return p == HAPOD_FP64 ? 0 : (p == HAPOD_FP32 ? 1 : 2); }
 
 constexpr size_t kAlign = 256;
-// the split-BF16 form computes the Gram of nodes wider than 64 columns with
-// split-BF16 products (128-column tiles that split FP32 values into hi / lo
-// as they are staged through LDS); narrower nodes, whose tiles are too small
-// to pay for the splitting, use FP32 MFMA
-constexpr int64_t kBf16MinCols = 65;
-// widest split-BF16 node whose 128-column tiles split while staging (two
-// column blocks); wider nodes read a pre-split twin (measured on the 2^20 x
-// 8192 root: 319 ms from the twin, 638 ms splitting in every tile)
-constexpr int64_t kStageSplitMaxCols = 256;
 constexpr int kSuperI = 4, kSuperJ = 8;  // Gram tile pairs per super-tile (32 = CUs of an XCD)
 
 // plain column-major n x m (leading dimension ld)
@@ -305,21 +312,6 @@ struct Events {
   }
 };
 
-int pick_chunks(int64_t n, int pairs, int target_items, int64_t min_rows) {
-  int64_t want = std::max<int64_t>(1, (target_items + pairs - 1) / pairs);
-  int64_t maxc = std::max<int64_t>(1, n / std::max<int64_t>(min_rows, 1));
-  return (int)std::max<int64_t>(1, std::min(want, maxc));
-}
-
-// Gram tile for a node of m columns: narrow nodes get split tiles (every
-// wavefront of a workgroup on the whole tile, over its own rows) sized to m,
-// so their MFMA work is not padded to 128 columns and no SIMD idles.
-int gram_tile_for(int64_t m) {
-  if (m <= 16) return 16;
-  if (m <= 32) return 32;
-  if (m <= 64) return 64;
-  return kGramTile;
-}
 
 // Tile autotuning.  For a node class of at most 256 columns (compute mode,
 // width rounded up to a multiple of 16, height class 2^ceil(log2 n)) seen for

@@ -124,6 +124,20 @@ struct GramFill {
   int32_t r0, c0, rn, cn;
 };
 hapod_status launch_gram_fill(const GramFill* d_fills, int count, const double* s2_base, hipStream_t stream);
+// the split-BF16 form computes the Gram of nodes wider than 64 columns with
+// split-BF16 products (128-column tiles that split FP32 values into hi / lo
+// as they are staged through LDS); narrower nodes, whose tiles are too small
+// to pay for the splitting, use FP32 MFMA
+constexpr int64_t kBf16MinCols = 65;
+// widest split-BF16 node whose 128-column tiles split while staging (two
+// column blocks); wider nodes read a pre-split twin (measured on the 2^20 x
+// 8192 root: 319 ms from the twin, 638 ms splitting in every tile)
+constexpr int64_t kStageSplitMaxCols = 256;
+// Gram tile for a node of m columns (16, 32, 64 or 128)
+int gram_tile_for(int64_t m);
+// row chunks of an n-row node: enough for about target_items work items over
+// `pairs` tile pairs, each chunk at least min_rows rows
+int pick_chunks(int64_t n, int pairs, int target_items, int64_t min_rows);
 hapod_status launch_gram(int compute, const GramNode* d_nodes, const GramItem* d_items,
                          const GramLaunch* launches, int num_launches,
                          const int32_t* d_reduce_pairs, const int32_t* d_reduce_node, int num_reduce,
