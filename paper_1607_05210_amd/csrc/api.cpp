@@ -1158,6 +1158,20 @@ struct Cols {
   }
 };
 
+// The conditions of the lift's guard-free dense mode for an n-row column
+// table of m columns and N outputs (launch_lift_residual): every column holds
+// all n rows and may be read to the next multiple of 128 rows (row-block-tiled
+// with a stride of at least 128 rows per column, or n a multiple of 128),
+// starts 16-byte aligned; m a multiple of 32, N of 128, ldb of 2.
+bool dense_ok(int64_t n, const Cols& A, int64_t N, int64_t ldb) {
+  if (A.size() % 32 != 0 || N % kLiftTileN != 0 || ldb % 2 != 0) return false;
+  for (int64_t j = 0; j < A.size(); ++j) {
+    if (A.rows[(size_t)j] != n || ((uintptr_t)A.p[(size_t)j] & 15u) != 0) return false;
+    if (A.rbs[(size_t)j] == kRowBlock && n % kRowBlock != 0) return false;
+  }
+  return true;
+}
+
 // out = A B[:, :N] in FP64: A an n-row column table of m columns, B
 // row-major m x N (ld ldb); out element (r, c) at out[c * ocs + blk_off(r,
 // obs)].  Descriptors come from the pool and go back to it after a stream
@@ -1199,7 +1213,9 @@ hapod_status lift_cols(Pool& pool, int64_t n, const Cols& A, const double* B, in
       st = HAPOD_E_DEVICE;
     }
     if (st == HAPOD_OK) st = launch_set_scalar_i64((int64_t*)dk, N, stream);
-    if (st == HAPOD_OK) st = launch_lift(0, (const LiftNode*)dn, 1, items, stream);
+    if (st == HAPOD_OK)
+      st = dense_ok(n, A, N, ldb) && ((uintptr_t)B & 15u) == 0 ? launch_lift_dense((const LiftNode*)dn, items, stream)
+                                                                 : launch_lift(0, (const LiftNode*)dn, 1, items, stream);
     if (hipStreamSynchronize(stream) != hipSuccess && st == HAPOD_OK) {
       set_error("lift: stream synchronisation failed");
       st = HAPOD_E_DEVICE;
@@ -1543,7 +1559,9 @@ hapod_status residual_cols(Pool& pool, int64_t n, const Cols& Q, const double* B
     return finish(HAPOD_E_DEVICE);
   }
   hapod_status st = launch_set_scalar_i64((int64_t*)dk, m, stream);
-  if (st == HAPOD_OK) st = launch_lift_residual((const LiftNode*)dn, (int)(rgroups * col_tiles), stream);
+  if (st == HAPOD_OK)
+    st = launch_lift_residual((const LiftNode*)dn, (int)(rgroups * col_tiles), stream,
+                              dense_ok(n, Q, m, ldb) && ((uintptr_t)B & 15u) == 0);
   if (st == HAPOD_OK) st = launch_sum_partials((const double*)rpart, rgroups * 2, m, res, stream);
   return finish(st);
 }

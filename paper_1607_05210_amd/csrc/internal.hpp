@@ -236,7 +236,12 @@ constexpr int kLiftNarrowM = 256;
 hapod_status launch_lift(int compute, const LiftNode* d_nodes, int num_nodes,
                          int num_items, hipStream_t stream, bool narrow = false);
 // Residual mode of the FP64 lift (see LiftNode::rcols), one node.
-hapod_status launch_lift_residual(const LiftNode* d_node, int num_items, hipStream_t stream);
+// dense: every column of the node holds all n rows, may be read to the next
+// multiple of 128 rows, starts 16-byte aligned, m is a multiple of 32 and N of
+// 128 (the operand loads then carry no guards).
+hapod_status launch_lift_residual(const LiftNode* d_node, int num_items, hipStream_t stream, bool dense = false);
+// The FP64 lift of one node under the dense conditions above.
+hapod_status launch_lift_dense(const LiftNode* d_node, int num_items, hipStream_t stream);
 // res[c] = sum over g < groups of rpart[g * N + c], in order of g
 hapod_status launch_sum_partials(const double* rpart, int64_t groups, int64_t N, double* res, hipStream_t stream);
 

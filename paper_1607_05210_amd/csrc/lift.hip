@@ -55,9 +55,15 @@ __device__ __forceinline__ void run4(const float* p, int64_t avail, float (&out)
 // along the rows, so that no wavefront idles on columns past N.
 // RES: the residual mode (LiftNode::rcols): the product is compared with the
 // node's second matrix instead of being stored.
-template <int C, bool NARROW, bool RES = false>
+// DENSE: every column holds all n rows and may be read to the next multiple
+// of 128 rows (row-block-tiled, or n a multiple of 128), every column starts
+// 16-byte aligned, and m, N and the row-block strides are whole tiles (m a
+// multiple of 32, N of 128): operand runs are loaded without guards or
+// branches (rows past n only reach outputs that are never stored or summed).
+template <int C, bool NARROW, bool RES = false, bool DENSE = false>
 __global__ __launch_bounds__(256) void lift_kernel(const LiftNode* __restrict__ nodes, int num_nodes) {
   static_assert(!RES || (C == 0 && !NARROW), "residual mode: FP64 128 x 128 tiles");
+  static_assert(!DENSE || (C == 0 && !NARROW), "dense mode: FP64 128 x 128 tiles");
   constexpr int TMk = NARROW ? 4 * WT : TM;
   constexpr int TNk = NARROW ? WT : TN;
   using Tr = LiftTraits<C>;
@@ -140,6 +146,13 @@ __global__ __launch_bounds__(256) void lift_kernel(const LiftNode* __restrict__ 
     const int kend = min(m, kc + KT);
     // a lane's run of column k (table slot t): up to 4 rows from row rl
     auto srun = [&](int t, Elem (&x)[4]) {
+      if constexpr (DENSE) {
+        const Elem* p = reinterpret_cast<const Elem*>(tcol[t]) + rblk * trbs[t] + roff;
+        const dv2 u = *(gptr<dv2>)as_global(p);
+        const dv2 v = *(gptr<dv2>)as_global(p + 2);
+        x[0] = u[0]; x[1] = u[1]; x[2] = v[0]; x[3] = v[1];
+        return;
+      }
       const int64_t avail = trows[t] - rl;
       if (avail <= 0) {
 #pragma unroll
@@ -149,6 +162,13 @@ __global__ __launch_bounds__(256) void lift_kernel(const LiftNode* __restrict__ 
       }
     };
     auto brun = [&](int k, BElem (&y)[4]) {
+      if constexpr (DENSE) {
+        const BElem* p = bop + (int64_t)k * nd.ldb + nl;
+        const dv2 u = *(gptr<dv2>)as_global(p);
+        const dv2 v = *(gptr<dv2>)as_global(p + 2);
+        y[0] = u[0]; y[1] = u[1]; y[2] = v[0]; y[3] = v[1];
+        return;
+      }
       if (k < kend && bavail > 0) run4(bop + (int64_t)k * nd.ldb + nl, bavail, y);
       else {
 #pragma unroll
@@ -163,7 +183,7 @@ __global__ __launch_bounds__(256) void lift_kernel(const LiftNode* __restrict__ 
 #pragma unroll
       for (int t = 0; t < U; ++t) {
         const int k = kb + 4 * t + g;
-        if (k < kend) srun(k - kc, va[t]);
+        if (DENSE || k < kend) srun(k - kc, va[t]);
         else {
 #pragma unroll
           for (int a = 0; a < 4; ++a) va[t][a] = Elem(0);
@@ -537,9 +557,19 @@ hapod_status launch_lift(int compute, const LiftNode* d_nodes, int num_nodes, in
   return HAPOD_OK;
 }
 
-hapod_status launch_lift_residual(const LiftNode* d_node, int num_items, hipStream_t stream) {
+hapod_status launch_lift_dense(const LiftNode* d_node, int num_items, hipStream_t stream) {
   if (num_items <= 0) return HAPOD_OK;
-  hipLaunchKernelGGL((lift_kernel<0, false, true>), dim3(num_items), dim3(256), 0, stream, d_node, 1);
+  hipLaunchKernelGGL((lift_kernel<0, false, false, true>), dim3(num_items), dim3(256), 0, stream, d_node, 1);
+  HAPOD_HIP(hipGetLastError());
+  return HAPOD_OK;
+}
+
+hapod_status launch_lift_residual(const LiftNode* d_node, int num_items, hipStream_t stream, bool dense) {
+  if (num_items <= 0) return HAPOD_OK;
+  if (dense)
+    hipLaunchKernelGGL((lift_kernel<0, false, true, true>), dim3(num_items), dim3(256), 0, stream, d_node, 1);
+  else
+    hipLaunchKernelGGL((lift_kernel<0, false, true>), dim3(num_items), dim3(256), 0, stream, d_node, 1);
   HAPOD_HIP(hipGetLastError());
   return HAPOD_OK;
 }
