@@ -300,6 +300,38 @@ hapod_status hapod_plan(const hapod_tree* tree, double eps_star, double omega,
 hapod_status hapod_plan_query(hapod_plan_t plan, double* eps, int32_t* level,
                               int64_t* acc);
 
+/* Device memory of a plan's runs, in bytes (host outputs, either may be NULL):
+ *   worst_case_bytes     an upper bound on what a run holds at once if every
+ *                        node kept all its inputs (rank = input count, at most
+ *                        its rows): per level the outputs still alive plus the
+ *                        level's outputs and batch scratch.  The ranks of
+ *                        Def. 3.2 are data-dependent, so a run usually needs
+ *                        far less (a chain's worst case grows with its length).
+ *   last_run_peak_bytes  the most the plan's pool held during the last run
+ *                        (0 before the first).
+ * hapod_plan itself returns HAPOD_E_NOMEM when mem_cap_bytes is below the
+ * scratch the leaf level needs whatever the ranks; beyond that the cap is
+ * enforced by every allocation of a run (HAPOD_E_NOMEM, the plan stays
+ * usable).                                                                  */
+hapod_status hapod_plan_workspace(hapod_plan_t plan, int64_t* worst_case_bytes,
+                                  int64_t* last_run_peak_bytes);
+
+/* One local POD of node `node` (-1 = root) exactly as a run of the plan
+ * computes it (Def. 2.5 with the node's Thm. 3.5 tolerance eps(node), the
+ * plan's precision and route: pass-through for eps = 0, the sketched route
+ * for nodes of at least 2 sketch_cols inputs, the QR route under qr_pod, else
+ * the method of snapshots with the plan's eigensolver choice and tile
+ * tuning), on input columns the caller supplies.
+ *   S    device, rows(node) x m, ld lds, storage type of the plan (rows(node):
+ *        n, or the node's leaf_rows / the most of its children's).
+ *   out  device, rows(node) x m capacity, ld ldo: the first *rank columns get
+ *        the modes, scaled (sigma_k phi_k) below the root, orthonormal at it.
+ *   sigma  host, m capacity.
+ * Scratch from the plan's pool.  Synchronises the stream.                  */
+hapod_status hapod_plan_node_pod(hapod_plan_t plan, int32_t node, const void* S, int64_t lds,
+                                 int64_t m, void* out, int64_t ldo, double* sigma,
+                                 int64_t* rank, void* stream);
+
 /* Leaf provider: returns in *ptr a device pointer to the leaf's
  * leaf_rows[leaf] x leaf_cols[leaf] snapshot matrix (column-major, storage
  * type of the plan's precision) and its leading dimension in *ld.  Called
@@ -358,6 +390,18 @@ hapod_status hapod_modes(hapod_plan_t plan, int32_t node, void* U, int64_t ldu,
  * Needs a completed run of a plan made with right_vectors = 1
  * (HAPOD_E_INVALID otherwise).  Synchronises the stream.                   */
 hapod_status hapod_right_vectors(hapod_plan_t plan, double* W, int64_t ldw, void* stream);
+
+/* The route each node took in the last run.                                */
+typedef enum {
+  HAPOD_ROUTE_PASSTHROUGH = 0, /* eps = 0: the input vectors, sigma = 1 (Def. 2.5); for the
+                                  root (omega = 0) its "modes" are not orthonormal            */
+  HAPOD_ROUTE_SNAPSHOTS = 1,   /* the method of snapshots (Gram, eigensolve, truncation, lift) */
+  HAPOD_ROUTE_QR = 2,          /* the QR route of hapod_node_pod_qr (plan option qr_pod)      */
+  HAPOD_ROUTE_SKETCH = 3       /* the sketched route of hapod_node_pod_sketch (sketch_cols)   */
+} hapod_route;
+/* route: host, one int32 (a hapod_route) for node (-1 = root).
+ * HAPOD_E_STATE before the first completed run.                             */
+hapod_status hapod_node_route(hapod_plan_t plan, int32_t node, int32_t* route);
 
 /* Diagnostics of a node that took the sketched route in the last run
  * (node = -1: the root).  out11: host, 11 doubles {ell, residual energy r,

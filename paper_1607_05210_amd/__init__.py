@@ -23,6 +23,7 @@ LIB_PATH = os.path.join(_HERE, "libhapod.so")
 
 FP64, FP32, BF16X3 = 0, 1, 2
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3}
+ROUTES = {0: "passthrough", 1: "snapshots", 2: "qr", 3: "sketch"}
 STATUS = {0: "OK", 1: "E_INVALID", 2: "E_TREE", 3: "E_NOMEM", 4: "E_DEVICE", 5: "E_NUMERIC",
           6: "E_STATE", 7: "E_CALLBACK", 8: "E_UNSUPPORTED"}
 HAPOD_EIG_MAX = 8192
@@ -67,6 +68,9 @@ _SIGS = {
     "hapod_node_pod_sketch": [_i64, _i64, _vp, _i64, _dbl, _i32, _i64, C.c_uint64, _vp, _i64, _pdbl, _pi64, _pdbl,
                               _vp],
     "hapod_sketch_stats": [_vp, _i32, _pdbl],
+    "hapod_plan_workspace": [_vp, _pi64, _pi64],
+    "hapod_node_route": [_vp, _i32, _pi32],
+    "hapod_plan_node_pod": [_vp, _i32, _vp, _i64, _i64, _vp, _i64, _pdbl, _pi64, _vp],
     "hapod_run_timing": [_vp, _pdbl],
     "hapod_level_timing": [_vp, _i32, _pdbl],
 }
@@ -387,6 +391,32 @@ class Plan:
         _check(_lib.hapod_node_stats(self._h, m_in.ctypes.data_as(_pi64), nneg.ctypes.data_as(_pi64),
                                      l1.ctypes.data_as(_pdbl), lmin.ctypes.data_as(_pdbl)), "hapod_node_stats")
         return dict(m_in=m_in, n_negative=nneg, lambda1=l1, lambda_min=lmin)
+
+    def workspace(self):
+        """(worst-case bytes of a run, peak bytes the pool held in the last run)."""
+        w, p = C.c_int64(0), C.c_int64(0)
+        _check(_lib.hapod_plan_workspace(self._h, C.byref(w), C.byref(p)), "hapod_plan_workspace")
+        return w.value, p.value
+
+    def route(self, node=-1):
+        """The route node took in the last run: passthrough, snapshots, qr or sketch."""
+        r = C.c_int32(0)
+        _check(_lib.hapod_node_route(self._h, int(node), C.byref(r)), "hapod_node_route")
+        return ROUTES[r.value]
+
+    def node_pod(self, node, S, out=None, stream=None):
+        """One local POD of `node` as a run computes it, on the caller's input
+        columns S (rows(node) x m): returns (sigma numpy, out[:, :rank])."""
+        import numpy as np
+        p, n, m, lds = _mat(S, "S", _elem(self.prec))
+        if out is None:
+            out = colmajor(n, m, _elem(self.prec), S.device)
+        po, _, _, ldo = _mat(out, "out", _elem(self.prec))
+        sig = np.zeros(max(m, 1))
+        r = C.c_int64(0)
+        _check(_lib.hapod_plan_node_pod(self._h, int(node), p, lds, m, po, ldo, sig.ctypes.data_as(_pdbl),
+                                        C.byref(r), _stream(stream)), "hapod_plan_node_pod")
+        return sig[:r.value].copy(), out[:, :r.value]
 
     def sketch_stats(self, node=-1):
         """Diagnostics of a node that took the sketched route (dict), or None."""

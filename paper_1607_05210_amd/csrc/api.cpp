@@ -132,6 +132,7 @@ class Pool {
     }
     size_of_[p] = bytes;
     held_ += bytes;
+    peak_ = std::max(peak_, held_);
     *out = p;
     return HAPOD_OK;
   }
@@ -209,6 +210,9 @@ class Pool {
   }
   void set_cap(size_t c) { cap_ = c; }
   size_t held() const { return held_; }
+  // the most device memory held since the last reset_peak()
+  size_t peak() const { return peak_; }
+  void reset_peak() { peak_ = held_; }
   // bytes held in freed blocks, ready for reuse
   size_t cached() const {
     size_t c = 0;
@@ -232,7 +236,7 @@ class Pool {
  private:
   std::map<size_t, std::vector<void*>> free_;
   std::map<void*, size_t> size_of_;
-  size_t held_ = 0, cap_ = 0;
+  size_t held_ = 0, cap_ = 0, peak_ = 0;
   void* pinned_ = nullptr;
   size_t pinned_bytes_ = 0;
   bool verbose_ = [] {
@@ -1121,6 +1125,9 @@ struct hapod_plan_s {
   std::vector<std::vector<double>> sigma;
   void* root_U = nullptr;  // owned by the pool
   bool root_passthrough = false;
+  // per node the route of the last run (HAPOD_ROUTE_*) and the pool's peak
+  std::vector<int32_t> route;
+  size_t run_peak = 0;
   std::vector<const void*> root_cols;  // pass-through root: its input columns
   std::vector<int64_t> root_rbs, root_rows;
   std::vector<int64_t> rows;           // rows each node's vectors hold
@@ -1822,6 +1829,47 @@ hapod_status sketch_pod_core(Pool& pool, int64_t n, int64_t m, const std::vector
 }
 
 
+// Device memory a run may need at most, every node keeping all its inputs
+// (rank = input count, capped by its rows): per level, the outputs still
+// alive (children of later levels) plus the level's own outputs and its
+// batch scratch (per node Gram, eigenvectors and lift operand, m^2 doubles
+// each, or the sketch's buffers on the sketched route; plus one set of
+// partial tiles of the Gram work items, 8192 x 128^2 doubles).  *min_need:
+// what the leaf level's scratch alone takes, which any run needs whatever
+// the ranks.
+size_t plan_worst_case(const hapod_plan_s& P, size_t* min_need) {
+  const int eb = elem_bytes(P.opts.prec);
+  const int32_t nn = P.num_nodes;
+  std::vector<int64_t> width(nn, 0), in(nn, 0);
+  const size_t partial = sizeof(double) * 8192 * kGramTile * kGramTile;
+  auto scratch = [&](int32_t a) -> size_t {
+    const size_t m = (size_t)in[a];
+    const int64_t ell = P.opts.sketch_cols;
+    if (ell > 0 && (int64_t)m >= 2 * ell && P.rows[a] >= ell)
+      return 3 * tiled_bytes(P.rows[a], ell, 8) + 3 * sizeof(double) * m * ell;
+    return 3 * sizeof(double) * m * m + (eb == 4 ? sizeof(float) * m * m : 0);
+  };
+  size_t worst = 0, leaf_scratch = 0;
+  for (int32_t l = 0; l < (int32_t)P.by_level.size(); ++l) {
+    size_t batch = 0, live = 0;
+    for (int32_t a : P.by_level[l]) {
+      in[a] = P.children[a].empty() ? P.leaf_cols[a] : 0;
+      for (int32_t b : P.children[a]) in[a] += width[b];
+      width[a] = (P.eps[a] == 0.0) ? in[a] : std::min<int64_t>(in[a], P.rows[a]);
+      if (P.eps[a] == 0.0) continue;
+      batch += scratch(a) + tiled_bytes(P.rows[a], width[a], eb);
+      if (l == 0) leaf_scratch += scratch(a);
+    }
+    // outputs of computed nodes below this level whose parent is at or above it
+    for (int32_t b = 0; b < nn; ++b)
+      if (P.level[b] <= l && P.parent[b] >= 0 && P.level[P.parent[b]] > l && P.eps[b] > 0.0)
+        live += tiled_bytes(P.rows[b], width[b], eb);
+    worst = std::max(worst, live + batch + (batch ? partial : 0));
+  }
+  if (min_need) *min_need = leaf_scratch;
+  return worst;
+}
+
 extern "C" {
 
 const char* hapod_last_error(void) { return g_last_error.c_str(); }
@@ -1956,8 +2004,47 @@ hapod_status hapod_plan(const hapod_tree* tree, double eps_star, double omega, c
     for (int32_t a = 0; a < nn; ++a)
       if (P->opts.node_eps_override[a] >= 0.0) P->eps[a] = P->opts.node_eps_override[a];
   P->opts.node_eps_override = nullptr;  // not kept beyond the call
-  if (P->opts.mem_cap_bytes > 0) P->pool.set_cap((size_t)P->opts.mem_cap_bytes);
+  if (P->opts.mem_cap_bytes > 0) {
+    // the leaf level's scratch is needed whatever the ranks: a cap below it
+    // can never be met
+    size_t need = 0;
+    (void)plan_worst_case(*P, &need);
+    if (need > (size_t)P->opts.mem_cap_bytes) {
+      set_error("hapod_plan: the leaf level alone needs " + std::to_string(need) + " bytes of device scratch, above " +
+                "mem_cap_bytes = " + std::to_string(P->opts.mem_cap_bytes));
+      return HAPOD_E_NOMEM;
+    }
+    P->pool.set_cap((size_t)P->opts.mem_cap_bytes);
+  }
   *out = P.release();
+  return HAPOD_OK;
+}
+
+hapod_status hapod_plan_workspace(hapod_plan_t P, int64_t* worst_case_bytes, int64_t* last_run_peak_bytes) {
+  if (!P) {
+    set_error("hapod_plan_workspace: NULL plan");
+    return HAPOD_E_INVALID;
+  }
+  if (worst_case_bytes) *worst_case_bytes = (int64_t)plan_worst_case(*P, nullptr);
+  if (last_run_peak_bytes) *last_run_peak_bytes = P->has_result ? (int64_t)P->run_peak : 0;
+  return HAPOD_OK;
+}
+
+hapod_status hapod_node_route(hapod_plan_t P, int32_t node, int32_t* route) {
+  if (!P || !route) {
+    set_error("hapod_node_route: NULL argument");
+    return HAPOD_E_INVALID;
+  }
+  if (!P->has_result) {
+    set_error("hapod_node_route: no completed run");
+    return HAPOD_E_STATE;
+  }
+  const int32_t a = node < 0 ? P->root : node;
+  if (a >= P->num_nodes) {
+    set_error("hapod_node_route: node out of range");
+    return HAPOD_E_INVALID;
+  }
+  *route = P->route[a];
   return HAPOD_OK;
 }
 
@@ -2130,6 +2217,8 @@ hapod_status hapod_run(hapod_plan_t P, hapod_leaf_fn get_leaf, void* user, void*
   P->lam_min.assign(nn, 0.0);
   P->sigma.assign(nn, {});
   P->sketch.assign(nn, SketchInfo{});
+  P->route.assign(nn, HAPOD_ROUTE_PASSTHROUGH);
+  P->pool.reset_peak();
   for (double& t : P->timing) t = 0.0;
 
   // Per node: the columns it hands to its parent (pointer, row-block stride,
@@ -2443,6 +2532,7 @@ hapod_status hapod_run(hapod_plan_t P, hapod_leaf_fn get_leaf, void* user, void*
             rest_node.push_back(a);
             continue;
           }
+          P->route[a] = HAPOD_ROUTE_SKETCH;
           hapod_status ks = sketch_node(a, j, lt);
           if (ks != HAPOD_OK) {
             (void)hipStreamSynchronize(stream);
@@ -2466,6 +2556,7 @@ hapod_status hapod_run(hapod_plan_t P, hapod_leaf_fn get_leaf, void* user, void*
             rest_node.push_back(a);
             continue;
           }
+          P->route[a] = HAPOD_ROUTE_QR;
           hapod_status qs = qr_node(a, j, lt);
           if (qs != HAPOD_OK) {
             (void)hipStreamSynchronize(stream);
@@ -2491,6 +2582,7 @@ hapod_status hapod_run(hapod_plan_t P, hapod_leaf_fn get_leaf, void* user, void*
       for (size_t k = 0; k < jobs.size(); ++k) {
         const int32_t a = job_node[k];
         const PodJob& j = jobs[k];
+        P->route[a] = HAPOD_ROUTE_SNAPSHOTS;
         P->rank[a] = j.rank;
         P->sigma[a] = j.sigma;
         P->vkeep[a] = j.vkeep;
@@ -2573,6 +2665,7 @@ hapod_status hapod_run(hapod_plan_t P, hapod_leaf_fn get_leaf, void* user, void*
   P->root_U = out_buf[P->root];
   out_buf[P->root] = nullptr;
   release_all();
+  P->run_peak = P->pool.peak();
   // the blocks freed by this run stay cached for the next one (mem_cap_bytes
   // bounds them; a failed device allocation returns them first)
   P->has_result = true;
@@ -3124,6 +3217,78 @@ hapod_status hapod_node_pod(hapod_precision prec, int64_t n, int64_t m, const vo
   *rank = jobs[0].rank;
   if (sigma && jobs[0].rank > 0) std::memcpy(sigma, jobs[0].sigma.data(), sizeof(double) * jobs[0].rank);
   return HAPOD_OK;
+}
+
+hapod_status hapod_plan_node_pod(hapod_plan_t P, int32_t node, const void* S, int64_t lds, int64_t m, void* out,
+                                 int64_t ldo, double* sigma, int64_t* rank, void* stream_) {
+  if (!P || !rank) {
+    set_error("hapod_plan_node_pod: NULL argument");
+    return HAPOD_E_INVALID;
+  }
+  const int32_t a = node < 0 ? P->root : node;
+  if (a >= P->num_nodes) {
+    set_error("hapod_plan_node_pod: node out of range");
+    return HAPOD_E_INVALID;
+  }
+  const hapod_precision prec = P->opts.prec;
+  const int eb = elem_bytes(prec);
+  const int64_t n = P->rows[a];
+  const double eps = P->eps[a];
+  const bool root = (a == P->root);
+  if (m < 0 || lds < std::max<int64_t>(n, 1) || ldo < std::max<int64_t>(n, 1) || (m > 0 && (!S || !out))) {
+    set_error("hapod_plan_node_pod: bad sizes or NULL pointer");
+    return HAPOD_E_INVALID;
+  }
+  hipStream_t stream = (hipStream_t)stream_;
+  *rank = 0;
+  if (eps == 0.0) {  // POD(S, 0) = {(1, s)}
+    if (m > 0) HAPOD_HIP(hipMemcpy2DAsync(out, ldo * eb, S, lds * eb, n * eb, m, hipMemcpyDeviceToDevice, stream));
+    HAPOD_HIP(hipStreamSynchronize(stream));
+    *rank = m;
+    if (sigma)
+      for (int64_t i = 0; i < m; ++i) sigma[i] = 1.0;
+    return HAPOD_OK;
+  }
+  if (m == 0) return HAPOD_OK;
+  auto to_caller = [&](int64_t, double** o, int64_t* ocs, int64_t* obs) {
+    *o = (double*)out;
+    *ocs = ldo;
+    *obs = kRowBlock;
+    return HAPOD_OK;
+  };
+  std::vector<double> sg;
+  hapod_status st = HAPOD_OK;
+  const int64_t ell = P->opts.sketch_cols;
+  if (ell > 0 && m >= 2 * ell && n >= ell) {
+    // the route, sketch width and seed a run gives this node
+    const uint64_t seed = 0x6a09e667f3bcc909ull ^ ((uint64_t)a * 0x9e3779b97f4a7c15ull);
+    std::vector<const void*> cols = column_table(S, lds, m, 8);
+    std::vector<int64_t> rbs((size_t)m, kRowBlock), rows((size_t)m, n);
+    st = sketch_pod_core(P->pool, n, m, cols, rbs, rows, ell, seed, eps, !root, to_caller, sg, rank, nullptr, stream);
+  } else if (P->opts.qr_pod && m <= kQrMaxM && m <= n) {
+    st = qr_pod_core(P->pool, n, m, (double*)const_cast<void*>(S), lds, false, false, eps, !root, to_caller, sg, rank,
+                     nullptr, nullptr, stream);
+  } else {
+    std::vector<PodJob> jobs(1);
+    jobs[0].cols = column_table(S, lds, m, eb);
+    jobs[0].rbs.assign((size_t)m, kRowBlock);
+    jobs[0].crows.assign((size_t)m, n);
+    jobs[0].n = n;
+    jobs[0].m = m;
+    jobs[0].eps = eps;
+    jobs[0].root = root;
+    jobs[0].out = out;
+    jobs[0].ocs = ldo;
+    jobs[0].obs = kRowBlock;
+    const int jmax = P->opts.jacobi_max > 0 ? std::min<int>(P->opts.jacobi_max, kJacobiMax) : 0;
+    st = run_pod_batch(prec, jobs, 0, 1, jmax, P->pool, stream, nullptr, nullptr, P->opts.autotune != 0);
+    if (st == HAPOD_OK) {
+      *rank = jobs[0].rank;
+      sg = jobs[0].sigma;
+    }
+  }
+  if (st == HAPOD_OK && sigma && *rank > 0) std::memcpy(sigma, sg.data(), sizeof(double) * *rank);
+  return st;
 }
 
 hapod_status hapod_node_pod_qr(int64_t n, int64_t m, const double* S, int64_t lds, double eps, int32_t scaled,

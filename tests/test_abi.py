@@ -136,3 +136,42 @@ def test_right_vectors_before_a_run_is_an_error():
     plan = hp.Plan(synth.star_tree(2), [4, 4, 0], 64, 1e-3, 0.5, prec="fp64", right_vectors=True)
     with pytest.raises(hp.HapodError):
         plan.right_vectors()
+
+
+@pytest.mark.parametrize("kw", [{"prec": "fp32", "sketch_cols": 256}, {"sketch_cols": 100},
+                                {"sketch_cols": 1024}, {"sketch_cols": 256, "right_vectors": True}])
+def test_plan_rejects_bad_sketch_options(kw):
+    """The sketched route is FP64 only, keeps no right singular vectors, and
+    its width is whole 128-column tiles up to 512."""
+    hp = pytest.importorskip("paper_1607_05210_amd")
+    with pytest.raises(hp.HapodError) as e:
+        hp.Plan(synth.star_tree(2), [64, 64, 0], 1000, 1e-3, 0.5, **kw)
+    assert e.value.status == 1
+
+
+def test_plan_time_memory_cap():
+    """A cap below the leaf level's scratch (needed whatever the ranks) fails
+    at plan time with HAPOD_E_NOMEM; a cap above it is accepted and the
+    worst case a run may need is reported."""
+    hp = pytest.importorskip("paper_1607_05210_amd")
+    parent, cols = synth.star_tree(64), [128] * 64 + [0]
+    with pytest.raises(hp.HapodError) as e:
+        hp.Plan(parent, cols, 1 << 20, 1e-5, 0.75, mem_cap_bytes=1 << 20)
+    assert e.value.status == 3
+    plan = hp.Plan(parent, cols, 1 << 20, 1e-5, 0.75, mem_cap_bytes=16 << 30)
+    worst, peak = plan.workspace()
+    # at least the 64 leaves' outputs (2^20 x 128 doubles each) plus the root's
+    # 8192-wide output, and nothing measured before a run
+    assert worst >= 65 * (1 << 20) * 128 * 8
+    assert peak == 0
+    # the FP32 form stores half the bytes
+    w32, _ = hp.Plan(parent, cols, 1 << 20, 1e-5, 0.75, prec="fp32").workspace()
+    assert w32 < worst
+
+
+def test_route_before_a_run_is_a_state_error():
+    hp = pytest.importorskip("paper_1607_05210_amd")
+    plan = hp.Plan(synth.star_tree(2), [4, 4, 0], 64, 1e-3, 0.5)
+    with pytest.raises(hp.HapodError) as e:
+        plan.route(-1)
+    assert e.value.status == 6

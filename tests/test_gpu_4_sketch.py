@@ -271,3 +271,40 @@ def test_sketch_option_rules(hp):
         with pytest.raises(hp.HapodError) as ei:
             hp.Plan(parent, [64, 64, 0], 1000, 1e-3, 0.5, **kw)
         assert ei.value.status == 1
+
+
+def test_plan_routes_workspace_and_node_pod(hp):
+    """The route each node took, the pool's peak against the worst-case
+    estimate, and hapod_plan_node_pod reproducing a node of the run: a leaf
+    (method of snapshots) and the root (sketched) on the same inputs the run
+    gave them; an omega = 0 root reports the pass-through route."""
+    n, L, c = 4096, 16, 64
+    S, data = sinus_star(n, L, c, 200, 10.0, 1e-10, seed=21)
+    parent = synth.star_tree(L)
+    cols = [c] * L + [0]
+    plan = hp.Plan(parent, cols, n, 1e-6, 0.75, prec="fp64", sketch_cols=256)
+    dev = {i: dev_colmajor(v) for i, v in data.items()}
+    plan.run(dev)
+    assert plan.route(-1) == "sketch" and plan.route(0) == "snapshots"
+    worst, peak = plan.workspace()
+    assert 0 < peak <= worst, (peak, worst)
+    ranks = plan.ranks()
+    sig_root, U = plan.modes()
+    # a leaf through the plan's node POD: its rank and singular values
+    s0, W0 = plan.node_pod(0, dev[0])
+    s0_run, _ = plan.modes(0, with_U=False)
+    assert len(s0) == ranks[0]
+    assert np.max(np.abs(s0 - s0_run)) <= 1e-12 * s0_run[0]
+    # the root's POD on the leaves' scaled modes (each leaf lossless here, so
+    # the node POD of every leaf gives the run's root input up to rounding)
+    ins = [plan.node_pod(i, dev[i])[1] for i in range(L)]
+    root_in = torch.cat(ins, dim=1).contiguous().t().contiguous().t()
+    sr, Ur = plan.node_pod(-1, root_in)
+    assert abs(len(sr) - len(sig_root)) <= 1
+    k = min(len(sr), len(sig_root))
+    st = plan.sketch_stats(-1)
+    assert np.max(np.abs(sr[:k] - sig_root[:k])) <= 1e-12 * sig_root[0] + math.sqrt(st["residual"])
+    # omega = 0: the root passes its inputs through
+    p0 = hp.Plan(parent, cols, n, 1e-6, 0.0, prec="fp64")
+    p0.run(dev)
+    assert p0.route(-1) == "passthrough" and p0.route(3) == "snapshots"
