@@ -245,9 +245,9 @@ typedef struct {
   int32_t jacobi_max;              /* k > 0: nodes with at most k input columns (k <= 1024)
                                       take the Jacobi eigensolver, wider ones Lanczos.
                                       0: automatic -- Jacobi up to 64 columns; 65..256
-                                      a full-length Lanczos run (every eigenpair, as
-                                      Jacobi gives); above 256 Lanczos stopped at the
-                                      Gram's rounding level                          */
+                                      every eigenpair (as Jacobi gives) from a
+                                      Householder reduction to tridiagonal form; above
+                                      256 Lanczos stopped at the Gram's rounding level */
   int32_t autotune;                /* 1: the first time a node class (precision, width,
                                       height class) is met, time the candidate Gram tiles
                                       on a buffer of its shape and keep the fastest for
@@ -284,6 +284,13 @@ typedef struct {
                                       otherwise).  0: off.  Timings: sketch, Q, B and
                                       residual count as Gram, the small SVD as
                                       eigensolve, the modes' product as lift.          */
+  const char* autotune_cache;      /* path or NULL: with autotune, the tile choices of node
+                                      classes are read from this text file when the plan is
+                                      made (one line per class: compute mode, width class,
+                                      log2 height class, tile) and the process's whole table
+                                      written back after every run; the file is replaced
+                                      through a temporary one.  Read during
+                                      hapod_plan only (the path string is copied).     */
 } hapod_options;
 
 /* Validate the tree (Def. 3.1), compute levels (height: leaves are level 1),

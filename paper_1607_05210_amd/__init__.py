@@ -45,7 +45,7 @@ class HapodOptions(C.Structure):
     _fields_ = [("prec", _i32), ("reorth", _i32), ("mem_cap_bytes", _i64),
                 ("node_eps_override", _pdbl), ("jacobi_max", _i32), ("autotune", _i32),
                 ("leaf_wave", _i32), ("block_gram", _i32), ("right_vectors", _i32),
-                ("qr_pod", _i32), ("sketch_cols", _i32)]
+                ("qr_pod", _i32), ("sketch_cols", _i32), ("autotune_cache", C.c_char_p)]
 
 
 LEAF_FN = C.CFUNCTYPE(_i32, _vp, _i32, C.POINTER(_vp), _pi64, _vp)
@@ -267,7 +267,8 @@ class Plan:
 
     def __init__(self, parent, leaf_cols, n, eps_star, omega, prec="fp64", reorth=False,
                  mem_cap_bytes=0, eps_override=None, jacobi_max=0, leaf_rows=None, leaf_wave=0,
-                 autotune=False, block_gram=False, right_vectors=False, qr_pod=False, sketch_cols=0):
+                 autotune=False, block_gram=False, right_vectors=False, qr_pod=False, sketch_cols=0,
+                 autotune_cache=None):
         import numpy as np
         self.num_nodes = len(parent)
         self.n = int(n)
@@ -284,7 +285,8 @@ class Plan:
             ov = arr.ctypes.data_as(_pdbl)
         opts = HapodOptions(self.prec, int(bool(reorth)), int(mem_cap_bytes), ov, int(jacobi_max),
                             int(bool(autotune)), int(leaf_wave), int(bool(block_gram)),
-                            int(bool(right_vectors)), int(bool(qr_pod)), int(sketch_cols))
+                            int(bool(right_vectors)), int(bool(qr_pod)), int(sketch_cols),
+                            os.fsencode(autotune_cache) if autotune_cache else None)
         h = C.c_void_p()
         _check(_lib.hapod_plan(C.byref(tree), float(eps_star), float(omega), C.byref(opts), C.byref(h)),
                "hapod_plan")

@@ -284,7 +284,7 @@ struct PodJob {
   double info[6] = {0, 0, 0, 0, 0, 0};
   int32_t sweeps = 0;
   bool wide = false;
-  bool wide_full = false;      // Lanczos run to m steps: every eigenpair, as Jacobi gives
+  bool wide_full = false;      // complete tridiagonal reduction: every eigenpair, as Jacobi gives
   bool wide_exhausted = true;  // wide eigensolve reached the Gram's rounding level
   double wide_missing = 0.0;   // energy of unconverged Ritz values above it
   double wide_unresolved = 0.0;  // trace(G) minus the returned eigenvalues
@@ -401,13 +401,52 @@ hapod_status autotune_tile(int compute, int eb, int64_t n, int64_t m_node, Pool&
   return HAPOD_OK;
 }
 
+// The tile table on disk (autotune_cache): one line per node class,
+// "compute width height_log2 tile".  Loaded into the process's table when a
+// plan names the file (entries already present win), written back whole
+// after every run of a plan with tuning on (to a temporary file first, then
+// renamed).
+void load_tile_cache(const std::string& path) {
+  FILE* f = std::fopen(path.c_str(), "r");
+  if (!f) return;
+  char line[256];
+  std::lock_guard<std::mutex> lk(tile_mutex());
+  // line by line: a line that does not parse is skipped, not the rest
+  while (std::fgets(line, sizeof(line), f)) {
+    int c = 0, nl = 0, t = 0;
+    long long w = 0;
+    if (std::sscanf(line, "%d %lld %d %d", &c, &w, &nl, &t) == 4 && (t == 16 || t == 32 || t == 64 || t == 128) &&
+        c >= 0 && c <= 3 && w > 0 && nl >= 0 && nl <= 62)
+      tile_table().emplace(TileKey{c, (int64_t)w, nl}, t);
+  }
+  std::fclose(f);
+}
+hapod_status save_tile_cache(const std::string& path) {
+  const std::string tmp = path + ".tmp";
+  FILE* f = std::fopen(tmp.c_str(), "w");
+  if (!f) {
+    set_error("autotune_cache: cannot write " + tmp);
+    return HAPOD_E_INVALID;
+  }
+  {
+    std::lock_guard<std::mutex> lk(tile_mutex());
+    for (const auto& kv : tile_table())
+      std::fprintf(f, "%d %lld %d %d\n", kv.first.compute, (long long)kv.first.m, kv.first.nlog, kv.second);
+  }
+  const bool ok = std::fclose(f) == 0 && std::rename(tmp.c_str(), path.c_str()) == 0;
+  if (!ok) {
+    set_error("autotune_cache: cannot replace " + path);
+    return HAPOD_E_INVALID;
+  }
+  return HAPOD_OK;
+}
+
 // Eigensolver choice.  jacobi_max > 0: Jacobi up to that width, Lanczos
 // above.  jacobi_max <= 0 (automatic): Jacobi in LDS up to kAutoJacobiMin;
-// between that and kAutoJacobiMax a full-length Lanczos run (every
-// eigenpair, as Jacobi gives, at a cost growing with m^2 instead of m^3 on
-// one workgroup: 2 ms against 32 ms at 128 columns; all such nodes of a
-// batch iterate together); above, Lanczos stopped at the Gram's rounding
-// level.
+// between that and kAutoJacobiMax every eigenpair, as Jacobi gives, from a
+// Householder reduction to tridiagonal form (one workgroup per node, all
+// such nodes of a batch in one launch; 2 ms against Jacobi's 32 ms at 128
+// columns); above, Lanczos stopped at the Gram's rounding level.
 constexpr int kAutoJacobiMin = 64;
 constexpr int kAutoJacobiMax = 256;
 constexpr int64_t kLiftTargetItems = 2048;  // lift workgroups per launch to aim for
@@ -491,7 +530,8 @@ hapod_status run_pod_batch(hapod_precision prec, std::vector<PodJob>& jobs, int 
     const int64_t m = j.m;
     j.wide = (jacobi_max > 0) ? (m > jacobi_max) : (m > kAutoJacobiMin);
     // a node taken from Jacobi only for speed keeps Jacobi's result: all
-    // eigenpairs (a full Lanczos run) and the same truncation policy
+    // eigenpairs (a complete tridiagonal reduction) and the same truncation
+    // policy
     j.wide_full = j.wide && jacobi_max <= 0 && m <= kAutoJacobiMax;
     L.tile = tile_for_node(node_compute(m), j.n, m);
     // split-BF16: nodes with several column tiles get a split twin of their
@@ -1139,6 +1179,7 @@ struct hapod_plan_s {
   std::vector<std::array<double, 4>> level_ms;  // {gram, eig, trunc, lift} per level
   // nodes that took the sketched route: their diagnostics (ell = 0 otherwise)
   std::vector<SketchInfo> sketch;
+  std::string tile_cache;  // autotune_cache, copied at plan time
   Pool pool;
 };
 
@@ -2004,6 +2045,11 @@ hapod_status hapod_plan(const hapod_tree* tree, double eps_star, double omega, c
     for (int32_t a = 0; a < nn; ++a)
       if (P->opts.node_eps_override[a] >= 0.0) P->eps[a] = P->opts.node_eps_override[a];
   P->opts.node_eps_override = nullptr;  // not kept beyond the call
+  if (P->opts.autotune_cache) {
+    P->tile_cache = P->opts.autotune_cache;
+    load_tile_cache(P->tile_cache);
+  }
+  P->opts.autotune_cache = nullptr;
   if (P->opts.mem_cap_bytes > 0) {
     // the leaf level's scratch is needed whatever the ranks: a cap below it
     // can never be met
@@ -2666,6 +2712,7 @@ hapod_status hapod_run(hapod_plan_t P, hapod_leaf_fn get_leaf, void* user, void*
   out_buf[P->root] = nullptr;
   release_all();
   P->run_peak = P->pool.peak();
+  if (!P->tile_cache.empty() && P->opts.autotune) HAPOD_TRY(save_tile_cache(P->tile_cache));
   // the blocks freed by this run stay cached for the next one (mem_cap_bytes
   // bounds them; a failed device allocation returns them first)
   P->has_result = true;

@@ -1,6 +1,9 @@
 // Eigensolver for Gram matrices too large for one workgroup's Jacobi
 // (the wide root of a star tree): the leading eigenpairs of G by Lanczos with
-// full reorthogonalisation, in FP64.
+// full reorthogonalisation, in FP64.  Runs that need every eigenpair of a
+// matrix of at most kHhMaxM columns replace the Krylov steps by a Householder
+// reduction to the same tridiagonal form (see tridiag_kernel); everything
+// from T on is shared.
 //
 //   q_0: deterministic pseudo-random unit vector.
 //   step j: w = G q_j; two passes of classical Gram-Schmidt against
@@ -951,6 +954,202 @@ __global__ __launch_bounds__(256) void ortho_sweep_kernel(const LzNode* __restri
   if (pass == 1 && t == 0) n.last[v] = zv[k - 1] * inv;
 }
 
+// ---- Full spectra of mid-size matrices (m <= kHhMaxM): Householder ------------
+// A full run needs every eigenpair, so the Krylov iteration has no early stop
+// to gain from; the orthogonal reduction Q^T G Q = T (Householder, Golub & Van
+// Loan, Matrix Computations, Sec. 8.3.1) gives the same (alpha, beta, Q) a
+// complete Lanczos run would, backward stable and in a fixed number of steps
+// with no host decisions.  One workgroup per matrix; the work copy A of G
+// (Z2, leading dimension m rounded up to even) stays in the L2 cache.
+//
+// Step k: the pending rank-2 update of step k-1 is applied to column k, whose
+// tail x = A[k+1:, k] gives the reflector H_k = I - tau v v^T (v[k+1] = 1,
+// H_k x = beta_k e_{k+1}); then one pass over the trailing block both applies
+// the pending update and forms p = A v, and w = tau p - (tau^2 / 2)(p^T v) v
+// becomes the next pending update A -= v w^T + w v^T.  Each trailing element
+// is read and written once per step.  The reflectors are kept below the
+// subdiagonal of A (tau_k in w[k]) for formq_kernel.
+constexpr int kHhMaxM = 256;
+typedef __attribute__((address_space(1))) dv2 gdv2;
+constexpr int kHhThreads = 1024;
+constexpr int kHhRowPairs = kHhMaxM / 2;            // threads along the rows, two rows each
+constexpr int kHhGroups = kHhThreads / kHhRowPairs;  // column groups
+
+__global__ __launch_bounds__(kHhThreads) void tridiag_kernel(const LzNode* __restrict__ nodes,
+                                                             const int* __restrict__ list) {
+  const LzNode n = nodes[list[blockIdx.x]];
+  const int m = (int)n.m;
+  const int lda = m + (m & 1);
+  double* A = n.Z2;
+  double* tau = n.w;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  __shared__ double sv[kHhMaxM], sw[kHhMaxM], nv[kHhMaxM];
+  __shared__ double pp[kHhGroups][kHhMaxM];
+  __shared__ double red[kHhThreads / 64];
+  __shared__ double scal[2];
+  for (int64_t e = t; e < (int64_t)lda * m; e += kHhThreads) {
+    const int j = (int)(e / lda), i = (int)(e - (int64_t)j * lda);
+    A[e] = (i < m) ? n.G[(int64_t)j * n.ldg + i] : 0.0;
+  }
+  for (int i = t; i < kHhMaxM; i += kHhThreads) {
+    sv[i] = 0.0;
+    sw[i] = 0.0;
+  }
+  __syncthreads();
+  auto block_sum = [&](double x) {
+    x = wave_sum(x);
+    if (lane == 0) red[wave] = x;
+    __syncthreads();
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < kHhThreads / 64; ++q) s += red[q];
+    return s;
+  };
+  const int rp = t % kHhRowPairs, cg = t / kHhRowPairs;
+  const int r = 2 * rp;
+  for (int k = 0; k + 2 < m; ++k) {
+    // column k with the pending update; its tail is x
+    double xi = 0.0;
+    if (t >= k && t < m) xi = A[t + (int64_t)k * lda] - (sv[t] * sw[k] + sw[t] * sv[k]);
+    if (t == k) scal[0] = xi;
+    if (t == k + 1) scal[1] = xi;
+    const double tail = block_sum((t >= k + 2 && t < m) ? xi * xi : 0.0);
+    const double d = scal[0], x0 = scal[1];
+    double beta = x0, tk = 0.0, scale = 0.0;
+    if (tail > 0.0) {
+      const double nrm = sqrt(x0 * x0 + tail);
+      beta = (x0 >= 0.0) ? -nrm : nrm;
+      tk = (beta - x0) / beta;
+      scale = 1.0 / (x0 - beta);
+    }
+    if (t < kHhMaxM) nv[t] = (t == k + 1) ? 1.0 : ((t >= k + 2 && t < m) ? xi * scale : 0.0);
+    if (t >= k + 2 && t < m) A[t + (int64_t)k * lda] = xi * scale;
+    if (t == 0) {
+      n.alpha[k] = d;
+      n.beta[k] = beta;
+      tau[k] = tk;
+    }
+    __syncthreads();
+    // trailing block (rows and columns k+1 ..): pending update, then p = A v
+    double acc0 = 0.0, acc1 = 0.0;
+    if (r + 1 >= k + 1 && r < m) {
+      const double v0 = sv[r], v1 = sv[r + 1], w0 = sw[r], w1 = sw[r + 1];
+      double* col = A + r;
+      int j = k + 1 + cg;
+      for (; j + 3 * kHhGroups < m; j += 4 * kHhGroups) {
+        dv2 a[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) a[u] = *(gptr<dv2>)as_global(col + (int64_t)(j + u * kHhGroups) * lda);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int jj = j + u * kHhGroups;
+          const double vj = sv[jj], wj = sw[jj], nj = nv[jj];
+          const double a0 = a[u][0] - (v0 * wj + w0 * vj), a1 = a[u][1] - (v1 * wj + w1 * vj);
+          *(gdv2*)(col + (int64_t)jj * lda) = dv2{a0, a1};
+          acc0 += a0 * nj;
+          acc1 += a1 * nj;
+        }
+      }
+      for (; j < m; j += kHhGroups) {
+        const dv2 a = *(gptr<dv2>)as_global(col + (int64_t)j * lda);
+        const double vj = sv[j], wj = sw[j], nj = nv[j];
+        const double a0 = a[0] - (v0 * wj + w0 * vj), a1 = a[1] - (v1 * wj + w1 * vj);
+        *(gdv2*)(col + (int64_t)j * lda) = dv2{a0, a1};
+        acc0 += a0 * nj;
+        acc1 += a1 * nj;
+      }
+    }
+    pp[cg][r] = acc0;
+    pp[cg][r + 1] = acc1;
+    __syncthreads();
+    // w = tau p - (tau / 2)(tau p . v) v
+    double pi = 0.0, vi = 0.0;
+    if (t >= k + 1 && t < m) {
+#pragma unroll
+      for (int q = 0; q < kHhGroups; ++q) pi += pp[q][t];
+      pi *= tk;
+      vi = nv[t];
+    }
+    const double K = 0.5 * tk * block_sum(pi * vi);
+    if (t < kHhMaxM) {
+      sv[t] = nv[t];
+      sw[t] = (t >= k + 1 && t < m) ? pi - K * vi : 0.0;
+    }
+    __syncthreads();
+  }
+  // the last 2 x 2 block (or the single entry)
+  if (t == 0) {
+    if (m >= 2) {
+      auto at = [&](int i, int j) { return A[i + (int64_t)j * lda] - (sv[i] * sw[j] + sw[i] * sv[j]); };
+      n.alpha[m - 2] = at(m - 2, m - 2);
+      n.beta[m - 2] = at(m - 1, m - 2);
+      n.alpha[m - 1] = at(m - 1, m - 1);
+      tau[m - 2] = 0.0;
+    } else if (m == 1) {
+      n.alpha[0] = A[0];
+    }
+    if (m >= 1) {
+      n.beta[m - 1] = 0.0;
+      tau[m - 1] = 0.0;
+    }
+  }
+}
+
+// Q = H_0 H_1 ... H_{m-3}: column j is H_0 ... H_{j-1} e_j (reflectors with
+// index >= j leave e_j alone).  Sixteen columns per workgroup (one wavefront
+// each, four rows per lane); the reflectors pass through LDS in chunks of 64,
+// highest index first.
+constexpr int kFqChunk = 64;
+__global__ __launch_bounds__(1024) void formq_kernel(const LzNode* __restrict__ nodes, const int* __restrict__ list) {
+  const LzNode n = nodes[list[blockIdx.z]];
+  const int m = (int)n.m;
+  const int lda = m + (m & 1);
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int j = blockIdx.x * 16 + wave;
+  if (blockIdx.x * 16 >= m) return;  // whole workgroup
+  extern __shared__ double rf[];      // kFqChunk x m reflectors, then their tau
+  double* rt = rf + (size_t)kFqChunk * m;
+  double q[kHhMaxM / 64];
+#pragma unroll
+  for (int s = 0; s < kHhMaxM / 64; ++s) q[s] = (lane + 64 * s == j) ? 1.0 : 0.0;
+  const int jmax = min(m, (int)blockIdx.x * 16 + 16);  // highest column + 1 in this workgroup
+  for (int c1 = jmax - 1; c1 > 0; c1 -= kFqChunk) {
+    const int c0 = max(0, c1 - kFqChunk);  // reflectors c0 .. c1-1
+    const int nc = c1 - c0;
+    __syncthreads();
+    for (int e = t; e < nc * m; e += 1024) {
+      const int c = e / m, row = e - c * m, kk = c0 + c;
+      rf[e] = (row == kk + 1) ? 1.0 : (row >= kk + 2 ? n.Z2[row + (int64_t)kk * lda] : 0.0);
+    }
+    for (int c = t; c < nc; c += 1024) rt[c] = n.w[c0 + c];
+    __syncthreads();
+    if (j < m)
+      for (int kk = min(c1, j) - 1; kk >= c0; --kk) {
+        const double tk = rt[kk - c0];
+        if (tk == 0.0) continue;
+        const double* v = rf + (size_t)(kk - c0) * m;
+        double dot = 0.0;
+#pragma unroll
+        for (int s = 0; s < kHhMaxM / 64; ++s) {
+          const int row = lane + 64 * s;
+          if (row < m) dot += v[row] * q[s];
+        }
+        dot = tk * wave_sum(dot);
+#pragma unroll
+        for (int s = 0; s < kHhMaxM / 64; ++s) {
+          const int row = lane + 64 * s;
+          if (row < m) q[s] -= dot * v[row];
+        }
+      }
+  }
+  if (j < m)
+#pragma unroll
+    for (int s = 0; s < kHhMaxM / 64; ++s) {
+      const int row = lane + 64 * s;
+      if (row < m) n.Q[(int64_t)j * m + row] = q[s];
+    }
+}
+
 // make the largest-magnitude entry of every column positive (one wave per column)
 __global__ __launch_bounds__(256) void sign_fix_kernel(const LzNode* __restrict__ nodes) {
   const LzNode n = nodes[blockIdx.z];
@@ -1017,12 +1216,25 @@ hapod_status wide_eigh_batch(std::vector<WideJob>& jobs, double u_p, wide_alloc_
   }
   // (the cooperative grid is the widest matrix's workgroup count times the
   // number of matrices, one workgroup per CU by its LDS: all must be resident)
+  // full runs of at most kHhMaxM columns: Householder reduction instead of
+  // the Krylov iteration (HAPOD_FULL_LANCZOS=1 keeps them on Lanczos)
+  static const bool force_lanczos = [] {
+    const char* e = std::getenv("HAPOD_FULL_LANCZOS");
+    return e && e[0] == '1';
+  }();
+  std::vector<char> hh(nn, 0);
+  std::vector<int> hh_list;
+  for (int i = 0; i < nn; ++i)
+    if (!force_lanczos && jobs[i].full && jobs[i].m > 0 && jobs[i].m <= kHhMaxM) {
+      hh[i] = 1;
+      hh_list.push_back(i);
+    }
   std::vector<char> coop(nn, 0);
   {
     int count = 0;
     for (int i = 0; i < nn; ++i) {
       const int64_t m = jobs[i].m;
-      if (m <= 0 || fused_node(i) || m > kCoopMaxM) continue;
+      if (m <= 0 || hh[i] || fused_node(i) || m > kCoopMaxM) continue;
       if ((count + 1) * coop_pick(kCoopMaxM) > n_cu) break;
       coop[i] = 1;
       ++count;
@@ -1051,7 +1263,8 @@ hapod_status wide_eigh_batch(std::vector<WideJob>& jobs, double u_p, wide_alloc_
     double* e2 = nullptr;  // bisection works in LDS
     double* Z = (double*)take(sizeof(double) * (size_t)k * k);
     double* last = (double*)take(sizeof(double) * k);
-    double* Z2 = (double*)take(sizeof(double) * (size_t)k * k);
+    // (k + 1 columns: the Householder work copy's leading dimension is m rounded up to even)
+    double* Z2 = (double*)take(sizeof(double) * (size_t)k * (k + 1));
     double* isc = nullptr;  // inverse iteration works in LDS
     int* ipiv = nullptr;
     double* tr = (double*)take(sizeof(double));
@@ -1096,6 +1309,8 @@ hapod_status wide_eigh_batch(std::vector<WideJob>& jobs, double u_p, wide_alloc_
   total = al(total + sizeof(double) * 2 * nn);
   const size_t o_lift = total;
   total = al(total + sizeof(LiftNode) * nn);
+  const size_t o_hh = total;
+  total = al(total + sizeof(int) * nn);
   const size_t o_bar = total;  // barrier counters, then the error flag
   total = al(total + sizeof(unsigned) * (nn + 1));
   char* blk = (char*)alloc(ctx, total);
@@ -1141,14 +1356,33 @@ hapod_status wide_eigh_batch(std::vector<WideJob>& jobs, double u_p, wide_alloc_
   std::vector<int> steps(kmax), act;
   std::vector<char> stopped(nn, 0);
   std::vector<double> prev_check(nn, 0.0);
+  // Householder nodes: the reduction, then Q from its reflectors
+  if (!hh_list.empty()) {
+    int* dhh = (int*)(blk + o_hh);
+    const unsigned nh = (unsigned)hh_list.size();
+    HAPOD_HIP(hipMemcpyAsync(dhh, hh_list.data(), sizeof(int) * nh, hipMemcpyHostToDevice, stream));
+    hipLaunchKernelGGL(tridiag_kernel, dim3(nh), dim3(kHhThreads), 0, stream, dn, dhh);
+    HAPOD_HIP(hipGetLastError());
+    int64_t hm = 0;
+    for (int i : hh_list) hm = std::max(hm, jobs[i].m);
+    const size_t shm = sizeof(double) * ((size_t)kFqChunk * hm + kFqChunk);
+    static bool fq_attr = false;
+    if (!fq_attr) {
+      HAPOD_HIP(hipFuncSetAttribute((const void*)formq_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)(sizeof(double) * ((size_t)kFqChunk * kHhMaxM + kFqChunk))));
+      fq_attr = true;
+    }
+    hipLaunchKernelGGL(formq_kernel, dim3((unsigned)((hm + 15) / 16), 1, nh), dim3(1024), shm, stream, dn, dhh);
+    HAPOD_HIP(hipGetLastError());
+  }
   // the active list: fused matrices, then cooperative ones, then the rest
   for (int i = 0; i < nn; ++i) stopped[i] = (kmax[i] == jobs[i].m);
   for (int i = 0; i < nn; ++i)
-    if (jobs[i].m > 0 && fused_node(i)) act.push_back(i);
+    if (jobs[i].m > 0 && !hh[i] && fused_node(i)) act.push_back(i);
   for (int i = 0; i < nn; ++i)
-    if (jobs[i].m > 0 && coop[i]) act.push_back(i);
+    if (jobs[i].m > 0 && !hh[i] && coop[i]) act.push_back(i);
   for (int i = 0; i < nn; ++i)
-    if (jobs[i].m > 0 && !fused_node(i) && !coop[i]) act.push_back(i);
+    if (jobs[i].m > 0 && !hh[i] && !fused_node(i) && !coop[i]) act.push_back(i);
   const char* venv = std::getenv("HAPOD_VERBOSE");
   const bool verbose = venv && venv[0] == '1';
   bool act_dirty = true;

@@ -231,9 +231,10 @@ def prescribed_svd(n, m, sigma, seed):
     return (U * sigma) @ W.T
 
 
-# m = 200: one-workgroup Krylov steps; 250, 300, 450: a matrix alone above
-# 224 columns takes the cooperative multi-workgroup steps (16 workgroups up
-# to 320 columns, 32 above)
+# m = 100, 200, 250: every eigenpair from the Householder reduction (one
+# workgroup); 300, 450: Krylov steps, a matrix alone above 224 columns on the
+# cooperative multi-workgroup kernel (16 workgroups up to 320 columns, 32
+# above)
 @pytest.mark.parametrize("n,m", [(8, 3), (64, 16), (33, 33), (16, 40), (500, 100), (4096, 64), (600, 200),
                                  (500, 250), (700, 300), (900, 450)])
 def test_node_pod_against_svd_oracle(hp, n, m):
@@ -279,10 +280,10 @@ def test_node_pod_split_bf16_one_256_tile(hp, n, m):
 
 @pytest.mark.parametrize("m", [200, 250])
 def test_node_pod_exact_multiplicity(hp, m):
-    """A lone node of 129..256 columns takes the full-length Krylov
-    eigensolver (one workgroup at 200 columns, cooperative workgroups at
-    250); G = 4 I (every eigenvalue repeated) breaks its Krylov space down at
-    every step: all m modes, sigma = 2, the span of the inputs."""
+    """A lone node of 129..256 columns needs every eigenpair (the
+    Householder reduction); G = 4 I (every eigenvalue repeated) is already
+    tridiagonal, so every reflector is the identity (a Krylov run would break
+    down at every step): all m modes, sigma = 2, the span of the inputs."""
     from oracle import metrics
     n = 256
     S = np.zeros((n, m))

@@ -259,10 +259,18 @@ def test_error_paths_leave_plan_usable(hp):
     assert e.value.status == 5
     plan.run(data)
     assert len(plan.modes()[0]) > 0
-    capped = hp.Plan(synth.star_tree(2), [10, 10, 0], 200, 1e-3, 0.5, mem_cap_bytes=4096)
+    # a cap below the leaf level's own scratch fails at plan time; one above
+    # it but below what the run needs (the leaves' modes alone take 2 x 200 x
+    # rank doubles) fails in the run, and the plan stays usable
+    with pytest.raises(hp.HapodError) as e:
+        hp.Plan(synth.star_tree(2), [10, 10, 0], 200, 1e-3, 0.5, mem_cap_bytes=4096)
+    assert e.value.status == 3
+    capped = hp.Plan(synth.star_tree(2), [10, 10, 0], 200, 1e-3, 0.5, mem_cap_bytes=6000)
     with pytest.raises(hp.HapodError) as e:
         capped.run(data)
     assert e.value.status == 3
+    plan.run(data)
+    assert len(plan.modes()[0]) > 0
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
@@ -503,3 +511,24 @@ def test_right_vectors_need_the_option(hp):
     plan.run({0: dev_colmajor(S[:, :8]), 1: dev_colmajor(S[:, 8:])})
     with pytest.raises(hp.HapodError):
         plan.right_vectors()  # plan made without right_vectors
+
+
+def test_autotune_cache_file(hp, tmp_path):
+    """With autotune and a cache file the tuned tile of each node class is
+    written back after the run (compute mode, width class, height class,
+    tile per line) and a plan made later reads it without error; a corrupt
+    line is ignored."""
+    n, L, c = 3000, 3, 40
+    S = synth.sinusoid(n, L * c, 60, 8.0, 0.0, seed=9)
+    data = dict(enumerate(split_cols(S, [c] * L)))
+    path = tmp_path / "tiles.txt"
+    path.write_text("not a line\n")
+    plan = hp.Plan(synth.star_tree(L), [c] * L + [0], n, 1e-6, 0.75, prec="fp32", autotune=True,
+                   autotune_cache=str(path))
+    plan.run({k: dev_colmajor(v, torch.float32) for k, v in data.items()})
+    lines = [ln.split() for ln in path.read_text().splitlines() if ln.strip()]
+    assert lines and all(len(ln) == 4 for ln in lines)
+    # the leaves' class: FP32 compute, width 48 (40 rounded up to 16), height 2^12
+    assert any(ln[0] == "1" and ln[1] == "48" and ln[2] == "12" and ln[3] in ("16", "32", "64", "128")
+               for ln in lines), lines
+    hp.Plan(synth.star_tree(L), [c] * L + [0], n, 1e-6, 0.75, prec="fp32", autotune=True, autotune_cache=str(path))
