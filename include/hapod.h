@@ -130,7 +130,9 @@ hapod_status hapod_truncate(int64_t m, const double* lambda, double eps,
  *           sigma_k phi_k, what a parent node consumes).  Non-NULL:
  *           out = S V diag(lambda)^(-1/2) (orthonormal modes, the root's
  *           output).
- *   out     device, n x N, ld ldo, storage type of prec.                    */
+ *   out     device, n x N, ld ldo, storage type of prec.
+ * Products: FP64 MFMA (HAPOD_FP64), FP32 MFMA (HAPOD_FP32), three BF16
+ * products per term with FP32 accumulation (HAPOD_BF16X3).                 */
 hapod_status hapod_lift(hapod_precision prec, int64_t n, int64_t m, int64_t N,
                         const void* S, int64_t lds, const double* V, int64_t ldv,
                         const double* lambda, void* out, int64_t ldo,

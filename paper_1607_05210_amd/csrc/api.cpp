@@ -459,10 +459,17 @@ hapod_status run_pod_batch(hapod_precision prec, std::vector<PodJob>& jobs, int 
   const int nj = (int)jobs.size();
   if (nj == 0) return HAPOD_OK;
   const double u_p = (prec == HAPOD_FP64) ? std::ldexp(1.0, -53) : std::ldexp(1.0, -24);
+  // the split-BF16 form lifts in split-BF16 too (HAPOD_LIFT_FP32=1: on FP32
+  // MFMA, as the FP32 form does)
+  static const bool split_lift = [] {
+    const char* e = std::getenv("HAPOD_LIFT_FP32");
+    return !(e && e[0] == '1');
+  }();
 
   // ---- sizes & scratch layout ---------------------------------------------
   struct Lay {
-    size_t cols, rbs, crows, cols2, rbs2, crows2, G, partial, lam, V, B, B32, sigma, rank, info, jwork, vwork, sweeps;
+    size_t cols, rbs, crows, cols2, rbs2, crows2, G, partial, lam, V, B, B32, Bs, sigma, rank, info, jwork, vwork,
+        sweeps;
     bool presplit, own256;
     int tile, slots, ntiles, pairs, nchunks;
     int64_t chunk_rows;
@@ -593,6 +600,7 @@ hapod_status run_pod_batch(hapod_precision prec, std::vector<PodJob>& jobs, int 
     const int64_t ldb = std::max<int64_t>((m + 3) / 4 * 4, 4);
     L.B = take(sizeof(double) * m * ldb);
     L.B32 = (compute != 0) ? take(sizeof(float) * m * ldb) : 0;
+    L.Bs = (compute == 2 && split_lift) ? take(split_operand_bytes(m)) : 0;
     L.sigma = take(sizeof(double) * std::max<int64_t>(m, 1));
     L.rank = take(sizeof(int64_t));
     L.info = take(sizeof(double) * 8);
@@ -1027,6 +1035,7 @@ hapod_status run_pod_batch(hapod_precision prec, std::vector<PodJob>& jobs, int 
     l.crows = (const int64_t*)(scratch + lay[i].crows);
     l.B = tnodes[i].B;
     l.B32 = tnodes[i].B32;
+    l.Bs = lay[i].Bs ? (char*)(scratch + lay[i].Bs) : nullptr;
     l.rank = tnodes[i].rank;
     l.out = j.out;
     l.n = j.n;
@@ -1055,10 +1064,16 @@ hapod_status run_pod_batch(hapod_precision prec, std::vector<PodJob>& jobs, int 
     ~Guard3() { p.free(s); }
   } guard3{pool, dlift};
   if (times && ev.ok) HAPOD_HIP(hipEventRecord(ev.e[3], stream));
-  // the split-BF16 form lifts on FP32 MFMA: the lift reads each input once
-  // per 128 output columns, so it is bandwidth-bound where the three-product
-  // split would only add VALU work, and FP32 products are at least as exact
-  const int lift_compute = (compute == 2) ? 1 : compute;
+  // the split-BF16 form lifts with three BF16 products per term: a lift of
+  // N output columns does 2 N flops per 4 input bytes, above the FP32 MFMA
+  // peak's share of HBM bandwidth once N passes about 40, while the BF16
+  // products keep it bandwidth-bound (the operand is split once, here)
+  const int lift_compute = (compute == 2 && !split_lift) ? 1 : compute;
+  if (lift_compute == 2 && nl0 + nl1 > 0) {
+    int64_t max_m = 0;
+    for (int i = 0; i < nj; ++i) max_m = std::max(max_m, jobs[i].m);
+    HAPOD_TRY(launch_split_operand((const LiftNode*)dlift, (int)(nl0 + nl1), max_m, stream));
+  }
   if (nl0) HAPOD_TRY(launch_lift(lift_compute, (const LiftNode*)dlift, (int)nl0, lift_items[0], stream, false));
   if (nl1)
     HAPOD_TRY(launch_lift(lift_compute, (const LiftNode*)dlift + nl0, (int)nl1, lift_items[1], stream, true));
@@ -3094,6 +3109,8 @@ hapod_status hapod_lift(hapod_precision prec, int64_t n, int64_t m, int64_t N, c
   HAPOD_TRY(launch_fill_i64((int64_t*)drows, n, m, stream));
   HAPOD_TRY(pool.alloc(sizeof(double) * std::max<int64_t>(m * N, 1), &dB));
   if (prec != HAPOD_FP64) HAPOD_TRY(pool.alloc(sizeof(float) * std::max<int64_t>(m * N, 1), &dB32));
+  void* dBs = nullptr;
+  if (prec == HAPOD_BF16X3) HAPOD_TRY(pool.alloc(std::max<size_t>(split_operand_bytes(m), 128), &dBs));
   HAPOD_TRY(pool.alloc(sizeof(int64_t), &drank));
   HAPOD_TRY(pool.alloc(sizeof(LiftNode), &dn));
   LiftNode l{};
@@ -3102,6 +3119,7 @@ hapod_status hapod_lift(hapod_precision prec, int64_t n, int64_t m, int64_t N, c
   l.crows = (const int64_t*)drows;
   l.B = (const double*)dB;
   l.B32 = (const float*)dB32;
+  l.Bs = (char*)dBs;
   l.rank = (const int64_t*)drank;
   l.out = out;
   l.n = n;
@@ -3128,7 +3146,12 @@ hapod_status hapod_lift(hapod_precision prec, int64_t n, int64_t m, int64_t N, c
     if (st != HAPOD_OK) break;
     st = launch_set_scalar_i64((int64_t*)drank, N, stream);
     if (st != HAPOD_OK) break;
-    st = launch_lift(prec == HAPOD_FP64 ? 0 : 1, (const LiftNode*)dn, 1, l.row_tiles * l.col_tiles, stream);
+    if (dBs) {
+      st = launch_split_operand((const LiftNode*)dn, 1, m, stream);
+      if (st != HAPOD_OK) break;
+    }
+    st = launch_lift(prec == HAPOD_FP64 ? 0 : (dBs ? 2 : 1), (const LiftNode*)dn, 1, l.row_tiles * l.col_tiles,
+                     stream);
   } while (0);
   (void)hipStreamSynchronize(stream);
   pool.free(dcols);
@@ -3136,6 +3159,7 @@ hapod_status hapod_lift(hapod_precision prec, int64_t n, int64_t m, int64_t N, c
   pool.free(drows);
   pool.free(dB);
   if (dB32) pool.free(dB32);
+  if (dBs) pool.free(dBs);
   pool.free(drank);
   pool.free(dn);
   return st;

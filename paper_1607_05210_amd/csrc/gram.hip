@@ -230,16 +230,13 @@ __global__ __launch_bounds__(256) void gram_tile_kernel(const GramNode* __restri
           for (int i = 0; i < 8; ++i) {
             if (i >= nld) continue;
             const float* x = reinterpret_cast<const float*>(&pre[i]);
-            uint16_t h[4], l[4];
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-              h[e] = bf16_bits_rne(x[e]);
-              l[e] = bf16_bits_rne(x[e] - bf16_bits_to_float(h[e]));
-            }
+            uint32_t h01, l01, h23, l23;
+            split_bf16x2(x[0], x[1], h01, l01);
+            split_bf16x2(x[2], x[3], h23, l23);
             char* q = stage[buf] + (32 * i + (t >> 3)) * kColB + part * 8;
             typedef __attribute__((ext_vector_type(2))) int i2;
-            *(i2*)q = i2{(int)(h[0] | ((uint32_t)h[1] << 16)), (int)(h[2] | ((uint32_t)h[3] << 16))};
-            *(i2*)(q + 64) = i2{(int)(l[0] | ((uint32_t)l[1] << 16)), (int)(l[2] | ((uint32_t)l[3] << 16))};
+            *(i2*)q = i2{(int)h01, (int)h23};
+            *(i2*)(q + 64) = i2{(int)l01, (int)l23};
           }
         }
       };
@@ -529,16 +526,13 @@ __global__ __launch_bounds__(512, 1) void gram_bf16_t256_kernel(const GramNode* 
       for (int i = 0; i < kOwn; ++i) {
         const i4 v = (slot == 0) ? own[0][i] : own[1][i];
         const float* x = reinterpret_cast<const float*>(&v);
-        uint16_t h[4], l[4];
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          h[e] = bf16_bits_rne(x[e]);
-          l[e] = bf16_bits_rne(x[e] - bf16_bits_to_float(h[e]));
-        }
+        uint32_t h01, l01, h23, l23;
+        split_bf16x2(x[0], x[1], h01, l01);
+        split_bf16x2(x[2], x[3], h23, l23);
         char* q = stage[buf] + (64 * i + (t >> 3)) * kColB + part * 8;
         typedef __attribute__((ext_vector_type(2))) int i2;
-        *(i2*)q = i2{(int)(h[0] | ((uint32_t)h[1] << 16)), (int)(h[2] | ((uint32_t)h[3] << 16))};
-        *(i2*)(q + 64) = i2{(int)(l[0] | ((uint32_t)l[1] << 16)), (int)(l[2] | ((uint32_t)l[3] << 16))};
+        *(i2*)q = i2{(int)h01, (int)h23};
+        *(i2*)(q + 64) = i2{(int)l01, (int)l23};
       }
     }
   };

@@ -227,14 +227,25 @@ struct LiftNode {
   const int64_t* rrbs;
   const int64_t* rrows;
   double* rpart;
+  // Split-BF16 lift (compute 2): the lift operand split once into BF16 hi
+  // and lo, transposed: for output column c < N and reduction stage s
+  // (reduction indices 32 s .. 32 s + 31, zero past m), 128 bytes at
+  // Bs + (c * ceil(m / 32) + s) * 128, the 32 hi then the 32 lo values.
+  // Written from B32 by launch_split_operand; room for m columns (N <= m).
+  char* Bs;
 };
-// compute: 0 FP64 MFMA, 1 FP32 MFMA (the split-BF16 form lifts on FP32
-// MFMA); output storage = input storage.
+// compute: 0 FP64 MFMA, 1 FP32 MFMA, 2 split-BF16 (three BF16 products per
+// term on BF16 MFMA, FP32 accumulation; reads Bs); output storage = input
+// storage.
 // narrow: every node has N <= 64 and its tiles are kLiftNarrowM x 64
 // (row_tiles and col_tiles counted for that tile).
 constexpr int kLiftNarrowM = 256;
 hapod_status launch_lift(int compute, const LiftNode* d_nodes, int num_nodes,
                          int num_items, hipStream_t stream, bool narrow = false);
+// Bs of every node from its B32, the first *rank columns (max_m: the widest
+// node's m, for the grid)
+hapod_status launch_split_operand(const LiftNode* d_nodes, int num_nodes, int64_t max_m, hipStream_t stream);
+inline size_t split_operand_bytes(int64_t m) { return (size_t)((m + 31) / 32) * 128 * (size_t)m; }
 // Residual mode of the FP64 lift (see LiftNode::rcols), one node.
 // dense: every column of the node holds all n rows, may be read to the next
 // multiple of 128 rows, starts 16-byte aligned, m is a multiple of 32 and N of

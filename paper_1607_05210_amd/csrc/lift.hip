@@ -540,6 +540,226 @@ __global__ __launch_bounds__(256, 2) void lift_staged_kernel(const LiftNode* __r
   }  // row tiles
 }
 
+// Split-BF16 lift: out = S B with every product x y taken as
+// xl yh + xh yl + xh yh (x = xh + xl, y = yh + yl, BF16 parts; FP32
+// accumulation), on BF16 MFMA (16 x 16 x 32).  Per stage of 32 reduction
+// indices the workgroup stages its S tile through LDS transposed (row-major,
+// the 32 values of a row contiguous, hi then lo), splitting each FP32 value as
+// it goes; each lane then reads the 8 consecutive reduction indices of one
+// row that its MFMA operand needs.  The B fragments come split and transposed
+// from Bs.  Tiles 128 x 128 (four wavefronts of 64 x 64), or 256 x 64 with
+// the wavefronts stacked along the rows for ranks up to 64; the accumulator
+// of a lane holds four consecutive rows of one column (one 16-byte store).
+template <bool NARROW>
+__global__ __launch_bounds__(256, 2) void lift_bf16_kernel(const LiftNode* __restrict__ nodes, int num_nodes) {
+  constexpr int TMk = NARROW ? 4 * WT : TM;
+  constexpr int TNk = NARROW ? WT : TN;
+  constexpr int KS = 32;
+  constexpr int RB = 144;             // LDS bytes per staged S row (64 hi, 64 lo, 16 pad)
+  constexpr int RQ = TMk / 4;         // row quads of a tile
+  constexpr int KC = KS * RQ / 256;   // columns per thread and stage (4 rows each)
+  constexpr int KTS = 256;            // column-table chunk
+  static_assert(KC * 256 == KS * RQ && (KC == 4 || KC == 8), "whole column quads per thread");
+  typedef __attribute__((ext_vector_type(4))) int i4;
+
+  const int item = xcd_item(blockIdx.x, gridDim.x);
+  int lo = 0, hi = num_nodes - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (nodes[mid].item_base <= item) lo = mid;
+    else hi = mid - 1;
+  }
+  const LiftNode nd = nodes[lo];
+  const int local = item - nd.item_base;
+  const int rg = local / nd.col_tiles, ct = local % nd.col_tiles;
+  const int64_t N = *nd.rank;
+  if ((int64_t)ct * TNk >= N) return;  // whole workgroup
+  const int rt_per = max(nd.rt_per, 1);
+  const int rt_begin = rg * rt_per, rt_end = min(rt_begin + rt_per, nd.row_tiles);
+
+  __shared__ __attribute__((aligned(16))) char sS[2][TMk * RB];
+  __shared__ const char* tcol[KTS];
+  __shared__ int64_t trbs[KTS];
+  __shared__ int64_t trows[KTS];
+
+  const int t = threadIdx.x;
+  const int wave = t >> 6, lane = t & 63;
+  const int wi = NARROW ? wave : (wave >> 1), wj = NARROW ? 0 : (wave & 1);
+  const int li = lane & 15, g = lane >> 4;
+  const int64_t n0 = (int64_t)ct * TNk + wj * WT;
+  const int m = nd.m;
+  const int nks = (m + KS - 1) / KS;
+  const int stages = nks;
+  const int rq = t % RQ, kq = t / RQ;  // this thread's row quad and column group
+  int table_base = -KTS;
+  auto ensure_table = [&](int kfirst) {
+    if (kfirst >= table_base && kfirst + KS <= table_base + KTS) return;
+    __syncthreads();
+    table_base = kfirst;
+    const int k = kfirst + t;
+    const bool kv = k < m;
+    tcol[t] = kv ? reinterpret_cast<const char*>(nd.cols[k]) : nullptr;
+    trbs[t] = kv ? nd.rbs[k] : kRowBlock;
+    trows[t] = kv ? nd.crows[k] : 0;
+    __syncthreads();
+  };
+  // this lane's B columns (one per 16-column block), zero past N
+  const char* bcol[NB];
+  bool bval[NB];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    const int64_t c = n0 + 16 * b + li;
+    bval[b] = c < N;
+    bcol[b] = nd.Bs + (bval[b] ? c : 0) * (int64_t)nks * 128 + 16 * g;
+  }
+
+  for (int rt = rt_begin; rt < rt_end; ++rt) {
+    const int64_t rtile = (int64_t)rt * TMk;
+    const bool active = (rtile + wi * WT < nd.n) && (n0 < N);
+    f4 acc[NB][NB];
+#pragma unroll
+    for (int a = 0; a < NB; ++a)
+#pragma unroll
+      for (int b = 0; b < NB; ++b) acc[a][b] = f4{0, 0, 0, 0};
+    i4 ps[KC];
+    bf8 ybh[NB], ybl[NB], nbh[NB], nbl[NB];
+    auto gload = [&](int st, bf8 (&yh)[NB], bf8 (&yl)[NB]) {
+      const int64_t row = rtile + 4 * rq;
+#pragma unroll
+      for (int c = 0; c < KC; ++c) {
+        const int k = st * KS + kq * KC + c;
+        const int tk = k - table_base;
+        const int64_t avail = (k < m) ? trows[tk] - row : 0;
+        const float* p = (k < m) ? reinterpret_cast<const float*>(tcol[tk]) + (row >> 7) * trbs[tk] + (row & (kRowBlock - 1))
+                                 : nullptr;
+        if (avail >= 4 && (((uintptr_t)p & 15u) == 0)) {
+          ps[c] = *(gptr<i4>)as_global(reinterpret_cast<const i4*>(p));
+        } else {
+          float x[4];
+#pragma unroll
+          for (int e = 0; e < 4; ++e) x[e] = (e < avail) ? p[e] : 0.f;
+          ps[c] = *reinterpret_cast<const i4*>(x);
+        }
+      }
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        if (bval[b]) {
+          const char* q = bcol[b] + (int64_t)st * 128;
+          yh[b] = *(gptr<bf8>)as_global(reinterpret_cast<const bf8*>(q));
+          yl[b] = *(gptr<bf8>)as_global(reinterpret_cast<const bf8*>(q + 64));
+        } else {
+          yh[b] = __builtin_bit_cast(bf8, i4{0, 0, 0, 0});
+          yl[b] = yh[b];
+        }
+      }
+    };
+    // rows 4 rq + e of columns kq KC .. kq KC + KC - 1, split into hi and lo
+    auto lstore = [&](int buf) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        uint32_t h[KC / 2], l[KC / 2];
+#pragma unroll
+        for (int c = 0; c < KC; c += 2)
+          split_bf16x2(reinterpret_cast<const float*>(&ps[c])[e], reinterpret_cast<const float*>(&ps[c + 1])[e],
+                       h[c / 2], l[c / 2]);
+        char* q = sS[buf] + (4 * rq + e) * RB + kq * KC * 2;
+        if constexpr (KC == 4) {
+          typedef __attribute__((ext_vector_type(2))) int i2;
+          *(i2*)q = i2{(int)h[0], (int)h[1]};
+          *(i2*)(q + 64) = i2{(int)l[0], (int)l[1]};
+        } else {
+          *(i4*)q = i4{(int)h[0], (int)h[1], (int)h[2], (int)h[3]};
+          *(i4*)(q + 64) = i4{(int)l[0], (int)l[1], (int)l[2], (int)l[3]};
+        }
+      }
+    };
+    auto compute = [&](int buf) {
+      const char* sb = sS[buf] + (wi * WT + li) * RB + g * 16;
+#pragma unroll
+      for (int a = 0; a < NB; ++a) {
+        const bf8 xh = *(const bf8*)(sb + a * 16 * RB);
+        const bf8 xl = *(const bf8*)(sb + a * 16 * RB + 64);
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+          acc[a][b] = mfma_bf16(xl, ybh[b], acc[a][b]);
+          acc[a][b] = mfma_bf16(xh, ybl[b], acc[a][b]);
+          acc[a][b] = mfma_bf16(xh, ybh[b], acc[a][b]);
+        }
+      }
+    };
+    if (stages > 0) {
+      ensure_table(0);
+      gload(0, ybh, ybl);
+      lstore(0);
+    }
+    __syncthreads();
+    for (int st = 0; st < stages; ++st) {
+      const bool more = st + 1 < stages;
+      if (more) {
+        ensure_table((st + 1) * KS);
+        gload(st + 1, nbh, nbl);
+      }
+      if (active) compute(st & 1);
+      if (more) lstore((st + 1) & 1);
+      __syncthreads();
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        ybh[b] = nbh[b];
+        ybl[b] = nbl[b];
+      }
+    }
+    if (!active) continue;
+    float* out = reinterpret_cast<float*>(nd.out);
+    const int64_t r0 = rtile + wi * WT;
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      const int64_t col = n0 + 16 * b + acc_col(lane);
+      if (col >= N) continue;
+#pragma unroll
+      for (int a = 0; a < NB; ++a) {
+        const int64_t row = r0 + 16 * a + acc_row<f4>(lane, 0);
+        float* p = out + col * nd.ocs + blk_off(row, nd.obs);
+        const f4 x = acc[a][b];
+        if (row + 4 <= nd.n && (((uintptr_t)p & 15u) == 0)) {
+          *(__attribute__((address_space(1))) fv4*)p = fv4{x[0], x[1], x[2], x[3]};
+        } else {
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+            if (row + v < nd.n) p[v] = x[v];
+        }
+      }
+    }
+  }  // row tiles
+}
+
+// Bs from B32: one thread per (stage s, column c), c < N, consecutive
+// threads on consecutive columns (rows of B32 read whole)
+__global__ __launch_bounds__(256) void split_operand_kernel(const LiftNode* __restrict__ nodes) {
+  const LiftNode nd = nodes[blockIdx.z];
+  const int m = nd.m;
+  const int nks = (m + 31) / 32;
+  const int64_t N = *nd.rank;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= N * nks) return;
+  const int s = (int)(e / N);
+  const int64_t c = e - (int64_t)s * N;
+  uint32_t h[16], l[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int k = 32 * s + 2 * q;
+    const float x0 = (k < m) ? nd.B32[(int64_t)k * nd.ldb + c] : 0.f;
+    const float x1 = (k + 1 < m) ? nd.B32[(int64_t)(k + 1) * nd.ldb + c] : 0.f;
+    split_bf16x2(x0, x1, h[q], l[q]);
+  }
+  typedef __attribute__((ext_vector_type(4))) unsigned u4;
+  u4* dst = reinterpret_cast<u4*>(nd.Bs + (c * nks + s) * 128);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    dst[q] = u4{h[4 * q], h[4 * q + 1], h[4 * q + 2], h[4 * q + 3]};
+    dst[4 + q] = u4{l[4 * q], l[4 * q + 1], l[4 * q + 2], l[4 * q + 3]};
+  }
+}
+
 }  // namespace
 
 hapod_status launch_lift(int compute, const LiftNode* d_nodes, int num_nodes, int num_items,
@@ -551,8 +771,19 @@ hapod_status launch_lift(int compute, const LiftNode* d_nodes, int num_nodes, in
     case 1: hipLaunchKernelGGL((lift_kernel<0, true>), g, b, 0, stream, d_nodes, num_nodes); break;
     case 2: hipLaunchKernelGGL((lift_staged_kernel<1, false>), g, b, 0, stream, d_nodes, num_nodes); break;
     case 3: hipLaunchKernelGGL((lift_staged_kernel<1, true>), g, b, 0, stream, d_nodes, num_nodes); break;
+    case 4: hipLaunchKernelGGL((lift_bf16_kernel<false>), g, b, 0, stream, d_nodes, num_nodes); break;
+    case 5: hipLaunchKernelGGL((lift_bf16_kernel<true>), g, b, 0, stream, d_nodes, num_nodes); break;
     default: set_error("launch_lift: unknown compute mode"); return HAPOD_E_INVALID;
   }
+  HAPOD_HIP(hipGetLastError());
+  return HAPOD_OK;
+}
+
+hapod_status launch_split_operand(const LiftNode* d_nodes, int num_nodes, int64_t max_m, hipStream_t stream) {
+  if (num_nodes <= 0 || max_m <= 0) return HAPOD_OK;
+  const int64_t pairs = max_m * ((max_m + 31) / 32);
+  hipLaunchKernelGGL(split_operand_kernel, dim3((unsigned)((pairs + 255) / 256), 1, (unsigned)num_nodes), dim3(256), 0,
+                     stream, d_nodes);
   HAPOD_HIP(hipGetLastError());
   return HAPOD_OK;
 }

@@ -34,32 +34,32 @@ __device__ __forceinline__ f4 mfma_bf16(bf8 a, bf8 b, f4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
 
-// IEEE-754 binary32 -> bfloat16, round to nearest, ties to even, written
-// from the format definition (bf16 is the upper half of a binary32).
-__device__ __forceinline__ uint16_t bf16_bits_rne(float x) {
-  uint32_t u = __builtin_bit_cast(uint32_t, x);
-  if ((u & 0x7f800000u) == 0x7f800000u) {       // Inf / NaN: truncate, keep NaN quiet
-    uint16_t h = (uint16_t)(u >> 16);
-    if (u & 0x007fffffu) h |= 0x0040u;
-    return h;
-  }
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (uint16_t)(u >> 16);
-}
-__device__ __forceinline__ float bf16_bits_to_float(uint16_t h) {
-  return __builtin_bit_cast(float, (uint32_t)h << 16);
+// Split of FP32 values into BF16 parts, x = hi + lo + r with hi = bf16(x),
+// lo = bf16(x - hi) (x - hi is exact in FP32), |r| <= 2^-16 |x|: two values
+// at a time on gfx950's packed conversion (v_cvt_pk_bf16_f32: round to
+// nearest, ties to even, the default mode; Inf stays Inf, NaN stays NaN).
+// hi2 / lo2 hold the parts of a in the low and of b in the high 16 bits.
+__device__ __forceinline__ void split_bf16x2(float a, float b, uint32_t& hi2, uint32_t& lo2) {
+  typedef float f2v __attribute__((ext_vector_type(2)));
+  typedef __bf16 b2v __attribute__((ext_vector_type(2)));
+  const f2v x{a, b};
+  const b2v h = __builtin_convertvector(x, b2v);
+  const b2v l = __builtin_convertvector(x - __builtin_convertvector(h, f2v), b2v);
+  hi2 = __builtin_bit_cast(uint32_t, h);
+  lo2 = __builtin_bit_cast(uint32_t, l);
 }
 
-// x = hi + lo + r with hi = bf16(x), lo = bf16(x - hi).
+// eight values: the hi parts and the lo parts as MFMA operands
 __device__ __forceinline__ void split_bf16x8(const float* x, bf8& hi, bf8& lo) {
+  typedef __attribute__((ext_vector_type(4))) uint32_t u4v;
+  u4v h, l;
+  uint32_t hh[4], ll[4];
 #pragma unroll
-  for (int e = 0; e < 8; ++e) {
-    uint16_t h = bf16_bits_rne(x[e]);
-    float r = x[e] - bf16_bits_to_float(h);
-    uint16_t l = bf16_bits_rne(r);
-    hi[e] = __builtin_bit_cast(__bf16, h);
-    lo[e] = __builtin_bit_cast(__bf16, l);
-  }
+  for (int e = 0; e < 4; ++e) split_bf16x2(x[2 * e], x[2 * e + 1], hh[e], ll[e]);
+  h = u4v{hh[0], hh[1], hh[2], hh[3]};
+  l = u4v{ll[0], ll[1], ll[2], ll[3]};
+  hi = __builtin_bit_cast(bf8, h);
+  lo = __builtin_bit_cast(bf8, l);
 }
 
 // Pointers into global memory (address space 1): loads through them become

@@ -28,16 +28,13 @@ __global__ __launch_bounds__(256) void split_cols_kernel(int64_t n, int64_t m, c
 #pragma unroll
     for (int e = 0; e < 4; ++e) x[e] = (e < avail) ? src[e] : 0.f;
   }
-  uint16_t h[4], l[4];
-#pragma unroll
-  for (int e = 0; e < 4; ++e) {
-    h[e] = bf16_bits_rne(x[e]);
-    l[e] = bf16_bits_rne(x[e] - bf16_bits_to_float(h[e]));
-  }
+  uint32_t h01, l01, h23, l23;
+  split_bf16x2(x[0], x[1], h01, l01);
+  split_bf16x2(x[2], x[3], h23, l23);
   uint16_t* blk = reinterpret_cast<uint16_t*>(dst + (b * m + c) * kRowBlock);
   typedef __attribute__((ext_vector_type(2))) uint32_t u2;
-  *reinterpret_cast<u2*>(blk + 4 * q) = u2{h[0] | ((uint32_t)h[1] << 16), h[2] | ((uint32_t)h[3] << 16)};
-  *reinterpret_cast<u2*>(blk + kRowBlock + 4 * q) = u2{l[0] | ((uint32_t)l[1] << 16), l[2] | ((uint32_t)l[3] << 16)};
+  *reinterpret_cast<u2*>(blk + 4 * q) = u2{h01, h23};
+  *reinterpret_cast<u2*>(blk + kRowBlock + 4 * q) = u2{l01, l23};
 }
 
 __global__ void fill_colptrs_kernel(const char* base, int64_t ld_bytes, int64_t m, const void** out) {
