@@ -28,7 +28,8 @@ U64 = 2.0 ** -53
 U32 = 2.0 ** -24
 ELEM = {"fp64": torch.float64, "fp32": torch.float32, "bf16x3": torch.float32}
 
-GRAM_SHAPES = [(1, 1), (7, 3), (100, 17), (4096, 64), (5000, 130), (3000, 256), (2049, 300), (64, 129)]
+GRAM_SHAPES = [(1, 1), (7, 3), (100, 17), (4096, 64), (5000, 130), (3000, 256), (2049, 300), (64, 129), (1000, 600),
+               (300, 520)]
 
 
 # ---------------------------------------------------------------- Gram ------
