@@ -428,6 +428,22 @@ hapod_status hapod_node_stats(hapod_plan_t plan, int64_t* m_in, int64_t* n_negat
  * HIP events on the run's stream: {total, gram, eig, truncate, lift, reorth}. */
 hapod_status hapod_run_timing(hapod_plan_t plan, double* ms6);
 
+/* How the last run's batches of method-of-snapshots nodes (Rem. 2.3; one
+ * level, or one wave of leaves) went, host, 3 values:
+ *   out3[0]  device-driven batches: every node's eigensolve needs no host
+ *            step (Jacobi, or the Householder reduction of 65..256 columns),
+ *            so the Gram, eigensolve, truncation (Def. 2.5) and lift run as
+ *            one launch sequence with nothing read back in between; outputs
+ *            and lift work lists are sized before the ranks are known (for
+ *            the node's rank in the previous run, else for m) and the lift's
+ *            tiles past the rank retire at once;
+ *   out3[1]  batches with the ranks read back before the lift (wide nodes on
+ *            Lanczos, right-vector runs, worst-case outputs above a quarter
+ *            of the free device memory, or HAPOD_HOST_LEVELS=1);
+ *   out3[2]  device-driven batches run again that way because a rank
+ *            outgrew the output sized for it (counted here, not in out3[0]). */
+hapod_status hapod_plan_batch_stats(hapod_plan_t plan, int64_t* out3);
+
 /* Device time in milliseconds of the phases of one level (1 = leaves) of the
  * last run, measured with HIP events on the run's stream around that level's
  * launches: {gram, eigensolve, truncate, lift}.  ms4: host, 4 doubles.      */

@@ -72,6 +72,7 @@ _SIGS = {
     "hapod_node_route": [_vp, _i32, _pi32],
     "hapod_plan_node_pod": [_vp, _i32, _vp, _i64, _i64, _vp, _i64, _pdbl, _pi64, _vp],
     "hapod_run_timing": [_vp, _pdbl],
+    "hapod_plan_batch_stats": [_vp, _pi64],
     "hapod_level_timing": [_vp, _i32, _pdbl],
 }
 for _name, _args in _SIGS.items():
@@ -449,6 +450,13 @@ class Plan:
         t = (C.c_double * 6)()
         _check(_lib.hapod_run_timing(self._h, t), "hapod_run_timing")
         return dict(zip(["total", "gram", "eig", "truncate", "lift", "reorth"], list(t)))
+
+    def batch_stats(self):
+        """Batches of the last run: device-driven, with ranks read back
+        before the lift, device-driven ones run again (hapod_plan_batch_stats)."""
+        t = (C.c_int64 * 3)()
+        _check(_lib.hapod_plan_batch_stats(self._h, t), "hapod_plan_batch_stats")
+        return dict(zip(["device", "host", "reruns"], list(t)))
 
 
 def hapod_plan(parent, leaf_cols, n, eps_star, omega, **kw) -> Plan:

@@ -296,10 +296,18 @@ struct PodJob {
   std::vector<double> s2;
   bool keep_v = false;      // copy V[:, :N] to a pool block of its own
   double* vkeep = nullptr;  // that block (m x N, ld m)
+  int64_t cap_hint = 0;     // the node's rank in the plan's previous run (0: none)
 };
 
 struct PhaseTimes {
   float gram = 0, eig = 0, trunc = 0, lift = 0;
+};
+
+// batches of the last run: device-driven (nothing back to the host between
+// the Gram and the lift), with the ranks read back before the lift, and
+// device-driven ones run again because a rank outgrew its output
+struct BatchStats {
+  int64_t device = 0, host = 0, reruns = 0;
 };
 
 struct Events {
@@ -451,9 +459,10 @@ constexpr int kAutoJacobiMin = 64;
 constexpr int kAutoJacobiMax = 256;
 constexpr int64_t kLiftTargetItems = 2048;  // lift workgroups per launch to aim for
 
-hapod_status run_pod_batch(hapod_precision prec, std::vector<PodJob>& jobs, int policy_small, int policy_wide,
-                           int jacobi_max, Pool& pool, hipStream_t stream, PhaseTimes* times,
-                           void** batch_block = nullptr, bool autotune = false) {
+hapod_status run_pod_batch_impl(hapod_precision prec, std::vector<PodJob>& jobs, int policy_small, int policy_wide,
+                                int jacobi_max, Pool& pool, hipStream_t stream, PhaseTimes* times,
+                                void** batch_block, bool autotune, bool allow_dev, bool* overflow,
+                                BatchStats* bstats) {
   const int compute = compute_mode(prec);
   const int eb = elem_bytes(prec);
   const int nj = (int)jobs.size();
@@ -469,13 +478,13 @@ hapod_status run_pod_batch(hapod_precision prec, std::vector<PodJob>& jobs, int 
   // ---- sizes & scratch layout ---------------------------------------------
   struct Lay {
     size_t cols, rbs, crows, cols2, rbs2, crows2, G, partial, lam, V, B, B32, Bs, sigma, rank, info, jwork, vwork,
-        sweeps;
+        sweeps, hh, hhdiag;
     bool presplit, own256;
     int tile, slots, ntiles, pairs, nchunks;
     int64_t chunk_rows;
   };
   std::vector<Lay> lay(nj);
-  size_t total = 0;
+  size_t total = 0, ttotal = 0;
   int total_pairs = 0;
   const int KB = (compute == 2) ? 32 : 16;
   // enough row chunks to give every CU several workgroups
@@ -531,15 +540,53 @@ hapod_status run_pod_batch(hapod_precision prec, std::vector<PodJob>& jobs, int 
   std::vector<size_t> twin_off(nj, 0);
   size_t arena_bytes = 0, group_fill = 0;
   int ngroups = 1;
+  for (auto& j : jobs) {
+    j.wide = (jacobi_max > 0) ? (j.m > jacobi_max) : (j.m > kAutoJacobiMin);
+    // a node taken from Jacobi only for speed keeps Jacobi's result: all
+    // eigenpairs (a complete tridiagonal reduction) and the same truncation
+    // policy
+    j.wide_full = j.wide && jacobi_max <= 0 && j.m <= kAutoJacobiMax;
+  }
+  // Device-driven batch: when every node's eigensolve runs without host
+  // steps (Jacobi, or the Householder reduction of a full run), nothing
+  // returns to the host between the Gram and the lift: outputs and lift
+  // work lists are sized for rank m (the lift's tiles past the rank the
+  // truncation writes retire at once) and the ranks come back with the other
+  // results at the end.  Not for right-vector runs (their copy of V is sized
+  // by the rank); HAPOD_HOST_LEVELS=1 keeps the rank readback.
+  static const bool host_levels = [] {
+    const char* e = std::getenv("HAPOD_HOST_LEVELS");
+    return e && e[0] == '1';
+  }();
+  bool dev = allow_dev && !host_levels && hh_available();
+  // output capacity of a batch-allocated node: its rank in the previous run
+  // (the layout of its output then matches a run that read the rank back),
+  // else m
+  std::vector<int64_t> cap(nj, 0);
+  size_t worst_out = 0;
+  for (int i = 0; i < nj; ++i) {
+    const PodJob& j = jobs[i];
+    if (j.keep_v || (j.m > 0 && j.wide && !(j.wide_full && j.m <= kHouseholderMaxM))) dev = false;
+    cap[i] = (j.cap_hint > 0 && j.cap_hint <= j.m) ? j.cap_hint : j.m;
+    if (!j.out && j.alloc_rows > 0 && j.m > 0)
+      worst_out += align_up(j.plain_out ? (size_t)j.alloc_rows * cap[i] * eb : tiled_bytes(j.n, cap[i], eb));
+  }
+  // the worst-case outputs must fit a quarter of what the device has free
+  // (and of what the plan's cap leaves); else the ranks come back first
+  if (dev && worst_out > 0) {
+    size_t free_b = 0, total_b = 0;
+    size_t room = pool.room();
+    if (hipMemGetInfo(&free_b, &total_b) == hipSuccess) {
+      const size_t avail = free_b + pool.cached();
+      room = std::min(room, avail > Pool::kReserve ? (avail - Pool::kReserve) / 4 : 0);
+    }
+    if (worst_out > room) dev = false;
+  }
+  if (bstats) ++(dev ? bstats->device : bstats->host);
   for (int i = 0; i < nj; ++i) {
     PodJob& j = jobs[i];
     Lay& L = lay[i];
     const int64_t m = j.m;
-    j.wide = (jacobi_max > 0) ? (m > jacobi_max) : (m > kAutoJacobiMin);
-    // a node taken from Jacobi only for speed keeps Jacobi's result: all
-    // eigenpairs (a complete tridiagonal reduction) and the same truncation
-    // policy
-    j.wide_full = j.wide && jacobi_max <= 0 && m <= kAutoJacobiMax;
     L.tile = tile_for_node(node_compute(m), j.n, m);
     // split-BF16: nodes with several column tiles get a split twin of their
     // input once, instead of splitting every element in each tile that reads
@@ -574,9 +621,16 @@ hapod_status run_pod_batch(hapod_precision prec, std::vector<PodJob>& jobs, int 
       total = align_up(total + bytes);
       return off;
     };
-    L.cols = take(sizeof(void*) * std::max<int64_t>(m, 1));
-    L.rbs = take(sizeof(int64_t) * std::max<int64_t>(m, 1));
-    L.crows = take(sizeof(int64_t) * std::max<int64_t>(m, 1));
+    // column tables: offsets inside the table region (placed after the rest,
+    // filled by one upload)
+    auto ttake = [&](size_t bytes) {
+      size_t off = ttotal;
+      ttotal = align_up(ttotal + bytes);
+      return off;
+    };
+    L.cols = ttake(sizeof(void*) * std::max<int64_t>(m, 1));
+    L.rbs = ttake(sizeof(int64_t) * std::max<int64_t>(m, 1));
+    L.crows = ttake(sizeof(int64_t) * std::max<int64_t>(m, 1));
     if (L.presplit) {
       const size_t tb = align_up(tiled_bytes(j.n, m, 4));
       if (group_fill + tb > twin_budget) {
@@ -588,9 +642,9 @@ hapod_status run_pod_batch(hapod_precision prec, std::vector<PodJob>& jobs, int 
       group_fill += tb;
       arena_bytes = std::max(arena_bytes, group_fill);
     }
-    L.cols2 = L.presplit ? take(sizeof(void*) * m) : 0;
-    L.rbs2 = L.presplit ? take(sizeof(int64_t) * m) : 0;
-    L.crows2 = L.presplit ? take(sizeof(int64_t) * m) : 0;
+    L.cols2 = L.presplit ? ttake(sizeof(void*) * m) : 0;
+    L.rbs2 = L.presplit ? ttake(sizeof(int64_t) * m) : 0;
+    L.crows2 = L.presplit ? ttake(sizeof(int64_t) * m) : 0;
     L.G = take(sizeof(double) * m * m);
     L.slots = L.nchunks * gram_slots_per_chunk(L.tile);
     L.partial = (L.slots > 1) ? take(sizeof(double) * (size_t)L.pairs * L.slots * L.tile * L.tile) : 0;
@@ -607,10 +661,28 @@ hapod_status run_pod_batch(hapod_precision prec, std::vector<PodJob>& jobs, int 
     L.jwork = (!j.wide && m > kJacobiLdsMax) ? take(sizeof(double) * jacobi_work_doubles((int)m)) : 0;
     L.vwork = (!j.wide) ? take(sizeof(double) * jacobi_vwork_doubles((int)std::max<int64_t>(m, 1))) : 0;
     L.sweeps = take(sizeof(int32_t) * 2);
+    // device-driven full runs: the Householder scratch, then trace, sum of
+    // eigenvalues and rounding level
+    L.hh = (dev && j.wide_full && m > 0) ? take(hh_scratch_bytes(m)) : 0;
+    L.hhdiag = (dev && j.wide_full && m > 0) ? take(sizeof(double) * 4) : 0;
     total_pairs += L.pairs;
   }
   const size_t flag_off = total;
   total = align_up(total + 64);
+  // the table region goes last
+  const size_t tbase = total;
+  total += ttotal;
+  for (int i = 0; i < nj; ++i) {
+    Lay& L = lay[i];
+    L.cols += tbase;
+    L.rbs += tbase;
+    L.crows += tbase;
+    if (L.presplit) {
+      L.cols2 += tbase;
+      L.rbs2 += tbase;
+      L.crows2 += tbase;
+    }
+  }
   char* scratch = nullptr;
   HAPOD_TRY(pool.alloc(total, (void**)&scratch));
   struct Guard {
@@ -772,14 +844,22 @@ hapod_status run_pod_batch(hapod_precision prec, std::vector<PodJob>& jobs, int 
   }
 
   Blob blob;
-  std::vector<size_t> col_off(nj), rbs_off(nj), rows_off(nj), col2_off(nj), rbs2_off(nj), rows2_off(nj);
+  // the column tables of every node, as one image of the table region
+  std::vector<char> timg(ttotal);
+  auto put = [&](size_t abs_off, const void* p, size_t bytes) {
+    if (bytes) std::memcpy(timg.data() + (abs_off - tbase), p, bytes);
+  };
   for (int i = 0; i < nj; ++i) {
-    col_off[i] = blob.add_vec(jobs[i].cols);
-    rbs_off[i] = blob.add_vec(jobs[i].rbs);
-    rows_off[i] = blob.add_vec(jobs[i].crows);
-    col2_off[i] = blob.add_vec(cols2[i]);
-    rbs2_off[i] = blob.add_vec(rbs2[i]);
-    rows2_off[i] = blob.add_vec(crows2[i]);
+    const size_t m = (size_t)jobs[i].m;
+    if (m == 0) continue;
+    put(lay[i].cols, jobs[i].cols.data(), sizeof(void*) * m);
+    put(lay[i].rbs, jobs[i].rbs.data(), sizeof(int64_t) * m);
+    put(lay[i].crows, jobs[i].crows.data(), sizeof(int64_t) * m);
+    if (lay[i].presplit) {
+      put(lay[i].cols2, cols2[i].data(), sizeof(void*) * m);
+      put(lay[i].rbs2, rbs2[i].data(), sizeof(int64_t) * m);
+      put(lay[i].crows2, crows2[i].data(), sizeof(int64_t) * m);
+    }
   }
   // Launches whose nodes each have one tile pair (no column blocks to share
   // in L2, so the super-tile order does not matter): nodes of very different
@@ -823,9 +903,132 @@ hapod_status run_pod_batch(hapod_precision prec, std::vector<PodJob>& jobs, int 
                                          t >= 8 ? 1 : -1});
       gitems.insert(gitems.end(), v.begin(), v.end());
     }
+  // device-driven full runs: descriptors of the Householder eigensolve and
+  // of its back-transformation; the truncation reads their rounding level
+  std::vector<char> hh_img;
+  std::vector<LiftNode> hh_lift;
+  std::vector<int> hh_idx;
+  int64_t hh_mmax = 0;
+  int hh_items = 0;
+  if (dev)
+    for (int i = 0; i < nj; ++i) {
+      if (!jobs[i].wide_full || jobs[i].m <= 0) continue;
+      const int64_t m = jobs[i].m;
+      const size_t nb = hh_node_bytes();
+      hh_img.resize(hh_img.size() + nb);
+      double* diag = (double*)(scratch + lay[i].hhdiag);
+      LiftNode l{};
+      hh_describe(m, gnodes[i].G, m, (double*)(scratch + lay[i].lam), (double*)(scratch + lay[i].V), m,
+                  scratch + lay[i].hh, u_p, diag + 2, diag, hh_img.data() + hh_idx.size() * nb, &l);
+      l.item_base = hh_items;
+      hh_items += l.row_tiles * l.col_tiles;
+      hh_lift.push_back(l);
+      hh_idx.push_back(i);
+      hh_mmax = std::max(hh_mmax, m);
+      tnodes[i].floor_ptr = diag + 2;
+    }
+  // outputs sized by the ranks (worst case m in a device-driven batch),
+  // carved from one block for the batch (one allocation instead of one per
+  // node; the caller frees the block once every node in it has been
+  // consumed), and the lift work lists: nodes of rank <= 64 take the narrow
+  // lift (256 x 64 tiles), the others 128 x 128 tiles, each kind one launch
+  std::vector<LiftNode> lnodes[2];
+  int lift_items[2] = {0, 0};
+  char* out_block_mine = nullptr;
+  auto build_lifts = [&](const std::vector<int64_t>& ranks, bool worst) -> hapod_status {
+    std::vector<size_t> out_off(nj, 0);
+    size_t out_total = 0;
+    for (int i = 0; i < nj; ++i) {
+      const PodJob& j = jobs[i];
+      if (j.out || j.alloc_rows <= 0 || j.m <= 0 || ranks[i] <= 0) continue;
+      out_off[i] = out_total;
+      out_total = align_up(out_total + (j.plain_out ? (size_t)j.alloc_rows * ranks[i] * eb
+                                                    : tiled_bytes(j.n, ranks[i], eb)));
+    }
+    char* out_block = nullptr;
+    if (out_total > 0) {
+      HAPOD_TRY(pool.alloc(out_total, (void**)&out_block));
+      out_block_mine = out_block;
+      if (batch_block) *batch_block = out_block;
+    }
+    for (int i = 0; i < nj; ++i) {
+      PodJob& j = jobs[i];
+      if (j.out || j.alloc_rows <= 0 || j.m <= 0 || ranks[i] <= 0) continue;
+      const int64_t N = ranks[i];
+      const size_t bytes = j.plain_out ? (size_t)j.alloc_rows * N * eb : tiled_bytes(j.n, N, eb);
+      j.out = out_block + out_off[i];
+      if (j.plain_out) {
+        j.ocs = j.alloc_rows;
+        j.obs = kRowBlock;
+        if (j.n < j.alloc_rows) HAPOD_TRY(launch_zero_bytes(j.out, bytes, stream));
+      } else {
+        j.ocs = kRowBlock;
+        j.obs = tiled_rbs(N);
+      }
+    }
+    // several row tiles per workgroup when there are many: the column table
+    // and the node lookup are then paid once per group of tiles (sized for
+    // one column tile per node when the ranks are worst cases: the items of
+    // column tiles past the rank retire at once and must not thin out the
+    // rest)
+    int64_t lift_tiles = 0;
+    for (int i = 0; i < nj; ++i)
+      if (jobs[i].m > 0 && jobs[i].n > 0 && ranks[i] > 0) {
+        const bool nar = ranks[i] <= kLiftTileN / 2;
+        const int64_t tm = nar ? kLiftNarrowM : kLiftTileM, tn = nar ? kLiftTileN / 2 : kLiftTileN;
+        lift_tiles += ((jobs[i].n + tm - 1) / tm) * (worst ? 1 : (ranks[i] + tn - 1) / tn);
+      }
+    const int rt_per = (int)std::max<int64_t>(1, std::min<int64_t>(16, lift_tiles / kLiftTargetItems));
+    for (int i = 0; i < nj; ++i) {
+      const PodJob& j = jobs[i];
+      if (j.m <= 0 || j.n <= 0 || ranks[i] <= 0) continue;
+      const int nar = ranks[i] <= kLiftTileN / 2 ? 1 : 0;
+      const int64_t tm = nar ? kLiftNarrowM : kLiftTileM, tn = nar ? kLiftTileN / 2 : kLiftTileN;
+      LiftNode l{};
+      l.cols = (const void* const*)(scratch + lay[i].cols);
+      l.rbs = (const int64_t*)(scratch + lay[i].rbs);
+      l.crows = (const int64_t*)(scratch + lay[i].crows);
+      l.B = tnodes[i].B;
+      l.B32 = tnodes[i].B32;
+      l.Bs = lay[i].Bs ? (char*)(scratch + lay[i].Bs) : nullptr;
+      l.rank = tnodes[i].rank;
+      l.out = j.out;
+      l.n = j.n;
+      l.ldb = tnodes[i].ldb;
+      l.ocs = j.ocs;
+      l.obs = j.obs;
+      l.m = (int32_t)j.m;
+      l.row_tiles = (int32_t)((j.n + tm - 1) / tm);
+      l.col_tiles = (int32_t)((ranks[i] + tn - 1) / tn);
+      l.item_base = lift_items[nar];
+      l.rt_per = rt_per;
+      lift_items[nar] += ((l.row_tiles + rt_per - 1) / rt_per) * l.col_tiles;
+      lnodes[nar].push_back(l);
+    }
+    return HAPOD_OK;
+  };
+  // (caller-provided outputs hold m columns: capacity m, no cap)
+  std::vector<char> capped(nj, 0);
+  if (dev) {
+    std::vector<int64_t> worst(nj);
+    for (int i = 0; i < nj; ++i) {
+      capped[i] = !jobs[i].out && jobs[i].alloc_rows > 0;
+      worst[i] = capped[i] ? cap[i] : jobs[i].m;
+    }
+    HAPOD_TRY(build_lifts(worst, true));
+    for (int k = 0; k < 2; ++k)
+      for (LiftNode& l : lnodes[k]) {
+        int i = 0;
+        while (i < nj && tnodes[i].rank != l.rank) ++i;
+        if (i < nj && capped[i]) l.ncap = cap[i];
+      }
+  }
+  std::vector<LiftNode> lall(lnodes[0]);
+  lall.insert(lall.end(), lnodes[1].begin(), lnodes[1].end());
   const size_t o_g = blob.add_vec(gnodes), o_gi = blob.add_vec(gitems), o_rp = blob.add_vec(rpairs),
                o_rn = blob.add_vec(rnode), o_es = blob.add_vec(enodes_small), o_eb = blob.add_vec(enodes_big),
-               o_t = blob.add_vec(tnodes), o_fill = blob.add_vec(fills), o_s2 = blob.add_vec(s2_all);
+               o_t = blob.add_vec(tnodes), o_fill = blob.add_vec(fills), o_s2 = blob.add_vec(s2_all),
+               o_hh = blob.add_vec(hh_img), o_hhl = blob.add_vec(hh_lift), o_l = blob.add_vec(lall);
   char* dblob = nullptr;
   HAPOD_TRY(pool.alloc(blob.host.size(), (void**)&dblob));
   struct Guard2 {
@@ -834,25 +1037,10 @@ hapod_status run_pod_batch(hapod_precision prec, std::vector<PodJob>& jobs, int 
     ~Guard2() { p.free(s); }
   } guard2{pool, dblob};
   HAPOD_HIP(hipMemcpyAsync(dblob, blob.host.data(), blob.host.size(), hipMemcpyHostToDevice, stream));
-  for (int i = 0; i < nj; ++i)
-    if (jobs[i].m > 0) {
-      HAPOD_HIP(hipMemcpyAsync(scratch + lay[i].cols, dblob + col_off[i], sizeof(void*) * jobs[i].m,
-                               hipMemcpyDeviceToDevice, stream));
-      HAPOD_HIP(hipMemcpyAsync(scratch + lay[i].rbs, dblob + rbs_off[i], sizeof(int64_t) * jobs[i].m,
-                               hipMemcpyDeviceToDevice, stream));
-      HAPOD_HIP(hipMemcpyAsync(scratch + lay[i].crows, dblob + rows_off[i], sizeof(int64_t) * jobs[i].m,
-                               hipMemcpyDeviceToDevice, stream));
-      if (lay[i].presplit) {
-        HAPOD_HIP(hipMemcpyAsync(scratch + lay[i].crows2, dblob + rows2_off[i], sizeof(int64_t) * jobs[i].m,
-                                 hipMemcpyDeviceToDevice, stream));
-        HAPOD_HIP(hipMemcpyAsync(scratch + lay[i].cols2, dblob + col2_off[i], sizeof(void*) * jobs[i].m,
-                                 hipMemcpyDeviceToDevice, stream));
-        HAPOD_HIP(hipMemcpyAsync(scratch + lay[i].rbs2, dblob + rbs2_off[i], sizeof(int64_t) * jobs[i].m,
-                                 hipMemcpyDeviceToDevice, stream));
-      }
-    }
+  if (ttotal > 0)
+    HAPOD_HIP(hipMemcpyAsync(scratch + tbase, timg.data(), ttotal, hipMemcpyHostToDevice, stream));
   int32_t* d_flag = (int32_t*)(scratch + flag_off);
-  HAPOD_HIP(hipMemsetAsync(d_flag, 0, 64, stream));
+  HAPOD_TRY(launch_zero_bytes(d_flag, 64, stream));
 
   Events ev;
   if (times && ev.ok) HAPOD_HIP(hipEventRecord(ev.e[0], stream));
@@ -878,9 +1066,13 @@ hapod_status run_pod_batch(hapod_precision prec, std::vector<PodJob>& jobs, int 
     HAPOD_TRY(launch_jacobi((const EigNode*)(dblob + o_es), (int)enodes_small.size(), max_small, stream));
   if (!enodes_big.empty())
     HAPOD_TRY(launch_jacobi((const EigNode*)(dblob + o_eb), (int)enodes_big.size(), max_big, stream));
-  // wide nodes: one batched Krylov eigensolve for all of them
+  // wide nodes: one batched Krylov eigensolve for all of them (device-driven
+  // batch: the Householder full runs, launched with no host step)
   std::vector<WideResult> wres(nj);
-  {
+  if (dev) {
+    HAPOD_TRY(hh_launch(dblob + o_hh, (int)hh_idx.size(), hh_mmax, (const LiftNode*)(dblob + o_hhl), hh_items,
+                        stream));
+  } else {
     std::vector<WideJob> wj;
     for (int i = 0; i < nj; ++i) {
       if (!jobs[i].wide || jobs[i].m <= 0) continue;
@@ -890,7 +1082,7 @@ hapod_status run_pod_batch(hapod_precision prec, std::vector<PodJob>& jobs, int 
     if (!wj.empty()) HAPOD_TRY(wide_eigh_batch(wj, u_p, &pool_alloc_cb, &pool_free_cb, &pool, stream));
   }
   for (int i = 0; i < nj; ++i) {
-    if (!jobs[i].wide || jobs[i].m <= 0) continue;
+    if (dev || !jobs[i].wide || jobs[i].m <= 0) continue;
     const WideResult& wr = wres[i];
     // eigenvalues beyond the computed block are set to zero by wide_eigh;
     // the floor of the truncation is the Gram's rounding level
@@ -947,7 +1139,7 @@ hapod_status run_pod_batch(hapod_precision prec, std::vector<PodJob>& jobs, int 
   // wide nodes changed floor_abs on the host: refresh the descriptors (one
   // copy through pinned staging)
   bool any_wide = false;
-  for (int i = 0; i < nj; ++i) any_wide |= jobs[i].wide;
+  for (int i = 0; i < nj; ++i) any_wide |= jobs[i].wide && !dev;
   char* pin = pool.pinned(std::max(sizeof(TruncNode), sizeof(int64_t)) * (size_t)nj);
   if (!pin) {
     set_error("hipHostMalloc of the descriptor staging failed");
@@ -960,109 +1152,47 @@ hapod_status run_pod_batch(hapod_precision prec, std::vector<PodJob>& jobs, int 
   // ---- truncation -----------------------------------------------------------
   HAPOD_TRY(launch_truncate((const TruncNode*)(dblob + o_t), nj, stream));
   if (times && ev.ok) HAPOD_HIP(hipEventRecord(ev.e[3], stream));
-  // ---- lift, sized by the ranks just computed ---------------------------------
+  // ---- lift, sized by the ranks just computed (device-driven batch: by the
+  // worst case, built before the launches) ----------------------------------
   // (the ranks come back through the same staging: stream order puts these
   // copies after the descriptor upload that read it)
-  std::vector<int64_t> ranks(nj, 0);
-  for (int i = 0; i < nj; ++i)
-    HAPOD_HIP(hipMemcpyAsync(pin + i * sizeof(int64_t), scratch + lay[i].rank, sizeof(int64_t),
-                             hipMemcpyDeviceToHost, stream));
-  HAPOD_HIP(hipStreamSynchronize(stream));
-  std::memcpy(ranks.data(), pin, sizeof(int64_t) * nj);
-  // right singular vectors kept for the factorisation of the snapshot map:
-  // the first N eigenvectors (columns of V, ld m) are contiguous
-  for (int i = 0; i < nj; ++i) {
-    PodJob& j = jobs[i];
-    if (!j.keep_v || ranks[i] <= 0 || j.m <= 0) continue;
-    const size_t bytes = sizeof(double) * (size_t)j.m * ranks[i];
-    HAPOD_TRY(pool.alloc(bytes, (void**)&j.vkeep));
-    HAPOD_HIP(hipMemcpyAsync(j.vkeep, scratch + lay[i].V, bytes, hipMemcpyDeviceToDevice, stream));
-  }
-  // outputs sized by the ranks, carved from one block for the batch (one
-  // allocation instead of one per node; the caller frees the block once
-  // every node in it has been consumed)
-  std::vector<size_t> out_off(nj, 0);
-  size_t out_total = 0;
-  for (int i = 0; i < nj; ++i) {
-    const PodJob& j = jobs[i];
-    if (j.out || j.alloc_rows <= 0 || j.m <= 0 || ranks[i] <= 0) continue;
-    out_off[i] = out_total;
-    out_total = align_up(out_total + (j.plain_out ? (size_t)j.alloc_rows * ranks[i] * eb
-                                                  : tiled_bytes(j.n, ranks[i], eb)));
-  }
-  char* out_block = nullptr;
-  if (out_total > 0) {
-    HAPOD_TRY(pool.alloc(out_total, (void**)&out_block));
-    if (batch_block) *batch_block = out_block;
-  }
-  for (int i = 0; i < nj; ++i) {
-    PodJob& j = jobs[i];
-    if (j.out || j.alloc_rows <= 0 || j.m <= 0 || ranks[i] <= 0) continue;
-    const int64_t N = ranks[i];
-    const size_t bytes = j.plain_out ? (size_t)j.alloc_rows * N * eb : tiled_bytes(j.n, N, eb);
-    j.out = out_block + out_off[i];
-    if (j.plain_out) {
-      j.ocs = j.alloc_rows;
-      j.obs = kRowBlock;
-      if (j.n < j.alloc_rows) HAPOD_TRY(launch_zero_bytes(j.out, bytes, stream));
-    } else {
-      j.ocs = kRowBlock;
-      j.obs = tiled_rbs(N);
-    }
-  }
-  // nodes of rank <= 64 take the narrow lift (256 x 64 tiles), the others
-  // 128 x 128 tiles; each kind is one launch
-  std::vector<LiftNode> lnodes[2];
-  int lift_items[2] = {0, 0};
-  // several row tiles per workgroup when there are many: the column table
-  // and the node lookup are then paid once per group of tiles
-  int64_t lift_tiles = 0;
-  for (int i = 0; i < nj; ++i)
-    if (jobs[i].m > 0 && jobs[i].n > 0 && ranks[i] > 0) {
-      const bool nar = ranks[i] <= kLiftTileN / 2;
-      const int64_t tm = nar ? kLiftNarrowM : kLiftTileM, tn = nar ? kLiftTileN / 2 : kLiftTileN;
-      lift_tiles += ((jobs[i].n + tm - 1) / tm) * ((ranks[i] + tn - 1) / tn);
-    }
-  const int rt_per = (int)std::max<int64_t>(1, std::min<int64_t>(16, lift_tiles / kLiftTargetItems));
-  for (int i = 0; i < nj; ++i) {
-    const PodJob& j = jobs[i];
-    if (j.m <= 0 || j.n <= 0 || ranks[i] <= 0) continue;
-    const int nar = ranks[i] <= kLiftTileN / 2 ? 1 : 0;
-    const int64_t tm = nar ? kLiftNarrowM : kLiftTileM, tn = nar ? kLiftTileN / 2 : kLiftTileN;
-    LiftNode l{};
-    l.cols = (const void* const*)(scratch + lay[i].cols);
-    l.rbs = (const int64_t*)(scratch + lay[i].rbs);
-    l.crows = (const int64_t*)(scratch + lay[i].crows);
-    l.B = tnodes[i].B;
-    l.B32 = tnodes[i].B32;
-    l.Bs = lay[i].Bs ? (char*)(scratch + lay[i].Bs) : nullptr;
-    l.rank = tnodes[i].rank;
-    l.out = j.out;
-    l.n = j.n;
-    l.ldb = tnodes[i].ldb;
-    l.ocs = j.ocs;
-    l.obs = j.obs;
-    l.m = (int32_t)j.m;
-    l.row_tiles = (int32_t)((j.n + tm - 1) / tm);
-    l.col_tiles = (int32_t)((ranks[i] + tn - 1) / tn);
-    l.item_base = lift_items[nar];
-    l.rt_per = rt_per;
-    lift_items[nar] += ((l.row_tiles + rt_per - 1) / rt_per) * l.col_tiles;
-    lnodes[nar].push_back(l);
-  }
   char* dlift = nullptr;
-  const size_t nl0 = lnodes[0].size(), nl1 = lnodes[1].size();
-  if (nl0 + nl1 > 0) {
-    std::vector<LiftNode> all(lnodes[0]);
-    all.insert(all.end(), lnodes[1].begin(), lnodes[1].end());
-    HAPOD_TRY(pool.alloc(sizeof(LiftNode) * all.size(), (void**)&dlift));
-    HAPOD_HIP(hipMemcpy(dlift, all.data(), sizeof(LiftNode) * all.size(), hipMemcpyHostToDevice));
+  bool dlift_owned = false;
+  if (dev) {
+    dlift = dblob + o_l;
+  } else {
+    std::vector<int64_t> ranks(nj, 0);
+    for (int i = 0; i < nj; ++i)
+      HAPOD_HIP(hipMemcpyAsync(pin + i * sizeof(int64_t), scratch + lay[i].rank, sizeof(int64_t),
+                               hipMemcpyDeviceToHost, stream));
+    HAPOD_HIP(hipStreamSynchronize(stream));
+    std::memcpy(ranks.data(), pin, sizeof(int64_t) * nj);
+    // right singular vectors kept for the factorisation of the snapshot map:
+    // the first N eigenvectors (columns of V, ld m) are contiguous
+    for (int i = 0; i < nj; ++i) {
+      PodJob& j = jobs[i];
+      if (!j.keep_v || ranks[i] <= 0 || j.m <= 0) continue;
+      const size_t bytes = sizeof(double) * (size_t)j.m * ranks[i];
+      HAPOD_TRY(pool.alloc(bytes, (void**)&j.vkeep));
+      HAPOD_HIP(hipMemcpyAsync(j.vkeep, scratch + lay[i].V, bytes, hipMemcpyDeviceToDevice, stream));
+    }
+    HAPOD_TRY(build_lifts(ranks, false));
+    if (!lnodes[0].empty() || !lnodes[1].empty()) {
+      std::vector<LiftNode> all(lnodes[0]);
+      all.insert(all.end(), lnodes[1].begin(), lnodes[1].end());
+      HAPOD_TRY(pool.alloc(sizeof(LiftNode) * all.size(), (void**)&dlift));
+      dlift_owned = true;
+      HAPOD_HIP(hipMemcpy(dlift, all.data(), sizeof(LiftNode) * all.size(), hipMemcpyHostToDevice));
+    }
   }
+  const size_t nl0 = lnodes[0].size(), nl1 = lnodes[1].size();
   struct Guard3 {
     Pool& p;
     void* s;
-    ~Guard3() { p.free(s); }
-  } guard3{pool, dlift};
+    ~Guard3() {
+      if (s) p.free(s);
+    }
+  } guard3{pool, dlift_owned ? dlift : nullptr};
   if (times && ev.ok) HAPOD_HIP(hipEventRecord(ev.e[3], stream));
   // the split-BF16 form lifts with three BF16 products per term: a lift of
   // N output columns does 2 N flops per 4 input bytes, above the FP32 MFMA
@@ -1091,6 +1221,18 @@ hapod_status run_pod_batch(hapod_precision prec, std::vector<PodJob>& jobs, int 
     PodJob& j = jobs[i];
     HAPOD_HIP(hipMemcpy(&j.rank, scratch + lay[i].rank, sizeof(int64_t), hipMemcpyDeviceToHost));
     HAPOD_HIP(hipMemcpy(j.info, scratch + lay[i].info, sizeof(double) * 6, hipMemcpyDeviceToHost));
+    if (dev && j.wide && j.m > 0) {
+      // the device-driven full run: every eigenpair (as a complete Krylov
+      // run reports it), the trace check from its finishing kernel
+      double dg[3] = {0, 0, 0};
+      HAPOD_HIP(hipMemcpy(dg, scratch + lay[i].hhdiag, sizeof(dg), hipMemcpyDeviceToHost));
+      j.sweeps = (int32_t)j.m;
+      j.wide_exhausted = true;
+      j.wide_missing = 0.0;
+      j.wide_noise_room = 0.0;
+      j.wide_unresolved = std::max(0.0, dg[0] - dg[1]);
+      j.wide_slack = 16.0 * ((double)j.m + std::sqrt((double)j.m)) * u_p * std::fabs(dg[0]);
+    }
     j.sigma.assign((size_t)j.rank, 0.0);
     if (j.rank > 0)
       HAPOD_HIP(hipMemcpy(j.sigma.data(), scratch + lay[i].sigma, sizeof(double) * j.rank, hipMemcpyDeviceToHost));
@@ -1106,6 +1248,19 @@ hapod_status run_pod_batch(hapod_precision prec, std::vector<PodJob>& jobs, int 
       return HAPOD_E_UNSUPPORTED;
     }
   }
+  if (dev && overflow) {
+    // a rank above its output's capacity: the lift stopped at the capacity;
+    // the batch runs again with the ranks read back first
+    bool over = false;
+    for (int i = 0; i < nj; ++i) over = over || (capped[i] && jobs[i].rank > cap[i]);
+    if (over) {
+      for (int i = 0; i < nj; ++i)
+        if (capped[i]) jobs[i].out = nullptr;
+      if (out_block_mine) pool.free(out_block_mine);
+      if (batch_block) *batch_block = nullptr;
+      *overflow = true;
+    }
+  }
   if (times && ev.ok) {
     float a = 0;
     if (hipEventElapsedTime(&a, ev.e[0], ev.e[1]) == hipSuccess) times->gram += a;
@@ -1116,6 +1271,26 @@ hapod_status run_pod_batch(hapod_precision prec, std::vector<PodJob>& jobs, int 
   return HAPOD_OK;
 }
 
+
+// A device-driven batch sizes each batch-allocated output for the rank the
+// node had in the plan's previous run (else for m); if a rank came out
+// larger, the batch runs again with the ranks read back before the lift.
+hapod_status run_pod_batch(hapod_precision prec, std::vector<PodJob>& jobs, int policy_small, int policy_wide,
+                           int jacobi_max, Pool& pool, hipStream_t stream, PhaseTimes* times,
+                           void** batch_block = nullptr, bool autotune = false, BatchStats* bstats = nullptr) {
+  bool overflow = false;
+  hapod_status st = run_pod_batch_impl(prec, jobs, policy_small, policy_wide, jacobi_max, pool, stream, times,
+                                       batch_block, autotune, true, &overflow, bstats);
+  if (st != HAPOD_OK || !overflow) return st;
+  if (bstats) {
+    --bstats->device;
+    ++bstats->reruns;
+  }
+  st = run_pod_batch_impl(prec, jobs, policy_small, policy_wide, jacobi_max, pool, stream, times, batch_block, false,
+                          false, &overflow, bstats);
+  if (bstats) --bstats->host;  // counted as a rerun only
+  return st;
+}
 
 hapod_status check_prec(hapod_precision p) {
   if (p != HAPOD_FP64 && p != HAPOD_FP32 && p != HAPOD_BF16X3) {
@@ -1176,6 +1351,8 @@ struct hapod_plan_s {
   // last run
   bool has_result = false;
   std::vector<int64_t> rank, m_in, n_neg;
+  std::vector<int64_t> rank_hint;  // ranks of the previous run (device-driven output capacity)
+  BatchStats bstats;               // batches of the last run
   std::vector<double> lam1, lam_min;
   std::vector<std::vector<double>> sigma;
   void* root_U = nullptr;  // owned by the pool
@@ -2271,6 +2448,9 @@ hapod_status hapod_run(hapod_plan_t P, hapod_leaf_fn get_leaf, void* user, void*
     P->root_U = nullptr;
   }
   P->root_passthrough = false;
+  // the previous run's ranks size the next run's device-driven outputs
+  if (P->rank.size() == (size_t)nn) P->rank_hint = P->rank;
+  P->bstats = BatchStats{};
   P->rank.assign(nn, 0);
   P->m_in.assign(nn, 0);
   P->n_neg.assign(nn, 0);
@@ -2564,6 +2744,7 @@ hapod_status hapod_run(hapod_plan_t P, hapod_leaf_fn get_leaf, void* user, void*
           }
         }
         j.keep_v = P->opts.right_vectors != 0;
+        j.cap_hint = (size_t)a < P->rank_hint.size() ? P->rank_hint[a] : 0;
         j.cols = std::move(in);
         j.rbs = std::move(in_rbs);
         j.crows = std::move(in_rows);
@@ -2631,7 +2812,7 @@ hapod_status hapod_run(hapod_plan_t P, hapod_leaf_fn get_leaf, void* user, void*
       void* blk = nullptr;
       hapod_status s = jobs.empty() ? HAPOD_OK
                                     : run_pod_batch(prec, jobs, 0, 1, jmax, P->pool, stream, &lt, &blk,
-                                                    P->opts.autotune != 0);
+                                                    P->opts.autotune != 0, &P->bstats);
       if (s != HAPOD_OK) {
         (void)hipStreamSynchronize(stream);
         if (blk) P->pool.free(blk);
@@ -2662,7 +2843,7 @@ hapod_status hapod_run(hapod_plan_t P, hapod_leaf_fn get_leaf, void* user, void*
           out_rows[a].assign((size_t)j.rank, P->n);
         } else {
           out_cols[a] = tiled_table(j.out, j.rank, eb);
-          out_rbs[a].assign((size_t)j.rank, tiled_rbs(j.rank));
+          out_rbs[a].assign((size_t)j.rank, j.obs);
           out_rows[a].assign((size_t)j.rank, j.n);
         }
         if (j.rank == 0 && out_buf[a]) release(a);
@@ -2825,6 +3006,17 @@ hapod_status hapod_node_stats(hapod_plan_t P, int64_t* m_in, int64_t* n_negative
   if (n_negative) std::memcpy(n_negative, P->n_neg.data(), nn * sizeof(int64_t));
   if (lambda1) std::memcpy(lambda1, P->lam1.data(), nn * sizeof(double));
   if (lambda_min) std::memcpy(lambda_min, P->lam_min.data(), nn * sizeof(double));
+  return HAPOD_OK;
+}
+
+hapod_status hapod_plan_batch_stats(hapod_plan_t P, int64_t* out3) {
+  if (!P || !out3) {
+    set_error("hapod_plan_batch_stats: NULL argument");
+    return HAPOD_E_INVALID;
+  }
+  out3[0] = P->bstats.device;
+  out3[1] = P->bstats.host;
+  out3[2] = P->bstats.reruns;
   return HAPOD_OK;
 }
 

@@ -184,6 +184,8 @@ struct TruncNode {
   int32_t policy;
   int32_t root;           // 1: B = V Lambda^{-1/2}, else B = V
   int32_t pad;
+  const double* floor_ptr;  // non-null: floor_abs is read from here (written
+                            // on the device by the eigensolve)
 };
 hapod_status launch_truncate(const TruncNode* d_nodes, int num_nodes, hipStream_t stream);
 // B[k * ldb + n] = V[k][n] (lambda == nullptr) or V[k][n] / sqrt(lambda[n]);
@@ -233,6 +235,10 @@ struct LiftNode {
   // Bs + (c * ceil(m / 32) + s) * 128, the 32 hi then the 32 lo values.
   // Written from B32 by launch_split_operand; room for m columns (N <= m).
   char* Bs;
+  // > 0: the output holds only this many columns; columns past it are not
+  // written (a device-driven batch sized the output before the rank was
+  // known and checks the rank afterwards)
+  int64_t ncap;
 };
 // compute: 0 FP64 MFMA, 1 FP32 MFMA, 2 split-BF16 (three BF16 products per
 // term on BF16 MFMA, FP32 accumulation; reads Bs); output storage = input

@@ -84,7 +84,7 @@ __global__ __launch_bounds__(256) void lift_kernel(const LiftNode* __restrict__ 
   // and share that stripe of S through its L2
   const int local = item - nd.item_base;
   const int rg = local / nd.col_tiles, ct = local % nd.col_tiles;
-  const int64_t N = *nd.rank;
+  const int64_t N = (nd.ncap > 0) ? min(*nd.rank, nd.ncap) : *nd.rank;
   if ((int64_t)ct * TNk >= N) return;  // whole workgroup
   const int rt_per = max(nd.rt_per, 1);
   const int rt_begin = rg * rt_per, rt_end = min(rt_begin + rt_per, nd.row_tiles);
@@ -336,7 +336,7 @@ __global__ __launch_bounds__(256, 2) void lift_staged_kernel(const LiftNode* __r
   const LiftNode nd = nodes[lo];
   const int local = item - nd.item_base;
   const int rg = local / nd.col_tiles, ct = local % nd.col_tiles;
-  const int64_t N = *nd.rank;
+  const int64_t N = (nd.ncap > 0) ? min(*nd.rank, nd.ncap) : *nd.rank;
   if ((int64_t)ct * TNk >= N) return;  // whole workgroup
   const int rt_per = max(nd.rt_per, 1);
   const int rt_begin = rg * rt_per, rt_end = min(rt_begin + rt_per, nd.row_tiles);
@@ -572,7 +572,7 @@ __global__ __launch_bounds__(256, 2) void lift_bf16_kernel(const LiftNode* __res
   const LiftNode nd = nodes[lo];
   const int local = item - nd.item_base;
   const int rg = local / nd.col_tiles, ct = local % nd.col_tiles;
-  const int64_t N = *nd.rank;
+  const int64_t N = (nd.ncap > 0) ? min(*nd.rank, nd.ncap) : *nd.rank;
   if ((int64_t)ct * TNk >= N) return;  // whole workgroup
   const int rt_per = max(nd.rt_per, 1);
   const int rt_begin = rg * rt_per, rt_end = min(rt_begin + rt_per, nd.row_tiles);
@@ -738,7 +738,7 @@ __global__ __launch_bounds__(256) void split_operand_kernel(const LiftNode* __re
   const LiftNode nd = nodes[blockIdx.z];
   const int m = nd.m;
   const int nks = (m + 31) / 32;
-  const int64_t N = *nd.rank;
+  const int64_t N = (nd.ncap > 0) ? min(*nd.rank, nd.ncap) : *nd.rank;
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= N * nks) return;
   const int s = (int)(e / N);

@@ -116,7 +116,7 @@ __global__ __launch_bounds__(kThreads) void truncate_kernel(const TruncNode* __r
   double nneg = 0.0;
   for (int i = tid; i < m; i += kThreads) nneg += (nd.lambda[i] < 0.0) ? 1.0 : 0.0;
   nneg = block_sum_double(nneg, shd);
-  const double theta = fmax(fmax(-lmin, nd.floor_abs), 0.0);
+  const double theta = fmax(fmax(-lmin, nd.floor_ptr ? *nd.floor_ptr : nd.floor_abs), 0.0);
 
   double tail_clamp = 0.0, tail_pol = 0.0;
   const int N_clamp = rank_for(nd.lambda, m, 0, 0.0, nd.eps2, shd, shi, &tail_clamp);

@@ -39,6 +39,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
+#include <cstring>
 #include <vector>
 
 #include "mfma.hpp"
@@ -97,6 +98,15 @@ struct LzNode {
   unsigned* bar;   // cooperative kernel: barrier counter (zeroed per launch)
   int64_t xlen;
   double* Z2;      // k x k: the eigenvectors between the two orthogonalisation sweeps
+  // device-only full runs (hh_launch): the rounding level and the trace
+  // check go to these, and the back-transformation's column table lives here
+  double* floor_out;
+  double* diag_out;
+  double u_p;
+  const void** qcols;
+  int64_t* qrbs;
+  int64_t* qrows;
+  int64_t* qrank;
 };
 
 // q = random, unnormalised (normalised by the finish kernel)
@@ -977,7 +987,7 @@ constexpr int kHhGroups = kHhThreads / kHhRowPairs;  // column groups
 
 __global__ __launch_bounds__(kHhThreads) void tridiag_kernel(const LzNode* __restrict__ nodes,
                                                              const int* __restrict__ list) {
-  const LzNode n = nodes[list[blockIdx.x]];
+  const LzNode n = nodes[list ? list[blockIdx.x] : blockIdx.x];
   const int m = (int)n.m;
   const int lda = m + (m & 1);
   double* A = n.Z2;
@@ -1101,7 +1111,7 @@ __global__ __launch_bounds__(kHhThreads) void tridiag_kernel(const LzNode* __res
 // highest index first.
 constexpr int kFqChunk = 64;
 __global__ __launch_bounds__(1024) void formq_kernel(const LzNode* __restrict__ nodes, const int* __restrict__ list) {
-  const LzNode n = nodes[list[blockIdx.z]];
+  const LzNode n = nodes[list ? list[blockIdx.z] : blockIdx.z];
   const int m = (int)n.m;
   const int lda = m + (m & 1);
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
@@ -1186,7 +1196,144 @@ __global__ void write_lambda_kernel(const LzNode* __restrict__ nodes) {
 
 size_t al(size_t x) { return (x + 255) / 256 * 256; }
 
+// the rounding level and the trace check of a device-only full run; the
+// column table of Q and the lift's rank for the back-transformation
+__global__ __launch_bounds__(256) void hh_finish_kernel(const LzNode* __restrict__ nodes) {
+  const LzNode n = nodes[blockIdx.x];
+  const int k = n.kk;
+  __shared__ double part[4];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < k; i += blockDim.x) s += n.theta[i];
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double tr = *n.tr;
+    const double theta_min = k > 0 ? n.theta[k - 1] : 0.0;
+    *n.floor_out = fmax(fmax(-theta_min, 0.0), 0.1 * n.u_p * fabs(tr));
+    n.diag_out[0] = tr;
+    n.diag_out[1] = part[0] + part[1] + part[2] + part[3];
+  }
+}
+
+__global__ __launch_bounds__(256) void hh_qtable_kernel(const LzNode* __restrict__ nodes) {
+  const LzNode n = nodes[blockIdx.z];
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j == 0) *n.qrank = n.b;
+  if (j >= n.kk) return;
+  n.qcols[j] = n.Q + j * n.m;
+  n.qrbs[j] = kRowBlock;
+  n.qrows[j] = n.m;
+}
+
 }  // namespace
+
+size_t hh_node_bytes() { return sizeof(LzNode); }
+
+bool hh_available() {
+  static const bool force_lanczos = [] {
+    const char* e = std::getenv("HAPOD_FULL_LANCZOS");
+    return e && e[0] == '1';
+  }();
+  return !force_lanczos;
+}
+
+// Q (m x (m + 1)), w, alpha, beta (m + 1), theta, Z, last, Z2 (m x (m + 1)),
+// trace, the back-transformation's column table and rank
+size_t hh_scratch_bytes(int64_t m) {
+  const size_t k = (size_t)m;
+  return al(sizeof(double) * k * (k + 1)) + al(sizeof(double) * k) * 5 + al(sizeof(double) * (k + 1)) +
+         al(sizeof(double) * k * k) + al(sizeof(double) * k * (k + 1)) + al(sizeof(double)) + al(sizeof(void*) * k) +
+         al(sizeof(int64_t) * k) * 2 + al(sizeof(int64_t));
+}
+
+void hh_describe(int64_t m, const double* G, int64_t ldg, double* lambda, double* V, int64_t ldv, char* scratch,
+                 double u_p, double* floor_out, double* diag_out, void* node, LiftNode* lift) {
+  const size_t k = (size_t)m;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    char* p = scratch + o;
+    o += al(bytes);
+    return p;
+  };
+  LzNode n{};
+  n.G = G;
+  n.ldg = ldg;
+  n.m = m;
+  n.Q = (double*)take(sizeof(double) * k * (k + 1));
+  n.w = (double*)take(sizeof(double) * k);
+  n.alpha = (double*)take(sizeof(double) * k);
+  n.beta = (double*)take(sizeof(double) * (k + 1));
+  n.theta = (double*)take(sizeof(double) * k);
+  n.last = (double*)take(sizeof(double) * k);
+  n.wn = (double*)take(sizeof(double) * k);
+  n.Z = (double*)take(sizeof(double) * k * k);
+  n.Z2 = (double*)take(sizeof(double) * k * (k + 1));
+  n.tr = (double*)take(sizeof(double));
+  n.h = n.wn;  // unused by the full-run kernels
+  n.qcols = (const void**)take(sizeof(void*) * k);
+  n.qrbs = (int64_t*)take(sizeof(int64_t) * k);
+  n.qrows = (int64_t*)take(sizeof(int64_t) * k);
+  n.qrank = (int64_t*)take(sizeof(int64_t));
+  n.V = V;
+  n.lambda = lambda;
+  n.ldv = ldv;
+  n.nrc = 1;
+  n.kk = (int32_t)m;
+  n.b = (int32_t)m;
+  n.floor_out = floor_out;
+  n.diag_out = diag_out;
+  n.u_p = u_p;
+  std::memcpy(node, &n, sizeof(n));
+  LiftNode l{};
+  l.cols = (const void* const*)n.qcols;
+  l.rbs = n.qrbs;
+  l.crows = n.qrows;
+  l.B = n.Z;
+  l.rank = n.qrank;
+  l.out = V;
+  l.n = m;
+  l.ldb = m;
+  l.ocs = ldv;
+  l.obs = kRowBlock;
+  l.m = (int32_t)m;
+  l.row_tiles = (int32_t)((m + kLiftTileM - 1) / kLiftTileM);
+  l.col_tiles = (int32_t)((m + kLiftTileN - 1) / kLiftTileN);
+  l.rt_per = 1;
+  *lift = l;
+}
+
+hapod_status hh_launch(const void* d_nodes_v, int nn, int64_t m_max, const LiftNode* d_lifts, int lift_items,
+                       hipStream_t stream) {
+  if (nn <= 0 || m_max <= 0) return HAPOD_OK;
+  const LzNode* dn = (const LzNode*)d_nodes_v;
+  const int kk = (int)m_max;
+  hipLaunchKernelGGL(setup_kernel, dim3(1, 1, nn), dim3(1024), 0, stream, dn);
+  hipLaunchKernelGGL(tridiag_kernel, dim3(nn), dim3(kHhThreads), 0, stream, dn, (const int*)nullptr);
+  static bool fq_attr = false;
+  if (!fq_attr) {
+    HAPOD_HIP(hipFuncSetAttribute((const void*)formq_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)(sizeof(double) * ((size_t)kFqChunk * kHhMaxM + kFqChunk))));
+    fq_attr = true;
+  }
+  hipLaunchKernelGGL(formq_kernel, dim3((unsigned)((m_max + 15) / 16), 1, nn), dim3(1024),
+                     sizeof(double) * ((size_t)kFqChunk * m_max + kFqChunk), stream, dn, (const int*)nullptr);
+  hipLaunchKernelGGL(bisect_kernel, dim3((unsigned)((kk + 3) / 4), 1, nn), dim3(256), sizeof(double) * 3 * (size_t)kk,
+                     stream, dn);
+  hipLaunchKernelGGL(inviter_kernel, dim3((unsigned)kk, 1, nn), dim3(64), (sizeof(double) * 5 + sizeof(int)) * (size_t)kk,
+                     stream, dn);
+  for (int pass = 0; pass < 2; ++pass)
+    hipLaunchKernelGGL(ortho_sweep_kernel, dim3((unsigned)kk, 1, nn), dim3(256), sizeof(double) * 2 * (size_t)kk,
+                       stream, dn, pass);
+  hipLaunchKernelGGL(hh_qtable_kernel, dim3((unsigned)((kk + 255) / 256), 1, nn), dim3(256), 0, stream, dn);
+  HAPOD_HIP(hipGetLastError());
+  HAPOD_TRY(launch_lift(0, d_lifts, nn, lift_items, stream));
+  hipLaunchKernelGGL(sign_fix_kernel, dim3((unsigned)((kk + 3) / 4), 1, nn), dim3(256), 0, stream, dn);
+  hipLaunchKernelGGL(write_lambda_kernel, dim3(64, 1, nn), dim3(256), 0, stream, dn);
+  hipLaunchKernelGGL(hh_finish_kernel, dim3(nn), dim3(256), 0, stream, dn);
+  HAPOD_HIP(hipGetLastError());
+  return HAPOD_OK;
+}
 
 hapod_status wide_eigh_batch(std::vector<WideJob>& jobs, double u_p, wide_alloc_fn alloc, wide_free_fn release,
                              void* ctx, hipStream_t stream) {
@@ -1218,10 +1365,7 @@ hapod_status wide_eigh_batch(std::vector<WideJob>& jobs, double u_p, wide_alloc_
   // number of matrices, one workgroup per CU by its LDS: all must be resident)
   // full runs of at most kHhMaxM columns: Householder reduction instead of
   // the Krylov iteration (HAPOD_FULL_LANCZOS=1 keeps them on Lanczos)
-  static const bool force_lanczos = [] {
-    const char* e = std::getenv("HAPOD_FULL_LANCZOS");
-    return e && e[0] == '1';
-  }();
+  const bool force_lanczos = !hh_available();
   std::vector<char> hh(nn, 0);
   std::vector<int> hh_list;
   for (int i = 0; i < nn; ++i)

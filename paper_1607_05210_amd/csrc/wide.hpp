@@ -39,6 +39,31 @@ hapod_status wide_eigh(const double* G, int64_t ldg, int64_t m, double* lambda, 
                        WideResult* res, bool full = false);
 constexpr int kWideMaxSteps = 768;
 
+// Every eigenpair of matrices of at most kHouseholderMaxM columns with no
+// host step in between (Householder reduction, tridiagonal eigenpairs,
+// back-transformation; the same kernels as a full wide_eigh run), for
+// batches whose launch sequence must not wait on the host.  The caller lays
+// out, per matrix, hh_scratch_bytes(m) of device scratch and hh_node_bytes()
+// of descriptor (uploaded with its other descriptors), then launches them all
+// with hh_launch.  Per matrix the finishing kernel writes
+//   *floor_out = max(-lambda_min, 0, u_p trace(G) / 10)   (the truncation's
+//   rounding level, as a full run reports it), and
+//   diag_out[0] = trace(G), diag_out[1] = sum of the eigenvalues.
+constexpr int64_t kHouseholderMaxM = 256;
+// false when HAPOD_FULL_LANCZOS=1 keeps full runs on the Krylov iteration
+bool hh_available();
+size_t hh_scratch_bytes(int64_t m);
+size_t hh_node_bytes();
+// Fills the host image of one matrix's descriptor (node, hh_node_bytes()) and
+// of its back-transformation lift (LiftNode, all m columns): scratch is the
+// matrix's device scratch.
+void hh_describe(int64_t m, const double* G, int64_t ldg, double* lambda, double* V, int64_t ldv, char* scratch,
+                 double u_p, double* floor_out, double* diag_out, void* node, LiftNode* lift);
+// d_nodes: nn descriptors (hh_node_bytes() apart); d_lifts: their nn lift
+// descriptors, item bases already set (lift_items in all, 128 x 128 tiles).
+hapod_status hh_launch(const void* d_nodes, int nn, int64_t m_max, const LiftNode* d_lifts, int lift_items,
+                       hipStream_t stream);
+
 // Several matrices at once (same results as one call each): every step of
 // the iteration is one launch per kernel for all matrices still iterating.
 struct WideJob {

@@ -532,3 +532,37 @@ def test_autotune_cache_file(hp, tmp_path):
     assert any(ln[0] == "1" and ln[1] == "48" and ln[2] == "12" and ln[3] in ("16", "32", "64", "128")
                for ln in lines), lines
     hp.Plan(synth.star_tree(L), [c] * L + [0], n, 1e-6, 0.75, prec="fp32", autotune=True, autotune_cache=str(path))
+
+
+def test_device_driven_rank_growth_reruns_the_batch(hp):
+    """Leaves of 65..256 columns take the device-driven batch: outputs sized
+    before the ranks are known, for the ranks of the plan's previous run.  A
+    second run whose ranks grow past them (rank-10 data, then rank-60 data)
+    must redo the batch with the ranks read back first; its modes equal,
+    bitwise, those of a fresh plan run once on the second data set (sized
+    for m), and stay within the oracle's bounds."""
+    n, L, c = 3000, 2, 100
+    lo = synth.sinusoid(n, L * c, 10, 1e9, 0.0, seed=21)     # 10 equal-weight modes
+    hi = synth.sinusoid(n, L * c, 60, 1e9, 0.0, seed=22)     # 60
+    eps = 1e-8 * np.linalg.norm(hi)
+    plan = hp.Plan(synth.star_tree(L), [c] * L + [0], n, eps, 0.75)
+    data_lo = {k: dev_colmajor(v) for k, v in enumerate(split_cols(lo, [c] * L))}
+    data_hi = {k: dev_colmajor(v) for k, v in enumerate(split_cols(hi, [c] * L))}
+    plan.run(data_lo)
+    s_lo, _ = plan.modes()
+    assert len(s_lo) == 10
+    assert plan.batch_stats() == {"device": 2, "host": 0, "reruns": 0}
+    plan.run(data_hi)
+    s1, U1 = plan.modes()
+    # leaves (10 -> 60) and root (10 -> 60) both outgrow their outputs
+    assert plan.batch_stats() == {"device": 0, "host": 0, "reruns": 2}
+    fresh = hp.Plan(synth.star_tree(L), [c] * L + [0], n, eps, 0.75)
+    fresh.run(data_hi)
+    s2, U2 = fresh.modes()
+    assert fresh.batch_stats() == {"device": 2, "host": 0, "reruns": 0}
+    assert len(s1) == len(s2) == 60
+    np.testing.assert_array_equal(s1, s2)
+    assert torch.equal(U1, U2)
+    s_ref, U_ref = pod.pod(hi, eps)
+    np.testing.assert_allclose(s1, s_ref[:60], rtol=1e-10)
+    assert metrics.subspace_error(U_ref, host(U1), 60) < 1e-8
