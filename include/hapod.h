@@ -293,6 +293,16 @@ typedef struct {
                                       written back after every run; the file is replaced
                                       through a temporary one.  Read during
                                       hapod_plan only (the path string is copied).     */
+  int32_t graph_levels;            /* 1: each device-driven batch (see
+                                      hapod_plan_batch_stats) is captured as a hipGraph
+                                      and launched as one; the next run replays the graph
+                                      at the same batch position when the batch's
+                                      descriptors, device buffers and launch parameters
+                                      hash the same (same leaves, same pool blocks), and
+                                      captures anew otherwise.  Uploads stay outside the
+                                      graph; the phases of a graph-launched batch are not
+                                      separated in hapod_run_timing (see
+                                      hapod_plan_graph_stats).  0: plain launches.      */
 } hapod_options;
 
 /* Validate the tree (Def. 3.1), compute levels (height: leaves are level 1),
@@ -443,6 +453,11 @@ hapod_status hapod_run_timing(hapod_plan_t plan, double* ms6);
  *   out3[2]  device-driven batches run again that way because a rank
  *            outgrew the output sized for it (counted here, not in out3[0]). */
 hapod_status hapod_plan_batch_stats(hapod_plan_t plan, int64_t* out3);
+
+/* hipGraphs of the last run (option graph_levels), host: out2 = {batches
+ * captured, batches replayed}; *graph_ms (may be NULL) the device time of
+ * their launches, measured with HIP events on the run's stream.           */
+hapod_status hapod_plan_graph_stats(hapod_plan_t plan, int64_t* out2, double* graph_ms);
 
 /* Device time in milliseconds of the phases of one level (1 = leaves) of the
  * last run, measured with HIP events on the run's stream around that level's

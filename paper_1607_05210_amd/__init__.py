@@ -45,7 +45,8 @@ class HapodOptions(C.Structure):
     _fields_ = [("prec", _i32), ("reorth", _i32), ("mem_cap_bytes", _i64),
                 ("node_eps_override", _pdbl), ("jacobi_max", _i32), ("autotune", _i32),
                 ("leaf_wave", _i32), ("block_gram", _i32), ("right_vectors", _i32),
-                ("qr_pod", _i32), ("sketch_cols", _i32), ("autotune_cache", C.c_char_p)]
+                ("qr_pod", _i32), ("sketch_cols", _i32), ("autotune_cache", C.c_char_p),
+                ("graph_levels", _i32)]
 
 
 LEAF_FN = C.CFUNCTYPE(_i32, _vp, _i32, C.POINTER(_vp), _pi64, _vp)
@@ -73,6 +74,7 @@ _SIGS = {
     "hapod_plan_node_pod": [_vp, _i32, _vp, _i64, _i64, _vp, _i64, _pdbl, _pi64, _vp],
     "hapod_run_timing": [_vp, _pdbl],
     "hapod_plan_batch_stats": [_vp, _pi64],
+    "hapod_plan_graph_stats": [_vp, _pi64, _pdbl],
     "hapod_level_timing": [_vp, _i32, _pdbl],
 }
 for _name, _args in _SIGS.items():
@@ -269,7 +271,7 @@ class Plan:
     def __init__(self, parent, leaf_cols, n, eps_star, omega, prec="fp64", reorth=False,
                  mem_cap_bytes=0, eps_override=None, jacobi_max=0, leaf_rows=None, leaf_wave=0,
                  autotune=False, block_gram=False, right_vectors=False, qr_pod=False, sketch_cols=0,
-                 autotune_cache=None):
+                 autotune_cache=None, graph_levels=False):
         import numpy as np
         self.num_nodes = len(parent)
         self.n = int(n)
@@ -287,7 +289,7 @@ class Plan:
         opts = HapodOptions(self.prec, int(bool(reorth)), int(mem_cap_bytes), ov, int(jacobi_max),
                             int(bool(autotune)), int(leaf_wave), int(bool(block_gram)),
                             int(bool(right_vectors)), int(bool(qr_pod)), int(sketch_cols),
-                            os.fsencode(autotune_cache) if autotune_cache else None)
+                            os.fsencode(autotune_cache) if autotune_cache else None, int(bool(graph_levels)))
         h = C.c_void_p()
         _check(_lib.hapod_plan(C.byref(tree), float(eps_star), float(omega), C.byref(opts), C.byref(h)),
                "hapod_plan")
@@ -450,6 +452,14 @@ class Plan:
         t = (C.c_double * 6)()
         _check(_lib.hapod_run_timing(self._h, t), "hapod_run_timing")
         return dict(zip(["total", "gram", "eig", "truncate", "lift", "reorth"], list(t)))
+
+    def graph_stats(self):
+        """hipGraphs of the last run: batches captured, replayed, and the
+        device time (ms) of their launches (hapod_plan_graph_stats)."""
+        t = (C.c_int64 * 2)()
+        ms = C.c_double(0.0)
+        _check(_lib.hapod_plan_graph_stats(self._h, t, C.byref(ms)), "hapod_plan_graph_stats")
+        return dict(captures=t[0], replays=t[1], ms=ms.value)
 
     def batch_stats(self):
         """Batches of the last run: device-driven, with ranks read back

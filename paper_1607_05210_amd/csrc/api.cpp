@@ -301,6 +301,7 @@ struct PodJob {
 
 struct PhaseTimes {
   float gram = 0, eig = 0, trunc = 0, lift = 0;
+  float graph = 0;  // batches launched as a hipGraph (phases not separated)
 };
 
 // batches of the last run: device-driven (nothing back to the host between
@@ -308,6 +309,43 @@ struct PhaseTimes {
 // device-driven ones run again because a rank outgrew its output
 struct BatchStats {
   int64_t device = 0, host = 0, reruns = 0;
+};
+
+// hipGraphs of device-driven batches (plan option graph_levels), one per
+// batch position in a run (level, or wave of leaves): a batch whose
+// descriptors, device buffers and launch parameters hash to what the graph
+// at its position was captured from replays it; any difference captures
+// anew.  Captured on a private stream (default priority), launched on the
+// run's stream; the uploads stay outside the graph.
+struct GraphCache {
+  struct Entry {
+    uint64_t sig = 0;
+    hipGraphExec_t exec = nullptr;
+  };
+  bool on = false;
+  hipStream_t cap = nullptr;
+  std::vector<Entry> entries;
+  size_t next = 0;
+  int64_t captures = 0, replays = 0;
+  ~GraphCache() {
+    for (auto& e : entries)
+      if (e.exec) (void)hipGraphExecDestroy(e.exec);
+    if (cap) (void)hipStreamDestroy(cap);
+  }
+};
+
+// FNV-1a over byte ranges
+struct Fnv {
+  uint64_t h = 1469598103934665603ull;
+  void add(const void* p, size_t n) {
+    const unsigned char* b = static_cast<const unsigned char*>(p);
+    for (size_t i = 0; i < n; ++i) h = (h ^ b[i]) * 1099511628211ull;
+  }
+  template <class T> void val(const T& v) { add(&v, sizeof(v)); }
+  template <class T> void vec(const std::vector<T>& v) {
+    val(v.size());
+    add(v.data(), v.size() * sizeof(T));
+  }
 };
 
 struct Events {
@@ -462,7 +500,7 @@ constexpr int64_t kLiftTargetItems = 2048;  // lift workgroups per launch to aim
 hapod_status run_pod_batch_impl(hapod_precision prec, std::vector<PodJob>& jobs, int policy_small, int policy_wide,
                                 int jacobi_max, Pool& pool, hipStream_t stream, PhaseTimes* times,
                                 void** batch_block, bool autotune, bool allow_dev, bool* overflow,
-                                BatchStats* bstats) {
+                                BatchStats* bstats, GraphCache* gcache) {
   const int compute = compute_mode(prec);
   const int eb = elem_bytes(prec);
   const int nj = (int)jobs.size();
@@ -1040,174 +1078,266 @@ hapod_status run_pod_batch_impl(hapod_precision prec, std::vector<PodJob>& jobs,
   if (ttotal > 0)
     HAPOD_HIP(hipMemcpyAsync(scratch + tbase, timg.data(), ttotal, hipMemcpyHostToDevice, stream));
   int32_t* d_flag = (int32_t*)(scratch + flag_off);
-  HAPOD_TRY(launch_zero_bytes(d_flag, 64, stream));
-
-  Events ev;
-  if (times && ev.ok) HAPOD_HIP(hipEventRecord(ev.e[0], stream));
-  // ---- split twins, then Gram, one twin group at a time; then the reduction
-  for (int gr = 0; gr < ngroups; ++gr) {
-    for (int i = 0; i < nj; ++i)
-      if (lay[i].presplit && twin_group[i] == gr)
-        HAPOD_TRY(launch_split_cols(jobs[i].n, jobs[i].m, (const void* const*)(scratch + lay[i].cols),
-                                    (const int64_t*)(scratch + lay[i].rbs),
-                                    (const int64_t*)(scratch + lay[i].crows), (float*)split_buf[i], stream));
-    HAPOD_TRY(launch_gram(compute, (const GramNode*)(dblob + o_g), (const GramItem*)(dblob + o_gi),
-                          glaunch[gr].data(), (int)glaunch[gr].size(), nullptr, nullptr, 0, 0, stream));
-  }
-  HAPOD_TRY(launch_gram(compute, (const GramNode*)(dblob + o_g), (const GramItem*)(dblob + o_gi), nullptr, 0,
-                        (const int32_t*)(dblob + o_rp), (const int32_t*)(dblob + o_rn), (int)rpairs.size(),
-                        max_reduce_tile, stream));
-  HAPOD_TRY(launch_gram_fill((const GramFill*)(dblob + o_fill), (int)fills.size(), (const double*)(dblob + o_s2),
-                             stream));
-  for (int i = 0; i < nj; ++i) HAPOD_TRY(launch_check_diag(gnodes[i].G, gnodes[i].ldg, jobs[i].m, d_flag, stream));
-  if (times && ev.ok) HAPOD_HIP(hipEventRecord(ev.e[1], stream));
-  // ---- eigensolve -----------------------------------------------------------
-  if (!enodes_small.empty())
-    HAPOD_TRY(launch_jacobi((const EigNode*)(dblob + o_es), (int)enodes_small.size(), max_small, stream));
-  if (!enodes_big.empty())
-    HAPOD_TRY(launch_jacobi((const EigNode*)(dblob + o_eb), (int)enodes_big.size(), max_big, stream));
-  // wide nodes: one batched Krylov eigensolve for all of them (device-driven
-  // batch: the Householder full runs, launched with no host step)
-  std::vector<WideResult> wres(nj);
-  if (dev) {
-    HAPOD_TRY(hh_launch(dblob + o_hh, (int)hh_idx.size(), hh_mmax, (const LiftNode*)(dblob + o_hhl), hh_items,
-                        stream));
-  } else {
-    std::vector<WideJob> wj;
-    for (int i = 0; i < nj; ++i) {
-      if (!jobs[i].wide || jobs[i].m <= 0) continue;
-      wj.push_back(WideJob{gnodes[i].G, jobs[i].m, jobs[i].m, (double*)(scratch + lay[i].lam),
-                           (double*)(scratch + lay[i].V), jobs[i].m, jobs[i].wide_full, &wres[i]});
-    }
-    if (!wj.empty()) HAPOD_TRY(wide_eigh_batch(wj, u_p, &pool_alloc_cb, &pool_free_cb, &pool, stream));
-  }
-  for (int i = 0; i < nj; ++i) {
-    if (dev || !jobs[i].wide || jobs[i].m <= 0) continue;
-    const WideResult& wr = wres[i];
-    // eigenvalues beyond the computed block are set to zero by wide_eigh;
-    // the floor of the truncation is the Gram's rounding level
-    tnodes[i].floor_abs = wr.floor_abs;
-    jobs[i].sweeps = wr.iterations;
-    jobs[i].wide_exhausted = wr.exhausted;
-    jobs[i].wide_missing = wr.missing;
-    jobs[i].wide_unresolved = wr.unresolved;
-    // the difference trace - sum(theta) carries the rounding of every
-    // eigenvalue and of the diagonal: allow 16 (block + sqrt(m)) u_p |trace|
-    jobs[i].wide_slack = 16.0 * (wr.block + std::sqrt((double)jobs[i].m)) * u_p * std::fabs(wr.trace);
-    // the eigenvalues past the block lie below the resolved level: up to
-    // (m - block) noise of unresolved energy is consistent with that (the
-    // truncation then cannot certify eps below the noise, as for any Gram of
-    // this precision); more means a large eigenvalue was never seen
-    jobs[i].wide_noise_room = (double)(jobs[i].m - wr.block) * wr.noise;
-    if (jobs[i].wide_full && wr.unresolved > jobs[i].wide_slack) {
-      // the Krylov space broke down before spanning the matrix (an exact
-      // multiplicity): fall back to the dense Jacobi eigensolver
-      const int m = (int)jobs[i].m;
-      if (const char* v = std::getenv("HAPOD_VERBOSE"))
-        if (v[0] == '1')
-          std::fprintf(stderr, "[hapod] m=%d: Krylov run left %.3e of trace %.3e unresolved (slack %.3e): Jacobi\n",
-                       m, wr.unresolved, wr.trace, jobs[i].wide_slack);
-      void *jw = nullptr, *vw = nullptr, *de = nullptr;
-      HAPOD_TRY(pool.alloc(sizeof(double) * jacobi_work_doubles(m), &jw));
-      hapod_status s = pool.alloc(sizeof(double) * jacobi_vwork_doubles(m), &vw);
-      if (s == HAPOD_OK) s = pool.alloc(sizeof(EigNode), &de);
-      if (s == HAPOD_OK) {
-        EigNode e{};
-        e.G = gnodes[i].G;
-        e.work = (double*)jw;
-        e.Vwork = (double*)vw;
-        e.lambda = (double*)(scratch + lay[i].lam);
-        e.V = (double*)(scratch + lay[i].V);
-        e.ldg = m;
-        e.ldv = m;
-        e.m = m;
-        s = hipMemcpyAsync(de, &e, sizeof(e), hipMemcpyHostToDevice, stream) == hipSuccess ? HAPOD_OK : HAPOD_E_DEVICE;
-        if (s == HAPOD_OK) s = launch_jacobi((const EigNode*)de, 1, m, stream);
-        if (s == HAPOD_OK && hipStreamSynchronize(stream) != hipSuccess) s = HAPOD_E_DEVICE;
-      }
-      if (de) pool.free(de);
-      if (vw) pool.free(vw);
-      pool.free(jw);
-      if (s != HAPOD_OK) return s;
-      jobs[i].wide_unresolved = 0.0;
-      jobs[i].wide_missing = 0.0;
-      jobs[i].wide_noise_room = 0.0;
-      jobs[i].wide_exhausted = true;
-    }
-  }
-  if (times && ev.ok) HAPOD_HIP(hipEventRecord(ev.e[2], stream));
-  // wide nodes changed floor_abs on the host: refresh the descriptors (one
-  // copy through pinned staging)
-  bool any_wide = false;
-  for (int i = 0; i < nj; ++i) any_wide |= jobs[i].wide && !dev;
-  char* pin = pool.pinned(std::max(sizeof(TruncNode), sizeof(int64_t)) * (size_t)nj);
-  if (!pin) {
-    set_error("hipHostMalloc of the descriptor staging failed");
-    return HAPOD_E_NOMEM;
-  }
-  if (any_wide) {
-    std::memcpy(pin, tnodes.data(), sizeof(TruncNode) * nj);
-    HAPOD_HIP(hipMemcpyAsync(dblob + o_t, pin, sizeof(TruncNode) * nj, hipMemcpyHostToDevice, stream));
-  }
-  // ---- truncation -----------------------------------------------------------
-  HAPOD_TRY(launch_truncate((const TruncNode*)(dblob + o_t), nj, stream));
-  if (times && ev.ok) HAPOD_HIP(hipEventRecord(ev.e[3], stream));
-  // ---- lift, sized by the ranks just computed (device-driven batch: by the
-  // worst case, built before the launches) ----------------------------------
-  // (the ranks come back through the same staging: stream order puts these
-  // copies after the descriptor upload that read it)
-  char* dlift = nullptr;
-  bool dlift_owned = false;
-  if (dev) {
-    dlift = dblob + o_l;
-  } else {
-    std::vector<int64_t> ranks(nj, 0);
-    for (int i = 0; i < nj; ++i)
-      HAPOD_HIP(hipMemcpyAsync(pin + i * sizeof(int64_t), scratch + lay[i].rank, sizeof(int64_t),
-                               hipMemcpyDeviceToHost, stream));
-    HAPOD_HIP(hipStreamSynchronize(stream));
-    std::memcpy(ranks.data(), pin, sizeof(int64_t) * nj);
-    // right singular vectors kept for the factorisation of the snapshot map:
-    // the first N eigenvectors (columns of V, ld m) are contiguous
-    for (int i = 0; i < nj; ++i) {
-      PodJob& j = jobs[i];
-      if (!j.keep_v || ranks[i] <= 0 || j.m <= 0) continue;
-      const size_t bytes = sizeof(double) * (size_t)j.m * ranks[i];
-      HAPOD_TRY(pool.alloc(bytes, (void**)&j.vkeep));
-      HAPOD_HIP(hipMemcpyAsync(j.vkeep, scratch + lay[i].V, bytes, hipMemcpyDeviceToDevice, stream));
-    }
-    HAPOD_TRY(build_lifts(ranks, false));
-    if (!lnodes[0].empty() || !lnodes[1].empty()) {
-      std::vector<LiftNode> all(lnodes[0]);
-      all.insert(all.end(), lnodes[1].begin(), lnodes[1].end());
-      HAPOD_TRY(pool.alloc(sizeof(LiftNode) * all.size(), (void**)&dlift));
-      dlift_owned = true;
-      HAPOD_HIP(hipMemcpy(dlift, all.data(), sizeof(LiftNode) * all.size(), hipMemcpyHostToDevice));
-    }
-  }
-  const size_t nl0 = lnodes[0].size(), nl1 = lnodes[1].size();
-  struct Guard3 {
-    Pool& p;
-    void* s;
-    ~Guard3() {
-      if (s) p.free(s);
-    }
-  } guard3{pool, dlift_owned ? dlift : nullptr};
-  if (times && ev.ok) HAPOD_HIP(hipEventRecord(ev.e[3], stream));
   // the split-BF16 form lifts with three BF16 products per term: a lift of
   // N output columns does 2 N flops per 4 input bytes, above the FP32 MFMA
   // peak's share of HBM bandwidth once N passes about 40, while the BF16
-  // products keep it bandwidth-bound (the operand is split once, here)
+  // products keep it bandwidth-bound (the operand is split once, below)
   const int lift_compute = (compute == 2 && !split_lift) ? 1 : compute;
-  if (lift_compute == 2 && nl0 + nl1 > 0) {
-    int64_t max_m = 0;
-    for (int i = 0; i < nj; ++i) max_m = std::max(max_m, jobs[i].m);
-    HAPOD_TRY(launch_split_operand((const LiftNode*)dlift, (int)(nl0 + nl1), max_m, stream));
+  // ---- a device-driven batch as a hipGraph: replay the one captured at this
+  // position when everything the launches read hashes the same, else capture
+  GraphCache* gc = (dev && gcache && gcache->on) ? gcache : nullptr;
+  GraphCache::Entry* ge = nullptr;
+  bool replay = false, capturing = false;
+  hipStream_t ls = stream;  // the stream the launches below go to
+  uint64_t sig = 0;
+  if (gc) {
+    Fnv f;
+    f.vec(blob.host);
+    f.vec(timg);
+    f.val(scratch);
+    f.val(dblob);
+    f.val(arena);
+    f.val(tbase);
+    f.val(compute);
+    f.val(lift_compute);
+    f.val(ngroups);
+    for (const auto& v : glaunch) f.vec(v);
+    for (void* b : split_buf) f.val(b);
+    for (const auto& L : lay) f.val(L);
+    for (const auto& j : jobs) {
+      f.val(j.n);
+      f.val(j.m);
+    }
+    f.val(rpairs.size());
+    f.val(max_reduce_tile);
+    f.val(fills.size());
+    f.val(enodes_small.size());
+    f.val(enodes_big.size());
+    f.val(max_small);
+    f.val(max_big);
+    f.val(hh_idx.size());
+    f.val(hh_mmax);
+    f.val(hh_items);
+    f.val(lift_items);
+    sig = f.h;
+    const size_t k = gc->next++;
+    if (gc->entries.size() <= k) gc->entries.resize(k + 1);
+    ge = &gc->entries[k];
+    if (ge->exec && ge->sig == sig) {
+      replay = true;
+    } else {
+      if (ge->exec) {
+        HAPOD_HIP(hipGraphExecDestroy(ge->exec));
+        ge->exec = nullptr;
+      }
+      if (!gc->cap) HAPOD_HIP(hipStreamCreateWithFlags(&gc->cap, hipStreamNonBlocking));
+      HAPOD_HIP(hipStreamBeginCapture(gc->cap, hipStreamCaptureModeRelaxed));
+      ls = gc->cap;
+      capturing = true;
+    }
   }
-  if (nl0) HAPOD_TRY(launch_lift(lift_compute, (const LiftNode*)dlift, (int)nl0, lift_items[0], stream, false));
-  if (nl1)
-    HAPOD_TRY(launch_lift(lift_compute, (const LiftNode*)dlift + nl0, (int)nl1, lift_items[1], stream, true));
-  if (times && ev.ok) HAPOD_HIP(hipEventRecord(ev.e[4], stream));
+  // a capture left open by an early return is ended (and dropped) here
+  struct CaptureGuard {
+    hipStream_t s;
+    bool* on;
+    ~CaptureGuard() {
+      if (*on) {
+        hipGraph_t g = nullptr;
+        if (hipStreamEndCapture(s, &g) == hipSuccess && g) (void)hipGraphDestroy(g);
+      }
+    }
+  } cap_guard{ls, &capturing};
+  // the host-mode lift descriptors, freed after the final synchronisation
+  char* lift_desc_owned = nullptr;
+  struct Guard3 {
+    Pool& p;
+    char*& s;
+    ~Guard3() {
+      if (s) p.free(s);
+    }
+  } guard3{pool, lift_desc_owned};
+  Events ev;
+  const bool tev = times && ev.ok && !gc;  // phase events (not inside a graph)
+  if (times && ev.ok && gc) HAPOD_HIP(hipEventRecord(ev.e[0], stream));
+  if (!replay) {
+    HAPOD_TRY(launch_zero_bytes(d_flag, 64, ls));
+
+    if (tev) HAPOD_HIP(hipEventRecord(ev.e[0], stream));
+    // ---- split twins, then Gram, one twin group at a time; then the reduction
+    for (int gr = 0; gr < ngroups; ++gr) {
+      for (int i = 0; i < nj; ++i)
+        if (lay[i].presplit && twin_group[i] == gr)
+          HAPOD_TRY(launch_split_cols(jobs[i].n, jobs[i].m, (const void* const*)(scratch + lay[i].cols),
+                                      (const int64_t*)(scratch + lay[i].rbs),
+                                      (const int64_t*)(scratch + lay[i].crows), (float*)split_buf[i], ls));
+      HAPOD_TRY(launch_gram(compute, (const GramNode*)(dblob + o_g), (const GramItem*)(dblob + o_gi),
+                            glaunch[gr].data(), (int)glaunch[gr].size(), nullptr, nullptr, 0, 0, ls));
+    }
+    HAPOD_TRY(launch_gram(compute, (const GramNode*)(dblob + o_g), (const GramItem*)(dblob + o_gi), nullptr, 0,
+                          (const int32_t*)(dblob + o_rp), (const int32_t*)(dblob + o_rn), (int)rpairs.size(),
+                          max_reduce_tile, ls));
+    HAPOD_TRY(launch_gram_fill((const GramFill*)(dblob + o_fill), (int)fills.size(), (const double*)(dblob + o_s2),
+                               ls));
+    for (int i = 0; i < nj; ++i) HAPOD_TRY(launch_check_diag(gnodes[i].G, gnodes[i].ldg, jobs[i].m, d_flag, ls));
+    if (tev) HAPOD_HIP(hipEventRecord(ev.e[1], stream));
+    // ---- eigensolve -----------------------------------------------------------
+    if (!enodes_small.empty())
+      HAPOD_TRY(launch_jacobi((const EigNode*)(dblob + o_es), (int)enodes_small.size(), max_small, ls));
+    if (!enodes_big.empty())
+      HAPOD_TRY(launch_jacobi((const EigNode*)(dblob + o_eb), (int)enodes_big.size(), max_big, ls));
+    // wide nodes: one batched Krylov eigensolve for all of them (device-driven
+    // batch: the Householder full runs, launched with no host step)
+    std::vector<WideResult> wres(nj);
+    if (dev) {
+      HAPOD_TRY(hh_launch(dblob + o_hh, (int)hh_idx.size(), hh_mmax, (const LiftNode*)(dblob + o_hhl), hh_items,
+                          ls));
+    } else {
+      std::vector<WideJob> wj;
+      for (int i = 0; i < nj; ++i) {
+        if (!jobs[i].wide || jobs[i].m <= 0) continue;
+        wj.push_back(WideJob{gnodes[i].G, jobs[i].m, jobs[i].m, (double*)(scratch + lay[i].lam),
+                             (double*)(scratch + lay[i].V), jobs[i].m, jobs[i].wide_full, &wres[i]});
+      }
+      if (!wj.empty()) HAPOD_TRY(wide_eigh_batch(wj, u_p, &pool_alloc_cb, &pool_free_cb, &pool, ls));
+    }
+    for (int i = 0; i < nj; ++i) {
+      if (dev || !jobs[i].wide || jobs[i].m <= 0) continue;
+      const WideResult& wr = wres[i];
+      // eigenvalues beyond the computed block are set to zero by wide_eigh;
+      // the floor of the truncation is the Gram's rounding level
+      tnodes[i].floor_abs = wr.floor_abs;
+      jobs[i].sweeps = wr.iterations;
+      jobs[i].wide_exhausted = wr.exhausted;
+      jobs[i].wide_missing = wr.missing;
+      jobs[i].wide_unresolved = wr.unresolved;
+      // the difference trace - sum(theta) carries the rounding of every
+      // eigenvalue and of the diagonal: allow 16 (block + sqrt(m)) u_p |trace|
+      jobs[i].wide_slack = 16.0 * (wr.block + std::sqrt((double)jobs[i].m)) * u_p * std::fabs(wr.trace);
+      // the eigenvalues past the block lie below the resolved level: up to
+      // (m - block) noise of unresolved energy is consistent with that (the
+      // truncation then cannot certify eps below the noise, as for any Gram of
+      // this precision); more means a large eigenvalue was never seen
+      jobs[i].wide_noise_room = (double)(jobs[i].m - wr.block) * wr.noise;
+      if (jobs[i].wide_full && wr.unresolved > jobs[i].wide_slack) {
+        // the Krylov space broke down before spanning the matrix (an exact
+        // multiplicity): fall back to the dense Jacobi eigensolver
+        const int m = (int)jobs[i].m;
+        if (const char* v = std::getenv("HAPOD_VERBOSE"))
+          if (v[0] == '1')
+            std::fprintf(stderr, "[hapod] m=%d: Krylov run left %.3e of trace %.3e unresolved (slack %.3e): Jacobi\n",
+                         m, wr.unresolved, wr.trace, jobs[i].wide_slack);
+        void *jw = nullptr, *vw = nullptr, *de = nullptr;
+        HAPOD_TRY(pool.alloc(sizeof(double) * jacobi_work_doubles(m), &jw));
+        hapod_status s = pool.alloc(sizeof(double) * jacobi_vwork_doubles(m), &vw);
+        if (s == HAPOD_OK) s = pool.alloc(sizeof(EigNode), &de);
+        if (s == HAPOD_OK) {
+          EigNode e{};
+          e.G = gnodes[i].G;
+          e.work = (double*)jw;
+          e.Vwork = (double*)vw;
+          e.lambda = (double*)(scratch + lay[i].lam);
+          e.V = (double*)(scratch + lay[i].V);
+          e.ldg = m;
+          e.ldv = m;
+          e.m = m;
+          s = hipMemcpyAsync(de, &e, sizeof(e), hipMemcpyHostToDevice, ls) == hipSuccess ? HAPOD_OK : HAPOD_E_DEVICE;
+          if (s == HAPOD_OK) s = launch_jacobi((const EigNode*)de, 1, m, ls);
+          if (s == HAPOD_OK && hipStreamSynchronize(ls) != hipSuccess) s = HAPOD_E_DEVICE;
+        }
+        if (de) pool.free(de);
+        if (vw) pool.free(vw);
+        pool.free(jw);
+        if (s != HAPOD_OK) return s;
+        jobs[i].wide_unresolved = 0.0;
+        jobs[i].wide_missing = 0.0;
+        jobs[i].wide_noise_room = 0.0;
+        jobs[i].wide_exhausted = true;
+      }
+    }
+    if (tev) HAPOD_HIP(hipEventRecord(ev.e[2], stream));
+    // wide nodes changed floor_abs on the host: refresh the descriptors (one
+    // copy through pinned staging)
+    bool any_wide = false;
+    for (int i = 0; i < nj; ++i) any_wide |= jobs[i].wide && !dev;
+    char* pin = dev ? nullptr : pool.pinned(std::max(sizeof(TruncNode), sizeof(int64_t)) * (size_t)nj);
+    if (!dev && !pin) {
+      set_error("hipHostMalloc of the descriptor staging failed");
+      return HAPOD_E_NOMEM;
+    }
+    if (any_wide) {
+      std::memcpy(pin, tnodes.data(), sizeof(TruncNode) * nj);
+      HAPOD_HIP(hipMemcpyAsync(dblob + o_t, pin, sizeof(TruncNode) * nj, hipMemcpyHostToDevice, ls));
+    }
+    // ---- truncation -----------------------------------------------------------
+    HAPOD_TRY(launch_truncate((const TruncNode*)(dblob + o_t), nj, ls));
+    if (tev) HAPOD_HIP(hipEventRecord(ev.e[3], stream));
+    // ---- lift, sized by the ranks just computed (device-driven batch: by the
+    // worst case, built before the launches) ----------------------------------
+    // (the ranks come back through the same staging: stream order puts these
+    // copies after the descriptor upload that read it)
+    char* dlift = nullptr;
+    bool dlift_owned = false;
+    if (dev) {
+      dlift = dblob + o_l;
+    } else {
+      std::vector<int64_t> ranks(nj, 0);
+      for (int i = 0; i < nj; ++i)
+        HAPOD_HIP(hipMemcpyAsync(pin + i * sizeof(int64_t), scratch + lay[i].rank, sizeof(int64_t),
+                                 hipMemcpyDeviceToHost, ls));
+      HAPOD_HIP(hipStreamSynchronize(ls));
+      std::memcpy(ranks.data(), pin, sizeof(int64_t) * nj);
+      // right singular vectors kept for the factorisation of the snapshot map:
+      // the first N eigenvectors (columns of V, ld m) are contiguous
+      for (int i = 0; i < nj; ++i) {
+        PodJob& j = jobs[i];
+        if (!j.keep_v || ranks[i] <= 0 || j.m <= 0) continue;
+        const size_t bytes = sizeof(double) * (size_t)j.m * ranks[i];
+        HAPOD_TRY(pool.alloc(bytes, (void**)&j.vkeep));
+        HAPOD_HIP(hipMemcpyAsync(j.vkeep, scratch + lay[i].V, bytes, hipMemcpyDeviceToDevice, ls));
+      }
+      HAPOD_TRY(build_lifts(ranks, false));
+      if (!lnodes[0].empty() || !lnodes[1].empty()) {
+        std::vector<LiftNode> all(lnodes[0]);
+        all.insert(all.end(), lnodes[1].begin(), lnodes[1].end());
+        HAPOD_TRY(pool.alloc(sizeof(LiftNode) * all.size(), (void**)&dlift));
+        dlift_owned = true;
+        HAPOD_HIP(hipMemcpy(dlift, all.data(), sizeof(LiftNode) * all.size(), hipMemcpyHostToDevice));
+      }
+    }
+    const size_t nl0 = lnodes[0].size(), nl1 = lnodes[1].size();
+    lift_desc_owned = dlift_owned ? dlift : nullptr;
+    if (tev) HAPOD_HIP(hipEventRecord(ev.e[3], stream));
+    if (lift_compute == 2 && nl0 + nl1 > 0) {
+      int64_t max_m = 0;
+      for (int i = 0; i < nj; ++i) max_m = std::max(max_m, jobs[i].m);
+      HAPOD_TRY(launch_split_operand((const LiftNode*)dlift, (int)(nl0 + nl1), max_m, ls));
+    }
+    if (nl0) HAPOD_TRY(launch_lift(lift_compute, (const LiftNode*)dlift, (int)nl0, lift_items[0], ls, false));
+    if (nl1)
+      HAPOD_TRY(launch_lift(lift_compute, (const LiftNode*)dlift + nl0, (int)nl1, lift_items[1], ls, true));
+    if (tev) HAPOD_HIP(hipEventRecord(ev.e[4], stream));
+
+  }
+  if (capturing) {
+    hipGraph_t g = nullptr;
+    capturing = false;
+    HAPOD_HIP(hipStreamEndCapture(gc->cap, &g));
+    const hipError_t ie = hipGraphInstantiate(&ge->exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ie != hipSuccess) {
+      ge->exec = nullptr;
+      set_error(std::string("hipGraphInstantiate: ") + hipGetErrorString(ie));
+      return HAPOD_E_DEVICE;
+    }
+    ge->sig = sig;
+    ++gc->captures;
+  } else if (replay) {
+    ++gc->replays;
+  }
+  if (gc) {
+    HAPOD_HIP(hipGraphLaunch(ge->exec, stream));
+    if (times && ev.ok) HAPOD_HIP(hipEventRecord(ev.e[4], stream));
+  }
 
   // ---- results ----------------------------------------------------------------
   HAPOD_HIP(hipStreamSynchronize(stream));
@@ -1261,7 +1391,11 @@ hapod_status run_pod_batch_impl(hapod_precision prec, std::vector<PodJob>& jobs,
       *overflow = true;
     }
   }
-  if (times && ev.ok) {
+  if (times && ev.ok && gc) {
+    // a graph launch: its phases are not separated
+    float a = 0;
+    if (hipEventElapsedTime(&a, ev.e[0], ev.e[4]) == hipSuccess) times->graph += a;
+  } else if (times && ev.ok) {
     float a = 0;
     if (hipEventElapsedTime(&a, ev.e[0], ev.e[1]) == hipSuccess) times->gram += a;
     if (hipEventElapsedTime(&a, ev.e[1], ev.e[2]) == hipSuccess) times->eig += a;
@@ -1277,17 +1411,18 @@ hapod_status run_pod_batch_impl(hapod_precision prec, std::vector<PodJob>& jobs,
 // larger, the batch runs again with the ranks read back before the lift.
 hapod_status run_pod_batch(hapod_precision prec, std::vector<PodJob>& jobs, int policy_small, int policy_wide,
                            int jacobi_max, Pool& pool, hipStream_t stream, PhaseTimes* times,
-                           void** batch_block = nullptr, bool autotune = false, BatchStats* bstats = nullptr) {
+                           void** batch_block = nullptr, bool autotune = false, BatchStats* bstats = nullptr,
+                           GraphCache* gcache = nullptr) {
   bool overflow = false;
   hapod_status st = run_pod_batch_impl(prec, jobs, policy_small, policy_wide, jacobi_max, pool, stream, times,
-                                       batch_block, autotune, true, &overflow, bstats);
+                                       batch_block, autotune, true, &overflow, bstats, gcache);
   if (st != HAPOD_OK || !overflow) return st;
   if (bstats) {
     --bstats->device;
     ++bstats->reruns;
   }
   st = run_pod_batch_impl(prec, jobs, policy_small, policy_wide, jacobi_max, pool, stream, times, batch_block, false,
-                          false, &overflow, bstats);
+                          false, &overflow, bstats, nullptr);
   if (bstats) --bstats->host;  // counted as a rerun only
   return st;
 }
@@ -1353,6 +1488,9 @@ struct hapod_plan_s {
   std::vector<int64_t> rank, m_in, n_neg;
   std::vector<int64_t> rank_hint;  // ranks of the previous run (device-driven output capacity)
   BatchStats bstats;               // batches of the last run
+  GraphCache graphs;               // graph_levels: captured device-driven batches
+  int64_t graph_captures = 0, graph_replays = 0;  // in the last run
+  double graph_ms = 0.0;                          // device time of its graph launches
   std::vector<double> lam1, lam_min;
   std::vector<std::vector<double>> sigma;
   void* root_U = nullptr;  // owned by the pool
@@ -2451,6 +2589,10 @@ hapod_status hapod_run(hapod_plan_t P, hapod_leaf_fn get_leaf, void* user, void*
   // the previous run's ranks size the next run's device-driven outputs
   if (P->rank.size() == (size_t)nn) P->rank_hint = P->rank;
   P->bstats = BatchStats{};
+  P->graphs.on = P->opts.graph_levels != 0;
+  P->graphs.next = 0;
+  const int64_t cap0 = P->graphs.captures, rep0 = P->graphs.replays;
+  P->graph_ms = 0.0;
   P->rank.assign(nn, 0);
   P->m_in.assign(nn, 0);
   P->n_neg.assign(nn, 0);
@@ -2812,7 +2954,7 @@ hapod_status hapod_run(hapod_plan_t P, hapod_leaf_fn get_leaf, void* user, void*
       void* blk = nullptr;
       hapod_status s = jobs.empty() ? HAPOD_OK
                                     : run_pod_batch(prec, jobs, 0, 1, jmax, P->pool, stream, &lt, &blk,
-                                                    P->opts.autotune != 0, &P->bstats);
+                                                    P->opts.autotune != 0, &P->bstats, &P->graphs);
       if (s != HAPOD_OK) {
         (void)hipStreamSynchronize(stream);
         if (blk) P->pool.free(blk);
@@ -2870,6 +3012,7 @@ hapod_status hapod_run(hapod_plan_t P, hapod_leaf_fn get_leaf, void* user, void*
           if (out_buf[b]) release(b);
     }
     P->level_ms[l] = {lt.gram, lt.eig, lt.trunc, lt.lift};
+    P->graph_ms += lt.graph;
     pt.gram += lt.gram;
     pt.eig += lt.eig;
     pt.trunc += lt.trunc;
@@ -2898,6 +3041,8 @@ hapod_status hapod_run(hapod_plan_t P, hapod_leaf_fn get_leaf, void* user, void*
   HAPOD_HIP(hipStreamSynchronize(stream));
   float total_ms = 0.f;
   (void)hipEventElapsedTime(&total_ms, t0, t1);
+  P->graph_captures = P->graphs.captures - cap0;
+  P->graph_replays = P->graphs.replays - rep0;
   P->timing[0] = total_ms;
   P->timing[1] = pt.gram;
   P->timing[2] = pt.eig;
@@ -3017,6 +3162,17 @@ hapod_status hapod_plan_batch_stats(hapod_plan_t P, int64_t* out3) {
   out3[0] = P->bstats.device;
   out3[1] = P->bstats.host;
   out3[2] = P->bstats.reruns;
+  return HAPOD_OK;
+}
+
+hapod_status hapod_plan_graph_stats(hapod_plan_t P, int64_t* out2, double* graph_ms) {
+  if (!P || !out2) {
+    set_error("hapod_plan_graph_stats: NULL argument");
+    return HAPOD_E_INVALID;
+  }
+  out2[0] = P->graph_captures;
+  out2[1] = P->graph_replays;
+  if (graph_ms) *graph_ms = P->graph_ms;
   return HAPOD_OK;
 }
 

@@ -566,3 +566,39 @@ def test_device_driven_rank_growth_reruns_the_batch(hp):
     s_ref, U_ref = pod.pod(hi, eps)
     np.testing.assert_allclose(s1, s_ref[:60], rtol=1e-10)
     assert metrics.subspace_error(U_ref, host(U1), 60) < 1e-8
+
+
+@pytest.mark.parametrize("prec", ["fp64", "bf16x3"])
+def test_graph_levels_replays_match_eager_runs(hp, prec):
+    """graph_levels: every device-driven batch (leaves of 100 columns, root of
+    4 x their rank) is captured as a hipGraph and launched as one.  Run 1
+    captures (outputs sized for m), run 2 captures again (outputs now sized
+    for the ranks of run 1), later runs replay.  Between the runs, eager work
+    on the same stream (another plan, torch arithmetic) and synchronisations;
+    every run's modes equal, bitwise, those of a plan without graphs."""
+    n, L, c = 5000, 4, 100
+    S = synth.sinusoid(n, L * c, 40, 8.0, 1e-9, seed=31)
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    data = {k: dev_colmajor(v, dt) for k, v in enumerate(split_cols(S, [c] * L))}
+    eps = 1e-6 * np.linalg.norm(S)
+    eager = hp.Plan(synth.star_tree(L), [c] * L + [0], n, eps, 0.75, prec=prec)
+    eager.run(data)
+    s0, U0 = eager.modes()
+    assert eager.batch_stats()["device"] == 2
+    gp = hp.Plan(synth.star_tree(L), [c] * L + [0], n, eps, 0.75, prec=prec, graph_levels=True)
+    seen = []
+    for r in range(5):
+        gp.run(data)
+        st = gp.graph_stats()
+        seen.append((st["captures"], st["replays"]))
+        s, U = gp.modes()
+        np.testing.assert_array_equal(s, s0)
+        assert torch.equal(U, U0), f"run {r}"
+        # eager work between the replays
+        eager.run(data)
+        x = torch.randn(1 << 20, device="cuda", dtype=torch.float64)
+        assert float((x * x).sum()) > 0.0
+        torch.cuda.synchronize()
+    assert seen[0] == (2, 0) and seen[1] == (2, 0), seen
+    assert all(sr == (0, 2) for sr in seen[2:]), seen
+    assert gp.graph_stats()["ms"] > 0.0
