@@ -621,9 +621,12 @@ __global__ __launch_bounds__(256, 2) void lift_bf16_kernel(const LiftNode* __res
     for (int a = 0; a < NB; ++a)
 #pragma unroll
       for (int b = 0; b < NB; ++b) acc[a][b] = f4{0, 0, 0, 0};
-    i4 ps[KC];
+    // S runs of two stages in flight (wide tiles; the narrow ones have no
+    // registers to spare and keep one)
+    constexpr int NPS = NARROW ? 1 : 2;
+    i4 psv[NPS][KC];
     bf8 ybh[NB], ybl[NB], nbh[NB], nbl[NB];
-    auto gload = [&](int st, bf8 (&yh)[NB], bf8 (&yl)[NB]) {
+    auto gload_s = [&](int st, i4 (&ps)[KC]) {
       const int64_t row = rtile + 4 * rq;
 #pragma unroll
       for (int c = 0; c < KC; ++c) {
@@ -641,6 +644,8 @@ __global__ __launch_bounds__(256, 2) void lift_bf16_kernel(const LiftNode* __res
           ps[c] = *reinterpret_cast<const i4*>(x);
         }
       }
+    };
+    auto gload_b = [&](int st, bf8 (&yh)[NB], bf8 (&yl)[NB]) {
 #pragma unroll
       for (int b = 0; b < NB; ++b) {
         if (bval[b]) {
@@ -654,7 +659,7 @@ __global__ __launch_bounds__(256, 2) void lift_bf16_kernel(const LiftNode* __res
       }
     };
     // rows 4 rq + e of columns kq KC .. kq KC + KC - 1, split into hi and lo
-    auto lstore = [&](int buf) {
+    auto lstore = [&](int buf, const i4 (&ps)[KC]) {
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         uint32_t h[KC / 2], l[KC / 2];
@@ -687,25 +692,68 @@ __global__ __launch_bounds__(256, 2) void lift_bf16_kernel(const LiftNode* __res
         }
       }
     };
-    if (stages > 0) {
-      ensure_table(0);
-      gload(0, ybh, ybl);
-      lstore(0);
-    }
-    __syncthreads();
-    for (int st = 0; st < stages; ++st) {
-      const bool more = st + 1 < stages;
-      if (more) {
-        ensure_table((st + 1) * KS);
-        gload(st + 1, nbh, nbl);
-      }
-      if (active) compute(st & 1);
-      if (more) lstore((st + 1) & 1);
-      __syncthreads();
+    auto shift_b = [&]() {
 #pragma unroll
       for (int b = 0; b < NB; ++b) {
         ybh[b] = nbh[b];
         ybl[b] = nbl[b];
+      }
+    };
+    if constexpr (NPS == 1) {
+      if (stages > 0) {
+        ensure_table(0);
+        gload_s(0, psv[0]);
+        gload_b(0, ybh, ybl);
+        lstore(0, psv[0]);
+      }
+      __syncthreads();
+      for (int st = 0; st < stages; ++st) {
+        const bool more = st + 1 < stages;
+        if (more) {
+          ensure_table((st + 1) * KS);
+          gload_s(st + 1, psv[0]);
+          gload_b(st + 1, nbh, nbl);
+        }
+        if (active) compute(st & 1);
+        if (more) lstore((st + 1) & 1, psv[0]);
+        __syncthreads();
+        shift_b();
+      }
+    } else {
+      // stage s sits in LDS buffer s & 1; while it is computed, stage s + 1
+      // waits in registers (slot (s + 1) & 1) and stage s + 2 is loading
+      // (slot s & 1); two stages per turn keep the slot indices constant
+      if (stages > 0) {
+        ensure_table(0);
+        gload_s(0, psv[0]);
+        gload_b(0, ybh, ybl);
+        lstore(0, psv[0]);
+        if (stages > 1) {
+          ensure_table(KS);
+          gload_s(1, psv[1]);
+        }
+      }
+      __syncthreads();
+      for (int st = 0; st < stages; st += 2) {
+        if (st + 2 < stages) {
+          ensure_table((st + 2) * KS);
+          gload_s(st + 2, psv[0]);
+        }
+        if (st + 1 < stages) gload_b(st + 1, nbh, nbl);
+        if (active) compute(0);
+        if (st + 1 < stages) lstore(1, psv[1]);
+        __syncthreads();
+        shift_b();
+        if (st + 1 >= stages) break;
+        if (st + 3 < stages) {
+          ensure_table((st + 3) * KS);
+          gload_s(st + 3, psv[1]);
+        }
+        if (st + 2 < stages) gload_b(st + 2, nbh, nbl);
+        if (active) compute(1);
+        if (st + 2 < stages) lstore(0, psv[0]);
+        __syncthreads();
+        shift_b();
       }
     }
     if (!active) continue;

@@ -1046,12 +1046,15 @@ __global__ __launch_bounds__(kHhThreads) void tridiag_kernel(const LzNode* __res
       const double v0 = sv[r], v1 = sv[r + 1], w0 = sw[r], w1 = sw[r + 1];
       double* col = A + r;
       int j = k + 1 + cg;
-      for (; j + 3 * kHhGroups < m; j += 4 * kHhGroups) {
-        dv2 a[4];
+      // eight columns' loads issued before any of their stores (a store
+      // to A keeps later loads of A from moving above it)
+      constexpr int U = 8;
+      for (; j + (U - 1) * kHhGroups < m; j += U * kHhGroups) {
+        dv2 a[U];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) a[u] = *(gptr<dv2>)as_global(col + (int64_t)(j + u * kHhGroups) * lda);
+        for (int u = 0; u < U; ++u) a[u] = *(gptr<dv2>)as_global(col + (int64_t)(j + u * kHhGroups) * lda);
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < U; ++u) {
           const int jj = j + u * kHhGroups;
           const double vj = sv[jj], wj = sw[jj], nj = nv[jj];
           const double a0 = a[u][0] - (v0 * wj + w0 * vj), a1 = a[u][1] - (v1 * wj + w1 * vj);
