@@ -61,7 +61,7 @@ __device__ __forceinline__ void run4(const float* p, int64_t avail, float (&out)
 // multiple of 32, N of 128): operand runs are loaded without guards or
 // branches (rows past n only reach outputs that are never stored or summed).
 template <int C, bool NARROW, bool RES = false, bool DENSE = false>
-__global__ __launch_bounds__(256) void lift_kernel(const LiftNode* __restrict__ nodes, int num_nodes) {
+__global__ __launch_bounds__(256, (C == 0) ? 2 : 1) void lift_kernel(const LiftNode* __restrict__ nodes, int num_nodes) {
   static_assert(!RES || (C == 0 && !NARROW), "residual mode: FP64 128 x 128 tiles");
   static_assert(!DENSE || (C == 0 && !NARROW), "dense mode: FP64 128 x 128 tiles");
   constexpr int TMk = NARROW ? 4 * WT : TM;
@@ -176,7 +176,7 @@ __global__ __launch_bounds__(256) void lift_kernel(const LiftNode* __restrict__ 
       }
     };
     // batches of U MFMA steps of 4 reduction indices each
-    constexpr int U = 4, KB = 4 * U;
+    constexpr int U = (C == 0) ? 1 : 4, KB = 4 * U;
     Elem xa[2][U][4];
     BElem xb[2][U][4];
     auto load = [&](int kb, Elem (&va)[U][4], BElem (&vb)[U][4]) {
@@ -237,6 +237,9 @@ __global__ __launch_bounds__(256) void lift_kernel(const LiftNode* __restrict__ 
           ssq[b] += d * d;
         }
       }
+      // one column block's reads at a time: hoisting all sixteen runs of T
+      // above the products would take 128 more registers
+      __builtin_amdgcn_sched_barrier(0);
     }
     continue;
   }
