@@ -260,6 +260,22 @@ struct Blob {
 // ---------------------------------------------------------------------------
 // One batch of local PODs (all nodes of a level, or a single node).
 // ---------------------------------------------------------------------------
+// The dense lift's preconditions on one column table: every column holds
+// all n rows, readable to the next multiple of 128 (a plain column only when
+// n is a multiple of 128), every column and row block starts 16-byte aligned.
+bool dense_cols(int64_t n, int64_t m, const void* const* p, const int64_t* rbs, const int64_t* rows) {
+  for (int64_t j = 0; j < m; ++j) {
+    if (rows[j] != n || ((uintptr_t)p[j] & 15u) != 0 || (rbs[j] & 1) != 0) return false;
+    if (rbs[j] == kRowBlock && n % kRowBlock != 0) return false;
+  }
+  return true;
+}
+// ... and on the sizes: m a multiple of 8, the operand's rows whole aligned
+// runs of 4 (ldb a multiple of 4, or N a multiple of 128 with ldb even).
+bool dense_sizes(int64_t m, int64_t N, int64_t ldb) {
+  return m % 8 == 0 && (ldb % 4 == 0 || (N % kLiftTileN == 0 && ldb % 2 == 0));
+}
+
 struct PodJob {
   // inputs
   std::vector<const void*> cols;  // host copy of the column pointers
@@ -1083,6 +1099,15 @@ hapod_status run_pod_batch_impl(hapod_precision prec, std::vector<PodJob>& jobs,
   // peak's share of HBM bandwidth once N passes about 40, while the BF16
   // products keep it bandwidth-bound (the operand is split once, below)
   const int lift_compute = (compute == 2 && !split_lift) ? 1 : compute;
+  // FP64: the 128 x 128 lift takes the unguarded loads when every node's
+  // columns and sizes allow them
+  bool lift_dense = (lift_compute == 0);
+  for (int i = 0; i < nj && lift_dense; ++i) {
+    const PodJob& j = jobs[i];
+    if (j.m <= 0 || j.n <= 0) continue;
+    lift_dense = dense_sizes(j.m, j.m, tnodes[i].ldb) && (((uintptr_t)tnodes[i].B & 15u) == 0) &&
+                 dense_cols(j.n, j.m, j.cols.data(), j.rbs.data(), j.crows.data());
+  }
   // ---- a device-driven batch as a hipGraph: replay the one captured at this
   // position when everything the launches read hashes the same, else capture
   GraphCache* gc = (dev && gcache && gcache->on) ? gcache : nullptr;
@@ -1312,7 +1337,10 @@ hapod_status run_pod_batch_impl(hapod_precision prec, std::vector<PodJob>& jobs,
       for (int i = 0; i < nj; ++i) max_m = std::max(max_m, jobs[i].m);
       HAPOD_TRY(launch_split_operand((const LiftNode*)dlift, (int)(nl0 + nl1), max_m, ls));
     }
-    if (nl0) HAPOD_TRY(launch_lift(lift_compute, (const LiftNode*)dlift, (int)nl0, lift_items[0], ls, false));
+    if (nl0 && lift_dense)
+      HAPOD_TRY(launch_lift_dense((const LiftNode*)dlift, (int)nl0, lift_items[0], ls));
+    else if (nl0)
+      HAPOD_TRY(launch_lift(lift_compute, (const LiftNode*)dlift, (int)nl0, lift_items[0], ls, false));
     if (nl1)
       HAPOD_TRY(launch_lift(lift_compute, (const LiftNode*)dlift + nl0, (int)nl1, lift_items[1], ls, true));
     if (tev) HAPOD_HIP(hipEventRecord(ev.e[4], stream));
@@ -1542,12 +1570,7 @@ struct Cols {
 // with a stride of at least 128 rows per column, or n a multiple of 128),
 // starts 16-byte aligned; m a multiple of 32, N of 128, ldb of 2.
 bool dense_ok(int64_t n, const Cols& A, int64_t N, int64_t ldb) {
-  if (A.size() % 32 != 0 || N % kLiftTileN != 0 || ldb % 2 != 0) return false;
-  for (int64_t j = 0; j < A.size(); ++j) {
-    if (A.rows[(size_t)j] != n || ((uintptr_t)A.p[(size_t)j] & 15u) != 0) return false;
-    if (A.rbs[(size_t)j] == kRowBlock && n % kRowBlock != 0) return false;
-  }
-  return true;
+  return dense_sizes(A.size(), N, ldb) && dense_cols(n, A.size(), A.p.data(), A.rbs.data(), A.rows.data());
 }
 
 // out = A B[:, :N] in FP64: A an n-row column table of m columns, B
@@ -1592,7 +1615,7 @@ hapod_status lift_cols(Pool& pool, int64_t n, const Cols& A, const double* B, in
     }
     if (st == HAPOD_OK) st = launch_set_scalar_i64((int64_t*)dk, N, stream);
     if (st == HAPOD_OK)
-      st = dense_ok(n, A, N, ldb) && ((uintptr_t)B & 15u) == 0 ? launch_lift_dense((const LiftNode*)dn, items, stream)
+      st = dense_ok(n, A, N, ldb) && ((uintptr_t)B & 15u) == 0 ? launch_lift_dense((const LiftNode*)dn, 1, items, stream)
                                                                  : launch_lift(0, (const LiftNode*)dn, 1, items, stream);
     if (hipStreamSynchronize(stream) != hipSuccess && st == HAPOD_OK) {
       set_error("lift: stream synchronisation failed");
@@ -3455,7 +3478,9 @@ hapod_status hapod_lift(hapod_precision prec, int64_t n, int64_t m, int64_t N, c
   HAPOD_TRY(pool.alloc(sizeof(int64_t) * std::max<int64_t>(m, 1), &drows));
   HAPOD_TRY(launch_fill_i64((int64_t*)drbs, kRowBlock, m, stream));
   HAPOD_TRY(launch_fill_i64((int64_t*)drows, n, m, stream));
-  HAPOD_TRY(pool.alloc(sizeof(double) * std::max<int64_t>(m * N, 1), &dB));
+  // FP64: the operand's rows padded to whole runs of 4, for the dense lift
+  const int64_t ldbB = (prec == HAPOD_FP64) ? (N + 3) / 4 * 4 : N;
+  HAPOD_TRY(pool.alloc(sizeof(double) * std::max<int64_t>(m * ldbB, 1), &dB));
   if (prec != HAPOD_FP64) HAPOD_TRY(pool.alloc(sizeof(float) * std::max<int64_t>(m * N, 1), &dB32));
   void* dBs = nullptr;
   if (prec == HAPOD_BF16X3) HAPOD_TRY(pool.alloc(std::max<size_t>(split_operand_bytes(m), 128), &dBs));
@@ -3471,7 +3496,7 @@ hapod_status hapod_lift(hapod_precision prec, int64_t n, int64_t m, int64_t N, c
   l.rank = (const int64_t*)drank;
   l.out = out;
   l.n = n;
-  l.ldb = N;
+  l.ldb = ldbB;
   l.ocs = ldo;
   l.obs = kRowBlock;
   l.m = (int32_t)m;
@@ -3490,7 +3515,7 @@ hapod_status hapod_lift(hapod_precision prec, int64_t n, int64_t m, int64_t N, c
       st = HAPOD_E_DEVICE;
       break;
     }
-    st = launch_lift_operand(V, ldv, lambda, m, N, (double*)dB, (float*)dB32, N, stream);
+    st = launch_lift_operand(V, ldv, lambda, m, N, (double*)dB, (float*)dB32, ldbB, stream);
     if (st != HAPOD_OK) break;
     st = launch_set_scalar_i64((int64_t*)drank, N, stream);
     if (st != HAPOD_OK) break;
@@ -3498,8 +3523,12 @@ hapod_status hapod_lift(hapod_precision prec, int64_t n, int64_t m, int64_t N, c
       st = launch_split_operand((const LiftNode*)dn, 1, m, stream);
       if (st != HAPOD_OK) break;
     }
-    st = launch_lift(prec == HAPOD_FP64 ? 0 : (dBs ? 2 : 1), (const LiftNode*)dn, 1, l.row_tiles * l.col_tiles,
-                     stream);
+    const bool dense = prec == HAPOD_FP64 && dense_sizes(m, N, ldbB) &&
+                       dense_cols(n, m, cols.data(), std::vector<int64_t>((size_t)m, kRowBlock).data(),
+                                  std::vector<int64_t>((size_t)m, n).data());
+    st = dense ? launch_lift_dense((const LiftNode*)dn, 1, l.row_tiles * l.col_tiles, stream)
+               : launch_lift(prec == HAPOD_FP64 ? 0 : (dBs ? 2 : 1), (const LiftNode*)dn, 1, l.row_tiles * l.col_tiles,
+                             stream);
   } while (0);
   (void)hipStreamSynchronize(stream);
   pool.free(dcols);

@@ -254,11 +254,14 @@ hapod_status launch_split_operand(const LiftNode* d_nodes, int num_nodes, int64_
 inline size_t split_operand_bytes(int64_t m) { return (size_t)((m + 31) / 32) * 128 * (size_t)m; }
 // Residual mode of the FP64 lift (see LiftNode::rcols), one node.
 // dense: every column of the node holds all n rows, may be read to the next
-// multiple of 128 rows, starts 16-byte aligned, m is a multiple of 32 and N of
-// 128 (the operand loads then carry no guards).
+// multiple of 128 rows, every column and row block starts 16-byte aligned,
+// m is a multiple of 8, and the operand B starts 16-byte aligned with ldb a
+// multiple of 4 (or N a multiple of 128 and ldb even): the operand loads then
+// carry no guards.
 hapod_status launch_lift_residual(const LiftNode* d_node, int num_items, hipStream_t stream, bool dense = false);
-// The FP64 lift of one node under the dense conditions above.
-hapod_status launch_lift_dense(const LiftNode* d_node, int num_items, hipStream_t stream);
+// The FP64 lift (128 x 128 tiles) of nodes that all meet the dense conditions
+// above.
+hapod_status launch_lift_dense(const LiftNode* d_nodes, int num_nodes, int num_items, hipStream_t stream);
 // res[c] = sum over g < groups of rpart[g * N + c], in order of g
 hapod_status launch_sum_partials(const double* rpart, int64_t groups, int64_t N, double* res, hipStream_t stream);
 

@@ -56,10 +56,12 @@ __device__ __forceinline__ void run4(const float* p, int64_t avail, float (&out)
 // RES: the residual mode (LiftNode::rcols): the product is compared with the
 // node's second matrix instead of being stored.
 // DENSE: every column holds all n rows and may be read to the next multiple
-// of 128 rows (row-block-tiled, or n a multiple of 128), every column starts
-// 16-byte aligned, and m, N and the row-block strides are whole tiles (m a
-// multiple of 32, N of 128): operand runs are loaded without guards or
-// branches (rows past n only reach outputs that are never stored or summed).
+// of 128 rows (row-block-tiled, or n a multiple of 128), every column and
+// every row block starts 16-byte aligned, m is a multiple of 8, and the lift
+// operand's rows are whole aligned runs (ldb a multiple of 4, or N a multiple
+// of 128 with ldb even): operand runs are loaded without guards or branches
+// (rows past n and columns past N only reach outputs that are never stored
+// or summed).
 template <int C, bool NARROW, bool RES = false, bool DENSE = false>
 __global__ __launch_bounds__(256, (C == 0) ? 2 : 1) void lift_kernel(const LiftNode* __restrict__ nodes, int num_nodes) {
   static_assert(!RES || (C == 0 && !NARROW), "residual mode: FP64 128 x 128 tiles");
@@ -163,7 +165,9 @@ __global__ __launch_bounds__(256, (C == 0) ? 2 : 1) void lift_kernel(const LiftN
     };
     auto brun = [&](int k, BElem (&y)[4]) {
       if constexpr (DENSE) {
-        const BElem* p = bop + (int64_t)k * nd.ldb + nl;
+        // runs past the operand's row (columns >= N, never stored) read
+        // the row's last run instead
+        const BElem* p = bop + (int64_t)k * nd.ldb + min(nl, nd.ldb - 4);
         const dv2 u = *(gptr<dv2>)as_global(p);
         const dv2 v = *(gptr<dv2>)as_global(p + 2);
         y[0] = u[0]; y[1] = u[1]; y[2] = v[0]; y[3] = v[1];
@@ -206,7 +210,11 @@ __global__ __launch_bounds__(256, (C == 0) ? 2 : 1) void lift_kernel(const LiftN
     for (int kb = kc; kb < kend; kb += 2 * KB) {
       load(kb + KB, xa[1], xb[1]);
       compute(xa[0], xb[0]);
-      if (kb + 2 * KB < kend) load(kb + 2 * KB, xa[0], xb[0]);
+      // dense: the refill is unconditional (the last one re-reads the chunk's
+      // last batch, unused), so each wait is for a fixed count of loads and
+      // the refill stays in flight under the next batch's products
+      if constexpr (DENSE) load(min(kb + 2 * KB, kend - KB), xa[0], xb[0]);
+      else if (kb + 2 * KB < kend) load(kb + 2 * KB, xa[0], xb[0]);
       compute(xa[1], xb[1]);
     }
   }
@@ -839,9 +847,10 @@ hapod_status launch_split_operand(const LiftNode* d_nodes, int num_nodes, int64_
   return HAPOD_OK;
 }
 
-hapod_status launch_lift_dense(const LiftNode* d_node, int num_items, hipStream_t stream) {
-  if (num_items <= 0) return HAPOD_OK;
-  hipLaunchKernelGGL((lift_kernel<0, false, false, true>), dim3(num_items), dim3(256), 0, stream, d_node, 1);
+hapod_status launch_lift_dense(const LiftNode* d_nodes, int num_nodes, int num_items, hipStream_t stream) {
+  if (num_items <= 0 || num_nodes <= 0) return HAPOD_OK;
+  hipLaunchKernelGGL((lift_kernel<0, false, false, true>), dim3(num_items), dim3(256), 0, stream, d_nodes,
+                     num_nodes);
   HAPOD_HIP(hipGetLastError());
   return HAPOD_OK;
 }

@@ -160,8 +160,12 @@ def test_truncate_empty(hp):
 
 
 # -------------------------------------------------------------------- lift ---
+# (4096, 96, 81) and (2048, 200, 171): FP64 on the unguarded (dense) lift,
+# whose operand runs past the padded row width (columns >= N) re-read the
+# row's last run; one and two column tiles
 @pytest.mark.parametrize("prec,rtol", [("fp64", 1e-13), ("fp32", 1e-5), ("bf16x3", 1e-4)])
-@pytest.mark.parametrize("n,m,N", [(1, 1, 1), (100, 7, 3), (4097, 130, 129), (300, 256, 200), (64, 40, 0)])
+@pytest.mark.parametrize("n,m,N", [(1, 1, 1), (100, 7, 3), (4097, 130, 129), (300, 256, 200), (64, 40, 0),
+                                   (4096, 96, 81), (2048, 200, 171)])
 def test_lift_against_numpy(hp, prec, rtol, n, m, N):
     rng = np.random.default_rng(n + m + N)
     S = rng.standard_normal((n, m))
@@ -250,6 +254,30 @@ def test_node_pod_against_svd_oracle(hp, n, m):
     assert len(s) == len(s_ref) == k + 1
     np.testing.assert_allclose(s, s_ref, rtol=1e-10)
     assert metrics.subspace_error(U_ref, host(U), len(s)) < 1e-9
+    assert metrics.orthonormality_error(host(U)) < 1e-9
+    s2, W = hp.hapod_node_pod("fp64", dev_colmajor(S), eps, scaled=True)
+    np.testing.assert_allclose(host(W), host(U) * s, rtol=0, atol=1e-12 * sigma[0])
+
+
+@pytest.mark.parametrize("n,m,k", [(4096, 96, 80), (2048, 200, 170)])
+def test_node_pod_dense_batch_lift(hp, n, m, k):
+    """FP64 nodes whose lift takes the unguarded loads (n a multiple of 128,
+    m of 8) at ranks above 64, one and two column tiles: ranks, sigma and
+    modes against the SVD oracle within the method of snapshots' own error
+    (eigenvalues to about m u sigma_1^2, Rem. 2.3), scaled against unscaled
+    modes."""
+    from oracle import metrics, pod
+    r = min(n, m)
+    sigma = 10.0 * 0.98 ** np.arange(r)
+    S = prescribed_svd(n, m, sigma, n + m)
+    eps = math.sqrt(0.5 * (np.sum(sigma[k:] ** 2) + np.sum(sigma[k + 1:] ** 2)))
+    s_ref, U_ref = pod.pod(S, eps)
+    s, U = hp.hapod_node_pod("fp64", dev_colmajor(S), eps)
+    assert len(s) == len(s_ref) == k + 1
+    floor = 64 * m * np.finfo(float).eps * sigma[0] ** 2  # eigenvalue error allowance
+    np.testing.assert_allclose(s, s_ref, rtol=0, atol=floor / s_ref[-1])
+    gap = sigma[k] ** 2 - sigma[k + 1] ** 2  # at the truncation
+    assert metrics.subspace_error(U_ref, host(U), len(s)) < floor / gap
     assert metrics.orthonormality_error(host(U)) < 1e-9
     s2, W = hp.hapod_node_pod("fp64", dev_colmajor(S), eps, scaled=True)
     np.testing.assert_allclose(host(W), host(U) * s, rtol=0, atol=1e-12 * sigma[0])
