@@ -320,37 +320,23 @@ __global__ __launch_bounds__(kOsjThreads) void osj_finish_kernel(const double* X
 // positive, marks the column as dependent (its row of R becomes e_k).
 // Right-looking elimination over all (i, j) of the trailing triangle at
 // once, then R^-1 row by row from the bottom with each dot product split
-// over 8 lanes.  kLds: both triangles packed in LDS (column-packed upper,
-// (i, j) at j (j + 1) / 2 + i), N <= kCholLdsMaxN; otherwise in place in W
-// and Rinv (workgroup-scope barriers order the global reads and writes).
-template <bool kLds>
+// over 8 lanes; in place in W and Rinv (workgroup-scope barriers order the
+// global reads and writes).  For N above kCholLdsMaxN; the blocked kernel
+// below takes the smaller ones.
 __global__ __launch_bounds__(1024) void chol_inv_wg_kernel(double* W, int64_t ldw, int N, double* Rinv, int64_t ldr,
                                                            int32_t* bad, double rel_floor) {
-  extern __shared__ double ch_lds[];
-  const int np = N * (N + 1) / 2;
   __shared__ double d0s[kCholWgMaxN];
   __shared__ double piv;
   __shared__ int nbad;
   const int t = threadIdx.x;
-  auto P = [&](int i, int j) -> double& {
-    return kLds ? ch_lds[j * (j + 1) / 2 + i] : W[(int64_t)j * ldw + i];
-  };
-  auto Iv = [&](int i, int j) -> double& {
-    return kLds ? ch_lds[np + j * (j + 1) / 2 + i] : Rinv[(int64_t)i * ldr + j];
-  };
+  auto P = [&](int i, int j) -> double& { return W[(int64_t)j * ldw + i]; };
+  auto Iv = [&](int i, int j) -> double& { return Rinv[(int64_t)i * ldr + j]; };
   auto unpack = [](int e, int& i, int& j) {
     j = (int)((sqrtf(8.0f * (float)e + 1.0f) - 1.0f) * 0.5f);
     while (j * (j + 1) / 2 > e) --j;
     while ((j + 1) * (j + 2) / 2 <= e) ++j;
     i = e - j * (j + 1) / 2;
   };
-  if (kLds) {
-    for (int e = t; e < np; e += 1024) {
-      int i, j;
-      unpack(e, i, j);
-      ch_lds[e] = W[(int64_t)j * ldw + i];
-    }
-  }
   for (int k = t; k < N; k += 1024) d0s[k] = W[(int64_t)k * ldw + k];
   if (t == 0) nbad = 0;
   __syncthreads();
@@ -393,17 +379,145 @@ __global__ __launch_bounds__(1024) void chol_inv_wg_kernel(double* W, int64_t ld
     }
     __syncthreads();
   }
-  if (kLds) {
-    for (int e = t; e < N * N; e += 1024) {
-      const int j = e / N, i = e - j * N;
-      if (i <= j) W[(int64_t)j * ldw + i] = P(i, j);
-      Rinv[(int64_t)i * ldr + j] = (i <= j) ? Iv(i, j) : 0.0;
+  for (int e = t; e < N * N; e += 1024) {
+    const int j = e / N, i = e - j * N;
+    if (i > j) Rinv[(int64_t)i * ldr + j] = 0.0;
+  }
+  if (t == 0 && bad) *bad = nbad;
+}
+
+// The same factorisation and inverse for N <= kCholLdsMaxN, blocked in
+// panels of 16 rows so that the workgroup meets at a few barriers per panel
+// instead of several per column (one workgroup of 1024 threads).
+//   Panel p (rows p0 .. p0 + 15): wavefront 0 factors the panel's rows over
+//   all columns p0 .. N - 1 in registers (lane l holds columns p0 + l and
+//   p0 + l + 64; the pivot and the panel's own entries travel by lane
+//   shuffles), with the same pivot rule as above; then every thread updates
+//   the trailing triangle by the panel's 16 rows.
+//   R^-1: the 16 x 16 diagonal blocks by back substitution (one wavefront
+//   per block, one lane per column), then the blocks at distance d = 1, 2,
+//   ... from the diagonal: X_IJ = -X_II sum_{I < L <= J} R_IL X_LJ.
+// Both triangles packed in LDS (column-packed upper: (i, j) at
+// j (j + 1) / 2 + i).
+constexpr int kCholPanel = 16;
+__global__ __launch_bounds__(1024) void chol_inv_blk_kernel(double* W, int64_t ldw, int N, double* Rinv, int64_t ldr,
+                                                            int32_t* bad, double rel_floor) {
+  extern __shared__ double cb_lds[];
+  constexpr int PB = kCholPanel;
+  constexpr int kMaxBlk = kCholLdsMaxN / PB;
+  __shared__ double d0[kCholLdsMaxN];
+  __shared__ double T[kMaxBlk - 1][PB][PB];
+  const int np = N * (N + 1) / 2;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  auto P = [&](int i, int j) -> double& { return cb_lds[j * (j + 1) / 2 + i]; };
+  auto X = [&](int i, int j) -> double& { return cb_lds[np + j * (j + 1) / 2 + i]; };
+  for (int j = wave; j < N; j += 16)
+    for (int i = lane; i <= j; i += 64) P(i, j) = W[(int64_t)j * ldw + i];
+  for (int k = t; k < N; k += 1024) d0[k] = W[(int64_t)k * ldw + k];
+  __syncthreads();
+  int nbad = 0;  // counted by lane 0 of wavefront 0
+  for (int p0 = 0; p0 < N; p0 += PB) {
+    const int pw = min(PB, N - p0), pe = p0 + pw;
+    if (wave == 0) {
+      double v[PB][2];
+      int jc[2] = {p0 + lane, p0 + lane + 64};
+#pragma unroll
+      for (int r = 0; r < PB; ++r)
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+          v[r][c] = (r < pw && jc[c] < N && p0 + r <= jc[c]) ? P(p0 + r, jc[c]) : 0.0;
+#pragma unroll
+      for (int r = 0; r < PB; ++r) {
+        if (r >= pw) continue;  // (uniform; keeps the loop unrolled, v in registers)
+        const int k = p0 + r;
+        const double d = __shfl(v[r][0], r);  // column k: lane r, first slot
+        const bool b = !(d > rel_floor * d0[k]) || !(d > 0.0) || !isfinite(d);
+        const double piv = b ? 0.0 : sqrt(d);
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          if (jc[c] > k && jc[c] < N) v[r][c] = b ? 0.0 : v[r][c] / piv;
+          else if (jc[c] == k) v[r][c] = b ? 1.0 : piv;
+        }
+        nbad += b ? 1 : 0;
+#pragma unroll
+        for (int r2 = r + 1; r2 < PB; ++r2) {
+          if (r2 >= pw) continue;
+          const double sk = __shfl(v[r][0], r2);  // R(k, p0 + r2)
+#pragma unroll
+          for (int c = 0; c < 2; ++c)
+            if (jc[c] >= p0 + r2 && jc[c] < N) v[r2][c] -= sk * v[r][c];
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < PB; ++r)
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+          if (r < pw && jc[c] >= p0 + r && jc[c] < N) P(p0 + r, jc[c]) = v[r][c];
     }
-  } else {
-    for (int e = t; e < N * N; e += 1024) {
-      const int j = e / N, i = e - j * N;
-      if (i > j) Rinv[(int64_t)i * ldr + j] = 0.0;
+    __syncthreads();
+    // trailing triangle pe <= i <= j < N
+    for (int j = pe + (t >> 5); j < N; j += 32)
+      for (int i = pe + (t & 31); i <= j; i += 32) {
+        double s = 0.0;
+        for (int r = 0; r < pw; ++r) s += P(p0 + r, i) * P(p0 + r, j);
+        P(i, j) -= s;
+      }
+    __syncthreads();
+  }
+  // R^-1: diagonal blocks
+  const int nb = (N + PB - 1) / PB;
+  if (wave < nb && lane < PB) {
+    const int J0 = wave * PB, bw = min(PB, N - J0), jl = lane;
+    if (jl < bw) {
+      double x[PB];
+#pragma unroll
+      for (int i = 0; i < PB; ++i) x[i] = 0.0;
+#pragma unroll
+      for (int i = PB - 1; i >= 0; --i) {
+        if (i > jl) continue;
+        if (i == jl) {
+          x[i] = 1.0 / P(J0 + i, J0 + i);
+        } else {
+          double s = 0.0;
+#pragma unroll
+          for (int l = i + 1; l < PB; ++l)
+            if (l <= jl) s += P(J0 + i, J0 + l) * x[l];
+          x[i] = -s / P(J0 + i, J0 + i);
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < PB; ++i)
+        if (i <= jl) X(J0 + i, J0 + jl) = x[i];
     }
+  }
+  __syncthreads();
+  // blocks at distance d from the diagonal
+  for (int d = 1; d < nb; ++d) {
+    const int cnt = (nb - d) * PB * PB;
+    for (int e = t; e < cnt; e += 1024) {
+      const int I = e / (PB * PB), i = (e / PB) % PB, j = e % PB;
+      const int gi = I * PB + i, gj = (I + d) * PB + j;
+      double s = 0.0;
+      if (gi < N && gj < N)
+        for (int l = (I + 1) * PB; l <= gj; ++l) s += P(gi, l) * X(l, gj);
+      T[I][i][j] = s;
+    }
+    __syncthreads();
+    for (int e = t; e < cnt; e += 1024) {
+      const int I = e / (PB * PB), i = (e / PB) % PB, j = e % PB;
+      const int gi = I * PB + i, gj = (I + d) * PB + j;
+      if (gi < N && gj < N) {
+        double s = 0.0;
+        for (int l = i; l < PB && I * PB + l < N; ++l) s += X(gi, I * PB + l) * T[I][l][j];
+        X(gi, gj) = -s;
+      }
+    }
+    __syncthreads();
+  }
+  for (int e = t; e < N * N; e += 1024) {
+    const int j = e / N, i = e - j * N;
+    if (i <= j) W[(int64_t)j * ldw + i] = P(i, j);
+    Rinv[(int64_t)i * ldr + j] = (i <= j) ? X(i, j) : 0.0;
   }
   if (t == 0 && bad) *bad = nbad;
 }
@@ -449,14 +563,14 @@ hapod_status launch_chol_inv_wg(double* W, int64_t ldw, int64_t N, double* Rinv,
   if (N <= kCholLdsMaxN) {
     static bool attr = false;
     if (!attr) {
-      HAPOD_HIP(hipFuncSetAttribute((const void*)chol_inv_wg_kernel<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+      HAPOD_HIP(hipFuncSetAttribute((const void*)chol_inv_blk_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                                     (int)(sizeof(double) * kCholLdsMaxN * (kCholLdsMaxN + 1))));
       attr = true;
     }
-    hipLaunchKernelGGL(chol_inv_wg_kernel<true>, dim3(1), dim3(1024), sizeof(double) * N * (N + 1), stream, W, ldw,
+    hipLaunchKernelGGL(chol_inv_blk_kernel, dim3(1), dim3(1024), sizeof(double) * N * (N + 1), stream, W, ldw,
                        (int)N, Rinv, ldr, d_bad, rel_floor);
   } else {
-    hipLaunchKernelGGL(chol_inv_wg_kernel<false>, dim3(1), dim3(1024), 0, stream, W, ldw, (int)N, Rinv, ldr, d_bad,
+    hipLaunchKernelGGL(chol_inv_wg_kernel, dim3(1), dim3(1024), 0, stream, W, ldw, (int)N, Rinv, ldr, d_bad,
                        rel_floor);
   }
   HAPOD_HIP(hipGetLastError());

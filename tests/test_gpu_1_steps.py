@@ -186,11 +186,12 @@ def test_lift_against_numpy(hp, prec, rtol, n, m, N):
 
 
 # ------------------------------------------------------------------ reorth ---
-@pytest.mark.parametrize("N", [90, 300, 1024])
+@pytest.mark.parametrize("N", [17, 90, 128, 300, 1024])
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-13), ("fp32", 1e-5)])
 def test_reorth(hp, prec, tol, N):
-    """Cholesky with both triangles in LDS (N <= 128) and in place in global
-    memory (above), up to the 1024-column limit."""
+    """Cholesky blocked in 16-row panels with both triangles in LDS (N <= 128:
+    a partial panel, and eight whole ones) and in place in global memory
+    (above), up to the 1024-column limit."""
     rng = np.random.default_rng(2)
     Q, _ = np.linalg.qr(rng.standard_normal((5000, N)))
     U = Q + 1e-5 * rng.standard_normal(Q.shape)
