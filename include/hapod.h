@@ -192,27 +192,36 @@ hapod_status hapod_node_pod_qr(int64_t n, int64_t m, const double* S, int64_t ld
  * 2011), without the Gram eigenproblem whose squared condition number
  * (Rem. 2.3) limits the method of snapshots to sigma_k^2 above about
  * u sigma_1^2:
- *   Y = S Omega (Omega m x ell Gaussian from a counter-based generator and
- *   `seed`), Q = orth(Y) by Cholesky-QR passes (as hapod_node_pod_qr), B =
- *   Q^T S, r = ||S - Q B||_F^2 summed from the residual columns themselves,
- *   the SVD of B from the QR factor of B^T (Cholesky-QR passes, one-sided
- *   Jacobi on R'^T), modes Q U_B.
+ *   Y = S Omega, Q = orth(Y) by Cholesky-QR passes (as hapod_node_pod_qr),
+ *   B = Q^T S, r = ||S - Q B||_F^2 summed from the residual columns
+ *   themselves, the SVD of B from the QR factor of B^T (Cholesky-QR passes,
+ *   one-sided Jacobi on R'^T), modes Q U_B.
+ * Omega (m x ell), from counter-based generators and `seed`:
+ *   kind 0: the sparse sign map (Martinsson & Tropp, Acta Numerica 2020,
+ *     Sec. 9.2): 8 nonzeros +-1/sqrt(8) per row, one in each of 8 column
+ *     blocks of ell / 8, positions and signs from the splitmix64 finaliser;
+ *     Y costs one pass over S.  Should r exceed eps^2, the route starts over
+ *     with the Gaussian;
+ *   kind 1: Gaussian (Box-Muller over the splitmix64 finaliser).
  * Rank: the smallest N with r + sum_{k>N} sigma_k(B)^2 <= eps^2, so the
  * modes' projection error ||S - U U^T S||_F^2 = r + sum_{k>N} sigma_k(B)^2
  * is at most eps^2 (Def. 2.5's requirement, as used by Thm. 3.3 - 3.5).
  * FP64 only.  ell in {128, 256, 384, 512}, ell <= m, ell <= n
- * (HAPOD_E_UNSUPPORTED otherwise); eps > 0 (HAPOD_E_INVALID otherwise).
+ * (HAPOD_E_UNSUPPORTED otherwise); eps > 0 and kind 0 or 1
+ * (HAPOD_E_INVALID otherwise).
  *   S, lds, eps, scaled, out, ldo, sigma, rank   as hapod_node_pod (double);
  *           sigma and out need ell entries / columns of capacity.
- *   info6   host, may be NULL: {r, passes on Y, passes on B^T, Jacobi sweeps,
- *           device ms, ell}.
- * r > eps^2 (the rank of S within eps exceeds what ell columns capture):
- * HAPOD_E_UNSUPPORTED, info6 still filled.
- * Scratch: two n x ell double buffers, an m x ell Gaussian and B^T, partial
- * sums, from the library's pool.  Synchronises the stream.                 */
+ *   info7   host, may be NULL: {r, passes on Y, passes on B^T, Jacobi sweeps,
+ *           device ms, ell, the test matrix of the result (0 sparse sign,
+ *           1 Gaussian)}.
+ * r > eps^2 with the Gaussian (the rank of S within eps exceeds what ell
+ * columns capture): HAPOD_E_UNSUPPORTED, info7 still filled.
+ * Scratch: two n x ell double buffers, an m x ell Gaussian, the sign map's
+ * table and B^T, partial sums, from the library's pool.  Synchronises the
+ * stream.                                                                  */
 hapod_status hapod_node_pod_sketch(int64_t n, int64_t m, const double* S, int64_t lds, double eps,
-                                   int32_t scaled, int64_t ell, uint64_t seed, double* out, int64_t ldo,
-                                   double* sigma, int64_t* rank, double* info6, void* stream);
+                                   int32_t scaled, int64_t ell, uint64_t seed, int32_t kind, double* out,
+                                   int64_t ldo, double* sigma, int64_t* rank, double* info7, void* stream);
 
 /* ------------------------------------------------------------------------ */
 /* Tree-level entry points.                                                 */
@@ -303,6 +312,11 @@ typedef struct {
                                       graph; the phases of a graph-launched batch are not
                                       separated in hapod_run_timing (see
                                       hapod_plan_graph_stats).  0: plain launches.      */
+  int32_t sketch_kind;             /* test matrix of the sketched route (sketch_cols):
+                                      0: the sparse sign map (see
+                                      hapod_node_pod_sketch), the Gaussian if its
+                                      residual exceeds eps^2; 1: the Gaussian.  Other
+                                      values: HAPOD_E_INVALID.                          */
 } hapod_options;
 
 /* Validate the tree (Def. 3.1), compute levels (height: leaves are level 1),
@@ -423,11 +437,13 @@ typedef enum {
 hapod_status hapod_node_route(hapod_plan_t plan, int32_t node, int32_t* route);
 
 /* Diagnostics of a node that took the sketched route in the last run
- * (node = -1: the root).  out11: host, 11 doubles {ell, residual energy r,
+ * (node = -1: the root).  out12: host, 12 doubles {ell, residual energy r,
  * Cholesky-QR passes on Y, passes on B^T, Jacobi sweeps, then device ms of:
- * sketch Y = S Omega, Q = orth(Y), B = Q^T S, residual, small SVD, modes}.
+ * sketch Y = S Omega, Q = orth(Y), B = Q^T S, residual, small SVD, modes,
+ * then the test matrix of the result (0 sparse sign map, 1 Gaussian)}; the
+ * counts and times are those of the attempt that gave the result.
  * HAPOD_E_STATE if there is no completed run or the node took another route. */
-hapod_status hapod_sketch_stats(hapod_plan_t plan, int32_t node, double* out11);
+hapod_status hapod_sketch_stats(hapod_plan_t plan, int32_t node, double* out12);
 
 /* Per-node diagnostics of the last run, host, num_nodes entries each, any may
  * be NULL: input columns m, negative Gram eigenvalues, lambda_1, lambda_min. */

@@ -24,6 +24,8 @@ LIB_PATH = os.path.join(_HERE, "libhapod.so")
 FP64, FP32, BF16X3 = 0, 1, 2
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3}
 ROUTES = {0: "passthrough", 1: "snapshots", 2: "qr", 3: "sketch"}
+_SKETCH_KINDS = {"sparse_sign": 0, "gaussian": 1}
+_SKETCH_NAMES = {v: k for k, v in _SKETCH_KINDS.items()}
 STATUS = {0: "OK", 1: "E_INVALID", 2: "E_TREE", 3: "E_NOMEM", 4: "E_DEVICE", 5: "E_NUMERIC",
           6: "E_STATE", 7: "E_CALLBACK", 8: "E_UNSUPPORTED"}
 HAPOD_EIG_MAX = 8192
@@ -46,7 +48,7 @@ class HapodOptions(C.Structure):
                 ("node_eps_override", _pdbl), ("jacobi_max", _i32), ("autotune", _i32),
                 ("leaf_wave", _i32), ("block_gram", _i32), ("right_vectors", _i32),
                 ("qr_pod", _i32), ("sketch_cols", _i32), ("autotune_cache", C.c_char_p),
-                ("graph_levels", _i32)]
+                ("graph_levels", _i32), ("sketch_kind", _i32)]
 
 
 LEAF_FN = C.CFUNCTYPE(_i32, _vp, _i32, C.POINTER(_vp), _pi64, _vp)
@@ -66,7 +68,7 @@ _SIGS = {
     "hapod_node_stats": [_vp, _pi64, _pi64, _pdbl, _pdbl],
     "hapod_right_vectors": [_vp, _vp, _i64, _vp],
     "hapod_node_pod_qr": [_i64, _i64, _vp, _i64, C.c_double, _i32, _vp, _i64, _pdbl, _pi64, _pi32, _pi32, _vp],
-    "hapod_node_pod_sketch": [_i64, _i64, _vp, _i64, _dbl, _i32, _i64, C.c_uint64, _vp, _i64, _pdbl, _pi64, _pdbl,
+    "hapod_node_pod_sketch": [_i64, _i64, _vp, _i64, _dbl, _i32, _i64, C.c_uint64, _i32, _vp, _i64, _pdbl, _pi64, _pdbl,
                               _vp],
     "hapod_sketch_stats": [_vp, _i32, _pdbl],
     "hapod_plan_workspace": [_vp, _pi64, _pi64],
@@ -241,10 +243,11 @@ def hapod_node_pod_qr(S, eps, scaled=False, out=None, stream=None):
     return sig[:r.value].copy(), out[:, :r.value], {"passes": npass.value, "sweeps": sw.value}
 
 
-def hapod_node_pod_sketch(S, eps, ell, seed=0, scaled=False, out=None, stream=None):
+def hapod_node_pod_sketch(S, eps, ell, seed=0, scaled=False, out=None, stream=None, kind="sparse_sign"):
     """POD(S, eps) of a wide S by a randomized range finder with ell sketch
-    columns (FP64): returns (sigma[rank] numpy, out[:, :rank], {"residual",
-    "passes_y", "passes_b", "sweeps", "ms", "ell"})."""
+    columns (FP64), test matrix "sparse_sign" (Gaussian should its residual
+    exceed eps^2) or "gaussian": returns (sigma[rank] numpy, out[:, :rank],
+    {"residual", "passes_y", "passes_b", "sweeps", "ms", "ell", "kind"})."""
     import numpy as np
     ps, n, m, lds = _mat(S, "S", torch.float64)
     if out is None:
@@ -252,12 +255,14 @@ def hapod_node_pod_sketch(S, eps, ell, seed=0, scaled=False, out=None, stream=No
     po, _, _, ldo = _mat(out, "out", torch.float64)
     sig = np.zeros(max(int(ell), 1))
     r = C.c_int64(0)
-    info = np.zeros(6)
-    _check(_lib.hapod_node_pod_sketch(n, m, ps, lds, float(eps), int(bool(scaled)), int(ell), int(seed), po, ldo,
-                                      sig.ctypes.data_as(_pdbl), C.byref(r), info.ctypes.data_as(_pdbl),
-                                      _stream(stream)), "hapod_node_pod_sketch")
+    info = np.zeros(7)
+    _check(_lib.hapod_node_pod_sketch(n, m, ps, lds, float(eps), int(bool(scaled)), int(ell), int(seed),
+                                      _SKETCH_KINDS[kind], po, ldo, sig.ctypes.data_as(_pdbl), C.byref(r),
+                                      info.ctypes.data_as(_pdbl), _stream(stream)), "hapod_node_pod_sketch")
     keys = ("residual", "passes_y", "passes_b", "sweeps", "ms", "ell")
-    return sig[:r.value].copy(), out[:, :r.value], dict(zip(keys, info.tolist()))
+    d = dict(zip(keys, info.tolist()[:6]))
+    d["kind"] = _SKETCH_NAMES[int(info[6])]
+    return sig[:r.value].copy(), out[:, :r.value], d
 
 
 # ---------------------------------------------------------------------------
@@ -271,7 +276,7 @@ class Plan:
     def __init__(self, parent, leaf_cols, n, eps_star, omega, prec="fp64", reorth=False,
                  mem_cap_bytes=0, eps_override=None, jacobi_max=0, leaf_rows=None, leaf_wave=0,
                  autotune=False, block_gram=False, right_vectors=False, qr_pod=False, sketch_cols=0,
-                 autotune_cache=None, graph_levels=False):
+                 autotune_cache=None, graph_levels=False, sketch_kind="sparse_sign"):
         import numpy as np
         self.num_nodes = len(parent)
         self.n = int(n)
@@ -289,7 +294,8 @@ class Plan:
         opts = HapodOptions(self.prec, int(bool(reorth)), int(mem_cap_bytes), ov, int(jacobi_max),
                             int(bool(autotune)), int(leaf_wave), int(bool(block_gram)),
                             int(bool(right_vectors)), int(bool(qr_pod)), int(sketch_cols),
-                            os.fsencode(autotune_cache) if autotune_cache else None, int(bool(graph_levels)))
+                            os.fsencode(autotune_cache) if autotune_cache else None, int(bool(graph_levels)),
+                            _SKETCH_KINDS[sketch_kind])
         h = C.c_void_p()
         _check(_lib.hapod_plan(C.byref(tree), float(eps_star), float(omega), C.byref(opts), C.byref(h)),
                "hapod_plan")
@@ -425,14 +431,15 @@ class Plan:
 
     def sketch_stats(self, node=-1):
         """Diagnostics of a node that took the sketched route (dict), or None."""
-        out = (C.c_double * 11)()
+        out = (C.c_double * 12)()
         st = _lib.hapod_sketch_stats(self._h, int(node), out)
         if st == 6:
             return None
         _check(st, "hapod_sketch_stats")
         v = list(out)
         return dict(ell=int(v[0]), residual=v[1], passes_y=int(v[2]), passes_b=int(v[3]), sweeps=int(v[4]),
-                    ms=dict(zip(["sketch", "orth", "cross", "residual", "small_svd", "lift"], v[5:11])))
+                    ms=dict(zip(["sketch", "orth", "cross", "residual", "small_svd", "lift"], v[5:11])),
+                    kind=_SKETCH_NAMES[int(v[11])])
 
     def ranks(self):
         import numpy as np

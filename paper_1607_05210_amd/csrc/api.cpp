@@ -1493,6 +1493,7 @@ struct SketchInfo {
   int32_t passes_y = 0;    // Cholesky-QR passes on the sketch Y = S Omega
   int32_t passes_b = 0;    // and on B^T = S^T Q
   int32_t sweeps = 0;      // Jacobi sweeps on the small factor
+  int32_t kind = 0;        // test matrix of the result: 0 sparse sign map, 1 Gaussian
   float ms[6] = {0, 0, 0, 0, 0, 0};  // sketch, orthonormalisation, B, residual, small SVD, lift
 };
 
@@ -2108,7 +2109,7 @@ hapod_status orth_blocks(Pool& pool, int64_t n, int64_t ell, const double* Y, in
 // cols/rbs/crows: the node's input columns (host copies of device pointers).
 hapod_status sketch_pod_core(Pool& pool, int64_t n, int64_t m, const std::vector<const void*>& cols,
                              const std::vector<int64_t>& rbs, const std::vector<int64_t>& crows, int64_t ell,
-                             uint64_t seed, double eps, bool scaled,
+                             uint64_t seed, int32_t kind, double eps, bool scaled,
                              const std::function<hapod_status(int64_t, double**, int64_t*, int64_t*)>& out_for_rank,
                              std::vector<double>& sigma, int64_t* rank, SketchInfo* info, hipStream_t stream) {
   *rank = 0;
@@ -2136,35 +2137,77 @@ hapod_status sketch_pod_core(Pool& pool, int64_t n, int64_t m, const std::vector
       set_error("sketched POD: hipEventCreate failed");
       return finish(HAPOD_E_DEVICE);
     }
+  void *dcols = nullptr, *drbs = nullptr, *drows = nullptr, *tab = nullptr;
   const std::pair<size_t, void**> want[] = {
       {sizeof(double) * (size_t)m * ell, &Om}, {tiled_bytes(n, ell, 8), &Y}, {sizeof(double) * (size_t)m * ell, &Bt},
       {sizeof(double) * m, &res}, {ll, &Rb}, {ll, &M}, {ll, &UB}, {sizeof(double) * ell, &dsig},
-      {sizeof(int32_t) * 2, &dinfo}};
+      {sizeof(int32_t) * 2, &dinfo}, {sizeof(void*) * (size_t)m, &dcols}, {sizeof(int64_t) * (size_t)m, &drbs},
+      {sizeof(int64_t) * (size_t)m, &drows}, {sizeof(int32_t) * kSignNnz * (size_t)sign_table_ld(m), &tab}};
   for (const auto& w : want) {
     hapod_status st = pool.alloc(w.first, w.second);
     if (st != HAPOD_OK) return finish(st);
     held.push_back(*w.second);
   }
+  const size_t held_base = held.size();
+  int64_t full_rows = n;
+  for (int64_t r : crows) full_rows = std::min(full_rows, r);
+  if (hipMemcpyAsync(dcols, cols.data(), sizeof(void*) * m, hipMemcpyHostToDevice, stream) != hipSuccess ||
+      hipMemcpyAsync(drbs, rbs.data(), sizeof(int64_t) * m, hipMemcpyHostToDevice, stream) != hipSuccess ||
+      hipMemcpyAsync(drows, crows.data(), sizeof(int64_t) * m, hipMemcpyHostToDevice, stream) != hipSuccess) {
+    set_error("sketched POD: column table upload failed");
+    return finish(HAPOD_E_DEVICE);
+  }
   hapod_status st = HAPOD_OK;
-  (void)hipEventRecord(ev[0], stream);
-  // ---- Y = S Omega ------------------------------------------------------------
-  if ((st = launch_normal_fill((double*)Om, m * ell, seed, stream)) != HAPOD_OK ||
-      (st = lift_cols(pool, n, Sc, (const double*)Om, ell, ell, (double*)Y, kRowBlock, tiled_rbs(ell), stream)) !=
-          HAPOD_OK)
-    return finish(st);
-  (void)hipEventRecord(ev[1], stream);
-  // ---- Q = orth(Y) ---------------------------------------------------------------
+  // The sparse sign map first (one pass over S at memory speed instead of an
+  // n x m x ell product); should its residual exceed eps^2, the Gaussian
+  // test matrix (whose range captures the leading subspace with the least
+  // oversampling) from the start.  Either way the residual decides, exactly.
   Cols Q;
-  if ((st = orth_blocks(pool, n, ell, (const double*)Y, n, tiled_rbs(ell), nullptr, held, Q, &si.passes_y, stream)) !=
-      HAPOD_OK)
-    return finish(st);
-  (void)hipEventRecord(ev[2], stream);
-  // ---- B^T = S^T Q (row-major B, ell x m) -----------------------------------------------
-  if ((st = cross_cols(pool, n, Q, Sc, (double*)Bt, m, stream)) != HAPOD_OK) return finish(st);
-  (void)hipEventRecord(ev[3], stream);
-  // ---- residual energy per column: ||s_j - Q b_j||^2 --------------------------------
-  if ((st = residual_cols(pool, n, Q, (const double*)Bt, m, Sc, (double*)res, stream)) != HAPOD_OK) return finish(st);
-  (void)hipEventRecord(ev[4], stream);
+  si.kind = (kind == 1) ? 1 : 0;
+  for (;;) {
+    (void)hipEventRecord(ev[0], stream);
+    // ---- Y = S Omega ----------------------------------------------------------
+    if (si.kind == 0) {
+      if ((st = launch_sign_table((int32_t*)tab, m, ell, seed, stream)) != HAPOD_OK ||
+          (st = launch_sign_sketch((const void* const*)dcols, (const int64_t*)drbs, (const int64_t*)drows, n, m,
+                                   full_rows, (const int32_t*)tab, ell, (double*)Y, kRowBlock, tiled_rbs(ell),
+                                   stream)) != HAPOD_OK)
+        return finish(st);
+    } else if ((st = launch_normal_fill((double*)Om, m * ell, seed, stream)) != HAPOD_OK ||
+               (st = lift_cols(pool, n, Sc, (const double*)Om, ell, ell, (double*)Y, kRowBlock, tiled_rbs(ell),
+                               stream)) != HAPOD_OK) {
+      return finish(st);
+    }
+    (void)hipEventRecord(ev[1], stream);
+    // ---- Q = orth(Y) -------------------------------------------------------------
+    if ((st = orth_blocks(pool, n, ell, (const double*)Y, n, tiled_rbs(ell), nullptr, held, Q, &si.passes_y,
+                          stream)) != HAPOD_OK)
+      return finish(st);
+    (void)hipEventRecord(ev[2], stream);
+    // ---- B^T = S^T Q (row-major B, ell x m) ---------------------------------------
+    if ((st = cross_cols(pool, n, Q, Sc, (double*)Bt, m, stream)) != HAPOD_OK) return finish(st);
+    (void)hipEventRecord(ev[3], stream);
+    // ---- residual energy per column: ||s_j - Q b_j||^2 ------------------------------
+    if ((st = residual_cols(pool, n, Q, (const double*)Bt, m, Sc, (double*)res, stream)) != HAPOD_OK)
+      return finish(st);
+    (void)hipEventRecord(ev[4], stream);
+    if (si.kind == 1) break;
+    std::vector<double> r0((size_t)m);
+    if (hipMemcpyAsync(r0.data(), res, sizeof(double) * m, hipMemcpyDeviceToHost, stream) != hipSuccess ||
+        hipStreamSynchronize(stream) != hipSuccess) {
+      set_error("sketched POD: readback failed");
+      return finish(HAPOD_E_DEVICE);
+    }
+    double rs0 = 0.0;
+    for (double v : r0) rs0 += v;
+    if (rs0 <= eps * eps) break;
+    // the sparse map missed part of the range: its Q blocks go back, the
+    // Gaussian takes over
+    for (size_t q = held_base; q < held.size(); ++q) pool.free(held[q]);
+    held.resize(held_base);
+    Q = Cols{};
+    si.kind = 1;
+  }
   // ---- SVD of B through B^T = Q' R' -----------------------------------------------------
   Cols Qt;
   if ((st = orth_blocks(pool, m, ell, (const double*)Bt, m, 0, (double*)Rb, held, Qt, &si.passes_b, stream)) !=
@@ -2298,6 +2341,10 @@ hapod_status hapod_plan(const hapod_tree* tree, double eps_star, double omega, c
     // vectors, and its sketch is whole 128-column tiles up to the Jacobi
     // SVD's 512 columns
     set_error("hapod_plan: sketch_cols needs the FP64 form, excludes right_vectors, and must be 128, 256, 384 or 512");
+    return HAPOD_E_INVALID;
+  }
+  if (opts && opts->sketch_kind != 0 && opts->sketch_kind != 1) {
+    set_error("hapod_plan: sketch_kind must be 0 (sparse sign map, Gaussian fallback) or 1 (Gaussian)");
     return HAPOD_E_INVALID;
   }
   auto P = std::make_unique<hapod_plan_s>();
@@ -2787,7 +2834,8 @@ hapod_status hapod_run(hapod_plan_t P, hapod_leaf_fn get_leaf, void* user, void*
     SketchInfo si;
     // one seed per node: reruns draw the same test matrix
     const uint64_t seed = 0x6a09e667f3bcc909ull ^ ((uint64_t)a * 0x9e3779b97f4a7c15ull);
-    hapod_status st = sketch_pod_core(P->pool, j.n, j.m, j.cols, j.rbs, j.crows, P->opts.sketch_cols, seed, j.eps,
+    hapod_status st = sketch_pod_core(P->pool, j.n, j.m, j.cols, j.rbs, j.crows, P->opts.sketch_cols, seed,
+                                      P->opts.sketch_kind, j.eps,
                                       !j.root, out_for, sg, &N, &si, stream);
     if (st != HAPOD_OK) {
       if (outp) P->pool.free(outp);
@@ -3138,8 +3186,8 @@ hapod_status hapod_modes(hapod_plan_t P, int32_t node, void* U, int64_t ldu, dou
   return HAPOD_OK;
 }
 
-hapod_status hapod_sketch_stats(hapod_plan_t P, int32_t node, double* out11) {
-  if (!P || !out11) {
+hapod_status hapod_sketch_stats(hapod_plan_t P, int32_t node, double* out12) {
+  if (!P || !out12) {
     set_error("hapod_sketch_stats: NULL argument");
     return HAPOD_E_INVALID;
   }
@@ -3153,9 +3201,9 @@ hapod_status hapod_sketch_stats(hapod_plan_t P, int32_t node, double* out11) {
     return HAPOD_E_STATE;
   }
   const SketchInfo& k = P->sketch[a];
-  const double v[11] = {(double)k.ell, k.residual, (double)k.passes_y, (double)k.passes_b, (double)k.sweeps,
-                        k.ms[0], k.ms[1], k.ms[2], k.ms[3], k.ms[4], k.ms[5]};
-  std::memcpy(out11, v, sizeof(v));
+  const double v[12] = {(double)k.ell, k.residual, (double)k.passes_y, (double)k.passes_b, (double)k.sweeps,
+                        k.ms[0], k.ms[1], k.ms[2], k.ms[3], k.ms[4], k.ms[5], (double)k.kind};
+  std::memcpy(out12, v, sizeof(v));
   return HAPOD_OK;
 }
 
@@ -3712,7 +3760,8 @@ hapod_status hapod_plan_node_pod(hapod_plan_t P, int32_t node, const void* S, in
     const uint64_t seed = 0x6a09e667f3bcc909ull ^ ((uint64_t)a * 0x9e3779b97f4a7c15ull);
     std::vector<const void*> cols = column_table(S, lds, m, 8);
     std::vector<int64_t> rbs((size_t)m, kRowBlock), rows((size_t)m, n);
-    st = sketch_pod_core(P->pool, n, m, cols, rbs, rows, ell, seed, eps, !root, to_caller, sg, rank, nullptr, stream);
+    st = sketch_pod_core(P->pool, n, m, cols, rbs, rows, ell, seed, P->opts.sketch_kind, eps, !root, to_caller, sg,
+                         rank, nullptr, stream);
   } else if (P->opts.qr_pod && m <= kQrMaxM && m <= n) {
     st = qr_pod_core(P->pool, n, m, (double*)const_cast<void*>(S), lds, false, false, eps, !root, to_caller, sg, rank,
                      nullptr, nullptr, stream);
@@ -3783,8 +3832,8 @@ hapod_status hapod_node_pod_qr(int64_t n, int64_t m, const double* S, int64_t ld
 }
 
 hapod_status hapod_node_pod_sketch(int64_t n, int64_t m, const double* S, int64_t lds, double eps, int32_t scaled,
-                                   int64_t ell, uint64_t seed, double* out, int64_t ldo, double* sigma, int64_t* rank,
-                                   double* info6, void* stream_) {
+                                   int64_t ell, uint64_t seed, int32_t kind, double* out, int64_t ldo, double* sigma,
+                                   int64_t* rank, double* info7, void* stream_) {
   if (n < 0 || m < 0 || !(eps > 0.0) || !rank || lds < std::max<int64_t>(n, 1) || (m > 0 && n > 0 && (!S || !out)) ||
       ldo < std::max<int64_t>(n, 1)) {
     set_error("hapod_node_pod_sketch: bad sizes, eps <= 0 or NULL pointer");
@@ -3793,6 +3842,10 @@ hapod_status hapod_node_pod_sketch(int64_t n, int64_t m, const double* S, int64_
   if (ell < kGramTile || ell > kSketchMaxCols || ell % kGramTile != 0 || m < ell || n < ell) {
     set_error("hapod_node_pod_sketch: ell must be 128, 256, 384 or 512 and at most m and n");
     return HAPOD_E_UNSUPPORTED;
+  }
+  if (kind != 0 && kind != 1) {
+    set_error("hapod_node_pod_sketch: kind must be 0 (sparse sign map, Gaussian fallback) or 1 (Gaussian)");
+    return HAPOD_E_INVALID;
   }
   hipStream_t stream = (hipStream_t)stream_;
   *rank = 0;
@@ -3806,12 +3859,13 @@ hapod_status hapod_node_pod_sketch(int64_t n, int64_t m, const double* S, int64_
   std::vector<int64_t> rbs((size_t)m, kRowBlock), rows((size_t)m, n);
   std::vector<double> sg;
   SketchInfo si;
-  hapod_status st = sketch_pod_core(step_pool(), n, m, cols, rbs, rows, ell, seed, eps, scaled != 0, to_caller, sg,
-                                    rank, &si, stream);
-  if (info6) {
-    const double v[6] = {si.residual, (double)si.passes_y, (double)si.passes_b, (double)si.sweeps,
-                         (double)(si.ms[0] + si.ms[1] + si.ms[2] + si.ms[3] + si.ms[4] + si.ms[5]), (double)si.ell};
-    std::memcpy(info6, v, sizeof(v));
+  hapod_status st = sketch_pod_core(step_pool(), n, m, cols, rbs, rows, ell, seed, kind, eps, scaled != 0, to_caller,
+                                    sg, rank, &si, stream);
+  if (info7) {
+    const double v[7] = {si.residual, (double)si.passes_y, (double)si.passes_b, (double)si.sweeps,
+                         (double)(si.ms[0] + si.ms[1] + si.ms[2] + si.ms[3] + si.ms[4] + si.ms[5]), (double)si.ell,
+                         (double)si.kind};
+    std::memcpy(info7, v, sizeof(v));
   }
   if (st == HAPOD_OK && sigma && *rank > 0) std::memcpy(sigma, sg.data(), sizeof(double) * *rank);
   return st;

@@ -1,8 +1,10 @@
 // Helpers of the sketched local POD (randomized range finder, Halko,
-// Martinsson & Tropp, SIAM Review 2011): the Gaussian test matrix and a
-// square transpose.  The products of that route run on the Gram and lift
-// kernels (cross-product and residual modes).
+// Martinsson & Tropp, SIAM Review 2011): the sparse sign sketch Y = S Omega,
+// the Gaussian test matrix and a square transpose.  The other products of
+// that route run on the Gram and lift kernels (cross-product and residual
+// modes).
 #include "internal.hpp"
+#include "mfma.hpp"
 
 namespace hapod {
 namespace {
@@ -30,6 +32,110 @@ __global__ __launch_bounds__(256) void normal_fill_kernel(double* __restrict__ o
   sincospi(2.0 * u2, &s, &c);
   out[2 * i] = r * c;
   if (2 * i + 1 < count) out[2 * i + 1] = r * s;
+}
+
+// The sparse sign map (a sparse dimension reduction map with kSignNnz
+// nonzeros per row, Martinsson & Tropp, Acta Numerica 2020, Sec. 9.2): row k
+// of Omega (m x ell) holds +-1/sqrt(kSignNnz) in each of the kSignNnz
+// column blocks of width ell / kSignNnz, at the position and with the sign
+// drawn from the splitmix64 finaliser of the counter (seed, kSignNnz k + t).
+// sign_table_kernel writes, per (k, t), position + ell * (sign < 0) at
+// tab[t * sign_table_ld(m) + k].
+__device__ __forceinline__ uint64_t mix64(uint64_t x) {
+  x += 0x9e3779b97f4a7c15ull;
+  x = (x ^ (x >> 30)) * 0xbf58476d1ce4e5b9ull;
+  x = (x ^ (x >> 27)) * 0x94d049bb133111ebull;
+  return x ^ (x >> 31);
+}
+__global__ __launch_bounds__(256) void sign_table_kernel(int32_t* __restrict__ tab, int64_t m, int32_t ell,
+                                                         uint64_t seed) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;  // counter kSignNnz k + t
+  if (e >= m * kSignNnz) return;
+  const int t = (int)(e % kSignNnz);
+  const int64_t k = e / kSignNnz;
+  const uint32_t bw = (uint32_t)(ell / kSignNnz);
+  const uint64_t z = mix64((seed * 0xd1342543de82ef95ull) ^ (uint64_t)e);
+  const uint32_t pos = (uint32_t)(((z >> 32) * (uint64_t)bw) >> 32);  // uniform in [0, bw)
+  tab[t * sign_table_ld(m) + k] = (int32_t)(t * bw + pos) + ((z & 1u) ? ell : 0);
+}
+
+// Y = S Omega for the sparse sign map: one workgroup per 32-row slice of S,
+// whose 32 x ell slice of Y accumulates in LDS (rows padded to ell + 1
+// doubles against bank conflicts).  Thread (t, i) = (threadIdx.x / 32,
+// threadIdx.x % 32) owns row i's entries in column block t, so each entry is
+// summed by one thread, in input-column order (deterministic); the sums go
+// to LDS as atomic adds whose results are not returned, so consecutive
+// updates do not wait for each other (one lane per entry: the order is the
+// lane's program order).  A slice that every column holds in full reads
+// 32 contiguous rows per column with no guards, kSketchBatch columns and
+// their table entries loaded ahead of their use; other slices, and the
+// columns past the last whole batch pair, read one column at a time with
+// rows past a column's own count as zero.  Rows of Y past n are not
+// written.  Y element (r, c) at Y[c * ocs + blk_off(r, obs)].
+__global__ __launch_bounds__(256, 1) void sign_sketch_kernel(const void* const* __restrict__ cols,
+                                                          const int64_t* __restrict__ rbs,
+                                                          const int64_t* __restrict__ crows, int64_t n, int64_t m,
+                                                          int64_t full_rows, const int32_t* __restrict__ tab,
+                                                          int32_t ell, double* __restrict__ Y, int64_t ocs,
+                                                          int64_t obs) {
+  extern __shared__ double ys[];
+  constexpr int U = kSketchBatch;
+  const int i = threadIdx.x & 31, t = threadIdx.x >> 5;
+  const int ld = ell + 1;
+  const int bw = ell / kSignNnz;
+  const int64_t row = (int64_t)blockIdx.x * 32 + i;
+  double* yr = ys + i * ld;
+  for (int q = 0; q < bw; ++q) yr[t * bw + q] = 0.0;
+  // (each thread touches only its own entries: no barrier needed before use)
+  auto add = [&](int32_t e, double x) {
+    const bool neg = e >= ell;
+    atomicAdd(&yr[neg ? e - ell : e], neg ? -x : x);
+  };
+  const int64_t tld = sign_table_ld(m);
+  const int32_t* tr = tab + t * tld;  // this thread's block: entries of consecutive columns
+  int64_t k0 = 0;
+  if ((int64_t)blockIdx.x * 32 + 32 <= full_rows) {
+    typedef __attribute__((ext_vector_type(4))) int i4;
+    constexpr int UQ = U / 4;
+    const int64_t mm = m / (2 * U) * (2 * U);
+    auto ld_x = [&](int64_t k) -> double {
+      return *as_global(reinterpret_cast<const double*>(cols[k]) + blk_off(row, rbs[k]));
+    };
+    double xa[U], xb[U];
+    i4 ea[UQ], eb[UQ];
+    auto load = [&](int64_t k, double (&x)[U], i4 (&e)[UQ]) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) x[u] = ld_x(k + u);
+#pragma unroll
+      for (int q = 0; q < UQ; ++q) e[q] = *as_global(reinterpret_cast<const i4*>(tr + k + 4 * q));
+    };
+    auto apply = [&](const double (&x)[U], const i4 (&e)[UQ]) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) add(e[u / 4][u % 4], x[u]);
+    };
+    if (mm > 0) load(0, xa, ea);
+    for (; k0 < mm; k0 += 2 * U) {
+      load(k0 + U, xb, eb);
+      // (the barriers keep each batch's loads ahead of the adds before it)
+      __builtin_amdgcn_sched_barrier(0);
+      apply(xa, ea);
+      // the refill is unconditional: past the last pair it re-reads the
+      // final batch (unused)
+      load(min(k0 + 2 * U, mm - U), xa, ea);
+      __builtin_amdgcn_sched_barrier(0);
+      apply(xb, eb);
+    }
+  }
+  for (int64_t k = k0; k < m; ++k) {
+    const double* c = reinterpret_cast<const double*>(cols[k]);
+    const double x = (row < crows[k]) ? c[blk_off(row, rbs[k])] : 0.0;
+    add(tr[k], x);
+  }
+  __syncthreads();
+  // write the slice: column c, 32 consecutive rows per pass
+  const double scale = 1.0 / sqrt((double)kSignNnz);
+  for (int c = t; c < ell; c += 8)
+    if (row < n) Y[(int64_t)c * ocs + blk_off(row, obs)] = ys[i * ld + c] * scale;
 }
 
 __global__ __launch_bounds__(256) void transpose_kernel(const double* __restrict__ A, int64_t lda, int64_t m,
@@ -94,6 +200,45 @@ hapod_status launch_normal_fill(double* out, int64_t count, uint64_t seed, hipSt
   const int64_t pairs = (count + 1) / 2;
   hipLaunchKernelGGL(normal_fill_kernel, dim3((unsigned)((pairs + 255) / 256)), dim3(256), 0, stream, out, count,
                      seed);
+  HAPOD_HIP(hipGetLastError());
+  return HAPOD_OK;
+}
+
+hapod_status launch_sign_table(int32_t* tab, int64_t m, int64_t ell, uint64_t seed, hipStream_t stream) {
+  if (m <= 0) return HAPOD_OK;
+  if (ell % kSignNnz != 0 || ell <= 0 || ell > kSketchMaxCols) {
+    set_error("sparse sign sketch: ell must be a positive multiple of 8 up to 512");
+    return HAPOD_E_UNSUPPORTED;
+  }
+  const int64_t total = m * kSignNnz;
+  hipLaunchKernelGGL(sign_table_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, stream, tab, m, (int32_t)ell,
+                     seed);
+  HAPOD_HIP(hipGetLastError());
+  return HAPOD_OK;
+}
+
+hapod_status launch_sign_sketch(const void* const* d_cols, const int64_t* d_rbs, const int64_t* d_rows, int64_t n,
+                                int64_t m, int64_t full_rows, const int32_t* tab, int64_t ell, double* Y, int64_t ocs,
+                                int64_t obs, hipStream_t stream) {
+  if (n <= 0 || m <= 0) return HAPOD_OK;
+  if (ell % kSignNnz != 0 || ell <= 0 || ell > kSketchMaxCols) {
+    set_error("sparse sign sketch: ell must be a positive multiple of 8 up to 512");
+    return HAPOD_E_UNSUPPORTED;
+  }
+  const size_t lds = sizeof(double) * 32 * (size_t)(ell + 1);
+  static bool attr = false;
+  if (!attr) {
+    HAPOD_HIP(hipFuncSetAttribute((const void*)sign_sketch_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)(sizeof(double) * 32 * (kSketchMaxCols + 1))));
+    attr = true;
+  }
+  const int64_t slices = (n + 31) / 32;
+  if (slices > INT32_MAX) {
+    set_error("sparse sign sketch: too many rows");
+    return HAPOD_E_UNSUPPORTED;
+  }
+  hipLaunchKernelGGL(sign_sketch_kernel, dim3((unsigned)slices), dim3(256), lds, stream, d_cols, d_rbs, d_rows, n, m,
+                     full_rows, tab, (int32_t)ell, Y, ocs, obs);
   HAPOD_HIP(hipGetLastError());
   return HAPOD_OK;
 }

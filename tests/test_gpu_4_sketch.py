@@ -78,11 +78,13 @@ def check_node(S, s_g, U_g, eps, info, tag, rank_slack=0):
     assert pe <= eps * eps * (1 + 1e-6) + metrics.rounding_slack(S), (tag, pe, eps * eps)
 
 
+@pytest.mark.parametrize("kind", ["sparse_sign", "gaussian"])
 @pytest.mark.parametrize("n,m,r,ell", [(3000, 1200, 300, 384), (3001, 1000, 200, 256), (2048, 4096, 100, 128)])
-def test_sketch_node_graded(hp, n, m, r, ell):
+def test_sketch_node_graded(hp, n, m, r, ell, kind):
     """Exact rank r < ell, singular values graded 10^(-k/20): the truncation
-    sits at sigma ~ 1e-10 sigma_1, far below the Gram floor."""
-    print(f"sketch node n={n} m={m} r={r} ell={ell}", flush=True)
+    sits at sigma ~ 1e-10 sigma_1, far below the Gram floor.  Both test
+    matrices hold the whole range (r < ell), so neither falls back."""
+    print(f"sketch node n={n} m={m} r={r} ell={ell} {kind}", flush=True)
     sig = 10.0 ** (-np.arange(r) / 20.0)
     S = wide_lowrank(n, m, sig, seed=n + m)
     # eps^2 between the tails at k = 2r/3 and k + 1 (sigma_k = 1e-10 for r = 300)
@@ -90,9 +92,10 @@ def test_sketch_node_graded(hp, n, m, r, ell):
     k = (2 * r) // 3
     eps = math.sqrt(0.5 * (t[k] + t[k + 1]))
     Sd = dev_colmajor(S)
-    s_g, U_g, info = hp.hapod_node_pod_sketch(Sd, eps, ell, seed=7)
+    s_g, U_g, info = hp.hapod_node_pod_sketch(Sd, eps, ell, seed=7, kind=kind)
     torch.cuda.synchronize()
-    check_node(S, s_g, host(U_g), eps, info, f"graded {n}x{m}")
+    assert info["kind"] == kind
+    check_node(S, s_g, host(U_g), eps, info, f"graded {n}x{m} {kind}")
     # the method of snapshots on the same node: its tail sums near eps^2 are
     # rounding noise of the Gram (~ m u sigma_1^2 >> eps^2)
     s_m, _ = hp.hapod_node_pod("fp64", Sd, eps)
@@ -114,10 +117,18 @@ def test_sketch_node_noisy_scaled_and_rerun(hp):
     # every signal mode is kept and the noise alone is discarded
     eps = math.sqrt(10.0 * noise_energy)
     Sd = dev_colmajor(S)
-    s1, W1, i1 = hp.hapod_node_pod_sketch(Sd, eps, 256, seed=3, scaled=True)
-    s2, W2, i2 = hp.hapod_node_pod_sketch(Sd, eps, 256, seed=3, scaled=True)
+    s1, W1, i1 = hp.hapod_node_pod_sketch(Sd, eps, 256, seed=3, scaled=True, kind="gaussian")
+    s2, W2, i2 = hp.hapod_node_pod_sketch(Sd, eps, 256, seed=3, scaled=True, kind="gaussian")
     torch.cuda.synchronize()
     assert np.array_equal(s1, s2) and torch.equal(W1, W2) and i1["residual"] == i2["residual"]
+    # the sparse sign map: certified the same way, its sums in a fixed order
+    # (bitwise-identical rerun)
+    s3, W3, i3 = hp.hapod_node_pod_sketch(Sd, eps, 256, seed=3, scaled=True)
+    s4, W4, i4 = hp.hapod_node_pod_sketch(Sd, eps, 256, seed=3, scaled=True)
+    torch.cuda.synchronize()
+    assert i3["kind"] == "sparse_sign" and i3["residual"] <= eps * eps
+    assert np.array_equal(s3, s4) and torch.equal(W3, W4) and i3["residual"] == i4["residual"]
+    check_node(S, s3, host(W3) / s3[None, :], eps, i3, "noisy scaled, sparse sign", rank_slack=1)
     W = host(W1)
     U = W / s1[None, :]
     assert i1["residual"] <= eps * eps
@@ -132,16 +143,25 @@ def test_sketch_node_noisy_scaled_and_rerun(hp):
     assert np.allclose(np.linalg.norm(W, axis=0), s1, rtol=1e-12)
 
 
-def test_sketch_node_rank_beyond_sketch_fails(hp):
-    """A rank the sketch cannot hold: HAPOD_E_UNSUPPORTED, residual reported."""
+@pytest.mark.parametrize("kind", ["sparse_sign", "gaussian"])
+def test_sketch_node_rank_beyond_sketch_fails(hp, kind):
+    """A rank the sketch cannot hold: HAPOD_E_UNSUPPORTED, residual reported
+    (the sparse sign map first falls back to the Gaussian, which fails too)."""
     n, m, r = 1500, 800, 400
     sig = np.exp(-np.arange(r) / 100.0)
     S = wide_lowrank(n, m, sig, seed=5)
     eps = math.sqrt(pod.tail_sums(sig)[350])
     with pytest.raises(hp.HapodError) as ei:
-        hp.hapod_node_pod_sketch(dev_colmajor(S), eps, 128)
+        hp.hapod_node_pod_sketch(dev_colmajor(S), eps, 128, kind=kind)
     assert ei.value.status == 8
     assert "residual" in hp.hapod_last_error()
+    # the abandoned attempts' buffers went back: a node that fits runs next
+    sig2 = 10.0 ** (-np.arange(100) / 20.0)
+    S2 = wide_lowrank(1024, 600, sig2, seed=6)
+    eps2 = math.sqrt(pod.tail_sums(sig2)[60])
+    s_g, U_g, info = hp.hapod_node_pod_sketch(dev_colmajor(S2), eps2, 128, kind=kind)
+    torch.cuda.synchronize()
+    check_node(S2, s_g, host(U_g), eps2, info, f"after a failure, {kind}")
 
 
 def test_sketch_node_argument_errors(hp):
@@ -185,6 +205,7 @@ def test_tree_sketch_root_meets_the_bound(hp):
         del plan
     sig, U, ranks, st = out["sketch"]
     assert st is not None and st["ell"] == 256
+    assert st["kind"] == "sparse_sign"  # K = 200 sinusoid modes fit the 256 columns
     assert list(ranks[:L]) == [len(ref[i][0]) for i in range(L)]
     # the root's own input is the literal HAPOD's up to the leaves' rounding;
     # its rank within the one the residual can add
