@@ -344,7 +344,7 @@ hapod_status launch_acc_transposed(double* R, int64_t ldr, int64_t c0, const dou
                                    int64_t cols, hipStream_t stream);
 constexpr int64_t kSketchMaxCols = 512;  // widest sketch (the Jacobi SVD's limit)
 constexpr int kSignNnz = 8;              // nonzeros per row of the sparse sign map
-constexpr int kSketchBatch = 24;         // input columns loaded ahead by the sparse sketch
+constexpr int kSketchBatch = 32;         // input columns loaded ahead by the sparse sketch
 // The sparse sign map of (m, ell, seed): per input column k and nonzero t <
 // kSignNnz, tab[t sign_table_ld(m) + k] = the nonzero's column + ell if it
 // is negative (device, kSignNnz sign_table_ld(m) int32).  ell a multiple of

@@ -95,17 +95,42 @@ __global__ __launch_bounds__(256, 1) void sign_sketch_kernel(const void* const* 
   const int32_t* tr = tab + t * tld;  // this thread's block: entries of consecutive columns
   int64_t k0 = 0;
   if ((int64_t)blockIdx.x * 32 + 32 <= full_rows) {
+    // The slice's 32 rows lie in one 128-row block: per column one base
+    // pointer (column start + block times row-block stride), computed by the
+    // lane of the column's place in a group of 64 columns (one vector load
+    // of the column table per lane, a group ahead) and handed to the whole
+    // wavefront by readlane, so the loop carries no scalar loads.
     typedef __attribute__((ext_vector_type(4))) int i4;
-    constexpr int UQ = U / 4;
-    const int64_t mm = m / (2 * U) * (2 * U);
-    auto ld_x = [&](int64_t k) -> double {
-      return *as_global(reinterpret_cast<const double*>(cols[k]) + blk_off(row, rbs[k]));
+    constexpr int UQ = U / 4, G = 64, NBG = G / U;
+    static_assert(G % U == 0 && U % 4 == 0, "whole batches per column group");
+    const int lane = threadIdx.x & 63;
+    const int64_t blk = ((int64_t)blockIdx.x * 32) >> 7;
+    const int64_t roff = row & (kRowBlock - 1);
+    const int64_t mg = m / G * G;  // columns in whole groups
+    // a group's column-table entries (loaded a group before they are needed)
+    // and the lane's base pointer from them
+    struct Raw {
+      const void* c;
+      int64_t rb;
+    };
+    auto group_raw = [&](int64_t g0) -> Raw {
+      const int64_t k = min(g0 + lane, m - 1);
+      return Raw{*as_global(cols + k), *as_global(rbs + k)};
+    };
+    auto base = [&](const Raw& r) -> uint64_t {
+      return (uint64_t)(reinterpret_cast<const double*>(r.c) + blk * r.rb);
+    };
+    auto col_ptr = [&](uint64_t gb, int u) -> const double* {
+      const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)gb, u);
+      const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(gb >> 32), u);
+      return reinterpret_cast<const double*>(((uint64_t)hi << 32) | lo);
     };
     double xa[U], xb[U];
     i4 ea[UQ], eb[UQ];
-    auto load = [&](int64_t k, double (&x)[U], i4 (&e)[UQ]) {
+    // batch j (U columns) of the group whose bases are in gb, first column k
+    auto load = [&](uint64_t gb, int j, int64_t k, double (&x)[U], i4 (&e)[UQ]) {
 #pragma unroll
-      for (int u = 0; u < U; ++u) x[u] = ld_x(k + u);
+      for (int u = 0; u < U; ++u) x[u] = *as_global(col_ptr(gb, j * U + u) + roff);
 #pragma unroll
       for (int q = 0; q < UQ; ++q) e[q] = *as_global(reinterpret_cast<const i4*>(tr + k + 4 * q));
     };
@@ -113,17 +138,31 @@ __global__ __launch_bounds__(256, 1) void sign_sketch_kernel(const void* const* 
 #pragma unroll
       for (int u = 0; u < U; ++u) add(e[u / 4][u % 4], x[u]);
     };
-    if (mm > 0) load(0, xa, ea);
-    for (; k0 < mm; k0 += 2 * U) {
-      load(k0 + U, xb, eb);
-      // (the barriers keep each batch's loads ahead of the adds before it)
-      __builtin_amdgcn_sched_barrier(0);
-      apply(xa, ea);
-      // the refill is unconditional: past the last pair it re-reads the
-      // final batch (unused)
-      load(min(k0 + 2 * U, mm - U), xa, ea);
-      __builtin_amdgcn_sched_barrier(0);
-      apply(xb, eb);
+    if (mg > 0) {
+      uint64_t gcur = base(group_raw(0));
+      Raw rnext = group_raw(min<int64_t>(G, mg - G));
+      load(gcur, 0, 0, xa, ea);
+      for (; k0 < mg; k0 += G) {
+        const uint64_t gnext = base(rnext);
+        // batches 1 .. NBG - 1 of this group, then batch 0 of the next one
+        // (past the last group: this group's last batch again, unused); the
+        // refills are unconditional, so each wait is for a fixed count
+#pragma unroll
+        for (int j = 1; j <= NBG; ++j) {
+          const bool odd = (j & 1) != 0;
+          const bool next = (j == NBG);
+          const uint64_t gb = next ? (k0 + G < mg ? gnext : gcur) : gcur;
+          const int jj = next ? (k0 + G < mg ? 0 : NBG - 1) : j;
+          const int64_t kk = next ? (k0 + G < mg ? k0 + G : k0 + (NBG - 1) * U) : k0 + j * U;
+          if (odd) load(gb, jj, kk, xb, eb);
+          else load(gb, jj, kk, xa, ea);
+          __builtin_amdgcn_sched_barrier(0);
+          if (odd) apply(xa, ea);
+          else apply(xb, eb);
+        }
+        gcur = gnext;
+        rnext = group_raw(min<int64_t>(k0 + 2 * G, mg - G));
+      }
     }
   }
   for (int64_t k = k0; k < m; ++k) {
