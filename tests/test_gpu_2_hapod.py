@@ -206,6 +206,49 @@ def test_balanced_three_levels(hp, prec):
             assert gap <= band, (a, Ng, No, gap, band)
 
 
+def test_full_rank_leaves(hp):
+    """Leaves whose POD keeps every snapshot (rank m: their scaled modes are
+    S V for a square orthogonal V): the root's rank and sigma as the literal
+    HAPOD's, modes within the Gram route's accuracy, and the same with the
+    right vectors kept.  A rank-20 signal plus noise 1e-2 (full-rank leaves);
+    omega = 0.999 leaves the leaves too little of the budget to drop a noise
+    mode, while the root (240 inputs: every eigenpair from the Householder
+    reduction) drops all of them."""
+    from oracle import hapod as ohapod
+    n, L, c = 1024, 5, 48
+    rng = np.random.default_rng(12)
+    sg = 10.0 * np.exp(-np.arange(20) / 4.0)
+    Q1, _ = np.linalg.qr(rng.standard_normal((n, 20)))
+    Q2, _ = np.linalg.qr(rng.standard_normal((L * c, 20)))
+    S = (Q1 * sg) @ Q2.T * math.sqrt(L * c) + 1e-2 * rng.standard_normal((n, L * c))
+    data = {i: S[:, i * c:(i + 1) * c] for i in range(L)}
+    parent = synth.star_tree(L)
+    cols = [c] * L + [0]
+    eps_star, omega = 0.4, 0.999
+    eps = tolerances.hapod_tolerances(parent, cols, eps_star, omega)
+    ref = ohapod.hapod(parent, data, eps)
+    assert all(len(ref[i][0]) == c for i in range(L))  # every leaf keeps all its columns
+    prec = "fp64"
+    dev = {i: dev_colmajor(v) for i, v in data.items()}
+    plan = hp.Plan(parent, cols, n, eps_star, omega, prec=prec)
+    plan.run(dev)
+    sig, U = plan.modes()
+    ranks = plan.ranks()
+    assert list(ranks[:L]) == [c] * L
+    s_ref, U_ref = ref[L]
+    with_v = hp.Plan(parent, cols, n, eps_star, omega, prec=prec, right_vectors=True)
+    with_v.run(dev)
+    sig2, U2 = with_v.modes()
+    print(f"  full-rank leaves {prec}: root rank {len(sig)} (oracle {len(s_ref)}, with right vectors {len(sig2)})")
+    assert len(sig) == len(s_ref)
+    np.testing.assert_allclose(sig, s_ref, rtol=1e-10)
+    r = metrics.resolved_rank(s_ref, len(sig), UP[prec], TAU[prec])
+    assert metrics.subspace_error(U_ref, host(U), r) <= TAU[prec]
+    assert len(sig2) == len(sig)
+    np.testing.assert_allclose(sig2, sig, rtol=1e-12)
+    assert metrics.subspace_error(host(U2), host(U), len(sig)) <= 1e-10
+
+
 def test_single_node_tree_equals_node_pod(hp):
     S = synth.sinusoid(500, 40, 30, 5.0, 0.0, seed=2)
     plan = hp.Plan([-1], [40], 500, 1e-3, 0.9, prec="fp64")
