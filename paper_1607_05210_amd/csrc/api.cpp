@@ -1243,6 +1243,10 @@ hapod_status run_pod_batch_impl(hapod_precision prec, std::vector<PodJob>& jobs,
       // truncation then cannot certify eps below the noise, as for any Gram of
       // this precision); more means a large eigenvalue was never seen
       jobs[i].wide_noise_room = (double)(jobs[i].m - wr.block) * wr.noise;
+      // the energy of the eigenvalues not returned (beyond the rounding
+      // allowance) is discarded whatever the rank: the truncation gets the
+      // rest of the budget (Def. 2.5 counts every discarded direction)
+      tnodes[i].eps2 = std::max(0.0, jobs[i].eps * jobs[i].eps - std::max(0.0, wr.unresolved - jobs[i].wide_slack));
       if (jobs[i].wide_full && wr.unresolved > jobs[i].wide_slack) {
         // the Krylov space broke down before spanning the matrix (an exact
         // multiplicity): fall back to the dense Jacobi eigensolver
@@ -1277,6 +1281,7 @@ hapod_status run_pod_batch_impl(hapod_precision prec, std::vector<PodJob>& jobs,
         jobs[i].wide_missing = 0.0;
         jobs[i].wide_noise_room = 0.0;
         jobs[i].wide_exhausted = true;
+        tnodes[i].eps2 = jobs[i].eps * jobs[i].eps;
       }
     }
     if (tev) HAPOD_HIP(hipEventRecord(ev.e[2], stream));
