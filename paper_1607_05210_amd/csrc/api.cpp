@@ -1738,7 +1738,9 @@ hapod_status cross_cols(Pool& pool, int64_t n, const Cols& L, const Cols& R, dou
 // 1/2) is shifted: Q^T Q + s I = R_p^T R_p, s = 11 (n m + m (m + 1)) u
 // tr(Q^T Q), the shift of shifted Cholesky-QR (tr >= ||Q||_2^2), which lifts
 // the directions A nearly lacks by about s^-1/2 per pass; the others are
-// plain.  Two plain passes in a row leave Q orthonormal to rounding.  The
+// plain.  Two plain passes in a row leave Q orthonormal to rounding; after
+// one plain pass the next pass's Gram already shows whether Q is (every entry
+// of Q^T Q - I within 8 (sqrt(n) + m) u), and then the passes stop.  The
 // first pass factors the equilibrated Gram D^-1 A^T A D^-1 (D the column
 // norms), so columns of very different size (a bump far from a short leaf's
 // rows is 1e-100 of its neighbours) start on equal terms: R_1 = R_1' D,
@@ -1778,6 +1780,10 @@ hapod_status cholqr_core(Pool& pool, int64_t n, int64_t m, const double* A, int6
   int64_t ld = lda;
   double* dst = (QA == A) ? QB : QA;
   int plain_run = 0, pass = 0;
+  // rounding of an entry of Q^T Q (n-term dot products) and of the m-term
+  // triangular solve that made Q
+  const double done_tol = 8.0 * (std::sqrt((double)n) + (double)m) * u;
+  bool done = false;
   for (; pass < kQrMaxPasses && plain_run < 2; ++pass) {
     if ((st = gram_impl(0, 8, n, m, src, ld, (double*)G, m, stream, 0, src_rbs)) != HAPOD_OK ||
         (st = launch_gram_zero_scale((double*)G, m, m, zero, pass == 0 ? (double*)dD : nullptr, stream)) !=
@@ -1789,6 +1795,12 @@ hapod_status cholqr_core(Pool& pool, int64_t n, int64_t m, const double* A, int6
         hipStreamSynchronize(stream) != hipSuccess) {
       set_error("Cholesky-QR: readback failed");
       return finish(HAPOD_E_DEVICE);
+    }
+    // the previous pass was plain and left Q^T Q within the Gram's own
+    // rounding of the identity: Q is orthonormal, no further pass
+    if (plain_run >= 1 && dev <= done_tol) {
+      done = true;
+      break;
     }
     const bool shifted = !((double)m * dev <= 0.5);
     if (shifted &&
@@ -1824,7 +1836,7 @@ hapod_status cholqr_core(Pool& pool, int64_t n, int64_t m, const double* A, int6
     }
     plain_run = shifted ? 0 : plain_run + 1;
   }
-  if (plain_run < 2) {
+  if (!done && plain_run < 2) {
     set_error("Cholesky-QR did not reach an orthonormal factor in 12 passes");
     return finish(HAPOD_E_NUMERIC);
   }
