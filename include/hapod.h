@@ -197,11 +197,13 @@ hapod_status hapod_node_pod_qr(int64_t n, int64_t m, const double* S, int64_t ld
  *   themselves, the SVD of B from the QR factor of B^T (Cholesky-QR passes,
  *   one-sided Jacobi on R'^T), modes Q U_B.
  * Omega (m x ell), from counter-based generators and `seed`:
- *   kind 0: the sparse sign map (Martinsson & Tropp, Acta Numerica 2020,
- *     Sec. 9.2): 8 nonzeros +-1/sqrt(8) per row, one in each of 8 column
- *     blocks of ell / 8, positions and signs from the splitmix64 finaliser;
- *     Y costs one pass over S.  Should r exceed eps^2, the route starts over
- *     with the Gaussian;
+ *   kind 0: a sparse sign map (Martinsson & Tropp, Acta Numerica 2020,
+ *     Sec. 9.2) in block-shifted form: 8 nonzeros +-1/sqrt(8) per row, one
+ *     in each of 8 column blocks of bw = ell / 8; per chunk of bw
+ *     consecutive rows of Omega and per block, the positions are one cyclic
+ *     shift of 0 .. bw - 1 and every position has its own sign, shift and
+ *     signs from the splitmix64 finaliser; Y costs one pass over S.  Should
+ *     r exceed eps^2, the route starts over with the Gaussian;
  *   kind 1: Gaussian (Box-Muller over the splitmix64 finaliser).
  * Rank: the smallest N with r + sum_{k>N} sigma_k(B)^2 <= eps^2, so the
  * modes' projection error ||S - U U^T S||_F^2 = r + sum_{k>N} sigma_k(B)^2
@@ -216,8 +218,8 @@ hapod_status hapod_node_pod_qr(int64_t n, int64_t m, const double* S, int64_t ld
  *           1 Gaussian)}.
  * r > eps^2 with the Gaussian (the rank of S within eps exceeds what ell
  * columns capture): HAPOD_E_UNSUPPORTED, info7 still filled.
- * Scratch: two n x ell double buffers, an m x ell Gaussian, the sign map's
- * table and B^T, partial sums, from the library's pool.  Synchronises the
+ * Scratch: two n x ell double buffers, an m x ell Gaussian and B^T, partial
+ * sums, from the library's pool.  Synchronises the
  * stream.                                                                  */
 hapod_status hapod_node_pod_sketch(int64_t n, int64_t m, const double* S, int64_t lds, double eps,
                                    int32_t scaled, int64_t ell, uint64_t seed, int32_t kind, double* out,

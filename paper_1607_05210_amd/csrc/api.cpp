@@ -2154,12 +2154,12 @@ hapod_status sketch_pod_core(Pool& pool, int64_t n, int64_t m, const std::vector
       set_error("sketched POD: hipEventCreate failed");
       return finish(HAPOD_E_DEVICE);
     }
-  void *dcols = nullptr, *drbs = nullptr, *drows = nullptr, *tab = nullptr;
+  void *dcols = nullptr, *drbs = nullptr, *drows = nullptr;
   const std::pair<size_t, void**> want[] = {
       {sizeof(double) * (size_t)m * ell, &Om}, {tiled_bytes(n, ell, 8), &Y}, {sizeof(double) * (size_t)m * ell, &Bt},
       {sizeof(double) * m, &res}, {ll, &Rb}, {ll, &M}, {ll, &UB}, {sizeof(double) * ell, &dsig},
       {sizeof(int32_t) * 2, &dinfo}, {sizeof(void*) * (size_t)m, &dcols}, {sizeof(int64_t) * (size_t)m, &drbs},
-      {sizeof(int64_t) * (size_t)m, &drows}, {sizeof(int32_t) * kSignNnz * (size_t)sign_table_ld(m), &tab}};
+      {sizeof(int64_t) * (size_t)m, &drows}};
   for (const auto& w : want) {
     hapod_status st = pool.alloc(w.first, w.second);
     if (st != HAPOD_OK) return finish(st);
@@ -2185,10 +2185,8 @@ hapod_status sketch_pod_core(Pool& pool, int64_t n, int64_t m, const std::vector
     (void)hipEventRecord(ev[0], stream);
     // ---- Y = S Omega ----------------------------------------------------------
     if (si.kind == 0) {
-      if ((st = launch_sign_table((int32_t*)tab, m, ell, seed, stream)) != HAPOD_OK ||
-          (st = launch_sign_sketch((const void* const*)dcols, (const int64_t*)drbs, (const int64_t*)drows, n, m,
-                                   full_rows, (const int32_t*)tab, ell, (double*)Y, kRowBlock, tiled_rbs(ell),
-                                   stream)) != HAPOD_OK)
+      if ((st = launch_sign_sketch((const void* const*)dcols, (const int64_t*)drbs, (const int64_t*)drows, n, m,
+                                   full_rows, seed, ell, (double*)Y, kRowBlock, tiled_rbs(ell), stream)) != HAPOD_OK)
         return finish(st);
     } else if ((st = launch_normal_fill((double*)Om, m * ell, seed, stream)) != HAPOD_OK ||
                (st = lift_cols(pool, n, Sc, (const double*)Om, ell, ell, (double*)Y, kRowBlock, tiled_rbs(ell),

@@ -344,19 +344,15 @@ hapod_status launch_acc_transposed(double* R, int64_t ldr, int64_t c0, const dou
                                    int64_t cols, hipStream_t stream);
 constexpr int64_t kSketchMaxCols = 512;  // widest sketch (the Jacobi SVD's limit)
 constexpr int kSignNnz = 8;              // nonzeros per row of the sparse sign map
-constexpr int kSketchBatch = 32;         // input columns loaded ahead by the sparse sketch
-// The sparse sign map of (m, ell, seed): per input column k and nonzero t <
-// kSignNnz, tab[t sign_table_ld(m) + k] = the nonzero's column + ell if it
-// is negative (device, kSignNnz sign_table_ld(m) int32).  ell a multiple of
-// 8, at most 512.
-__host__ __device__ inline int64_t sign_table_ld(int64_t m) { return (m + 3) / 4 * 4; }
-hapod_status launch_sign_table(int32_t* tab, int64_t m, int64_t ell, uint64_t seed, hipStream_t stream);
-// Y = S Omega for that map (entries +-1/sqrt(kSignNnz)): S an n-row column
-// table of m columns (device arrays; full_rows: rows every column holds, 16-
-// byte alignment not needed), Y element (r, c) at Y[c * ocs + blk_off(r,
+constexpr int kSketchRows = 64;          // rows of S per workgroup of the sparse sketch
+constexpr int kSketchDepth = 2;          // column chunks the sparse sketch loads ahead
+// Y = S Omega for the sparse sign map of (m, ell, seed) in its block-shifted
+// form (entries +-1/sqrt(kSignNnz); ell = 128, 256, 384 or 512): S an n-row
+// column table of m columns (device arrays; full_rows: rows every column
+// holds; 8-byte alignment), Y element (r, c) at Y[c * ocs + blk_off(r,
 // obs)], rows < n written.
 hapod_status launch_sign_sketch(const void* const* d_cols, const int64_t* d_rbs, const int64_t* d_rows, int64_t n,
-                                int64_t m, int64_t full_rows, const int32_t* tab, int64_t ell, double* Y, int64_t ocs,
+                                int64_t m, int64_t full_rows, uint64_t seed, int64_t ell, double* Y, int64_t ocs,
                                 int64_t obs, hipStream_t stream);
 
 }  // namespace hapod

@@ -35,146 +35,181 @@ __global__ __launch_bounds__(256) void normal_fill_kernel(double* __restrict__ o
 }
 
 // The sparse sign map (a sparse dimension reduction map with kSignNnz
-// nonzeros per row, Martinsson & Tropp, Acta Numerica 2020, Sec. 9.2): row k
-// of Omega (m x ell) holds +-1/sqrt(kSignNnz) in each of the kSignNnz
-// column blocks of width ell / kSignNnz, at the position and with the sign
-// drawn from the splitmix64 finaliser of the counter (seed, kSignNnz k + t).
-// sign_table_kernel writes, per (k, t), position + ell * (sign < 0) at
-// tab[t * sign_table_ld(m) + k].
+// nonzeros per row, Martinsson & Tropp, Acta Numerica 2020, Sec. 9.2), in a
+// block-shifted form: Omega (m x ell) has kSignNnz column blocks of width
+// bw = ell / kSignNnz, and row k of Omega holds +-1/sqrt(kSignNnz) once in
+// each block.  The input columns go in chunks of bw; in block t, chunk g's
+// column g bw + j sits at position (j + shift) mod bw, with the shift
+// uniform in [0, bw) and the sign of every position an independent fair
+// bit, both drawn from the splitmix64 finaliser of the counter (seed,
+// kSignNnz g + t).  Each row of Omega thus has one nonzero per block, as in
+// the i.i.d. form; two columns of one chunk never share a position, and
+// columns of different chunks share one in a block with probability 1 / bw.
+// The positions of a chunk being a cyclic shift, a thread can keep its
+// block's bw sums of one row in registers.  Record kSignNnz g + t holds the
+// sign bits (bit p: position p negative) and the shift; the sketch kernel
+// draws each where it needs it.
 __device__ __forceinline__ uint64_t mix64(uint64_t x) {
   x += 0x9e3779b97f4a7c15ull;
   x = (x ^ (x >> 30)) * 0xbf58476d1ce4e5b9ull;
   x = (x ^ (x >> 27)) * 0x94d049bb133111ebull;
   return x ^ (x >> 31);
 }
-__global__ __launch_bounds__(256) void sign_table_kernel(int32_t* __restrict__ tab, int64_t m, int32_t ell,
-                                                         uint64_t seed) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;  // counter kSignNnz k + t
-  if (e >= m * kSignNnz) return;
-  const int t = (int)(e % kSignNnz);
-  const int64_t k = e / kSignNnz;
-  const uint32_t bw = (uint32_t)(ell / kSignNnz);
-  const uint64_t z = mix64((seed * 0xd1342543de82ef95ull) ^ (uint64_t)e);
-  const uint32_t pos = (uint32_t)(((z >> 32) * (uint64_t)bw) >> 32);  // uniform in [0, bw)
-  tab[t * sign_table_ld(m) + k] = (int32_t)(t * bw + pos) + ((z & 1u) ? ell : 0);
+// record e = kSignNnz g + t of the map: its sign bits and shift
+struct SignRecord {
+  uint64_t signs;
+  uint32_t shift;
+};
+__device__ __forceinline__ SignRecord sign_record(uint64_t seed, uint64_t e, uint32_t bw) {
+  const uint64_t z = mix64((seed * 0xd1342543de82ef95ull) ^ e);
+  return SignRecord{mix64(z), (uint32_t)(((z >> 32) * (uint64_t)bw) >> 32)};  // shift uniform in [0, bw)
 }
-
-// Y = S Omega for the sparse sign map: one workgroup per 32-row slice of S,
-// whose 32 x ell slice of Y accumulates in LDS (rows padded to ell + 1
-// doubles against bank conflicts).  Thread (t, i) = (threadIdx.x / 32,
-// threadIdx.x % 32) owns row i's entries in column block t, so each entry is
-// summed by one thread, in input-column order (deterministic); the sums go
-// to LDS as atomic adds whose results are not returned, so consecutive
-// updates do not wait for each other (one lane per entry: the order is the
-// lane's program order).  A slice that every column holds in full reads
-// 32 contiguous rows per column with no guards, kSketchBatch columns and
-// their table entries loaded ahead of their use; other slices, and the
-// columns past the last whole batch pair, read one column at a time with
-// rows past a column's own count as zero.  Rows of Y past n are not
-// written.  Y element (r, c) at Y[c * ocs + blk_off(r, obs)].
-__global__ __launch_bounds__(256, 1) void sign_sketch_kernel(const void* const* __restrict__ cols,
-                                                          const int64_t* __restrict__ rbs,
-                                                          const int64_t* __restrict__ crows, int64_t n, int64_t m,
-                                                          int64_t full_rows, const int32_t* __restrict__ tab,
-                                                          int32_t ell, double* __restrict__ Y, int64_t ocs,
-                                                          int64_t obs) {
-  extern __shared__ double ys[];
-  constexpr int U = kSketchBatch;
-  const int i = threadIdx.x & 31, t = threadIdx.x >> 5;
-  const int ld = ell + 1;
-  const int bw = ell / kSignNnz;
-  const int64_t row = (int64_t)blockIdx.x * 32 + i;
-  double* yr = ys + i * ld;
-  for (int q = 0; q < bw; ++q) yr[t * bw + q] = 0.0;
-  // (each thread touches only its own entries: no barrier needed before use)
-  auto add = [&](int32_t e, double x) {
-    const bool neg = e >= ell;
-    atomicAdd(&yr[neg ? e - ell : e], neg ? -x : x);
+// Y = S Omega for that map: one workgroup of kSignNnz wavefronts per slice of
+// kSketchRows rows (one row per lane), wavefront t holding, per lane, the
+// row's bw sums of column block t in registers.  Per chunk of bw columns the
+// wavefronts t < bw / 8 load eight columns each (one column's 64 rows, 512
+// contiguous bytes, per load; kSketchDepth chunks ahead) into LDS, every
+// column stored twice in a row ([x_0 .. x_{bw-1}, x_0 .. x_{bw-1}]), so
+// that each wavefront reads its shifted order as one contiguous window and
+// adds it, signed, to its sums: each sum in chunk order, deterministic.  The
+// column bases come from one vector load of the column table per chunk,
+// handed out by readlane.  SAFE (slices some column does not hold in full)
+// reads rows past a column's own count as zero; columns past m (the last
+// chunk's rest) read as zero.  Rows of Y past n are not written.  Y element
+// (r, c) at Y[c * ocs + blk_off(r, obs)].
+template <int BW, bool SAFE>
+__global__ __launch_bounds__(kSignNnz * 64, 1) void sign_sketch_kernel(
+    const void* const* __restrict__ cols, const int64_t* __restrict__ rbs, const int64_t* __restrict__ crows,
+    int64_t n, int64_t m, int64_t chunks, int64_t slice0, uint64_t seed, double* __restrict__ Y, int64_t ocs,
+    int64_t obs) {
+  constexpr int R = kSketchRows, D = kSketchDepth, CPW = 8, G = 8;
+  static_assert(R == 64 && BW % CPW == 0 && BW <= 64 && BW % G == 0 && D % 2 == 0, "sketch shape");
+  extern __shared__ double stg[];  // two buffers of 2 BW staged columns x R rows
+  const int lane = threadIdx.x & 63;
+  const int t = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));  // this wavefront's column block
+  const bool loader = (BW == 64) || t * CPW < BW;
+  const int64_t s0 = (slice0 + blockIdx.x) * R;
+  const int64_t row = s0 + lane;
+  const int64_t blk = s0 >> 7, soff = s0 & (kRowBlock - 1);
+  const int64_t steps = (chunks + D - 1) / D * D;  // whole steps of D chunks; chunks past the last are all zero
+  double acc[BW];
+#pragma unroll
+  for (int p = 0; p < BW; ++p) acc[p] = 0.0;
+  struct Raw {
+    const void* c;
+    int64_t rb;
+    int64_t rows;
   };
-  const int64_t tld = sign_table_ld(m);
-  const int32_t* tr = tab + t * tld;  // this thread's block: entries of consecutive columns
-  int64_t k0 = 0;
-  if ((int64_t)blockIdx.x * 32 + 32 <= full_rows) {
-    // The slice's 32 rows lie in one 128-row block: per column one base
-    // pointer (column start + block times row-block stride), computed by the
-    // lane of the column's place in a group of 64 columns (one vector load
-    // of the column table per lane, a group ahead) and handed to the whole
-    // wavefront by readlane, so the loop carries no scalar loads.
-    typedef __attribute__((ext_vector_type(4))) int i4;
-    constexpr int UQ = U / 4, G = 64, NBG = G / U;
-    static_assert(G % U == 0 && U % 4 == 0, "whole batches per column group");
-    const int lane = threadIdx.x & 63;
-    const int64_t blk = ((int64_t)blockIdx.x * 32) >> 7;
-    const int64_t roff = row & (kRowBlock - 1);
-    const int64_t mg = m / G * G;  // columns in whole groups
-    // a group's column-table entries (loaded a group before they are needed)
-    // and the lane's base pointer from them
-    struct Raw {
-      const void* c;
-      int64_t rb;
-    };
-    auto group_raw = [&](int64_t g0) -> Raw {
-      const int64_t k = min(g0 + lane, m - 1);
-      return Raw{*as_global(cols + k), *as_global(rbs + k)};
-    };
-    auto base = [&](const Raw& r) -> uint64_t {
-      return (uint64_t)(reinterpret_cast<const double*>(r.c) + blk * r.rb);
-    };
-    auto col_ptr = [&](uint64_t gb, int u) -> const double* {
-      const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)gb, u);
-      const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(gb >> 32), u);
-      return reinterpret_cast<const double*>(((uint64_t)hi << 32) | lo);
-    };
-    double xa[U], xb[U];
-    i4 ea[UQ], eb[UQ];
-    // batch j (U columns) of the group whose bases are in gb, first column k
-    auto load = [&](uint64_t gb, int j, int64_t k, double (&x)[U], i4 (&e)[UQ]) {
+  // the column table of chunk g, one column per lane (lanes past bw repeat
+  // the last; columns past m read as column m - 1, their values dropped)
+  auto load_ct = [&](int64_t g) -> Raw {
+    const int64_t k = min(g * BW + min(lane, BW - 1), m - 1);
+    Raw r{*as_global(cols + k), *as_global(rbs + k), 0};
+    if constexpr (SAFE) r.rows = *as_global(crows + k);
+    return r;
+  };
+  auto readlane64 = [&](uint64_t v, int idx) -> uint64_t {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, idx);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), idx);
+    return ((uint64_t)hi << 32) | lo;
+  };
+  double sv[D][CPW];
+  Raw rr[D];
+  // Slot s (static) takes chunk jj (past the last: chunk jj's clamped
+  // columns, dropped).  Loads are unconditional in the full-slice form, so
+  // every wait is for a fixed count.
+  auto refill = [&](int s, int64_t jj) {
+    // chunk jj's column table (loaded D chunks ago), used up before the slot
+    // is refilled, so that the new load can take the same registers
+    const uint64_t cb = (uint64_t)(reinterpret_cast<const double*>(rr[s].c) + blk * rr[s].rb + soff);
+    const uint64_t crows_s = (uint64_t)rr[s].rows;
+    rr[s] = load_ct(jj + D);
+    if (loader) {
 #pragma unroll
-      for (int u = 0; u < U; ++u) x[u] = *as_global(col_ptr(gb, j * U + u) + roff);
-#pragma unroll
-      for (int q = 0; q < UQ; ++q) e[q] = *as_global(reinterpret_cast<const i4*>(tr + k + 4 * q));
-    };
-    auto apply = [&](const double (&x)[U], const i4 (&e)[UQ]) {
-#pragma unroll
-      for (int u = 0; u < U; ++u) add(e[u / 4][u % 4], x[u]);
-    };
-    if (mg > 0) {
-      uint64_t gcur = base(group_raw(0));
-      Raw rnext = group_raw(min<int64_t>(G, mg - G));
-      load(gcur, 0, 0, xa, ea);
-      for (; k0 < mg; k0 += G) {
-        const uint64_t gnext = base(rnext);
-        // batches 1 .. NBG - 1 of this group, then batch 0 of the next one
-        // (past the last group: this group's last batch again, unused); the
-        // refills are unconditional, so each wait is for a fixed count
-#pragma unroll
-        for (int j = 1; j <= NBG; ++j) {
-          const bool odd = (j & 1) != 0;
-          const bool next = (j == NBG);
-          const uint64_t gb = next ? (k0 + G < mg ? gnext : gcur) : gcur;
-          const int jj = next ? (k0 + G < mg ? 0 : NBG - 1) : j;
-          const int64_t kk = next ? (k0 + G < mg ? k0 + G : k0 + (NBG - 1) * U) : k0 + j * U;
-          if (odd) load(gb, jj, kk, xb, eb);
-          else load(gb, jj, kk, xa, ea);
-          __builtin_amdgcn_sched_barrier(0);
-          if (odd) apply(xa, ea);
-          else apply(xb, eb);
+      for (int q = 0; q < CPW; ++q) {
+        const int c = t * CPW + q;
+        const double* p = reinterpret_cast<const double*>(readlane64(cb, c)) + lane;
+        if constexpr (SAFE) {
+          const int64_t rk = (int64_t)readlane64(crows_s, c);
+          sv[s][q] = (row < rk) ? *as_global(p) : 0.0;
+        } else {
+          sv[s][q] = *as_global(p);
         }
-        gcur = gnext;
-        rnext = group_raw(min<int64_t>(k0 + 2 * G, mg - G));
       }
     }
+    // (indexed by the lane's own wavefront number, a vector register, so that
+    // the load stays a vector load counted with the others)
+  };
+#pragma unroll
+  for (int s = 0; s < D; ++s) rr[s] = load_ct(s);
+#pragma unroll
+  for (int s = 0; s < D; ++s) {
+    refill(s, s);
+    // the column table loaded for the slot's next chunk, marked as used here
+    // (an empty asm), so that it is not sunk past the drain below
+    asm volatile("" : "+v"(rr[s].c), "+v"(rr[s].rb), "+v"(rr[s].rows));
+    __builtin_amdgcn_sched_barrier(0);
   }
-  for (int64_t k = k0; k < m; ++k) {
-    const double* c = reinterpret_cast<const double*>(cols[k]);
-    const double x = (row < crows[k]) ? c[blk_off(row, rbs[k])] : 0.0;
-    add(tr[k], x);
+  // Nothing in flight on entry: the loop's waits are then those of its own
+  // issue order (the compiler merges the entry state into every iteration's).
+  __builtin_amdgcn_s_waitcnt(0x0f70);  // vmcnt(0)
+  for (int64_t j0 = 0; j0 < steps; j0 += D) {
+#pragma unroll
+    for (int s = 0; s < D; ++s) {
+      const int64_t j = j0 + s;
+      // buffer s & 1 (D even: the chunk's parity) was last read two chunks
+      // ago, before the last barrier
+      double* st = stg + (s & 1) * (2 * BW * R);
+      if (loader) {
+#pragma unroll
+        for (int q = 0; q < CPW; ++q) {
+          const int c = t * CPW + q;
+          const double v = (j * BW + c < m) ? sv[s][q] : 0.0;
+          st[c * R + lane] = v;
+          st[(c + BW) * R + lane] = v;
+        }
+      }
+      const SignRecord rec = sign_record(seed, (uint64_t)(j * kSignNnz + t), (uint32_t)BW);  // scalar arithmetic
+      const uint32_t mlo = (uint32_t)rec.signs, mhi = (uint32_t)(rec.signs >> 32);
+      const int shift = (int)rec.shift;
+      __syncthreads();
+      // position p takes column (p - shift) mod bw: entry BW - shift + p of the doubled row
+      const double* xr = st + (BW - shift) * R + lane;
+      double xa[G], xb[G];
+      auto read = [&](int g0, double (&x)[G]) {
+#pragma unroll
+        for (int u = 0; u < G; ++u) x[u] = xr[(g0 + u) * R];
+      };
+      auto add = [&](int g0, const double (&x)[G]) {
+#pragma unroll
+        for (int u = 0; u < G; ++u) {
+          const int p = g0 + u;
+          const uint32_t word = (p < 32) ? mlo : mhi;
+          const uint32_t sb = (word << (31 - (p & 31))) & 0x80000000u;
+          const uint64_t bits = __builtin_bit_cast(uint64_t, x[u]) ^ ((uint64_t)sb << 32);
+          acc[p] += __builtin_bit_cast(double, bits);
+        }
+      };
+      read(0, xa);
+#pragma unroll
+      for (int g0 = 0; g0 < BW; g0 += 2 * G) {
+        if (g0 + G < BW) read(g0 + G, xb);
+        __builtin_amdgcn_sched_barrier(0);
+        add(g0, xa);
+        if (g0 + 2 * G < BW) read(g0 + 2 * G, xa);
+        __builtin_amdgcn_sched_barrier(0);
+        if (g0 + G < BW) add(g0 + G, xb);
+      }
+      __builtin_amdgcn_sched_barrier(0);
+      refill(s, j + D);  // (at the chunk's end: the loop's first wait is then for its own loads)
+      __builtin_amdgcn_sched_barrier(0);
+    }
   }
-  __syncthreads();
-  // write the slice: column c, 32 consecutive rows per pass
   const double scale = 1.0 / sqrt((double)kSignNnz);
-  for (int c = t; c < ell; c += 8)
-    if (row < n) Y[(int64_t)c * ocs + blk_off(row, obs)] = ys[i * ld + c] * scale;
+  if (row < n) {
+#pragma unroll
+    for (int p = 0; p < BW; ++p) Y[(int64_t)(t * BW + p) * ocs + blk_off(row, obs)] = acc[p] * scale;
+  }
 }
 
 __global__ __launch_bounds__(256) void transpose_kernel(const double* __restrict__ A, int64_t lda, int64_t m,
@@ -243,43 +278,55 @@ hapod_status launch_normal_fill(double* out, int64_t count, uint64_t seed, hipSt
   return HAPOD_OK;
 }
 
-hapod_status launch_sign_table(int32_t* tab, int64_t m, int64_t ell, uint64_t seed, hipStream_t stream) {
-  if (m <= 0) return HAPOD_OK;
-  if (ell % kSignNnz != 0 || ell <= 0 || ell > kSketchMaxCols) {
-    set_error("sparse sign sketch: ell must be a positive multiple of 8 up to 512");
-    return HAPOD_E_UNSUPPORTED;
-  }
-  const int64_t total = m * kSignNnz;
-  hipLaunchKernelGGL(sign_table_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, stream, tab, m, (int32_t)ell,
-                     seed);
-  HAPOD_HIP(hipGetLastError());
-  return HAPOD_OK;
-}
-
-hapod_status launch_sign_sketch(const void* const* d_cols, const int64_t* d_rbs, const int64_t* d_rows, int64_t n,
-                                int64_t m, int64_t full_rows, const int32_t* tab, int64_t ell, double* Y, int64_t ocs,
-                                int64_t obs, hipStream_t stream) {
-  if (n <= 0 || m <= 0) return HAPOD_OK;
-  if (ell % kSignNnz != 0 || ell <= 0 || ell > kSketchMaxCols) {
-    set_error("sparse sign sketch: ell must be a positive multiple of 8 up to 512");
-    return HAPOD_E_UNSUPPORTED;
-  }
-  const size_t lds = sizeof(double) * 32 * (size_t)(ell + 1);
+namespace {
+template <int BW>
+hapod_status sign_sketch_bw(const void* const* d_cols, const int64_t* d_rbs, const int64_t* d_rows, int64_t n, int64_t m,
+                            int64_t full_rows, uint64_t seed, double* Y, int64_t ocs, int64_t obs,
+                            hipStream_t stream) {
+  const size_t lds = sizeof(double) * 2 * 2 * BW * kSketchRows;
   static bool attr = false;
   if (!attr) {
-    HAPOD_HIP(hipFuncSetAttribute((const void*)sign_sketch_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  (int)(sizeof(double) * 32 * (kSketchMaxCols + 1))));
+    HAPOD_HIP(hipFuncSetAttribute((const void*)sign_sketch_kernel<BW, false>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    HAPOD_HIP(hipFuncSetAttribute((const void*)sign_sketch_kernel<BW, true>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     attr = true;
   }
-  const int64_t slices = (n + 31) / 32;
+  const int64_t chunks = (m + BW - 1) / BW;
+  const int64_t slices = (n + kSketchRows - 1) / kSketchRows;
+  const int64_t fast = std::min(slices, std::max<int64_t>(full_rows, 0) / kSketchRows);
   if (slices > INT32_MAX) {
     set_error("sparse sign sketch: too many rows");
     return HAPOD_E_UNSUPPORTED;
   }
-  hipLaunchKernelGGL(sign_sketch_kernel, dim3((unsigned)slices), dim3(256), lds, stream, d_cols, d_rbs, d_rows, n, m,
-                     full_rows, tab, (int32_t)ell, Y, ocs, obs);
-  HAPOD_HIP(hipGetLastError());
+  const dim3 block(kSignNnz * 64);
+  if (fast > 0) {
+    hipLaunchKernelGGL((sign_sketch_kernel<BW, false>), dim3((unsigned)fast), block, lds, stream, d_cols, d_rbs,
+                       d_rows, n, m, chunks, (int64_t)0, seed, Y, ocs, obs);
+    HAPOD_HIP(hipGetLastError());
+  }
+  if (slices > fast) {
+    hipLaunchKernelGGL((sign_sketch_kernel<BW, true>), dim3((unsigned)(slices - fast)), block, lds, stream, d_cols,
+                       d_rbs, d_rows, n, m, chunks, fast, seed, Y, ocs, obs);
+    HAPOD_HIP(hipGetLastError());
+  }
   return HAPOD_OK;
+}
+}  // namespace
+
+hapod_status launch_sign_sketch(const void* const* d_cols, const int64_t* d_rbs, const int64_t* d_rows, int64_t n,
+                                int64_t m, int64_t full_rows, uint64_t seed, int64_t ell, double* Y, int64_t ocs,
+                                int64_t obs, hipStream_t stream) {
+  if (n <= 0 || m <= 0) return HAPOD_OK;
+  switch (ell) {
+    case 128: return sign_sketch_bw<16>(d_cols, d_rbs, d_rows, n, m, full_rows, seed, Y, ocs, obs, stream);
+    case 256: return sign_sketch_bw<32>(d_cols, d_rbs, d_rows, n, m, full_rows, seed, Y, ocs, obs, stream);
+    case 384: return sign_sketch_bw<48>(d_cols, d_rbs, d_rows, n, m, full_rows, seed, Y, ocs, obs, stream);
+    case 512: return sign_sketch_bw<64>(d_cols, d_rbs, d_rows, n, m, full_rows, seed, Y, ocs, obs, stream);
+    default:
+      set_error("sparse sign sketch: ell must be 128, 256, 384 or 512");
+      return HAPOD_E_UNSUPPORTED;
+  }
 }
 
 hapod_status launch_transpose(const double* A, int64_t lda, int64_t m, double* T, int64_t ldt, hipStream_t stream) {
