@@ -319,6 +319,27 @@ typedef struct {
                                       hapod_node_pod_sketch), the Gaussian if its
                                       residual exceeds eps^2; 1: the Gaussian.  Other
                                       values: HAPOD_E_INVALID.                          */
+  int32_t leaf_layout;             /* how a leaf provider's pointer holds the leaf:
+                                      0: column-major, leading dimension ld >= rows;
+                                      1: this library's row-block layout -- blocks of 128
+                                      rows, block b holding rows 128 b .. 128 b + 127 of
+                                      every column of the leaf, column j at element
+                                      128 j of the block (a block spans 128 x leaf_cols
+                                      elements; ld is ignored).  Other values:
+                                      HAPOD_E_INVALID.                                   */
+  int32_t leaf_passthrough;        /* 1: a computed leaf whose truncation keeps every one
+                                      of its columns (rank = leaf_cols, nothing
+                                      discarded) hands its own columns to its parent in
+                                      place of its scaled modes sigma_k u_k = S v_k: the
+                                      same span and Gram spectrum (the right factor V is
+                                      orthogonal), so the parent's POD is the same up to
+                                      rounding, and the leaf's lift is saved.  Such a
+                                      leaf's data is read again when its parent's group
+                                      runs (no release call in between; see
+                                      hapod_leaf_fn), and its batch reads the ranks back
+                                      before the lift.  Not with right_vectors (the leaf
+                                      keeps its modes then).  0: off.  Other values:
+                                      HAPOD_E_INVALID.                                   */
 } hapod_options;
 
 /* Validate the tree (Def. 3.1), compute levels (height: leaves are level 1),
@@ -432,7 +453,10 @@ typedef enum {
                                   root (omega = 0) its "modes" are not orthonormal            */
   HAPOD_ROUTE_SNAPSHOTS = 1,   /* the method of snapshots (Gram, eigensolve, truncation, lift) */
   HAPOD_ROUTE_QR = 2,          /* the QR route of hapod_node_pod_qr (plan option qr_pod)      */
-  HAPOD_ROUTE_SKETCH = 3       /* the sketched route of hapod_node_pod_sketch (sketch_cols)   */
+  HAPOD_ROUTE_SKETCH = 3,      /* the sketched route of hapod_node_pod_sketch (sketch_cols)   */
+  HAPOD_ROUTE_FULL_LEAF = 4    /* a leaf through the method of snapshots up to the truncation,
+                                  which kept every column: its own columns went to the parent
+                                  (plan option leaf_passthrough); sigma as computed            */
 } hapod_route;
 /* route: host, one int32 (a hapod_route) for node (-1 = root).
  * HAPOD_E_STATE before the first completed run.                             */

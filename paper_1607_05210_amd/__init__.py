@@ -23,9 +23,11 @@ LIB_PATH = os.path.join(_HERE, "libhapod.so")
 
 FP64, FP32, BF16X3 = 0, 1, 2
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3}
-ROUTES = {0: "passthrough", 1: "snapshots", 2: "qr", 3: "sketch"}
+ROUTES = {0: "passthrough", 1: "snapshots", 2: "qr", 3: "sketch", 4: "full_leaf"}
 _SKETCH_KINDS = {"sparse_sign": 0, "gaussian": 1}
 _SKETCH_NAMES = {v: k for k, v in _SKETCH_KINDS.items()}
+_LEAF_LAYOUTS = {"column": 0, "blocks": 1}
+ROW_BLOCK = 128  # rows per block of the library's row-block layout
 STATUS = {0: "OK", 1: "E_INVALID", 2: "E_TREE", 3: "E_NOMEM", 4: "E_DEVICE", 5: "E_NUMERIC",
           6: "E_STATE", 7: "E_CALLBACK", 8: "E_UNSUPPORTED"}
 HAPOD_EIG_MAX = 8192
@@ -48,7 +50,8 @@ class HapodOptions(C.Structure):
                 ("node_eps_override", _pdbl), ("jacobi_max", _i32), ("autotune", _i32),
                 ("leaf_wave", _i32), ("block_gram", _i32), ("right_vectors", _i32),
                 ("qr_pod", _i32), ("sketch_cols", _i32), ("autotune_cache", C.c_char_p),
-                ("graph_levels", _i32), ("sketch_kind", _i32)]
+                ("graph_levels", _i32), ("sketch_kind", _i32), ("leaf_layout", _i32),
+                ("leaf_passthrough", _i32)]
 
 
 LEAF_FN = C.CFUNCTYPE(_i32, _vp, _i32, C.POINTER(_vp), _pi64, _vp)
@@ -136,6 +139,31 @@ def _mat(t, name, dtype=None):
         raise ValueError(f"{name}: must be column-major (stride(0) == 1)")
     ld = t.stride(1) if m > 1 else max(n, 1)
     return C.c_void_p(t.data_ptr()), n, m, max(ld, 1)
+
+
+def to_blocks(S):
+    """An n x m tensor in the library's row-block layout: a contiguous
+    (ceil(n / 128), m, 128) tensor, element (r, j) at [r // 128, j, r % 128]
+    (rows past n zero) -- the layout a plan made with leaf_layout="blocks"
+    expects of its leaves."""
+    n, m = S.shape
+    nb = (n + ROW_BLOCK - 1) // ROW_BLOCK
+    B = torch.zeros((nb, m, ROW_BLOCK), dtype=S.dtype, device=S.device)
+    full = n // ROW_BLOCK
+    if full:
+        B[:full].copy_(S[:full * ROW_BLOCK].reshape(full, ROW_BLOCK, m).transpose(1, 2))
+    if n > full * ROW_BLOCK:
+        B[full, :, :n - full * ROW_BLOCK].copy_(S[full * ROW_BLOCK:].t())
+    return B
+
+
+def _blocks(t, name, dtype):
+    """Pointer of a leaf in the row-block layout (see to_blocks)."""
+    if t.dim() != 3 or t.shape[2] != ROW_BLOCK or not t.is_contiguous():
+        raise ValueError(f"{name}: expected a contiguous (blocks, cols, {ROW_BLOCK}) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name}: expected {dtype}, got {t.dtype}")
+    return C.c_void_p(t.data_ptr())
 
 
 def _elem(prec):
@@ -276,11 +304,13 @@ class Plan:
     def __init__(self, parent, leaf_cols, n, eps_star, omega, prec="fp64", reorth=False,
                  mem_cap_bytes=0, eps_override=None, jacobi_max=0, leaf_rows=None, leaf_wave=0,
                  autotune=False, block_gram=False, right_vectors=False, qr_pod=False, sketch_cols=0,
-                 autotune_cache=None, graph_levels=False, sketch_kind="sparse_sign"):
+                 autotune_cache=None, graph_levels=False, sketch_kind="sparse_sign", leaf_layout="column",
+                 leaf_passthrough=False):
         import numpy as np
         self.num_nodes = len(parent)
         self.n = int(n)
         self.prec = _prec(prec)
+        self._layout = _LEAF_LAYOUTS[leaf_layout]
         self._parent = (C.c_int32 * self.num_nodes)(*[int(p) for p in parent])
         self._cols = (C.c_int64 * self.num_nodes)(*[int(c) for c in leaf_cols])
         self._rows = None
@@ -295,7 +325,7 @@ class Plan:
                             int(bool(autotune)), int(leaf_wave), int(bool(block_gram)),
                             int(bool(right_vectors)), int(bool(qr_pod)), int(sketch_cols),
                             os.fsencode(autotune_cache) if autotune_cache else None, int(bool(graph_levels)),
-                            _SKETCH_KINDS[sketch_kind])
+                            _SKETCH_KINDS[sketch_kind], _LEAF_LAYOUTS[leaf_layout], int(bool(leaf_passthrough)))
         h = C.c_void_p()
         _check(_lib.hapod_plan(C.byref(tree), float(eps_star), float(omega), C.byref(opts), C.byref(h)),
                "hapod_plan")
@@ -326,7 +356,8 @@ class Plan:
         return eps, lev, acc
 
     def run(self, leaves, stream=None, hold=True):
-        """``leaves``: dict leaf id -> column-major device tensor, or a
+        """``leaves``: dict leaf id -> column-major device tensor (a
+        ``to_blocks`` tensor when the plan has leaf_layout="blocks"), or a
         callable leaf id -> tensor (called once per leaf, in level order, just
         before the launch group that first reads it).  With ``hold`` every
         tensor handed over stays referenced until the library reports that no
@@ -348,7 +379,10 @@ class Plan:
                         rel()
                     return 0
                 t = leaves(leaf) if callable(leaves) else leaves[leaf]
-                p, n, m, ldt = _mat(t, f"leaf {leaf}", elem)
+                if self._layout == 1:
+                    p, ldt = _blocks(t, f"leaf {leaf}", elem), 0
+                else:
+                    p, n, m, ldt = _mat(t, f"leaf {leaf}", elem)
                 if hold:
                     held[leaf] = t
                 ptr[0] = p.value
@@ -410,7 +444,7 @@ class Plan:
         return w.value, p.value
 
     def route(self, node=-1):
-        """The route node took in the last run: passthrough, snapshots, qr or sketch."""
+        """The route node took in the last run: passthrough, snapshots, qr, sketch or full_leaf."""
         r = C.c_int32(0)
         _check(_lib.hapod_node_route(self._h, int(node), C.byref(r)), "hapod_node_route")
         return ROUTES[r.value]

@@ -311,6 +311,10 @@ struct PodJob {
   std::vector<std::pair<int64_t, int64_t>> sblk;
   std::vector<double> s2;
   bool keep_v = false;      // copy V[:, :N] to a pool block of its own
+  // a leaf that may hand its own columns to its parent when its rank is m
+  // (host-driven batch: no output, no lift for it then; passed says so)
+  bool pass_full = false;
+  bool passed = false;
   double* vkeep = nullptr;  // that block (m x N, ld m)
   int64_t cap_hint = 0;     // the node's rank in the plan's previous run (0: none)
 };
@@ -620,7 +624,7 @@ hapod_status run_pod_batch_impl(hapod_precision prec, std::vector<PodJob>& jobs,
   size_t worst_out = 0;
   for (int i = 0; i < nj; ++i) {
     const PodJob& j = jobs[i];
-    if (j.keep_v || (j.m > 0 && j.wide && !(j.wide_full && j.m <= kHouseholderMaxM))) dev = false;
+    if (j.keep_v || j.pass_full || (j.m > 0 && j.wide && !(j.wide_full && j.m <= kHouseholderMaxM))) dev = false;
     cap[i] = (j.cap_hint > 0 && j.cap_hint <= j.m) ? j.cap_hint : j.m;
     if (!j.out && j.alloc_rows > 0 && j.m > 0)
       worst_out += align_up(j.plain_out ? (size_t)j.alloc_rows * cap[i] * eb : tiled_bytes(j.n, cap[i], eb));
@@ -1325,7 +1329,14 @@ hapod_status run_pod_batch_impl(hapod_precision prec, std::vector<PodJob>& jobs,
         HAPOD_TRY(pool.alloc(bytes, (void**)&j.vkeep));
         HAPOD_HIP(hipMemcpyAsync(j.vkeep, scratch + lay[i].V, bytes, hipMemcpyDeviceToDevice, ls));
       }
-      HAPOD_TRY(build_lifts(ranks, false));
+      // a full-rank leaf that may pass its columns on gets no output and no lift
+      std::vector<int64_t> lranks(ranks);
+      for (int i = 0; i < nj; ++i) {
+        PodJob& j = jobs[i];
+        j.passed = j.pass_full && !j.out && j.m > 0 && ranks[i] == j.m;
+        if (j.passed) lranks[i] = 0;
+      }
+      HAPOD_TRY(build_lifts(lranks, false));
       if (!lnodes[0].empty() || !lnodes[1].empty()) {
         std::vector<LiftNode> all(lnodes[0]);
         all.insert(all.end(), lnodes[1].begin(), lnodes[1].end());
@@ -2362,6 +2373,11 @@ hapod_status hapod_plan(const hapod_tree* tree, double eps_star, double omega, c
     set_error("hapod_plan: sketch_kind must be 0 (sparse sign map, Gaussian fallback) or 1 (Gaussian)");
     return HAPOD_E_INVALID;
   }
+  if (opts && ((opts->leaf_layout != 0 && opts->leaf_layout != 1) ||
+               (opts->leaf_passthrough != 0 && opts->leaf_passthrough != 1))) {
+    set_error("hapod_plan: leaf_layout and leaf_passthrough must be 0 or 1");
+    return HAPOD_E_INVALID;
+  }
   auto P = std::make_unique<hapod_plan_s>();
   const int32_t nn = tree->num_nodes;
   P->num_nodes = nn;
@@ -2734,12 +2750,18 @@ hapod_status hapod_run(hapod_plan_t P, hapod_leaf_fn get_leaf, void* user, void*
       set_error("leaf provider returned " + std::to_string(rc) + " for leaf " + std::to_string(a));
       return HAPOD_E_CALLBACK;
     }
-    if (P->leaf_cols[a] > 0 && (!ptr || ld < P->rows[a])) {
+    const bool tiled = P->opts.leaf_layout == 1;
+    if (P->leaf_cols[a] > 0 && (!ptr || (!tiled && ld < P->rows[a]))) {
       set_error("leaf provider gave a NULL pointer or ld < rows for leaf " + std::to_string(a));
       return HAPOD_E_CALLBACK;
     }
-    cols = column_table(ptr, ld, P->leaf_cols[a], eb);
-    rbs.assign(cols.size(), kRowBlock);
+    if (tiled) {
+      cols = tiled_table(ptr, P->leaf_cols[a], eb);
+      rbs.assign(cols.size(), tiled_rbs(P->leaf_cols[a]));
+    } else {
+      cols = column_table(ptr, ld, P->leaf_cols[a], eb);
+      rbs.assign(cols.size(), kRowBlock);
+    }
     rows.assign(cols.size(), P->rows[a]);
     return HAPOD_OK;
   };
@@ -2972,6 +2994,7 @@ hapod_status hapod_run(hapod_plan_t P, hapod_leaf_fn get_leaf, void* user, void*
           }
         }
         j.keep_v = P->opts.right_vectors != 0;
+        j.pass_full = P->opts.leaf_passthrough != 0 && !j.keep_v && P->children[a].empty() && a != P->root;
         j.cap_hint = (size_t)a < P->rank_hint.size() ? P->rank_hint[a] : 0;
         j.cols = std::move(in);
         j.rbs = std::move(in_rbs);
@@ -3065,7 +3088,14 @@ hapod_status hapod_run(hapod_plan_t P, hapod_leaf_fn get_leaf, void* user, void*
           out_blk[a] = (int)blocks.size() - 1;
           ++blocks.back().second;
         }
-        if (a == P->root) {
+        if (j.passed) {
+          // a full-rank leaf: its own columns go up (read again by the parent)
+          out_cols[a] = j.cols;
+          out_rbs[a] = j.rbs;
+          out_rows[a] = j.crows;
+          holds_leaf[a] = 1;
+          P->route[a] = HAPOD_ROUTE_FULL_LEAF;
+        } else if (a == P->root) {
           out_cols[a] = column_table(j.out, P->n, j.rank, eb);
           out_rbs[a].assign((size_t)j.rank, kRowBlock);
           out_rows[a].assign((size_t)j.rank, P->n);

@@ -149,6 +149,38 @@ def test_plan_rejects_bad_sketch_options(kw):
     assert e.value.status == 1
 
 
+@pytest.mark.parametrize("field,value", [("leaf_layout", 2), ("leaf_layout", -1), ("leaf_passthrough", 2)])
+def test_plan_rejects_bad_leaf_options(field, value):
+    """leaf_layout and leaf_passthrough are 0 or 1 (checked at the C-ABI)."""
+    import ctypes as C
+    hp = pytest.importorskip("paper_1607_05210_amd")
+    parent = (C.c_int32 * 3)(*synth.star_tree(2))
+    cols = (C.c_int64 * 3)(4, 4, 0)
+    tree = hp.HapodTree(3, parent, cols, 64, None)
+    opts = hp.HapodOptions()
+    opts.prec = 0
+    setattr(opts, field, value)
+    h = C.c_void_p()
+    assert hp._lib.hapod_plan(C.byref(tree), 1e-3, 0.5, C.byref(opts), C.byref(h)) == 1  # HAPOD_E_INVALID
+    setattr(opts, field, 1)
+    assert hp._lib.hapod_plan(C.byref(tree), 1e-3, 0.5, C.byref(opts), C.byref(h)) == 0
+    hp._lib.hapod_destroy(h)
+
+
+def test_to_blocks_layout():
+    """to_blocks: element (r, j) of an n x m matrix at [r // 128, j, r % 128],
+    rows past n zero (CPU tensors)."""
+    hp = pytest.importorskip("paper_1607_05210_amd")
+    import torch
+    S = torch.arange(300 * 3, dtype=torch.float64).reshape(3, 300).t()  # column-major 300 x 3
+    B = hp.to_blocks(S)
+    assert B.shape == (3, 3, 128) and B.is_contiguous()
+    for r in (0, 127, 128, 255, 256, 299):
+        for j in range(3):
+            assert B[r // 128, j, r % 128] == S[r, j]
+    assert not B[2, :, 300 - 256:].any()
+
+
 def test_plan_time_memory_cap():
     """A cap below the leaf level's scratch (needed whatever the ranks) fails
     at plan time with HAPOD_E_NOMEM; a cap above it is accepted and the

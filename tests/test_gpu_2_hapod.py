@@ -250,6 +250,53 @@ def test_full_rank_leaves(hp, L):
     assert len(sig2) == len(sig)
     np.testing.assert_allclose(sig2, sig, rtol=1e-12)
     assert metrics.subspace_error(host(U2), host(U), len(sig)) <= 1e-10
+    # the leaves' own columns handed to the root (same span and Gram
+    # spectrum as S V), read from the row-block layout
+    blocks = {i: hp.to_blocks(v) for i, v in dev.items()}
+    passed = hp.Plan(parent, cols, n, eps_star, omega, prec=prec, leaf_layout="blocks", leaf_passthrough=True)
+    passed.run(blocks)
+    sig3, U3 = passed.modes()
+    assert [passed.route(i) for i in range(L)] == ["full_leaf"] * L
+    assert list(passed.ranks()[:L]) == [c] * L
+    assert len(sig3) == len(sig)
+    np.testing.assert_allclose(sig3, s_ref, rtol=1e-10)
+    np.testing.assert_allclose(sig3, sig, rtol=1e-11)
+    assert metrics.subspace_error(host(U3), host(U), len(sig)) <= 1e-10
+
+
+def test_leaf_blocks_layout_and_passthrough_mixed(hp):
+    """Leaves in the row-block layout (n = 1000: a partial last block) give
+    the column-major run's result; with leaf_passthrough the full-rank leaves
+    hand their columns up while a leaf of rank 5 takes its lift, and the
+    root keeps the same rank and sigma."""
+    n, c, L = 1000, 40, 4
+    rng = np.random.default_rng(7)
+    data = {i: rng.standard_normal((n, c)) for i in range(L)}
+    data[2] = rng.standard_normal((n, 5)) @ rng.standard_normal((5, c))  # rank 5
+    parent = synth.star_tree(L)
+    cols = [c] * L + [0]
+    eps_star, omega = 1e-6, 0.7
+    dev = {i: dev_colmajor(v) for i, v in data.items()}
+    ref = hp.Plan(parent, cols, n, eps_star, omega, prec="fp64")
+    ref.run(dev)
+    sig, U = ref.modes()
+    blocks = {i: hp.to_blocks(v) for i, v in dev.items()}
+    B = blocks[1].cpu().numpy()
+    np.testing.assert_array_equal(B[7, 3, 99], data[1][7 * 128 + 99, 3])   # element (r, j) at [r // 128, j, r % 128]
+    assert B.shape == (8, c, 128) and not B[7, :, n - 7 * 128:].any()       # rows past n zero
+    for passthrough in (False, True):
+        plan = hp.Plan(parent, cols, n, eps_star, omega, prec="fp64", leaf_layout="blocks",
+                       leaf_passthrough=passthrough)
+        plan.run(blocks)
+        sig2, U2 = plan.modes()
+        routes = [plan.route(i) for i in range(L)]
+        print(f"  blocks layout, passthrough {passthrough}: leaf ranks {list(plan.ranks()[:L])}, routes {routes}, "
+              f"root rank {len(sig2)} (column-major {len(sig)})")
+        assert list(plan.ranks()[:L]) == list(ref.ranks()[:L])
+        assert routes == (["full_leaf", "full_leaf", "snapshots", "full_leaf"] if passthrough else ["snapshots"] * L)
+        assert len(sig2) == len(sig)
+        np.testing.assert_allclose(sig2, sig, rtol=1e-11)
+        assert metrics.subspace_error(host(U2), host(U), len(sig)) <= 1e-10
 
 
 def test_single_node_tree_equals_node_pod(hp):

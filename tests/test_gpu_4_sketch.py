@@ -197,13 +197,25 @@ def test_tree_sketch_root_meets_the_bound(hp):
     s_ref, U_ref = ref[L]
     dev = {i: dev_colmajor(v) for i, v in data.items()}
     out = {}
-    for name, kw in (("sketch", dict(sketch_cols=256)), ("gram", {})):
+    blocks = {i: hp.to_blocks(v) for i, v in dev.items()}
+    for name, kw in (("sketch", dict(sketch_cols=256)), ("gram", {}),
+                     ("passed", dict(sketch_cols=256, leaf_layout="blocks", leaf_passthrough=True))):
         plan = hp.Plan(parent, cols, n, eps_star, omega, prec="fp64", **kw)
-        plan.run(dev)
+        plan.run(blocks if name == "passed" else dev)
         sig, U = plan.modes()
-        out[name] = (sig, host(U), plan.ranks(), plan.sketch_stats())
+        out[name] = (sig, host(U), plan.ranks(), plan.sketch_stats(), [plan.route(i) for i in range(L)])
         del plan
-    sig, U, ranks, st = out["sketch"]
+    # full-rank leaves handing their own columns (row-block layout) to the
+    # sketched root: the same rank, sigma to the residual's level
+    sig_p, U_p, ranks_p, st_p, routes_p = out["passed"]
+    print(f"  leaf passthrough: routes {set(routes_p)}, root rank {len(sig_p)} (sketch {len(out['sketch'][0])}), "
+          f"residual {st_p['residual']:.3e}")
+    assert all(r == ("full_leaf" if ranks_p[i] == c else "snapshots") for i, r in enumerate(routes_p))
+    assert "full_leaf" in routes_p
+    assert len(sig_p) == len(out["sketch"][0])
+    assert np.max(np.abs(sig_p - out["sketch"][0])) <= 1e-12 * sig_p[0] + math.sqrt(st_p["residual"])
+    assert metrics.mean_projection_error(S, U_p) <= eps_star ** 2
+    sig, U, ranks, st, _ = out["sketch"]
     assert st is not None and st["ell"] == 256
     assert st["kind"] == "sparse_sign"  # K = 200 sinusoid modes fit the 256 columns
     assert list(ranks[:L]) == [len(ref[i][0]) for i in range(L)]
