@@ -338,8 +338,11 @@ typedef struct {
                                       runs (no release call in between; see
                                       hapod_leaf_fn), and its batch reads the ranks back
                                       before the lift.  Not with right_vectors (the leaf
-                                      keeps its modes then).  0: off.  Other values:
-                                      HAPOD_E_INVALID.                                   */
+                                      keeps its modes then).  In the FP32 and split-BF16
+                                      forms the parent's Gram of the raw columns (nearly
+                                      collinear snapshots) loses more to FP32 rounding
+                                      than one of orthogonal, graded modes.  0: off.
+                                      Other values: HAPOD_E_INVALID.                     */
 } hapod_options;
 
 /* Validate the tree (Def. 3.1), compute levels (height: leaves are level 1),

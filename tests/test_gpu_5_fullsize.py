@@ -34,14 +34,14 @@ def test_star1Mx8192_every_form(hp):
     weyl = ref["weyl"]
     out = {}
     print("full size: FP64 leaves", flush=True)
-    leaves = bench.gpu_leaves(w, torch.float64)
+    leaves = bench.gpu_leaves(w, torch.float64, blocks=True)
     for form in ("fp64", "fp64_mos"):
         print(f"full size: {form}", flush=True)
         out[form] = bench.run_form(hp, w, leaves, form, 1, 0, ref)["accuracy"]
     del leaves
     torch.cuda.empty_cache()
     print("full size: FP32 leaves", flush=True)
-    leaves = bench.gpu_leaves(w, torch.float32)
+    leaves = bench.gpu_leaves(w, torch.float32, blocks=True)
     for form in ("fp32", "bf16x3"):
         print(f"full size: {form}", flush=True)
         out[form] = bench.run_form(hp, w, leaves, form, 1, 0, ref)["accuracy"]
