@@ -1801,11 +1801,20 @@ hapod_status cholqr_core(Pool& pool, int64_t n, int64_t m, const double* A, int6
             HAPOD_OK ||
         (st = launch_identity_dev((double*)G, m, m, (double*)ddev, stream)) != HAPOD_OK)
       return finish(st);
+    // one readback per pass: this Gram's deviation and the previous pass's
+    // Cholesky flag (after a bad pivot this Gram is meaningless, and unused)
     double dev = 0.0;
+    int32_t bad_prev = 0;
     if (hipMemcpyAsync(&dev, ddev, sizeof(double), hipMemcpyDeviceToHost, stream) != hipSuccess ||
+        (pass > 0 && hipMemcpyAsync(&bad_prev, (int32_t*)dbad + pass - 1, sizeof(bad_prev), hipMemcpyDeviceToHost,
+                                    stream) != hipSuccess) ||
         hipStreamSynchronize(stream) != hipSuccess) {
       set_error("Cholesky-QR: readback failed");
       return finish(HAPOD_E_DEVICE);
+    }
+    if (bad_prev) {
+      set_error("Cholesky-QR: a Cholesky pivot was not positive (non-finite input?)");
+      return finish(HAPOD_E_NUMERIC);
     }
     // the previous pass was plain and left Q^T Q within the Gram's own
     // rounding of the identity: Q is orthonormal, no further pass
@@ -1835,8 +1844,12 @@ hapod_status cholqr_core(Pool& pool, int64_t n, int64_t m, const double* A, int6
     src_rbs = trbs;
     ld = n;
     dst = (dst == QA) ? QB : QA;
+    plain_run = shifted ? 0 : plain_run + 1;
+  }
+  if (!done && pass > 0) {
+    // the last pass's Cholesky flag (checked by the next readback otherwise)
     int32_t bad = 0;
-    if (hipMemcpyAsync(&bad, (int32_t*)dbad + pass, sizeof(bad), hipMemcpyDeviceToHost, stream) != hipSuccess ||
+    if (hipMemcpyAsync(&bad, (int32_t*)dbad + pass - 1, sizeof(bad), hipMemcpyDeviceToHost, stream) != hipSuccess ||
         hipStreamSynchronize(stream) != hipSuccess) {
       set_error("Cholesky-QR: readback failed");
       return finish(HAPOD_E_DEVICE);
@@ -1845,7 +1858,6 @@ hapod_status cholqr_core(Pool& pool, int64_t n, int64_t m, const double* A, int6
       set_error("Cholesky-QR: a Cholesky pivot was not positive (non-finite input?)");
       return finish(HAPOD_E_NUMERIC);
     }
-    plain_run = shifted ? 0 : plain_run + 1;
   }
   if (!done && plain_run < 2) {
     set_error("Cholesky-QR did not reach an orthonormal factor in 12 passes");
