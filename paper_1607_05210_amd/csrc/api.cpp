@@ -3354,8 +3354,11 @@ hapod_status gram_impl(int compute, int eb, int64_t n, int64_t m, const void* S,
   const int pairs = nt * (nt + 1) / 2;
   const int KB = (compute == 2) ? 32 : 16;
   // the level batches' work-item goal (8192, measured there on 2^20- and
-  // 2^22-row nodes)
-  int nch = (n > 0) ? pick_chunks(n, pairs, std::max(8192, pairs), 2048) : 1;
+  // 2^22-row nodes); short inputs (the sketched route's B^T, 8192 rows) take
+  // chunks down to 256 rows, so that a one-tile Gram is not 4 workgroups
+  // each over 2048 rows (0.25 ms of latency per Cholesky-QR pass)
+  int nch = (n > 0) ? pick_chunks(n, pairs, std::max(8192, pairs), std::max<int64_t>(256, std::min<int64_t>(2048, n / 64)))
+                    : 1;
   int64_t cr = (n > 0) ? ((n + nch - 1) / nch + kRowBlock - 1) / kRowBlock * kRowBlock : kRowBlock;
   nch = (n > 0) ? (int)((n + cr - 1) / cr) : 1;
   bool vec_ok = (cr % KB == 0);
