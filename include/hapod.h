@@ -208,6 +208,12 @@ hapod_status hapod_node_pod_qr(int64_t n, int64_t m, const double* S, int64_t ld
  * Rank: the smallest N with r + sum_{k>N} sigma_k(B)^2 <= eps^2, so the
  * modes' projection error ||S - U U^T S||_F^2 = r + sum_{k>N} sigma_k(B)^2
  * is at most eps^2 (Def. 2.5's requirement, as used by Thm. 3.3 - 3.5).
+ * Unscaled modes (scaled = 0) take that error from the modes themselves:
+ * N is chosen with eps^2 / 64 of the budget left for r, then
+ * ||S - U C||_F^2 with C = U^T S = U_B[:, :N]^T B (an n x m x N product in
+ * place of the n x m x ell one for r) must come out <= eps^2; should it
+ * not, r is computed and N set exactly as above.  r is then reported as
+ * that error less sum_{k>N} sigma_k(B)^2.
  * FP64 only.  ell in {128, 256, 384, 512}, ell <= m, ell <= n
  * (HAPOD_E_UNSUPPORTED otherwise); eps > 0 and kind 0 or 1
  * (HAPOD_E_INVALID otherwise).
@@ -466,13 +472,16 @@ typedef enum {
 hapod_status hapod_node_route(hapod_plan_t plan, int32_t node, int32_t* route);
 
 /* Diagnostics of a node that took the sketched route in the last run
- * (node = -1: the root).  out12: host, 12 doubles {ell, residual energy r,
+ * (node = -1: the root).  out13: host, 13 doubles {ell, residual energy r,
  * Cholesky-QR passes on Y, passes on B^T, Jacobi sweeps, then device ms of:
  * sketch Y = S Omega, Q = orth(Y), B = Q^T S, residual, small SVD, modes,
- * then the test matrix of the result (0 sparse sign map, 1 Gaussian)}; the
- * counts and times are those of the attempt that gave the result.
+ * then the test matrix of the result (0 sparse sign map, 1 Gaussian), then
+ * the columns of the basis in the residual product (ell, or the rank N when
+ * the residual was taken against the kept modes; see
+ * hapod_node_pod_sketch)}; the counts and times are those of the attempt
+ * that gave the result.
  * HAPOD_E_STATE if there is no completed run or the node took another route. */
-hapod_status hapod_sketch_stats(hapod_plan_t plan, int32_t node, double* out12);
+hapod_status hapod_sketch_stats(hapod_plan_t plan, int32_t node, double* out13);
 
 /* Per-node diagnostics of the last run, host, num_nodes entries each, any may
  * be NULL: input columns m, negative Gram eigenvalues, lambda_1, lambda_min. */

@@ -465,7 +465,7 @@ class Plan:
 
     def sketch_stats(self, node=-1):
         """Diagnostics of a node that took the sketched route (dict), or None."""
-        out = (C.c_double * 12)()
+        out = (C.c_double * 13)()
         st = _lib.hapod_sketch_stats(self._h, int(node), out)
         if st == 6:
             return None
@@ -473,7 +473,7 @@ class Plan:
         v = list(out)
         return dict(ell=int(v[0]), residual=v[1], passes_y=int(v[2]), passes_b=int(v[3]), sweeps=int(v[4]),
                     ms=dict(zip(["sketch", "orth", "cross", "residual", "small_svd", "lift"], v[5:11])),
-                    kind=_SKETCH_NAMES[int(v[11])])
+                    kind=_SKETCH_NAMES[int(v[11])], res_cols=int(v[12]))
 
     def ranks(self):
         import numpy as np

@@ -1510,6 +1510,7 @@ struct SketchInfo {
   int32_t passes_b = 0;    // and on B^T = S^T Q
   int32_t sweeps = 0;      // Jacobi sweeps on the small factor
   int32_t kind = 0;        // test matrix of the result: 0 sparse sign map, 1 Gaussian
+  int64_t res_cols = 0;    // columns of the basis the residual product used (ell, or the rank)
   float ms[6] = {0, 0, 0, 0, 0, 0};  // sketch, orthonormalisation, B, residual, small SVD, lift
 };
 
@@ -2204,6 +2205,7 @@ hapod_status sketch_pod_core(Pool& pool, int64_t n, int64_t m, const std::vector
   // oversampling) from the start.  Either way the residual decides, exactly.
   Cols Q;
   si.kind = (kind == 1) ? 1 : 0;
+  const bool post = !scaled;
   for (;;) {
     (void)hipEventRecord(ev[0], stream);
     // ---- Y = S Omega ----------------------------------------------------------
@@ -2225,6 +2227,9 @@ hapod_status sketch_pod_core(Pool& pool, int64_t n, int64_t m, const std::vector
     // ---- B^T = S^T Q (row-major B, ell x m) ---------------------------------------
     if ((st = cross_cols(pool, n, Q, Sc, (double*)Bt, m, stream)) != HAPOD_OK) return finish(st);
     (void)hipEventRecord(ev[3], stream);
+    // unscaled modes are Q U_B[:, :N] themselves: their residual is taken
+    // after the SVD, against the N kept columns (below)
+    if (post) break;
     // ---- residual energy per column: ||s_j - Q b_j||^2 ------------------------------
     if ((st = residual_cols(pool, n, Q, (const double*)Bt, m, Sc, (double*)res, stream)) != HAPOD_OK)
       return finish(st);
@@ -2259,7 +2264,7 @@ hapod_status sketch_pod_core(Pool& pool, int64_t n, int64_t m, const std::vector
   std::vector<double> sg((size_t)ell), rs((size_t)m);
   int32_t jinfo = 0;
   if (hipMemcpyAsync(sg.data(), dsig, sizeof(double) * ell, hipMemcpyDeviceToHost, stream) != hipSuccess ||
-      hipMemcpyAsync(rs.data(), res, sizeof(double) * m, hipMemcpyDeviceToHost, stream) != hipSuccess ||
+      (!post && hipMemcpyAsync(rs.data(), res, sizeof(double) * m, hipMemcpyDeviceToHost, stream) != hipSuccess) ||
       hipMemcpyAsync(&jinfo, dinfo, sizeof(int32_t), hipMemcpyDeviceToHost, stream) != hipSuccess ||
       hipStreamSynchronize(stream) != hipSuccess) {
     set_error("sketched POD: readback failed");
@@ -2270,10 +2275,123 @@ hapod_status sketch_pod_core(Pool& pool, int64_t n, int64_t m, const std::vector
     return finish(HAPOD_E_NUMERIC);
   }
   si.sweeps = jinfo;
+  const double e2 = eps * eps;
+  if (post) {
+    // The residual of the modes U = Q U_B[:, :N] themselves: ||S - U U^T S||^2
+    // = ||S - U C||^2 with C = U_B[:, :N]^T B (the coefficients, from B on
+    // the small side), an n x m x N product instead of n x m x ell.  N is
+    // chosen first with e2 / 64 of the budget left for the residual r of the
+    // whole sketch basis (the discarded energy is r + sum_{k>N} sigma_k^2 by
+    // orthogonality); the computed residual then certifies it.  Should it
+    // exceed e2, r itself is taken and N set exactly (or, r above e2, the
+    // route starts over with the Gaussian, or fails as the i.i.d. path does).
+    auto tail_rank = [&](double r0, double budget, double* tail_out) {
+      int64_t N = ell;
+      double tail = r0;
+      while (N > 0 && tail + sg[(size_t)N - 1] * sg[(size_t)N - 1] <= budget) {
+        tail += sg[(size_t)N - 1] * sg[(size_t)N - 1];
+        --N;
+      }
+      *tail_out = tail - r0;
+      return N;
+    };
+    double tail = 0.0;
+    int64_t N = tail_rank(0.0, e2 * (1.0 - 1.0 / 64.0), &tail);
+    double* out = nullptr;
+    int64_t ocs = 0, obs = 0;
+    const Cols Bcols = Cols::of(Bt, m, 0, ell, m, 8);  // B^T, m x ell, column c = row c of B
+    auto modes_and_residual = [&](int64_t Nk, double* rN) -> hapod_status {
+      if (Nk == 0) {
+        // no mode kept: the residual is all of S
+        if ((st = residual_cols(pool, n, Q, (const double*)Bt, m, Sc, (double*)res, stream)) != HAPOD_OK) return st;
+      } else {
+        HAPOD_TRY(out_for_rank(Nk, &out, &ocs, &obs));
+        HAPOD_TRY(lift_cols(pool, n, Q, (const double*)UB, ell, Nk, out, ocs, obs, stream));
+        // C^T = B^T U_B[:, :N] (m x N, ld m) is C row-major: the residual's
+        // operand, padded to a multiple of 32 rows (the product's guard-free
+        // form) with zero rows against repeats of the first mode
+        const int64_t Np = std::min<int64_t>(ell, (Nk + 31) / 32 * 32);
+        HAPOD_TRY(lift_cols(pool, m, Bcols, (const double*)UB, ell, Nk, (double*)Om, m, kRowBlock, stream));
+        if (Np > Nk) HAPOD_TRY(launch_zero_bytes((double*)Om + Nk * m, sizeof(double) * (size_t)(Np - Nk) * m, stream));
+        (void)hipEventRecord(ev[6], stream);
+        Cols U = Cols::of(out, ocs, obs == kRowBlock ? 0 : obs, Nk, n, 8);
+        for (int64_t k = Nk; k < Np; ++k) {
+          U.p.push_back(U.p[0]);
+          U.rbs.push_back(U.rbs[0]);
+          U.rows.push_back(U.rows[0]);
+        }
+        HAPOD_TRY(residual_cols(pool, n, U, (const double*)Om, m, Sc, (double*)res, stream));
+      }
+      if (hipMemcpyAsync(rs.data(), res, sizeof(double) * m, hipMemcpyDeviceToHost, stream) != hipSuccess ||
+          hipStreamSynchronize(stream) != hipSuccess) {
+        set_error("sketched POD: readback failed");
+        return HAPOD_E_DEVICE;
+      }
+      double acc = 0.0;
+      for (double v : rs) acc += v;
+      *rN = acc;
+      return HAPOD_OK;
+    };
+    double rN = 0.0;
+    if ((st = modes_and_residual(N, &rN)) != HAPOD_OK) return finish(st);
+    si.res_cols = N;
+    if (!(rN <= e2)) {
+      // the budget's reserve was too small: r of the whole basis decides
+      if ((st = residual_cols(pool, n, Q, (const double*)Bt, m, Sc, (double*)res, stream)) != HAPOD_OK)
+        return finish(st);
+      if (hipMemcpyAsync(rs.data(), res, sizeof(double) * m, hipMemcpyDeviceToHost, stream) != hipSuccess ||
+          hipStreamSynchronize(stream) != hipSuccess) {
+        set_error("sketched POD: readback failed");
+        return finish(HAPOD_E_DEVICE);
+      }
+      double r = 0.0;
+      for (double v : rs) r += v;
+      if (!(r <= e2)) {
+        if (si.kind == 0) {
+          // the sparse map missed part of the range: the Gaussian from the start
+          if ((st = finish(HAPOD_OK)) != HAPOD_OK) return st;
+          return sketch_pod_core(pool, n, m, cols, rbs, crows, ell, seed, 1, eps, scaled, out_for_rank, sigma, rank,
+                                 info, stream);
+        }
+        si.residual = r;
+        set_error("sketched POD: the residual energy " + std::to_string(r) + " of a " + std::to_string(ell) +
+                  "-column sketch exceeds eps^2 = " + std::to_string(e2) +
+                  " (the node's rank is beyond the sketch: use a wider sketch or the method of snapshots)");
+        if (info) *info = si;
+        return finish(HAPOD_E_UNSUPPORTED);
+      }
+      const int64_t N2 = tail_rank(r, e2, &tail);
+      if (N2 != N) {
+        N = N2;
+        if ((st = modes_and_residual(N, &rN)) != HAPOD_OK) return finish(st);
+      }
+      si.res_cols = ell;
+      rN = r + tail;
+    }
+    si.residual = std::max(0.0, rN - tail);
+    (void)hipEventSynchronize(ev[6]);
+    // ms: sketch, orthonormalisation, B, residual (after the modes), small SVD, modes
+    float a[6] = {0, 0, 0, 0, 0, 0};
+    (void)hipEventElapsedTime(&a[0], ev[0], ev[1]);
+    (void)hipEventElapsedTime(&a[1], ev[1], ev[2]);
+    (void)hipEventElapsedTime(&a[2], ev[2], ev[3]);
+    (void)hipEventElapsedTime(&a[4], ev[3], ev[5]);
+    if (N > 0) (void)hipEventElapsedTime(&a[5], ev[5], ev[6]);
+    float total = 0.f;
+    (void)hipEventRecord(ev[4], stream);
+    (void)hipEventSynchronize(ev[4]);
+    (void)hipEventElapsedTime(&total, ev[0], ev[4]);
+    a[3] = std::max(0.f, total - a[0] - a[1] - a[2] - a[4] - a[5]);
+    for (int k = 0; k < 6; ++k) si.ms[k] = a[k];
+    *rank = N;
+    sigma.assign(sg.begin(), sg.begin() + N);
+    if (info) *info = si;
+    return finish(HAPOD_OK);
+  }
+  si.res_cols = ell;
   double r2 = 0.0;
   for (double v : rs) r2 += v;
   si.residual = r2;
-  const double e2 = eps * eps;
   if (!(r2 <= e2)) {
     set_error("sketched POD: the residual energy " + std::to_string(r2) + " of a " + std::to_string(ell) +
               "-column sketch exceeds eps^2 = " + std::to_string(e2) +
@@ -2866,6 +2984,13 @@ hapod_status hapod_run(hapod_plan_t P, hapod_leaf_fn get_leaf, void* user, void*
     void* outp = nullptr;
     auto out_for = [&](int64_t N, double** o, int64_t* ocs, int64_t* obs) -> hapod_status {
       const size_t bytes = j.root ? sizeof(double) * (size_t)P->n * N : tiled_bytes(j.n, N, 8);
+      if (outp) {
+        // asked again (a rank set anew after a residual check): the earlier
+        // output goes back once the stream is done with it
+        (void)hipStreamSynchronize(stream);
+        P->pool.free(outp);
+        outp = nullptr;
+      }
       HAPOD_TRY(P->pool.alloc(bytes, &outp));
       if (j.root) {
         *ocs = P->n;
@@ -3243,8 +3368,8 @@ hapod_status hapod_modes(hapod_plan_t P, int32_t node, void* U, int64_t ldu, dou
   return HAPOD_OK;
 }
 
-hapod_status hapod_sketch_stats(hapod_plan_t P, int32_t node, double* out12) {
-  if (!P || !out12) {
+hapod_status hapod_sketch_stats(hapod_plan_t P, int32_t node, double* out13) {
+  if (!P || !out13) {
     set_error("hapod_sketch_stats: NULL argument");
     return HAPOD_E_INVALID;
   }
@@ -3258,9 +3383,9 @@ hapod_status hapod_sketch_stats(hapod_plan_t P, int32_t node, double* out12) {
     return HAPOD_E_STATE;
   }
   const SketchInfo& k = P->sketch[a];
-  const double v[12] = {(double)k.ell, k.residual, (double)k.passes_y, (double)k.passes_b, (double)k.sweeps,
-                        k.ms[0], k.ms[1], k.ms[2], k.ms[3], k.ms[4], k.ms[5], (double)k.kind};
-  std::memcpy(out12, v, sizeof(v));
+  const double v[13] = {(double)k.ell, k.residual, (double)k.passes_y, (double)k.passes_b, (double)k.sweeps,
+                        k.ms[0], k.ms[1], k.ms[2], k.ms[3], k.ms[4], k.ms[5], (double)k.kind, (double)k.res_cols};
+  std::memcpy(out13, v, sizeof(v));
   return HAPOD_OK;
 }
 

@@ -141,6 +141,18 @@ def test_sketch_node_noisy_scaled_and_rerun(hp):
     check_node(S, s1, U, eps, i1, "noisy scaled", rank_slack=1)
     # scaled modes are sigma_k u_k
     assert np.allclose(np.linalg.norm(W, axis=0), s1, rtol=1e-12)
+    # unscaled modes: the error of the kept modes is computed from the modes
+    # themselves (rank chosen with eps^2 / 64 left for the residual); with
+    # eps^2 = 1.05 r that reserve is too small (the noise directions B holds
+    # carry about 0.1 r), so r of the whole basis is taken and the rank set
+    # anew -- both certified against the projection error.  With only
+    # 0.05 r of the budget left for B's tail, the tight case keeps most of
+    # the noise directions the sketch holds (the rank exceeds the oracle's
+    # where r moves the tail across eps^2)
+    for e2, tag, slack in ((eps * eps, "noisy unscaled", 1), (1.05 * i1["residual"], "noisy unscaled, tight budget", 256)):
+        s5, U5, i5 = hp.hapod_node_pod_sketch(Sd, math.sqrt(e2), 256, seed=3, scaled=False, kind="gaussian")
+        assert abs(i5["residual"] - i1["residual"]) <= 1e-6 * e2, (tag, i5["residual"], i1["residual"])
+        check_node(S, s5, host(U5), math.sqrt(e2), i5, tag, rank_slack=slack)
 
 
 @pytest.mark.parametrize("kind", ["sparse_sign", "gaussian"])
