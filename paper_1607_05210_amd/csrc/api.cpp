@@ -1586,7 +1586,8 @@ struct Cols {
 // table of m columns and N outputs (launch_lift_residual): every column holds
 // all n rows and may be read to the next multiple of 128 rows (row-block-tiled
 // with a stride of at least 128 rows per column, or n a multiple of 128),
-// starts 16-byte aligned; m a multiple of 32, N of 128, ldb of 2.
+// starts 16-byte aligned; m a multiple of 8, and ldb of 4 (or N of 128 and
+// ldb of 2).
 bool dense_ok(int64_t n, const Cols& A, int64_t N, int64_t ldb) {
   return dense_sizes(A.size(), N, ldb) && dense_cols(n, A.size(), A.p.data(), A.rbs.data(), A.rows.data());
 }
@@ -2308,9 +2309,9 @@ hapod_status sketch_pod_core(Pool& pool, int64_t n, int64_t m, const std::vector
         HAPOD_TRY(out_for_rank(Nk, &out, &ocs, &obs));
         HAPOD_TRY(lift_cols(pool, n, Q, (const double*)UB, ell, Nk, out, ocs, obs, stream));
         // C^T = B^T U_B[:, :N] (m x N, ld m) is C row-major: the residual's
-        // operand, padded to a multiple of 32 rows (the product's guard-free
+        // operand, padded to a multiple of 8 rows (the product's guard-free
         // form) with zero rows against repeats of the first mode
-        const int64_t Np = std::min<int64_t>(ell, (Nk + 31) / 32 * 32);
+        const int64_t Np = std::min<int64_t>(ell, (Nk + 7) / 8 * 8);
         HAPOD_TRY(lift_cols(pool, m, Bcols, (const double*)UB, ell, Nk, (double*)Om, m, kRowBlock, stream));
         if (Np > Nk) HAPOD_TRY(launch_zero_bytes((double*)Om + Nk * m, sizeof(double) * (size_t)(Np - Nk) * m, stream));
         (void)hipEventRecord(ev[6], stream);
