@@ -149,6 +149,7 @@ class Pool {
     if (it == size_of_.end()) return;
     held_ -= it->second;
     size_of_.erase(it);
+    (void)hipDeviceSynchronize();
     (void)hipFree(p);
   }
   // Return cached blocks until at least `bytes` went back: the smallest
@@ -156,6 +157,9 @@ class Pool {
   // Large blocks are the expensive ones to map again, and the next run of
   // the plan asks for the same sizes.
   void trim_until(size_t bytes) {
+    // (cached blocks may still be read by queued work: helpers return them
+    // without synchronising their stream)
+    (void)hipDeviceSynchronize();
     size_t freed = 0;
     while (freed < bytes) {
       for (auto it = free_.begin(); it != free_.end();)
@@ -173,6 +177,7 @@ class Pool {
     }
   }
   void trim() {
+    (void)hipDeviceSynchronize();
     for (auto& kv : free_)
       for (void* p : kv.second) {
         held_ -= size_of_[p];
@@ -189,6 +194,35 @@ class Pool {
     if (pinned_) (void)hipHostFree(pinned_);
     pinned_ = nullptr;
     pinned_bytes_ = 0;
+    if (ring_) (void)hipHostFree(ring_);
+    ring_ = nullptr;
+    ring_pos_ = 0;
+  }
+  // A pinned copy of `bytes` host bytes for an upload the caller does not
+  // wait for (NULL if no ring could be mapped, or too large): the helpers'
+  // descriptor tables go through it, so that they return without a stream
+  // synchronisation.  A region is reused only after the ring wraps, which
+  // waits for the device to finish everything queued.
+  const void* stage(const void* src, size_t bytes) {
+    constexpr size_t kRing = size_t(32) << 20;
+    const size_t b = align_up(std::max<size_t>(bytes, 1));
+    if (b > kRing) return nullptr;
+    if (!ring_) {
+      if (hipHostMalloc(&ring_, kRing, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        ring_ = nullptr;
+        return nullptr;
+      }
+      ring_pos_ = 0;
+    }
+    if (ring_pos_ + b > kRing) {
+      if (hipDeviceSynchronize() != hipSuccess) return nullptr;
+      ring_pos_ = 0;
+    }
+    char* p = (char*)ring_ + ring_pos_;
+    std::memcpy(p, src, bytes);
+    ring_pos_ += b;
+    return p;
   }
   // Pinned host staging of at least `bytes` (grown on demand; its contents
   // do not survive growth).  Small descriptor uploads and readbacks go
@@ -239,6 +273,8 @@ class Pool {
   size_t held_ = 0, cap_ = 0, peak_ = 0;
   void* pinned_ = nullptr;
   size_t pinned_bytes_ = 0;
+  void* ring_ = nullptr;
+  size_t ring_pos_ = 0;
   bool verbose_ = [] {
     const char* v = std::getenv("HAPOD_VERBOSE");
     return v && v[0] == '1';
@@ -1594,8 +1630,23 @@ bool dense_ok(int64_t n, const Cols& A, int64_t N, int64_t ldb) {
 
 // out = A B[:, :N] in FP64: A an n-row column table of m columns, B
 // row-major m x N (ld ldb); out element (r, c) at out[c * ocs + blk_off(r,
-// obs)].  Descriptors come from the pool and go back to it after a stream
-// synchronisation (the uploads read host memory of this call).
+// obs)].  Descriptors come from the pool and go back to it at once (see
+// upload).
+// Enqueue the upload of host bytes through the pool's staging ring; where no
+// ring region was had, from `src` itself, and *wait is set: the caller then
+// synchronises its stream before `src` goes away.  Blocks a helper takes
+// from the pool go back to it without a synchronisation: every later use of
+// them is queued on the same stream (the pool's own frees wait for the
+// device).
+bool upload(Pool& pool, void* dst, const void* src, size_t bytes, hipStream_t stream, bool* wait) {
+  const void* s = pool.stage(src, bytes);
+  if (!s) {
+    s = src;
+    *wait = true;
+  }
+  return hipMemcpyAsync(dst, s, bytes, hipMemcpyHostToDevice, stream) == hipSuccess;
+}
+
 hapod_status lift_cols(Pool& pool, int64_t n, const Cols& A, const double* B, int64_t ldb, int64_t N, double* out,
                        int64_t ocs, int64_t obs, hipStream_t stream) {
   const int64_t m = A.size();
@@ -1625,18 +1676,20 @@ hapod_status lift_cols(Pool& pool, int64_t n, const Cols& A, const double* B, in
     l.col_tiles = (int32_t)col_tiles;
     l.rt_per = rt_per;
     const int items = (int)(((row_tiles + rt_per - 1) / rt_per) * col_tiles);
-    if (hipMemcpyAsync(dc, A.p.data(), sizeof(void*) * m, hipMemcpyHostToDevice, stream) != hipSuccess ||
-        hipMemcpyAsync(dr, A.rbs.data(), sizeof(int64_t) * m, hipMemcpyHostToDevice, stream) != hipSuccess ||
-        hipMemcpyAsync(dw, A.rows.data(), sizeof(int64_t) * m, hipMemcpyHostToDevice, stream) != hipSuccess ||
-        hipMemcpyAsync(dn, &l, sizeof(l), hipMemcpyHostToDevice, stream) != hipSuccess) {
+    bool wait = false;
+    if (!upload(pool, dc, A.p.data(), sizeof(void*) * m, stream, &wait) ||
+        !upload(pool, dr, A.rbs.data(), sizeof(int64_t) * m, stream, &wait) ||
+        !upload(pool, dw, A.rows.data(), sizeof(int64_t) * m, stream, &wait) ||
+        !upload(pool, dn, &l, sizeof(l), stream, &wait)) {
       set_error("lift: descriptor upload failed");
       st = HAPOD_E_DEVICE;
+      wait = true;
     }
     if (st == HAPOD_OK) st = launch_set_scalar_i64((int64_t*)dk, N, stream);
     if (st == HAPOD_OK)
       st = dense_ok(n, A, N, ldb) && ((uintptr_t)B & 15u) == 0 ? launch_lift_dense((const LiftNode*)dn, 1, items, stream)
                                                                  : launch_lift(0, (const LiftNode*)dn, 1, items, stream);
-    if (hipStreamSynchronize(stream) != hipSuccess && st == HAPOD_OK) {
+    if ((wait || st != HAPOD_OK) && hipStreamSynchronize(stream) != hipSuccess && st == HAPOD_OK) {
       set_error("lift: stream synchronisation failed");
       st = HAPOD_E_DEVICE;
     }
@@ -1678,8 +1731,9 @@ hapod_status cross_cols(Pool& pool, int64_t n, const Cols& L, const Cols& R, dou
   for (const void* c : X.p) vec = vec && (((uintptr_t)c & 15u) == 0);
   void *dxc = nullptr, *dxr = nullptr, *dxw = nullptr, *part = nullptr, *blob = nullptr;
   std::vector<void*> held;
+  bool wait = false;  // an upload read host memory of this call directly (see upload)
   auto finish = [&](hapod_status st) {
-    (void)hipStreamSynchronize(stream);
+    if (wait || st != HAPOD_OK) (void)hipStreamSynchronize(stream);
     for (void* q : held) pool.free(q);
     return st;
   };
@@ -1731,10 +1785,10 @@ hapod_status cross_cols(Pool& pool, int64_t n, const Cols& L, const Cols& R, dou
   if (st != HAPOD_OK) return finish(st);
   held.push_back(blob);
   char* db = (char*)blob;
-  if (hipMemcpyAsync(db, bl.host.data(), bl.host.size(), hipMemcpyHostToDevice, stream) != hipSuccess ||
-      hipMemcpyAsync(dxc, X.p.data(), sizeof(void*) * mt, hipMemcpyHostToDevice, stream) != hipSuccess ||
-      hipMemcpyAsync(dxr, X.rbs.data(), sizeof(int64_t) * mt, hipMemcpyHostToDevice, stream) != hipSuccess ||
-      hipMemcpyAsync(dxw, X.rows.data(), sizeof(int64_t) * mt, hipMemcpyHostToDevice, stream) != hipSuccess) {
+  if (!upload(pool, db, bl.host.data(), bl.host.size(), stream, &wait) ||
+      !upload(pool, dxc, X.p.data(), sizeof(void*) * mt, stream, &wait) ||
+      !upload(pool, dxr, X.rbs.data(), sizeof(int64_t) * mt, stream, &wait) ||
+      !upload(pool, dxw, X.rows.data(), sizeof(int64_t) * mt, stream, &wait)) {
     set_error("cross product: upload failed");
     return finish(HAPOD_E_DEVICE);
   }
@@ -1962,8 +2016,9 @@ hapod_status residual_cols(Pool& pool, int64_t n, const Cols& Q, const double* B
   void *dqc = nullptr, *dqr = nullptr, *dqw = nullptr, *drc = nullptr, *drr = nullptr, *drw = nullptr,
        *rpart = nullptr, *dn = nullptr, *dk = nullptr;
   std::vector<void*> held;
+  bool wait = false;  // an upload read host memory of this call directly (see upload)
   auto finish = [&](hapod_status st) {
-    (void)hipStreamSynchronize(stream);
+    if (wait || st != HAPOD_OK) (void)hipStreamSynchronize(stream);
     for (void* q : held) pool.free(q);
     return st;
   };
@@ -1992,9 +2047,7 @@ hapod_status residual_cols(Pool& pool, int64_t n, const Cols& Q, const double* B
   l.rrbs = (const int64_t*)drr;
   l.rrows = (const int64_t*)drw;
   l.rpart = (double*)rpart;
-  auto up = [&](void* d, const void* h, size_t bytes) {
-    return hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, stream) == hipSuccess;
-  };
+  auto up = [&](void* d, const void* h, size_t bytes) { return upload(pool, d, h, bytes, stream, &wait); };
   if (!up(dqc, Q.p.data(), sizeof(void*) * ell) || !up(dqr, Q.rbs.data(), sizeof(int64_t) * ell) ||
       !up(dqw, Q.rows.data(), sizeof(int64_t) * ell) || !up(drc, R.p.data(), sizeof(void*) * m) ||
       !up(drr, R.rbs.data(), sizeof(int64_t) * m) || !up(drw, R.rows.data(), sizeof(int64_t) * m) ||
@@ -3546,9 +3599,11 @@ hapod_status gram_impl(int compute, int eb, int64_t n, int64_t m, const void* S,
   HAPOD_TRY(pool.alloc(blob.host.size(), &dblob));
   char* db = (char*)dblob;
   hapod_status st = HAPOD_OK;
+  bool wait = false;  // (the stream is synchronised below in any case)
   do {
-    if (hipMemcpy(db, blob.host.data(), blob.host.size(), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(dcols, db + o_c, sizeof(void*) * m, hipMemcpyDeviceToDevice) != hipSuccess) {
+    // queued behind the caller's earlier work rather than waiting for it
+    if (!upload(pool, db, blob.host.data(), blob.host.size(), stream, &wait) ||
+        hipMemcpyAsync(dcols, db + o_c, sizeof(void*) * m, hipMemcpyDeviceToDevice, stream) != hipSuccess) {
       set_error("hapod_gram: descriptor upload failed");
       st = HAPOD_E_DEVICE;
       break;
